@@ -1,0 +1,369 @@
+"""FP64 CPU oracle for the MLFMA near-field (P2P) operator -- ctypes wrapper.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  The GPU library
+and its Python binding never import it; the two share no code.
+
+The C source (``p2p_oracle.c``) is the plain definition of each step; this
+module only marshals numpy arrays.  Every function names the paper passage it
+follows (arXiv 2511.21535), or the reading taken where the paper is silent.
+
+Pins: the tests in ``tests/test_oracle_*.py`` check every function here against
+closed forms, invariants, hand-computed values and brute force, not against
+itself.  Parity unpinned: the Locality metric's absolute values (the paper's
+dispersion formulas in Table 5 are garbled); only its D = 1 and V' = N/S
+special cases are pinned.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "p2p_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (OpenMP, -O2; no -march=native so the
+    library runs on any x86-64 host)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+                               _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        _lib = ctypes.CDLL(_LIB)
+        _declare(_lib)
+    return _lib
+
+
+P = ctypes.c_void_p
+I64 = ctypes.c_int64
+I32 = ctypes.c_int32
+F64 = ctypes.c_double
+
+
+def _declare(lib):
+    lib.orc_morton3.restype = ctypes.c_uint64
+    lib.orc_morton3.argtypes = [ctypes.c_uint32] * 3 + [ctypes.c_int]
+    lib.orc_particle_keys.restype = I64
+    lib.orc_particle_keys.argtypes = [I64, P, P, P, P]
+    lib.orc_grid_bits.restype = I32
+    lib.orc_grid_bits.argtypes = [I32, P]
+    lib.orc_grid_keys.restype = None
+    lib.orc_grid_keys.argtypes = [I32, P, P, P]
+    lib.orc_build_tree_particles.restype = I64
+    lib.orc_build_tree_particles.argtypes = [I64, P, I32, I32, P, P, P, P, P, P]
+    lib.orc_build_tree_grids.restype = I64
+    lib.orc_build_tree_grids.argtypes = [I32, P, P, I64, P, P, P, P, P, P, P, P]
+    lib.orc_neighbors.restype = I64
+    lib.orc_neighbors.argtypes = [I64, P, P, P, P, I64, P, P, I64]
+    lib.orc_red_offsets.restype = I64
+    lib.orc_red_offsets.argtypes = [I64, P, P, P, P, P]
+    lib.orc_restructure_rows.restype = None
+    lib.orc_restructure_rows.argtypes = [I64, P, P, P, P, P, P, I64, P]
+    lib.orc_gravity_leaves.restype = I64
+    lib.orc_gravity_leaves.argtypes = [P, P, P, P, F64, P, P, P, I64, P, P, P, P, P, P, P]
+    lib.orc_gravity_adjoint_leaves.restype = I64
+    lib.orc_gravity_adjoint_leaves.argtypes = ([P] * 4 + [F64] + [P] * 4 + [P, P, P, I64, P, P]
+                                               + [P] * 5)
+    lib.orc_helmholtz.restype = None
+    lib.orc_helmholtz.argtypes = [I32, P, P, P, P, I32, P, P, I64, P]
+    lib.orc_helmholtz_transpose.restype = None
+    lib.orc_helmholtz_transpose.argtypes = [I32, P, P, P, P, I64, I32, P, P]
+    lib.orc_locality.restype = None
+    lib.orc_locality.argtypes = [I64, P, P, I64, I64, F64, F64, P]
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+# ---------------------------------------------------------------------------
+# Keys and trees
+# ---------------------------------------------------------------------------
+def morton3(x: int, y: int, z: int, bits: int) -> int:
+    """Bit interleave, x least significant (reading R10 of the near-field
+    ordering: leaves in ascending key order)."""
+    return int(_load().orc_morton3(x, y, z, bits))
+
+
+def particle_keys(x, y, z):
+    """Depth-20 Morton keys of particles in [0,1)^3.  Returns (keys, n_bad)."""
+    x, y, z = (_c(v, np.float64) for v in (x, y, z))
+    key = np.zeros(x.shape[0], dtype=np.uint64)
+    bad = _load().orc_particle_keys(x.shape[0], _p(x), _p(y), _p(z), _p(key))
+    return key, int(bad)
+
+
+def grid_bits(n_side) -> int:
+    n_side = _c(n_side, np.int32)
+    return int(_load().orc_grid_bits(n_side.shape[0], _p(n_side)))
+
+
+def grid_offsets(n_side):
+    n_side = np.asarray(n_side, dtype=np.int64)
+    off = np.zeros(n_side.shape[0] + 1, dtype=np.int64)
+    off[1:] = np.cumsum(n_side ** 3)
+    return off
+
+
+def grid_keys(n_side):
+    n_side = _c(n_side, np.int32)
+    off = grid_offsets(n_side)
+    key = np.zeros(int(off[-1]), dtype=np.uint64)
+    _load().orc_grid_keys(n_side.shape[0], _p(n_side), _p(off), _p(key))
+    return key
+
+
+class Tree:
+    """Oracle tree: perm, leaf_start, leaf_key, leaf_level (the boundary's
+    outputs) plus anchor/size/inst, which only the oracle keeps."""
+
+    def __init__(self, perm, leaf_start, leaf_key, leaf_level, anchor, size, inst, kind):
+        self.perm, self.leaf_start, self.leaf_key, self.leaf_level = perm, leaf_start, leaf_key, leaf_level
+        self.anchor, self.size, self.inst, self.kind = anchor, size, inst, kind
+
+    @property
+    def n_leaves(self):
+        return self.leaf_key.shape[0]
+
+    @property
+    def occ(self):
+        return np.diff(self.leaf_start)
+
+
+def build_tree_particles(x, y, z, depth: int, leaf_cap: int) -> Tree:
+    """Octree over the unit cube (Sec. 5.2: an irregular tree rebuilt every
+    step; reading R8: split iff count > leaf_cap and level < depth; leaf_cap = 0
+    means a uniform tree of depth `depth`)."""
+    key, bad = particle_keys(x, y, z)
+    if bad:
+        raise ValueError(f"{bad} points outside [0,1)^3")
+    n = key.shape[0]
+    perm = np.zeros(n, dtype=np.int32)
+    ls = np.zeros(n + 1, dtype=np.int32)
+    lk = np.zeros(max(n, 1), dtype=np.uint64)
+    ll = np.zeros(max(n, 1), dtype=np.int8)
+    an = np.zeros((max(n, 1), 3), dtype=np.int32)
+    sz = np.zeros(max(n, 1), dtype=np.int32)
+    L = _load().orc_build_tree_particles(n, _p(key), depth, leaf_cap, _p(perm), _p(ls), _p(lk),
+                                         _p(ll), _p(an), _p(sz))
+    return Tree(perm, ls[: L + 1].copy(), lk[:L].copy(), ll[:L].copy(), an[:L].copy(),
+                sz[:L].copy(), None, "particles")
+
+
+def build_tree_grids(n_side) -> Tree:
+    """Boxes of 4x4x4 grid points (Sec. 5.1: a regular tree over a uniform
+    mesh), boxes and points in Morton order."""
+    n_side = _c(n_side, np.int32)
+    off = grid_offsets(n_side)
+    key = grid_keys(n_side)
+    n = key.shape[0]
+    perm = np.zeros(n, dtype=np.int32)
+    ls = np.zeros(n + 1, dtype=np.int32)
+    Lmax = n // 64 + 1
+    lk = np.zeros(Lmax, dtype=np.uint64)
+    ll = np.zeros(Lmax, dtype=np.int8)
+    an = np.zeros((Lmax, 3), dtype=np.int32)
+    sz = np.zeros(Lmax, dtype=np.int32)
+    inst = np.zeros(Lmax, dtype=np.int32)
+    L = _load().orc_build_tree_grids(n_side.shape[0], _p(n_side), _p(off), n, _p(key), _p(perm),
+                                     _p(ls), _p(lk), _p(ll), _p(an), _p(sz), _p(inst))
+    return Tree(perm, ls[: L + 1].copy(), lk[:L].copy(), ll[:L].copy(), an[:L].copy(),
+                sz[:L].copy(), inst[:L].copy(), "grids")
+
+
+def neighbors(tree: Tree, targets=None):
+    """Near lists (the E2 neighbourhood, Sec. 5.1; reading R5: leaves whose
+    closed cubes touch, the leaf itself included, ascending).  Brute force
+    over all leaves.  Returns (nbr_start int64 [T+1], nbr_idx int32 [E])."""
+    L = tree.n_leaves
+    if targets is None:
+        targets = np.arange(L, dtype=np.int32)
+    targets = _c(targets, np.int32)
+    T = targets.shape[0]
+    start = np.zeros(T + 1, dtype=np.int64)
+    lib = _load()
+    inst = tree.inst if tree.inst is not None else None
+    total = lib.orc_neighbors(L, _p(tree.anchor), _p(tree.size), _p(inst), _p(targets), T,
+                              _p(start), None, 0)
+    idx = np.zeros(max(total, 1), dtype=np.int32)
+    lib.orc_neighbors(L, _p(tree.anchor), _p(tree.size), _p(inst), _p(targets), T, _p(start),
+                      _p(idx), total)
+    return start, idx[:total]
+
+
+# ---------------------------------------------------------------------------
+# Redundant layout
+# ---------------------------------------------------------------------------
+def red_offsets(tree: Tree, nbr_start, nbr_idx):
+    """Segment starts and self offsets of the redundant layout (Sec. 5.2.1:
+    data duplicated so each target reads one contiguous block)."""
+    L = tree.n_leaves
+    rs = np.zeros(L + 1, dtype=np.int64)
+    self_ = np.zeros(max(L, 1), dtype=np.int32)
+    S = _load().orc_red_offsets(L, _p(tree.leaf_start), _p(_c(nbr_start, np.int64)),
+                                _p(_c(nbr_idx, np.int32)), _p(rs), _p(self_))
+    return rs, self_[:L].copy(), int(S)
+
+
+def restructure_rows(tree: Tree, nbr_start, nbr_idx, red_start, src):
+    """Copy rows of `src` (caller order, first axis = point) into the
+    redundant layout, bit for bit."""
+    src = np.ascontiguousarray(src)
+    row_bytes = src.strides[0] if src.ndim > 0 else src.itemsize
+    S = int(red_start[-1])
+    out = np.zeros((S,) + src.shape[1:], dtype=src.dtype)
+    _load().orc_restructure_rows(tree.n_leaves, _p(tree.leaf_start), _p(tree.perm),
+                                 _p(_c(nbr_start, np.int64)), _p(_c(nbr_idx, np.int32)),
+                                 _p(_c(red_start, np.int64)), _p(src), row_bytes, _p(out))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Gravity
+# ---------------------------------------------------------------------------
+def gravity_leaves(x, y, z, m, eps, tree: Tree, sel, sel_nbr_start, sel_nbr_idx):
+    """Near-field gravity for the particles of the selected leaves (reading R1:
+    G = 1, phi negative, Plummer softening).  Returns (caller idx, phi, ax, ay, az)."""
+    x, y, z, m = (_c(v, np.float64) for v in (x, y, z, m))
+    sel = _c(sel, np.int32)
+    occ = np.diff(tree.leaf_start)
+    T = int(occ[sel].sum()) if sel.shape[0] else 0
+    idx = np.zeros(max(T, 1), dtype=np.int32)
+    outs = [np.zeros(max(T, 1)) for _ in range(4)]
+    _load().orc_gravity_leaves(_p(x), _p(y), _p(z), _p(m), float(eps), _p(tree.perm),
+                               _p(tree.leaf_start), _p(sel), sel.shape[0],
+                               _p(_c(sel_nbr_start, np.int64)), _p(_c(sel_nbr_idx, np.int32)),
+                               _p(idx), *[_p(o) for o in outs])
+    return (idx[:T],) + tuple(o[:T] for o in outs)
+
+
+def gravity(x, y, z, m, eps, tree: Tree, nbr=None):
+    """Near-field gravity for every particle, in caller order."""
+    if nbr is None:
+        nbr = neighbors(tree)
+    sel = np.arange(tree.n_leaves, dtype=np.int32)
+    idx, p, ax, ay, az = gravity_leaves(x, y, z, m, eps, tree, sel, *nbr)
+    n = len(x)
+    out = [np.zeros(n) for _ in range(4)]
+    for o, v in zip(out, (p, ax, ay, az)):
+        o[idx] = v
+    return tuple(out)
+
+
+def gravity_adjoint_leaves(x, y, z, m, eps, gp, gax, gay, gaz, tree: Tree, sel, sel_nbr_start,
+                           sel_nbr_idx):
+    """Reverse-mode derivative of near-field gravity w.r.t. m and x for the
+    particles of the selected leaves.  Returns (caller idx, gm, gx, gy, gz)."""
+    arrs = [_c(v, np.float64) for v in (x, y, z, m, gp, gax, gay, gaz)]
+    sel = _c(sel, np.int32)
+    occ = np.diff(tree.leaf_start)
+    T = int(occ[sel].sum()) if sel.shape[0] else 0
+    idx = np.zeros(max(T, 1), dtype=np.int32)
+    outs = [np.zeros(max(T, 1)) for _ in range(4)]
+    _load().orc_gravity_adjoint_leaves(*[_p(a) for a in arrs[:4]], float(eps),
+                                       *[_p(a) for a in arrs[4:]], _p(tree.perm),
+                                       _p(tree.leaf_start), _p(sel), sel.shape[0],
+                                       _p(_c(sel_nbr_start, np.int64)),
+                                       _p(_c(sel_nbr_idx, np.int32)), _p(idx),
+                                       *[_p(o) for o in outs])
+    return (idx[:T],) + tuple(o[:T] for o in outs)
+
+
+def gravity_adjoint(x, y, z, m, eps, gp, gax, gay, gaz, tree: Tree, nbr=None):
+    if nbr is None:
+        nbr = neighbors(tree)
+    sel = np.arange(tree.n_leaves, dtype=np.int32)
+    idx, gm, gx, gy, gz = gravity_adjoint_leaves(x, y, z, m, eps, gp, gax, gay, gaz, tree, sel,
+                                                 *nbr)
+    n = len(x)
+    out = [np.zeros(n) for _ in range(4)]
+    for o, v in zip(out, (gm, gx, gy, gz)):
+        o[idx] = v
+    return tuple(out)
+
+
+# ---------------------------------------------------------------------------
+# Helmholtz
+# ---------------------------------------------------------------------------
+def _grid_args(n_side, h=None, kw=None):
+    n_side = _c(n_side, np.int32)
+    if h is None:
+        h = 1.0 / n_side.astype(np.float64)
+    if kw is None:
+        kw = 2.0 * np.pi / (10.0 * np.asarray(h, dtype=np.float64))
+    off = grid_offsets(n_side)
+    return n_side, _c(h, np.float64), _c(kw, np.float64), off
+
+
+def helmholtz(n_side, q, targets=None, h=None, kw=None):
+    """u_I = sum_{J near I, J != I} e^{ik r}/(4 pi r) q_J on regular grids
+    (Sec. 5.1; reading R3/R4: 3-D kernel, cell-centred points, k = 2 pi/(10 h)).
+    q: complex [N, nrhs] (or [N]) in caller order.  Returns complex128
+    [len(targets), nrhs] (or [len(targets)])."""
+    n_side, h, kw, off = _grid_args(n_side, h, kw)
+    q = np.asarray(q)
+    vec = q.ndim == 1
+    q2 = _c(q.reshape(q.shape[0], -1), np.complex128)
+    n, nrhs = q2.shape
+    if targets is None:
+        targets = np.arange(n, dtype=np.int64)
+    targets = _c(targets, np.int64)
+    u = np.zeros((targets.shape[0], nrhs), dtype=np.complex128)
+    _load().orc_helmholtz(n_side.shape[0], _p(n_side), _p(h), _p(kw), _p(off), nrhs, _p(q2),
+                          _p(targets), targets.shape[0], _p(u))
+    return u[:, 0] if vec else u
+
+
+def helmholtz_transpose(n_side, g, h=None, kw=None):
+    """(A^T g)_J = sum_I A_IJ g_I by scattering (adjoint of the near-field
+    Helmholtz operator)."""
+    n_side, h, kw, off = _grid_args(n_side, h, kw)
+    g = np.asarray(g)
+    vec = g.ndim == 1
+    g2 = _c(g.reshape(g.shape[0], -1), np.complex128)
+    n, nrhs = g2.shape
+    out = np.zeros((n, nrhs), dtype=np.complex128)
+    _load().orc_helmholtz_transpose(n_side.shape[0], _p(n_side), _p(h), _p(kw), _p(off), n, nrhs,
+                                    _p(g2), _p(out))
+    return out[:, 0] if vec else out
+
+
+# ---------------------------------------------------------------------------
+# Locality
+# ---------------------------------------------------------------------------
+def locality(nbr_start, nbr_idx, n, S, bytes_per_entry, cache_bytes):
+    """Definition 1 with Formulas (10)/(11) (Sec. 3.4); reading R19: D = runs
+    of consecutive leaf ids, V = whole footprint per layout, C = cache bytes."""
+    out = np.zeros(6)
+    nbr_start = _c(nbr_start, np.int64)
+    _load().orc_locality(nbr_start.shape[0] - 1, _p(nbr_start), _p(_c(nbr_idx, np.int32)), n, S,
+                         float(bytes_per_entry), float(cache_bytes), _p(out))
+    keys = ["D_mean", "V_gather", "V_red", "D_ratio", "V_ratio", "locality"]
+    return dict(zip(keys, out.tolist()))
+
+
+def pair_count(tree: Tree, nbr_start, nbr_idx):
+    """Ordered near pairs, self excluded: sum_A occ(A) sum_{B in nbr(A)} occ(B) - N."""
+    occ = np.diff(tree.leaf_start).astype(np.int64)
+    seg = np.add.reduceat(occ[nbr_idx], nbr_start[:-1]) if nbr_idx.shape[0] else np.zeros(0)
+    seg = np.where(np.diff(nbr_start) > 0, seg, 0)
+    return int((occ * seg).sum() - occ.sum())
