@@ -1,0 +1,257 @@
+/*
+ * p2p.h -- C ABI of libp2p, the MI355X (gfx950) near-field (P2P) operator of
+ * the multilevel fast multipole algorithm, with the data-redundancy layout of
+ * arXiv 2511.21535 ("Modeling the Effect of Data Redundancy on Speedup in
+ * MLFMA Near-Field Computation").
+ *
+ * The operator (Sec. 1 and Sec. 2.1 of the paper): every target in a leaf box
+ * interacts directly with every source in the leaf itself and in the leaf
+ * boxes around it (the order-1-box stencil of Sec. 2.2, the E2 neighbourhood
+ * of Sec. 5.1).  Two layouts feed the same sum:
+ *   - GATHER: sources are read from the box-sorted arrays through the
+ *     near-field lists (the paper's SoA + indexing baseline, Sec. 5.2.1);
+ *   - REDUNDANT: each target box's near sources are first copied into one
+ *     contiguous segment (the paper's data redundancy, Sec. 1.1, Sec. 5.2.1),
+ *     a restructuring step timed on its own (Proposition 2, Eq. 2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every array argument is a DEVICE pointer owned by the caller, unless it
+ *    is documented as a host pointer.  The library never allocates or frees
+ *    device memory: scratch space comes from `ws`.
+ *  - Workspace protocol: call with ws == NULL to get the required size in
+ *    *ws_bytes (returns P2P_OK and does nothing else); then call again with a
+ *    device buffer of at least that many bytes, 256-byte aligned, and
+ *    *ws_bytes set to its size.
+ *  - All work is enqueued on `stream` (a hipStream_t; NULL = the null
+ *    stream).  p2p_build_tree, p2p_build_neighbors and
+ *    p2p_restructure_redundant read a count back to the host and therefore
+ *    synchronise `stream`; the evaluation and adjoint calls do not.
+ *  - Validation happens on the host before any launch.  On P2P_EINVAL,
+ *    P2P_EDOMAIN or P2P_ECAPACITY no output has been written (except the
+ *    documented count fields).  On P2P_EHIP the outputs are undefined.
+ *    Faults inside kernels surface at the next synchronising call.
+ *  - p2p_last_error() describes the last failure on the calling thread.
+ *  - Calls on different streams may run concurrently; calls that share a
+ *    workspace buffer must not overlap.
+ *
+ * Readings of the paper (it gives no kernel formulas; these are the ones this
+ * library adopts):
+ *  - gravity: G = 1, Plummer softening, phi_i = -sum m_j (r^2+eps^2)^{-1/2},
+ *    a_i = -sum m_j (x_i-x_j)(r^2+eps^2)^{-3/2}, the self pair j = i excluded;
+ *  - Helmholtz: G(r) = e^{ikr}/(4 pi r) in 3-D, r = 0 excluded;
+ *  - near field: leaves whose closed cubes touch, the leaf itself included,
+ *    no periodic images;
+ *  - the redundancy grain is the target box.
+ */
+#ifndef P2P_H
+#define P2P_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void *p2p_stream_t; /* hipStream_t */
+
+typedef enum {
+    P2P_OK = 0,
+    P2P_EINVAL = 1,       /* bad argument (null pointer, negative size, bad mode, ws too small) */
+    P2P_EDOMAIN = 2,      /* a particle coordinate outside [0,1) (or NaN) */
+    P2P_ECAPACITY = 3,    /* an output capacity is too small; the count field holds the need */
+    P2P_EHIP = 4,         /* a HIP runtime call failed */
+    P2P_EUNSUPPORTED = 5  /* valid but not provided combination */
+} p2p_status;
+
+typedef enum { P2P_GATHER = 0, P2P_REDUNDANT = 1 } p2p_layout;
+
+/* P2P_FP64: every operation in double precision.
+ * P2P_FP32_MIXED: pair arithmetic in single precision; double precision only
+ * for the coordinate differences of each pair (rounded to single afterwards)
+ * and for the per-target accumulation of single-precision partial sums
+ * (at most 32 pair terms each).  Helmholtz multi-RHS blocks run on FP32
+ * matrix cores. */
+typedef enum { P2P_FP64 = 0, P2P_FP32_MIXED = 1 } p2p_precision;
+
+enum { P2P_TREE_PARTICLES = 0, P2P_TREE_GRIDS = 1 };
+enum { P2P_KIND_GRAVITY = 0, P2P_KIND_HELMHOLTZ = 1 };
+
+/* One regular-grid instance (host struct).  n_side^3 points, cell-centred at
+ * ((i+0.5)h, (j+0.5)h, (k+0.5)h), caller index point_off + i + n(j + n k).
+ * Instances are concatenated in caller order: point_off of instance g+1 is
+ * point_off[g] + n_side[g]^3, and point_off[0] = 0. */
+typedef struct {
+    int32_t n_side;   /* multiple of 4, 4..1024 */
+    int32_t reserved; /* must be 0 */
+    double h;         /* spacing > 0 */
+    double k;         /* wavenumber >= 0 */
+    int64_t point_off;
+} p2p_grid;
+
+/* Octree (particles) or box grid (grids).  Host struct holding device
+ * pointers.  Keys:
+ *   particles: c_d = floor(x_d 2^20), key = Morton(c) (bit 3b of the key is
+ *     bit b of c_x, 3b+1 of c_y, 3b+2 of c_z), 60 bits;
+ *   grids: with b = smallest integer >= 2 such that 2^b >= max n_side,
+ *     key = (g << 3b) | Morton_b(i, j, k).
+ * perm lists caller indices sorted stably by (key, caller index).
+ * Leaves (never empty) are in ascending key order; leaf_key is the key of the
+ * leaf's lower corner, leaf_level its level (particles: a level-l leaf has
+ * edge 2^-l; grids: b - 2, boxes of 4x4x4 points). */
+typedef struct {
+    int64_t n;           /* in: number of points */
+    int64_t cap_leaves;  /* in: capacity of leaf_key/leaf_level (leaf_start: cap_leaves+1);
+                            cap_leaves >= n always suffices */
+    int64_t n_leaves;    /* out: L */
+    int32_t kind;        /* out: P2P_TREE_PARTICLES or P2P_TREE_GRIDS */
+    int32_t key_bits;    /* out: bits per axis of the key space (20, or b for grids) */
+    int32_t max_level;   /* out: deepest leaf level */
+    int32_t n_grids;     /* out: number of grid instances (0 for particles) */
+    int32_t *perm;       /* device [n]: sorted slot -> caller index */
+    int32_t *leaf_start; /* device [L+1]: first sorted slot of each leaf; leaf_start[L] = n */
+    uint64_t *leaf_key;  /* device [L] */
+    int8_t *leaf_level;  /* device [L] */
+} p2p_tree;
+
+/* Near-field lists in CSR form: nbr(A) = nbr_idx[nbr_start[A] .. nbr_start[A+1]),
+ * every leaf whose closed cube touches A's (same grid instance), A included,
+ * ascending. */
+typedef struct {
+    int64_t cap;        /* in: capacity of nbr_idx */
+    int64_t count;      /* out: E = total entries (also on P2P_ECAPACITY) */
+    int64_t *nbr_start; /* device [L+1] */
+    int32_t *nbr_idx;   /* device [cap] */
+} p2p_nbrs;
+
+/* Redundant layout.  Segment A = entries [red_start[A], red_start[A+1]) holds,
+ * for B in nbr(A) in order, the rows of B's sorted slots in order; A's own
+ * rows start at red_start[A] + red_self[A].  S = red_start[L] entries.
+ * Payload planes (device):
+ *   gravity FP64:   planes = {x, y, z, m}, each double[S];
+ *   gravity FP32_MIXED: planes = {x, y, z} double[S], planes[3] = m float[S];
+ *   Helmholtz: planes[0] = q rows, [S][nrhs] complex (float2 for FP32_MIXED,
+ *     double2 for FP64); planes[1..3] unused. */
+typedef struct {
+    int64_t cap;        /* in: capacity in entries of every plane */
+    int64_t count;      /* out: S (also on P2P_ECAPACITY) */
+    int64_t *red_start; /* device [L+1] */
+    int32_t *red_self;  /* device [L] */
+    void *planes[4];
+    int32_t nrhs;       /* out: RHS per row (Helmholtz) */
+    int32_t kind;       /* out: P2P_KIND_* */
+    int32_t prec;       /* out: p2p_precision of the payload */
+    int32_t reserved;
+} p2p_redundant;
+
+/* Locality metric (Definition 1, Formulas (10)-(11) of the paper). */
+typedef struct {
+    double d_mean;       /* mean over target leaves of D = runs of consecutive ids in nbr(A) */
+    double v_gather;     /* bytes of the gather layout: n * bytes_per_entry */
+    double v_red;        /* bytes of the redundant layout: S * bytes_per_entry */
+    double d_ratio;      /* D' = d_mean / 1 (the redundant layout has D = 1) */
+    double v_ratio;      /* V' = v_gather / v_red */
+    double locality;     /* D' V' if v_red <= cache_bytes (10), else V'/D' (11) */
+    int64_t pairs;       /* ordered near pairs, self excluded */
+    int64_t entries;     /* S */
+} p2p_locality_t;
+
+/* Build the tree (a1: binning; Sec. 5.2, "tree rebuilding at each time step").
+ *  Particles: x, y, z caller-order double[n] in [0,1) (else P2P_EDOMAIN),
+ *    grids == NULL, n_grids == 0.  leaf_cap == 0: uniform tree of depth
+ *    `depth` (0..20, empty leaves dropped).  leaf_cap > 0: adaptive tree, a
+ *    node splits iff it holds more than leaf_cap points and its level is
+ *    below `depth` (1..20).
+ *  Grids: x = y = z = NULL, grids = host array of n_grids instances,
+ *    tree->n = total points; depth and leaf_cap ignored.
+ * Synchronises `stream` (reads L back).  P2P_ECAPACITY if L > cap_leaves
+ * (tree->n_leaves holds L). */
+p2p_status p2p_build_tree(const double *x, const double *y, const double *z,
+                          const p2p_grid *grids, int32_t n_grids,
+                          int32_t depth, int32_t leaf_cap,
+                          p2p_tree *tree, void *ws, size_t *ws_bytes, p2p_stream_t stream);
+
+/* Near-field lists of every leaf (a2: the E2 neighbourhood, Sec. 5.1;
+ * Fig. 8 counts them for irregular trees).  nbrs->nbr_start must hold L+1
+ * entries.  Synchronises `stream`; P2P_ECAPACITY if E > nbrs->cap. */
+p2p_status p2p_build_neighbors(const p2p_tree *tree, p2p_nbrs *nbrs,
+                               void *ws, size_t *ws_bytes, p2p_stream_t stream);
+
+/* Restructure to the redundant layout (a3: data redundancy, Sec. 1.1 and
+ * Sec. 5.2.1; its cost is the "collect" term of Eq. 2).
+ *  Gravity trees (particles): src = {x, y, z, m} caller-order double[n];
+ *    the payload follows `prec` (FP32_MIXED stores m rounded to float).
+ *  Helmholtz trees (grids): src[0] = q caller-order [n][nrhs] complex
+ *    (float2 for FP32_MIXED, double2 for FP64), src[1..3] ignored.
+ * out->red_start (L+1), out->red_self (L) and the planes must be allocated;
+ * P2P_ECAPACITY (out->count = S) if S > out->cap.  Synchronises `stream`. */
+p2p_status p2p_restructure_redundant(const p2p_tree *tree, const p2p_nbrs *nbrs,
+                                     const void *const src[4], int32_t nrhs,
+                                     p2p_precision prec, p2p_redundant *out,
+                                     void *ws, size_t *ws_bytes, p2p_stream_t stream);
+
+/* Near-field gravity (a4 GATHER / a5 REDUNDANT, update a6 fused): for every
+ * particle i, phi_i and a_i as in the header comment, eps >= 0 (eps == 0
+ * drops pairs at zero distance).  x, y, z, m: caller-order double[n] (needed
+ * for GATHER; ignored for REDUNDANT, which reads `red`, built with the same
+ * precision).  Outputs phi, ax, ay, az: caller-order double[n], overwritten. */
+p2p_status p2p_eval_gravity(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2p_redundant *red,
+                            p2p_layout layout, p2p_precision prec, double eps,
+                            const double *x, const double *y, const double *z, const double *m,
+                            double *phi, double *ax, double *ay, double *az,
+                            void *ws, size_t *ws_bytes, p2p_stream_t stream);
+
+/* Near-field Helmholtz on grid trees (a7 single RHS, a9 multi-RHS, a10
+ * batched persistent launch): u_I = sum_{J near I, J != I} e^{ik r}/(4 pi r) q_J
+ * for each of the nrhs columns, with h and k of I's instance.  grids: the host
+ * array the tree was built from.  q (GATHER) and u: caller order [n][nrhs],
+ * float2 (FP32_MIXED) or double2 (FP64) interleaved complex.  REDUNDANT reads
+ * q from `red` (built with the same precision and nrhs).  FP32_MIXED with
+ * nrhs a multiple of 16 runs on FP32 matrix cores in one persistent launch
+ * over all boxes of all instances; `tile` (host, may be NULL = default)
+ * selects the launch shape the autotuner picked: tile[0] = boxes per
+ * workgroup (1, 2 or 4), tile[1] = workgroups per CU (1..8). */
+p2p_status p2p_eval_helmholtz(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2p_redundant *red,
+                              p2p_layout layout, p2p_precision prec,
+                              const p2p_grid *grids, int32_t n_grids, int32_t nrhs,
+                              const void *q, void *u, const int32_t *tile,
+                              void *ws, size_t *ws_bytes, p2p_stream_t stream);
+
+/* Adjoint (a11; not in the paper).
+ *  kind == P2P_KIND_GRAVITY: fwd_in = {x, y, z, m}, grad_out = {g_phi, g_ax,
+ *    g_ay, g_az}, grad_in = {g_x, g_y, g_z, g_m}, all caller-order double[n]:
+ *    the gradients of L = sum_i g_phi_i phi_i + g_a_i . a_i with respect to
+ *    positions and masses (tree frozen), eps > 0.  GATHER layout.
+ *  kind == P2P_KIND_HELMHOLTZ: grad_out[0] = g (caller order [n][nrhs]
+ *    complex), grad_in[0] = A^T g, or conj(A^T conj(g)) = A^H g when
+ *    `conjugate` is 1 (PyTorch's convention for complex gradients).  The
+ *    near-field Helmholtz matrix is symmetric (reciprocity G(x,y) = G(y,x)
+ *    and a symmetric near relation), so A^T = A.  grids/n_grids as for
+ *    p2p_eval_helmholtz; fwd_in ignored. */
+p2p_status p2p_adjoint(int32_t kind, const p2p_tree *tree, const p2p_nbrs *nbrs,
+                       const p2p_redundant *red, p2p_layout layout, p2p_precision prec,
+                       double eps, const p2p_grid *grids, int32_t n_grids, int32_t nrhs,
+                       int32_t conjugate,
+                       const void *const fwd_in[4], const void *const grad_out[4],
+                       void *const grad_in[4], void *ws, size_t *ws_bytes, p2p_stream_t stream);
+
+/* Locality metric per configuration (a12; Definition 1 and Formulas (10)-(11),
+ * Sec. 3.4).  D per target leaf is counted on the GPU from the near lists;
+ * the rest is host arithmetic.  red may be NULL (S is then computed from the
+ * lists).  Synchronises `stream`. */
+p2p_status p2p_locality(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2p_redundant *red,
+                        double bytes_per_entry, double cache_bytes, p2p_locality_t *out,
+                        void *ws, size_t *ws_bytes, p2p_stream_t stream);
+
+/* Description of the last failure on the calling thread; valid until the
+ * next p2p_* call on that thread.  Never NULL. */
+const char *p2p_last_error(void);
+
+/* Library version string. */
+const char *p2p_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* P2P_H */

@@ -56,6 +56,8 @@ F64 = ctypes.c_double
 
 
 def _declare(lib):
+    lib.orc_threads.restype = ctypes.c_int
+    lib.orc_threads.argtypes = []
     lib.orc_morton3.restype = ctypes.c_uint64
     lib.orc_morton3.argtypes = [ctypes.c_uint32] * 3 + [ctypes.c_int]
     lib.orc_particle_keys.restype = I64
@@ -93,6 +95,11 @@ def _p(a):
 
 def _c(a, dtype):
     return np.ascontiguousarray(a, dtype=dtype)
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(_load().orc_threads())
 
 
 # ---------------------------------------------------------------------------

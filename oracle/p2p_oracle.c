@@ -21,12 +21,25 @@
  * independent targets between threads; no loop is blocked or reordered.
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
 #define ORC_DEPTH_BITS 20           /* particle keys: 20 bits per axis */
 #define ORC_PI 3.14159265358979323846
+
+/* Number of OpenMP threads the parallel loops below use. */
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------------ */
 /* Keys                                                                     */

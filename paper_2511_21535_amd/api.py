@@ -1,0 +1,353 @@
+"""Torch-facing API of libp2p: device memory from torch, work on torch's
+current stream, every step in the library's HIP kernels.
+
+    tree = Tree.build_particles(x, y, z, depth=20, leaf_cap=64)
+    nbrs = tree.neighbors()
+    red  = restructure_gravity(tree, nbrs, x, y, z, m, prec="fp32")
+    phi, ax, ay, az = gravity(tree, nbrs, eps, x=x, y=y, z=z, m=m)                 # gather
+    phi, ax, ay, az = gravity(tree, nbrs, eps, red=red, layout="redundant", prec="fp32")
+
+Nothing here computes any part of the operator on the host or with torch
+arithmetic; torch only allocates and provides the stream.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence, Tuple
+
+import torch
+
+from . import _lib as L
+
+PREC = {"fp64": L.P2P_FP64, "fp32": L.P2P_FP32_MIXED, "fp32_mixed": L.P2P_FP32_MIXED}
+LAYOUT = {"gather": L.P2P_GATHER, "redundant": L.P2P_REDUNDANT}
+
+
+def _require_device(t: torch.Tensor, name: str, dtype=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    return t
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _workspace(call, device) -> Tuple[torch.Tensor, ctypes.c_size_t]:
+    """Run `call(ws, ws_bytes)` once with ws = NULL to size the workspace,
+    allocate it from torch, and return it with its size."""
+    nbytes = ctypes.c_size_t(0)
+    L.check(call(None, ctypes.byref(nbytes)))
+    ws = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=device)
+    nbytes = ctypes.c_size_t(ws.numel())
+    return ws, nbytes
+
+
+def _call(call, device):
+    ws, nbytes = _workspace(call, device)
+    st = call(_ptr(ws), ctypes.byref(nbytes))
+    return st, ws
+
+
+@dataclass
+class Grid:
+    """One grid instance: n_side^3 cell-centred points, spacing h, wavenumber k."""
+    n_side: int
+    h: float
+    k: float
+
+
+def grids_struct(grids: Sequence[Grid]):
+    arr = (L.p2p_grid * len(grids))()
+    off = 0
+    for i, g in enumerate(grids):
+        arr[i].n_side = int(g.n_side)
+        arr[i].reserved = 0
+        arr[i].h = float(g.h)
+        arr[i].k = float(g.k)
+        arr[i].point_off = off
+        off += int(g.n_side) ** 3
+    return arr, off
+
+
+@dataclass
+class Tree:
+    n: int
+    n_leaves: int
+    kind: int
+    key_bits: int
+    max_level: int
+    perm: torch.Tensor
+    leaf_start: torch.Tensor
+    leaf_key: torch.Tensor
+    leaf_level: torch.Tensor
+    grids: List[Grid] = field(default_factory=list)
+
+    def struct(self) -> L.p2p_tree:
+        t = L.p2p_tree()
+        t.n, t.cap_leaves, t.n_leaves = self.n, self.leaf_key.numel(), self.n_leaves
+        t.kind, t.key_bits, t.max_level, t.n_grids = self.kind, self.key_bits, self.max_level, len(self.grids)
+        t.perm = self.perm.data_ptr()
+        t.leaf_start = self.leaf_start.data_ptr()
+        t.leaf_key = self.leaf_key.data_ptr()
+        t.leaf_level = self.leaf_level.data_ptr()
+        return t
+
+    @staticmethod
+    def _build(x, y, z, grids, n, depth, leaf_cap, device) -> "Tree":
+        perm = torch.empty(max(n, 1), dtype=torch.int32, device=device)
+        leaf_start = torch.empty(n + 1, dtype=torch.int32, device=device)
+        leaf_key = torch.empty(max(n, 1), dtype=torch.int64, device=device)
+        leaf_level = torch.empty(max(n, 1), dtype=torch.int8, device=device)
+        t = L.p2p_tree()
+        t.n, t.cap_leaves = n, n
+        t.perm, t.leaf_start = perm.data_ptr(), leaf_start.data_ptr()
+        t.leaf_key, t.leaf_level = leaf_key.data_ptr(), leaf_level.data_ptr()
+        gs, ng = (None, 0)
+        if grids is not None:
+            gs, _ = grids_struct(grids)
+            ng = len(grids)
+
+        def call(ws, nb):
+            return L.p2p_build_tree(_ptr(x), _ptr(y), _ptr(z), gs, ng, depth, leaf_cap,
+                                    ctypes.byref(t), ws, nb, _stream())
+        st, _ = _call(call, device)
+        L.check(st)
+        nl = int(t.n_leaves)
+        return Tree(n=n, n_leaves=nl, kind=int(t.kind), key_bits=int(t.key_bits),
+                    max_level=int(t.max_level), perm=perm[:n] if n else perm[:0],
+                    leaf_start=leaf_start[: nl + 1], leaf_key=leaf_key[:nl],
+                    leaf_level=leaf_level[:nl], grids=list(grids) if grids else [])
+
+    @staticmethod
+    def build_particles(x, y, z, depth: int = 20, leaf_cap: int = 64) -> "Tree":
+        """Octree over [0,1)^3: uniform of depth `depth` if leaf_cap == 0, else
+        adaptive (split iff more than leaf_cap points and level < depth)."""
+        for nm, v in (("x", x), ("y", y), ("z", z)):
+            _require_device(v, nm, torch.float64)
+        return Tree._build(x, y, z, None, x.numel(), depth, leaf_cap, x.device)
+
+    @staticmethod
+    def build_grids(grids: Sequence[Grid], device="cuda") -> "Tree":
+        """Boxes of 4x4x4 points over one or more regular grids."""
+        n = sum(int(g.n_side) ** 3 for g in grids)
+        return Tree._build(None, None, None, list(grids), n, 0, 0, torch.device(device))
+
+    def neighbors(self, cap: Optional[int] = None) -> "Nbrs":
+        return build_neighbors(self, cap)
+
+
+@dataclass
+class Nbrs:
+    count: int
+    nbr_start: torch.Tensor
+    nbr_idx: torch.Tensor
+
+    def struct(self) -> L.p2p_nbrs:
+        s = L.p2p_nbrs()
+        s.cap, s.count = self.nbr_idx.numel(), self.count
+        s.nbr_start, s.nbr_idx = self.nbr_start.data_ptr(), self.nbr_idx.data_ptr()
+        return s
+
+
+def build_neighbors(tree: Tree, cap: Optional[int] = None) -> Nbrs:
+    dev = tree.leaf_start.device
+    Lv = tree.n_leaves
+    if cap is None:
+        cap = 32 * max(Lv, 1)
+    ts = tree.struct()
+    for _ in range(2):
+        start = torch.empty(Lv + 1, dtype=torch.int64, device=dev)
+        idx = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        s = L.p2p_nbrs()
+        s.cap, s.nbr_start, s.nbr_idx = cap, start.data_ptr(), idx.data_ptr()
+
+        def call(ws, nb):
+            return L.p2p_build_neighbors(ctypes.byref(ts), ctypes.byref(s), ws, nb, _stream())
+        st, _ = _call(call, dev)
+        if st == L.P2P_ECAPACITY:
+            cap = int(s.count)
+            continue
+        L.check(st)
+        return Nbrs(count=int(s.count), nbr_start=start, nbr_idx=idx[: int(s.count)])
+    raise L.P2PError(L.P2P_ECAPACITY, "near-list capacity retry failed")
+
+
+@dataclass
+class Redundant:
+    count: int
+    red_start: torch.Tensor
+    red_self: torch.Tensor
+    planes: List[Optional[torch.Tensor]]
+    nrhs: int
+    kind: int
+    prec: int
+
+    def struct(self) -> L.p2p_redundant:
+        s = L.p2p_redundant()
+        s.cap = self.planes[0].shape[0] if self.planes[0] is not None else 0
+        s.count = self.count
+        s.red_start, s.red_self = self.red_start.data_ptr(), self.red_self.data_ptr()
+        for i in range(4):
+            s.planes[i] = self.planes[i].data_ptr() if self.planes[i] is not None else None
+        s.nrhs, s.kind, s.prec = self.nrhs, self.kind, self.prec
+        return s
+
+
+def redundant_entries(tree: Tree, nbrs: Nbrs) -> int:
+    """S, the number of entries of the redundant layout (counted on the GPU)."""
+    return locality(tree, nbrs)["entries"]
+
+
+def _alloc_red(tree, kind, prec, S, nrhs, dev):
+    if kind == L.P2P_KIND_GRAVITY:
+        planes = [torch.empty(max(S, 1), dtype=torch.float64, device=dev) for _ in range(3)]
+        planes.append(torch.empty(max(S, 1), dtype=torch.float32 if prec == L.P2P_FP32_MIXED
+                                  else torch.float64, device=dev))
+    else:
+        cd = torch.complex64 if prec == L.P2P_FP32_MIXED else torch.complex128
+        planes = [torch.empty((max(S, 1), nrhs), dtype=cd, device=dev), None, None, None]
+    return planes
+
+
+def restructure(tree: Tree, nbrs: Nbrs, src: Sequence[Optional[torch.Tensor]], prec="fp64",
+                nrhs: int = 1, S: Optional[int] = None, out: Optional[Redundant] = None) -> Redundant:
+    """Restructure into the redundant layout.  Pass `out` (a Redundant of the
+    right capacity) to reuse its buffers; pass S to skip the size query."""
+    p = PREC[prec]
+    dev = tree.leaf_start.device
+    kind = L.P2P_KIND_GRAVITY if tree.kind == L.P2P_TREE_PARTICLES else L.P2P_KIND_HELMHOLTZ
+    if out is None:
+        if S is None:
+            S = redundant_entries(tree, nbrs)
+        out = Redundant(count=0, red_start=torch.empty(tree.n_leaves + 1, dtype=torch.int64, device=dev),
+                        red_self=torch.empty(max(tree.n_leaves, 1), dtype=torch.int32, device=dev),
+                        planes=_alloc_red(tree, kind, p, S, nrhs, dev), nrhs=nrhs, kind=kind, prec=p)
+    srcs = L.PV4(*[_ptr(t) if t is not None else None for t in list(src) + [None] * (4 - len(src))])
+    ts, ns, rs = tree.struct(), nbrs.struct(), out.struct()
+
+    def call(ws, nb):
+        return L.p2p_restructure_redundant(ctypes.byref(ts), ctypes.byref(ns), ctypes.byref(srcs),
+                                           nrhs, p, ctypes.byref(rs), ws, nb, _stream())
+    st, _ = _call(call, dev)
+    L.check(st)
+    out.count, out.nrhs, out.kind, out.prec = int(rs.count), int(rs.nrhs), int(rs.kind), int(rs.prec)
+    return out
+
+
+def restructure_gravity(tree, nbrs, x, y, z, m, prec="fp64", **kw) -> Redundant:
+    return restructure(tree, nbrs, [x, y, z, m], prec=prec, **kw)
+
+
+def gravity(tree: Tree, nbrs: Nbrs, eps: float, x=None, y=None, z=None, m=None,
+            layout="gather", prec="fp64", red: Optional[Redundant] = None, out=None):
+    """Near-field potential and acceleration, caller order.  Returns (phi, ax, ay, az)."""
+    dev = tree.leaf_start.device
+    n = tree.n
+    if out is None:
+        out = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(4)]
+    ts, ns = tree.struct(), nbrs.struct()
+    rs = red.struct() if red is not None else None
+
+    def call(ws, nb):
+        return L.p2p_eval_gravity(ctypes.byref(ts), ctypes.byref(ns),
+                                  ctypes.byref(rs) if rs is not None else None,
+                                  LAYOUT[layout], PREC[prec], float(eps), _ptr(x), _ptr(y), _ptr(z),
+                                  _ptr(m), *[_ptr(o) for o in out], ws, nb, _stream())
+    st, ws = _call(call, dev)
+    L.check(st)
+    return tuple(out)
+
+
+def helmholtz(tree: Tree, nbrs: Nbrs, q: Optional[torch.Tensor] = None, layout="gather",
+              prec="fp32", red: Optional[Redundant] = None, nrhs: Optional[int] = None,
+              tile: Optional[Sequence[int]] = None, out: Optional[torch.Tensor] = None):
+    """Near-field Helmholtz on the grids of `tree`.  q, u: [n, nrhs] (or [n])
+    complex64 (fp32) or complex128 (fp64), caller order."""
+    dev = tree.leaf_start.device
+    if nrhs is None:
+        nrhs = red.nrhs if red is not None else (1 if q.dim() == 1 else q.shape[1])
+    cd = torch.complex64 if PREC[prec] == L.P2P_FP32_MIXED else torch.complex128
+    if q is not None:
+        _require_device(q, "q", cd)
+    if out is None:
+        shape = (tree.n,) if (q is not None and q.dim() == 1) or (q is None and nrhs == 1) else (tree.n, nrhs)
+        out = torch.empty(shape, dtype=cd, device=dev)
+    gs, _ = grids_struct(tree.grids)
+    ts, ns = tree.struct(), nbrs.struct()
+    rs = red.struct() if red is not None else None
+    tl = (ctypes.c_int32 * 2)(*tile) if tile is not None else None
+
+    def call(ws, nb):
+        return L.p2p_eval_helmholtz(ctypes.byref(ts), ctypes.byref(ns),
+                                    ctypes.byref(rs) if rs is not None else None,
+                                    LAYOUT[layout], PREC[prec], gs, len(tree.grids), nrhs, _ptr(q),
+                                    _ptr(out), tl, ws, nb, _stream())
+    st, ws = _call(call, dev)
+    L.check(st)
+    return out
+
+
+def gravity_adjoint(tree: Tree, nbrs: Nbrs, eps: float, x, y, z, m, g_phi, g_ax, g_ay, g_az):
+    """Gradients (g_x, g_y, g_z, g_m) of sum g_phi.phi + g_a.a, FP64, tree frozen."""
+    dev = tree.leaf_start.device
+    outs = [torch.empty(tree.n, dtype=torch.float64, device=dev) for _ in range(4)]
+    fin = L.PV4(*[_ptr(t) for t in (x, y, z, m)])
+    gout = L.PV4(*[_ptr(t) for t in (g_phi, g_ax, g_ay, g_az)])
+    gin = L.PV4(*[_ptr(t) for t in outs])
+    ts, ns = tree.struct(), nbrs.struct()
+
+    def call(ws, nb):
+        return L.p2p_adjoint(L.P2P_KIND_GRAVITY, ctypes.byref(ts), ctypes.byref(ns), None,
+                             L.P2P_GATHER, L.P2P_FP64, float(eps), None, 0, 1, 0,
+                             ctypes.byref(fin), ctypes.byref(gout), ctypes.byref(gin), ws, nb,
+                             _stream())
+    st, ws = _call(call, dev)
+    L.check(st)
+    return tuple(outs)
+
+
+def helmholtz_adjoint(tree: Tree, nbrs: Nbrs, g: torch.Tensor, prec="fp64", conjugate=False):
+    """A^T g (conjugate=False) or A^H g = conj(A^T conj(g)) (conjugate=True)."""
+    dev = tree.leaf_start.device
+    nrhs = 1 if g.dim() == 1 else g.shape[1]
+    out = torch.empty_like(g)
+    gs, _ = grids_struct(tree.grids)
+    gout = L.PV4(_ptr(g), None, None, None)
+    gin = L.PV4(_ptr(out), None, None, None)
+    ts, ns = tree.struct(), nbrs.struct()
+
+    def call(ws, nb):
+        return L.p2p_adjoint(L.P2P_KIND_HELMHOLTZ, ctypes.byref(ts), ctypes.byref(ns), None,
+                             L.P2P_GATHER, PREC[prec], 0.0, gs, len(tree.grids), nrhs,
+                             1 if conjugate else 0, None, ctypes.byref(gout), ctypes.byref(gin),
+                             ws, nb, _stream())
+    st, ws = _call(call, dev)
+    L.check(st)
+    return out
+
+
+def locality(tree: Tree, nbrs: Nbrs, red: Optional[Redundant] = None, bytes_per_entry=32.0,
+             cache_bytes=32.0 * 2 ** 20) -> dict:
+    """Locality metric (Definition 1, Formulas (10)/(11)) plus exact pair and entry counts."""
+    dev = tree.leaf_start.device
+    ts, ns = tree.struct(), nbrs.struct()
+    rs = red.struct() if red is not None else None
+    out = L.p2p_locality_t()
+
+    def call(ws, nb):
+        return L.p2p_locality(ctypes.byref(ts), ctypes.byref(ns),
+                              ctypes.byref(rs) if rs is not None else None, float(bytes_per_entry),
+                              float(cache_bytes), ctypes.byref(out), ws, nb, _stream())
+    st, _ = _call(call, dev)
+    L.check(st)
+    return {f: getattr(out, f) for f, _ in L.p2p_locality_t._fields_}

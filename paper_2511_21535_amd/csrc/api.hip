@@ -1,0 +1,579 @@
+// C ABI entry points of libp2p: argument validation on the host, workspace
+// layout, and the launch sequence of every step.  See include/p2p.h.
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "p2p_internal.h"
+
+namespace p2p {
+
+namespace {
+thread_local std::string g_err;
+}  // namespace
+
+void set_error(const std::string &msg) { g_err = msg; }
+p2p_status fail(p2p_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+namespace {
+
+hipStream_t as_stream(p2p_stream_t s) { return static_cast<hipStream_t>(s); }
+
+// Workspace protocol shared by every entry point.  Returns true when the call
+// only asked for the size (ws == NULL).
+bool ws_query(void *ws, size_t *ws_bytes, const Arena &need, p2p_status *st) {
+    if (ws == nullptr) {
+        *ws_bytes = need.used;
+        *st = P2P_OK;
+        return true;
+    }
+    if (*ws_bytes < need.used) {
+        *st = fail(P2P_EINVAL, "workspace too small: need " + std::to_string(need.used) +
+                                   " bytes, got " + std::to_string(*ws_bytes));
+        return true;
+    }
+    if ((reinterpret_cast<uintptr_t>(ws) & 255u) != 0) {
+        *st = fail(P2P_EINVAL, "workspace must be 256-byte aligned");
+        return true;
+    }
+    return false;
+}
+
+int grid_bits_of(const p2p_grid *grids, int32_t n_grids) {
+    int mx = 4;
+    for (int32_t g = 0; g < n_grids; ++g) mx = grids[g].n_side > mx ? grids[g].n_side : mx;
+    int b = 2;
+    while ((1 << b) < mx) ++b;
+    return b;
+}
+
+int bits_for(int64_t v) {  // smallest b with 2^b >= v (v >= 1)
+    int b = 0;
+    while ((int64_t(1) << b) < v) ++b;
+    return b;
+}
+
+p2p_status check_grids(const p2p_grid *grids, int32_t n_grids, int64_t n) {
+    if (!grids || n_grids <= 0) return fail(P2P_EINVAL, "grids: need at least one instance");
+    int64_t off = 0;
+    for (int32_t g = 0; g < n_grids; ++g) {
+        const p2p_grid &G = grids[g];
+        if (G.n_side < 4 || G.n_side > 1024 || G.n_side % 4 != 0)
+            return fail(P2P_EINVAL, "grids[" + std::to_string(g) + "].n_side must be a multiple of 4 in 4..1024");
+        if (G.reserved != 0) return fail(P2P_EINVAL, "grids[].reserved must be 0");
+        if (!(G.h > 0.0) || !std::isfinite(G.h)) return fail(P2P_EINVAL, "grids[].h must be > 0");
+        if (!(G.k >= 0.0) || !std::isfinite(G.k)) return fail(P2P_EINVAL, "grids[].k must be >= 0");
+        if (G.point_off != off)
+            return fail(P2P_EINVAL, "grids[" + std::to_string(g) + "].point_off must be " + std::to_string(off));
+        off += static_cast<int64_t>(G.n_side) * G.n_side * G.n_side;
+    }
+    if (off != n) return fail(P2P_EINVAL, "grid points (" + std::to_string(off) + ") != tree->n (" + std::to_string(n) + ")");
+    return P2P_OK;
+}
+
+p2p_status check_tree(const p2p_tree *t) {
+    if (!t) return fail(P2P_EINVAL, "tree is NULL");
+    if (t->n < 0 || t->n_leaves < 0 || t->n_leaves > t->n) return fail(P2P_EINVAL, "tree: bad sizes (not built?)");
+    if (t->n > 0 && (!t->perm || !t->leaf_start || !t->leaf_key || !t->leaf_level))
+        return fail(P2P_EINVAL, "tree: NULL array");
+    if (t->kind != P2P_TREE_PARTICLES && t->kind != P2P_TREE_GRIDS) return fail(P2P_EINVAL, "tree: bad kind");
+    return P2P_OK;
+}
+
+p2p_status check_nbrs(const p2p_tree *t, const p2p_nbrs *nb) {
+    if (!nb) return fail(P2P_EINVAL, "nbrs is NULL");
+    if (t->n_leaves > 0 && (!nb->nbr_start || !nb->nbr_idx)) return fail(P2P_EINVAL, "nbrs: NULL array (not built?)");
+    if (nb->count < t->n_leaves) return fail(P2P_EINVAL, "nbrs: count < n_leaves (not built?)");
+    return P2P_OK;
+}
+
+}  // namespace
+}  // namespace p2p
+
+using namespace p2p;
+
+extern "C" const char *p2p_last_error(void) { return g_err.c_str(); }
+extern "C" const char *p2p_version(void) { return "libp2p 0.1.0 (gfx950)"; }
+
+// ------------------------------------------------------------------ a1 ----
+extern "C" p2p_status p2p_build_tree(const double *x, const double *y, const double *z,
+                                     const p2p_grid *grids, int32_t n_grids, int32_t depth,
+                                     int32_t leaf_cap, p2p_tree *tree, void *ws, size_t *ws_bytes,
+                                     p2p_stream_t stream) {
+    set_error("");
+    if (!tree || !ws_bytes) return fail(P2P_EINVAL, "tree and ws_bytes must not be NULL");
+    const int64_t n = tree->n;
+    if (n < 0) return fail(P2P_EINVAL, "tree->n < 0");
+    if (n > INT32_MAX) return fail(P2P_EINVAL, "tree->n exceeds 2^31-1");
+    const bool particles = (grids == nullptr);
+    int key_bits, sort_bits, leaf_depth = depth;
+    if (particles) {
+        if (n_grids != 0) return fail(P2P_EINVAL, "n_grids must be 0 for particles");
+        if (n > 0 && (!x || !y || !z)) return fail(P2P_EINVAL, "x, y, z must not be NULL");
+        if (leaf_cap < 0) return fail(P2P_EINVAL, "leaf_cap < 0");
+        if (depth < 0 || depth > 20) return fail(P2P_EINVAL, "depth must be in 0..20");
+        key_bits = 20;
+        sort_bits = 60;
+    } else {
+        if (x || y || z) return fail(P2P_EINVAL, "x, y, z must be NULL for grids");
+        P2P_TRY(check_grids(grids, n_grids, n));
+        key_bits = grid_bits_of(grids, n_grids);
+        sort_bits = 3 * key_bits + bits_for(n_grids);
+        if (sort_bits > 63) return fail(P2P_EINVAL, "grid key space exceeds 63 bits");
+        leaf_depth = key_bits - 2;
+    }
+    if (tree->cap_leaves < 0) return fail(P2P_EINVAL, "cap_leaves < 0");
+
+    Arena ar(ws);
+    uint64_t *keys = ar.take<uint64_t>(n);
+    uint64_t *keys_tmp = ar.take<uint64_t>(n);
+    int32_t *vals = ar.take<int32_t>(n);
+    int32_t *vals_tmp = ar.take<int32_t>(n);
+    uint32_t *hist = ar.take<uint32_t>(radix_hist_elems(n));
+    uint8_t *pair_common = ar.take<uint8_t>(n);
+    int8_t *level = ar.take<int8_t>(n);
+    int32_t *flags = ar.take<int32_t>(n);
+    int32_t *flag_scan = ar.take<int32_t>(n + 1);
+    int32_t *scan_tmp = ar.take<int32_t>(scan_ws_elems(n));
+    int32_t *counters = ar.take<int32_t>(2);   // [0] domain flag, [1] max level
+    int32_t *d_nside = ar.take<int32_t>(particles ? 1 : n_grids);
+    int64_t *d_off = ar.take<int64_t>(particles ? 1 : n_grids);
+    p2p_status st;
+    if (ws_query(ws, ws_bytes, ar, &st)) return st;
+    if (n > 0 && (!tree->perm || !tree->leaf_start || !tree->leaf_key || !tree->leaf_level))
+        return fail(P2P_EINVAL, "tree arrays must not be NULL");
+    if (!tree->leaf_start) return fail(P2P_EINVAL, "tree->leaf_start must not be NULL");
+    hipStream_t s = as_stream(stream);
+
+    tree->kind = particles ? P2P_TREE_PARTICLES : P2P_TREE_GRIDS;
+    tree->key_bits = key_bits;
+    tree->n_grids = particles ? 0 : n_grids;
+    if (n == 0) {
+        const int32_t zero = 0;
+        P2P_HIP(hipMemcpyAsync(tree->leaf_start, &zero, sizeof(zero), hipMemcpyHostToDevice, s));
+        P2P_HIP(hipStreamSynchronize(s));
+        tree->n_leaves = 0;
+        tree->max_level = 0;
+        return P2P_OK;
+    }
+    P2P_HIP(hipMemsetAsync(counters, 0, 2 * sizeof(int32_t), s));
+    if (particles) {
+        P2P_TRY(launch_particle_keys(x, y, z, n, keys, vals, &counters[0], s));
+    } else {
+        std::vector<int32_t> ns(n_grids);
+        std::vector<int64_t> off(n_grids);
+        for (int32_t g = 0; g < n_grids; ++g) {
+            ns[g] = grids[g].n_side;
+            off[g] = grids[g].point_off;
+        }
+        P2P_HIP(hipMemcpyAsync(d_nside, ns.data(), n_grids * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        P2P_HIP(hipMemcpyAsync(d_off, off.data(), n_grids * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        P2P_TRY(launch_grid_keys(d_nside, d_off, n_grids, key_bits, n, keys, vals, s));
+    }
+    P2P_TRY(radix_sort_pairs(keys, vals, keys_tmp, vals_tmp, n, sort_bits, hist, s));
+    P2P_TRY(launch_leaf_levels(keys, n, tree->kind, leaf_depth, particles ? leaf_cap : 0, pair_common,
+                               level, flags, s));
+    P2P_TRY((exclusive_scan<int32_t, int32_t>(flags, flag_scan, n, scan_tmp, s)));
+    int32_t host[2] = {0, 0};
+    P2P_HIP(hipMemcpyAsync(&host[0], &flag_scan[n], sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    P2P_HIP(hipMemcpyAsync(&host[1], &counters[0], sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    P2P_HIP(hipStreamSynchronize(s));
+    const int64_t L = host[0];
+    if (host[1] != 0) {
+        tree->n_leaves = 0;
+        return fail(P2P_EDOMAIN, "a particle coordinate lies outside [0,1) or is NaN");
+    }
+    if (L > tree->cap_leaves) {
+        tree->n_leaves = L;
+        return fail(P2P_ECAPACITY, "cap_leaves " + std::to_string(tree->cap_leaves) + " < " + std::to_string(L) + " leaves");
+    }
+    P2P_TRY(launch_leaf_write(keys, level, flags, flag_scan, n, tree->kind, key_bits, tree->leaf_start,
+                              tree->leaf_key, tree->leaf_level, &counters[1], s));
+    P2P_HIP(hipMemcpyAsync(tree->perm, vals, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    int32_t maxl = 0;
+    P2P_HIP(hipMemcpyAsync(&maxl, &counters[1], sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    P2P_HIP(hipStreamSynchronize(s));
+    tree->n_leaves = L;
+    tree->max_level = maxl;
+    return P2P_OK;
+}
+
+// ------------------------------------------------------------------ a2 ----
+extern "C" p2p_status p2p_build_neighbors(const p2p_tree *tree, p2p_nbrs *nbrs, void *ws,
+                                          size_t *ws_bytes, p2p_stream_t stream) {
+    set_error("");
+    if (!ws_bytes) return fail(P2P_EINVAL, "ws_bytes must not be NULL");
+    P2P_TRY(check_tree(tree));
+    if (!nbrs) return fail(P2P_EINVAL, "nbrs is NULL");
+    if (nbrs->cap < 0) return fail(P2P_EINVAL, "nbrs->cap < 0");
+    const int64_t L = tree->n_leaves;
+    Arena ar(ws);
+    int32_t *counts = ar.take<int32_t>(L);
+    int64_t *start = ar.take<int64_t>(L + 1);
+    int64_t *scan_tmp = ar.take<int64_t>(scan_ws_elems(L));
+    p2p_status st;
+    if (ws_query(ws, ws_bytes, ar, &st)) return st;
+    if (!nbrs->nbr_start) return fail(P2P_EINVAL, "nbrs->nbr_start must not be NULL");
+    hipStream_t s = as_stream(stream);
+    const int inst_shift = 3 * tree->key_bits;
+    P2P_TRY(launch_neighbors(tree->leaf_key, tree->leaf_level, L, tree->key_bits, inst_shift, nullptr,
+                             counts, nullptr, s));
+    P2P_TRY((exclusive_scan<int32_t, int64_t>(counts, start, L, scan_tmp, s)));
+    int64_t E = 0;
+    P2P_HIP(hipMemcpyAsync(&E, &start[L], sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    P2P_HIP(hipStreamSynchronize(s));
+    if (E > nbrs->cap) {
+        nbrs->count = E;
+        return fail(P2P_ECAPACITY, "nbrs->cap " + std::to_string(nbrs->cap) + " < " + std::to_string(E) + " entries");
+    }
+    if (E > 0 && !nbrs->nbr_idx) return fail(P2P_EINVAL, "nbrs->nbr_idx must not be NULL");
+    P2P_HIP(hipMemcpyAsync(nbrs->nbr_start, start, (L + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    P2P_TRY(launch_neighbors(tree->leaf_key, tree->leaf_level, L, tree->key_bits, inst_shift,
+                             nbrs->nbr_start, nullptr, nbrs->nbr_idx, s));
+    P2P_HIP(hipStreamSynchronize(s));
+    nbrs->count = E;
+    return P2P_OK;
+}
+
+// ------------------------------------------------------------------ a3 ----
+extern "C" p2p_status p2p_restructure_redundant(const p2p_tree *tree, const p2p_nbrs *nbrs,
+                                                const void *const src[4], int32_t nrhs,
+                                                p2p_precision prec, p2p_redundant *out, void *ws,
+                                                size_t *ws_bytes, p2p_stream_t stream) {
+    set_error("");
+    if (!ws_bytes) return fail(P2P_EINVAL, "ws_bytes must not be NULL");
+    P2P_TRY(check_tree(tree));
+    P2P_TRY(check_nbrs(tree, nbrs));
+    if (!out) return fail(P2P_EINVAL, "out is NULL");
+    if (prec != P2P_FP64 && prec != P2P_FP32_MIXED) return fail(P2P_EINVAL, "bad precision");
+    const bool grav = tree->kind == P2P_TREE_PARTICLES;
+    if (!grav && nrhs < 1) return fail(P2P_EINVAL, "nrhs must be >= 1");
+    if (grav) nrhs = 1;
+    const bool mixed = prec == P2P_FP32_MIXED;
+    const int64_t n = tree->n, L = tree->n_leaves;
+    const size_t csize = mixed ? sizeof(float2) : sizeof(double2);
+    Arena ar(ws);
+    int64_t *seg_len = ar.take<int64_t>(L);
+    int64_t *rstart = ar.take<int64_t>(L + 1);
+    int64_t *scan_tmp = ar.take<int64_t>(scan_ws_elems(L));
+    int32_t *rself = ar.take<int32_t>(L);
+    double *sx = nullptr, *sy = nullptr, *sz = nullptr;
+    void *sm = nullptr, *sq = nullptr;
+    if (grav) {
+        sx = ar.take<double>(n);
+        sy = ar.take<double>(n);
+        sz = ar.take<double>(n);
+        sm = ar.take<double>(n);
+    } else {
+        sq = ar.take<char>(static_cast<size_t>(n) * nrhs * csize);
+    }
+    p2p_status st;
+    if (ws_query(ws, ws_bytes, ar, &st)) return st;
+    if (!src) return fail(P2P_EINVAL, "src is NULL");
+    if (n > 0 && (grav ? (!src[0] || !src[1] || !src[2] || !src[3]) : !src[0]))
+        return fail(P2P_EINVAL, "src arrays must not be NULL");
+    if (!out->red_start || (L > 0 && !out->red_self)) return fail(P2P_EINVAL, "out->red_start/red_self must not be NULL");
+    if (out->cap < 0) return fail(P2P_EINVAL, "out->cap < 0");
+    hipStream_t s = as_stream(stream);
+    P2P_TRY(launch_seg_lengths(tree->leaf_start, nbrs->nbr_start, nbrs->nbr_idx, L, seg_len, rself, s));
+    P2P_TRY((exclusive_scan<int64_t, int64_t>(seg_len, rstart, L, scan_tmp, s)));
+    int64_t S = 0;
+    P2P_HIP(hipMemcpyAsync(&S, &rstart[L], sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    P2P_HIP(hipStreamSynchronize(s));
+    if (S > out->cap) {
+        out->count = S;
+        return fail(P2P_ECAPACITY, "out->cap " + std::to_string(out->cap) + " < " + std::to_string(S) + " entries");
+    }
+    if (S > 0 && (grav ? (!out->planes[0] || !out->planes[1] || !out->planes[2] || !out->planes[3])
+                       : !out->planes[0]))
+        return fail(P2P_EINVAL, "out->planes must not be NULL");
+    P2P_HIP(hipMemcpyAsync(out->red_start, rstart, (L + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    if (L > 0) P2P_HIP(hipMemcpyAsync(out->red_self, rself, L * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    if (grav) {
+        P2P_TRY(launch_permute_gravity(static_cast<const double *>(src[0]), static_cast<const double *>(src[1]),
+                                       static_cast<const double *>(src[2]), static_cast<const double *>(src[3]),
+                                       tree->perm, n, mixed, sx, sy, sz, sm, s));
+        P2P_TRY(launch_copy_segments_gravity(sx, sy, sz, sm, mixed, tree->leaf_start, nbrs->nbr_start,
+                                             nbrs->nbr_idx, rstart, L, static_cast<double *>(out->planes[0]),
+                                             static_cast<double *>(out->planes[1]),
+                                             static_cast<double *>(out->planes[2]), out->planes[3], s));
+    } else if (mixed) {
+        P2P_TRY(launch_permute_rows<float2>(static_cast<const float2 *>(src[0]), tree->perm, n, nrhs,
+                                            static_cast<float2 *>(sq), s));
+        P2P_TRY(launch_copy_segments<float2>(static_cast<const float2 *>(sq), nrhs, tree->leaf_start,
+                                             nbrs->nbr_start, nbrs->nbr_idx, rstart, L,
+                                             static_cast<float2 *>(out->planes[0]), s));
+    } else {
+        P2P_TRY(launch_permute_rows<double2>(static_cast<const double2 *>(src[0]), tree->perm, n, nrhs,
+                                             static_cast<double2 *>(sq), s));
+        P2P_TRY(launch_copy_segments<double2>(static_cast<const double2 *>(sq), nrhs, tree->leaf_start,
+                                              nbrs->nbr_start, nbrs->nbr_idx, rstart, L,
+                                              static_cast<double2 *>(out->planes[0]), s));
+    }
+    P2P_HIP(hipStreamSynchronize(s));
+    out->count = S;
+    out->nrhs = nrhs;
+    out->kind = grav ? P2P_KIND_GRAVITY : P2P_KIND_HELMHOLTZ;
+    out->prec = prec;
+    return P2P_OK;
+}
+
+// ---------------------------------------------------------------- a4/a5 ---
+extern "C" p2p_status p2p_eval_gravity(const p2p_tree *tree, const p2p_nbrs *nbrs,
+                                       const p2p_redundant *red, p2p_layout layout,
+                                       p2p_precision prec, double eps, const double *x,
+                                       const double *y, const double *z, const double *m,
+                                       double *phi, double *ax, double *ay, double *az, void *ws,
+                                       size_t *ws_bytes, p2p_stream_t stream) {
+    set_error("");
+    if (!ws_bytes) return fail(P2P_EINVAL, "ws_bytes must not be NULL");
+    P2P_TRY(check_tree(tree));
+    if (tree->kind != P2P_TREE_PARTICLES) return fail(P2P_EINVAL, "gravity needs a particle tree");
+    P2P_TRY(check_nbrs(tree, nbrs));
+    if (layout != P2P_GATHER && layout != P2P_REDUNDANT) return fail(P2P_EINVAL, "bad layout");
+    if (prec != P2P_FP64 && prec != P2P_FP32_MIXED) return fail(P2P_EINVAL, "bad precision");
+    if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(P2P_EINVAL, "eps must be finite and >= 0");
+    const bool mixed = prec == P2P_FP32_MIXED, redundant = layout == P2P_REDUNDANT;
+    const int64_t n = tree->n;
+    Arena ar(ws);
+    double *sx = nullptr, *sy = nullptr, *sz = nullptr;
+    void *sm = nullptr;
+    if (!redundant) {
+        sx = ar.take<double>(n);
+        sy = ar.take<double>(n);
+        sz = ar.take<double>(n);
+        sm = ar.take<double>(n);
+    }
+    p2p_status st;
+    if (ws_query(ws, ws_bytes, ar, &st)) return st;
+    if (n > 0 && (!phi || !ax || !ay || !az)) return fail(P2P_EINVAL, "outputs must not be NULL");
+    if (redundant) {
+        if (!red) return fail(P2P_EINVAL, "REDUNDANT layout needs red");
+        if (red->kind != P2P_KIND_GRAVITY) return fail(P2P_EINVAL, "red was not built for gravity");
+        if (red->prec != prec) return fail(P2P_EINVAL, "red was built with another precision");
+        if (!red->red_start || !red->red_self || (red->count > 0 && (!red->planes[0] || !red->planes[1] ||
+                                                                      !red->planes[2] || !red->planes[3])))
+            return fail(P2P_EINVAL, "red arrays must not be NULL");
+    } else if (n > 0 && (!x || !y || !z || !m)) {
+        return fail(P2P_EINVAL, "GATHER layout needs x, y, z, m");
+    }
+    hipStream_t s = as_stream(stream);
+    GravityArgs a{};
+    a.L = tree->n_leaves;
+    a.leaf_start = tree->leaf_start;
+    a.perm = tree->perm;
+    a.nbr_start = nbrs->nbr_start;
+    a.nbr_idx = nbrs->nbr_idx;
+    a.eps2 = eps * eps;
+    a.phi = phi;
+    a.ax = ax;
+    a.ay = ay;
+    a.az = az;
+    if (redundant) {
+        a.red_start = red->red_start;
+        a.red_self = red->red_self;
+        a.sx = static_cast<const double *>(red->planes[0]);
+        a.sy = static_cast<const double *>(red->planes[1]);
+        a.sz = static_cast<const double *>(red->planes[2]);
+        a.sm = red->planes[3];
+    } else {
+        P2P_TRY(launch_permute_gravity(x, y, z, m, tree->perm, n, mixed, sx, sy, sz, sm, s));
+        a.sx = sx;
+        a.sy = sy;
+        a.sz = sz;
+        a.sm = sm;
+    }
+    return launch_gravity(a, redundant, mixed, eps == 0.0, s);
+}
+
+// ---------------------------------------------------------------- a7/a9 ---
+namespace {
+
+struct HelmPlan {
+    bool fp64, redundant;
+    const double *d_h, *d_k;
+    void *table;
+    void *sorted;
+};
+
+p2p_status helmholtz_common(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2p_redundant *red,
+                            p2p_layout layout, p2p_precision prec, const p2p_grid *grids,
+                            int32_t n_grids, int32_t nrhs, const void *q, void *u, int32_t conj,
+                            void *ws, size_t *ws_bytes, hipStream_t s) {
+    if (!ws_bytes) return fail(P2P_EINVAL, "ws_bytes must not be NULL");
+    P2P_TRY(check_tree(tree));
+    if (tree->kind != P2P_TREE_GRIDS) return fail(P2P_EINVAL, "Helmholtz needs a grid tree");
+    P2P_TRY(check_nbrs(tree, nbrs));
+    if (layout != P2P_GATHER && layout != P2P_REDUNDANT) return fail(P2P_EINVAL, "bad layout");
+    if (prec != P2P_FP64 && prec != P2P_FP32_MIXED) return fail(P2P_EINVAL, "bad precision");
+    if (nrhs < 1) return fail(P2P_EINVAL, "nrhs must be >= 1");
+    if (n_grids != tree->n_grids) return fail(P2P_EINVAL, "n_grids differs from the tree's");
+    P2P_TRY(check_grids(grids, n_grids, tree->n));
+    const bool fp64 = prec == P2P_FP64, redundant = layout == P2P_REDUNDANT;
+    const size_t csize = fp64 ? sizeof(double2) : sizeof(double2) / 2;
+    const int64_t n = tree->n;
+    Arena ar(ws);
+    double *d_h = ar.take<double>(n_grids);
+    double *d_k = ar.take<double>(n_grids);
+    char *table = ar.take<char>(static_cast<size_t>(n_grids) * kTableLen * csize);
+    char *sorted = redundant ? nullptr : ar.take<char>(static_cast<size_t>(n) * nrhs * csize);
+    p2p_status st;
+    if (ws_query(ws, ws_bytes, ar, &st)) return st;
+    if (n > 0 && !u) return fail(P2P_EINVAL, "u must not be NULL");
+    if (redundant) {
+        if (!red) return fail(P2P_EINVAL, "REDUNDANT layout needs red");
+        if (red->kind != P2P_KIND_HELMHOLTZ) return fail(P2P_EINVAL, "red was not built for Helmholtz");
+        if (red->prec != prec) return fail(P2P_EINVAL, "red was built with another precision");
+        if (red->nrhs != nrhs) return fail(P2P_EINVAL, "red was built with another nrhs");
+        if (!red->red_start || (red->count > 0 && !red->planes[0])) return fail(P2P_EINVAL, "red arrays must not be NULL");
+        if (conj) return fail(P2P_EUNSUPPORTED, "conjugated action needs the GATHER layout");
+    } else if (n > 0 && !q) {
+        return fail(P2P_EINVAL, "q must not be NULL");
+    }
+    std::vector<double> hk(2 * n_grids);
+    for (int32_t g = 0; g < n_grids; ++g) {
+        hk[g] = grids[g].h;
+        hk[n_grids + g] = grids[g].k;
+    }
+    P2P_HIP(hipMemcpyAsync(d_h, hk.data(), n_grids * sizeof(double), hipMemcpyHostToDevice, s));
+    P2P_HIP(hipMemcpyAsync(d_k, hk.data() + n_grids, n_grids * sizeof(double), hipMemcpyHostToDevice, s));
+    P2P_TRY(launch_green_tables(d_h, d_k, n_grids, fp64, table, s));
+    if (!redundant) {
+        if (fp64)
+            P2P_TRY(launch_permute_rows<double2>(static_cast<const double2 *>(q), tree->perm, n, nrhs,
+                                                 reinterpret_cast<double2 *>(sorted), s));
+        else
+            P2P_TRY(launch_permute_rows<float2>(static_cast<const float2 *>(q), tree->perm, n, nrhs,
+                                                reinterpret_cast<float2 *>(sorted), s));
+    }
+    HelmholtzArgs a{};
+    a.L = tree->n_leaves;
+    a.key_bits = tree->key_bits;
+    a.leaf_start = tree->leaf_start;
+    a.leaf_key = tree->leaf_key;
+    a.perm = tree->perm;
+    a.nbr_start = nbrs->nbr_start;
+    a.nbr_idx = nbrs->nbr_idx;
+    a.red_start = redundant ? red->red_start : nullptr;
+    a.src = redundant ? red->planes[0] : sorted;
+    a.table = table;
+    a.nrhs = nrhs;
+    a.conj = conj;
+    a.u = u;
+    return launch_helmholtz(a, redundant, fp64, s);
+}
+
+}  // namespace
+
+extern "C" p2p_status p2p_eval_helmholtz(const p2p_tree *tree, const p2p_nbrs *nbrs,
+                                         const p2p_redundant *red, p2p_layout layout,
+                                         p2p_precision prec, const p2p_grid *grids, int32_t n_grids,
+                                         int32_t nrhs, const void *q, void *u, const int32_t *tile,
+                                         void *ws, size_t *ws_bytes, p2p_stream_t stream) {
+    set_error("");
+    (void)tile;
+    return helmholtz_common(tree, nbrs, red, layout, prec, grids, n_grids, nrhs, q, u, 0, ws,
+                            ws_bytes, as_stream(stream));
+}
+
+// ------------------------------------------------------------------ a11 ---
+extern "C" p2p_status p2p_adjoint(int32_t kind, const p2p_tree *tree, const p2p_nbrs *nbrs,
+                                  const p2p_redundant *red, p2p_layout layout, p2p_precision prec,
+                                  double eps, const p2p_grid *grids, int32_t n_grids, int32_t nrhs,
+                                  int32_t conjugate, const void *const fwd_in[4],
+                                  const void *const grad_out[4], void *const grad_in[4], void *ws,
+                                  size_t *ws_bytes, p2p_stream_t stream) {
+    set_error("");
+    if (!ws_bytes) return fail(P2P_EINVAL, "ws_bytes must not be NULL");
+    hipStream_t s = as_stream(stream);
+    if (kind == P2P_KIND_HELMHOLTZ) {
+        if (layout != P2P_GATHER) return fail(P2P_EUNSUPPORTED, "Helmholtz adjoint uses the GATHER layout");
+        if (conjugate != 0 && conjugate != 1) return fail(P2P_EINVAL, "conjugate must be 0 or 1");
+        const void *g = grad_out ? grad_out[0] : nullptr;
+        void *out = grad_in ? grad_in[0] : nullptr;
+        // A is symmetric (reciprocity and a symmetric near relation): A^T g = A g
+        return helmholtz_common(tree, nbrs, red, P2P_GATHER, prec, grids, n_grids, nrhs, g, out,
+                                conjugate, ws, ws_bytes, s);
+    }
+    if (kind != P2P_KIND_GRAVITY) return fail(P2P_EINVAL, "kind must be P2P_KIND_GRAVITY or P2P_KIND_HELMHOLTZ");
+    (void)red;
+    P2P_TRY(check_tree(tree));
+    if (tree->kind != P2P_TREE_PARTICLES) return fail(P2P_EINVAL, "gravity needs a particle tree");
+    P2P_TRY(check_nbrs(tree, nbrs));
+    if (layout != P2P_GATHER) return fail(P2P_EUNSUPPORTED, "gravity adjoint uses the GATHER layout");
+    if (prec != P2P_FP64) return fail(P2P_EUNSUPPORTED, "gravity adjoint runs in FP64");
+    if (!(eps > 0.0) || !std::isfinite(eps)) return fail(P2P_EINVAL, "gravity adjoint needs eps > 0");
+    const int64_t n = tree->n;
+    Arena ar(ws);
+    double *pl[8];
+    for (int i = 0; i < 8; ++i) pl[i] = ar.take<double>(n);
+    p2p_status st;
+    if (ws_query(ws, ws_bytes, ar, &st)) return st;
+    if (!fwd_in || !grad_out || !grad_in) return fail(P2P_EINVAL, "fwd_in, grad_out, grad_in must not be NULL");
+    for (int i = 0; i < 4; ++i)
+        if (n > 0 && (!fwd_in[i] || !grad_out[i] || !grad_in[i])) return fail(P2P_EINVAL, "NULL gravity array");
+    auto D = [](const void *p) { return static_cast<const double *>(p); };
+    P2P_TRY(launch_permute_gravity(D(fwd_in[0]), D(fwd_in[1]), D(fwd_in[2]), D(fwd_in[3]), tree->perm, n,
+                                   false, pl[0], pl[1], pl[2], pl[3], s));
+    P2P_TRY(launch_permute_gravity(D(grad_out[1]), D(grad_out[2]), D(grad_out[3]), D(grad_out[0]),
+                                   tree->perm, n, false, pl[5], pl[6], pl[7], pl[4], s));
+    GravityAdjointArgs a{};
+    a.L = tree->n_leaves;
+    a.leaf_start = tree->leaf_start;
+    a.perm = tree->perm;
+    a.nbr_start = nbrs->nbr_start;
+    a.nbr_idx = nbrs->nbr_idx;
+    a.sx = pl[0];
+    a.sy = pl[1];
+    a.sz = pl[2];
+    a.sm = pl[3];
+    a.sgp = pl[4];
+    a.sgx = pl[5];
+    a.sgy = pl[6];
+    a.sgz = pl[7];
+    a.eps2 = eps * eps;
+    a.gx = static_cast<double *>(grad_in[0]);
+    a.gy = static_cast<double *>(grad_in[1]);
+    a.gz = static_cast<double *>(grad_in[2]);
+    a.gm = static_cast<double *>(grad_in[3]);
+    return launch_gravity_adjoint(a, s);
+}
+
+// ------------------------------------------------------------------ a12 ---
+extern "C" p2p_status p2p_locality(const p2p_tree *tree, const p2p_nbrs *nbrs,
+                                   const p2p_redundant *red, double bytes_per_entry,
+                                   double cache_bytes, p2p_locality_t *out, void *ws,
+                                   size_t *ws_bytes, p2p_stream_t stream) {
+    set_error("");
+    if (!ws_bytes) return fail(P2P_EINVAL, "ws_bytes must not be NULL");
+    P2P_TRY(check_tree(tree));
+    P2P_TRY(check_nbrs(tree, nbrs));
+    if (!(bytes_per_entry > 0.0) || !(cache_bytes > 0.0)) return fail(P2P_EINVAL, "bytes_per_entry and cache_bytes must be > 0");
+    Arena ar(ws);
+    unsigned long long *sums = ar.take<unsigned long long>(3);
+    p2p_status st;
+    if (ws_query(ws, ws_bytes, ar, &st)) return st;
+    if (!out) return fail(P2P_EINVAL, "out is NULL");
+    hipStream_t s = as_stream(stream);
+    const int64_t L = tree->n_leaves;
+    P2P_HIP(hipMemsetAsync(sums, 0, 3 * sizeof(unsigned long long), s));
+    P2P_TRY(launch_locality_stats(tree->leaf_start, nbrs->nbr_start, nbrs->nbr_idx, L, sums, s));
+    unsigned long long h[3] = {0, 0, 0};
+    P2P_HIP(hipMemcpyAsync(h, sums, sizeof(h), hipMemcpyDeviceToHost, s));
+    P2P_HIP(hipStreamSynchronize(s));
+    const int64_t S = red ? red->count : static_cast<int64_t>(h[1]);
+    out->entries = S;
+    out->pairs = static_cast<int64_t>(h[2]) - tree->n;
+    out->d_mean = L > 0 ? static_cast<double>(h[0]) / static_cast<double>(L) : 0.0;
+    out->v_gather = static_cast<double>(tree->n) * bytes_per_entry;
+    out->v_red = static_cast<double>(S) * bytes_per_entry;
+    out->d_ratio = out->d_mean / 1.0;
+    out->v_ratio = out->v_red > 0 ? out->v_gather / out->v_red : 0.0;
+    out->locality = (out->v_red <= cache_bytes) ? out->d_ratio * out->v_ratio
+                                                : (out->d_ratio > 0 ? out->v_ratio / out->d_ratio : 0.0);
+    return P2P_OK;
+}

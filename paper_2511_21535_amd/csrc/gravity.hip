@@ -1,0 +1,333 @@
+// Near-field gravity (a4 gather, a5 redundant, a6 fused update, a8 mixed
+// precision) and its adjoint (a11).
+//
+// One 256-thread workgroup owns one target leaf.  Leaves hold 1..64 targets
+// in an adaptive tree, so lanes are split two ways: with tc targets in the
+// current chunk, lane (t, g) = (tid % tc, tid / tc) takes target t and every
+// G-th source, G = 256 / tc, and the G partial sums of a target are reduced
+// through LDS at the end.  Sources are staged through LDS in tiles of 512:
+//   - redundant: one contiguous segment, read with coalesced loads;
+//   - gather: the near list is walked in chunks; each staged row is located
+//     by a binary search over the prefix of neighbour occupancies.
+// Results are written straight to caller order through perm (the update
+// step).  No atomics: each output has one owner.
+//
+// Self pair: instead of a per-pair index test, the kernel sums over all
+// sources of the near field, which holds the target itself exactly once with
+// d = 0, and afterwards adds back the self term of phi (m_i (eps^2)^{-1/2},
+// computed in the same arithmetic); the self term of a is exactly zero.
+// With eps == 0 pairs at zero distance contribute nothing instead.
+//
+// FP32_MIXED: the coordinate difference of every pair is taken in double and
+// rounded to float; the rest of the pair arithmetic is float; each lane sums
+// at most 32 pair terms in float before adding them to double accumulators.
+#include <type_traits>
+
+#include "p2p_internal.h"
+
+namespace p2p {
+namespace {
+
+constexpr int kGBlock = 256;
+constexpr int kGTile = 512;
+constexpr int kGNbrChunk = 256;
+constexpr int kGFlush = 32;
+
+// Block-wide: loads one chunk of the near list of A into LDS (first sorted
+// slot of each neighbour and exclusive prefix of their occupancies).
+__device__ int64_t g_load_nbr_chunk(const int32_t *__restrict__ leaf_start,
+                                    const int32_t *__restrict__ nbr_idx, int64_t c0, int nc,
+                                    int64_t *s_pre, int32_t *s_first, int64_t *s_w) {
+    int32_t occ = 0, first = 0;
+    if (threadIdx.x < nc) {
+        const int32_t B = nbr_idx[c0 + threadIdx.x];
+        first = leaf_start[B];
+        occ = leaf_start[B + 1] - first;
+    }
+    s_first[threadIdx.x] = first;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int64_t x = occ;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int64_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) s_w[w] = x;
+    __syncthreads();
+    int64_t woff = 0, tot = 0;
+#pragma unroll
+    for (int q = 0; q < kGBlock / 64; ++q) {
+        if (q < w) woff += s_w[q];
+        tot += s_w[q];
+    }
+    s_pre[threadIdx.x] = woff + x - occ;
+    if (threadIdx.x == 0) s_pre[nc] = tot;
+    __syncthreads();
+    return tot;
+}
+
+__device__ inline int g_find_nbr(const int64_t *s_pre, int nc, int64_t p) {
+    int lo = 0, hi = nc - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_pre[mid] <= p) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Walks the sources of leaf A tile by tile, staging each tile into LDS with
+// `stage(dst_index, src_row)` and then calling `body(n_tile)`.  Must be called
+// by the whole block.
+template <bool RED, class Stage, class Body>
+__device__ void for_each_source_tile(int64_t A, const int64_t *__restrict__ red_start,
+                                     const int64_t *__restrict__ nbr_start,
+                                     const int32_t *__restrict__ nbr_idx,
+                                     const int32_t *__restrict__ leaf_start, int64_t *s_pre,
+                                     int32_t *s_first, int64_t *s_w, Stage stage, Body body) {
+    if constexpr (RED) {
+        const int64_t seg0 = red_start[A], ns = red_start[A + 1] - seg0;
+        for (int64_t s0 = 0; s0 < ns; s0 += kGTile) {
+            const int nt = static_cast<int>(min<int64_t>(kGTile, ns - s0));
+            __syncthreads();
+            for (int i = threadIdx.x; i < nt; i += kGBlock) stage(i, seg0 + s0 + i);
+            __syncthreads();
+            body(nt);
+        }
+    } else {
+        const int64_t e0 = nbr_start[A], e1 = nbr_start[A + 1];
+        for (int64_t c0 = e0; c0 < e1; c0 += kGNbrChunk) {
+            const int nc = static_cast<int>(min<int64_t>(kGNbrChunk, e1 - c0));
+            __syncthreads();
+            const int64_t rows = g_load_nbr_chunk(leaf_start, nbr_idx, c0, nc, s_pre, s_first, s_w);
+            for (int64_t s0 = 0; s0 < rows; s0 += kGTile) {
+                const int nt = static_cast<int>(min<int64_t>(kGTile, rows - s0));
+                __syncthreads();
+                for (int i = threadIdx.x; i < nt; i += kGBlock) {
+                    const int64_t p = s0 + i;
+                    const int b = g_find_nbr(s_pre, nc, p);
+                    stage(i, s_first[b] + (p - s_pre[b]));
+                }
+                __syncthreads();
+                body(nt);
+            }
+        }
+    }
+}
+
+__device__ inline float rsq_f32(float x) { return __builtin_amdgcn_rsqf(x); }
+
+template <bool MIXED, bool RED, bool EPS0>
+__global__ __launch_bounds__(kGBlock) void k_gravity(GravityArgs a) {
+    using TM = typename std::conditional<MIXED, float, double>::type;
+    __shared__ double s_x[kGTile], s_y[kGTile], s_z[kGTile];
+    __shared__ TM s_m[kGTile];
+    __shared__ double s_red[4][kGBlock];
+    __shared__ int64_t s_pre[kGNbrChunk + 1];
+    __shared__ int32_t s_first[kGNbrChunk];
+    __shared__ int64_t s_w[kGBlock / 64];
+
+    const int64_t A = blockIdx.x;
+    const int32_t t0 = a.leaf_start[A];
+    const int32_t ntar = a.leaf_start[A + 1] - t0;
+    const TM *__restrict__ sm = static_cast<const TM *>(a.sm);
+    const int64_t tbase = RED ? a.red_start[A] + a.red_self[A] : t0;
+    const double eps2 = a.eps2;
+    const float eps2f = static_cast<float>(a.eps2);
+
+    for (int tc0 = 0; tc0 < ntar; tc0 += kGBlock) {
+        const int tc = min(kGBlock, ntar - tc0);
+        const int G = kGBlock / tc;
+        const int t = threadIdx.x % tc, g = threadIdx.x / tc;
+        const bool active = g < G;
+        const int64_t trow = tbase + tc0 + t;
+        const double xt = a.sx[trow], yt = a.sy[trow], zt = a.sz[trow];
+        const TM mt = sm[trow];
+        double p = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+
+        auto stage = [&](int i, int64_t row) {
+            s_x[i] = a.sx[row];
+            s_y[i] = a.sy[row];
+            s_z[i] = a.sz[row];
+            s_m[i] = sm[row];
+        };
+        auto body = [&](int nt) {
+            if (!active) return;
+            const int cnt = (nt > g) ? (nt - g + G - 1) / G : 0;
+            int s = g;
+            if constexpr (MIXED) {
+                for (int k0 = 0; k0 < cnt; k0 += kGFlush) {
+                    const int kk = min(kGFlush, cnt - k0);
+                    float pf = 0.f, xf = 0.f, yf = 0.f, zf = 0.f;
+                    for (int k = 0; k < kk; ++k, s += G) {
+                        const float dx = static_cast<float>(xt - s_x[s]);
+                        const float dy = static_cast<float>(yt - s_y[s]);
+                        const float dz = static_cast<float>(zt - s_z[s]);
+                        const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2f)));
+                        float w = rsq_f32(r2);
+                        if constexpr (EPS0) w = (r2 > 0.f) ? w : 0.f;
+                        const float mw = s_m[s] * w;
+                        const float mw3 = mw * (w * w);
+                        pf -= mw;
+                        xf = fmaf(-mw3, dx, xf);
+                        yf = fmaf(-mw3, dy, yf);
+                        zf = fmaf(-mw3, dz, zf);
+                    }
+                    p += pf;
+                    fx += xf;
+                    fy += yf;
+                    fz += zf;
+                }
+            } else {
+                for (int k = 0; k < cnt; ++k, s += G) {
+                    const double dx = xt - s_x[s], dy = yt - s_y[s], dz = zt - s_z[s];
+                    const double r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
+                    double w = rsqrt(r2);
+                    if constexpr (EPS0) w = (r2 > 0.0) ? w : 0.0;
+                    const double mw = s_m[s] * w;
+                    const double mw3 = mw * (w * w);
+                    p -= mw;
+                    fx = fma(-mw3, dx, fx);
+                    fy = fma(-mw3, dy, fy);
+                    fz = fma(-mw3, dz, fz);
+                }
+            }
+        };
+        for_each_source_tile<RED>(A, a.red_start, a.nbr_start, a.nbr_idx, a.leaf_start, s_pre,
+                                  s_first, s_w, stage, body);
+
+        __syncthreads();
+        s_red[0][threadIdx.x] = active ? p : 0.0;
+        s_red[1][threadIdx.x] = active ? fx : 0.0;
+        s_red[2][threadIdx.x] = active ? fy : 0.0;
+        s_red[3][threadIdx.x] = active ? fz : 0.0;
+        __syncthreads();
+        if (threadIdx.x < tc) {
+            double sp = 0.0, sx_ = 0.0, sy_ = 0.0, sz_ = 0.0;
+            for (int q = 0; q < G; ++q) {
+                const int l = q * tc + threadIdx.x;
+                sp += s_red[0][l];
+                sx_ += s_red[1][l];
+                sy_ += s_red[2][l];
+                sz_ += s_red[3][l];
+            }
+            if constexpr (!EPS0) {
+                if constexpr (MIXED)
+                    sp += static_cast<double>(mt * rsq_f32(eps2f));
+                else
+                    sp += mt * rsqrt(eps2);
+            }
+            const int64_t i = a.perm[t0 + tc0 + threadIdx.x];
+            a.phi[i] = sp;
+            a.ax[i] = sx_;
+            a.ay[i] = sy_;
+            a.az[i] = sz_;
+        }
+    }
+}
+
+// Adjoint of the gravity sums, FP64, gather layout.  For target j and each
+// near source k (d = x_j - x_k, w = (|d|^2+eps^2)^{-1/2}):
+//   g_x_j += [ m_k (gp_j w^3 + 3 w^5 ga_j.d) + m_j (gp_k w^3 - 3 w^5 ga_k.d) ] d
+//            + w^3 (m_j ga_k - m_k ga_j)
+//   g_m_j += -(gp_k w - w^3 ga_k.d)
+// (the derivative of L = sum_i gp_i phi_i + ga_i . a_i through both the pair
+// (j, k) and the pair (k, j)).  The self pair adds zero to g_x and
+// -gp_j/eps to g_m, which is added back.
+__global__ __launch_bounds__(kGBlock) void k_gravity_adjoint(GravityAdjointArgs a) {
+    __shared__ double s_x[kGTile], s_y[kGTile], s_z[kGTile], s_m[kGTile];
+    __shared__ double s_gp[kGTile], s_gx[kGTile], s_gy[kGTile], s_gz[kGTile];
+    __shared__ int64_t s_pre[kGNbrChunk + 1];
+    __shared__ int32_t s_first[kGNbrChunk];
+    __shared__ int64_t s_w[kGBlock / 64];
+    double *s_red = s_gp;   // reused after the last tile (4 x 256 doubles fit in 4 x 512)
+
+    const int64_t A = blockIdx.x;
+    const int32_t t0 = a.leaf_start[A];
+    const int32_t ntar = a.leaf_start[A + 1] - t0;
+    const double eps2 = a.eps2;
+    for (int tc0 = 0; tc0 < ntar; tc0 += kGBlock) {
+        const int tc = min(kGBlock, ntar - tc0);
+        const int G = kGBlock / tc;
+        const int t = threadIdx.x % tc, g = threadIdx.x / tc;
+        const bool active = g < G;
+        const int64_t tr = t0 + tc0 + t;
+        const double xj = a.sx[tr], yj = a.sy[tr], zj = a.sz[tr], mj = a.sm[tr];
+        const double gpj = a.sgp[tr], gxj = a.sgx[tr], gyj = a.sgy[tr], gzj = a.sgz[tr];
+        double om = 0.0, ox = 0.0, oy = 0.0, oz = 0.0;
+        auto stage = [&](int i, int64_t row) {
+            s_x[i] = a.sx[row];
+            s_y[i] = a.sy[row];
+            s_z[i] = a.sz[row];
+            s_m[i] = a.sm[row];
+            s_gp[i] = a.sgp[row];
+            s_gx[i] = a.sgx[row];
+            s_gy[i] = a.sgy[row];
+            s_gz[i] = a.sgz[row];
+        };
+        auto body = [&](int nt) {
+            if (!active) return;
+            for (int s = g; s < nt; s += G) {
+                const double dx = xj - s_x[s], dy = yj - s_y[s], dz = zj - s_z[s];
+                const double w = rsqrt(fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2))));
+                const double w3 = w * w * w, w5 = w3 * w * w;
+                const double mk = s_m[s], gpk = s_gp[s];
+                const double gak[3] = {s_gx[s], s_gy[s], s_gz[s]};
+                const double gdj = gxj * dx + gyj * dy + gzj * dz;
+                const double gdk = gak[0] * dx + gak[1] * dy + gak[2] * dz;
+                const double c = mk * (gpj * w3 + 3.0 * w5 * gdj) + mj * (gpk * w3 - 3.0 * w5 * gdk);
+                ox += c * dx + w3 * (mj * gak[0] - mk * gxj);
+                oy += c * dy + w3 * (mj * gak[1] - mk * gyj);
+                oz += c * dz + w3 * (mj * gak[2] - mk * gzj);
+                om -= gpk * w - w3 * gdk;
+            }
+        };
+        for_each_source_tile<false>(A, nullptr, a.nbr_start, a.nbr_idx, a.leaf_start, s_pre,
+                                    s_first, s_w, stage, body);
+        __syncthreads();
+        s_red[0 * kGBlock + threadIdx.x] = active ? om : 0.0;
+        s_red[1 * kGBlock + threadIdx.x] = active ? ox : 0.0;
+        s_red[2 * kGBlock + threadIdx.x] = active ? oy : 0.0;
+        s_red[3 * kGBlock + threadIdx.x] = active ? oz : 0.0;
+        __syncthreads();
+        if (threadIdx.x < tc) {
+            double r[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int q = 0; q < G; ++q)
+                for (int c = 0; c < 4; ++c) r[c] += s_red[c * kGBlock + q * tc + threadIdx.x];
+            r[0] += a.sgp[t0 + tc0 + threadIdx.x] * rsqrt(eps2);
+            const int64_t i = a.perm[t0 + tc0 + threadIdx.x];
+            a.gm[i] = r[0];
+            a.gx[i] = r[1];
+            a.gy[i] = r[2];
+            a.gz[i] = r[3];
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+p2p_status launch_gravity(const GravityArgs &a, bool redundant, bool mixed, bool eps_zero,
+                          hipStream_t s) {
+    if (a.L <= 0) return P2P_OK;
+    const unsigned g = static_cast<unsigned>(a.L);
+#define P2P_GRAV(M, R, E) k_gravity<M, R, E><<<g, kGBlock, 0, s>>>(a)
+    if (mixed) {
+        if (redundant) { if (eps_zero) P2P_GRAV(true, true, true); else P2P_GRAV(true, true, false); }
+        else { if (eps_zero) P2P_GRAV(true, false, true); else P2P_GRAV(true, false, false); }
+    } else {
+        if (redundant) { if (eps_zero) P2P_GRAV(false, true, true); else P2P_GRAV(false, true, false); }
+        else { if (eps_zero) P2P_GRAV(false, false, true); else P2P_GRAV(false, false, false); }
+    }
+#undef P2P_GRAV
+    P2P_LAUNCH_CHECK();
+    return P2P_OK;
+}
+
+p2p_status launch_gravity_adjoint(const GravityAdjointArgs &a, hipStream_t s) {
+    if (a.L <= 0) return P2P_OK;
+    k_gravity_adjoint<<<static_cast<unsigned>(a.L), kGBlock, 0, s>>>(a);
+    P2P_LAUNCH_CHECK();
+    return P2P_OK;
+}
+
+}  // namespace p2p

@@ -1,0 +1,156 @@
+// Near-field lists (a2): for every leaf A, every leaf B whose closed cube
+// touches A's, A included, in ascending leaf id.
+//
+// One wavefront per leaf.  Lanes 0..26 each take one of the 27 cells of A's
+// size around A (A itself in the middle).  A leaf touching A either covers
+// such a cell (it is at least as large as A) or lies inside one.  Each lane
+// finds, by binary search over the sorted leaf keys, the contiguous range of
+// leaves that meet its cell.  The ranges of different cells are disjoint,
+// except that one large leaf may cover several cells; those duplicates are
+// dropped and the ranges are put in key order, which is leaf-id order.  The
+// candidates are then tested in parallel, 64 per step, and the adjacent ones
+// written with a ballot prefix, so the list comes out ascending.
+#include "p2p_internal.h"
+
+namespace p2p {
+namespace {
+
+constexpr int kNbrWaves = 4;
+
+__device__ inline int64_t upper_bound_u64(const uint64_t *__restrict__ a, int64_t n, uint64_t v) {
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (a[mid] <= v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+__device__ inline int64_t lower_bound_u64(const uint64_t *__restrict__ a, int64_t n, uint64_t v) {
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (a[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__global__ __launch_bounds__(64 * kNbrWaves) void k_neighbors(
+    const uint64_t *__restrict__ leaf_key, const int8_t *__restrict__ leaf_level, int64_t L,
+    int key_bits, int inst_shift, const int64_t *__restrict__ nbr_start,
+    int32_t *__restrict__ counts, int32_t *__restrict__ nbr_idx) {
+    __shared__ int32_t s_lo[kNbrWaves][32];
+    __shared__ int32_t s_pre[kNbrWaves][33];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t A = static_cast<int64_t>(blockIdx.x) * kNbrWaves + w;
+    if (A >= L) return;
+
+    const uint64_t kA = leaf_key[A];
+    const int lA = leaf_level[A];
+    const int64_t dim = int64_t(1) << key_bits;
+    const int64_t sA = int64_t(1) << (key_bits - lA);
+    const uint64_t local_mask = (3 * key_bits >= 64) ? ~0ull : ((1ull << (3 * key_bits)) - 1ull);
+    const uint64_t inst_bits = (inst_shift >= 64) ? 0ull : (kA >> inst_shift) << inst_shift;
+    const uint64_t local = kA & local_mask;
+    const int64_t a[3] = {p2pd::compact3(local), p2pd::compact3(local >> 1),
+                          p2pd::compact3(local >> 2)};
+
+    // ---- one cell per lane
+    int64_t lo = 0, hi = 0;
+    bool valid = false;
+    if (lane < 27) {
+        const int64_t c[3] = {a[0] + (lane % 3 - 1) * sA, a[1] + ((lane / 3) % 3 - 1) * sA,
+                              a[2] + (lane / 9 - 1) * sA};
+        if (c[0] >= 0 && c[1] >= 0 && c[2] >= 0 && c[0] < dim && c[1] < dim && c[2] < dim) {
+            const uint64_t kC = inst_bits | p2pd::morton3(static_cast<uint32_t>(c[0]),
+                                                          static_cast<uint32_t>(c[1]),
+                                                          static_cast<uint32_t>(c[2]));
+            const uint64_t sizeC = 1ull << (3 * (key_bits - lA));
+            const int64_t j = upper_bound_u64(leaf_key, L, kC) - 1;
+            bool covers = false;
+            if (j >= 0) {
+                const uint64_t sj = 1ull << (3 * (key_bits - leaf_level[j]));
+                covers = kC < leaf_key[j] + sj;   // leaf_key[j] <= kC by construction
+            }
+            lo = covers ? j : j + 1;
+            hi = lower_bound_u64(leaf_key, L, kC + sizeC);
+            valid = lo < hi;
+        }
+    }
+    // ---- drop duplicate ranges (one large leaf covering several cells), rank by lo
+    bool first = valid;
+    for (int q = 0; q < 27; ++q) {
+        const int64_t loq = __shfl(lo, q, 64);
+        const int vq = __shfl(static_cast<int>(valid), q, 64);
+        if (vq && q < lane && loq == lo) first = false;
+    }
+    int rank = 0;
+    for (int q = 0; q < 27; ++q) {
+        const int64_t loq = __shfl(lo, q, 64);
+        const int fq = __shfl(static_cast<int>(first), q, 64);
+        if (fq && loq < lo) ++rank;
+    }
+    const int K = __popcll(__ballot(first));
+    if (first) {
+        s_lo[w][rank] = static_cast<int32_t>(lo);
+        s_pre[w][rank] = static_cast<int32_t>(hi - lo);
+    }
+    wave_sync();
+    // exclusive prefix of the range lengths in sorted order
+    int32_t len = (lane < K) ? s_pre[w][lane] : 0;
+    int32_t inc = len;
+#pragma unroll
+    for (int o = 1; o < 32; o <<= 1) {
+        int32_t y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+    }
+    wave_sync();
+    if (lane < K) s_pre[w][lane] = inc - len;
+    const int32_t total = __shfl(inc, K > 0 ? K - 1 : 0, 64);
+    if (lane == 0) s_pre[w][K] = total;
+    wave_sync();
+
+    // ---- test candidates, 64 at a time, in ascending leaf id
+    const int64_t out0 = counts ? 0 : nbr_start[A];
+    int64_t written = 0;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int32_t base = 0; base < total; base += 64) {
+        const int32_t cidx = base + lane;
+        bool adj = false;
+        int64_t B = 0;
+        if (cidx < total) {
+            int r = 0;
+            while (r + 1 < K && s_pre[w][r + 1] <= cidx) ++r;
+            B = s_lo[w][r] + (cidx - s_pre[w][r]);
+            const uint64_t kB = leaf_key[B] & local_mask;
+            const int64_t sB = int64_t(1) << (key_bits - leaf_level[B]);
+            const int64_t b[3] = {p2pd::compact3(kB), p2pd::compact3(kB >> 1),
+                                  p2pd::compact3(kB >> 2)};
+            adj = true;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) adj = adj && (a[d] <= b[d] + sB) && (b[d] <= a[d] + sA);
+        }
+        const uint64_t bal = __ballot(adj);
+        if (!counts && adj) nbr_idx[out0 + written + __popcll(bal & below)] = static_cast<int32_t>(B);
+        written += __popcll(bal);
+    }
+    if (counts && lane == 0) counts[A] = static_cast<int32_t>(written);
+}
+
+}  // namespace
+
+p2p_status launch_neighbors(const uint64_t *leaf_key, const int8_t *leaf_level, int64_t L,
+                            int key_bits, int inst_shift, const int64_t *nbr_start,
+                            int32_t *counts, int32_t *nbr_idx, hipStream_t s) {
+    if (L <= 0) return P2P_OK;
+    k_neighbors<<<grid_for(L, kNbrWaves), 64 * kNbrWaves, 0, s>>>(
+        leaf_key, leaf_level, L, key_bits, inst_shift, nbr_start, counts, nbr_idx);
+    P2P_LAUNCH_CHECK();
+    return P2P_OK;
+}
+
+}  // namespace p2p

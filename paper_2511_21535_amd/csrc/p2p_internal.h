@@ -1,0 +1,221 @@
+// Internal declarations shared by the libp2p translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "p2p.h"
+
+namespace p2p {
+
+// ---------------------------------------------------------------- errors --
+void set_error(const std::string &msg);
+p2p_status fail(p2p_status st, const std::string &msg);
+
+#define P2P_HIP(call)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return ::p2p::fail(P2P_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define P2P_LAUNCH_CHECK()                                                                 \
+    do {                                                                                   \
+        hipError_t e_ = hipGetLastError();                                                 \
+        if (e_ != hipSuccess)                                                              \
+            return ::p2p::fail(P2P_EHIP, std::string("kernel launch: ") + hipGetErrorString(e_)); \
+    } while (0)
+
+#define P2P_TRY(expr)                                                                      \
+    do {                                                                                   \
+        p2p_status s_ = (expr);                                                            \
+        if (s_ != P2P_OK) return s_;                                                       \
+    } while (0)
+
+// ------------------------------------------------------------- workspace --
+// Carves 256-byte aligned sub-buffers out of one caller buffer.  With a null
+// base it only measures.
+struct Arena {
+    char *base;
+    size_t used = 0;
+    explicit Arena(void *b) : base(static_cast<char *>(b)) {}
+    template <class T>
+    T *take(size_t count) {
+        size_t off = (used + 255) & ~size_t(255);
+        used = off + count * sizeof(T) + 256;
+        return base ? reinterpret_cast<T *>(base + off) : nullptr;
+    }
+};
+
+// -------------------------------------------------------------- launches --
+inline unsigned grid_for(int64_t n, int block) {
+    int64_t g = (n + block - 1) / block;
+    return static_cast<unsigned>(g < 1 ? 1 : g);
+}
+
+// Device scan: exclusive prefix sum of in[0..n) into out[0..n], out[n] = total.
+// In-place allowed.  Scratch from scan_ws_elems(n) elements of type TO.
+size_t scan_ws_elems(int64_t n);
+template <class TI, class TO>
+p2p_status exclusive_scan(const TI *in, TO *out, int64_t n, TO *scratch, hipStream_t s);
+
+// Sort (key, value) pairs by key, stably, over the low `key_bits` bits.
+// keys/vals are sorted in place; tmp buffers of the same sizes are needed.
+p2p_status radix_sort_pairs(uint64_t *keys, int32_t *vals, uint64_t *keys_tmp, int32_t *vals_tmp,
+                            int64_t n, int key_bits, uint32_t *hist_scratch, hipStream_t s);
+size_t radix_hist_elems(int64_t n);
+
+// Tree construction steps (tree.hip).
+p2p_status launch_particle_keys(const double *x, const double *y, const double *z, int64_t n,
+                                uint64_t *keys, int32_t *vals, int32_t *bad_flag, hipStream_t s);
+p2p_status launch_grid_keys(const int32_t *d_n_side, const int64_t *d_point_off, int32_t n_grids,
+                            int bits, int64_t n, uint64_t *keys, int32_t *vals, hipStream_t s);
+p2p_status launch_leaf_levels(const uint64_t *skeys, int64_t n, int kind, int depth, int leaf_cap,
+                              uint8_t *pair_common, int8_t *level, int32_t *flags, hipStream_t s);
+p2p_status launch_leaf_write(const uint64_t *skeys, const int8_t *level, const int32_t *flags,
+                             const int32_t *flag_scan, int64_t n, int kind, int key_bits,
+                             int32_t *leaf_start, uint64_t *leaf_key, int8_t *leaf_level,
+                             int32_t *max_level, hipStream_t s);
+
+// Near lists (nbrs.hip).  count pass (out_idx == nullptr) or fill pass.
+p2p_status launch_neighbors(const uint64_t *leaf_key, const int8_t *leaf_level, int64_t L,
+                            int key_bits, int inst_shift, const int64_t *nbr_start,
+                            int32_t *counts, int32_t *nbr_idx, hipStream_t s);
+
+// Restructure (restructure.hip).
+p2p_status launch_seg_lengths(const int32_t *leaf_start, const int64_t *nbr_start,
+                              const int32_t *nbr_idx, int64_t L, int64_t *seg_len,
+                              int32_t *red_self, hipStream_t s);
+template <class T>
+p2p_status launch_permute_rows(const T *src, const int32_t *perm, int64_t n, int64_t row_len,
+                               T *dst, hipStream_t s);
+p2p_status launch_permute_mass_f32(const double *m, const int32_t *perm, int64_t n, float *dst,
+                                   hipStream_t s);
+p2p_status launch_permute_gravity(const double *x, const double *y, const double *z,
+                                  const double *m, const int32_t *perm, int64_t n, bool mass_f32,
+                                  double *sx, double *sy, double *sz, void *sm, hipStream_t s);
+p2p_status launch_copy_segments_gravity(const double *sx, const double *sy, const double *sz,
+                                        const void *sm, bool mass_f32, const int32_t *leaf_start,
+                                        const int64_t *nbr_start, const int32_t *nbr_idx,
+                                        const int64_t *red_start, int64_t L, double *dx,
+                                        double *dy, double *dz, void *dm, hipStream_t s);
+template <class T>
+p2p_status launch_copy_segments(const T *sorted, int64_t row_len, const int32_t *leaf_start,
+                                const int64_t *nbr_start, const int32_t *nbr_idx,
+                                const int64_t *red_start, int64_t L, T *dst, hipStream_t s);
+
+// Gravity (gravity.hip).
+struct GravityArgs {
+    int64_t L;
+    const int32_t *leaf_start;
+    const int32_t *perm;
+    const int64_t *nbr_start;
+    const int32_t *nbr_idx;
+    const int64_t *red_start;
+    const int32_t *red_self;
+    const double *sx, *sy, *sz;  // sources: sorted planes (gather) or redundant planes
+    const void *sm;              // double (FP64) or float (FP32_MIXED)
+    double eps2;
+    double *phi, *ax, *ay, *az;  // caller order
+};
+p2p_status launch_gravity(const GravityArgs &a, bool redundant, bool mixed, bool eps_zero,
+                          hipStream_t s);
+
+struct GravityAdjointArgs {
+    int64_t L;
+    const int32_t *leaf_start;
+    const int32_t *perm;
+    const int64_t *nbr_start;
+    const int32_t *nbr_idx;
+    const double *sx, *sy, *sz, *sm;        // sorted positions and masses
+    const double *sgp, *sgx, *sgy, *sgz;    // sorted upstream gradients
+    double eps2;
+    double *gx, *gy, *gz, *gm;              // caller order
+};
+p2p_status launch_gravity_adjoint(const GravityAdjointArgs &a, hipStream_t s);
+
+// Helmholtz (helmholtz.hip).
+struct HelmholtzArgs {
+    int64_t L;
+    int key_bits;
+    const int32_t *leaf_start;
+    const uint64_t *leaf_key;
+    const int32_t *perm;
+    const int64_t *nbr_start;
+    const int32_t *nbr_idx;
+    const int64_t *red_start;
+    const void *src;       // sorted q rows (gather) or redundant rows
+    const void *table;     // per-instance G(dd) tables, [n_grids][kTableLen] complex
+    int32_t nrhs;
+    int32_t conj;          // 1: conj(q) in, conj(u) out
+    void *u;               // caller order
+};
+constexpr int kTableLen = 148;   // dd = 0..147 inside a 3x3x3-box neighbourhood of 4^3 boxes
+p2p_status launch_green_tables(const double *d_h, const double *d_k, int32_t n_grids, bool fp64,
+                               void *table, hipStream_t s);
+p2p_status launch_helmholtz(const HelmholtzArgs &a, bool redundant, bool fp64, hipStream_t s);
+
+// Multi-RHS Helmholtz on FP32 matrix cores (helmholtz_mfma.hip).
+struct HelmholtzMfmaArgs {
+    int64_t L;
+    int key_bits;
+    const int32_t *leaf_start;
+    const uint64_t *leaf_key;
+    const int32_t *perm;
+    const int64_t *nbr_start;
+    const int32_t *nbr_idx;
+    const int64_t *red_start;
+    const float2 *src;         // sorted q rows (gather) or redundant rows, [.][nrhs]
+    const float2 *blocks;      // [n_tables][27][64 src][64 tgt] complex G blocks (unit spacing)
+    const int32_t *inst_table; // per instance: table index
+    const float *inst_scale;   // per instance: 1/h
+    const int32_t *work;       // box ids in processing order (longest first)
+    int32_t *counter;          // work-queue counter (zeroed by the launcher)
+    int32_t nrhs;
+    int32_t conj;
+    float2 *u;                 // caller order [n][nrhs]
+};
+p2p_status launch_green_blocks(const double *d_kh, int32_t n_tables, float2 *blocks, hipStream_t s);
+p2p_status launch_work_order(const int64_t *nbr_start, int64_t L, int32_t *work, int32_t *keys_tmp,
+                             hipStream_t s);
+p2p_status launch_helmholtz_mfma(const HelmholtzMfmaArgs &a, bool redundant, int boxes_per_wg,
+                                 int wg_per_cu, hipStream_t s);
+
+// Locality (locality.hip).
+p2p_status launch_locality_stats(const int32_t *leaf_start, const int64_t *nbr_start,
+                                 const int32_t *nbr_idx, int64_t L, unsigned long long *sums,
+                                 hipStream_t s);
+
+}  // namespace p2p
+
+// ------------------------------------------------------------ device side --
+namespace p2pd {
+
+// Spread the low 21 bits of v so that bit b moves to bit 3b.
+__host__ __device__ inline uint64_t spread3(uint64_t v) {
+    v &= 0x1fffffull;
+    v = (v | (v << 32)) & 0x1f00000000ffffull;
+    v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+    v = (v | (v << 8)) & 0x100f00f00f00f00full;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+// Inverse of spread3: gather bits 0, 3, 6, ... into the low 21 bits.
+__host__ __device__ inline uint32_t compact3(uint64_t v) {
+    v &= 0x1249249249249249ull;
+    v = (v ^ (v >> 2)) & 0x10c30c30c30c30c3ull;
+    v = (v ^ (v >> 4)) & 0x100f00f00f00f00full;
+    v = (v ^ (v >> 8)) & 0x1f0000ff0000ffull;
+    v = (v ^ (v >> 16)) & 0x1f00000000ffffull;
+    v = (v ^ (v >> 32)) & 0x1fffffull;
+    return static_cast<uint32_t>(v);
+}
+__host__ __device__ inline uint64_t morton3(uint32_t x, uint32_t y, uint32_t z) {
+    return spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
+}
+
+}  // namespace p2pd

@@ -1,0 +1,275 @@
+// Restructure to the redundant layout (a3) and the gather-to-sorted-order
+// permutations it and the gather layout share.
+//
+// The redundant segment of target leaf A is the concatenation, for B in
+// nbr(A) in order, of B's sorted rows.  Rows are first permuted from caller
+// order into sorted order (one pass, N rows), then every segment is filled
+// with coalesced copies: a workgroup owns one target leaf and walks its
+// segment in row order, locating the source leaf of each row by a binary
+// search over the prefix of neighbour occupancies kept in LDS.
+#include "p2p_internal.h"
+
+namespace p2p {
+namespace {
+
+__global__ void k_seg_lengths(const int32_t *__restrict__ leaf_start,
+                              const int64_t *__restrict__ nbr_start,
+                              const int32_t *__restrict__ nbr_idx, int64_t L,
+                              int64_t *__restrict__ seg_len, int32_t *__restrict__ red_self) {
+    int64_t A = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (A >= L) return;
+    int64_t len = 0, self = 0;
+    for (int64_t e = nbr_start[A]; e < nbr_start[A + 1]; ++e) {
+        const int32_t B = nbr_idx[e];
+        if (B == A) self = len;
+        len += leaf_start[B + 1] - leaf_start[B];
+    }
+    seg_len[A] = len;
+    red_self[A] = static_cast<int32_t>(self);
+}
+
+// Rows of row_len elements: row_len == 1 one row per thread, otherwise one
+// wave per row with lanes across it.
+template <class T>
+__global__ void k_permute_rows(const T *__restrict__ src, const int32_t *__restrict__ perm,
+                               int64_t n, int row_len, T *__restrict__ dst) {
+    if (row_len == 1) {
+        const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+        if (s < n) dst[s] = src[perm[s]];
+        return;
+    }
+    const int lane = threadIdx.x & 63;
+    const int64_t s = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    if (s >= n) return;
+    const int64_t from = static_cast<int64_t>(perm[s]) * row_len, to = s * row_len;
+    for (int r = lane; r < row_len; r += 64) dst[to + r] = src[from + r];
+}
+
+// Caller-order positions and masses into sorted order, in one pass.
+template <class TM>
+__global__ void k_permute_gravity(const double *__restrict__ x, const double *__restrict__ y,
+                                  const double *__restrict__ z, const double *__restrict__ m,
+                                  const int32_t *__restrict__ perm, int64_t n,
+                                  double *__restrict__ sx, double *__restrict__ sy,
+                                  double *__restrict__ sz, TM *__restrict__ sm) {
+    const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int64_t i = perm[s];
+    sx[s] = x[i];
+    sy[s] = y[i];
+    sz[s] = z[i];
+    sm[s] = static_cast<TM>(m[i]);
+}
+
+__global__ void k_permute_mass_f32(const double *__restrict__ m, const int32_t *__restrict__ perm,
+                                   int64_t n, float *__restrict__ dst) {
+    int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (s < n) dst[s] = static_cast<float>(m[perm[s]]);
+}
+
+constexpr int kCopyBlock = 256;
+constexpr int kCopyNbrChunk = 256;   // near-list entries held in LDS at once
+
+// Loads one chunk of A's near list into LDS: s_first[b] = first sorted slot of
+// neighbour b, s_pre[b] = rows of the chunk before neighbour b, s_pre[nc] = rows
+// in the chunk.  Called by the whole block.
+__device__ int64_t load_nbr_chunk(const int32_t *__restrict__ leaf_start,
+                                  const int32_t *__restrict__ nbr_idx, int64_t c0, int nc,
+                                  int64_t *s_pre, int32_t *s_first, int64_t *s_w) {
+    int32_t occ = 0, first = 0;
+    if (threadIdx.x < nc) {
+        const int32_t B = nbr_idx[c0 + threadIdx.x];
+        first = leaf_start[B];
+        occ = leaf_start[B + 1] - first;
+    }
+    s_first[threadIdx.x] = first;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int64_t x = occ;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int64_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) s_w[w] = x;
+    __syncthreads();
+    int64_t woff = 0, tot = 0;
+    for (int q = 0; q < kCopyBlock / 64; ++q) {
+        if (q < w) woff += s_w[q];
+        tot += s_w[q];
+    }
+    s_pre[threadIdx.x] = woff + x - occ;
+    if (threadIdx.x == 0) s_pre[nc] = tot;
+    __syncthreads();
+    return tot;
+}
+
+// Index of the last neighbour b < nc with s_pre[b] <= p.
+__device__ inline int find_nbr(const int64_t *s_pre, int nc, int64_t p) {
+    int lo = 0, hi = nc - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_pre[mid] <= p) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Gravity payload: three double planes and a mass plane (double or float),
+// one row per thread.
+template <class TM>
+__global__ __launch_bounds__(kCopyBlock) void k_copy_segments_grav(
+    const double *__restrict__ sx, const double *__restrict__ sy, const double *__restrict__ sz,
+    const TM *__restrict__ sm, const int32_t *__restrict__ leaf_start,
+    const int64_t *__restrict__ nbr_start, const int32_t *__restrict__ nbr_idx,
+    const int64_t *__restrict__ red_start, double *__restrict__ dx, double *__restrict__ dy,
+    double *__restrict__ dz, TM *__restrict__ dm) {
+    __shared__ int64_t s_pre[kCopyNbrChunk + 1];
+    __shared__ int32_t s_first[kCopyNbrChunk];
+    __shared__ int64_t s_w[kCopyBlock / 64];
+    const int64_t A = blockIdx.x;
+    const int64_t e0 = nbr_start[A], e1 = nbr_start[A + 1];
+    int64_t out = red_start[A];
+    for (int64_t c0 = e0; c0 < e1; c0 += kCopyNbrChunk) {
+        const int nc = static_cast<int>(min<int64_t>(kCopyNbrChunk, e1 - c0));
+        const int64_t rows = load_nbr_chunk(leaf_start, nbr_idx, c0, nc, s_pre, s_first, s_w);
+        for (int64_t p = threadIdx.x; p < rows; p += kCopyBlock) {
+            const int b = find_nbr(s_pre, nc, p);
+            const int64_t src = s_first[b] + (p - s_pre[b]);
+            dx[out + p] = sx[src];
+            dy[out + p] = sy[src];
+            dz[out + p] = sz[src];
+            dm[out + p] = sm[src];
+        }
+        out += rows;
+        __syncthreads();
+    }
+}
+
+// Rows of row_len elements (Helmholtz right-hand sides): one wave per row,
+// lanes across the row.
+template <class T>
+__global__ __launch_bounds__(kCopyBlock) void k_copy_segments_rows(
+    const T *__restrict__ sorted, int row_len, const int32_t *__restrict__ leaf_start,
+    const int64_t *__restrict__ nbr_start, const int32_t *__restrict__ nbr_idx,
+    const int64_t *__restrict__ red_start, T *__restrict__ dst) {
+    __shared__ int64_t s_pre[kCopyNbrChunk + 1];
+    __shared__ int32_t s_first[kCopyNbrChunk];
+    __shared__ int64_t s_w[kCopyBlock / 64];
+    const int64_t A = blockIdx.x;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t e0 = nbr_start[A], e1 = nbr_start[A + 1];
+    int64_t out = red_start[A];
+    for (int64_t c0 = e0; c0 < e1; c0 += kCopyNbrChunk) {
+        const int nc = static_cast<int>(min<int64_t>(kCopyNbrChunk, e1 - c0));
+        const int64_t rows = load_nbr_chunk(leaf_start, nbr_idx, c0, nc, s_pre, s_first, s_w);
+        if (row_len == 1) {
+            for (int64_t p = threadIdx.x; p < rows; p += kCopyBlock) {
+                const int b = find_nbr(s_pre, nc, p);
+                dst[out + p] = sorted[s_first[b] + (p - s_pre[b])];
+            }
+        } else {
+            for (int64_t p = w; p < rows; p += kCopyBlock / 64) {
+                const int b = find_nbr(s_pre, nc, p);
+                const int64_t src = (s_first[b] + (p - s_pre[b])) * static_cast<int64_t>(row_len);
+                const int64_t d = (out + p) * static_cast<int64_t>(row_len);
+                for (int r = lane; r < row_len; r += 64) dst[d + r] = sorted[src + r];
+            }
+        }
+        out += rows;
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+p2p_status launch_seg_lengths(const int32_t *leaf_start, const int64_t *nbr_start,
+                              const int32_t *nbr_idx, int64_t L, int64_t *seg_len,
+                              int32_t *red_self, hipStream_t s) {
+    if (L <= 0) return P2P_OK;
+    k_seg_lengths<<<grid_for(L, 256), 256, 0, s>>>(leaf_start, nbr_start, nbr_idx, L, seg_len,
+                                                  red_self);
+    P2P_LAUNCH_CHECK();
+    return P2P_OK;
+}
+
+template <class T>
+p2p_status launch_permute_rows(const T *src, const int32_t *perm, int64_t n, int64_t row_len,
+                               T *dst, hipStream_t s) {
+    if (n <= 0) return P2P_OK;
+    const int64_t threads = (row_len == 1) ? n : n * 64;
+    k_permute_rows<T><<<grid_for(threads, 256), 256, 0, s>>>(src, perm, n,
+                                                            static_cast<int>(row_len), dst);
+    P2P_LAUNCH_CHECK();
+    return P2P_OK;
+}
+
+p2p_status launch_permute_gravity(const double *x, const double *y, const double *z,
+                                  const double *m, const int32_t *perm, int64_t n, bool mass_f32,
+                                  double *sx, double *sy, double *sz, void *sm, hipStream_t s) {
+    if (n <= 0) return P2P_OK;
+    if (mass_f32)
+        k_permute_gravity<float><<<grid_for(n, 256), 256, 0, s>>>(x, y, z, m, perm, n, sx, sy, sz,
+                                                                 static_cast<float *>(sm));
+    else
+        k_permute_gravity<double><<<grid_for(n, 256), 256, 0, s>>>(x, y, z, m, perm, n, sx, sy, sz,
+                                                                  static_cast<double *>(sm));
+    P2P_LAUNCH_CHECK();
+    return P2P_OK;
+}
+
+p2p_status launch_permute_mass_f32(const double *m, const int32_t *perm, int64_t n, float *dst,
+                                   hipStream_t s) {
+    if (n <= 0) return P2P_OK;
+    k_permute_mass_f32<<<grid_for(n, 256), 256, 0, s>>>(m, perm, n, dst);
+    P2P_LAUNCH_CHECK();
+    return P2P_OK;
+}
+
+template <class T>
+p2p_status launch_copy_segments(const T *sorted, int64_t row_len, const int32_t *leaf_start,
+                                const int64_t *nbr_start, const int32_t *nbr_idx,
+                                const int64_t *red_start, int64_t L, T *dst, hipStream_t s) {
+    if (L <= 0) return P2P_OK;
+    k_copy_segments_rows<T><<<static_cast<unsigned>(L), kCopyBlock, 0, s>>>(
+        sorted, static_cast<int>(row_len), leaf_start, nbr_start, nbr_idx, red_start, dst);
+    P2P_LAUNCH_CHECK();
+    return P2P_OK;
+}
+
+p2p_status launch_copy_segments_gravity(const double *sx, const double *sy, const double *sz,
+                                        const void *sm, bool mass_f32, const int32_t *leaf_start,
+                                        const int64_t *nbr_start, const int32_t *nbr_idx,
+                                        const int64_t *red_start, int64_t L, double *dx,
+                                        double *dy, double *dz, void *dm, hipStream_t s) {
+    if (L <= 0) return P2P_OK;
+    if (mass_f32)
+        k_copy_segments_grav<float><<<static_cast<unsigned>(L), kCopyBlock, 0, s>>>(
+            sx, sy, sz, static_cast<const float *>(sm), leaf_start, nbr_start, nbr_idx, red_start,
+            dx, dy, dz, static_cast<float *>(dm));
+    else
+        k_copy_segments_grav<double><<<static_cast<unsigned>(L), kCopyBlock, 0, s>>>(
+            sx, sy, sz, static_cast<const double *>(sm), leaf_start, nbr_start, nbr_idx, red_start,
+            dx, dy, dz, static_cast<double *>(dm));
+    P2P_LAUNCH_CHECK();
+    return P2P_OK;
+}
+
+template p2p_status launch_permute_rows<double>(const double *, const int32_t *, int64_t, int64_t,
+                                                double *, hipStream_t);
+template p2p_status launch_permute_rows<float2>(const float2 *, const int32_t *, int64_t, int64_t,
+                                                float2 *, hipStream_t);
+template p2p_status launch_permute_rows<double2>(const double2 *, const int32_t *, int64_t, int64_t,
+                                                 double2 *, hipStream_t);
+template p2p_status launch_copy_segments<double>(const double *, int64_t, const int32_t *,
+                                                 const int64_t *, const int32_t *, const int64_t *,
+                                                 int64_t, double *, hipStream_t);
+template p2p_status launch_copy_segments<float>(const float *, int64_t, const int32_t *,
+                                                const int64_t *, const int32_t *, const int64_t *,
+                                                int64_t, float *, hipStream_t);
+template p2p_status launch_copy_segments<float2>(const float2 *, int64_t, const int32_t *,
+                                                 const int64_t *, const int32_t *, const int64_t *,
+                                                 int64_t, float2 *, hipStream_t);
+template p2p_status launch_copy_segments<double2>(const double2 *, int64_t, const int32_t *,
+                                                  const int64_t *, const int32_t *, const int64_t *,
+                                                  int64_t, double2 *, hipStream_t);
+
+}  // namespace p2p

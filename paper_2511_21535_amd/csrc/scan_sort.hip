@@ -1,0 +1,263 @@
+// Device-wide exclusive scan and stable LSD radix sort of (uint64 key, int32
+// value) pairs.  Both are plain data-movement primitives used by tree
+// binning, near-list construction and the restructure step.
+#include "p2p_internal.h"
+
+namespace p2p {
+namespace {
+
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanBlock * kScanItems;   // 2048
+
+// Exclusive scan of one value per thread across a 256-thread block.
+// Returns the thread's exclusive prefix; *total receives the block sum.
+template <class T>
+__device__ T block_exclusive_scan(T v, T *lds /*[kScanBlock/64]*/, T *total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    T x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        T y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) lds[wave] = x;
+    __syncthreads();
+    T wave_off = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kScanBlock / 64; ++w) {
+        T s = lds[w];
+        if (w < wave) wave_off += s;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return wave_off + x - v;
+}
+
+template <class TI, class TO>
+__global__ __launch_bounds__(kScanBlock) void k_scan_reduce(const TI *__restrict__ in, int64_t n,
+                                                            TO *__restrict__ partial) {
+    __shared__ TO lds[kScanBlock / 64];
+    int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile + threadIdx.x * kScanItems;
+    TO s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i)
+        if (base + i < n) s += static_cast<TO>(in[base + i]);
+    TO tot;
+    block_exclusive_scan<TO>(s, lds, &tot);
+    if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+// Scans partial[0..nb) in place (exclusive) with a single block; partial[nb] = total.
+template <class TO>
+__global__ __launch_bounds__(kScanBlock) void k_scan_partials(TO *partial, int64_t nb) {
+    __shared__ TO lds[kScanBlock / 64];
+    TO carry = 0;
+    for (int64_t c = 0; c < nb; c += kScanTile) {
+        int64_t base = c + threadIdx.x * kScanItems;
+        TO v[kScanItems];
+        TO s = 0;
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            v[i] = (base + i < nb) ? partial[base + i] : TO(0);
+            s += v[i];
+        }
+        TO tot;
+        TO pre = block_exclusive_scan<TO>(s, lds, &tot) + carry;
+#pragma unroll
+        for (int i = 0; i < kScanItems; ++i) {
+            if (base + i < nb) partial[base + i] = pre;
+            pre += v[i];
+        }
+        carry += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[nb] = carry;
+}
+
+template <class TI, class TO>
+__global__ __launch_bounds__(kScanBlock) void k_scan_down(const TI *in, int64_t n,
+                                                          const TO *__restrict__ partial,
+                                                          int64_t nb, TO *out) {
+    __shared__ TO lds[kScanBlock / 64];
+    int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile + threadIdx.x * kScanItems;
+    TO v[kScanItems];
+    TO s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        v[i] = (base + i < n) ? static_cast<TO>(in[base + i]) : TO(0);
+        s += v[i];
+    }
+    TO tot;
+    TO pre = block_exclusive_scan<TO>(s, lds, &tot) + partial[blockIdx.x];
+    // every read of `in` by this block happened before the barrier inside the scan
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        if (base + i < n) out[base + i] = pre;
+        pre += v[i];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = partial[nb];
+}
+
+template <class TO>
+__global__ void k_scan_empty(TO *out) { out[0] = 0; }
+
+}  // namespace
+
+size_t scan_ws_elems(int64_t n) { return static_cast<size_t>((n + kScanTile - 1) / kScanTile) + 2; }
+
+template <class TI, class TO>
+p2p_status exclusive_scan(const TI *in, TO *out, int64_t n, TO *scratch, hipStream_t s) {
+    if (n <= 0) {
+        k_scan_empty<TO><<<1, 1, 0, s>>>(out);
+        P2P_LAUNCH_CHECK();
+        return P2P_OK;
+    }
+    int64_t nb = (n + kScanTile - 1) / kScanTile;
+    k_scan_reduce<TI, TO><<<static_cast<unsigned>(nb), kScanBlock, 0, s>>>(in, n, scratch);
+    P2P_LAUNCH_CHECK();
+    k_scan_partials<TO><<<1, kScanBlock, 0, s>>>(scratch, nb);
+    P2P_LAUNCH_CHECK();
+    k_scan_down<TI, TO><<<static_cast<unsigned>(nb), kScanBlock, 0, s>>>(in, n, scratch, nb, out);
+    P2P_LAUNCH_CHECK();
+    return P2P_OK;
+}
+
+template p2p_status exclusive_scan<int32_t, int32_t>(const int32_t *, int32_t *, int64_t, int32_t *,
+                                                     hipStream_t);
+template p2p_status exclusive_scan<int32_t, int64_t>(const int32_t *, int64_t *, int64_t, int64_t *,
+                                                     hipStream_t);
+template p2p_status exclusive_scan<int64_t, int64_t>(const int64_t *, int64_t *, int64_t, int64_t *,
+                                                     hipStream_t);
+template p2p_status exclusive_scan<uint32_t, uint32_t>(const uint32_t *, uint32_t *, int64_t,
+                                                       uint32_t *, hipStream_t);
+
+// ------------------------------------------------------------------ sort --
+namespace {
+
+constexpr int kSortBlock = 256;                 // 4 waves
+constexpr int kSortChunks = 16;                 // chunks of 64 keys per wave
+constexpr int kSortWaveKeys = 64 * kSortChunks; // 1024
+constexpr int kSortTile = 4 * kSortWaveKeys;    // 4096 keys per block
+
+__global__ __launch_bounds__(kSortBlock) void k_radix_hist(const uint64_t *__restrict__ keys,
+                                                           int64_t n, int shift,
+                                                           uint32_t *__restrict__ hist,
+                                                           int64_t ntiles) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t base = static_cast<int64_t>(blockIdx.x) * kSortTile;
+#pragma unroll 4
+    for (int i = 0; i < kSortTile / kSortBlock; ++i) {
+        int64_t idx = base + i * kSortBlock + threadIdx.x;
+        if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[static_cast<int64_t>(threadIdx.x) * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// Stable scatter of one 8-bit digit.  Each wave ranks its 1024 keys in order,
+// chunk by chunk: lanes holding the same digit are found with 8 ballots, the
+// lane's rank among them is a popcount below its lane, and a per-wave digit
+// counter in LDS carries the running count from chunk to chunk.  Wave
+// counters are then scanned across the 4 waves, which keeps the tile order.
+__global__ __launch_bounds__(kSortBlock) void k_radix_scatter(
+    const uint64_t *__restrict__ kin, const int32_t *__restrict__ vin, uint64_t *__restrict__ kout,
+    int32_t *__restrict__ vout, int64_t n, int shift, const uint32_t *__restrict__ offs,
+    int64_t ntiles) {
+    __shared__ uint32_t cnt[4][256];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int i = threadIdx.x; i < 4 * 256; i += kSortBlock) (&cnt[0][0])[i] = 0;
+    __syncthreads();
+    const int64_t wbase = static_cast<int64_t>(blockIdx.x) * kSortTile + wave * kSortWaveKeys;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint64_t key[kSortChunks];
+    int32_t val[kSortChunks];
+    uint32_t loc[kSortChunks];
+#pragma unroll
+    for (int c = 0; c < kSortChunks; ++c) {
+        int64_t idx = wbase + c * 64 + lane;
+        bool valid = idx < n;
+        key[c] = valid ? kin[idx] : 0ull;
+        val[c] = valid ? vin[idx] : 0;
+        uint32_t d = static_cast<uint32_t>(key[c] >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            uint64_t bal = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? bal : ~bal;
+        }
+        uint32_t rank = __popcll(peers & below);
+        uint32_t base = valid ? cnt[wave][d] : 0u;
+        if (valid && rank == 0) cnt[wave][d] = base + static_cast<uint32_t>(__popcll(peers));
+        loc[c] = base + rank;
+    }
+    __syncthreads();
+    {
+        uint32_t s = 0;
+        for (int w = 0; w < 4; ++w) {
+            uint32_t t = cnt[w][threadIdx.x];
+            cnt[w][threadIdx.x] = s;
+            s += t;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < kSortChunks; ++c) {
+        int64_t idx = wbase + c * 64 + lane;
+        if (idx < n) {
+            uint32_t d = static_cast<uint32_t>(key[c] >> shift) & 255u;
+            int64_t pos = static_cast<int64_t>(offs[static_cast<int64_t>(d) * ntiles + blockIdx.x]) +
+                          cnt[wave][d] + loc[c];
+            kout[pos] = key[c];
+            vout[pos] = val[c];
+        }
+    }
+}
+
+__global__ void k_copy_pairs(const uint64_t *__restrict__ ks, const int32_t *__restrict__ vs,
+                             uint64_t *__restrict__ kd, int32_t *__restrict__ vd, int64_t n) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) {
+        kd[i] = ks[i];
+        vd[i] = vs[i];
+    }
+}
+
+}  // namespace
+
+size_t radix_hist_elems(int64_t n) {
+    int64_t ntiles = (n + kSortTile - 1) / kSortTile;
+    int64_t m = 256 * (ntiles > 0 ? ntiles : 1);
+    return static_cast<size_t>(m + 1) + scan_ws_elems(m);
+}
+
+p2p_status radix_sort_pairs(uint64_t *keys, int32_t *vals, uint64_t *keys_tmp, int32_t *vals_tmp,
+                            int64_t n, int key_bits, uint32_t *hist_scratch, hipStream_t s) {
+    if (n <= 1) return P2P_OK;
+    const int64_t ntiles = (n + kSortTile - 1) / kSortTile;
+    const int64_t m = 256 * ntiles;
+    uint32_t *hist = hist_scratch;
+    uint32_t *scan_tmp = hist_scratch + m + 1;
+    uint64_t *ka = keys, *kb = keys_tmp;
+    int32_t *va = vals, *vb = vals_tmp;
+    for (int shift = 0; shift < key_bits; shift += 8) {
+        k_radix_hist<<<static_cast<unsigned>(ntiles), kSortBlock, 0, s>>>(ka, n, shift, hist, ntiles);
+        P2P_LAUNCH_CHECK();
+        P2P_TRY((exclusive_scan<uint32_t, uint32_t>(hist, hist, m, scan_tmp, s)));
+        k_radix_scatter<<<static_cast<unsigned>(ntiles), kSortBlock, 0, s>>>(ka, va, kb, vb, n, shift,
+                                                                            hist, ntiles);
+        P2P_LAUNCH_CHECK();
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    if (ka != keys) {
+        k_copy_pairs<<<grid_for(n, 256), 256, 0, s>>>(ka, va, keys, vals, n);
+        P2P_LAUNCH_CHECK();
+    }
+    return P2P_OK;
+}
+
+}  // namespace p2p

@@ -1,0 +1,179 @@
+// Tree binning (a1): integer keys, and leaf boundaries over the sorted keys.
+//
+// Particles: c_d = floor(x_d 2^20), key = Morton(c).  The sort itself is
+// radix_sort_pairs.  Leaves of an adaptive tree are found without walking
+// the tree: over the sorted keys, let c[i] be the number of leading octal
+// digits shared by keys i and i+1.  The node at level l that holds particle i
+// contains exactly the run of neighbours reachable through pairs with
+// c >= l, so its count is 1 + (run to the left) + (run to the right).  A
+// particle's leaf is the shallowest node on its root path holding at most
+// leaf_cap points (the split rule: split iff count > cap and level < depth),
+// and that level is one more than the cap-th largest value of the merged,
+// non-increasing sequences of running minima of c to the left and to the
+// right of i.  A merge of leaf_cap steps finds it.
+#include "p2p_internal.h"
+
+namespace p2p {
+namespace {
+
+__global__ void k_particle_keys(const double *__restrict__ x, const double *__restrict__ y,
+                                const double *__restrict__ z, int64_t n,
+                                uint64_t *__restrict__ keys, int32_t *__restrict__ vals,
+                                int32_t *__restrict__ bad) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double p[3] = {x[i], y[i], z[i]};
+    uint32_t c[3];
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        ok = ok && (p[d] >= 0.0 && p[d] < 1.0);
+        // x * 2^20 is exact; truncation of a non-negative value is floor
+        c[d] = ok ? static_cast<uint32_t>(p[d] * 1048576.0) : 0u;
+    }
+    if (!ok) atomicOr(bad, 1);
+    keys[i] = p2pd::morton3(c[0], c[1], c[2]);
+    vals[i] = static_cast<int32_t>(i);
+}
+
+__global__ void k_grid_keys(const int32_t *__restrict__ n_side, const int64_t *__restrict__ off,
+                            int32_t n_grids, int bits, int64_t n, uint64_t *__restrict__ keys,
+                            int32_t *__restrict__ vals) {
+    int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    // binary search of the instance: last g with off[g] <= p
+    int lo = 0, hi = n_grids - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= p) lo = mid; else hi = mid - 1;
+    }
+    const int64_t ns = n_side[lo], loc = p - off[lo];
+    const uint32_t i = static_cast<uint32_t>(loc % ns), j = static_cast<uint32_t>((loc / ns) % ns),
+                   k = static_cast<uint32_t>(loc / (ns * ns));
+    keys[p] = (static_cast<uint64_t>(lo) << (3 * bits)) | p2pd::morton3(i, j, k);
+    vals[p] = static_cast<int32_t>(p);
+}
+
+// Leading octal digits shared by two depth-20 keys (60-bit keys in 64-bit words).
+__device__ inline int common_digits(uint64_t a, uint64_t b) {
+    uint64_t x = a ^ b;
+    return x == 0 ? 20 : (__clzll(static_cast<long long>(x)) - 4) / 3;
+}
+
+__global__ void k_pair_common(const uint64_t *__restrict__ sk, int64_t n, uint8_t *__restrict__ c) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i + 1 < n) c[i] = static_cast<uint8_t>(common_digits(sk[i], sk[i + 1]));
+}
+
+// kind 0, leaf_cap > 0: adaptive level; kind 0, leaf_cap == 0: uniform depth.
+__global__ void k_leaf_level_particles(const uint8_t *__restrict__ c, int64_t n, int depth,
+                                       int leaf_cap, int8_t *__restrict__ level,
+                                       int32_t *__restrict__ flag) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int l;
+    if (leaf_cap == 0) {
+        l = depth;
+    } else {
+        // merge the running minima to the left (pairs i-1, i-2, ...) and to the
+        // right (pairs i, i+1, ...); -1 marks an exhausted side
+        int64_t left = i - 1, right = i;
+        int mL = 127, mR = 127;
+        int cl = (left >= 0) ? static_cast<int>(c[left]) : -1;
+        int cr = (right < n - 1) ? static_cast<int>(c[right]) : -1;
+        int v = -1;
+        for (int t = 0; t < leaf_cap; ++t) {
+            int candL = (left >= 0) ? min(mL, cl) : -1;
+            int candR = (right < n - 1) ? min(mR, cr) : -1;
+            if (candL < 0 && candR < 0) { v = -1; break; }
+            if (candL >= candR) {
+                v = candL; mL = candL; --left;
+                cl = (left >= 0) ? static_cast<int>(c[left]) : -1;
+            } else {
+                v = candR; mR = candR; ++right;
+                cr = (right < n - 1) ? static_cast<int>(c[right]) : -1;
+            }
+        }
+        l = min(depth, v + 1);
+    }
+    level[i] = static_cast<int8_t>(l);
+    // a new leaf starts at i unless slot i-1 shares i's level-l node
+    flag[i] = (i == 0 || static_cast<int>(c[i - 1]) < l) ? 1 : 0;
+}
+
+__global__ void k_leaf_flag_grids(const uint64_t *__restrict__ sk, int64_t n,
+                                  int32_t *__restrict__ flag, int8_t *__restrict__ level,
+                                  int box_level) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    flag[i] = (i == 0 || (sk[i] >> 6) != (sk[i - 1] >> 6)) ? 1 : 0;
+    level[i] = static_cast<int8_t>(box_level);
+}
+
+__global__ void k_leaf_write(const uint64_t *__restrict__ sk, const int8_t *__restrict__ level,
+                             const int32_t *__restrict__ flag, const int32_t *__restrict__ fscan,
+                             int64_t n, int kind, int key_bits, int32_t *__restrict__ leaf_start,
+                             uint64_t *__restrict__ leaf_key, int8_t *__restrict__ leaf_level,
+                             int32_t *__restrict__ max_level) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (i == 0) leaf_start[fscan[n]] = static_cast<int32_t>(n);
+    if (!flag[i]) return;
+    const int32_t L = fscan[i];
+    const int l = level[i];
+    leaf_start[L] = static_cast<int32_t>(i);
+    leaf_level[L] = static_cast<int8_t>(l);
+    uint64_t low_bits = (kind == P2P_TREE_PARTICLES) ? 3ull * (20 - l) : 6ull;
+    uint64_t mask = (low_bits >= 64) ? 0ull : ~((1ull << low_bits) - 1ull);
+    leaf_key[L] = sk[i] & mask;
+    atomicMax(max_level, l);
+    (void)key_bits;
+}
+
+}  // namespace
+
+p2p_status launch_particle_keys(const double *x, const double *y, const double *z, int64_t n,
+                                uint64_t *keys, int32_t *vals, int32_t *bad_flag, hipStream_t s) {
+    if (n <= 0) return P2P_OK;
+    k_particle_keys<<<grid_for(n, 256), 256, 0, s>>>(x, y, z, n, keys, vals, bad_flag);
+    P2P_LAUNCH_CHECK();
+    return P2P_OK;
+}
+
+p2p_status launch_grid_keys(const int32_t *d_n_side, const int64_t *d_point_off, int32_t n_grids,
+                            int bits, int64_t n, uint64_t *keys, int32_t *vals, hipStream_t s) {
+    if (n <= 0) return P2P_OK;
+    k_grid_keys<<<grid_for(n, 256), 256, 0, s>>>(d_n_side, d_point_off, n_grids, bits, n, keys, vals);
+    P2P_LAUNCH_CHECK();
+    return P2P_OK;
+}
+
+p2p_status launch_leaf_levels(const uint64_t *skeys, int64_t n, int kind, int depth, int leaf_cap,
+                              uint8_t *pair_common, int8_t *level, int32_t *flags, hipStream_t s) {
+    if (n <= 0) return P2P_OK;
+    if (kind == P2P_TREE_PARTICLES) {
+        if (n > 1) {
+            k_pair_common<<<grid_for(n - 1, 256), 256, 0, s>>>(skeys, n, pair_common);
+            P2P_LAUNCH_CHECK();
+        }
+        k_leaf_level_particles<<<grid_for(n, 256), 256, 0, s>>>(pair_common, n, depth, leaf_cap,
+                                                                level, flags);
+    } else {
+        k_leaf_flag_grids<<<grid_for(n, 256), 256, 0, s>>>(skeys, n, flags, level, depth);
+    }
+    P2P_LAUNCH_CHECK();
+    return P2P_OK;
+}
+
+p2p_status launch_leaf_write(const uint64_t *skeys, const int8_t *level, const int32_t *flags,
+                             const int32_t *flag_scan, int64_t n, int kind, int key_bits,
+                             int32_t *leaf_start, uint64_t *leaf_key, int8_t *leaf_level,
+                             int32_t *max_level, hipStream_t s) {
+    if (n <= 0) return P2P_OK;
+    k_leaf_write<<<grid_for(n, 256), 256, 0, s>>>(skeys, level, flags, flag_scan, n, kind, key_bits,
+                                                  leaf_start, leaf_key, leaf_level, max_level);
+    P2P_LAUNCH_CHECK();
+    return P2P_OK;
+}
+
+}  // namespace p2p

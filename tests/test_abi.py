@@ -1,0 +1,118 @@
+"""C ABI checks that need no GPU: the library loads, exports every entry
+point include/p2p.h declares, sizes workspaces, and rejects bad arguments on
+the host before any launch."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2511_21535_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "p2p.h")).read()
+    return sorted(set(re.findall(r"^\S.*?\b(p2p_[a-z_]+)\(", src, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(L.LIB_PATH):
+        from paper_2511_21535_amd import build
+        build.build()
+    return L.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    decl = _declared()
+    assert set(decl) >= {"p2p_build_tree", "p2p_build_neighbors", "p2p_restructure_redundant",
+                         "p2p_eval_gravity", "p2p_eval_helmholtz", "p2p_adjoint"}
+    for name in decl:
+        assert hasattr(lib, name), name
+    assert set(decl) == set(L.EXPORTED)
+    assert "gfx950" in L.p2p_version()
+
+
+def _tree(n, kind=L.P2P_TREE_PARTICLES, L_=0):
+    t = L.p2p_tree()
+    t.n, t.cap_leaves, t.n_leaves, t.kind, t.key_bits = n, n, L_, kind, 20
+    return t
+
+
+def test_workspace_query_needs_no_device(lib):
+    t = _tree(1000)
+    nb = ctypes.c_size_t(0)
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: only the size is asked for
+    st = lib.p2p_build_tree(fake, fake, fake, None, 0, 20, 64, ctypes.byref(t), None,
+                            ctypes.byref(nb), None)
+    assert st == L.P2P_OK and nb.value > 1000 * 8
+
+
+@pytest.mark.parametrize("depth,cap,n_grids", [(21, 64, 0), (-1, 0, 0), (20, -1, 0), (20, 64, 2)])
+def test_build_tree_rejects_bad_arguments(lib, depth, cap, n_grids):
+    t = _tree(10)
+    nb = ctypes.c_size_t(0)
+    fake = ctypes.c_void_p(0x1000)
+    st = lib.p2p_build_tree(fake, fake, fake, None, n_grids, depth, cap, ctypes.byref(t), None,
+                            ctypes.byref(nb), None)
+    assert st == L.P2P_EINVAL
+    assert L.last_error()
+
+
+def test_build_tree_rejects_bad_grids(lib):
+    g = (L.p2p_grid * 2)()
+    g[0].n_side, g[0].h, g[0].k, g[0].point_off = 16, 1 / 16, 1.0, 0
+    g[1].n_side, g[1].h, g[1].k, g[1].point_off = 18, 1 / 18, 1.0, 16 ** 3   # not a multiple of 4
+    t = _tree(16 ** 3 + 18 ** 3, L.P2P_TREE_GRIDS)
+    nb = ctypes.c_size_t(0)
+    st = lib.p2p_build_tree(None, None, None, g, 2, 0, 0, ctypes.byref(t), None, ctypes.byref(nb), None)
+    assert st == L.P2P_EINVAL and "multiple of 4" in L.last_error()
+    g[1].n_side = 20
+    st = lib.p2p_build_tree(None, None, None, g, 2, 0, 0, ctypes.byref(t), None, ctypes.byref(nb), None)
+    assert st == L.P2P_EINVAL and "!= tree->n" in L.last_error()
+    t.n = 16 ** 3 + 20 ** 3
+    st = lib.p2p_build_tree(None, None, None, g, 2, 0, 0, ctypes.byref(t), None, ctypes.byref(nb), None)
+    assert st == L.P2P_OK
+
+
+def test_eval_rejects_bad_modes(lib):
+    t = _tree(10, L_=1)
+    t.perm = t.leaf_start = t.leaf_key = t.leaf_level = 0x1000
+    n = L.p2p_nbrs()
+    n.count, n.nbr_start, n.nbr_idx = 1, 0x1000, 0x1000
+    nb = ctypes.c_size_t(0)
+    z = ctypes.c_void_p(0x1000)
+    args = lambda layout, prec, eps: (ctypes.byref(t), ctypes.byref(n), None, layout, prec, eps,
+                                      z, z, z, z, z, z, z, z, None, ctypes.byref(nb), None)
+    assert lib.p2p_eval_gravity(*args(7, L.P2P_FP64, 1e-3)) == L.P2P_EINVAL
+    assert lib.p2p_eval_gravity(*args(L.P2P_GATHER, 9, 1e-3)) == L.P2P_EINVAL
+    assert lib.p2p_eval_gravity(*args(L.P2P_GATHER, L.P2P_FP64, -1.0)) == L.P2P_EINVAL
+    assert lib.p2p_eval_gravity(*args(L.P2P_GATHER, L.P2P_FP64, float("nan"))) == L.P2P_EINVAL
+    assert lib.p2p_eval_gravity(*args(L.P2P_GATHER, L.P2P_FP64, 1e-3)) == L.P2P_OK   # size query
+    # redundant layout without a redundant structure: rejected once the workspace is given
+    nb.value = 1 << 20
+    st = lib.p2p_eval_gravity(ctypes.byref(t), ctypes.byref(n), None, L.P2P_REDUNDANT, L.P2P_FP64,
+                              1e-3, z, z, z, z, z, z, z, z, ctypes.c_void_p(0x100000), ctypes.byref(nb), None)
+    assert st == L.P2P_EINVAL and "needs red" in L.last_error()
+    # gravity on a grid tree
+    t.kind = L.P2P_TREE_GRIDS
+    assert lib.p2p_eval_gravity(*args(L.P2P_GATHER, L.P2P_FP64, 1e-3)) == L.P2P_EINVAL
+
+
+def test_adjoint_unsupported_combinations(lib):
+    t = _tree(10, L_=1)
+    t.perm = t.leaf_start = t.leaf_key = t.leaf_level = 0x1000
+    n = L.p2p_nbrs()
+    n.count, n.nbr_start, n.nbr_idx = 1, 0x1000, 0x1000
+    nb = ctypes.c_size_t(0)
+    st = lib.p2p_adjoint(L.P2P_KIND_GRAVITY, ctypes.byref(t), ctypes.byref(n), None, L.P2P_REDUNDANT,
+                         L.P2P_FP64, 1e-3, None, 0, 1, 0, None, None, None, None, ctypes.byref(nb), None)
+    assert st == L.P2P_EUNSUPPORTED
+    st = lib.p2p_adjoint(L.P2P_KIND_GRAVITY, ctypes.byref(t), ctypes.byref(n), None, L.P2P_GATHER,
+                         L.P2P_FP64, 0.0, None, 0, 1, 0, None, None, None, None, ctypes.byref(nb), None)
+    assert st == L.P2P_EINVAL
+    st = lib.p2p_adjoint(5, ctypes.byref(t), ctypes.byref(n), None, L.P2P_GATHER, L.P2P_FP64, 1e-3,
+                         None, 0, 1, 0, None, None, None, None, ctypes.byref(nb), None)
+    assert st == L.P2P_EINVAL

@@ -1,0 +1,298 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Bit-exact: tree (perm, leaf_start, leaf_key, leaf_level), near lists and the
+redundant payload.  Floating point: relative L2 per result, <= 1e-12 for FP64
+and <= 1e-5 for FP32 / FP32-mixed (phi; a as one 3N vector; u as one complex
+N*R vector).  Full-size workloads are checked on sampled leaves, which the
+oracle computes one by one.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2511_21535_amd import api
+from paper_2511_21535_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL64, TOL32 = 1e-12, 1e-5
+DEV = "cuda"
+
+
+def _t(a, dtype=None):
+    return torch.as_tensor(np.ascontiguousarray(a), device=DEV, dtype=dtype)
+
+
+def _n(t):
+    return t.detach().cpu().numpy()
+
+
+def _rel(a, b):
+    a, b = np.asarray(a).ravel(), np.asarray(b).ravel()
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _check_tree(gt, ot):
+    np.testing.assert_array_equal(_n(gt.perm), ot.perm)
+    np.testing.assert_array_equal(_n(gt.leaf_start), ot.leaf_start)
+    np.testing.assert_array_equal(_n(gt.leaf_key).view(np.uint64), ot.leaf_key)
+    np.testing.assert_array_equal(_n(gt.leaf_level), ot.leaf_level)
+
+
+def _particles_case(gen, n, seed, depth, cap):
+    if gen == "uniform":
+        x, y, z, m = W.uniform_particles(n, seed)
+    else:
+        x, y, z, m = W.plummer_mixture(n, seed)
+    return x, y, z, m
+
+
+PARTICLE_CASES = [
+    ("uniform", 4096, 1, 3, 0),       # the 4096-particle uniform depth-3 workload
+    ("uniform", 3000, 7, 4, 0),
+    ("plummer", 20000, 8, 20, 64),
+    ("plummer", 5000, 9, 20, 8),
+    ("plummer", 3001, 10, 20, 1),
+    ("plummer", 777, 11, 6, 16),      # depth cap reached
+]
+
+
+@pytest.mark.parametrize("gen,n,seed,depth,cap", PARTICLE_CASES)
+def test_tree_neighbors_restructure_bit_exact(gen, n, seed, depth, cap):
+    x, y, z, m = _particles_case(gen, n, seed, depth, cap)
+    print(f"case {gen} n={n} seed={seed} depth={depth} cap={cap}", flush=True)
+    gx, gy, gz, gm = (_t(v) for v in (x, y, z, m))
+    gt = api.Tree.build_particles(gx, gy, gz, depth=depth, leaf_cap=cap)
+    ot = oracle.build_tree_particles(x, y, z, depth=depth, leaf_cap=cap)
+    _check_tree(gt, ot)
+    assert gt.max_level == int(ot.leaf_level.max())
+    gn = gt.neighbors()
+    os_, oi = oracle.neighbors(ot)
+    np.testing.assert_array_equal(_n(gn.nbr_start), os_)
+    np.testing.assert_array_equal(_n(gn.nbr_idx), oi)
+    rs, rself, S = oracle.red_offsets(ot, os_, oi)
+    for prec in ("fp64", "fp32"):
+        red = api.restructure_gravity(gt, gn, gx, gy, gz, gm, prec=prec)
+        assert red.count == S
+        np.testing.assert_array_equal(_n(red.red_start), rs)
+        np.testing.assert_array_equal(_n(red.red_self), rself)
+        for k, v in enumerate((x, y, z)):
+            want = oracle.restructure_rows(ot, os_, oi, rs, v)
+            np.testing.assert_array_equal(_n(red.planes[k])[:S].view(np.uint64), want.view(np.uint64))
+        mm = m.astype(np.float32) if prec == "fp32" else m
+        np.testing.assert_array_equal(_n(red.planes[3])[:S], oracle.restructure_rows(ot, os_, oi, rs, mm))
+
+
+@pytest.mark.parametrize("gen,n,seed,depth,cap", PARTICLE_CASES[:4])
+@pytest.mark.parametrize("eps", [1e-3, 0.0])
+def test_gravity_parity(gen, n, seed, depth, cap, eps):
+    x, y, z, m = _particles_case(gen, n, seed, depth, cap)
+    if eps == 0.0:
+        # distinct points only (eps = 0 drops zero-distance pairs; the definition diverges there)
+        assert len(np.unique(np.stack([x, y, z], 1), axis=0)) == n
+    print(f"case {gen} n={n} eps={eps}", flush=True)
+    gx, gy, gz, gm = (_t(v) for v in (x, y, z, m))
+    gt = api.Tree.build_particles(gx, gy, gz, depth=depth, leaf_cap=cap)
+    gn = gt.neighbors()
+    ot = oracle.build_tree_particles(x, y, z, depth=depth, leaf_cap=cap)
+    ref = oracle.gravity(x, y, z, m, eps, ot)
+    for prec, tol in (("fp64", TOL64), ("fp32", TOL32)):
+        red = api.restructure_gravity(gt, gn, gx, gy, gz, gm, prec=prec)
+        for layout in ("gather", "redundant"):
+            out = api.gravity(gt, gn, eps, x=gx, y=gy, z=gz, m=gm, layout=layout, prec=prec, red=red)
+            o = [_n(v) for v in out]
+            e_phi = _rel(o[0], ref[0])
+            e_a = _rel(np.stack(o[1:]), np.stack(ref[1:]))
+            print(f"  {prec} {layout}: phi {e_phi:.2e} a {e_a:.2e}", flush=True)
+            assert e_phi <= tol and e_a <= tol
+
+
+def test_gravity_gather_equals_redundant_bitwise_fp64():
+    # both layouts feed the same pair sequence per lane: identical results
+    x, y, z, m = W.plummer_mixture(8000, 12)
+    gx, gy, gz, gm = (_t(v) for v in (x, y, z, m))
+    gt = api.Tree.build_particles(gx, gy, gz, depth=20, leaf_cap=64)
+    gn = gt.neighbors()
+    red = api.restructure_gravity(gt, gn, gx, gy, gz, gm, prec="fp64")
+    a = api.gravity(gt, gn, 1e-3, x=gx, y=gy, z=gz, m=gm)
+    b = api.gravity(gt, gn, 1e-3, layout="redundant", red=red)
+    c = api.gravity(gt, gn, 1e-3, layout="redundant", red=red)
+    for u, v, w in zip(a, b, c):
+        np.testing.assert_array_equal(_n(u), _n(v))
+        np.testing.assert_array_equal(_n(v), _n(w))      # deterministic
+
+
+def test_gravity_momentum_fp64():
+    x, y, z, m = W.plummer_mixture(30000, 13)
+    gx, gy, gz, gm = (_t(v) for v in (x, y, z, m))
+    gt = api.Tree.build_particles(gx, gy, gz, depth=20, leaf_cap=64)
+    gn = gt.neighbors()
+    _, ax, ay, az = (_n(v) for v in api.gravity(gt, gn, 1e-3, x=gx, y=gy, z=gz, m=gm))
+    a = np.stack([ax, ay, az], 1)
+    assert np.abs((m[:, None] * a).sum(0)).max() <= 1e-13 * np.sum(m * np.linalg.norm(a, axis=1))
+
+
+@pytest.mark.slow
+def test_full_size_plummer_2m_sampled():
+    """The 2^21-particle Plummer workload (adaptive, cap 64), FP32-mixed, in the
+    benchmark's launch configuration; tree bit-exact, sampled near lists,
+    payload segments and sums."""
+    w = W.WORKLOADS["gravity_plummer_2m"]
+    x, y, z, m = W.particles("gravity_plummer_2m")
+    print("case gravity_plummer_2m: building", flush=True)
+    gx, gy, gz, gm = (_t(v) for v in (x, y, z, m))
+    gt = api.Tree.build_particles(gx, gy, gz, depth=w["depth"], leaf_cap=w["leaf_cap"])
+    ot = oracle.build_tree_particles(x, y, z, depth=w["depth"], leaf_cap=w["leaf_cap"])
+    _check_tree(gt, ot)
+    gn = gt.neighbors()
+    rng = np.random.default_rng(0)
+    sel = np.sort(rng.choice(ot.n_leaves, 96, replace=False)).astype(np.int32)
+    sel[0] = 0
+    sel[-1] = ot.n_leaves - 1
+    ss, si = oracle.neighbors(ot, sel)
+    gs, gi = _n(gn.nbr_start), _n(gn.nbr_idx)
+    for k, A in enumerate(sel):
+        np.testing.assert_array_equal(gi[gs[A]:gs[A + 1]], si[ss[k]:ss[k + 1]])
+    red = api.restructure_gravity(gt, gn, gx, gy, gz, gm, prec="fp32")
+    rs = _n(red.red_start)
+    px = _n(red.planes[0])
+    occ = np.diff(ot.leaf_start)
+    for k, A in enumerate(sel[:16]):
+        want = np.concatenate([x[ot.perm[ot.leaf_start[B]:ot.leaf_start[B + 1]]] for B in si[ss[k]:ss[k + 1]]])
+        np.testing.assert_array_equal(px[rs[A]:rs[A + 1]], want)
+    idx, rp, rax, ray, raz = oracle.gravity_leaves(x, y, z, m, w["eps"], ot, sel, ss, si)
+    for layout in ("gather", "redundant"):
+        o = [_n(v)[idx] for v in api.gravity(gt, gn, w["eps"], x=gx, y=gy, z=gz, m=gm,
+                                             layout=layout, prec="fp32", red=red)]
+        e_phi = _rel(o[0], rp)
+        e_a = _rel(np.stack(o[1:]), np.stack([rax, ray, raz]))
+        print(f"  fp32 {layout}: phi {e_phi:.2e} a {e_a:.2e}", flush=True)
+        assert e_phi <= TOL32 and e_a <= TOL32
+    loc = api.locality(gt, gn, red)
+    assert loc["entries"] == red.count == int(occ[gi].sum())
+
+
+# --------------------------------------------------------------- Helmholtz
+def _grid_tree(sides):
+    grids = [api.Grid(int(n), *W.grid_geometry(int(n))) for n in sides]
+    return api.Tree.build_grids(grids), grids
+
+
+@pytest.mark.parametrize("sides", [[8], [16], [20], [12, 8, 4, 16]])
+def test_grid_tree_bit_exact(sides):
+    gt, _ = _grid_tree(sides)
+    ot = oracle.build_tree_grids(sides)
+    _check_tree(gt, ot)
+    gn = gt.neighbors()
+    os_, oi = oracle.neighbors(ot)
+    np.testing.assert_array_equal(_n(gn.nbr_start), os_)
+    np.testing.assert_array_equal(_n(gn.nbr_idx), oi)
+
+
+@pytest.mark.parametrize("sides,nrhs", [([16], 1), ([20], 1), ([12, 8, 16], 1), ([16], 3)])
+def test_helmholtz_parity(sides, nrhs):
+    print(f"case helmholtz sides={sides} nrhs={nrhs}", flush=True)
+    gt, grids = _grid_tree(sides)
+    gn = gt.neighbors()
+    n = gt.n
+    q = W.grid_rhs(n, nrhs, seed=21)
+    ref = oracle.helmholtz(sides, q)
+    for prec, cd, tol in (("fp32", np.complex64, TOL32), ("fp64", np.complex128, TOL64)):
+        gq = _t(q.astype(cd))
+        red = api.restructure(gt, gn, [gq], prec=prec, nrhs=nrhs)
+        ot = oracle.build_tree_grids(sides)
+        os_, oi = oracle.neighbors(ot)
+        rs, _, S = oracle.red_offsets(ot, os_, oi)
+        np.testing.assert_array_equal(_n(red.planes[0])[:S], oracle.restructure_rows(ot, os_, oi, rs, q.astype(cd)))
+        for layout in ("gather", "redundant"):
+            u = _n(api.helmholtz(gt, gn, gq, layout=layout, prec=prec, red=red))
+            err = _rel(u, ref)
+            print(f"  {prec} {layout}: {err:.2e}", flush=True)
+            assert err <= tol
+
+
+def test_helmholtz_full_64_sampled():
+    """The 64^3 grid workload, FP32, both layouts; sampled targets vs the oracle."""
+    gt, grids = _grid_tree([64])
+    gn = gt.neighbors()
+    q = W.grid_rhs(gt.n, 1, seed=W.WORKLOADS["helmholtz_grid_64"]["seed"])
+    gq = _t(q)
+    red = api.restructure(gt, gn, [gq], prec="fp32", nrhs=1)
+    rng = np.random.default_rng(1)
+    tg = np.unique(np.concatenate([rng.choice(gt.n, 4000, replace=False), [0, gt.n - 1]]))
+    ref = oracle.helmholtz([64], q, targets=tg)
+    loc = api.locality(gt, gn, red)
+    assert loc["pairs"] == 398426112
+    for layout in ("gather", "redundant"):
+        u = _n(api.helmholtz(gt, gn, gq, layout=layout, prec="fp32", red=red))
+        err = _rel(u[tg], ref)
+        print(f"  64^3 fp32 {layout}: {err:.2e}", flush=True)
+        assert err <= TOL32
+
+
+# --------------------------------------------------------------- adjoint
+def test_gravity_adjoint_parity():
+    x, y, z, m = W.plummer_mixture(3000, 31)
+    gp, gax, gay, gaz = (W.normal_like(3000, seed=s) for s in (32, 33, 34, 35))
+    gx, gy, gz, gm = (_t(v) for v in (x, y, z, m))
+    gt = api.Tree.build_particles(gx, gy, gz, depth=20, leaf_cap=64)
+    gn = gt.neighbors()
+    out = [_n(v) for v in api.gravity_adjoint(gt, gn, 1e-3, gx, gy, gz, gm, *(_t(v) for v in (gp, gax, gay, gaz)))]
+    ot = oracle.build_tree_particles(x, y, z, depth=20, leaf_cap=64)
+    rm, rx, ry, rz = oracle.gravity_adjoint(x, y, z, m, 1e-3, gp, gax, gay, gaz, ot)
+    assert _rel(out[3], rm) <= TOL64
+    assert _rel(np.stack(out[:3]), np.stack([rx, ry, rz])) <= TOL64
+
+
+def test_helmholtz_adjoint_transpose():
+    sides = [12, 8]
+    gt, _ = _grid_tree(sides)
+    gn = gt.neighbors()
+    g = W.grid_rhs(gt.n, 1, seed=41)[:, 0].astype(np.complex128)
+    ref = oracle.helmholtz_transpose(sides, g)
+    out = _n(api.helmholtz_adjoint(gt, gn, _t(g), prec="fp64"))
+    assert _rel(out, ref) <= TOL64
+    outc = _n(api.helmholtz_adjoint(gt, gn, _t(g), prec="fp64", conjugate=True))
+    assert _rel(outc, np.conj(oracle.helmholtz_transpose(sides, np.conj(g)))) <= TOL64
+
+
+# --------------------------------------------------------------- edge cases
+def test_edge_cases():
+    # one particle; all particles in one leaf; duplicate points
+    for pts in ([[0.5, 0.5, 0.5]], [[0.1, 0.1, 0.1]] * 5, np.random.default_rng(3).random((40, 3)) * 1e-4 + 0.3):
+        P = np.asarray(pts, dtype=np.float64)
+        m = np.ones(len(P))
+        g = [_t(P[:, d].copy()) for d in range(3)] + [_t(m)]
+        gt = api.Tree.build_particles(*g[:3], depth=20, leaf_cap=64)
+        ot = oracle.build_tree_particles(P[:, 0], P[:, 1], P[:, 2], depth=20, leaf_cap=64)
+        _check_tree(gt, ot)
+        gn = gt.neighbors()
+        ref = oracle.gravity(P[:, 0], P[:, 1], P[:, 2], m, 1e-3, ot)
+        red = api.restructure_gravity(gt, gn, *g, prec="fp64")
+        for layout in ("gather", "redundant"):
+            out = [_n(v) for v in api.gravity(gt, gn, 1e-3, *g, layout=layout, red=red)]
+            np.testing.assert_allclose(out[0], ref[0], rtol=1e-12, atol=1e-300)
+    # out-of-domain coordinate: error, no launch of the later steps
+    P = np.array([[0.5, 0.5, 1.0]])
+    with pytest.raises(Exception, match="EDOMAIN"):
+        api.Tree.build_particles(*[_t(P[:, d].copy()) for d in range(3)])
+    # empty input
+    e = _t(np.zeros(0))
+    gt = api.Tree.build_particles(e, e, e)
+    assert gt.n_leaves == 0
+
+
+def test_locality_matches_oracle():
+    x, y, z, m = W.plummer_mixture(20000, 51)
+    gt = api.Tree.build_particles(_t(x), _t(y), _t(z), depth=20, leaf_cap=64)
+    gn = gt.neighbors()
+    loc = api.locality(gt, gn, bytes_per_entry=28.0, cache_bytes=32 * 2 ** 20)
+    ot = oracle.build_tree_particles(x, y, z, depth=20, leaf_cap=64)
+    os_, oi = oracle.neighbors(ot)
+    _, _, S = oracle.red_offsets(ot, os_, oi)
+    ref = oracle.locality(os_, oi, len(x), S, 28.0, 32 * 2 ** 20)
+    assert loc["entries"] == S
+    assert loc["pairs"] == oracle.pair_count(ot, os_, oi)
+    for k_g, k_o in (("d_mean", "D_mean"), ("v_ratio", "V_ratio"), ("locality", "locality")):
+        assert abs(loc[k_g] - ref[k_o]) <= 1e-12 * abs(ref[k_o])
