@@ -112,22 +112,27 @@ __global__ void k_leaf_flag_grids(const uint64_t *__restrict__ sk, int64_t n,
 
 __global__ void k_leaf_write(const uint64_t *__restrict__ sk, const int8_t *__restrict__ level,
                              const int32_t *__restrict__ flag, const int32_t *__restrict__ fscan,
-                             int64_t n, int kind, int key_bits, int32_t *__restrict__ leaf_start,
+                             int64_t n, int kind, int32_t *__restrict__ leaf_start,
                              uint64_t *__restrict__ leaf_key, int8_t *__restrict__ leaf_level,
                              int32_t *__restrict__ max_level) {
-    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    if (i == 0) leaf_start[fscan[n]] = static_cast<int32_t>(n);
-    if (!flag[i]) return;
-    const int32_t L = fscan[i];
-    const int l = level[i];
-    leaf_start[L] = static_cast<int32_t>(i);
-    leaf_level[L] = static_cast<int8_t>(l);
-    uint64_t low_bits = (kind == P2P_TREE_PARTICLES) ? 3ull * (20 - l) : 6ull;
-    uint64_t mask = (low_bits >= 64) ? 0ull : ~((1ull << low_bits) - 1ull);
-    leaf_key[L] = sk[i] & mask;
-    atomicMax(max_level, l);
-    (void)key_bits;
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    int lmax = -1;
+    if (i < n) {
+        if (i == 0) leaf_start[fscan[n]] = static_cast<int32_t>(n);
+        if (flag[i]) {
+            const int32_t L = fscan[i];
+            const int l = level[i];
+            leaf_start[L] = static_cast<int32_t>(i);
+            leaf_level[L] = static_cast<int8_t>(l);
+            const uint64_t low_bits = (kind == P2P_TREE_PARTICLES) ? 3ull * (20 - l) : 6ull;
+            const uint64_t mask = (low_bits >= 64) ? 0ull : ~((1ull << low_bits) - 1ull);
+            leaf_key[L] = sk[i] & mask;
+            lmax = l;
+        }
+    }
+    // one atomic per wave instead of one per leaf
+    for (int o = 32; o > 0; o >>= 1) lmax = max(lmax, __shfl_xor(lmax, o, 64));
+    if ((threadIdx.x & 63) == 0 && lmax >= 0) atomicMax(max_level, lmax);
 }
 
 }  // namespace
@@ -170,7 +175,8 @@ p2p_status launch_leaf_write(const uint64_t *skeys, const int8_t *level, const i
                              int32_t *leaf_start, uint64_t *leaf_key, int8_t *leaf_level,
                              int32_t *max_level, hipStream_t s) {
     if (n <= 0) return P2P_OK;
-    k_leaf_write<<<grid_for(n, 256), 256, 0, s>>>(skeys, level, flags, flag_scan, n, kind, key_bits,
+    (void)key_bits;
+    k_leaf_write<<<grid_for(n, 256), 256, 0, s>>>(skeys, level, flags, flag_scan, n, kind,
                                                   leaf_start, leaf_key, leaf_level, max_level);
     P2P_LAUNCH_CHECK();
     return P2P_OK;
