@@ -285,7 +285,7 @@ def helmholtz(tree: Tree, nbrs: Nbrs, q: Optional[torch.Tensor] = None, layout="
     gs, _ = grids_struct(tree.grids)
     ts, ns = tree.struct(), nbrs.struct()
     rs = red.struct() if red is not None else None
-    tl = (ctypes.c_int32 * 2)(*tile) if tile is not None else None
+    tl = (ctypes.c_int32 * 3)(*tile) if tile is not None else None
 
     def call(ws, nb):
         return L.p2p_eval_helmholtz(ctypes.byref(ts), ctypes.byref(ns),

@@ -1,0 +1,93 @@
+"""Autotuner for the launch shape of the multi-RHS Helmholtz matrix-core kernel.
+
+Candidates are (waves per workgroup, workgroups per CU, right-hand sides per
+wave).  Each candidate is timed on the actual problem with HIP events (one
+warm-up, then the median of `reps` calls) and the fastest is cached in a JSON
+file keyed by device name, grid sizes, nrhs and layout.  The cache path is
+$P2P_AUTOTUNE_CACHE, else ~/.cache/p2p_mi355x_autotune.json.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+from typing import Dict, Optional, Sequence, Tuple
+
+import torch
+
+from . import api
+
+CANDIDATES = [(w, c, r) for w in (1, 2, 4) for c in (1, 2, 4, 8) for r in (32, 64)]
+
+
+def cache_path() -> str:
+    return os.environ.get("P2P_AUTOTUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "p2p_mi355x_autotune.json"))
+
+
+def problem_key(tree: api.Tree, nrhs: int, layout: str) -> str:
+    dev = torch.cuda.get_device_name(tree.leaf_start.device)
+    sizes = ",".join(str(g.n_side) for g in tree.grids)
+    h = hashlib.sha1(sizes.encode()).hexdigest()[:16]
+    return f"{dev}|grids={len(tree.grids)}:{h}|nrhs={nrhs}|{layout}"
+
+
+def _load_cache() -> Dict[str, dict]:
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _save_cache(c: Dict[str, dict]) -> None:
+    p = cache_path()
+    os.makedirs(os.path.dirname(p), exist_ok=True)
+    tmp = p + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(c, f, indent=1, sort_keys=True)
+    os.replace(tmp, p)
+
+
+def time_call(fn, reps: int = 3) -> float:
+    """Median milliseconds of fn() over `reps` calls after one warm-up."""
+    fn()
+    ts = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def tune_helmholtz(tree: api.Tree, nbrs: api.Nbrs, q: Optional[torch.Tensor] = None,
+                   red: Optional[api.Redundant] = None, layout: str = "gather",
+                   candidates: Sequence[Tuple[int, int, int]] = CANDIDATES, reps: int = 3,
+                   use_cache: bool = True) -> Tuple[Tuple[int, int, int], Dict[str, float]]:
+    """Pick the fastest launch shape for this problem; returns (tile, timings)."""
+    nrhs = red.nrhs if red is not None else q.shape[1]
+    key = problem_key(tree, nrhs, layout)
+    cache = _load_cache() if use_cache else {}
+    if key in cache:
+        e = cache[key]
+        return tuple(e["tile"]), e.get("ms", {})
+    out = torch.empty((tree.n, nrhs), dtype=torch.complex64, device=tree.leaf_start.device)
+    timings = {}
+    for cand in candidates:
+        if nrhs % cand[2]:
+            continue
+        fn = lambda: api.helmholtz(tree, nbrs, q, layout=layout, prec="fp32", red=red, nrhs=nrhs,
+                                   tile=cand, out=out)
+        timings[str(list(cand))] = time_call(fn, reps)
+    best = min(timings, key=timings.get)
+    tile = tuple(json.loads(best))
+    if use_cache:
+        cache = _load_cache()
+        cache[key] = {"tile": list(tile), "ms": timings}
+        _save_cache(cache)
+    return tile, timings

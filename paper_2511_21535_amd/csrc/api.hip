@@ -403,7 +403,7 @@ struct HelmPlan {
 p2p_status helmholtz_common(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2p_redundant *red,
                             p2p_layout layout, p2p_precision prec, const p2p_grid *grids,
                             int32_t n_grids, int32_t nrhs, const void *q, void *u, int32_t conj,
-                            void *ws, size_t *ws_bytes, hipStream_t s) {
+                            const int32_t *tile, void *ws, size_t *ws_bytes, hipStream_t s) {
     if (!ws_bytes) return fail(P2P_EINVAL, "ws_bytes must not be NULL");
     P2P_TRY(check_tree(tree));
     if (tree->kind != P2P_TREE_GRIDS) return fail(P2P_EINVAL, "Helmholtz needs a grid tree");
@@ -414,12 +414,57 @@ p2p_status helmholtz_common(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2
     if (n_grids != tree->n_grids) return fail(P2P_EINVAL, "n_grids differs from the tree's");
     P2P_TRY(check_grids(grids, n_grids, tree->n));
     const bool fp64 = prec == P2P_FP64, redundant = layout == P2P_REDUNDANT;
-    const size_t csize = fp64 ? sizeof(double2) : sizeof(double2) / 2;
-    const int64_t n = tree->n;
+    const bool mfma = !fp64 && nrhs % 32 == 0;
+    int waves_per_wg = 4, wg_per_cu = 2, rhs_tile = (nrhs % 64 == 0) ? 64 : 32;
+    if (tile) {
+        if (!mfma) return fail(P2P_EINVAL, "tile applies to the matrix-core path (FP32_MIXED, nrhs % 32 == 0)");
+        waves_per_wg = tile[0];
+        wg_per_cu = tile[1];
+        rhs_tile = tile[2];
+        if (waves_per_wg != 1 && waves_per_wg != 2 && waves_per_wg != 4)
+            return fail(P2P_EINVAL, "tile[0] (waves per workgroup) must be 1, 2 or 4");
+        if (wg_per_cu < 1 || wg_per_cu > 16) return fail(P2P_EINVAL, "tile[1] (workgroups per CU) must be in 1..16");
+        if ((rhs_tile != 32 && rhs_tile != 64) || nrhs % rhs_tile != 0)
+            return fail(P2P_EINVAL, "tile[2] (RHS tile) must be 32 or 64 and divide nrhs");
+    }
+    const size_t csize = fp64 ? sizeof(double2) : sizeof(float2);
+    const int64_t n = tree->n, L = tree->n_leaves;
+
+    // distinct k h values share one set of unit-spacing G blocks (relative tolerance 1e-12)
+    std::vector<double> khs;
+    std::vector<int32_t> itab(n_grids);
+    std::vector<float> iscale(n_grids);
+    for (int32_t g = 0; g < n_grids; ++g) {
+        const double kh = grids[g].k * grids[g].h;
+        int32_t t = -1;
+        for (size_t j = 0; j < khs.size(); ++j)
+            if (std::fabs(khs[j] - kh) <= 1e-12 * std::fmax(std::fabs(kh), 1e-300) || khs[j] == kh) {
+                t = static_cast<int32_t>(j);
+                break;
+            }
+        if (t < 0) {
+            t = static_cast<int32_t>(khs.size());
+            khs.push_back(kh);
+        }
+        itab[g] = t;
+        iscale[g] = static_cast<float>(1.0 / grids[g].h);
+    }
+    const int32_t n_tables = static_cast<int32_t>(khs.size());
+
     Arena ar(ws);
     double *d_h = ar.take<double>(n_grids);
     double *d_k = ar.take<double>(n_grids);
-    char *table = ar.take<char>(static_cast<size_t>(n_grids) * kTableLen * csize);
+    char *table = mfma ? nullptr : ar.take<char>(static_cast<size_t>(n_grids) * kTableLen * csize);
+    double *d_kh = mfma ? ar.take<double>(n_tables) : nullptr;
+    float2 *blocks = mfma ? ar.take<float2>(static_cast<size_t>(n_tables) * 27 * 4096) : nullptr;
+    int32_t *d_itab = mfma ? ar.take<int32_t>(n_grids) : nullptr;
+    float *d_iscale = mfma ? ar.take<float>(n_grids) : nullptr;
+    int32_t *work = mfma ? ar.take<int32_t>(L) : nullptr;
+    uint64_t *wkeys = mfma ? ar.take<uint64_t>(L) : nullptr;
+    uint64_t *wkeys_tmp = mfma ? ar.take<uint64_t>(L) : nullptr;
+    int32_t *wvals_tmp = mfma ? ar.take<int32_t>(L) : nullptr;
+    uint32_t *whist = mfma ? ar.take<uint32_t>(radix_hist_elems(L)) : nullptr;
+    int32_t *counter = mfma ? ar.take<int32_t>(64) : nullptr;
     char *sorted = redundant ? nullptr : ar.take<char>(static_cast<size_t>(n) * nrhs * csize);
     p2p_status st;
     if (ws_query(ws, ws_bytes, ar, &st)) return st;
@@ -434,14 +479,6 @@ p2p_status helmholtz_common(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2
     } else if (n > 0 && !q) {
         return fail(P2P_EINVAL, "q must not be NULL");
     }
-    std::vector<double> hk(2 * n_grids);
-    for (int32_t g = 0; g < n_grids; ++g) {
-        hk[g] = grids[g].h;
-        hk[n_grids + g] = grids[g].k;
-    }
-    P2P_HIP(hipMemcpyAsync(d_h, hk.data(), n_grids * sizeof(double), hipMemcpyHostToDevice, s));
-    P2P_HIP(hipMemcpyAsync(d_k, hk.data() + n_grids, n_grids * sizeof(double), hipMemcpyHostToDevice, s));
-    P2P_TRY(launch_green_tables(d_h, d_k, n_grids, fp64, table, s));
     if (!redundant) {
         if (fp64)
             P2P_TRY(launch_permute_rows<double2>(static_cast<const double2 *>(q), tree->perm, n, nrhs,
@@ -450,8 +487,42 @@ p2p_status helmholtz_common(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2
             P2P_TRY(launch_permute_rows<float2>(static_cast<const float2 *>(q), tree->perm, n, nrhs,
                                                 reinterpret_cast<float2 *>(sorted), s));
     }
+    if (mfma) {
+        P2P_HIP(hipMemcpyAsync(d_kh, khs.data(), n_tables * sizeof(double), hipMemcpyHostToDevice, s));
+        P2P_HIP(hipMemcpyAsync(d_itab, itab.data(), n_grids * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        P2P_HIP(hipMemcpyAsync(d_iscale, iscale.data(), n_grids * sizeof(float), hipMemcpyHostToDevice, s));
+        P2P_TRY(launch_green_blocks(d_kh, n_tables, blocks, s));
+        P2P_TRY(launch_work_order(nbrs->nbr_start, L, work, wkeys, wkeys_tmp, wvals_tmp, whist, s));
+        HelmholtzMfmaArgs a{};
+        a.L = L;
+        a.key_bits = tree->key_bits;
+        a.leaf_start = tree->leaf_start;
+        a.leaf_key = tree->leaf_key;
+        a.perm = tree->perm;
+        a.nbr_start = nbrs->nbr_start;
+        a.nbr_idx = nbrs->nbr_idx;
+        a.red_start = redundant ? red->red_start : nullptr;
+        a.src = redundant ? static_cast<const float2 *>(red->planes[0]) : reinterpret_cast<const float2 *>(sorted);
+        a.blocks = blocks;
+        a.inst_table = d_itab;
+        a.inst_scale = d_iscale;
+        a.work = work;
+        a.counter = counter;
+        a.nrhs = nrhs;
+        a.conj = conj;
+        a.u = static_cast<float2 *>(u);
+        return launch_helmholtz_mfma(a, redundant, waves_per_wg, wg_per_cu, rhs_tile, s);
+    }
+    std::vector<double> hk(2 * n_grids);
+    for (int32_t g = 0; g < n_grids; ++g) {
+        hk[g] = grids[g].h;
+        hk[n_grids + g] = grids[g].k;
+    }
+    P2P_HIP(hipMemcpyAsync(d_h, hk.data(), n_grids * sizeof(double), hipMemcpyHostToDevice, s));
+    P2P_HIP(hipMemcpyAsync(d_k, hk.data() + n_grids, n_grids * sizeof(double), hipMemcpyHostToDevice, s));
+    P2P_TRY(launch_green_tables(d_h, d_k, n_grids, fp64, table, s));
     HelmholtzArgs a{};
-    a.L = tree->n_leaves;
+    a.L = L;
     a.key_bits = tree->key_bits;
     a.leaf_start = tree->leaf_start;
     a.leaf_key = tree->leaf_key;
@@ -475,8 +546,7 @@ extern "C" p2p_status p2p_eval_helmholtz(const p2p_tree *tree, const p2p_nbrs *n
                                          int32_t nrhs, const void *q, void *u, const int32_t *tile,
                                          void *ws, size_t *ws_bytes, p2p_stream_t stream) {
     set_error("");
-    (void)tile;
-    return helmholtz_common(tree, nbrs, red, layout, prec, grids, n_grids, nrhs, q, u, 0, ws,
+    return helmholtz_common(tree, nbrs, red, layout, prec, grids, n_grids, nrhs, q, u, 0, tile, ws,
                             ws_bytes, as_stream(stream));
 }
 
@@ -497,7 +567,7 @@ extern "C" p2p_status p2p_adjoint(int32_t kind, const p2p_tree *tree, const p2p_
         void *out = grad_in ? grad_in[0] : nullptr;
         // A is symmetric (reciprocity and a symmetric near relation): A^T g = A g
         return helmholtz_common(tree, nbrs, red, P2P_GATHER, prec, grids, n_grids, nrhs, g, out,
-                                conjugate, ws, ws_bytes, s);
+                                conjugate, nullptr, ws, ws_bytes, s);
     }
     if (kind != P2P_KIND_GRAVITY) return fail(P2P_EINVAL, "kind must be P2P_KIND_GRAVITY or P2P_KIND_HELMHOLTZ");
     (void)red;

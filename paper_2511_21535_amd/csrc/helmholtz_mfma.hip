@@ -1,0 +1,243 @@
+// Multi-RHS near-field Helmholtz on FP32 matrix cores (a9) in one persistent
+// launch over every box of every grid instance (a10).
+//
+// For target box b (64 points) and R right-hand sides:
+//     U_b (64 x R) = sum_{o in near offsets} G_o (64 x 64) Q_{b+o} (64 x R),
+// a dense complex contraction.  On a regular grid G_o depends only on the box
+// offset o (27 values) and on k h, so the 27 blocks are built once per call
+// in FP64 for unit spacing (G scales as 1/h) and shared by all boxes of all
+// instances with the same k h; the scale 1/h is applied when U is stored.
+//
+// One wavefront owns one target box and a chunk of 32*TJ right-hand sides.
+// The complex product runs as four real v_mfma_f32_32x32x2f32 per 32x32
+// tile: Re U += Re G Re Q - Im G Im Q, Im U += Re G Im Q + Im G Re Q.  Per
+// k-step (2 sources) a lane loads one complex G entry per row tile and one
+// complex Q entry per column tile; G is stored source-major, [o][s][t], and
+// Q row-major, [s][rhs], so both loads are contiguous across 32 lanes.
+// Lane layouts of the instruction: A[i][k] from lane k*32 + i, B[k][j] from
+// lane k*32 + j, and accumulator register r of lane l holds row
+// 8 (r/4) + 4 (l/32) + r%4, column l%32.
+//
+// Work distribution: waves take boxes from an atomic counter over a list
+// ordered by decreasing near-list length (longest processing time first),
+// and exit when the list is exhausted.
+#include "p2p_internal.h"
+
+namespace p2p {
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+constexpr double kPi = 3.14159265358979323846;
+
+// blocks[t][o][s][i] = e^{i kh sqrt(dd)} / (4 pi sqrt(dd)), dd = |l_i - (l_s + 4 o)|^2,
+// zero for dd = 0.  o = (ox+1) + 3 (oy+1) + 9 (oz+1); l_* are local Morton coordinates.
+__global__ void k_green_blocks(const double *__restrict__ kh, int32_t n_tables,
+                               float2 *__restrict__ blocks) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t per = 27 * 64 * 64;
+    if (t >= per * n_tables) return;
+    const int tab = static_cast<int>(t / per);
+    const int rem = static_cast<int>(t % per);
+    const int o = rem / 4096, s = (rem / 64) % 64, i = rem % 64;
+    const int od[3] = {o % 3 - 1, (o / 3) % 3 - 1, o / 9 - 1};
+    int dd = 0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int li = ((i >> d) & 1) | (((i >> (d + 3)) & 1) << 1);
+        const int ls = ((s >> d) & 1) | (((s >> (d + 3)) & 1) << 1);
+        const int diff = li - (ls + 4 * od[d]);
+        dd += diff * diff;
+    }
+    float2 v = make_float2(0.f, 0.f);
+    if (dd > 0) {
+        const double r = sqrt(static_cast<double>(dd));
+        const double a = 1.0 / (4.0 * kPi * r);
+        double sn, cs;
+        sincos(kh[tab] * r, &sn, &cs);
+        v = make_float2(static_cast<float>(cs * a), static_cast<float>(sn * a));
+    }
+    blocks[t] = v;
+}
+
+__global__ void k_work_keys(const int64_t *__restrict__ nbr_start, int64_t L,
+                            uint64_t *__restrict__ keys, int32_t *__restrict__ vals) {
+    const int64_t A = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (A >= L) return;
+    const int64_t c = nbr_start[A + 1] - nbr_start[A];
+    keys[A] = static_cast<uint64_t>(255 - min<int64_t>(c, 255));   // longest lists first
+    vals[A] = static_cast<int32_t>(A);
+}
+
+__global__ void k_zero_counter(int32_t *c, int n) {
+    if (static_cast<int>(threadIdx.x) < n) c[threadIdx.x] = 0;
+}
+
+template <bool RED, bool CONJ, int TJ>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_helm_mfma(
+    int64_t L, int key_bits, int32_t nrhs, const int32_t *__restrict__ leaf_start,
+    const uint64_t *__restrict__ leaf_key, const int32_t *__restrict__ perm,
+    const int64_t *__restrict__ nbr_start, const int32_t *__restrict__ nbr_idx,
+    const int64_t *__restrict__ red_start, const float2 *__restrict__ src,
+    const float2 *__restrict__ blocks, const int32_t *__restrict__ inst_table,
+    const float *__restrict__ inst_scale, const int32_t *__restrict__ work,
+    int32_t *__restrict__ counter, float2 *__restrict__ u) {
+    const int lane = threadIdx.x & 63;
+    const int half = lane >> 5, col = lane & 31;
+    const uint64_t local_mask = (1ull << (3 * key_bits)) - 1ull;
+    const int chunks = nrhs / (32 * TJ);
+    const int64_t items = L * chunks;
+
+    for (;;) {
+        int item = 0;
+        if (lane == 0) item = atomicAdd(counter, 1);
+        item = __builtin_amdgcn_readfirstlane(__shfl(item, 0, 64));
+        if (item >= items) break;
+        const int64_t A = work[item / chunks];
+        const int rhs0 = (item % chunks) * 32 * TJ;
+        const uint64_t kA = leaf_key[A];
+        const int g = static_cast<int>(kA >> (3 * key_bits));
+        const float2 *__restrict__ gbase = blocks + static_cast<int64_t>(inst_table[g]) * (27 * 4096);
+        const uint64_t lA = kA & local_mask;
+        const int ax = static_cast<int>(p2pd::compact3(lA)), ay = static_cast<int>(p2pd::compact3(lA >> 1)),
+                  az = static_cast<int>(p2pd::compact3(lA >> 2));
+        const int64_t e0 = nbr_start[A];
+        const int ne = static_cast<int>(nbr_start[A + 1] - e0);
+
+        // lane e (< ne) works out the operand offsets of near box e once: the
+        // G block of its offset and its first Q row; the k-loop reads them
+        // back with readlane, so no memory access sits between boxes
+        int my_goff = 0, my_row_lo = 0, my_row_hi = 0;
+        if (lane < ne) {
+            const int32_t B = nbr_idx[e0 + lane];
+            const uint64_t lB = leaf_key[B] & local_mask;
+            const int ox = (static_cast<int>(p2pd::compact3(lB)) - ax) / 4;
+            const int oy = (static_cast<int>(p2pd::compact3(lB >> 1)) - ay) / 4;
+            const int oz = (static_cast<int>(p2pd::compact3(lB >> 2)) - az) / 4;
+            my_goff = ((ox + 1) + 3 * (oy + 1) + 9 * (oz + 1)) * 4096;
+            const int64_t row0 = RED ? red_start[A] + 64 * static_cast<int64_t>(lane) : leaf_start[B];
+            my_row_lo = static_cast<int>(row0 & 0xffffffff);
+            my_row_hi = static_cast<int>(row0 >> 32);
+        }
+        auto box_ptrs = [&](int e, const float2 *&Gp, const float2 *&Qp) {
+            const int goff = __builtin_amdgcn_readlane(my_goff, e);
+            const int64_t row0 = (static_cast<int64_t>(__builtin_amdgcn_readlane(my_row_hi, e)) << 32) |
+                                 static_cast<uint32_t>(__builtin_amdgcn_readlane(my_row_lo, e));
+            Gp = gbase + goff + half * 64 + col;
+            Qp = src + (row0 + half) * nrhs + rhs0 + col;
+        };
+
+        floatx16 ur[2][TJ], ui[2][TJ];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < TJ; ++b) {
+                ur[a][b] = floatx16{0};
+                ui[a][b] = floatx16{0};
+            }
+
+        const int64_t qstep = 2 * static_cast<int64_t>(nrhs);   // two source rows per k-step
+        auto load = [&](const float2 *Gp, const float2 *Qp, int kk, float2 (&gv)[2], float2 (&qv)[TJ]) {
+#pragma unroll
+            for (int a = 0; a < 2; ++a) gv[a] = Gp[kk * 128 + 32 * a];
+#pragma unroll
+            for (int b = 0; b < TJ; ++b) qv[b] = Qp[kk * qstep + 32 * b];
+        };
+        auto mma = [&](const float2 (&gv)[2], const float2 (&qv)[TJ]) {
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const float gr = gv[a].x, gi = CONJ ? -gv[a].y : gv[a].y;
+#pragma unroll
+                for (int b = 0; b < TJ; ++b) {
+                    ur[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(gr, qv[b].x, ur[a][b], 0, 0, 0);
+                    ui[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(gr, qv[b].y, ui[a][b], 0, 0, 0);
+                    ur[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(-gi, qv[b].y, ur[a][b], 0, 0, 0);
+                    ui[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(gi, qv[b].x, ui[a][b], 0, 0, 0);
+                }
+            }
+        };
+
+        // ping-pong operand registers, one k-step of prefetch, across box boundaries
+        const float2 *Gc, *Qc, *Gn, *Qn;
+        box_ptrs(0, Gc, Qc);
+        float2 ga[2], qa[TJ], gb[2], qb[TJ];
+        load(Gc, Qc, 0, ga, qa);
+        for (int e = 0; e < ne; ++e) {
+            box_ptrs(e + 1 < ne ? e + 1 : e, Gn, Qn);
+#pragma unroll
+            for (int kk = 0; kk < 32; kk += 2) {
+                load(Gc, Qc, kk + 1, gb, qb);
+                mma(ga, qa);
+                if (kk + 2 < 32)
+                    load(Gc, Qc, kk + 2, ga, qa);
+                else
+                    load(Gn, Qn, 0, ga, qa);
+                mma(gb, qb);
+            }
+            Gc = Gn;
+            Qc = Qn;
+        }
+        const float sc = inst_scale[g];
+        const int32_t t0 = leaf_start[A];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int i = 32 * a + 8 * (r / 4) + 4 * half + (r % 4);
+                const int64_t row = static_cast<int64_t>(perm[t0 + i]) * nrhs + rhs0 + col;
+#pragma unroll
+                for (int b = 0; b < TJ; ++b) u[row + 32 * b] = make_float2(ur[a][b][r] * sc, ui[a][b][r] * sc);
+            }
+    }
+}
+
+}  // namespace
+
+p2p_status launch_green_blocks(const double *d_kh, int32_t n_tables, float2 *blocks, hipStream_t s) {
+    const int64_t n = static_cast<int64_t>(n_tables) * 27 * 4096;
+    k_green_blocks<<<grid_for(n, 256), 256, 0, s>>>(d_kh, n_tables, blocks);
+    P2P_LAUNCH_CHECK();
+    return P2P_OK;
+}
+
+p2p_status launch_work_order(const int64_t *nbr_start, int64_t L, int32_t *work, uint64_t *keys,
+                             uint64_t *keys_tmp, int32_t *vals_tmp, uint32_t *hist,
+                             hipStream_t s) {
+    if (L <= 0) return P2P_OK;
+    k_work_keys<<<grid_for(L, 256), 256, 0, s>>>(nbr_start, L, keys, work);
+    P2P_LAUNCH_CHECK();
+    return radix_sort_pairs(keys, work, keys_tmp, vals_tmp, L, 8, hist, s);
+}
+
+template <bool RED, bool CONJ, int TJ>
+static void launch_mfma_t(const HelmholtzMfmaArgs &a, unsigned grid, unsigned block, hipStream_t s) {
+    k_helm_mfma<RED, CONJ, TJ><<<grid, block, 0, s>>>(
+        a.L, a.key_bits, a.nrhs, a.leaf_start, a.leaf_key, a.perm, a.nbr_start, a.nbr_idx,
+        a.red_start, a.src, a.blocks, a.inst_table, a.inst_scale, a.work, a.counter, a.u);
+}
+
+p2p_status launch_helmholtz_mfma(const HelmholtzMfmaArgs &a, bool redundant, int waves_per_wg,
+                                 int wg_per_cu, int rhs_tile, hipStream_t s) {
+    if (a.L <= 0) return P2P_OK;
+    int dev = 0, cus = 0;
+    P2P_HIP(hipGetDevice(&dev));
+    P2P_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    k_zero_counter<<<1, 64, 0, s>>>(a.counter, 1);
+    P2P_LAUNCH_CHECK();
+    const unsigned block = 64u * static_cast<unsigned>(waves_per_wg);
+    const unsigned grid = static_cast<unsigned>(cus) * static_cast<unsigned>(wg_per_cu);
+    const bool cj = a.conj != 0;
+    const int TJ = (rhs_tile == 64) ? 2 : 1;
+#define P2P_MF(R, C, T) launch_mfma_t<R, C, T>(a, grid, block, s)
+    if (TJ == 2) {
+        if (redundant) { if (cj) P2P_MF(true, true, 2); else P2P_MF(true, false, 2); }
+        else { if (cj) P2P_MF(false, true, 2); else P2P_MF(false, false, 2); }
+    } else {
+        if (redundant) { if (cj) P2P_MF(true, true, 1); else P2P_MF(true, false, 1); }
+        else { if (cj) P2P_MF(false, true, 1); else P2P_MF(false, false, 1); }
+    }
+#undef P2P_MF
+    P2P_LAUNCH_CHECK();
+    return P2P_OK;
+}
+
+}  // namespace p2p

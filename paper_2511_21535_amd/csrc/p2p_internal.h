@@ -179,10 +179,11 @@ struct HelmholtzMfmaArgs {
     float2 *u;                 // caller order [n][nrhs]
 };
 p2p_status launch_green_blocks(const double *d_kh, int32_t n_tables, float2 *blocks, hipStream_t s);
-p2p_status launch_work_order(const int64_t *nbr_start, int64_t L, int32_t *work, int32_t *keys_tmp,
+p2p_status launch_work_order(const int64_t *nbr_start, int64_t L, int32_t *work, uint64_t *keys,
+                             uint64_t *keys_tmp, int32_t *vals_tmp, uint32_t *hist,
                              hipStream_t s);
-p2p_status launch_helmholtz_mfma(const HelmholtzMfmaArgs &a, bool redundant, int boxes_per_wg,
-                                 int wg_per_cu, hipStream_t s);
+p2p_status launch_helmholtz_mfma(const HelmholtzMfmaArgs &a, bool redundant, int waves_per_wg,
+                                 int wg_per_cu, int rhs_tile, hipStream_t s);
 
 // Locality (locality.hip).
 p2p_status launch_locality_stats(const int32_t *leaf_start, const int64_t *nbr_start,
