@@ -1,10 +1,10 @@
 """Benchmark: near-field pair-interactions/s, redundant vs gather layout
 (restructure included), on one MI355X.
 
-Workload (the irregular gravity case): 2^21 particles from a mixture of 8
-Plummer spheres, adaptive octree with leaf cap 64, Plummer softening 1e-3,
-FP32-mixed pair arithmetic.  One step is one pass of the whole path over the
-resident inputs: tree binning, near lists, restructure to the redundant
+Default workload (the irregular gravity case): 2^21 particles from a mixture
+of 8 Plummer spheres, adaptive octree with leaf cap 64, Plummer softening
+1e-3, FP32-mixed pair arithmetic.  One step is one pass of the whole path over
+the resident inputs: tree binning, near lists, restructure to the redundant
 layout, redundant evaluation, gather evaluation (the update into caller order
 is fused into both evaluations).  Every sub-step is timed with HIP events on
 the stream the library launches on.
@@ -12,9 +12,16 @@ the stream the library launches on.
 value = pairs / (restructure + redundant evaluation), over the K timed steps.
 The line also carries the rate without the restructure, the gather rate, the
 sub-step times, the Locality metric, the roofline of the dominant kernel
-(the redundant evaluation) and the FP64 CPU oracle timed on a sample.
+(the redundant evaluation) and the FP64 CPU oracle timed on the workload.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+--workload selects one of the other configurations for the same measurement
+(their lines are reference measurements, not the headline):
+  gravity_uniform_4096      4096 uniform particles, uniform depth 3, FP64
+  helmholtz_grid_64         64^3 grid, 1 RHS, FP32 (VALU table kernel)
+  helmholtz_batched_128x64  128 grids 16^3..48^3, 64 RHS, FP32 matrix cores, autotuned
+  adjoint_gravity_256k      2^18 Plummer particles, forward + adjoint, FP64
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu]
 """
 from __future__ import annotations
 
@@ -29,16 +36,21 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-WORKLOAD = "gravity_plummer_2m"
+DEFAULT_WORKLOAD = "gravity_plummer_2m"
 METRIC = "near-field pair-interactions/s, redundant vs gather layout (incl. restructure)"
 
-# Roofline of the redundant evaluation (VALU-bound): minimal VALU issue slots
-# per FP32-mixed pair: 3 FP64 differences, 3 conversions to FP32, 3 FMA for
-# r^2 + eps^2, 1 quarter-rate rsqrt (4 slots), 3 multiplies (w^2, m w,
-# m w^3), 1 add (phi) and 3 FMA (a).
-SLOTS_PER_PAIR = 3 + 3 + 3 + 4 + 3 + 1 + 3          # = 20
 # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = VALU lane-slots per second
 VALU_PEAK_SLOTS = 256 * 4 * 16 * 2.4e9               # = 3.93e13
+# Minimal VALU issue slots per FP32-mixed gravity pair: 3 FP64 differences,
+# 3 conversions to FP32, 3 FMA for r^2 + eps^2, 1 quarter-rate rsqrt (4
+# slots), 3 multiplies (w^2, m w, m w^3), 1 add (phi) and 3 FMA (a).
+SLOTS_PER_PAIR_MIXED = 3 + 3 + 3 + 4 + 3 + 1 + 3    # = 20
+# FP64 gravity pair: 3 differences, 3 FMA for r^2 + eps^2, rsqrt (4 slots),
+# 3 multiplies, 1 add, 3 FMA.
+SLOTS_PER_PAIR_FP64 = 3 + 3 + 4 + 3 + 1 + 3         # = 17
+# FP32 vector FMA without packed issue: 256 CUs x 64 lanes x 2 flop x 2.4 GHz
+FP32_VALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12  # = 78.6
+FP32_MFMA_PEAK_TFLOPS = 157.3                        # dense FP32 matrix (published)
 
 
 def parse():
@@ -46,13 +58,39 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-leaves", type=int, default=0,
                     help="target leaves in the CPU oracle sample (0 = all)")
     return ap.parse_args()
 
 
-def cpu_baseline(x, y, z, m, w, n_leaves_sample, min_seconds=10.0, max_reps=8):
+def _timed_steps(step, K, W):
+    import torch
+    for _ in range(W):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs = [step() for _ in range(K)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = np.array([[a.elapsed_time(b) for a, b in zip(e[:-1], e[1:])] for e in evs])
+    return wall, ms.sum(0) / 1e3        # seconds summed over the K steps, per sub-step
+
+
+def _events(k):
+    import torch
+    return [torch.cuda.Event(enable_timing=True) for _ in range(k)]
+
+
+def _base(metric, value, unit, K, W, wall, dtype, config, higher=True):
+    return {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": K, "warmup": W,
+            "ms_per_step": wall / K * 1e3, "higher_is_better": higher, "scaling": "weak",
+            "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
+
+
+# --------------------------------------------------------------- CPU oracle
+def cpu_baseline_gravity(x, y, z, m, w, n_leaves_sample, min_seconds=10.0, max_reps=8):
     """The FP64 oracle, as it stands, on target leaves of the same workload
     (all of them by default): pairs evaluated per second of oracle evaluation
     time, the evaluation repeated until about `min_seconds` have passed
@@ -86,40 +124,54 @@ def cpu_baseline(x, y, z, m, w, n_leaves_sample, min_seconds=10.0, max_reps=8):
                       f"of {t_eval:.2f} s (oracle tree build {t_tree:.2f} s and near lists not counted)"}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the near-field path is built and measured for a single MI355X.", file=sys.stderr)
-        sys.exit(2)
+def cpu_baseline_helmholtz(sides, q, n_targets, unit):
+    """The FP64 oracle on `n_targets` targets drawn uniformly (seed 123)."""
+    import oracle
+    n = int(sum(int(s) ** 3 for s in sides))
+    rng = np.random.default_rng(123)
+    tg = np.sort(rng.choice(n, min(n_targets, n), replace=False)).astype(np.int64)
+    sides = np.asarray(sides)
+    off = oracle.grid_offsets(sides)
+    pairs = 0
+    for t in tg:
+        g = int(np.searchsorted(off, t, side="right") - 1)
+        ns = int(sides[g])
+        loc = t - off[g]
+        c = np.array([loc % ns, (loc // ns) % ns, loc // (ns * ns)]) // 4
+        nb = ns // 4
+        pairs += 64 * int(np.prod([min(ci + 1, nb - 1) - max(ci - 1, 0) + 1 for ci in c])) - 1
+    t0 = time.perf_counter()
+    oracle.helmholtz(sides, q, targets=tg)
+    dt = time.perf_counter() - t0
+    nrhs = 1 if q.ndim == 1 else q.shape[1]
+    return {"value": pairs * nrhs / dt, "unit": unit, "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"{len(tg)} of {n} targets drawn uniformly (seed 123), {pairs} pairs x {nrhs} "
+                      f"RHS, complex128, {dt:.2f} s"}
+
+
+# --------------------------------------------------------------- gravity
+def run_gravity(wname, args):
     import torch
     from paper_2511_21535_amd import api
     from paper_2511_21535_amd import workloads as W
-
-    if not torch.cuda.is_available():
-        print("bench.py needs a GPU", file=sys.stderr)
-        sys.exit(1)
     dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    w = W.WORKLOADS[WORKLOAD]
-    x, y, z, m = W.particles(WORKLOAD)
+    w = W.WORKLOADS[wname]
+    x, y, z, m = W.particles(wname)
     gx, gy, gz, gm = (torch.as_tensor(v, device=dev) for v in (x, y, z, m))
-    eps, prec = w["eps"], "fp32"
+    eps, prec = w["eps"], w["prec"]
+    mixed = prec == "fp32"
     n = x.shape[0]
+    bpe = 28.0 if mixed else 32.0
 
-    # sizes (one untimed pass): leaves, near entries, redundant entries, pairs
     tree = api.Tree.build_particles(gx, gy, gz, depth=w["depth"], leaf_cap=w["leaf_cap"])
     nbrs = tree.neighbors()
-    loc = api.locality(tree, nbrs, bytes_per_entry=28.0, cache_bytes=32.0 * 2 ** 20)
+    loc = api.locality(tree, nbrs, bytes_per_entry=bpe, cache_bytes=32.0 * 2 ** 20)
     S, pairs = int(loc["entries"]), int(loc["pairs"])
     red = api.restructure_gravity(tree, nbrs, gx, gy, gz, gm, prec=prec, S=S)
     outs = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(4)]
 
-    def ev():
-        return torch.cuda.Event(enable_timing=True)
-
     def step():
-        e = [ev() for _ in range(6)]
+        e = _events(6)
         e[0].record()
         t = api.Tree.build_particles(gx, gy, gz, depth=w["depth"], leaf_cap=w["leaf_cap"])
         e[1].record()
@@ -133,59 +185,176 @@ def main():
         e[5].record()
         return e
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    evs = [step() for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = np.array([[a.elapsed_time(b) for a, b in zip(e[:-1], e[1:])] for e in evs])  # [K, 5]
-    t_tree, t_nbr, t_res, t_red, t_gat = ms.sum(0) / 1e3   # seconds over K steps
     K = args.steps
+    wall, (t_tree, t_nbr, t_res, t_red, t_gat) = _timed_steps(step, K, args.warmup)
     value = pairs * K / (t_res + t_red)
-    rate_red = pairs * K / t_red
-    rate_gat = pairs * K / t_gat
-    avg_red = t_red / K
-    achieved = pairs * SLOTS_PER_PAIR / avg_red / 1e12
+    rate_red, rate_gat = pairs * K / t_red, pairs * K / t_gat
+    slots = SLOTS_PER_PAIR_MIXED if mixed else SLOTS_PER_PAIR_FP64
+    achieved = pairs * slots / (t_red / K) / 1e12
     peak = VALU_PEAK_SLOTS / 1e12
-    line = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "pair-interactions/s",
-        "n_gpus": 1,
-        "steps": K,
-        "warmup": args.warmup,
-        "ms_per_step": wall / K * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32+f64",
-        "data": "synthetic",
-        "config": {
-            "workload": "gravity_plummer_2m: 2^21 particles, 8 Plummer spheres (scale radii "
-                        "0.01-0.1), adaptive octree leaf cap 64, eps 1e-3, FP32-mixed",
-            "n": n, "leaves": tree.n_leaves, "max_level": tree.max_level,
-            "near_entries": nbrs.count, "redundant_entries": S, "pairs": pairs,
-            "parallelism": "single GPU",
-        },
-        "rates": {
-            "redundant_incl_restructure": value,
-            "redundant_excl_restructure": rate_red,
-            "gather": rate_gat,
-            "speedup_redundant_vs_gather_incl_restructure": value / rate_gat,
-            "speedup_redundant_vs_gather_kernel_only": rate_red / rate_gat,
-        },
+    desc = {"gravity_plummer_2m": "2^21 particles, 8 Plummer spheres (scale radii 0.01-0.1), adaptive "
+                                  "octree leaf cap 64, eps 1e-3, FP32-mixed",
+            "gravity_uniform_4096": "4096 particles uniform in the unit cube, uniform octree depth 3, "
+                                    "eps 1e-3, FP64",
+            "adjoint_gravity_256k": "2^18 Plummer particles, leaf cap 64, eps 1e-3, FP64"}[wname]
+    # algorithmic restructure traffic: segments written once, caller rows read
+    # once, sorted rows written and read once
+    res_bytes = S * bpe + n * (32 + 2 * bpe)
+    line = _base(METRIC, value, "pair-interactions/s", K, args.warmup, wall,
+                 "f32+f64" if mixed else "f64",
+                 {"workload": f"{wname}: {desc}", "n": n, "leaves": tree.n_leaves,
+                  "max_level": tree.max_level, "near_entries": nbrs.count, "redundant_entries": S,
+                  "pairs": pairs, "parallelism": "single GPU"})
+    line.update({
+        "rates": {"redundant_incl_restructure": value, "redundant_excl_restructure": rate_red,
+                  "gather": rate_gat,
+                  "speedup_redundant_vs_gather_incl_restructure": value / rate_gat,
+                  "speedup_redundant_vs_gather_kernel_only": rate_red / rate_gat},
         "ms": {"tree": t_tree / K * 1e3, "neighbors": t_nbr / K * 1e3, "restructure": t_res / K * 1e3,
                "eval_redundant": t_red / K * 1e3, "eval_gather": t_gat / K * 1e3},
         "locality": {k: loc[k] for k in ("d_mean", "d_ratio", "v_ratio", "locality")},
-        "roofline": {"bound": "alu", "kernel": "k_gravity<mixed, redundant>",
+        "roofline": {"bound": "alu", "kernel": f"k_gravity<{'mixed' if mixed else 'fp64'}, redundant>",
                      "achieved": achieved, "peak": peak, "unit": "T VALU lane-slots/s",
-                     "frac": achieved / peak, "traffic": None,
-                     "algorithmic_per_pair": SLOTS_PER_PAIR},
-    }
+                     "frac": achieved / peak, "traffic": None, "algorithmic_per_pair": slots},
+        "restructure_roofline": {"bound": "hbm", "achieved": res_bytes / (t_res / K) / 1e9,
+                                 "peak": 8000.0, "unit": "GB/s",
+                                 "frac": res_bytes / (t_res / K) / 8e12, "bytes": res_bytes},
+    })
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(x, y, z, m, w, args.cpu_leaves)
+        line["cpu_baseline"] = cpu_baseline_gravity(x, y, z, m, w, args.cpu_leaves)
+    return line
+
+
+# --------------------------------------------------------------- Helmholtz
+def run_helmholtz(wname, args):
+    import torch
+    from paper_2511_21535_amd import api, autotune
+    from paper_2511_21535_amd import workloads as W
+    dev = torch.device("cuda:0")
+    w = W.WORKLOADS[wname]
+    if wname == "helmholtz_grid_64":
+        sides = np.array([w["n_side"]])
+    else:
+        sides = W.batched_grid_sides(w["n_instances"], w["seed"])
+    grids = [api.Grid(int(s), *W.grid_geometry(int(s))) for s in sides]
+    nrhs = w["nrhs"]
+    q = W.grid_rhs(int((sides.astype(np.int64) ** 3).sum()), nrhs, seed=w["seed"])
+    gq = torch.as_tensor(q if nrhs > 1 else q[:, 0].copy(), device=dev)
+    tree = api.Tree.build_grids(grids, device=dev)
+    nbrs = tree.neighbors()
+    loc = api.locality(tree, nbrs, bytes_per_entry=8.0 * nrhs, cache_bytes=32.0 * 2 ** 20)
+    S, pairs = int(loc["entries"]), int(loc["pairs"])
+    red = api.restructure(tree, nbrs, [gq], prec="fp32", nrhs=nrhs, S=S)
+    mfma = nrhs % 32 == 0
+    tile = None
+    if mfma:
+        tile, _ = autotune.tune_helmholtz(tree, nbrs, q=gq, layout="gather")
+    out = torch.empty_like(gq)
+
+    def step():
+        e = _events(6)
+        e[0].record()
+        t = api.Tree.build_grids(grids, device=dev)
+        e[1].record()
+        nb = t.neighbors(cap=nbrs.count)
+        e[2].record()
+        r = api.restructure(t, nb, [gq], prec="fp32", nrhs=nrhs, out=red)
+        e[3].record()
+        api.helmholtz(t, nb, None, layout="redundant", prec="fp32", red=r, nrhs=nrhs, tile=tile, out=out)
+        e[4].record()
+        api.helmholtz(t, nb, gq, layout="gather", prec="fp32", tile=tile, out=out)
+        e[5].record()
+        return e
+
+    K = args.steps
+    wall, (t_tree, t_nbr, t_res, t_red, t_gat) = _timed_steps(step, K, args.warmup)
+    work = pairs * nrhs
+    value = work * K / (t_res + t_red)
+    flops = 8.0 * work
+    if mfma:
+        kern, t_dom = "k_helm_mfma<gather> (v_mfma_f32_32x32x2f32)", t_gat / K
+        roof = {"bound": "mfma", "peak": FP32_MFMA_PEAK_TFLOPS}
+    else:
+        kern, t_dom = "k_helmholtz<float2, redundant>", t_red / K
+        roof = {"bound": "alu", "peak": FP32_VALU_PEAK_TFLOPS}
+    ach = flops / t_dom / 1e12
+    roof.update({"kernel": kern, "achieved": ach, "unit": "TFLOP/s", "frac": ach / roof["peak"],
+                 "traffic": None, "algorithmic_per_pair": "8 flop per complex multiply-add"})
+    unit = "pair-interactions/s" if nrhs == 1 else "pair-RHS-interactions/s"
+    cfg = {"workload": wname, "grids": len(sides), "points": tree.n, "boxes": tree.n_leaves,
+           "nrhs": nrhs, "near_entries": nbrs.count, "redundant_entries": S, "pairs": pairs,
+           "tile": list(tile) if tile else None, "parallelism": "single GPU"}
+    line = _base(METRIC + ("" if nrhs == 1 else ", x RHS"), value, unit, K, args.warmup, wall,
+                 "f32 (complex64)", cfg)
+    line.update({
+        "rates": {"redundant_incl_restructure": value, "redundant_excl_restructure": work * K / t_red,
+                  "gather": work * K / t_gat,
+                  "speedup_redundant_vs_gather_incl_restructure": (work * K / (t_res + t_red)) / (work * K / t_gat),
+                  "speedup_redundant_vs_gather_kernel_only": t_gat / t_red},
+        "ms": {"tree": t_tree / K * 1e3, "neighbors": t_nbr / K * 1e3, "restructure": t_res / K * 1e3,
+               "eval_redundant": t_red / K * 1e3, "eval_gather": t_gat / K * 1e3},
+        "locality": {k: loc[k] for k in ("d_mean", "d_ratio", "v_ratio", "locality")},
+        "roofline": roof,
+    })
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline_helmholtz(sides, q if nrhs > 1 else q[:, 0],
+                                                      20000 if nrhs == 1 else 400, unit)
+    return line
+
+
+# --------------------------------------------------------------- adjoint
+def run_adjoint(wname, args):
+    import torch
+    from paper_2511_21535_amd import api
+    from paper_2511_21535_amd import workloads as W
+    dev = torch.device("cuda:0")
+    w = W.WORKLOADS[wname]
+    x, y, z, m = W.particles(wname)
+    n = len(x)
+    g = [torch.as_tensor(W.normal_like(n, seed=w["seed"] + 10 * k), device=dev) for k in range(1, 5)]
+    gx, gy, gz, gm = (torch.as_tensor(v, device=dev) for v in (x, y, z, m))
+    tree = api.Tree.build_particles(gx, gy, gz, depth=w["depth"], leaf_cap=w["leaf_cap"])
+    nbrs = tree.neighbors()
+    pairs = int(api.locality(tree, nbrs)["pairs"])
+
+    def step():
+        e = _events(3)
+        e[0].record()
+        api.gravity(tree, nbrs, w["eps"], x=gx, y=gy, z=gz, m=gm, prec="fp64")
+        e[1].record()
+        api.gravity_adjoint(tree, nbrs, w["eps"], gx, gy, gz, gm, *g)
+        e[2].record()
+        return e
+
+    K = args.steps
+    wall, (t_fwd, t_adj) = _timed_steps(step, K, args.warmup)
+    value = pairs * K / (t_fwd + t_adj)
+    line = _base("near-field pair-interactions/s, forward + adjoint (gather, FP64)", value,
+                 "pair-interactions/s", K, args.warmup, wall, "f64",
+                 {"workload": wname, "n": n, "leaves": tree.n_leaves, "pairs": pairs,
+                  "parallelism": "single GPU"})
+    line["ms"] = {"forward": t_fwd / K * 1e3, "adjoint": t_adj / K * 1e3}
+    return line
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the near-field path is built and measured for a single MI355X.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    wl = args.workload
+    if wl.startswith("helmholtz"):
+        line = run_helmholtz(wl, args)
+    elif wl.startswith("adjoint"):
+        line = run_adjoint(wl, args)
+    else:
+        line = run_gravity(wl, args)
     print(json.dumps(line), flush=True)
 
 
