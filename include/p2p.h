@@ -69,10 +69,11 @@ typedef enum { P2P_GATHER = 0, P2P_REDUNDANT = 1 } p2p_layout;
 
 /* P2P_FP64: every operation in double precision.
  * P2P_FP32_MIXED: pair arithmetic in single precision; double precision only
- * for the coordinate differences of each pair (rounded to single afterwards)
- * and for the per-target accumulation of single-precision partial sums
- * (at most 32 pair terms each).  Helmholtz multi-RHS blocks run on FP32
- * matrix cores. */
+ * for removing the large offset from coordinates (gravity: each position is
+ * taken relative to the centre of the target leaf in double and rounded to
+ * single once per (target leaf, source)) and for the per-target accumulation
+ * of single-precision partial sums (at most 32 pair terms each).  Helmholtz
+ * multi-RHS blocks run on FP32 matrix cores. */
 typedef enum { P2P_FP64 = 0, P2P_FP32_MIXED = 1 } p2p_precision;
 
 enum { P2P_TREE_PARTICLES = 0, P2P_TREE_GRIDS = 1 };
@@ -130,7 +131,11 @@ typedef struct {
  * rows start at red_start[A] + red_self[A].  S = red_start[L] entries.
  * Payload planes (device):
  *   gravity FP64:   planes = {x, y, z, m}, each double[S];
- *   gravity FP32_MIXED: planes = {x, y, z} double[S], planes[3] = m float[S];
+ *   gravity FP32_MIXED: planes[0] = float4[S] (x - c, y - c, z - c, m), where c
+ *     is the centre of the segment's target leaf, the difference taken in
+ *     double and rounded to float once (the large offset removed in double,
+ *     so pair differences are float differences of small numbers);
+ *     planes[1..3] unused;
  *   Helmholtz: planes[0] = q rows, [S][nrhs] complex (float2 for FP32_MIXED,
  *     double2 for FP64); planes[1..3] unused. */
 typedef struct {

@@ -76,6 +76,8 @@ def _declare(lib):
     lib.orc_red_offsets.argtypes = [I64, P, P, P, P, P]
     lib.orc_restructure_rows.restype = None
     lib.orc_restructure_rows.argtypes = [I64, P, P, P, P, P, P, I64, P]
+    lib.orc_restructure_gravity_rel.restype = None
+    lib.orc_restructure_gravity_rel.argtypes = [I64, P, P, P, P, P, P, P, P, P, P, P, P]
     lib.orc_gravity_leaves.restype = I64
     lib.orc_gravity_leaves.argtypes = [P, P, P, P, F64, P, P, P, I64, P, P, P, P, P, P, P]
     lib.orc_gravity_adjoint_leaves.restype = I64
@@ -242,6 +244,20 @@ def restructure_rows(tree: Tree, nbr_start, nbr_idx, red_start, src):
                                  _p(_c(nbr_start, np.int64)), _p(_c(nbr_idx, np.int32)),
                                  _p(_c(red_start, np.int64)), _p(src), row_bytes, _p(out))
     return out
+
+
+def restructure_gravity_rel(tree: Tree, nbr_start, nbr_idx, red_start, x, y, z, m):
+    """FP32-mixed redundant payload: float32 [S, 4] rows (x - c_A, y - c_A,
+    z - c_A, m) with c_A the centre of the segment's target leaf, the
+    difference taken in double and rounded to single."""
+    S = int(red_start[-1])
+    out = np.zeros((max(S, 1), 4), dtype=np.float32)
+    arrs = [_c(v, np.float64) for v in (x, y, z, m)]
+    _load().orc_restructure_gravity_rel(tree.n_leaves, _p(tree.leaf_start), _p(tree.perm),
+                                        _p(_c(nbr_start, np.int64)), _p(_c(nbr_idx, np.int32)),
+                                        _p(_c(red_start, np.int64)), _p(tree.anchor), _p(tree.size),
+                                        *[_p(a) for a in arrs], _p(out))
+    return out[:S]
 
 
 # ---------------------------------------------------------------------------

@@ -329,6 +329,37 @@ void orc_restructure_rows(int64_t L, const int32_t *leaf_start, const int32_t *p
     }
 }
 
+/* FP32-mixed gravity payload of the redundant layout: for target leaf A with
+ * centre c_A = (anchor_A + size_A / 2) 2^-20 (exact in double), every source
+ * row of its segment becomes (float)(x - c_A), (float)(y - c_A),
+ * (float)(z - c_A), (float)m: the offset removed in double, the result
+ * rounded to single.  out4: float[S][4]. */
+void orc_restructure_gravity_rel(int64_t L, const int32_t *leaf_start, const int32_t *perm,
+                                 const int64_t *nbr_start, const int32_t *nbr_idx,
+                                 const int64_t *red_start, const int32_t *anchor,
+                                 const int32_t *size, const double *x, const double *y,
+                                 const double *z, const double *m, float *out4)
+{
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t A = 0; A < L; ++A) {
+        double c[3];
+        for (int d = 0; d < 3; ++d)
+            c[d] = ((double)anchor[3 * A + d] + 0.5 * (double)size[A]) / (double)(1u << ORC_DEPTH_BITS);
+        int64_t w = red_start[A];
+        for (int64_t e = nbr_start[A]; e < nbr_start[A + 1]; ++e) {
+            int32_t B = nbr_idx[e];
+            for (int32_t s = leaf_start[B]; s < leaf_start[B + 1]; ++s) {
+                int64_t j = perm[s];
+                out4[4 * w + 0] = (float)(x[j] - c[0]);
+                out4[4 * w + 1] = (float)(y[j] - c[1]);
+                out4[4 * w + 2] = (float)(z[j] - c[2]);
+                out4[4 * w + 3] = (float)m[j];
+                ++w;
+            }
+        }
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Gravity                                                                  */
 /* ------------------------------------------------------------------------ */

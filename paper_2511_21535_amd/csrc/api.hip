@@ -263,6 +263,7 @@ extern "C" p2p_status p2p_restructure_redundant(const p2p_tree *tree, const p2p_
     int32_t *rself = ar.take<int32_t>(L);
     double *sx = nullptr, *sy = nullptr, *sz = nullptr;
     void *sm = nullptr, *sq = nullptr;
+    if (grav && L > 0 && tree->key_bits != 20) return fail(P2P_EINVAL, "gravity restructure needs a particle tree");
     if (grav) {
         sx = ar.take<double>(n);
         sy = ar.take<double>(n);
@@ -288,19 +289,20 @@ extern "C" p2p_status p2p_restructure_redundant(const p2p_tree *tree, const p2p_
         out->count = S;
         return fail(P2P_ECAPACITY, "out->cap " + std::to_string(out->cap) + " < " + std::to_string(S) + " entries");
     }
-    if (S > 0 && (grav ? (!out->planes[0] || !out->planes[1] || !out->planes[2] || !out->planes[3])
-                       : !out->planes[0]))
+    if (S > 0 && ((grav && !mixed) ? (!out->planes[0] || !out->planes[1] || !out->planes[2] || !out->planes[3])
+                                   : !out->planes[0]))
         return fail(P2P_EINVAL, "out->planes must not be NULL");
     P2P_HIP(hipMemcpyAsync(out->red_start, rstart, (L + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
     if (L > 0) P2P_HIP(hipMemcpyAsync(out->red_self, rself, L * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     if (grav) {
         P2P_TRY(launch_permute_gravity(static_cast<const double *>(src[0]), static_cast<const double *>(src[1]),
                                        static_cast<const double *>(src[2]), static_cast<const double *>(src[3]),
-                                       tree->perm, n, mixed, sx, sy, sz, sm, s));
-        P2P_TRY(launch_copy_segments_gravity(sx, sy, sz, sm, mixed, tree->leaf_start, nbrs->nbr_start,
-                                             nbrs->nbr_idx, rstart, L, static_cast<double *>(out->planes[0]),
-                                             static_cast<double *>(out->planes[1]),
-                                             static_cast<double *>(out->planes[2]), out->planes[3], s));
+                                       tree->perm, n, false, sx, sy, sz, sm, s));
+        P2P_TRY(launch_copy_segments_gravity(
+            sx, sy, sz, static_cast<const double *>(sm), tree->leaf_key, tree->leaf_level, tree->leaf_start,
+            nbrs->nbr_start, nbrs->nbr_idx, rstart, L, static_cast<double *>(out->planes[0]),
+            static_cast<double *>(out->planes[1]), static_cast<double *>(out->planes[2]),
+            static_cast<double *>(out->planes[3]), mixed ? static_cast<float4 *>(out->planes[0]) : nullptr, s));
     } else if (mixed) {
         P2P_TRY(launch_permute_rows<float2>(static_cast<const float2 *>(src[0]), tree->perm, n, nrhs,
                                             static_cast<float2 *>(sq), s));
@@ -355,8 +357,9 @@ extern "C" p2p_status p2p_eval_gravity(const p2p_tree *tree, const p2p_nbrs *nbr
         if (!red) return fail(P2P_EINVAL, "REDUNDANT layout needs red");
         if (red->kind != P2P_KIND_GRAVITY) return fail(P2P_EINVAL, "red was not built for gravity");
         if (red->prec != prec) return fail(P2P_EINVAL, "red was built with another precision");
-        if (!red->red_start || !red->red_self || (red->count > 0 && (!red->planes[0] || !red->planes[1] ||
-                                                                      !red->planes[2] || !red->planes[3])))
+        if (!red->red_start || !red->red_self ||
+            (red->count > 0 && (mixed ? !red->planes[0]
+                                      : (!red->planes[0] || !red->planes[1] || !red->planes[2] || !red->planes[3]))))
             return fail(P2P_EINVAL, "red arrays must not be NULL");
     } else if (n > 0 && (!x || !y || !z || !m)) {
         return fail(P2P_EINVAL, "GATHER layout needs x, y, z, m");
@@ -366,6 +369,8 @@ extern "C" p2p_status p2p_eval_gravity(const p2p_tree *tree, const p2p_nbrs *nbr
     a.L = tree->n_leaves;
     a.leaf_start = tree->leaf_start;
     a.perm = tree->perm;
+    a.leaf_key = tree->leaf_key;
+    a.leaf_level = tree->leaf_level;
     a.nbr_start = nbrs->nbr_start;
     a.nbr_idx = nbrs->nbr_idx;
     a.eps2 = eps * eps;
@@ -376,16 +381,20 @@ extern "C" p2p_status p2p_eval_gravity(const p2p_tree *tree, const p2p_nbrs *nbr
     if (redundant) {
         a.red_start = red->red_start;
         a.red_self = red->red_self;
-        a.sx = static_cast<const double *>(red->planes[0]);
-        a.sy = static_cast<const double *>(red->planes[1]);
-        a.sz = static_cast<const double *>(red->planes[2]);
-        a.sm = red->planes[3];
+        if (mixed) {
+            a.red4 = static_cast<const float4 *>(red->planes[0]);
+        } else {
+            a.sx = static_cast<const double *>(red->planes[0]);
+            a.sy = static_cast<const double *>(red->planes[1]);
+            a.sz = static_cast<const double *>(red->planes[2]);
+            a.sm = static_cast<const double *>(red->planes[3]);
+        }
     } else {
-        P2P_TRY(launch_permute_gravity(x, y, z, m, tree->perm, n, mixed, sx, sy, sz, sm, s));
+        P2P_TRY(launch_permute_gravity(x, y, z, m, tree->perm, n, false, sx, sy, sz, sm, s));
         a.sx = sx;
         a.sy = sy;
         a.sz = sz;
-        a.sm = sm;
+        a.sm = static_cast<const double *>(sm);
     }
     return launch_gravity(a, redundant, mixed, eps == 0.0, s);
 }

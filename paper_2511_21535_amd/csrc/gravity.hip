@@ -18,9 +18,15 @@
 // computed in the same arithmetic); the self term of a is exactly zero.
 // With eps == 0 pairs at zero distance contribute nothing instead.
 //
-// FP32_MIXED: the coordinate difference of every pair is taken in double and
-// rounded to float; the rest of the pair arithmetic is float; each lane sums
-// at most 32 pair terms in float before adding them to double accumulators.
+// FP32_MIXED: coordinates are taken relative to the centre of the target leaf
+// in double and rounded to float once per (target leaf, source) -- the
+// redundant layout stores them that way, the gather layout converts while
+// staging -- so the large offset is removed in double and every pair
+// difference is a float difference of small numbers; the rest of the pair
+// arithmetic is float; each lane sums at most 32 pair terms in float before
+// adding them to double accumulators.  Sources sit in LDS as float4 (x, y, z,
+// m) for FP32_MIXED and double4 for FP64, one address stream per pair, and
+// the strided source loop is unrolled by four.
 #include <type_traits>
 
 #include "p2p_internal.h"
@@ -116,11 +122,22 @@ __device__ void for_each_source_tile(int64_t A, const int64_t *__restrict__ red_
 
 __device__ inline float rsq_f32(float x) { return __builtin_amdgcn_rsqf(x); }
 
+// Centre of a particle leaf (exact in double: integers below 2^21 times 2^-20).
+__device__ inline void leaf_centre(uint64_t key, int level, double c[3]) {
+    const double half = 0.5 * static_cast<double>(1u << (20 - level));
+    c[0] = (static_cast<double>(p2pd::compact3(key)) + half) * 0x1p-20;
+    c[1] = (static_cast<double>(p2pd::compact3(key >> 1)) + half) * 0x1p-20;
+    c[2] = (static_cast<double>(p2pd::compact3(key >> 2)) + half) * 0x1p-20;
+}
+
+struct alignas(32) double4a {
+    double x, y, z, w;
+};
+
 template <bool MIXED, bool RED, bool EPS0>
 __global__ __launch_bounds__(kGBlock) void k_gravity(GravityArgs a) {
-    using TM = typename std::conditional<MIXED, float, double>::type;
-    __shared__ double s_x[kGTile], s_y[kGTile], s_z[kGTile];
-    __shared__ TM s_m[kGTile];
+    using Src = typename std::conditional<MIXED, float4, double4a>::type;
+    __shared__ Src s_src[kGTile];
     __shared__ double s_red[4][kGBlock];
     __shared__ int64_t s_pre[kGNbrChunk + 1];
     __shared__ int32_t s_first[kGNbrChunk];
@@ -129,67 +146,103 @@ __global__ __launch_bounds__(kGBlock) void k_gravity(GravityArgs a) {
     const int64_t A = blockIdx.x;
     const int32_t t0 = a.leaf_start[A];
     const int32_t ntar = a.leaf_start[A + 1] - t0;
-    const TM *__restrict__ sm = static_cast<const TM *>(a.sm);
-    const int64_t tbase = RED ? a.red_start[A] + a.red_self[A] : t0;
     const double eps2 = a.eps2;
     const float eps2f = static_cast<float>(a.eps2);
+    double c[3] = {0.0, 0.0, 0.0};
+    if (MIXED) leaf_centre(a.leaf_key[A], a.leaf_level[A], c);
 
     for (int tc0 = 0; tc0 < ntar; tc0 += kGBlock) {
         const int tc = min(kGBlock, ntar - tc0);
         const int G = kGBlock / tc;
         const int t = threadIdx.x % tc, g = threadIdx.x / tc;
         const bool active = g < G;
-        const int64_t trow = tbase + tc0 + t;
-        const double xt = a.sx[trow], yt = a.sy[trow], zt = a.sz[trow];
-        const TM mt = sm[trow];
+        // target position (relative to the leaf centre for FP32_MIXED) and mass
+        Src tv;
+        if constexpr (MIXED) {
+            if constexpr (RED) {
+                tv = a.red4[a.red_start[A] + a.red_self[A] + tc0 + t];
+            } else {
+                const int64_t r = t0 + tc0 + t;
+                tv = make_float4(static_cast<float>(a.sx[r] - c[0]), static_cast<float>(a.sy[r] - c[1]),
+                                 static_cast<float>(a.sz[r] - c[2]), static_cast<float>(a.sm[r]));
+            }
+        } else {
+            const int64_t r = RED ? a.red_start[A] + a.red_self[A] + tc0 + t : t0 + tc0 + t;
+            tv = {a.sx[r], a.sy[r], a.sz[r], a.sm[r]};
+        }
         double p = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
 
         auto stage = [&](int i, int64_t row) {
-            s_x[i] = a.sx[row];
-            s_y[i] = a.sy[row];
-            s_z[i] = a.sz[row];
-            s_m[i] = sm[row];
+            if constexpr (MIXED) {
+                if constexpr (RED)
+                    s_src[i] = a.red4[row];
+                else
+                    s_src[i] = make_float4(static_cast<float>(a.sx[row] - c[0]),
+                                           static_cast<float>(a.sy[row] - c[1]),
+                                           static_cast<float>(a.sz[row] - c[2]),
+                                           static_cast<float>(a.sm[row]));
+            } else {
+                s_src[i] = {a.sx[row], a.sy[row], a.sz[row], a.sm[row]};
+            }
         };
         auto body = [&](int nt) {
             if (!active) return;
             const int cnt = (nt > g) ? (nt - g + G - 1) / G : 0;
-            int s = g;
+            const Src *sp = s_src + g;
             if constexpr (MIXED) {
+                auto pair = [&](const float4 v, float &pf, float &xf, float &yf, float &zf) {
+                    const float dx = tv.x - v.x, dy = tv.y - v.y, dz = tv.z - v.z;
+                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2f)));
+                    float w = rsq_f32(r2);
+                    if constexpr (EPS0) w = (r2 > 0.f) ? w : 0.f;
+                    const float mw = v.w * w;
+                    const float mw3 = mw * (w * w);
+                    pf -= mw;
+                    xf = fmaf(-mw3, dx, xf);
+                    yf = fmaf(-mw3, dy, yf);
+                    zf = fmaf(-mw3, dz, zf);
+                };
                 for (int k0 = 0; k0 < cnt; k0 += kGFlush) {
                     const int kk = min(kGFlush, cnt - k0);
                     float pf = 0.f, xf = 0.f, yf = 0.f, zf = 0.f;
-                    for (int k = 0; k < kk; ++k, s += G) {
-                        const float dx = static_cast<float>(xt - s_x[s]);
-                        const float dy = static_cast<float>(yt - s_y[s]);
-                        const float dz = static_cast<float>(zt - s_z[s]);
-                        const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2f)));
-                        float w = rsq_f32(r2);
-                        if constexpr (EPS0) w = (r2 > 0.f) ? w : 0.f;
-                        const float mw = s_m[s] * w;
-                        const float mw3 = mw * (w * w);
-                        pf -= mw;
-                        xf = fmaf(-mw3, dx, xf);
-                        yf = fmaf(-mw3, dy, yf);
-                        zf = fmaf(-mw3, dz, zf);
+                    int j = 0;
+                    for (; j + 4 <= kk; j += 4) {
+                        const float4 v0 = sp[0], v1 = sp[G], v2 = sp[2 * G], v3 = sp[3 * G];
+                        pair(v0, pf, xf, yf, zf);
+                        pair(v1, pf, xf, yf, zf);
+                        pair(v2, pf, xf, yf, zf);
+                        pair(v3, pf, xf, yf, zf);
+                        sp += 4 * G;
                     }
+                    for (; j < kk; ++j, sp += G) pair(sp[0], pf, xf, yf, zf);
                     p += pf;
                     fx += xf;
                     fy += yf;
                     fz += zf;
                 }
             } else {
-                for (int k = 0; k < cnt; ++k, s += G) {
-                    const double dx = xt - s_x[s], dy = yt - s_y[s], dz = zt - s_z[s];
+                auto pair = [&](const double4a v) {
+                    const double dx = tv.x - v.x, dy = tv.y - v.y, dz = tv.z - v.z;
                     const double r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
                     double w = rsqrt(r2);
                     if constexpr (EPS0) w = (r2 > 0.0) ? w : 0.0;
-                    const double mw = s_m[s] * w;
+                    const double mw = v.w * w;
                     const double mw3 = mw * (w * w);
                     p -= mw;
                     fx = fma(-mw3, dx, fx);
                     fy = fma(-mw3, dy, fy);
                     fz = fma(-mw3, dz, fz);
+                };
+                int j = 0;
+                for (; j + 4 <= cnt; j += 4) {
+                    const double4a v0 = sp[0], v1 = sp[G], v2 = sp[2 * G], v3 = sp[3 * G];
+                    pair(v0);
+                    pair(v1);
+                    pair(v2);
+                    pair(v3);
+                    sp += 4 * G;
                 }
+                for (; j < cnt; ++j, sp += G) pair(sp[0]);
             }
         };
         for_each_source_tile<RED>(A, a.red_start, a.nbr_start, a.nbr_idx, a.leaf_start, s_pre,
@@ -202,22 +255,23 @@ __global__ __launch_bounds__(kGBlock) void k_gravity(GravityArgs a) {
         s_red[3][threadIdx.x] = active ? fz : 0.0;
         __syncthreads();
         if (threadIdx.x < tc) {
-            double sp = 0.0, sx_ = 0.0, sy_ = 0.0, sz_ = 0.0;
+            double sp_ = 0.0, sx_ = 0.0, sy_ = 0.0, sz_ = 0.0;
             for (int q = 0; q < G; ++q) {
                 const int l = q * tc + threadIdx.x;
-                sp += s_red[0][l];
+                sp_ += s_red[0][l];
                 sx_ += s_red[1][l];
                 sy_ += s_red[2][l];
                 sz_ += s_red[3][l];
             }
+            // add back the self pair (d = 0), computed in the same arithmetic
             if constexpr (!EPS0) {
                 if constexpr (MIXED)
-                    sp += static_cast<double>(mt * rsq_f32(eps2f));
+                    sp_ += static_cast<double>(tv.w * rsq_f32(eps2f));
                 else
-                    sp += mt * rsqrt(eps2);
+                    sp_ += tv.w * rsqrt(eps2);
             }
             const int64_t i = a.perm[t0 + tc0 + threadIdx.x];
-            a.phi[i] = sp;
+            a.phi[i] = sp_;
             a.ax[i] = sx_;
             a.ay[i] = sy_;
             a.az[i] = sz_;

@@ -97,11 +97,15 @@ p2p_status launch_permute_mass_f32(const double *m, const int32_t *perm, int64_t
 p2p_status launch_permute_gravity(const double *x, const double *y, const double *z,
                                   const double *m, const int32_t *perm, int64_t n, bool mass_f32,
                                   double *sx, double *sy, double *sz, void *sm, hipStream_t s);
+// Gravity payload: FP64 planes (d4 == nullptr) or, for FP32_MIXED, float4
+// (x - c_A, y - c_A, z - c_A, m) relative to the centre of target leaf A.
 p2p_status launch_copy_segments_gravity(const double *sx, const double *sy, const double *sz,
-                                        const void *sm, bool mass_f32, const int32_t *leaf_start,
+                                        const double *sm, const uint64_t *leaf_key,
+                                        const int8_t *leaf_level, const int32_t *leaf_start,
                                         const int64_t *nbr_start, const int32_t *nbr_idx,
                                         const int64_t *red_start, int64_t L, double *dx,
-                                        double *dy, double *dz, void *dm, hipStream_t s);
+                                        double *dy, double *dz, double *dm, float4 *d4,
+                                        hipStream_t s);
 template <class T>
 p2p_status launch_copy_segments(const T *sorted, int64_t row_len, const int32_t *leaf_start,
                                 const int64_t *nbr_start, const int32_t *nbr_idx,
@@ -112,14 +116,16 @@ struct GravityArgs {
     int64_t L;
     const int32_t *leaf_start;
     const int32_t *perm;
+    const uint64_t *leaf_key;
+    const int8_t *leaf_level;
     const int64_t *nbr_start;
     const int32_t *nbr_idx;
     const int64_t *red_start;
     const int32_t *red_self;
-    const double *sx, *sy, *sz;  // sources: sorted planes (gather) or redundant planes
-    const void *sm;              // double (FP64) or float (FP32_MIXED)
+    const double *sx, *sy, *sz, *sm;  // FP64 planes: sorted (gather) or redundant (FP64)
+    const float4 *red4;               // FP32_MIXED redundant payload (leaf-relative x, y, z, m)
     double eps2;
-    double *phi, *ax, *ay, *az;  // caller order
+    double *phi, *ax, *ay, *az;       // caller order
 };
 p2p_status launch_gravity(const GravityArgs &a, bool redundant, bool mixed, bool eps_zero,
                           hipStream_t s);

@@ -113,34 +113,76 @@ __device__ inline int find_nbr(const int64_t *s_pre, int nc, int64_t p) {
     return lo;
 }
 
-// Gravity payload: three double planes and a mass plane (double or float),
-// one row per thread.
-template <class TM>
-__global__ __launch_bounds__(kCopyBlock) void k_copy_segments_grav(
+// Gravity payload, one wavefront per target leaf (four per workgroup, no
+// workgroup barriers).  Lanes load a chunk of 64 near-list entries, form the
+// exclusive prefix of their occupancies with wave shuffles, and then copy the
+// segment row by row; a row finds its source leaf by binary search over the
+// prefix.  FP32_MIXED rows are written as float4 (x - c_A, y - c_A, z - c_A,
+// m) with c_A the centre of the target leaf, the difference taken in double.
+template <bool MIXED>
+__global__ __launch_bounds__(256) void k_copy_segments_grav(
     const double *__restrict__ sx, const double *__restrict__ sy, const double *__restrict__ sz,
-    const TM *__restrict__ sm, const int32_t *__restrict__ leaf_start,
+    const double *__restrict__ sm, const uint64_t *__restrict__ leaf_key,
+    const int8_t *__restrict__ leaf_level, const int32_t *__restrict__ leaf_start,
     const int64_t *__restrict__ nbr_start, const int32_t *__restrict__ nbr_idx,
-    const int64_t *__restrict__ red_start, double *__restrict__ dx, double *__restrict__ dy,
-    double *__restrict__ dz, TM *__restrict__ dm) {
-    __shared__ int64_t s_pre[kCopyNbrChunk + 1];
-    __shared__ int32_t s_first[kCopyNbrChunk];
-    __shared__ int64_t s_w[kCopyBlock / 64];
-    const int64_t A = blockIdx.x;
+    const int64_t *__restrict__ red_start, int64_t L, double *__restrict__ dx,
+    double *__restrict__ dy, double *__restrict__ dz, double *__restrict__ dm,
+    float4 *__restrict__ d4) {
+    __shared__ int32_t s_pre[4][65];
+    __shared__ int32_t s_first[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t A = static_cast<int64_t>(blockIdx.x) * 4 + w;
+    if (A >= L) return;
+    double c[3] = {0.0, 0.0, 0.0};
+    if (MIXED) {
+        const uint64_t k = leaf_key[A];
+        const double half = 0.5 * static_cast<double>(1u << (20 - leaf_level[A]));
+        c[0] = (static_cast<double>(p2pd::compact3(k)) + half) * 0x1p-20;
+        c[1] = (static_cast<double>(p2pd::compact3(k >> 1)) + half) * 0x1p-20;
+        c[2] = (static_cast<double>(p2pd::compact3(k >> 2)) + half) * 0x1p-20;
+    }
     const int64_t e0 = nbr_start[A], e1 = nbr_start[A + 1];
     int64_t out = red_start[A];
-    for (int64_t c0 = e0; c0 < e1; c0 += kCopyNbrChunk) {
-        const int nc = static_cast<int>(min<int64_t>(kCopyNbrChunk, e1 - c0));
-        const int64_t rows = load_nbr_chunk(leaf_start, nbr_idx, c0, nc, s_pre, s_first, s_w);
-        for (int64_t p = threadIdx.x; p < rows; p += kCopyBlock) {
-            const int b = find_nbr(s_pre, nc, p);
-            const int64_t src = s_first[b] + (p - s_pre[b]);
-            dx[out + p] = sx[src];
-            dy[out + p] = sy[src];
-            dz[out + p] = sz[src];
-            dm[out + p] = sm[src];
+    for (int64_t c0 = e0; c0 < e1; c0 += 64) {
+        const int nc = static_cast<int>(min<int64_t>(64, e1 - c0));
+        int32_t occ = 0, first = 0;
+        if (lane < nc) {
+            const int32_t B = nbr_idx[c0 + lane];
+            first = leaf_start[B];
+            occ = leaf_start[B + 1] - first;
+        }
+        int32_t inc = occ;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int32_t y = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += y;
+        }
+        s_pre[w][lane] = inc - occ;
+        s_first[w][lane] = first;
+        const int32_t rows = __shfl(inc, 63, 64);
+        if (lane == 0) s_pre[w][64] = rows;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        for (int32_t p = lane; p < rows; p += 64) {
+            int lo = 0, hi = nc - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_pre[w][mid] <= p) lo = mid; else hi = mid - 1;
+            }
+            const int64_t src = s_first[w][lo] + (p - s_pre[w][lo]);
+            if constexpr (MIXED) {
+                d4[out + p] = make_float4(static_cast<float>(sx[src] - c[0]), static_cast<float>(sy[src] - c[1]),
+                                          static_cast<float>(sz[src] - c[2]), static_cast<float>(sm[src]));
+            } else {
+                dx[out + p] = sx[src];
+                dy[out + p] = sy[src];
+                dz[out + p] = sz[src];
+                dm[out + p] = sm[src];
+            }
         }
         out += rows;
-        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -236,19 +278,20 @@ p2p_status launch_copy_segments(const T *sorted, int64_t row_len, const int32_t 
 }
 
 p2p_status launch_copy_segments_gravity(const double *sx, const double *sy, const double *sz,
-                                        const void *sm, bool mass_f32, const int32_t *leaf_start,
+                                        const double *sm, const uint64_t *leaf_key,
+                                        const int8_t *leaf_level, const int32_t *leaf_start,
                                         const int64_t *nbr_start, const int32_t *nbr_idx,
                                         const int64_t *red_start, int64_t L, double *dx,
-                                        double *dy, double *dz, void *dm, hipStream_t s) {
+                                        double *dy, double *dz, double *dm, float4 *d4,
+                                        hipStream_t s) {
     if (L <= 0) return P2P_OK;
-    if (mass_f32)
-        k_copy_segments_grav<float><<<static_cast<unsigned>(L), kCopyBlock, 0, s>>>(
-            sx, sy, sz, static_cast<const float *>(sm), leaf_start, nbr_start, nbr_idx, red_start,
-            dx, dy, dz, static_cast<float *>(dm));
+    const unsigned g = grid_for(L, 4);
+    if (d4)
+        k_copy_segments_grav<true><<<g, 256, 0, s>>>(sx, sy, sz, sm, leaf_key, leaf_level, leaf_start,
+                                                     nbr_start, nbr_idx, red_start, L, dx, dy, dz, dm, d4);
     else
-        k_copy_segments_grav<double><<<static_cast<unsigned>(L), kCopyBlock, 0, s>>>(
-            sx, sy, sz, static_cast<const double *>(sm), leaf_start, nbr_start, nbr_idx, red_start,
-            dx, dy, dz, static_cast<double *>(dm));
+        k_copy_segments_grav<false><<<g, 256, 0, s>>>(sx, sy, sz, sm, leaf_key, leaf_level, leaf_start,
+                                                      nbr_start, nbr_idx, red_start, L, dx, dy, dz, dm, d4);
     P2P_LAUNCH_CHECK();
     return P2P_OK;
 }

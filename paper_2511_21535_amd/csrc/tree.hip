@@ -116,7 +116,7 @@ __global__ void k_leaf_write(const uint64_t *__restrict__ sk, const int8_t *__re
                              uint64_t *__restrict__ leaf_key, int8_t *__restrict__ leaf_level,
                              int32_t *__restrict__ max_level) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    int lmax = -1;
+    (void)max_level;
     if (i < n) {
         if (i == 0) leaf_start[fscan[n]] = static_cast<int32_t>(n);
         if (flag[i]) {
@@ -127,12 +127,26 @@ __global__ void k_leaf_write(const uint64_t *__restrict__ sk, const int8_t *__re
             const uint64_t low_bits = (kind == P2P_TREE_PARTICLES) ? 3ull * (20 - l) : 6ull;
             const uint64_t mask = (low_bits >= 64) ? 0ull : ~((1ull << low_bits) - 1ull);
             leaf_key[L] = sk[i] & mask;
-            lmax = l;
         }
     }
-    // one atomic per wave instead of one per leaf
-    for (int o = 32; o > 0; o >>= 1) lmax = max(lmax, __shfl_xor(lmax, o, 64));
-    if ((threadIdx.x & 63) == 0 && lmax >= 0) atomicMax(max_level, lmax);
+}
+
+// Deepest leaf level: one workgroup strides over the levels (no atomics).
+__global__ __launch_bounds__(1024) void k_max_level(const int8_t *__restrict__ leaf_level,
+                                                    const int32_t *__restrict__ fscan, int64_t n,
+                                                    int32_t *__restrict__ out) {
+    __shared__ int s_m[16];
+    const int64_t L = fscan[n];
+    int m = 0;
+    for (int64_t i = threadIdx.x; i < L; i += blockDim.x) m = max(m, static_cast<int>(leaf_level[i]));
+    for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int r = 0;
+        for (int w = 0; w < static_cast<int>(blockDim.x >> 6); ++w) r = max(r, s_m[w]);
+        *out = r;
+    }
 }
 
 }  // namespace
@@ -178,6 +192,8 @@ p2p_status launch_leaf_write(const uint64_t *skeys, const int8_t *level, const i
     (void)key_bits;
     k_leaf_write<<<grid_for(n, 256), 256, 0, s>>>(skeys, level, flags, flag_scan, n, kind,
                                                   leaf_start, leaf_key, leaf_level, max_level);
+    P2P_LAUNCH_CHECK();
+    k_max_level<<<1, 1024, 0, s>>>(leaf_level, flag_scan, n, max_level);
     P2P_LAUNCH_CHECK();
     return P2P_OK;
 }

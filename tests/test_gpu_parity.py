@@ -77,11 +77,13 @@ def test_tree_neighbors_restructure_bit_exact(gen, n, seed, depth, cap):
         assert red.count == S
         np.testing.assert_array_equal(_n(red.red_start), rs)
         np.testing.assert_array_equal(_n(red.red_self), rself)
-        for k, v in enumerate((x, y, z)):
-            want = oracle.restructure_rows(ot, os_, oi, rs, v)
-            np.testing.assert_array_equal(_n(red.planes[k])[:S].view(np.uint64), want.view(np.uint64))
-        mm = m.astype(np.float32) if prec == "fp32" else m
-        np.testing.assert_array_equal(_n(red.planes[3])[:S], oracle.restructure_rows(ot, os_, oi, rs, mm))
+        if prec == "fp64":
+            for k, v in enumerate((x, y, z, m)):
+                want = oracle.restructure_rows(ot, os_, oi, rs, v)
+                np.testing.assert_array_equal(_n(red.planes[k])[:S].view(np.uint64), want.view(np.uint64))
+        else:
+            want = oracle.restructure_gravity_rel(ot, os_, oi, rs, x, y, z, m)
+            np.testing.assert_array_equal(_n(red.planes[0])[:S].view(np.uint32), want.view(np.uint32))
 
 
 @pytest.mark.parametrize("gen,n,seed,depth,cap", PARTICLE_CASES[:4])
@@ -108,16 +110,17 @@ def test_gravity_parity(gen, n, seed, depth, cap, eps):
             assert e_phi <= tol and e_a <= tol
 
 
-def test_gravity_gather_equals_redundant_bitwise_fp64():
-    # both layouts feed the same pair sequence per lane: identical results
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_gravity_gather_equals_redundant_bitwise(prec):
+    # both layouts feed the same values in the same order to every lane: identical results
     x, y, z, m = W.plummer_mixture(8000, 12)
     gx, gy, gz, gm = (_t(v) for v in (x, y, z, m))
     gt = api.Tree.build_particles(gx, gy, gz, depth=20, leaf_cap=64)
     gn = gt.neighbors()
-    red = api.restructure_gravity(gt, gn, gx, gy, gz, gm, prec="fp64")
-    a = api.gravity(gt, gn, 1e-3, x=gx, y=gy, z=gz, m=gm)
-    b = api.gravity(gt, gn, 1e-3, layout="redundant", red=red)
-    c = api.gravity(gt, gn, 1e-3, layout="redundant", red=red)
+    red = api.restructure_gravity(gt, gn, gx, gy, gz, gm, prec=prec)
+    a = api.gravity(gt, gn, 1e-3, x=gx, y=gy, z=gz, m=gm, prec=prec)
+    b = api.gravity(gt, gn, 1e-3, layout="redundant", red=red, prec=prec)
+    c = api.gravity(gt, gn, 1e-3, layout="redundant", red=red, prec=prec)
     for u, v, w in zip(a, b, c):
         np.testing.assert_array_equal(_n(u), _n(v))
         np.testing.assert_array_equal(_n(v), _n(w))      # deterministic
@@ -156,11 +159,14 @@ def test_full_size_plummer_2m_sampled():
         np.testing.assert_array_equal(gi[gs[A]:gs[A + 1]], si[ss[k]:ss[k + 1]])
     red = api.restructure_gravity(gt, gn, gx, gy, gz, gm, prec="fp32")
     rs = _n(red.red_start)
-    px = _n(red.planes[0])
+    p4 = _n(red.planes[0])
     occ = np.diff(ot.leaf_start)
     for k, A in enumerate(sel[:16]):
-        want = np.concatenate([x[ot.perm[ot.leaf_start[B]:ot.leaf_start[B + 1]]] for B in si[ss[k]:ss[k + 1]]])
-        np.testing.assert_array_equal(px[rs[A]:rs[A + 1]], want)
+        c = (ot.anchor[A] + 0.5 * ot.size[A]) * 2.0 ** -20
+        src = np.concatenate([ot.perm[ot.leaf_start[B]:ot.leaf_start[B + 1]] for B in si[ss[k]:ss[k + 1]]])
+        want = np.stack([(x[src] - c[0]).astype(np.float32), (y[src] - c[1]).astype(np.float32),
+                         (z[src] - c[2]).astype(np.float32), m[src].astype(np.float32)], 1)
+        np.testing.assert_array_equal(p4[rs[A]:rs[A + 1]], want)
     idx, rp, rax, ray, raz = oracle.gravity_leaves(x, y, z, m, w["eps"], ot, sel, ss, si)
     for layout in ("gather", "redundant"):
         o = [_n(v)[idx] for v in api.gravity(gt, gn, w["eps"], x=gx, y=gy, z=gz, m=gm,

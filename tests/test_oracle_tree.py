@@ -217,3 +217,23 @@ def test_locality_hand_values():
     assert loc["D_mean"] == 1.0 and loc["V_ratio"] == 0.125 and loc["locality"] == 0.125
     loc = oracle.locality(s1, i1, len(x), S, 32.0, cache_bytes=1.0)
     assert loc["locality"] == 0.125 / 1.0 * 1.0 / 1.0 or loc["locality"] == 0.125
+
+
+def test_relative_payload_from_rows_and_centres():
+    # the FP32-mixed payload is the bit-copied row minus the target leaf's centre,
+    # rounded to single; the centre is the midpoint of the leaf's cube
+    x, y, z, m = W.plummer_mixture(3000, 16)
+    t = oracle.build_tree_particles(x, y, z, depth=20, leaf_cap=32)
+    start, idx = oracle.neighbors(t)
+    rs, _, S = oracle.red_offsets(t, start, idx)
+    p4 = oracle.restructure_gravity_rel(t, start, idx, rs, x, y, z, m)
+    lo, hi = _cube_bounds(t)
+    centre = 0.5 * (lo + hi)
+    owner = np.repeat(np.arange(t.n_leaves), np.diff(rs))
+    for d, v in enumerate((x, y, z)):
+        rows = oracle.restructure_rows(t, start, idx, rs, v)
+        np.testing.assert_array_equal(p4[:, d], (rows - centre[owner, d]).astype(np.float32))
+        # relative coordinates stay within the near field of the owner leaf
+        span = np.max(t.size) * 2.0 ** -20
+        assert np.all(np.abs(p4[:, d]) <= 1.5 * span + 1e-12)
+    np.testing.assert_array_equal(p4[:, 3], oracle.restructure_rows(t, start, idx, rs, m).astype(np.float32))
