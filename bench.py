@@ -64,7 +64,21 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-leaves", type=int, default=0,
                     help="target leaves in the CPU oracle sample (0 = all)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 1 GiB (3 times), the reference for "
+                         "scaling the FETCH_SIZE / WRITE_SIZE counters")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """Plain device-to-device copy of 2^30 bytes, three times, for counter scaling."""
+    import torch
+    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": a.numel() * 4, "reps": 3}), flush=True)
 
 
 def _timed_steps(step, K, W):
@@ -350,6 +364,9 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     wl = args.workload
     if wl.startswith("helmholtz"):
         line = run_helmholtz(wl, args)

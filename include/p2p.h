@@ -130,7 +130,7 @@ typedef struct {
  * for B in nbr(A) in order, the rows of B's sorted slots in order; A's own
  * rows start at red_start[A] + red_self[A].  S = red_start[L] entries.
  * Payload planes (device):
- *   gravity FP64:   planes = {x, y, z, m}, each double[S];
+ *   gravity FP64: planes[0] = double[S][4] rows (x, y, z, m), 32-byte rows;
  *   gravity FP32_MIXED: planes[0] = float4[S] (x - c, y - c, z - c, m), where c
  *     is the centre of the segment's target leaf, the difference taken in
  *     double and rounded to float once (the large offset removed in double,

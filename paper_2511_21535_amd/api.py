@@ -212,7 +212,7 @@ def _alloc_red(tree, kind, prec, S, nrhs, dev):
     if kind == L.P2P_KIND_GRAVITY and prec == L.P2P_FP32_MIXED:
         planes = [torch.empty((max(S, 1), 4), dtype=torch.float32, device=dev), None, None, None]
     elif kind == L.P2P_KIND_GRAVITY:
-        planes = [torch.empty(max(S, 1), dtype=torch.float64, device=dev) for _ in range(4)]
+        planes = [torch.empty((max(S, 1), 4), dtype=torch.float64, device=dev), None, None, None]
     else:
         cd = torch.complex64 if prec == L.P2P_FP32_MIXED else torch.complex128
         planes = [torch.empty((max(S, 1), nrhs), dtype=cd, device=dev), None, None, None]

@@ -211,17 +211,21 @@ extern "C" p2p_status p2p_build_neighbors(const p2p_tree *tree, p2p_nbrs *nbrs, 
     if (!nbrs) return fail(P2P_EINVAL, "nbrs is NULL");
     if (nbrs->cap < 0) return fail(P2P_EINVAL, "nbrs->cap < 0");
     const int64_t L = tree->n_leaves;
+    // total key bits: 3 per axis, plus the instance index for grids
+    const int total_bits = 3 * tree->key_bits + (tree->kind == P2P_TREE_GRIDS ? bits_for(tree->n_grids) : 0);
     Arena ar(ws);
     int32_t *counts = ar.take<int32_t>(L);
     int64_t *start = ar.take<int64_t>(L + 1);
     int64_t *scan_tmp = ar.take<int64_t>(scan_ws_elems(L));
+    int32_t *dir = ar.take<int32_t>((size_t(1) << neighbor_dir_bits(total_bits)) + 1);
     p2p_status st;
     if (ws_query(ws, ws_bytes, ar, &st)) return st;
     if (!nbrs->nbr_start) return fail(P2P_EINVAL, "nbrs->nbr_start must not be NULL");
     hipStream_t s = as_stream(stream);
     const int inst_shift = 3 * tree->key_bits;
-    P2P_TRY(launch_neighbors(tree->leaf_key, tree->leaf_level, L, tree->key_bits, inst_shift, nullptr,
-                             counts, nullptr, s));
+    P2P_TRY(launch_key_directory(tree->leaf_key, L, total_bits, dir, s));
+    P2P_TRY(launch_neighbors(tree->leaf_key, tree->leaf_level, L, tree->key_bits, inst_shift, dir,
+                             total_bits, nullptr, counts, nullptr, s));
     P2P_TRY((exclusive_scan<int32_t, int64_t>(counts, start, L, scan_tmp, s)));
     int64_t E = 0;
     P2P_HIP(hipMemcpyAsync(&E, &start[L], sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -232,8 +236,8 @@ extern "C" p2p_status p2p_build_neighbors(const p2p_tree *tree, p2p_nbrs *nbrs, 
     }
     if (E > 0 && !nbrs->nbr_idx) return fail(P2P_EINVAL, "nbrs->nbr_idx must not be NULL");
     P2P_HIP(hipMemcpyAsync(nbrs->nbr_start, start, (L + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
-    P2P_TRY(launch_neighbors(tree->leaf_key, tree->leaf_level, L, tree->key_bits, inst_shift,
-                             nbrs->nbr_start, nullptr, nbrs->nbr_idx, s));
+    P2P_TRY(launch_neighbors(tree->leaf_key, tree->leaf_level, L, tree->key_bits, inst_shift, dir,
+                             total_bits, nbrs->nbr_start, nullptr, nbrs->nbr_idx, s));
     P2P_HIP(hipStreamSynchronize(s));
     nbrs->count = E;
     return P2P_OK;
@@ -261,17 +265,12 @@ extern "C" p2p_status p2p_restructure_redundant(const p2p_tree *tree, const p2p_
     int64_t *rstart = ar.take<int64_t>(L + 1);
     int64_t *scan_tmp = ar.take<int64_t>(scan_ws_elems(L));
     int32_t *rself = ar.take<int32_t>(L);
-    double *sx = nullptr, *sy = nullptr, *sz = nullptr;
-    void *sm = nullptr, *sq = nullptr;
-    if (grav && L > 0 && tree->key_bits != 20) return fail(P2P_EINVAL, "gravity restructure needs a particle tree");
-    if (grav) {
-        sx = ar.take<double>(n);
-        sy = ar.take<double>(n);
-        sz = ar.take<double>(n);
-        sm = ar.take<double>(n);
-    } else {
+    Row4d *s4 = nullptr;
+    void *sq = nullptr;
+    if (grav)
+        s4 = ar.take<Row4d>(n);
+    else
         sq = ar.take<char>(static_cast<size_t>(n) * nrhs * csize);
-    }
     p2p_status st;
     if (ws_query(ws, ws_bytes, ar, &st)) return st;
     if (!src) return fail(P2P_EINVAL, "src is NULL");
@@ -289,20 +288,18 @@ extern "C" p2p_status p2p_restructure_redundant(const p2p_tree *tree, const p2p_
         out->count = S;
         return fail(P2P_ECAPACITY, "out->cap " + std::to_string(out->cap) + " < " + std::to_string(S) + " entries");
     }
-    if (S > 0 && ((grav && !mixed) ? (!out->planes[0] || !out->planes[1] || !out->planes[2] || !out->planes[3])
-                                   : !out->planes[0]))
+    if (S > 0 && !out->planes[0])
         return fail(P2P_EINVAL, "out->planes must not be NULL");
     P2P_HIP(hipMemcpyAsync(out->red_start, rstart, (L + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
     if (L > 0) P2P_HIP(hipMemcpyAsync(out->red_self, rself, L * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     if (grav) {
-        P2P_TRY(launch_permute_gravity(static_cast<const double *>(src[0]), static_cast<const double *>(src[1]),
-                                       static_cast<const double *>(src[2]), static_cast<const double *>(src[3]),
-                                       tree->perm, n, false, sx, sy, sz, sm, s));
-        P2P_TRY(launch_copy_segments_gravity(
-            sx, sy, sz, static_cast<const double *>(sm), tree->leaf_key, tree->leaf_level, tree->leaf_start,
-            nbrs->nbr_start, nbrs->nbr_idx, rstart, L, static_cast<double *>(out->planes[0]),
-            static_cast<double *>(out->planes[1]), static_cast<double *>(out->planes[2]),
-            static_cast<double *>(out->planes[3]), mixed ? static_cast<float4 *>(out->planes[0]) : nullptr, s));
+        P2P_TRY(launch_permute4(static_cast<const double *>(src[0]), static_cast<const double *>(src[1]),
+                                static_cast<const double *>(src[2]), static_cast<const double *>(src[3]),
+                                tree->perm, n, s4, s));
+        P2P_TRY(launch_copy_segments_gravity(s4, tree->leaf_key, tree->leaf_level, tree->leaf_start,
+                                             nbrs->nbr_start, nbrs->nbr_idx, rstart, L,
+                                             mixed ? nullptr : static_cast<Row4d *>(out->planes[0]),
+                                             mixed ? static_cast<float4 *>(out->planes[0]) : nullptr, s));
     } else if (mixed) {
         P2P_TRY(launch_permute_rows<float2>(static_cast<const float2 *>(src[0]), tree->perm, n, nrhs,
                                             static_cast<float2 *>(sq), s));
@@ -342,14 +339,7 @@ extern "C" p2p_status p2p_eval_gravity(const p2p_tree *tree, const p2p_nbrs *nbr
     const bool mixed = prec == P2P_FP32_MIXED, redundant = layout == P2P_REDUNDANT;
     const int64_t n = tree->n;
     Arena ar(ws);
-    double *sx = nullptr, *sy = nullptr, *sz = nullptr;
-    void *sm = nullptr;
-    if (!redundant) {
-        sx = ar.take<double>(n);
-        sy = ar.take<double>(n);
-        sz = ar.take<double>(n);
-        sm = ar.take<double>(n);
-    }
+    Row4d *s4 = redundant ? nullptr : ar.take<Row4d>(n);
     p2p_status st;
     if (ws_query(ws, ws_bytes, ar, &st)) return st;
     if (n > 0 && (!phi || !ax || !ay || !az)) return fail(P2P_EINVAL, "outputs must not be NULL");
@@ -357,9 +347,7 @@ extern "C" p2p_status p2p_eval_gravity(const p2p_tree *tree, const p2p_nbrs *nbr
         if (!red) return fail(P2P_EINVAL, "REDUNDANT layout needs red");
         if (red->kind != P2P_KIND_GRAVITY) return fail(P2P_EINVAL, "red was not built for gravity");
         if (red->prec != prec) return fail(P2P_EINVAL, "red was built with another precision");
-        if (!red->red_start || !red->red_self ||
-            (red->count > 0 && (mixed ? !red->planes[0]
-                                      : (!red->planes[0] || !red->planes[1] || !red->planes[2] || !red->planes[3]))))
+        if (!red->red_start || !red->red_self || (red->count > 0 && !red->planes[0]))
             return fail(P2P_EINVAL, "red arrays must not be NULL");
     } else if (n > 0 && (!x || !y || !z || !m)) {
         return fail(P2P_EINVAL, "GATHER layout needs x, y, z, m");
@@ -381,20 +369,13 @@ extern "C" p2p_status p2p_eval_gravity(const p2p_tree *tree, const p2p_nbrs *nbr
     if (redundant) {
         a.red_start = red->red_start;
         a.red_self = red->red_self;
-        if (mixed) {
+        if (mixed)
             a.red4 = static_cast<const float4 *>(red->planes[0]);
-        } else {
-            a.sx = static_cast<const double *>(red->planes[0]);
-            a.sy = static_cast<const double *>(red->planes[1]);
-            a.sz = static_cast<const double *>(red->planes[2]);
-            a.sm = static_cast<const double *>(red->planes[3]);
-        }
+        else
+            a.s4 = static_cast<const Row4d *>(red->planes[0]);
     } else {
-        P2P_TRY(launch_permute_gravity(x, y, z, m, tree->perm, n, false, sx, sy, sz, sm, s));
-        a.sx = sx;
-        a.sy = sy;
-        a.sz = sz;
-        a.sm = static_cast<const double *>(sm);
+        P2P_TRY(launch_permute4(x, y, z, m, tree->perm, n, s4, s));
+        a.s4 = s4;
     }
     return launch_gravity(a, redundant, mixed, eps == 0.0, s);
 }
@@ -588,32 +569,25 @@ extern "C" p2p_status p2p_adjoint(int32_t kind, const p2p_tree *tree, const p2p_
     if (!(eps > 0.0) || !std::isfinite(eps)) return fail(P2P_EINVAL, "gravity adjoint needs eps > 0");
     const int64_t n = tree->n;
     Arena ar(ws);
-    double *pl[8];
-    for (int i = 0; i < 8; ++i) pl[i] = ar.take<double>(n);
+    Row4d *s4 = ar.take<Row4d>(n);
+    Row4d *g4 = ar.take<Row4d>(n);
     p2p_status st;
     if (ws_query(ws, ws_bytes, ar, &st)) return st;
     if (!fwd_in || !grad_out || !grad_in) return fail(P2P_EINVAL, "fwd_in, grad_out, grad_in must not be NULL");
     for (int i = 0; i < 4; ++i)
         if (n > 0 && (!fwd_in[i] || !grad_out[i] || !grad_in[i])) return fail(P2P_EINVAL, "NULL gravity array");
     auto D = [](const void *p) { return static_cast<const double *>(p); };
-    P2P_TRY(launch_permute_gravity(D(fwd_in[0]), D(fwd_in[1]), D(fwd_in[2]), D(fwd_in[3]), tree->perm, n,
-                                   false, pl[0], pl[1], pl[2], pl[3], s));
-    P2P_TRY(launch_permute_gravity(D(grad_out[1]), D(grad_out[2]), D(grad_out[3]), D(grad_out[0]),
-                                   tree->perm, n, false, pl[5], pl[6], pl[7], pl[4], s));
+    P2P_TRY(launch_permute4(D(fwd_in[0]), D(fwd_in[1]), D(fwd_in[2]), D(fwd_in[3]), tree->perm, n, s4, s));
+    P2P_TRY(launch_permute4(D(grad_out[0]), D(grad_out[1]), D(grad_out[2]), D(grad_out[3]), tree->perm, n,
+                            g4, s));
     GravityAdjointArgs a{};
     a.L = tree->n_leaves;
     a.leaf_start = tree->leaf_start;
     a.perm = tree->perm;
     a.nbr_start = nbrs->nbr_start;
     a.nbr_idx = nbrs->nbr_idx;
-    a.sx = pl[0];
-    a.sy = pl[1];
-    a.sz = pl[2];
-    a.sm = pl[3];
-    a.sgp = pl[4];
-    a.sgx = pl[5];
-    a.sgy = pl[6];
-    a.sgz = pl[7];
+    a.s4 = s4;
+    a.g4 = g4;
     a.eps2 = eps * eps;
     a.gx = static_cast<double *>(grad_in[0]);
     a.gy = static_cast<double *>(grad_in[1]);

@@ -130,20 +130,17 @@ __device__ inline void leaf_centre(uint64_t key, int level, double c[3]) {
     c[2] = (static_cast<double>(p2pd::compact3(key >> 2)) + half) * 0x1p-20;
 }
 
-struct alignas(32) double4a {
-    double x, y, z, w;
-};
-
 template <bool MIXED, bool RED, bool EPS0>
-__global__ __launch_bounds__(kGBlock) void k_gravity(GravityArgs a) {
-    using Src = typename std::conditional<MIXED, float4, double4a>::type;
+__device__ __forceinline__ void gravity_body(const GravityArgs &a) {
+    using Src = typename std::conditional<MIXED, float4, Row4d>::type;
     __shared__ Src s_src[kGTile];
     __shared__ double s_red[4][kGBlock];
     __shared__ int64_t s_pre[kGNbrChunk + 1];
     __shared__ int32_t s_first[kGNbrChunk];
     __shared__ int64_t s_w[kGBlock / 64];
 
-    const int64_t A = blockIdx.x;
+    // gather: neighbouring leaves on one XCD share their sources in its L2
+    const int64_t A = RED ? static_cast<int64_t>(blockIdx.x) : p2pd::xcd_contiguous(blockIdx.x, gridDim.x);
     const int32_t t0 = a.leaf_start[A];
     const int32_t ntar = a.leaf_start[A + 1] - t0;
     const double eps2 = a.eps2;
@@ -162,27 +159,26 @@ __global__ __launch_bounds__(kGBlock) void k_gravity(GravityArgs a) {
             if constexpr (RED) {
                 tv = a.red4[a.red_start[A] + a.red_self[A] + tc0 + t];
             } else {
-                const int64_t r = t0 + tc0 + t;
-                tv = make_float4(static_cast<float>(a.sx[r] - c[0]), static_cast<float>(a.sy[r] - c[1]),
-                                 static_cast<float>(a.sz[r] - c[2]), static_cast<float>(a.sm[r]));
+                const Row4d v = a.s4[t0 + tc0 + t];
+                tv = make_float4(static_cast<float>(v.x - c[0]), static_cast<float>(v.y - c[1]),
+                                 static_cast<float>(v.z - c[2]), static_cast<float>(v.w));
             }
         } else {
-            const int64_t r = RED ? a.red_start[A] + a.red_self[A] + tc0 + t : t0 + tc0 + t;
-            tv = {a.sx[r], a.sy[r], a.sz[r], a.sm[r]};
+            tv = a.s4[RED ? a.red_start[A] + a.red_self[A] + tc0 + t : t0 + tc0 + t];
         }
         double p = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
 
         auto stage = [&](int i, int64_t row) {
             if constexpr (MIXED) {
-                if constexpr (RED)
+                if constexpr (RED) {
                     s_src[i] = a.red4[row];
-                else
-                    s_src[i] = make_float4(static_cast<float>(a.sx[row] - c[0]),
-                                           static_cast<float>(a.sy[row] - c[1]),
-                                           static_cast<float>(a.sz[row] - c[2]),
-                                           static_cast<float>(a.sm[row]));
+                } else {
+                    const Row4d v = a.s4[row];
+                    s_src[i] = make_float4(static_cast<float>(v.x - c[0]), static_cast<float>(v.y - c[1]),
+                                           static_cast<float>(v.z - c[2]), static_cast<float>(v.w));
+                }
             } else {
-                s_src[i] = {a.sx[row], a.sy[row], a.sz[row], a.sm[row]};
+                s_src[i] = a.s4[row];
             }
         };
         auto body = [&](int nt) {
@@ -221,7 +217,7 @@ __global__ __launch_bounds__(kGBlock) void k_gravity(GravityArgs a) {
                     fz += zf;
                 }
             } else {
-                auto pair = [&](const double4a v) {
+                auto pair = [&](const Row4d v) {
                     const double dx = tv.x - v.x, dy = tv.y - v.y, dz = tv.z - v.z;
                     const double r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
                     double w = rsqrt(r2);
@@ -235,7 +231,7 @@ __global__ __launch_bounds__(kGBlock) void k_gravity(GravityArgs a) {
                 };
                 int j = 0;
                 for (; j + 4 <= cnt; j += 4) {
-                    const double4a v0 = sp[0], v1 = sp[G], v2 = sp[2 * G], v3 = sp[3 * G];
+                    const Row4d v0 = sp[0], v1 = sp[G], v2 = sp[2 * G], v3 = sp[3 * G];
                     pair(v0);
                     pair(v1);
                     pair(v2);
@@ -279,6 +275,19 @@ __global__ __launch_bounds__(kGBlock) void k_gravity(GravityArgs a) {
     }
 }
 
+// The FP32-mixed redundant kernel fits in 64 VGPRs without spills, so it asks
+// for 8 waves per SIMD (more workgroups in flight hide the tile staging); the
+// other variants keep the compiler's register budget.
+template <bool MIXED, bool RED, bool EPS0>
+__global__ __launch_bounds__(kGBlock) void k_gravity(GravityArgs a) {
+    gravity_body<MIXED, RED, EPS0>(a);
+}
+template <bool EPS0>
+__global__ __launch_bounds__(kGBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_gravity_mixed_red(
+    GravityArgs a) {
+    gravity_body<true, true, EPS0>(a);
+}
+
 // Adjoint of the gravity sums, FP64, gather layout.  For target j and each
 // near source k (d = x_j - x_k, w = (|d|^2+eps^2)^{-1/2}):
 //   g_x_j += [ m_k (gp_j w^3 + 3 w^5 ga_j.d) + m_j (gp_k w^3 - 3 w^5 ga_k.d) ] d
@@ -288,12 +297,12 @@ __global__ __launch_bounds__(kGBlock) void k_gravity(GravityArgs a) {
 // (j, k) and the pair (k, j)).  The self pair adds zero to g_x and
 // -gp_j/eps to g_m, which is added back.
 __global__ __launch_bounds__(kGBlock) void k_gravity_adjoint(GravityAdjointArgs a) {
-    __shared__ double s_x[kGTile], s_y[kGTile], s_z[kGTile], s_m[kGTile];
-    __shared__ double s_gp[kGTile], s_gx[kGTile], s_gy[kGTile], s_gz[kGTile];
+    __shared__ Row4d s_p[kGTile];    // sources (x, y, z, m)
+    __shared__ Row4d s_g[kGTile];    // their upstream gradients (g_phi, g_ax, g_ay, g_az)
     __shared__ int64_t s_pre[kGNbrChunk + 1];
     __shared__ int32_t s_first[kGNbrChunk];
     __shared__ int64_t s_w[kGBlock / 64];
-    double *s_red = s_gp;   // reused after the last tile (4 x 256 doubles fit in 4 x 512)
+    double *s_red = reinterpret_cast<double *>(s_g);   // reused after the last tile
 
     const int64_t A = blockIdx.x;
     const int32_t t0 = a.leaf_start[A];
@@ -305,34 +314,26 @@ __global__ __launch_bounds__(kGBlock) void k_gravity_adjoint(GravityAdjointArgs 
         const int t = threadIdx.x % tc, g = threadIdx.x / tc;
         const bool active = g < G;
         const int64_t tr = t0 + tc0 + t;
-        const double xj = a.sx[tr], yj = a.sy[tr], zj = a.sz[tr], mj = a.sm[tr];
-        const double gpj = a.sgp[tr], gxj = a.sgx[tr], gyj = a.sgy[tr], gzj = a.sgz[tr];
+        const Row4d pj = a.s4[tr], gj = a.g4[tr];
         double om = 0.0, ox = 0.0, oy = 0.0, oz = 0.0;
         auto stage = [&](int i, int64_t row) {
-            s_x[i] = a.sx[row];
-            s_y[i] = a.sy[row];
-            s_z[i] = a.sz[row];
-            s_m[i] = a.sm[row];
-            s_gp[i] = a.sgp[row];
-            s_gx[i] = a.sgx[row];
-            s_gy[i] = a.sgy[row];
-            s_gz[i] = a.sgz[row];
+            s_p[i] = a.s4[row];
+            s_g[i] = a.g4[row];
         };
         auto body = [&](int nt) {
             if (!active) return;
             for (int s = g; s < nt; s += G) {
-                const double dx = xj - s_x[s], dy = yj - s_y[s], dz = zj - s_z[s];
+                const Row4d pk = s_p[s], gk = s_g[s];
+                const double dx = pj.x - pk.x, dy = pj.y - pk.y, dz = pj.z - pk.z;
                 const double w = rsqrt(fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2))));
                 const double w3 = w * w * w, w5 = w3 * w * w;
-                const double mk = s_m[s], gpk = s_gp[s];
-                const double gak[3] = {s_gx[s], s_gy[s], s_gz[s]};
-                const double gdj = gxj * dx + gyj * dy + gzj * dz;
-                const double gdk = gak[0] * dx + gak[1] * dy + gak[2] * dz;
-                const double c = mk * (gpj * w3 + 3.0 * w5 * gdj) + mj * (gpk * w3 - 3.0 * w5 * gdk);
-                ox += c * dx + w3 * (mj * gak[0] - mk * gxj);
-                oy += c * dy + w3 * (mj * gak[1] - mk * gyj);
-                oz += c * dz + w3 * (mj * gak[2] - mk * gzj);
-                om -= gpk * w - w3 * gdk;
+                const double gdj = gj.y * dx + gj.z * dy + gj.w * dz;
+                const double gdk = gk.y * dx + gk.z * dy + gk.w * dz;
+                const double c = pk.w * (gj.x * w3 + 3.0 * w5 * gdj) + pj.w * (gk.x * w3 - 3.0 * w5 * gdk);
+                ox += c * dx + w3 * (pj.w * gk.y - pk.w * gj.y);
+                oy += c * dy + w3 * (pj.w * gk.z - pk.w * gj.z);
+                oz += c * dz + w3 * (pj.w * gk.w - pk.w * gj.w);
+                om -= gk.x * w - w3 * gdk;
             }
         };
         for_each_source_tile<false>(A, nullptr, a.nbr_start, a.nbr_idx, a.leaf_start, s_pre,
@@ -347,7 +348,7 @@ __global__ __launch_bounds__(kGBlock) void k_gravity_adjoint(GravityAdjointArgs 
             double r[4] = {0.0, 0.0, 0.0, 0.0};
             for (int q = 0; q < G; ++q)
                 for (int c = 0; c < 4; ++c) r[c] += s_red[c * kGBlock + q * tc + threadIdx.x];
-            r[0] += a.sgp[t0 + tc0 + threadIdx.x] * rsqrt(eps2);
+            r[0] += gj.x * rsqrt(eps2);   // the self pair added -g_phi_j / eps to g_m
             const int64_t i = a.perm[t0 + tc0 + threadIdx.x];
             a.gm[i] = r[0];
             a.gx[i] = r[1];
@@ -366,7 +367,10 @@ p2p_status launch_gravity(const GravityArgs &a, bool redundant, bool mixed, bool
     const unsigned g = static_cast<unsigned>(a.L);
 #define P2P_GRAV(M, R, E) k_gravity<M, R, E><<<g, kGBlock, 0, s>>>(a)
     if (mixed) {
-        if (redundant) { if (eps_zero) P2P_GRAV(true, true, true); else P2P_GRAV(true, true, false); }
+        if (redundant) {
+            if (eps_zero) k_gravity_mixed_red<true><<<g, kGBlock, 0, s>>>(a);
+            else k_gravity_mixed_red<false><<<g, kGBlock, 0, s>>>(a);
+        }
         else { if (eps_zero) P2P_GRAV(true, false, true); else P2P_GRAV(true, false, false); }
     } else {
         if (redundant) { if (eps_zero) P2P_GRAV(false, true, true); else P2P_GRAV(false, true, false); }

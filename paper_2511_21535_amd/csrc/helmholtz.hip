@@ -12,7 +12,10 @@
 // e = l_t - 4 o (o = box offset of B) and source local coordinates
 // (sx, sy, sz) in 0..3, dd = (e_x - sx)^2 + (e_y - sy)^2 + (e_z - sz)^2; the
 // per-axis squares are precomputed per box, so each pair costs one integer
-// add, one LDS read and four FMAs.
+// add, one LDS read and four FMAs.  The near boxes of a target box are dealt
+// to the four wavefronts of its workgroup (box e to wave e % 4), which gives
+// four times the waves to hide the scalar loads of the sources; the four
+// partial sums meet in LDS.
 #include "p2p_internal.h"
 
 namespace p2p {
@@ -49,8 +52,10 @@ __device__ inline int lane_axis(int l, int axis) {
     return ((l >> axis) & 1) | (((l >> (axis + 3)) & 1) << 1);
 }
 
+constexpr int kHWaves = 4;
+
 template <class C, bool RED, bool CONJ, bool ONE>
-__global__ __launch_bounds__(64) void k_helmholtz(
+__global__ __launch_bounds__(64 * kHWaves) void k_helmholtz(
     int64_t L, int key_bits, int32_t nrhs, const int32_t *__restrict__ leaf_start,
     const uint64_t *__restrict__ leaf_key, const int32_t *__restrict__ perm,
     const int64_t *__restrict__ nbr_start, const int32_t *__restrict__ nbr_idx,
@@ -58,13 +63,15 @@ __global__ __launch_bounds__(64) void k_helmholtz(
     const C *__restrict__ tables, C *__restrict__ u) {
     using R = typename Real<C>::T;
     __shared__ C s_tab[kTableLen];
-    const int lane = threadIdx.x;
+    __shared__ C s_part[kHWaves][64];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t A = blockIdx.x;
     const uint64_t local_mask = (1ull << (3 * key_bits)) - 1ull;
     const uint64_t kA = leaf_key[A];
     const int g = static_cast<int>(kA >> (3 * key_bits));
     const C *__restrict__ table = tables + static_cast<int64_t>(g) * kTableLen;
-    for (int i = lane; i < kTableLen; i += 64) s_tab[i] = table[i];
+    for (int i = threadIdx.x; i < kTableLen; i += 64 * kHWaves) s_tab[i] = table[i];
     __syncthreads();
 
     const uint64_t lA = kA & local_mask;
@@ -77,7 +84,7 @@ __global__ __launch_bounds__(64) void k_helmholtz(
     const int64_t stride = ONE ? 1 : nrhs;
     for (int32_t r = 0; r < (ONE ? 1 : nrhs); ++r) {
         R ur = 0, ui = 0;
-        for (int64_t e = e0; e < e1; ++e) {
+        for (int64_t e = e0 + wv; e < e1; e += kHWaves) {
             const int32_t B = nbr_idx[e];
             const uint64_t lB = leaf_key[B] & local_mask;
             const int o[3] = {(static_cast<int>(p2pd::compact3(lB)) - ax) / 4,
@@ -110,11 +117,22 @@ __global__ __launch_bounds__(64) void k_helmholtz(
                 ui = fma(gi, q.x, ui);
             }
         }
-        const int64_t i = perm[leaf_start[A] + lane];
-        C out;
-        out.x = ur;
-        out.y = ui;
-        u[i * stride + r] = out;
+        C part;
+        part.x = ur;
+        part.y = ui;
+        s_part[wv][lane] = part;
+        __syncthreads();
+        if (wv == 0) {
+            C out = s_part[0][lane];
+#pragma unroll
+            for (int q = 1; q < kHWaves; ++q) {
+                out.x += s_part[q][lane].x;
+                out.y += s_part[q][lane].y;
+            }
+            const int64_t i = perm[leaf_start[A] + lane];
+            u[i * stride + r] = out;
+        }
+        __syncthreads();
     }
 }
 
@@ -136,12 +154,12 @@ p2p_status launch_green_tables(const double *d_h, const double *d_k, int32_t n_g
 template <class C, bool RED, bool CONJ>
 static void launch_helm_t(const HelmholtzArgs &a, hipStream_t s) {
     if (a.nrhs == 1)
-        k_helmholtz<C, RED, CONJ, true><<<static_cast<unsigned>(a.L), 64, 0, s>>>(
+        k_helmholtz<C, RED, CONJ, true><<<static_cast<unsigned>(a.L), 64 * kHWaves, 0, s>>>(
             a.L, a.key_bits, a.nrhs, a.leaf_start, a.leaf_key, a.perm, a.nbr_start, a.nbr_idx,
             a.red_start, static_cast<const C *>(a.src), static_cast<const C *>(a.table),
             static_cast<C *>(a.u));
     else
-        k_helmholtz<C, RED, CONJ, false><<<static_cast<unsigned>(a.L), 64, 0, s>>>(
+        k_helmholtz<C, RED, CONJ, false><<<static_cast<unsigned>(a.L), 64 * kHWaves, 0, s>>>(
             a.L, a.key_bits, a.nrhs, a.leaf_start, a.leaf_key, a.perm, a.nbr_start, a.nbr_idx,
             a.red_start, static_cast<const C *>(a.src), static_cast<const C *>(a.table),
             static_cast<C *>(a.u));

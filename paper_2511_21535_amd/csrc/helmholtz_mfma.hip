@@ -156,22 +156,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             }
         };
 
-        // ping-pong operand registers, one k-step of prefetch, across box boundaries
+        // four operand buffers in rotation: the loads of k-step kk + 3 are issued
+        // while step kk runs, across box boundaries (the last box prefetches
+        // its own first steps again, harmlessly)
         const float2 *Gc, *Qc, *Gn, *Qn;
         box_ptrs(0, Gc, Qc);
-        float2 ga[2], qa[TJ], gb[2], qb[TJ];
-        load(Gc, Qc, 0, ga, qa);
+        float2 gbuf[4][2], qbuf[4][TJ];
+        load(Gc, Qc, 0, gbuf[0], qbuf[0]);
+        load(Gc, Qc, 1, gbuf[1], qbuf[1]);
+        load(Gc, Qc, 2, gbuf[2], qbuf[2]);
         for (int e = 0; e < ne; ++e) {
             box_ptrs(e + 1 < ne ? e + 1 : e, Gn, Qn);
 #pragma unroll
-            for (int kk = 0; kk < 32; kk += 2) {
-                load(Gc, Qc, kk + 1, gb, qb);
-                mma(ga, qa);
-                if (kk + 2 < 32)
-                    load(Gc, Qc, kk + 2, ga, qa);
+            for (int kk = 0; kk < 32; ++kk) {
+                const int ks = kk + 3;
+                if (ks < 32)
+                    load(Gc, Qc, ks, gbuf[ks & 3], qbuf[ks & 3]);
                 else
-                    load(Gn, Qn, 0, ga, qa);
-                mma(gb, qb);
+                    load(Gn, Qn, ks - 32, gbuf[ks & 3], qbuf[ks & 3]);
+                mma(gbuf[kk & 3], qbuf[kk & 3]);
             }
             Gc = Gn;
             Qc = Qn;

@@ -10,6 +10,10 @@
 // dropped and the ranges are put in key order, which is leaf-id order.  The
 // candidates are then tested in parallel, 64 per step, and the adjacent ones
 // written with a ballot prefix, so the list comes out ascending.
+//
+// The searches start from a directory over the top bits of the key: dir[p]
+// is the first leaf whose key is at least p << shift, so a key's bucket bounds
+// its search to the leaves of that bucket.
 #include "p2p_internal.h"
 
 namespace p2p {
@@ -17,21 +21,30 @@ namespace {
 
 constexpr int kNbrWaves = 4;
 
-__device__ inline int64_t upper_bound_u64(const uint64_t *__restrict__ a, int64_t n, uint64_t v) {
-    int64_t lo = 0, hi = n;
+// First index in [lo, hi) with a[i] > v (upper) or a[i] >= v (lower).
+__device__ inline int64_t bound_in(const uint64_t *__restrict__ a, int64_t lo, int64_t hi, uint64_t v,
+                                   bool upper) {
     while (lo < hi) {
-        int64_t mid = (lo + hi) >> 1;
-        if (a[mid] <= v) lo = mid + 1; else hi = mid;
+        const int64_t mid = (lo + hi) >> 1;
+        if (upper ? (a[mid] <= v) : (a[mid] < v)) lo = mid + 1; else hi = mid;
     }
     return lo;
 }
-__device__ inline int64_t lower_bound_u64(const uint64_t *__restrict__ a, int64_t n, uint64_t v) {
-    int64_t lo = 0, hi = n;
-    while (lo < hi) {
-        int64_t mid = (lo + hi) >> 1;
-        if (a[mid] < v) lo = mid + 1; else hi = mid;
-    }
-    return lo;
+
+__device__ inline int64_t dir_bound(const uint64_t *__restrict__ a, const int32_t *__restrict__ dir,
+                                    int dir_bits, int shift, uint64_t v, bool upper) {
+    const uint64_t p = v >> shift;
+    if (p >= (1ull << dir_bits)) return dir[1ull << dir_bits];
+    return bound_in(a, dir[p], dir[p + 1], v, upper);
+}
+
+__global__ void k_key_directory(const uint64_t *__restrict__ leaf_key, int64_t L, int dir_bits,
+                                int shift, int32_t *__restrict__ dir) {
+    const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t nb = (int64_t(1) << dir_bits) + 1;
+    if (p >= nb) return;
+    dir[p] = (p == nb - 1) ? static_cast<int32_t>(L)
+                           : static_cast<int32_t>(bound_in(leaf_key, 0, L, static_cast<uint64_t>(p) << shift, false));
 }
 
 __device__ inline void wave_sync() {
@@ -41,8 +54,8 @@ __device__ inline void wave_sync() {
 
 __global__ __launch_bounds__(64 * kNbrWaves) void k_neighbors(
     const uint64_t *__restrict__ leaf_key, const int8_t *__restrict__ leaf_level, int64_t L,
-    int key_bits, int inst_shift, const int64_t *__restrict__ nbr_start,
-    int32_t *__restrict__ counts, int32_t *__restrict__ nbr_idx) {
+    int key_bits, int inst_shift, const int32_t *__restrict__ dir, int dir_bits, int dir_shift,
+    const int64_t *__restrict__ nbr_start, int32_t *__restrict__ counts, int32_t *__restrict__ nbr_idx) {
     __shared__ int32_t s_lo[kNbrWaves][32];
     __shared__ int32_t s_pre[kNbrWaves][33];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -70,14 +83,14 @@ __global__ __launch_bounds__(64 * kNbrWaves) void k_neighbors(
                                                           static_cast<uint32_t>(c[1]),
                                                           static_cast<uint32_t>(c[2]));
             const uint64_t sizeC = 1ull << (3 * (key_bits - lA));
-            const int64_t j = upper_bound_u64(leaf_key, L, kC) - 1;
+            const int64_t j = dir_bound(leaf_key, dir, dir_bits, dir_shift, kC, true) - 1;
             bool covers = false;
             if (j >= 0) {
                 const uint64_t sj = 1ull << (3 * (key_bits - leaf_level[j]));
                 covers = kC < leaf_key[j] + sj;   // leaf_key[j] <= kC by construction
             }
             lo = covers ? j : j + 1;
-            hi = lower_bound_u64(leaf_key, L, kC + sizeC);
+            hi = dir_bound(leaf_key, dir, dir_bits, dir_shift, kC + sizeC, false);
             valid = lo < hi;
         }
     }
@@ -143,12 +156,26 @@ __global__ __launch_bounds__(64 * kNbrWaves) void k_neighbors(
 
 }  // namespace
 
+int neighbor_dir_bits(int total_key_bits) { return total_key_bits < 18 ? total_key_bits : 18; }
+
+p2p_status launch_key_directory(const uint64_t *leaf_key, int64_t L, int total_key_bits, int32_t *dir,
+                                hipStream_t s) {
+    const int db = neighbor_dir_bits(total_key_bits);
+    const int64_t nb = (int64_t(1) << db) + 1;
+    k_key_directory<<<grid_for(nb, 256), 256, 0, s>>>(leaf_key, L, db, total_key_bits - db, dir);
+    P2P_LAUNCH_CHECK();
+    return P2P_OK;
+}
+
 p2p_status launch_neighbors(const uint64_t *leaf_key, const int8_t *leaf_level, int64_t L,
-                            int key_bits, int inst_shift, const int64_t *nbr_start,
-                            int32_t *counts, int32_t *nbr_idx, hipStream_t s) {
+                            int key_bits, int inst_shift, const int32_t *dir, int total_key_bits,
+                            const int64_t *nbr_start, int32_t *counts, int32_t *nbr_idx,
+                            hipStream_t s) {
     if (L <= 0) return P2P_OK;
+    const int db = neighbor_dir_bits(total_key_bits);
     k_neighbors<<<grid_for(L, kNbrWaves), 64 * kNbrWaves, 0, s>>>(
-        leaf_key, leaf_level, L, key_bits, inst_shift, nbr_start, counts, nbr_idx);
+        leaf_key, leaf_level, L, key_bits, inst_shift, dir, db, total_key_bits - db, nbr_start, counts,
+        nbr_idx);
     P2P_LAUNCH_CHECK();
     return P2P_OK;
 }

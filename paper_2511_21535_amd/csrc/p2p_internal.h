@@ -11,6 +11,12 @@
 
 namespace p2p {
 
+// One particle row (x, y, z, m) or four gradient components, 32-byte aligned so
+// a row moves as two 16-byte accesses.
+struct alignas(32) Row4d {
+    double x, y, z, w;
+};
+
 // ---------------------------------------------------------------- errors --
 void set_error(const std::string &msg);
 p2p_status fail(p2p_status st, const std::string &msg);
@@ -81,9 +87,15 @@ p2p_status launch_leaf_write(const uint64_t *skeys, const int8_t *level, const i
                              int32_t *max_level, hipStream_t s);
 
 // Near lists (nbrs.hip).  count pass (out_idx == nullptr) or fill pass.
+// Directory over the top bits of the leaf keys (dir: (1 << neighbor_dir_bits) + 1
+// entries), then the count pass (nbr_idx == nullptr) or the fill pass.
+int neighbor_dir_bits(int total_key_bits);
+p2p_status launch_key_directory(const uint64_t *leaf_key, int64_t L, int total_key_bits, int32_t *dir,
+                                hipStream_t s);
 p2p_status launch_neighbors(const uint64_t *leaf_key, const int8_t *leaf_level, int64_t L,
-                            int key_bits, int inst_shift, const int64_t *nbr_start,
-                            int32_t *counts, int32_t *nbr_idx, hipStream_t s);
+                            int key_bits, int inst_shift, const int32_t *dir, int total_key_bits,
+                            const int64_t *nbr_start, int32_t *counts, int32_t *nbr_idx,
+                            hipStream_t s);
 
 // Restructure (restructure.hip).
 p2p_status launch_seg_lengths(const int32_t *leaf_start, const int64_t *nbr_start,
@@ -92,20 +104,17 @@ p2p_status launch_seg_lengths(const int32_t *leaf_start, const int64_t *nbr_star
 template <class T>
 p2p_status launch_permute_rows(const T *src, const int32_t *perm, int64_t n, int64_t row_len,
                                T *dst, hipStream_t s);
-p2p_status launch_permute_mass_f32(const double *m, const int32_t *perm, int64_t n, float *dst,
-                                   hipStream_t s);
-p2p_status launch_permute_gravity(const double *x, const double *y, const double *z,
-                                  const double *m, const int32_t *perm, int64_t n, bool mass_f32,
-                                  double *sx, double *sy, double *sz, void *sm, hipStream_t s);
-// Gravity payload: FP64 planes (d4 == nullptr) or, for FP32_MIXED, float4
-// (x - c_A, y - c_A, z - c_A, m) relative to the centre of target leaf A.
-p2p_status launch_copy_segments_gravity(const double *sx, const double *sy, const double *sz,
-                                        const double *sm, const uint64_t *leaf_key,
+// out[s] = (a[perm[s]], b[perm[s]], c[perm[s]], d[perm[s]]): four caller-order
+// planes into sorted rows.
+p2p_status launch_permute4(const double *a, const double *b, const double *c, const double *d,
+                           const int32_t *perm, int64_t n, Row4d *out, hipStream_t s);
+// Gravity payload from sorted rows: FP64 rows (d8) or, for FP32_MIXED, float4
+// (x - c_A, y - c_A, z - c_A, m) relative to the centre of target leaf A (d4).
+p2p_status launch_copy_segments_gravity(const Row4d *sorted, const uint64_t *leaf_key,
                                         const int8_t *leaf_level, const int32_t *leaf_start,
                                         const int64_t *nbr_start, const int32_t *nbr_idx,
-                                        const int64_t *red_start, int64_t L, double *dx,
-                                        double *dy, double *dz, double *dm, float4 *d4,
-                                        hipStream_t s);
+                                        const int64_t *red_start, int64_t L, Row4d *d8,
+                                        float4 *d4, hipStream_t s);
 template <class T>
 p2p_status launch_copy_segments(const T *sorted, int64_t row_len, const int32_t *leaf_start,
                                 const int64_t *nbr_start, const int32_t *nbr_idx,
@@ -122,7 +131,7 @@ struct GravityArgs {
     const int32_t *nbr_idx;
     const int64_t *red_start;
     const int32_t *red_self;
-    const double *sx, *sy, *sz, *sm;  // FP64 planes: sorted (gather) or redundant (FP64)
+    const Row4d *s4;                  // FP64 rows (x, y, z, m): sorted (gather) or redundant (FP64)
     const float4 *red4;               // FP32_MIXED redundant payload (leaf-relative x, y, z, m)
     double eps2;
     double *phi, *ax, *ay, *az;       // caller order
@@ -136,8 +145,8 @@ struct GravityAdjointArgs {
     const int32_t *perm;
     const int64_t *nbr_start;
     const int32_t *nbr_idx;
-    const double *sx, *sy, *sz, *sm;        // sorted positions and masses
-    const double *sgp, *sgx, *sgy, *sgz;    // sorted upstream gradients
+    const Row4d *s4;                        // sorted rows (x, y, z, m)
+    const Row4d *g4;                        // sorted upstream gradients (g_phi, g_ax, g_ay, g_az)
     double eps2;
     double *gx, *gy, *gz, *gm;              // caller order
 };
@@ -223,6 +232,15 @@ __host__ __device__ inline uint32_t compact3(uint64_t v) {
 }
 __host__ __device__ inline uint64_t morton3(uint32_t x, uint32_t y, uint32_t z) {
     return spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  This bijection on [0, n) maps workgroup b so that XCD x = b % 8 owns
+// one contiguous range of work items, and neighbouring items (which share
+// most of their source rows in Morton order) stay in the same L2.
+__device__ inline int64_t xcd_contiguous(int64_t b, int64_t n) {
+    const int64_t x = b & 7, k = b >> 3, q = n >> 3, r = n & 7;
+    return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
 }
 
 }  // namespace p2pd

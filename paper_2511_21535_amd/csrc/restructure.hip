@@ -45,27 +45,16 @@ __global__ void k_permute_rows(const T *__restrict__ src, const int32_t *__restr
     for (int r = lane; r < row_len; r += 64) dst[to + r] = src[from + r];
 }
 
-// Caller-order positions and masses into sorted order, in one pass.
-template <class TM>
-__global__ void k_permute_gravity(const double *__restrict__ x, const double *__restrict__ y,
-                                  const double *__restrict__ z, const double *__restrict__ m,
-                                  const int32_t *__restrict__ perm, int64_t n,
-                                  double *__restrict__ sx, double *__restrict__ sy,
-                                  double *__restrict__ sz, TM *__restrict__ sm) {
+// Four caller-order planes into sorted rows, in one pass.
+__global__ void k_permute4(const double *__restrict__ a, const double *__restrict__ b,
+                           const double *__restrict__ c, const double *__restrict__ d,
+                           const int32_t *__restrict__ perm, int64_t n, Row4d *__restrict__ out) {
     const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const int64_t i = perm[s];
-    sx[s] = x[i];
-    sy[s] = y[i];
-    sz[s] = z[i];
-    sm[s] = static_cast<TM>(m[i]);
+    out[s] = Row4d{a[i], b[i], c[i], d[i]};
 }
 
-__global__ void k_permute_mass_f32(const double *__restrict__ m, const int32_t *__restrict__ perm,
-                                   int64_t n, float *__restrict__ dst) {
-    int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (s < n) dst[s] = static_cast<float>(m[perm[s]]);
-}
 
 constexpr int kCopyBlock = 256;
 constexpr int kCopyNbrChunk = 256;   // near-list entries held in LDS at once
@@ -121,17 +110,15 @@ __device__ inline int find_nbr(const int64_t *s_pre, int nc, int64_t p) {
 // m) with c_A the centre of the target leaf, the difference taken in double.
 template <bool MIXED>
 __global__ __launch_bounds__(256) void k_copy_segments_grav(
-    const double *__restrict__ sx, const double *__restrict__ sy, const double *__restrict__ sz,
-    const double *__restrict__ sm, const uint64_t *__restrict__ leaf_key,
+    const Row4d *__restrict__ sorted, const uint64_t *__restrict__ leaf_key,
     const int8_t *__restrict__ leaf_level, const int32_t *__restrict__ leaf_start,
     const int64_t *__restrict__ nbr_start, const int32_t *__restrict__ nbr_idx,
-    const int64_t *__restrict__ red_start, int64_t L, double *__restrict__ dx,
-    double *__restrict__ dy, double *__restrict__ dz, double *__restrict__ dm,
+    const int64_t *__restrict__ red_start, int64_t L, Row4d *__restrict__ d8,
     float4 *__restrict__ d4) {
     __shared__ int32_t s_pre[4][65];
     __shared__ int32_t s_first[4][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t A = static_cast<int64_t>(blockIdx.x) * 4 + w;
+    const int64_t A = p2pd::xcd_contiguous(blockIdx.x, gridDim.x) * 4 + w;
     if (A >= L) return;
     double c[3] = {0.0, 0.0, 0.0};
     if (MIXED) {
@@ -163,23 +150,32 @@ __global__ __launch_bounds__(256) void k_copy_segments_grav(
         if (lane == 0) s_pre[w][64] = rows;
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        for (int32_t p = lane; p < rows; p += 64) {
-            int lo = 0, hi = nc - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (s_pre[w][mid] <= p) lo = mid; else hi = mid - 1;
-            }
-            const int64_t src = s_first[w][lo] + (p - s_pre[w][lo]);
-            if constexpr (MIXED) {
-                d4[out + p] = make_float4(static_cast<float>(sx[src] - c[0]), static_cast<float>(sy[src] - c[1]),
-                                          static_cast<float>(sz[src] - c[2]), static_cast<float>(sm[src]));
-            } else {
-                dx[out + p] = sx[src];
-                dy[out + p] = sy[src];
-                dz[out + p] = sz[src];
-                dm[out + p] = sm[src];
-            }
+        // rows p = lane + 64 j; the neighbour of each row is found by walking
+        // forward from the previous row's (rows only increase), and the loads
+        // of four rows are issued before any of them is used
+        int b = 0;
+        auto src_row = [&](int32_t p) {
+            while (b + 1 < nc && s_pre[w][b + 1] <= p) ++b;
+            return sorted[s_first[w][b] + (p - s_pre[w][b])];
+        };
+        auto put = [&](int64_t d, const Row4d &v) {
+            if constexpr (MIXED)
+                d4[d] = make_float4(static_cast<float>(v.x - c[0]), static_cast<float>(v.y - c[1]),
+                                    static_cast<float>(v.z - c[2]), static_cast<float>(v.w));
+            else
+                d8[d] = v;
+        };
+        // full groups of 256 rows with no per-row condition, so the four loads
+        // and the four stores of a group are all in flight together
+        int32_t p0 = 0;
+        for (; p0 + 256 <= rows; p0 += 256) {
+            Row4d v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = src_row(p0 + 64 * u + lane);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) put(out + p0 + 64 * u + lane, v[u]);
         }
+        for (int32_t p = p0 + lane; p < rows; p += 64) put(out + p, src_row(p));
         out += rows;
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -244,24 +240,27 @@ p2p_status launch_permute_rows(const T *src, const int32_t *perm, int64_t n, int
     return P2P_OK;
 }
 
-p2p_status launch_permute_gravity(const double *x, const double *y, const double *z,
-                                  const double *m, const int32_t *perm, int64_t n, bool mass_f32,
-                                  double *sx, double *sy, double *sz, void *sm, hipStream_t s) {
+p2p_status launch_permute4(const double *a, const double *b, const double *c, const double *d,
+                           const int32_t *perm, int64_t n, Row4d *out, hipStream_t s) {
     if (n <= 0) return P2P_OK;
-    if (mass_f32)
-        k_permute_gravity<float><<<grid_for(n, 256), 256, 0, s>>>(x, y, z, m, perm, n, sx, sy, sz,
-                                                                 static_cast<float *>(sm));
-    else
-        k_permute_gravity<double><<<grid_for(n, 256), 256, 0, s>>>(x, y, z, m, perm, n, sx, sy, sz,
-                                                                  static_cast<double *>(sm));
+    k_permute4<<<grid_for(n, 256), 256, 0, s>>>(a, b, c, d, perm, n, out);
     P2P_LAUNCH_CHECK();
     return P2P_OK;
 }
 
-p2p_status launch_permute_mass_f32(const double *m, const int32_t *perm, int64_t n, float *dst,
-                                   hipStream_t s) {
-    if (n <= 0) return P2P_OK;
-    k_permute_mass_f32<<<grid_for(n, 256), 256, 0, s>>>(m, perm, n, dst);
+p2p_status launch_copy_segments_gravity(const Row4d *sorted, const uint64_t *leaf_key,
+                                        const int8_t *leaf_level, const int32_t *leaf_start,
+                                        const int64_t *nbr_start, const int32_t *nbr_idx,
+                                        const int64_t *red_start, int64_t L, Row4d *d8,
+                                        float4 *d4, hipStream_t s) {
+    if (L <= 0) return P2P_OK;
+    const unsigned g = grid_for(L, 4);
+    if (d4)
+        k_copy_segments_grav<true><<<g, 256, 0, s>>>(sorted, leaf_key, leaf_level, leaf_start, nbr_start,
+                                                     nbr_idx, red_start, L, d8, d4);
+    else
+        k_copy_segments_grav<false><<<g, 256, 0, s>>>(sorted, leaf_key, leaf_level, leaf_start, nbr_start,
+                                                      nbr_idx, red_start, L, d8, d4);
     P2P_LAUNCH_CHECK();
     return P2P_OK;
 }
@@ -273,25 +272,6 @@ p2p_status launch_copy_segments(const T *sorted, int64_t row_len, const int32_t 
     if (L <= 0) return P2P_OK;
     k_copy_segments_rows<T><<<static_cast<unsigned>(L), kCopyBlock, 0, s>>>(
         sorted, static_cast<int>(row_len), leaf_start, nbr_start, nbr_idx, red_start, dst);
-    P2P_LAUNCH_CHECK();
-    return P2P_OK;
-}
-
-p2p_status launch_copy_segments_gravity(const double *sx, const double *sy, const double *sz,
-                                        const double *sm, const uint64_t *leaf_key,
-                                        const int8_t *leaf_level, const int32_t *leaf_start,
-                                        const int64_t *nbr_start, const int32_t *nbr_idx,
-                                        const int64_t *red_start, int64_t L, double *dx,
-                                        double *dy, double *dz, double *dm, float4 *d4,
-                                        hipStream_t s) {
-    if (L <= 0) return P2P_OK;
-    const unsigned g = grid_for(L, 4);
-    if (d4)
-        k_copy_segments_grav<true><<<g, 256, 0, s>>>(sx, sy, sz, sm, leaf_key, leaf_level, leaf_start,
-                                                     nbr_start, nbr_idx, red_start, L, dx, dy, dz, dm, d4);
-    else
-        k_copy_segments_grav<false><<<g, 256, 0, s>>>(sx, sy, sz, sm, leaf_key, leaf_level, leaf_start,
-                                                      nbr_start, nbr_idx, red_start, L, dx, dy, dz, dm, d4);
     P2P_LAUNCH_CHECK();
     return P2P_OK;
 }

@@ -162,58 +162,88 @@ __global__ __launch_bounds__(kSortBlock) void k_radix_hist(const uint64_t *__res
 // chunk by chunk: lanes holding the same digit are found with 8 ballots, the
 // lane's rank among them is a popcount below its lane, and a per-wave digit
 // counter in LDS carries the running count from chunk to chunk.  Wave
-// counters are then scanned across the 4 waves, which keeps the tile order.
+// counters are then scanned across the 4 waves and across the 256 digits,
+// which gives every key its position in the tile sorted by digit (stable).
+// The tile is rearranged in LDS into that order and written out in order, so
+// the keys of one digit leave as one contiguous, coalesced run.
 __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(
     const uint64_t *__restrict__ kin, const int32_t *__restrict__ vin, uint64_t *__restrict__ kout,
     int32_t *__restrict__ vout, int64_t n, int shift, const uint32_t *__restrict__ offs,
     int64_t ntiles) {
     __shared__ uint32_t cnt[4][256];
+    __shared__ uint32_t dstart[256];     // first tile position of each digit
+    __shared__ uint32_t s_w[4];
+    __shared__ uint64_t s_key[kSortTile];
+    __shared__ int32_t s_val[kSortTile];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int i = threadIdx.x; i < 4 * 256; i += kSortBlock) (&cnt[0][0])[i] = 0;
     __syncthreads();
-    const int64_t wbase = static_cast<int64_t>(blockIdx.x) * kSortTile + wave * kSortWaveKeys;
+    const int64_t tbase = static_cast<int64_t>(blockIdx.x) * kSortTile;
+    const int64_t wbase = tbase + wave * kSortWaveKeys;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     uint64_t key[kSortChunks];
     int32_t val[kSortChunks];
     uint32_t loc[kSortChunks];
 #pragma unroll
     for (int c = 0; c < kSortChunks; ++c) {
-        int64_t idx = wbase + c * 64 + lane;
-        bool valid = idx < n;
+        const int64_t idx = wbase + c * 64 + lane;
+        const bool valid = idx < n;
         key[c] = valid ? kin[idx] : 0ull;
         val[c] = valid ? vin[idx] : 0;
-        uint32_t d = static_cast<uint32_t>(key[c] >> shift) & 255u;
+        const uint32_t d = static_cast<uint32_t>(key[c] >> shift) & 255u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
-            uint64_t bal = __ballot((d >> b) & 1u);
+            const uint64_t bal = __ballot((d >> b) & 1u);
             peers &= ((d >> b) & 1u) ? bal : ~bal;
         }
-        uint32_t rank = __popcll(peers & below);
-        uint32_t base = valid ? cnt[wave][d] : 0u;
+        const uint32_t rank = __popcll(peers & below);
+        const uint32_t base = valid ? cnt[wave][d] : 0u;
         if (valid && rank == 0) cnt[wave][d] = base + static_cast<uint32_t>(__popcll(peers));
         loc[c] = base + rank;
     }
     __syncthreads();
-    {
-        uint32_t s = 0;
-        for (int w = 0; w < 4; ++w) {
-            uint32_t t = cnt[w][threadIdx.x];
-            cnt[w][threadIdx.x] = s;
-            s += t;
+    // per digit (thread = digit): exclusive scan over the waves, and the digit's total
+    uint32_t tot = 0;
+    for (int w = 0; w < 4; ++w) {
+        const uint32_t t = cnt[w][threadIdx.x];
+        cnt[w][threadIdx.x] = tot;
+        tot += t;
+    }
+    // exclusive scan of the digit totals across the 256 threads
+    uint32_t inc = tot;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) s_w[wave] = inc;
+    __syncthreads();
+    uint32_t woff = 0;
+    for (int w = 0; w < wave; ++w) woff += s_w[w];
+    dstart[threadIdx.x] = woff + inc - tot;
+    __syncthreads();
+    // rearrange the tile in LDS by digit
+#pragma unroll
+    for (int c = 0; c < kSortChunks; ++c) {
+        const int64_t idx = wbase + c * 64 + lane;
+        if (idx < n) {
+            const uint32_t d = static_cast<uint32_t>(key[c] >> shift) & 255u;
+            const uint32_t pos = dstart[d] + cnt[wave][d] + loc[c];
+            s_key[pos] = key[c];
+            s_val[pos] = val[c];
         }
     }
     __syncthreads();
-#pragma unroll
-    for (int c = 0; c < kSortChunks; ++c) {
-        int64_t idx = wbase + c * 64 + lane;
-        if (idx < n) {
-            uint32_t d = static_cast<uint32_t>(key[c] >> shift) & 255u;
-            int64_t pos = static_cast<int64_t>(offs[static_cast<int64_t>(d) * ntiles + blockIdx.x]) +
-                          cnt[wave][d] + loc[c];
-            kout[pos] = key[c];
-            vout[pos] = val[c];
-        }
+    // write out in tile order: position i of digit d goes to offs[d] + (i - dstart[d])
+    const int tile_n = static_cast<int>(min<int64_t>(kSortTile, n - tbase));
+    for (int i = threadIdx.x; i < tile_n; i += kSortBlock) {
+        const uint64_t k = s_key[i];
+        const uint32_t d = static_cast<uint32_t>(k >> shift) & 255u;
+        const int64_t pos = static_cast<int64_t>(offs[static_cast<int64_t>(d) * ntiles + blockIdx.x]) +
+                            (i - static_cast<int64_t>(dstart[d]));
+        kout[pos] = k;
+        vout[pos] = s_val[i];
     }
 }
 

@@ -78,9 +78,8 @@ def test_tree_neighbors_restructure_bit_exact(gen, n, seed, depth, cap):
         np.testing.assert_array_equal(_n(red.red_start), rs)
         np.testing.assert_array_equal(_n(red.red_self), rself)
         if prec == "fp64":
-            for k, v in enumerate((x, y, z, m)):
-                want = oracle.restructure_rows(ot, os_, oi, rs, v)
-                np.testing.assert_array_equal(_n(red.planes[k])[:S].view(np.uint64), want.view(np.uint64))
+            want = oracle.restructure_rows(ot, os_, oi, rs, np.stack([x, y, z, m], 1))
+            np.testing.assert_array_equal(_n(red.planes[0])[:S].view(np.uint64), want.view(np.uint64))
         else:
             want = oracle.restructure_gravity_rel(ot, os_, oi, rs, x, y, z, m)
             np.testing.assert_array_equal(_n(red.planes[0])[:S].view(np.uint32), want.view(np.uint32))
