@@ -26,6 +26,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -71,14 +72,47 @@ def parse():
 
 
 def copy_calibration():
-    """Plain device-to-device copy of 2^30 bytes, three times, for counter scaling."""
+    """Plain device-to-device copy of 2^30 bytes, three times, for counter
+    scaling; also the copy and fill rates of that size (HIP events)."""
     import torch
     a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     for _ in range(3):
         b.copy_(a)
     torch.cuda.synchronize()
-    print(json.dumps({"copy_calibration_bytes": a.numel() * 4, "reps": 3}), flush=True)
+    ev = _events(3)
+    ev[0].record()
+    for _ in range(5):
+        b.copy_(a)
+    ev[1].record()
+    for _ in range(5):
+        b.fill_(1.0)
+    ev[2].record()
+    torch.cuda.synchronize()
+    nb = a.numel() * 4
+    print(json.dumps({"copy_calibration_bytes": nb, "reps": 3,
+                      "copy_GBps_read_plus_write": 2 * nb * 5 / ev[0].elapsed_time(ev[1]) / 1e6,
+                      "fill_GBps_write": nb * 5 / ev[1].elapsed_time(ev[2]) / 1e6}), flush=True)
+
+
+def pmc_traffic(kernel, workload, source):
+    """HBM bytes per launch of `kernel` on `workload`, from the FETCH_SIZE and
+    WRITE_SIZE counter summary kept in profiles/<kernel>_<workload>_hbm_counters.md,
+    each counter scaled by what it reads for a plain copy of known size.  The
+    summary records the SHA-256 of the kernel's source file when the counters
+    were taken; if that file has changed since, or there is no summary, the
+    traffic is unknown (None)."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_hbm_counters.md")
+    try:
+        rec = next(json.loads(l.split("record:", 1)[1]) for l in open(path) if l.startswith("record:"))
+    except (OSError, StopIteration, ValueError):
+        return None
+    with open(os.path.join(ROOT, "paper_2511_21535_amd", "csrc", source), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
+            return None
+    return {"bytes": rec["fetch_kib"] * 1024 * rec["fetch_scale"] + rec["write_kib"] * 1024 * rec["write_scale"],
+            "read_bytes": rec["fetch_kib"] * 1024 * rec["fetch_scale"],
+            "write_bytes": rec["write_kib"] * 1024 * rec["write_scale"]}
 
 
 def _timed_steps(step, K, W):
@@ -216,6 +250,11 @@ def run_gravity(wname, args):
     # algorithmic restructure traffic: segments written once, caller rows read
     # once, sorted rows written and read once
     res_bytes = S * bpe + n * (32 + 2 * 32)
+    # algorithmic bytes of the redundant evaluation: the redundant rows read
+    # once, four FP64 results written per target, the permutation read once
+    eval_bytes = S * bpe + n * (4 * 8 + 4)
+    kname = "k_gravity_mixed_red" if mixed else "k_gravity_fp64_red"
+    traffic = pmc_traffic(kname, wname, "gravity.hip")
     line = _base(METRIC, value, "pair-interactions/s", K, args.warmup, wall,
                  "f32+f64" if mixed else "f64",
                  {"workload": f"{wname}: {desc}", "n": n, "leaves": tree.n_leaves,
@@ -229,9 +268,11 @@ def run_gravity(wname, args):
         "ms": {"tree": t_tree / K * 1e3, "neighbors": t_nbr / K * 1e3, "restructure": t_res / K * 1e3,
                "eval_redundant": t_red / K * 1e3, "eval_gather": t_gat / K * 1e3},
         "locality": {k: loc[k] for k in ("d_mean", "d_ratio", "v_ratio", "locality")},
-        "roofline": {"bound": "alu", "kernel": f"k_gravity<{'mixed' if mixed else 'fp64'}, redundant>",
-                     "achieved": achieved, "peak": peak, "unit": "T VALU lane-slots/s",
-                     "frac": achieved / peak, "traffic": None, "algorithmic_per_pair": slots},
+        "roofline": {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": peak,
+                     "unit": "T VALU lane-slots/s", "frac": achieved / peak,
+                     "traffic": traffic["bytes"] if traffic else None,
+                     "traffic_detail": dict(traffic, algorithmic_bytes=eval_bytes) if traffic else None,
+                     "algorithmic_per_pair": slots},
         "restructure_roofline": {"bound": "hbm", "achieved": res_bytes / (t_res / K) / 1e9,
                                  "peak": 8000.0, "unit": "GB/s",
                                  "frac": res_bytes / (t_res / K) / 8e12, "bytes": res_bytes},
@@ -288,14 +329,21 @@ def run_helmholtz(wname, args):
     value = work * K / (t_res + t_red)
     flops = 8.0 * work
     if mfma:
-        kern, t_dom = "k_helm_mfma<gather> (v_mfma_f32_32x32x2f32)", t_gat / K
-        roof = {"bound": "mfma", "peak": FP32_MFMA_PEAK_TFLOPS}
+        kern, src, t_dom = "k_helm_mfma_gather", "helmholtz_mfma.hip", t_gat / K
+        roof = {"bound": "mfma", "peak": FP32_MFMA_PEAK_TFLOPS, "instruction": "v_mfma_f32_32x32x2f32"}
+        # sorted right-hand sides read once, results written once (complex64)
+        alg_bytes = 2 * tree.n * nrhs * 8
     else:
-        kern, t_dom = "k_helmholtz<float2, redundant>", t_red / K
+        kern, src, t_dom = "k_helmholtz_red", "helmholtz.hip", t_red / K
         roof = {"bound": "alu", "peak": FP32_VALU_PEAK_TFLOPS}
+        # redundant rows read once, results written once (complex64)
+        alg_bytes = S * nrhs * 8 + tree.n * nrhs * 8
     ach = flops / t_dom / 1e12
+    traffic = pmc_traffic(kern, wname, src)
     roof.update({"kernel": kern, "achieved": ach, "unit": "TFLOP/s", "frac": ach / roof["peak"],
-                 "traffic": None, "algorithmic_per_pair": "8 flop per complex multiply-add"})
+                 "traffic": traffic["bytes"] if traffic else None,
+                 "traffic_detail": dict(traffic, algorithmic_bytes=alg_bytes) if traffic else None,
+                 "algorithmic_per_pair": "8 flop per complex multiply-add"})
     unit = "pair-interactions/s" if nrhs == 1 else "pair-RHS-interactions/s"
     cfg = {"workload": wname, "grids": len(sides), "points": tree.n, "boxes": tree.n_leaves,
            "nrhs": nrhs, "near_entries": nbrs.count, "redundant_entries": S, "pairs": pairs,

@@ -24,9 +24,10 @@
  *    device buffer of at least that many bytes, 256-byte aligned, and
  *    *ws_bytes set to its size.
  *  - All work is enqueued on `stream` (a hipStream_t; NULL = the null
- *    stream).  p2p_build_tree, p2p_build_neighbors and
- *    p2p_restructure_redundant read a count back to the host and therefore
- *    synchronise `stream`; the evaluation and adjoint calls do not.
+ *    stream).  p2p_build_tree and p2p_build_neighbors read counts back to
+ *    the host and therefore synchronise `stream`; p2p_restructure_redundant
+ *    does so only when the near lists do not carry the layout size
+ *    (nbrs->red_entries < 0); the evaluation and adjoint calls never do.
  *  - Validation happens on the host before any launch.  On P2P_EINVAL,
  *    P2P_EDOMAIN or P2P_ECAPACITY no output has been written (except the
  *    documented count fields).  On P2P_EHIP the outputs are undefined.
@@ -114,16 +115,21 @@ typedef struct {
     int32_t *leaf_start; /* device [L+1]: first sorted slot of each leaf; leaf_start[L] = n */
     uint64_t *leaf_key;  /* device [L] */
     int8_t *leaf_level;  /* device [L] */
+    int32_t *iperm;      /* device [n]: caller index -> sorted slot (the inverse of perm) */
 } p2p_tree;
 
 /* Near-field lists in CSR form: nbr(A) = nbr_idx[nbr_start[A] .. nbr_start[A+1]),
  * every leaf whose closed cube touches A's (same grid instance), A included,
  * ascending. */
 typedef struct {
-    int64_t cap;        /* in: capacity of nbr_idx */
-    int64_t count;      /* out: E = total entries (also on P2P_ECAPACITY) */
-    int64_t *nbr_start; /* device [L+1] */
-    int32_t *nbr_idx;   /* device [cap] */
+    int64_t cap;         /* in: capacity of nbr_idx */
+    int64_t count;       /* out: E = total entries (also on P2P_ECAPACITY) */
+    int64_t *nbr_start;  /* device [L+1] */
+    int32_t *nbr_idx;    /* device [cap] */
+    int64_t red_entries; /* out: S = sum over A of the points of the leaves in
+                            nbr(A), the size of the redundant layout over these
+                            lists; a caller that fills the lists itself sets -1
+                            (unknown) */
 } p2p_nbrs;
 
 /* Redundant layout.  Segment A = entries [red_start[A], red_start[A+1]) holds,
@@ -170,8 +176,9 @@ typedef struct {
  *    below `depth` (1..20).
  *  Grids: x = y = z = NULL, grids = host array of n_grids instances,
  *    tree->n = total points; depth and leaf_cap ignored.
- * Synchronises `stream` (reads L back).  P2P_ECAPACITY if L > cap_leaves
- * (tree->n_leaves holds L). */
+ * tree->perm and tree->iperm must hold n entries each, the leaf arrays
+ * cap_leaves (+1).  Synchronises `stream` (reads L back).  P2P_ECAPACITY if
+ * L > cap_leaves (tree->n_leaves holds L). */
 p2p_status p2p_build_tree(const double *x, const double *y, const double *z,
                           const p2p_grid *grids, int32_t n_grids,
                           int32_t depth, int32_t leaf_cap,
@@ -179,7 +186,8 @@ p2p_status p2p_build_tree(const double *x, const double *y, const double *z,
 
 /* Near-field lists of every leaf (a2: the E2 neighbourhood, Sec. 5.1;
  * Fig. 8 counts them for irregular trees).  nbrs->nbr_start must hold L+1
- * entries.  Synchronises `stream`; P2P_ECAPACITY if E > nbrs->cap. */
+ * entries.  Also sets nbrs->red_entries.  Synchronises `stream`;
+ * P2P_ECAPACITY if E > nbrs->cap (count and red_entries are still set). */
 p2p_status p2p_build_neighbors(const p2p_tree *tree, p2p_nbrs *nbrs,
                                void *ws, size_t *ws_bytes, p2p_stream_t stream);
 
@@ -190,7 +198,9 @@ p2p_status p2p_build_neighbors(const p2p_tree *tree, p2p_nbrs *nbrs,
  *  Helmholtz trees (grids): src[0] = q caller-order [n][nrhs] complex
  *    (float2 for FP32_MIXED, double2 for FP64), src[1..3] ignored.
  * out->red_start (L+1), out->red_self (L) and the planes must be allocated;
- * P2P_ECAPACITY (out->count = S) if S > out->cap.  Synchronises `stream`. */
+ * P2P_ECAPACITY (out->count = S) if S > out->cap.  S is taken from
+ * nbrs->red_entries; only if that is negative is it counted on the GPU and
+ * read back (synchronising `stream`). */
 p2p_status p2p_restructure_redundant(const p2p_tree *tree, const p2p_nbrs *nbrs,
                                      const void *const src[4], int32_t nrhs,
                                      p2p_precision prec, p2p_redundant *out,

@@ -36,12 +36,14 @@ class p2p_tree(ctypes.Structure):
                 ("kind", ctypes.c_int32), ("key_bits", ctypes.c_int32),
                 ("max_level", ctypes.c_int32), ("n_grids", ctypes.c_int32),
                 ("perm", ctypes.c_void_p), ("leaf_start", ctypes.c_void_p),
-                ("leaf_key", ctypes.c_void_p), ("leaf_level", ctypes.c_void_p)]
+                ("leaf_key", ctypes.c_void_p), ("leaf_level", ctypes.c_void_p),
+                ("iperm", ctypes.c_void_p)]
 
 
 class p2p_nbrs(ctypes.Structure):
     _fields_ = [("cap", ctypes.c_int64), ("count", ctypes.c_int64),
-                ("nbr_start", ctypes.c_void_p), ("nbr_idx", ctypes.c_void_p)]
+                ("nbr_start", ctypes.c_void_p), ("nbr_idx", ctypes.c_void_p),
+                ("red_entries", ctypes.c_int64)]
 
 
 class p2p_redundant(ctypes.Structure):

@@ -90,6 +90,7 @@ class Tree:
     leaf_start: torch.Tensor
     leaf_key: torch.Tensor
     leaf_level: torch.Tensor
+    iperm: torch.Tensor
     grids: List[Grid] = field(default_factory=list)
 
     def struct(self) -> L.p2p_tree:
@@ -100,11 +101,13 @@ class Tree:
         t.leaf_start = self.leaf_start.data_ptr()
         t.leaf_key = self.leaf_key.data_ptr()
         t.leaf_level = self.leaf_level.data_ptr()
+        t.iperm = self.iperm.data_ptr()
         return t
 
     @staticmethod
     def _build(x, y, z, grids, n, depth, leaf_cap, device) -> "Tree":
         perm = torch.empty(max(n, 1), dtype=torch.int32, device=device)
+        iperm = torch.empty(max(n, 1), dtype=torch.int32, device=device)
         leaf_start = torch.empty(n + 1, dtype=torch.int32, device=device)
         leaf_key = torch.empty(max(n, 1), dtype=torch.int64, device=device)
         leaf_level = torch.empty(max(n, 1), dtype=torch.int8, device=device)
@@ -112,6 +115,7 @@ class Tree:
         t.n, t.cap_leaves = n, n
         t.perm, t.leaf_start = perm.data_ptr(), leaf_start.data_ptr()
         t.leaf_key, t.leaf_level = leaf_key.data_ptr(), leaf_level.data_ptr()
+        t.iperm = iperm.data_ptr()
         gs, ng = (None, 0)
         if grids is not None:
             gs, _ = grids_struct(grids)
@@ -126,7 +130,8 @@ class Tree:
         return Tree(n=n, n_leaves=nl, kind=int(t.kind), key_bits=int(t.key_bits),
                     max_level=int(t.max_level), perm=perm[:n] if n else perm[:0],
                     leaf_start=leaf_start[: nl + 1], leaf_key=leaf_key[:nl],
-                    leaf_level=leaf_level[:nl], grids=list(grids) if grids else [])
+                    leaf_level=leaf_level[:nl], iperm=iperm[:n] if n else iperm[:0],
+                    grids=list(grids) if grids else [])
 
     @staticmethod
     def build_particles(x, y, z, depth: int = 20, leaf_cap: int = 64) -> "Tree":
@@ -151,11 +156,13 @@ class Nbrs:
     count: int
     nbr_start: torch.Tensor
     nbr_idx: torch.Tensor
+    red_entries: int = -1      # S of the redundant layout over these lists (-1: unknown)
 
     def struct(self) -> L.p2p_nbrs:
         s = L.p2p_nbrs()
         s.cap, s.count = self.nbr_idx.numel(), self.count
         s.nbr_start, s.nbr_idx = self.nbr_start.data_ptr(), self.nbr_idx.data_ptr()
+        s.red_entries = self.red_entries
         return s
 
 
@@ -178,7 +185,8 @@ def build_neighbors(tree: Tree, cap: Optional[int] = None) -> Nbrs:
             cap = int(s.count)
             continue
         L.check(st)
-        return Nbrs(count=int(s.count), nbr_start=start, nbr_idx=idx[: int(s.count)])
+        return Nbrs(count=int(s.count), nbr_start=start, nbr_idx=idx[: int(s.count)],
+                    red_entries=int(s.red_entries))
     raise L.P2PError(L.P2P_ECAPACITY, "near-list capacity retry failed")
 
 
@@ -204,7 +212,10 @@ class Redundant:
 
 
 def redundant_entries(tree: Tree, nbrs: Nbrs) -> int:
-    """S, the number of entries of the redundant layout (counted on the GPU)."""
+    """S, the number of entries of the redundant layout (from the near lists,
+    else counted on the GPU)."""
+    if nbrs.red_entries >= 0:
+        return nbrs.red_entries
     return locality(tree, nbrs)["entries"]
 
 

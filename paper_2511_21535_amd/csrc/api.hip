@@ -78,7 +78,7 @@ p2p_status check_grids(const p2p_grid *grids, int32_t n_grids, int64_t n) {
 p2p_status check_tree(const p2p_tree *t) {
     if (!t) return fail(P2P_EINVAL, "tree is NULL");
     if (t->n < 0 || t->n_leaves < 0 || t->n_leaves > t->n) return fail(P2P_EINVAL, "tree: bad sizes (not built?)");
-    if (t->n > 0 && (!t->perm || !t->leaf_start || !t->leaf_key || !t->leaf_level))
+    if (t->n > 0 && (!t->perm || !t->iperm || !t->leaf_start || !t->leaf_key || !t->leaf_level))
         return fail(P2P_EINVAL, "tree: NULL array");
     if (t->kind != P2P_TREE_PARTICLES && t->kind != P2P_TREE_GRIDS) return fail(P2P_EINVAL, "tree: bad kind");
     return P2P_OK;
@@ -144,7 +144,7 @@ extern "C" p2p_status p2p_build_tree(const double *x, const double *y, const dou
     int64_t *d_off = ar.take<int64_t>(particles ? 1 : n_grids);
     p2p_status st;
     if (ws_query(ws, ws_bytes, ar, &st)) return st;
-    if (n > 0 && (!tree->perm || !tree->leaf_start || !tree->leaf_key || !tree->leaf_level))
+    if (n > 0 && (!tree->perm || !tree->iperm || !tree->leaf_start || !tree->leaf_key || !tree->leaf_level))
         return fail(P2P_EINVAL, "tree arrays must not be NULL");
     if (!tree->leaf_start) return fail(P2P_EINVAL, "tree->leaf_start must not be NULL");
     hipStream_t s = as_stream(stream);
@@ -193,7 +193,7 @@ extern "C" p2p_status p2p_build_tree(const double *x, const double *y, const dou
     }
     P2P_TRY(launch_leaf_write(keys, level, flags, flag_scan, n, tree->kind, key_bits, tree->leaf_start,
                               tree->leaf_key, tree->leaf_level, &counters[1], s));
-    P2P_HIP(hipMemcpyAsync(tree->perm, vals, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    P2P_TRY(launch_perm_and_inverse(vals, n, tree->perm, tree->iperm, s));
     int32_t maxl = 0;
     P2P_HIP(hipMemcpyAsync(&maxl, &counters[1], sizeof(int32_t), hipMemcpyDeviceToHost, s));
     P2P_HIP(hipStreamSynchronize(s));
@@ -218,6 +218,8 @@ extern "C" p2p_status p2p_build_neighbors(const p2p_tree *tree, p2p_nbrs *nbrs, 
     int64_t *start = ar.take<int64_t>(L + 1);
     int64_t *scan_tmp = ar.take<int64_t>(scan_ws_elems(L));
     int32_t *dir = ar.take<int32_t>((size_t(1) << neighbor_dir_bits(total_bits)) + 1);
+    int32_t *segs = ar.take<int32_t>(L);
+    int64_t *seg_scan = ar.take<int64_t>(L + 1);
     p2p_status st;
     if (ws_query(ws, ws_bytes, ar, &st)) return st;
     if (!nbrs->nbr_start) return fail(P2P_EINVAL, "nbrs->nbr_start must not be NULL");
@@ -225,11 +227,16 @@ extern "C" p2p_status p2p_build_neighbors(const p2p_tree *tree, p2p_nbrs *nbrs, 
     const int inst_shift = 3 * tree->key_bits;
     P2P_TRY(launch_key_directory(tree->leaf_key, L, total_bits, dir, s));
     P2P_TRY(launch_neighbors(tree->leaf_key, tree->leaf_level, L, tree->key_bits, inst_shift, dir,
-                             total_bits, nullptr, counts, nullptr, s));
+                             total_bits, nullptr, counts, nullptr, tree->leaf_start, segs, s));
     P2P_TRY((exclusive_scan<int32_t, int64_t>(counts, start, L, scan_tmp, s)));
-    int64_t E = 0;
-    P2P_HIP(hipMemcpyAsync(&E, &start[L], sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    P2P_TRY((exclusive_scan<int32_t, int64_t>(segs, seg_scan, L, scan_tmp, s)));
+    int64_t E = 0, S = 0;
+    if (L > 0) {
+        P2P_HIP(hipMemcpyAsync(&E, &start[L], sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        P2P_HIP(hipMemcpyAsync(&S, &seg_scan[L], sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    }
     P2P_HIP(hipStreamSynchronize(s));
+    nbrs->red_entries = S;
     if (E > nbrs->cap) {
         nbrs->count = E;
         return fail(P2P_ECAPACITY, "nbrs->cap " + std::to_string(nbrs->cap) + " < " + std::to_string(E) + " entries");
@@ -237,7 +244,7 @@ extern "C" p2p_status p2p_build_neighbors(const p2p_tree *tree, p2p_nbrs *nbrs, 
     if (E > 0 && !nbrs->nbr_idx) return fail(P2P_EINVAL, "nbrs->nbr_idx must not be NULL");
     P2P_HIP(hipMemcpyAsync(nbrs->nbr_start, start, (L + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
     P2P_TRY(launch_neighbors(tree->leaf_key, tree->leaf_level, L, tree->key_bits, inst_shift, dir,
-                             total_bits, nbrs->nbr_start, nullptr, nbrs->nbr_idx, s));
+                             total_bits, nbrs->nbr_start, nullptr, nbrs->nbr_idx, nullptr, nullptr, s));
     P2P_HIP(hipStreamSynchronize(s));
     nbrs->count = E;
     return P2P_OK;
@@ -261,10 +268,10 @@ extern "C" p2p_status p2p_restructure_redundant(const p2p_tree *tree, const p2p_
     const int64_t n = tree->n, L = tree->n_leaves;
     const size_t csize = mixed ? sizeof(float2) : sizeof(double2);
     Arena ar(ws);
-    int64_t *seg_len = ar.take<int64_t>(L);
-    int64_t *rstart = ar.take<int64_t>(L + 1);
+    int32_t *seg_len = ar.take<int32_t>(L);
     int64_t *scan_tmp = ar.take<int64_t>(scan_ws_elems(L));
-    int32_t *rself = ar.take<int32_t>(L);
+    int64_t *count_start = ar.take<int64_t>(nbrs->red_entries < 0 ? L + 1 : 0);
+    int32_t *count_self = ar.take<int32_t>(nbrs->red_entries < 0 ? L : 0);
     Row4d *s4 = nullptr;
     void *sq = nullptr;
     if (grav)
@@ -279,41 +286,44 @@ extern "C" p2p_status p2p_restructure_redundant(const p2p_tree *tree, const p2p_
     if (!out->red_start || (L > 0 && !out->red_self)) return fail(P2P_EINVAL, "out->red_start/red_self must not be NULL");
     if (out->cap < 0) return fail(P2P_EINVAL, "out->cap < 0");
     hipStream_t s = as_stream(stream);
-    P2P_TRY(launch_seg_lengths(tree->leaf_start, nbrs->nbr_start, nbrs->nbr_idx, L, seg_len, rself, s));
-    P2P_TRY((exclusive_scan<int64_t, int64_t>(seg_len, rstart, L, scan_tmp, s)));
-    int64_t S = 0;
-    P2P_HIP(hipMemcpyAsync(&S, &rstart[L], sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    P2P_HIP(hipStreamSynchronize(s));
+    // S: carried by the near lists, else counted here and read back
+    int64_t S = nbrs->red_entries;
+    if (S < 0) {
+        P2P_TRY(launch_seg_lengths(tree->leaf_start, nbrs->nbr_start, nbrs->nbr_idx, L, seg_len, count_self, s));
+        P2P_TRY((exclusive_scan<int32_t, int64_t>(seg_len, count_start, L, scan_tmp, s)));
+        S = 0;
+        if (L > 0) P2P_HIP(hipMemcpyAsync(&S, &count_start[L], sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        P2P_HIP(hipStreamSynchronize(s));
+    }
     if (S > out->cap) {
         out->count = S;
         return fail(P2P_ECAPACITY, "out->cap " + std::to_string(out->cap) + " < " + std::to_string(S) + " entries");
     }
     if (S > 0 && !out->planes[0])
         return fail(P2P_EINVAL, "out->planes must not be NULL");
-    P2P_HIP(hipMemcpyAsync(out->red_start, rstart, (L + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
-    if (L > 0) P2P_HIP(hipMemcpyAsync(out->red_self, rself, L * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    P2P_TRY(launch_seg_lengths(tree->leaf_start, nbrs->nbr_start, nbrs->nbr_idx, L, seg_len, out->red_self, s));
+    P2P_TRY((exclusive_scan<int32_t, int64_t>(seg_len, out->red_start, L, scan_tmp, s)));
     if (grav) {
-        P2P_TRY(launch_permute4(static_cast<const double *>(src[0]), static_cast<const double *>(src[1]),
+        P2P_TRY(launch_scatter4(static_cast<const double *>(src[0]), static_cast<const double *>(src[1]),
                                 static_cast<const double *>(src[2]), static_cast<const double *>(src[3]),
-                                tree->perm, n, s4, s));
+                                tree->iperm, n, s4, s));
         P2P_TRY(launch_copy_segments_gravity(s4, tree->leaf_key, tree->leaf_level, tree->leaf_start,
-                                             nbrs->nbr_start, nbrs->nbr_idx, rstart, L,
+                                             nbrs->nbr_start, nbrs->nbr_idx, out->red_start, L,
                                              mixed ? nullptr : static_cast<Row4d *>(out->planes[0]),
                                              mixed ? static_cast<float4 *>(out->planes[0]) : nullptr, s));
     } else if (mixed) {
         P2P_TRY(launch_permute_rows<float2>(static_cast<const float2 *>(src[0]), tree->perm, n, nrhs,
                                             static_cast<float2 *>(sq), s));
         P2P_TRY(launch_copy_segments<float2>(static_cast<const float2 *>(sq), nrhs, tree->leaf_start,
-                                             nbrs->nbr_start, nbrs->nbr_idx, rstart, L,
+                                             nbrs->nbr_start, nbrs->nbr_idx, out->red_start, L,
                                              static_cast<float2 *>(out->planes[0]), s));
     } else {
         P2P_TRY(launch_permute_rows<double2>(static_cast<const double2 *>(src[0]), tree->perm, n, nrhs,
                                              static_cast<double2 *>(sq), s));
         P2P_TRY(launch_copy_segments<double2>(static_cast<const double2 *>(sq), nrhs, tree->leaf_start,
-                                              nbrs->nbr_start, nbrs->nbr_idx, rstart, L,
+                                              nbrs->nbr_start, nbrs->nbr_idx, out->red_start, L,
                                               static_cast<double2 *>(out->planes[0]), s));
     }
-    P2P_HIP(hipStreamSynchronize(s));
     out->count = S;
     out->nrhs = nrhs;
     out->kind = grav ? P2P_KIND_GRAVITY : P2P_KIND_HELMHOLTZ;
@@ -374,7 +384,7 @@ extern "C" p2p_status p2p_eval_gravity(const p2p_tree *tree, const p2p_nbrs *nbr
         else
             a.s4 = static_cast<const Row4d *>(red->planes[0]);
     } else {
-        P2P_TRY(launch_permute4(x, y, z, m, tree->perm, n, s4, s));
+        P2P_TRY(launch_scatter4(x, y, z, m, tree->iperm, n, s4, s));
         a.s4 = s4;
     }
     return launch_gravity(a, redundant, mixed, eps == 0.0, s);
@@ -577,8 +587,8 @@ extern "C" p2p_status p2p_adjoint(int32_t kind, const p2p_tree *tree, const p2p_
     for (int i = 0; i < 4; ++i)
         if (n > 0 && (!fwd_in[i] || !grad_out[i] || !grad_in[i])) return fail(P2P_EINVAL, "NULL gravity array");
     auto D = [](const void *p) { return static_cast<const double *>(p); };
-    P2P_TRY(launch_permute4(D(fwd_in[0]), D(fwd_in[1]), D(fwd_in[2]), D(fwd_in[3]), tree->perm, n, s4, s));
-    P2P_TRY(launch_permute4(D(grad_out[0]), D(grad_out[1]), D(grad_out[2]), D(grad_out[3]), tree->perm, n,
+    P2P_TRY(launch_scatter4(D(fwd_in[0]), D(fwd_in[1]), D(fwd_in[2]), D(fwd_in[3]), tree->iperm, n, s4, s));
+    P2P_TRY(launch_scatter4(D(grad_out[0]), D(grad_out[1]), D(grad_out[2]), D(grad_out[3]), tree->iperm, n,
                             g4, s));
     GravityAdjointArgs a{};
     a.L = tree->n_leaves;

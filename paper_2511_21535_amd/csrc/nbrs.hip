@@ -11,6 +11,9 @@
 // candidates are then tested in parallel, 64 per step, and the adjacent ones
 // written with a ballot prefix, so the list comes out ascending.
 //
+// The counting pass (counts != NULL) also sums, per leaf A, the points of the
+// leaves in nbr(A): the length of A's segment in the redundant layout.
+//
 // The searches start from a directory over the top bits of the key: dir[p]
 // is the first leaf whose key is at least p << shift, so a key's bucket bounds
 // its search to the leaves of that bucket.
@@ -55,7 +58,8 @@ __device__ inline void wave_sync() {
 __global__ __launch_bounds__(64 * kNbrWaves) void k_neighbors(
     const uint64_t *__restrict__ leaf_key, const int8_t *__restrict__ leaf_level, int64_t L,
     int key_bits, int inst_shift, const int32_t *__restrict__ dir, int dir_bits, int dir_shift,
-    const int64_t *__restrict__ nbr_start, int32_t *__restrict__ counts, int32_t *__restrict__ nbr_idx) {
+    const int64_t *__restrict__ nbr_start, int32_t *__restrict__ counts, int32_t *__restrict__ nbr_idx,
+    const int32_t *__restrict__ leaf_start, int32_t *__restrict__ segs) {
     __shared__ int32_t s_lo[kNbrWaves][32];
     __shared__ int32_t s_pre[kNbrWaves][33];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -131,6 +135,7 @@ __global__ __launch_bounds__(64 * kNbrWaves) void k_neighbors(
     const int64_t out0 = counts ? 0 : nbr_start[A];
     int64_t written = 0;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int32_t occ_sum = 0;     // points of this lane's adjacent candidates (count pass)
     for (int32_t base = 0; base < total; base += 64) {
         const int32_t cidx = base + lane;
         bool adj = false;
@@ -149,9 +154,17 @@ __global__ __launch_bounds__(64 * kNbrWaves) void k_neighbors(
         }
         const uint64_t bal = __ballot(adj);
         if (!counts && adj) nbr_idx[out0 + written + __popcll(bal & below)] = static_cast<int32_t>(B);
+        if (counts && adj) occ_sum += leaf_start[B + 1] - leaf_start[B];
         written += __popcll(bal);
     }
-    if (counts && lane == 0) counts[A] = static_cast<int32_t>(written);
+    if (counts) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) occ_sum += __shfl_xor(occ_sum, o, 64);
+        if (lane == 0) {
+            counts[A] = static_cast<int32_t>(written);
+            segs[A] = occ_sum;
+        }
+    }
 }
 
 }  // namespace
@@ -170,12 +183,12 @@ p2p_status launch_key_directory(const uint64_t *leaf_key, int64_t L, int total_k
 p2p_status launch_neighbors(const uint64_t *leaf_key, const int8_t *leaf_level, int64_t L,
                             int key_bits, int inst_shift, const int32_t *dir, int total_key_bits,
                             const int64_t *nbr_start, int32_t *counts, int32_t *nbr_idx,
-                            hipStream_t s) {
+                            const int32_t *leaf_start, int32_t *segs, hipStream_t s) {
     if (L <= 0) return P2P_OK;
     const int db = neighbor_dir_bits(total_key_bits);
     k_neighbors<<<grid_for(L, kNbrWaves), 64 * kNbrWaves, 0, s>>>(
         leaf_key, leaf_level, L, key_bits, inst_shift, dir, db, total_key_bits - db, nbr_start, counts,
-        nbr_idx);
+        nbr_idx, leaf_start, segs);
     P2P_LAUNCH_CHECK();
     return P2P_OK;
 }

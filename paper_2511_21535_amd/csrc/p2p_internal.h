@@ -81,6 +81,8 @@ p2p_status launch_grid_keys(const int32_t *d_n_side, const int64_t *d_point_off,
                             int bits, int64_t n, uint64_t *keys, int32_t *vals, hipStream_t s);
 p2p_status launch_leaf_levels(const uint64_t *skeys, int64_t n, int kind, int depth, int leaf_cap,
                               uint8_t *pair_common, int8_t *level, int32_t *flags, hipStream_t s);
+p2p_status launch_perm_and_inverse(const int32_t *vals, int64_t n, int32_t *perm, int32_t *iperm,
+                                   hipStream_t s);
 p2p_status launch_leaf_write(const uint64_t *skeys, const int8_t *level, const int32_t *flags,
                              const int32_t *flag_scan, int64_t n, int kind, int key_bits,
                              int32_t *leaf_start, uint64_t *leaf_key, int8_t *leaf_level,
@@ -95,19 +97,20 @@ p2p_status launch_key_directory(const uint64_t *leaf_key, int64_t L, int total_k
 p2p_status launch_neighbors(const uint64_t *leaf_key, const int8_t *leaf_level, int64_t L,
                             int key_bits, int inst_shift, const int32_t *dir, int total_key_bits,
                             const int64_t *nbr_start, int32_t *counts, int32_t *nbr_idx,
-                            hipStream_t s);
+                            const int32_t *leaf_start, int32_t *segs, hipStream_t s);
 
 // Restructure (restructure.hip).
 p2p_status launch_seg_lengths(const int32_t *leaf_start, const int64_t *nbr_start,
-                              const int32_t *nbr_idx, int64_t L, int64_t *seg_len,
+                              const int32_t *nbr_idx, int64_t L, int32_t *seg_len,
                               int32_t *red_self, hipStream_t s);
 template <class T>
 p2p_status launch_permute_rows(const T *src, const int32_t *perm, int64_t n, int64_t row_len,
                                T *dst, hipStream_t s);
 // out[s] = (a[perm[s]], b[perm[s]], c[perm[s]], d[perm[s]]): four caller-order
 // planes into sorted rows.
-p2p_status launch_permute4(const double *a, const double *b, const double *c, const double *d,
-                           const int32_t *perm, int64_t n, Row4d *out, hipStream_t s);
+// Caller-order planes (a, b, c, d) into sorted rows: out[iperm[i]] = (a, b, c, d)[i].
+p2p_status launch_scatter4(const double *a, const double *b, const double *c, const double *d,
+                           const int32_t *iperm, int64_t n, Row4d *out, hipStream_t s);
 // Gravity payload from sorted rows: FP64 rows (d8) or, for FP32_MIXED, float4
 // (x - c_A, y - c_A, z - c_A, m) relative to the centre of target leaf A (d4).
 p2p_status launch_copy_segments_gravity(const Row4d *sorted, const uint64_t *leaf_key,

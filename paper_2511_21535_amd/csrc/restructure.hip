@@ -2,57 +2,104 @@
 // permutations it and the gather layout share.
 //
 // The redundant segment of target leaf A is the concatenation, for B in
-// nbr(A) in order, of B's sorted rows.  Rows are first permuted from caller
+// nbr(A) in order, of B's sorted rows.  Rows are first moved from caller
 // order into sorted order (one pass, N rows), then every segment is filled
-// with coalesced copies: a workgroup owns one target leaf and walks its
-// segment in row order, locating the source leaf of each row by a binary
-// search over the prefix of neighbour occupancies kept in LDS.
+// with coalesced copies, walking the segment in row order and locating the
+// source leaf of each row in the prefix of neighbour occupancies kept in LDS.
 #include "p2p_internal.h"
 
 namespace p2p {
 namespace {
 
-__global__ void k_seg_lengths(const int32_t *__restrict__ leaf_start,
-                              const int64_t *__restrict__ nbr_start,
-                              const int32_t *__restrict__ nbr_idx, int64_t L,
-                              int64_t *__restrict__ seg_len, int32_t *__restrict__ red_self) {
-    int64_t A = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (A >= L) return;
-    int64_t len = 0, self = 0;
-    for (int64_t e = nbr_start[A]; e < nbr_start[A + 1]; ++e) {
+// Streaming stores for the redundant segments: written once here and read
+// once by the evaluation much later, so they are kept from displacing the
+// sorted source rows (re-read by about 27 target leaves each) in L2.
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+typedef uint32_t nt_u4 __attribute__((ext_vector_type(4)));
+typedef uint32_t nt_u2 __attribute__((ext_vector_type(2)));
+
+__device__ inline void stream_store(float4 *d, const float4 &v) {
+    const nt_f4 t = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(t, reinterpret_cast<nt_f4 *>(d));
+}
+__device__ inline void stream_store(Row4d *d, const Row4d &v) {
+    const nt_d2 a = {v.x, v.y}, b = {v.z, v.w};
+    __builtin_nontemporal_store(a, reinterpret_cast<nt_d2 *>(d));
+    __builtin_nontemporal_store(b, reinterpret_cast<nt_d2 *>(d) + 1);
+}
+__device__ inline void stream_store(uint4 *d, const uint4 &v) {
+    const nt_u4 t = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(t, reinterpret_cast<nt_u4 *>(d));
+}
+__device__ inline void stream_store(uint2 *d, const uint2 &v) {
+    const nt_u2 t = {v.x, v.y};
+    __builtin_nontemporal_store(t, reinterpret_cast<nt_u2 *>(d));
+}
+__device__ inline void stream_store(uint32_t *d, const uint32_t &v) { __builtin_nontemporal_store(v, d); }
+
+// Segment length of every target leaf A (the points of the leaves in nbr(A))
+// and the offset of A's own rows in it (the points of the neighbours listed
+// before A, the lists being ascending): 16 lanes per leaf, lanes across the
+// list, two sums over the 16 lanes.
+constexpr int kSegLanes = 16;
+
+__global__ __launch_bounds__(256) void k_seg_lengths(const int32_t *__restrict__ leaf_start,
+                                                     const int64_t *__restrict__ nbr_start,
+                                                     const int32_t *__restrict__ nbr_idx, int64_t L,
+                                                     int32_t *__restrict__ seg_len,
+                                                     int32_t *__restrict__ red_self) {
+    const int sub = threadIdx.x % kSegLanes;
+    const int64_t A = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / kSegLanes;
+    if (A >= L) return;     // whole 16-lane groups leave together
+    int32_t len = 0, before = 0;
+    for (int64_t e = nbr_start[A] + sub; e < nbr_start[A + 1]; e += kSegLanes) {
         const int32_t B = nbr_idx[e];
-        if (B == A) self = len;
-        len += leaf_start[B + 1] - leaf_start[B];
+        const int32_t occ = leaf_start[B + 1] - leaf_start[B];
+        len += occ;
+        if (B < A) before += occ;
     }
-    seg_len[A] = len;
-    red_self[A] = static_cast<int32_t>(self);
+#pragma unroll
+    for (int o = kSegLanes / 2; o > 0; o >>= 1) {
+        len += __shfl_xor(len, o, kSegLanes);
+        before += __shfl_xor(before, o, kSegLanes);
+    }
+    if (sub == 0) {
+        seg_len[A] = len;
+        red_self[A] = before;
+    }
 }
 
-// Rows of row_len elements: row_len == 1 one row per thread, otherwise one
-// wave per row with lanes across it.
-template <class T>
-__global__ void k_permute_rows(const T *__restrict__ src, const int32_t *__restrict__ perm,
-                               int64_t n, int row_len, T *__restrict__ dst) {
-    if (row_len == 1) {
-        const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-        if (s < n) dst[s] = src[perm[s]];
-        return;
+// Rows of upr units (a unit is the widest of 16, 8 or 4 bytes that divides the
+// row): one thread per unit, UN units per thread in flight.
+template <class U, int UN, class I>
+__global__ __launch_bounds__(256) void k_permute_units(const U *__restrict__ src,
+                                                       const int32_t *__restrict__ perm, I units,
+                                                       I upr, U *__restrict__ dst) {
+    const I base = static_cast<I>(blockIdx.x) * (256 * UN) + threadIdx.x;
+    // units past the end repeat the last unit (same bytes, same place), so the
+    // loads and stores carry no condition
+    U v[UN];
+#pragma unroll
+    for (int k = 0; k < UN; ++k) {
+        const I u = min(base + 256 * k, units - 1);
+        const I s = u / upr;
+        v[k] = src[static_cast<uint64_t>(perm[s]) * upr + (u - s * upr)];
     }
-    const int lane = threadIdx.x & 63;
-    const int64_t s = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
-    if (s >= n) return;
-    const int64_t from = static_cast<int64_t>(perm[s]) * row_len, to = s * row_len;
-    for (int r = lane; r < row_len; r += 64) dst[to + r] = src[from + r];
+#pragma unroll
+    for (int k = 0; k < UN; ++k) dst[min(base + 256 * k, units - 1)] = v[k];
 }
 
-// Four caller-order planes into sorted rows, in one pass.
-__global__ void k_permute4(const double *__restrict__ a, const double *__restrict__ b,
+// Four caller-order planes into sorted rows, in one pass: each thread reads
+// one caller index from the four planes (coalesced) and writes its 32-byte row
+// to the sorted slot iperm[i] (one aligned 32-byte write, where gathering
+// would fetch a separate cache line from every plane).
+__global__ void k_scatter4(const double *__restrict__ a, const double *__restrict__ b,
                            const double *__restrict__ c, const double *__restrict__ d,
-                           const int32_t *__restrict__ perm, int64_t n, Row4d *__restrict__ out) {
-    const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const int64_t i = perm[s];
-    out[s] = Row4d{a[i], b[i], c[i], d[i]};
+                           const int32_t *__restrict__ iperm, int64_t n, Row4d *__restrict__ out) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    out[iperm[i]] = Row4d{a[i], b[i], c[i], d[i]};
 }
 
 
@@ -92,22 +139,18 @@ __device__ int64_t load_nbr_chunk(const int32_t *__restrict__ leaf_start,
     return tot;
 }
 
-// Index of the last neighbour b < nc with s_pre[b] <= p.
-__device__ inline int find_nbr(const int64_t *s_pre, int nc, int64_t p) {
-    int lo = 0, hi = nc - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (s_pre[mid] <= p) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
 // Gravity payload, one wavefront per target leaf (four per workgroup, no
-// workgroup barriers).  Lanes load a chunk of 64 near-list entries, form the
-// exclusive prefix of their occupancies with wave shuffles, and then copy the
-// segment row by row; a row finds its source leaf by binary search over the
-// prefix.  FP32_MIXED rows are written as float4 (x - c_A, y - c_A, z - c_A,
-// m) with c_A the centre of the target leaf, the difference taken in double.
+// workgroup barriers).  Lanes load a chunk of 64 near-list entries and form
+// the exclusive prefix of their occupancies with wave shuffles; each lane then
+// marks the rows of its neighbour in an LDS map (row -> neighbour), and the
+// segment is copied eight rows per lane at a time, every row finding its
+// source through the map (or, for a chunk of more than kMapRows rows, by a
+// forward walk over the prefix).  FP32_MIXED rows are written as float4
+// (x - c_A, y - c_A, z - c_A, m) with c_A the centre of the target leaf, the
+// difference taken in double.
+constexpr int kMapRows = 4096;
+constexpr int kRowsPerLane = 8;
+
 template <bool MIXED>
 __global__ __launch_bounds__(256) void k_copy_segments_grav(
     const Row4d *__restrict__ sorted, const uint64_t *__restrict__ leaf_key,
@@ -117,6 +160,7 @@ __global__ __launch_bounds__(256) void k_copy_segments_grav(
     float4 *__restrict__ d4) {
     __shared__ int32_t s_pre[4][65];
     __shared__ int32_t s_first[4][64];
+    __shared__ uint8_t s_map[4][kMapRows];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t A = p2pd::xcd_contiguous(blockIdx.x, gridDim.x) * 4 + w;
     if (A >= L) return;
@@ -148,69 +192,87 @@ __global__ __launch_bounds__(256) void k_copy_segments_grav(
         s_first[w][lane] = first;
         const int32_t rows = __shfl(inc, 63, 64);
         if (lane == 0) s_pre[w][64] = rows;
+        const bool use_map = rows <= kMapRows;
+        if (use_map)
+            for (int32_t r = inc - occ; r < inc; ++r) s_map[w][r] = static_cast<uint8_t>(lane);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        // rows p = lane + 64 j; the neighbour of each row is found by walking
-        // forward from the previous row's (rows only increase), and the loads
-        // of four rows are issued before any of them is used
         int b = 0;
         auto src_row = [&](int32_t p) {
+            if (use_map) {
+                const int bb = s_map[w][p];
+                return sorted[s_first[w][bb] + (p - s_pre[w][bb])];
+            }
             while (b + 1 < nc && s_pre[w][b + 1] <= p) ++b;
             return sorted[s_first[w][b] + (p - s_pre[w][b])];
         };
-        auto put = [&](int64_t d, const Row4d &v) {
-            if constexpr (MIXED)
-                d4[d] = make_float4(static_cast<float>(v.x - c[0]), static_cast<float>(v.y - c[1]),
-                                    static_cast<float>(v.z - c[2]), static_cast<float>(v.w));
-            else
-                d8[d] = v;
-        };
-        // full groups of 256 rows with no per-row condition, so the four loads
-        // and the four stores of a group are all in flight together
-        int32_t p0 = 0;
-        for (; p0 + 256 <= rows; p0 += 256) {
-            Row4d v[4];
+        // all loads of a group are issued before any of its stores; lanes
+        // past the end take the last row again and store it to its own place
+        // once more (the same bytes), so no load or store is conditional
+        for (int32_t p0 = 0; p0 < rows; p0 += 64 * kRowsPerLane) {
+            Row4d v[kRowsPerLane];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) v[u] = src_row(p0 + 64 * u + lane);
+            for (int u = 0; u < kRowsPerLane; ++u) v[u] = src_row(min(p0 + 64 * u + lane, rows - 1));
 #pragma unroll
-            for (int u = 0; u < 4; ++u) put(out + p0 + 64 * u + lane, v[u]);
+            for (int u = 0; u < kRowsPerLane; ++u) {
+                const int64_t d = out + min(p0 + 64 * u + lane, rows - 1);
+                if constexpr (MIXED)
+                    stream_store(d4 + d, make_float4(static_cast<float>(v[u].x - c[0]),
+                                                     static_cast<float>(v[u].y - c[1]),
+                                                     static_cast<float>(v[u].z - c[2]),
+                                                     static_cast<float>(v[u].w)));
+                else
+                    stream_store(d8 + d, v[u]);
+            }
         }
-        for (int32_t p = p0 + lane; p < rows; p += 64) put(out + p, src_row(p));
         out += rows;
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
     }
 }
 
-// Rows of row_len elements (Helmholtz right-hand sides): one wave per row,
-// lanes across the row.
-template <class T>
-__global__ __launch_bounds__(kCopyBlock) void k_copy_segments_rows(
-    const T *__restrict__ sorted, int row_len, const int32_t *__restrict__ leaf_start,
+// Rows of upr units (Helmholtz right-hand sides): one workgroup per target
+// leaf.  The rows of one neighbour are contiguous in sorted order, so a segment
+// is a concatenation of runs; in unit space, unit u of the chunk belongs to
+// the run b with s_pre[b] * upr <= u, and its source is u shifted by that
+// run's (first - pre) * upr.  Threads take units tid, tid + 256, ...; each
+// walks its run index forward (units only increase) and issues UN loads before
+// its UN stores, none of them under a condition.
+template <class U, int UN>
+__global__ __launch_bounds__(kCopyBlock) void k_copy_segments_units(
+    const U *__restrict__ sorted, int64_t upr, const int32_t *__restrict__ leaf_start,
     const int64_t *__restrict__ nbr_start, const int32_t *__restrict__ nbr_idx,
-    const int64_t *__restrict__ red_start, T *__restrict__ dst) {
+    const int64_t *__restrict__ red_start, int64_t L, U *__restrict__ dst) {
     __shared__ int64_t s_pre[kCopyNbrChunk + 1];
     __shared__ int32_t s_first[kCopyNbrChunk];
     __shared__ int64_t s_w[kCopyBlock / 64];
-    const int64_t A = blockIdx.x;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t A = p2pd::xcd_contiguous(blockIdx.x, gridDim.x);
+    if (A >= L) return;
     const int64_t e0 = nbr_start[A], e1 = nbr_start[A + 1];
     int64_t out = red_start[A];
     for (int64_t c0 = e0; c0 < e1; c0 += kCopyNbrChunk) {
         const int nc = static_cast<int>(min<int64_t>(kCopyNbrChunk, e1 - c0));
         const int64_t rows = load_nbr_chunk(leaf_start, nbr_idx, c0, nc, s_pre, s_first, s_w);
-        if (row_len == 1) {
-            for (int64_t p = threadIdx.x; p < rows; p += kCopyBlock) {
-                const int b = find_nbr(s_pre, nc, p);
-                dst[out + p] = sorted[s_first[b] + (p - s_pre[b])];
+        const int64_t units = rows * upr;
+        U *__restrict__ d = dst + out * upr;
+        int b = 0;
+        int64_t next = (nc > 1) ? s_pre[1] * upr : units;    // first unit of run b + 1
+        int64_t shift = (static_cast<int64_t>(s_first[0]) - s_pre[0]) * upr;
+        for (int64_t u0 = threadIdx.x; u0 < units; u0 += kCopyBlock * UN) {
+            // units past the end repeat the last unit (same bytes, same place)
+            U v[UN];
+#pragma unroll
+            for (int k = 0; k < UN; ++k) {
+                const int64_t u = min(u0 + kCopyBlock * k, units - 1);
+                while (u >= next) {
+                    ++b;
+                    next = (b + 1 < nc) ? s_pre[b + 1] * upr : units;
+                    shift = (static_cast<int64_t>(s_first[b]) - s_pre[b]) * upr;
+                }
+                v[k] = sorted[u + shift];
             }
-        } else {
-            for (int64_t p = w; p < rows; p += kCopyBlock / 64) {
-                const int b = find_nbr(s_pre, nc, p);
-                const int64_t src = (s_first[b] + (p - s_pre[b])) * static_cast<int64_t>(row_len);
-                const int64_t d = (out + p) * static_cast<int64_t>(row_len);
-                for (int r = lane; r < row_len; r += 64) dst[d + r] = sorted[src + r];
-            }
+#pragma unroll
+            for (int k = 0; k < UN; ++k) stream_store(d + min(u0 + kCopyBlock * k, units - 1), v[k]);
         }
         out += rows;
         __syncthreads();
@@ -220,30 +282,70 @@ __global__ __launch_bounds__(kCopyBlock) void k_copy_segments_rows(
 }  // namespace
 
 p2p_status launch_seg_lengths(const int32_t *leaf_start, const int64_t *nbr_start,
-                              const int32_t *nbr_idx, int64_t L, int64_t *seg_len,
+                              const int32_t *nbr_idx, int64_t L, int32_t *seg_len,
                               int32_t *red_self, hipStream_t s) {
     if (L <= 0) return P2P_OK;
-    k_seg_lengths<<<grid_for(L, 256), 256, 0, s>>>(leaf_start, nbr_start, nbr_idx, L, seg_len,
-                                                  red_self);
+    k_seg_lengths<<<grid_for(L * kSegLanes, 256), 256, 0, s>>>(leaf_start, nbr_start, nbr_idx, L, seg_len,
+                                                                red_self);
     P2P_LAUNCH_CHECK();
     return P2P_OK;
 }
+
+namespace {
+
+// Widest unit (16, 8 or 4 bytes) that divides a row of `row_bytes`.
+int unit_bytes(int64_t row_bytes) {
+    return (row_bytes % 16 == 0) ? 16 : (row_bytes % 8 == 0) ? 8 : 4;
+}
+
+template <class U>
+p2p_status permute_units(const void *src, const int32_t *perm, int64_t n, int64_t row_bytes,
+                         void *dst, hipStream_t s) {
+    constexpr int UN = 4;
+    const uint64_t upr = static_cast<uint64_t>(row_bytes) / sizeof(U);
+    const uint64_t units = static_cast<uint64_t>(n) * upr;
+    const uint64_t blocks = (units + 256 * UN - 1) / (256 * UN);
+    // 32-bit unit indices while they fit (with room for the last block's overshoot)
+    if (units + 256 * UN < (uint64_t(1) << 32))
+        k_permute_units<U, UN, uint32_t><<<static_cast<unsigned>(blocks), 256, 0, s>>>(
+            static_cast<const U *>(src), perm, static_cast<uint32_t>(units),
+            static_cast<uint32_t>(upr), static_cast<U *>(dst));
+    else
+        k_permute_units<U, UN, uint64_t><<<static_cast<unsigned>(blocks), 256, 0, s>>>(
+            static_cast<const U *>(src), perm, units, upr, static_cast<U *>(dst));
+    P2P_LAUNCH_CHECK();
+    return P2P_OK;
+}
+
+template <class U>
+p2p_status copy_units(const void *sorted, int64_t row_bytes, const int32_t *leaf_start,
+                      const int64_t *nbr_start, const int32_t *nbr_idx, const int64_t *red_start,
+                      int64_t L, void *dst, hipStream_t s) {
+    k_copy_segments_units<U, 4><<<static_cast<unsigned>(L), kCopyBlock, 0, s>>>(
+        static_cast<const U *>(sorted), row_bytes / static_cast<int64_t>(sizeof(U)), leaf_start,
+        nbr_start, nbr_idx, red_start, L, static_cast<U *>(dst));
+    P2P_LAUNCH_CHECK();
+    return P2P_OK;
+}
+
+}  // namespace
 
 template <class T>
 p2p_status launch_permute_rows(const T *src, const int32_t *perm, int64_t n, int64_t row_len,
                                T *dst, hipStream_t s) {
     if (n <= 0) return P2P_OK;
-    const int64_t threads = (row_len == 1) ? n : n * 64;
-    k_permute_rows<T><<<grid_for(threads, 256), 256, 0, s>>>(src, perm, n,
-                                                            static_cast<int>(row_len), dst);
-    P2P_LAUNCH_CHECK();
-    return P2P_OK;
+    const int64_t rb = row_len * static_cast<int64_t>(sizeof(T));
+    switch (unit_bytes(rb)) {
+    case 16: return permute_units<uint4>(src, perm, n, rb, dst, s);
+    case 8: return permute_units<uint2>(src, perm, n, rb, dst, s);
+    default: return permute_units<uint32_t>(src, perm, n, rb, dst, s);
+    }
 }
 
-p2p_status launch_permute4(const double *a, const double *b, const double *c, const double *d,
-                           const int32_t *perm, int64_t n, Row4d *out, hipStream_t s) {
+p2p_status launch_scatter4(const double *a, const double *b, const double *c, const double *d,
+                           const int32_t *iperm, int64_t n, Row4d *out, hipStream_t s) {
     if (n <= 0) return P2P_OK;
-    k_permute4<<<grid_for(n, 256), 256, 0, s>>>(a, b, c, d, perm, n, out);
+    k_scatter4<<<grid_for(n, 256), 256, 0, s>>>(a, b, c, d, iperm, n, out);
     P2P_LAUNCH_CHECK();
     return P2P_OK;
 }
@@ -270,10 +372,13 @@ p2p_status launch_copy_segments(const T *sorted, int64_t row_len, const int32_t 
                                 const int64_t *nbr_start, const int32_t *nbr_idx,
                                 const int64_t *red_start, int64_t L, T *dst, hipStream_t s) {
     if (L <= 0) return P2P_OK;
-    k_copy_segments_rows<T><<<static_cast<unsigned>(L), kCopyBlock, 0, s>>>(
-        sorted, static_cast<int>(row_len), leaf_start, nbr_start, nbr_idx, red_start, dst);
-    P2P_LAUNCH_CHECK();
-    return P2P_OK;
+    const int64_t rb = row_len * static_cast<int64_t>(sizeof(T));
+    switch (unit_bytes(rb)) {
+    case 16: return copy_units<uint4>(sorted, rb, leaf_start, nbr_start, nbr_idx, red_start, L, dst, s);
+    case 8: return copy_units<uint2>(sorted, rb, leaf_start, nbr_start, nbr_idx, red_start, L, dst, s);
+    default:
+        return copy_units<uint32_t>(sorted, rb, leaf_start, nbr_start, nbr_idx, red_start, L, dst, s);
+    }
 }
 
 template p2p_status launch_permute_rows<double>(const double *, const int32_t *, int64_t, int64_t,

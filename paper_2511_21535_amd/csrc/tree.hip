@@ -149,7 +149,26 @@ __global__ __launch_bounds__(1024) void k_max_level(const int8_t *__restrict__ l
     }
 }
 
+// perm[s] = caller index of sorted slot s, and its inverse.
+__global__ void k_perm_and_inverse(const int32_t *__restrict__ vals, int64_t n,
+                                   int32_t *__restrict__ perm, int32_t *__restrict__ iperm) {
+    const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int32_t i = vals[s];
+    perm[s] = i;
+    iperm[i] = static_cast<int32_t>(s);
+}
+
 }  // namespace
+
+p2p_status launch_perm_and_inverse(const int32_t *vals, int64_t n, int32_t *perm, int32_t *iperm,
+                                   hipStream_t s) {
+    if (n <= 0) return P2P_OK;
+    k_perm_and_inverse<<<grid_for(n, 256), 256, 0, s>>>(vals, n, perm, iperm);
+    P2P_LAUNCH_CHECK();
+    return P2P_OK;
+}
+
 
 p2p_status launch_particle_keys(const double *x, const double *y, const double *z, int64_t n,
                                 uint64_t *keys, int32_t *vals, int32_t *bad_flag, hipStream_t s) {

@@ -79,7 +79,7 @@ def test_build_tree_rejects_bad_grids(lib):
 
 def test_eval_rejects_bad_modes(lib):
     t = _tree(10, L_=1)
-    t.perm = t.leaf_start = t.leaf_key = t.leaf_level = 0x1000
+    t.perm = t.iperm = t.leaf_start = t.leaf_key = t.leaf_level = 0x1000
     n = L.p2p_nbrs()
     n.count, n.nbr_start, n.nbr_idx = 1, 0x1000, 0x1000
     nb = ctypes.c_size_t(0)
@@ -103,7 +103,7 @@ def test_eval_rejects_bad_modes(lib):
 
 def test_adjoint_unsupported_combinations(lib):
     t = _tree(10, L_=1)
-    t.perm = t.leaf_start = t.leaf_key = t.leaf_level = 0x1000
+    t.perm = t.iperm = t.leaf_start = t.leaf_key = t.leaf_level = 0x1000
     n = L.p2p_nbrs()
     n.count, n.nbr_start, n.nbr_idx = 1, 0x1000, 0x1000
     nb = ctypes.c_size_t(0)

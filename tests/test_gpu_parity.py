@@ -6,6 +6,8 @@ and <= 1e-5 for FP32 / FP32-mixed (phi; a as one 3N vector; u as one complex
 N*R vector).  Full-size workloads are checked on sampled leaves, which the
 oracle computes one by one.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -35,6 +37,8 @@ def _rel(a, b):
 
 def _check_tree(gt, ot):
     np.testing.assert_array_equal(_n(gt.perm), ot.perm)
+    # iperm is the inverse of perm
+    np.testing.assert_array_equal(_n(gt.iperm)[ot.perm], np.arange(len(ot.perm), dtype=np.int32))
     np.testing.assert_array_equal(_n(gt.leaf_start), ot.leaf_start)
     np.testing.assert_array_equal(_n(gt.leaf_key).view(np.uint64), ot.leaf_key)
     np.testing.assert_array_equal(_n(gt.leaf_level), ot.leaf_level)
@@ -72,8 +76,15 @@ def test_tree_neighbors_restructure_bit_exact(gen, n, seed, depth, cap):
     np.testing.assert_array_equal(_n(gn.nbr_start), os_)
     np.testing.assert_array_equal(_n(gn.nbr_idx), oi)
     rs, rself, S = oracle.red_offsets(ot, os_, oi)
+    assert gn.red_entries == S
+    # lists without the layout size: the restructure counts S itself
+    gn_unknown = dataclasses.replace(gn, red_entries=-1)
     for prec in ("fp64", "fp32"):
         red = api.restructure_gravity(gt, gn, gx, gy, gz, gm, prec=prec)
+        red_u = api.restructure_gravity(gt, gn_unknown, gx, gy, gz, gm, prec=prec)
+        assert red_u.count == S
+        np.testing.assert_array_equal(_n(red_u.red_start), rs)
+        np.testing.assert_array_equal(_n(red_u.planes[0])[:S], _n(red.planes[0])[:S])
         assert red.count == S
         np.testing.assert_array_equal(_n(red.red_start), rs)
         np.testing.assert_array_equal(_n(red.red_self), rself)
@@ -193,6 +204,7 @@ def test_grid_tree_bit_exact(sides):
     os_, oi = oracle.neighbors(ot)
     np.testing.assert_array_equal(_n(gn.nbr_start), os_)
     np.testing.assert_array_equal(_n(gn.nbr_idx), oi)
+    assert gn.red_entries == oracle.red_offsets(ot, os_, oi)[2]
 
 
 @pytest.mark.parametrize("sides,nrhs", [([16], 1), ([20], 1), ([12, 8, 16], 1), ([16], 3)])
