@@ -66,14 +66,15 @@ def parse():
     ap.add_argument("--cpu-leaves", type=int, default=0,
                     help="target leaves in the CPU oracle sample (0 = all)")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="only run a plain device copy of 1 GiB (3 times), the reference for "
-                         "scaling the FETCH_SIZE / WRITE_SIZE counters")
+                    help="only run plain device copies of 1 GiB, the reference for scaling the "
+                         "FETCH_SIZE / WRITE_SIZE counters, and print the copy and fill rates")
     return ap.parse_args()
 
 
 def copy_calibration():
-    """Plain device-to-device copy of 2^30 bytes, three times, for counter
-    scaling; also the copy and fill rates of that size (HIP events)."""
+    """Plain device-to-device copies of 2^30 bytes (3, then 5 timed), the
+    reference for scaling the FETCH_SIZE / WRITE_SIZE counters; also the copy
+    and fill rates of that size (HIP events)."""
     import torch
     a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)

@@ -303,6 +303,8 @@ extern "C" p2p_status p2p_restructure_redundant(const p2p_tree *tree, const p2p_
         return fail(P2P_EINVAL, "out->planes must not be NULL");
     P2P_TRY(launch_seg_lengths(tree->leaf_start, nbrs->nbr_start, nbrs->nbr_idx, L, seg_len, out->red_self, s));
     P2P_TRY((exclusive_scan<int32_t, int64_t>(seg_len, out->red_start, L, scan_tmp, s)));
+    const int64_t entry_bytes = grav ? (mixed ? 16 : 32) : static_cast<int64_t>(nrhs) * static_cast<int64_t>(csize);
+    const bool streaming = S * entry_bytes > kStreamingLayoutBytes;
     if (grav) {
         P2P_TRY(launch_scatter4(static_cast<const double *>(src[0]), static_cast<const double *>(src[1]),
                                 static_cast<const double *>(src[2]), static_cast<const double *>(src[3]),
@@ -310,19 +312,20 @@ extern "C" p2p_status p2p_restructure_redundant(const p2p_tree *tree, const p2p_
         P2P_TRY(launch_copy_segments_gravity(s4, tree->leaf_key, tree->leaf_level, tree->leaf_start,
                                              nbrs->nbr_start, nbrs->nbr_idx, out->red_start, L,
                                              mixed ? nullptr : static_cast<Row4d *>(out->planes[0]),
-                                             mixed ? static_cast<float4 *>(out->planes[0]) : nullptr, s));
+                                             mixed ? static_cast<float4 *>(out->planes[0]) : nullptr,
+                                             streaming, s));
     } else if (mixed) {
         P2P_TRY(launch_permute_rows<float2>(static_cast<const float2 *>(src[0]), tree->perm, n, nrhs,
                                             static_cast<float2 *>(sq), s));
         P2P_TRY(launch_copy_segments<float2>(static_cast<const float2 *>(sq), nrhs, tree->leaf_start,
                                              nbrs->nbr_start, nbrs->nbr_idx, out->red_start, L,
-                                             static_cast<float2 *>(out->planes[0]), s));
+                                             static_cast<float2 *>(out->planes[0]), streaming, s));
     } else {
         P2P_TRY(launch_permute_rows<double2>(static_cast<const double2 *>(src[0]), tree->perm, n, nrhs,
                                              static_cast<double2 *>(sq), s));
         P2P_TRY(launch_copy_segments<double2>(static_cast<const double2 *>(sq), nrhs, tree->leaf_start,
                                               nbrs->nbr_start, nbrs->nbr_idx, out->red_start, L,
-                                              static_cast<double2 *>(out->planes[0]), s));
+                                              static_cast<double2 *>(out->planes[0]), streaming, s));
     }
     out->count = S;
     out->nrhs = nrhs;

@@ -117,11 +117,15 @@ p2p_status launch_copy_segments_gravity(const Row4d *sorted, const uint64_t *lea
                                         const int8_t *leaf_level, const int32_t *leaf_start,
                                         const int64_t *nbr_start, const int32_t *nbr_idx,
                                         const int64_t *red_start, int64_t L, Row4d *d8,
-                                        float4 *d4, hipStream_t s);
+                                        float4 *d4, bool streaming, hipStream_t s);
 template <class T>
 p2p_status launch_copy_segments(const T *sorted, int64_t row_len, const int32_t *leaf_start,
                                 const int64_t *nbr_start, const int32_t *nbr_idx,
-                                const int64_t *red_start, int64_t L, T *dst, hipStream_t s);
+                                const int64_t *red_start, int64_t L, T *dst, bool streaming,
+                                hipStream_t s);
+// Redundant layouts larger than this are written with streaming (nontemporal)
+// stores; smaller ones stay in the 256 MB last-level cache for the evaluation.
+constexpr int64_t kStreamingLayoutBytes = int64_t(128) << 20;
 
 // Gravity (gravity.hip).
 struct GravityArgs {

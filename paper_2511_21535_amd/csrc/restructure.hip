@@ -11,9 +11,11 @@
 namespace p2p {
 namespace {
 
-// Streaming stores for the redundant segments: written once here and read
-// once by the evaluation much later, so they are kept from displacing the
-// sorted source rows (re-read by about 27 target leaves each) in L2.
+// Streaming stores for the redundant segments of a large layout: written once
+// here and read once by the evaluation, so they are kept from displacing the
+// sorted source rows (re-read by about 27 target leaves each) in L2.  A layout
+// that fits the last-level cache is stored normally, where the evaluation
+// finds it.
 typedef float nt_f4 __attribute__((ext_vector_type(4)));
 typedef double nt_d2 __attribute__((ext_vector_type(2)));
 typedef uint32_t nt_u4 __attribute__((ext_vector_type(4)));
@@ -37,6 +39,14 @@ __device__ inline void stream_store(uint2 *d, const uint2 &v) {
     __builtin_nontemporal_store(t, reinterpret_cast<nt_u2 *>(d));
 }
 __device__ inline void stream_store(uint32_t *d, const uint32_t &v) { __builtin_nontemporal_store(v, d); }
+
+template <bool NT, class T>
+__device__ inline void put_row(T *d, const T &v) {
+    if constexpr (NT)
+        stream_store(d, v);
+    else
+        *d = v;
+}
 
 // Segment length of every target leaf A (the points of the leaves in nbr(A))
 // and the offset of A's own rows in it (the points of the neighbours listed
@@ -151,7 +161,7 @@ __device__ int64_t load_nbr_chunk(const int32_t *__restrict__ leaf_start,
 constexpr int kMapRows = 4096;
 constexpr int kRowsPerLane = 8;
 
-template <bool MIXED>
+template <bool MIXED, bool NT>
 __global__ __launch_bounds__(256) void k_copy_segments_grav(
     const Row4d *__restrict__ sorted, const uint64_t *__restrict__ leaf_key,
     const int8_t *__restrict__ leaf_level, const int32_t *__restrict__ leaf_start,
@@ -217,12 +227,12 @@ __global__ __launch_bounds__(256) void k_copy_segments_grav(
             for (int u = 0; u < kRowsPerLane; ++u) {
                 const int64_t d = out + min(p0 + 64 * u + lane, rows - 1);
                 if constexpr (MIXED)
-                    stream_store(d4 + d, make_float4(static_cast<float>(v[u].x - c[0]),
+                    put_row<NT>(d4 + d, make_float4(static_cast<float>(v[u].x - c[0]),
                                                      static_cast<float>(v[u].y - c[1]),
                                                      static_cast<float>(v[u].z - c[2]),
                                                      static_cast<float>(v[u].w)));
                 else
-                    stream_store(d8 + d, v[u]);
+                    put_row<NT>(d8 + d, v[u]);
             }
         }
         out += rows;
@@ -238,7 +248,7 @@ __global__ __launch_bounds__(256) void k_copy_segments_grav(
 // run's (first - pre) * upr.  Threads take units tid, tid + 256, ...; each
 // walks its run index forward (units only increase) and issues UN loads before
 // its UN stores, none of them under a condition.
-template <class U, int UN>
+template <class U, int UN, bool NT>
 __global__ __launch_bounds__(kCopyBlock) void k_copy_segments_units(
     const U *__restrict__ sorted, int64_t upr, const int32_t *__restrict__ leaf_start,
     const int64_t *__restrict__ nbr_start, const int32_t *__restrict__ nbr_idx,
@@ -272,7 +282,7 @@ __global__ __launch_bounds__(kCopyBlock) void k_copy_segments_units(
                 v[k] = sorted[u + shift];
             }
 #pragma unroll
-            for (int k = 0; k < UN; ++k) stream_store(d + min(u0 + kCopyBlock * k, units - 1), v[k]);
+            for (int k = 0; k < UN; ++k) put_row<NT>(d + min(u0 + kCopyBlock * k, units - 1), v[k]);
         }
         out += rows;
         __syncthreads();
@@ -320,10 +330,16 @@ p2p_status permute_units(const void *src, const int32_t *perm, int64_t n, int64_
 template <class U>
 p2p_status copy_units(const void *sorted, int64_t row_bytes, const int32_t *leaf_start,
                       const int64_t *nbr_start, const int32_t *nbr_idx, const int64_t *red_start,
-                      int64_t L, void *dst, hipStream_t s) {
-    k_copy_segments_units<U, 4><<<static_cast<unsigned>(L), kCopyBlock, 0, s>>>(
-        static_cast<const U *>(sorted), row_bytes / static_cast<int64_t>(sizeof(U)), leaf_start,
-        nbr_start, nbr_idx, red_start, L, static_cast<U *>(dst));
+                      int64_t L, void *dst, bool streaming, hipStream_t s) {
+    const int64_t upr = row_bytes / static_cast<int64_t>(sizeof(U));
+    if (streaming)
+        k_copy_segments_units<U, 4, true><<<static_cast<unsigned>(L), kCopyBlock, 0, s>>>(
+            static_cast<const U *>(sorted), upr, leaf_start, nbr_start, nbr_idx, red_start, L,
+            static_cast<U *>(dst));
+    else
+        k_copy_segments_units<U, 4, false><<<static_cast<unsigned>(L), kCopyBlock, 0, s>>>(
+            static_cast<const U *>(sorted), upr, leaf_start, nbr_start, nbr_idx, red_start, L,
+            static_cast<U *>(dst));
     P2P_LAUNCH_CHECK();
     return P2P_OK;
 }
@@ -354,15 +370,18 @@ p2p_status launch_copy_segments_gravity(const Row4d *sorted, const uint64_t *lea
                                         const int8_t *leaf_level, const int32_t *leaf_start,
                                         const int64_t *nbr_start, const int32_t *nbr_idx,
                                         const int64_t *red_start, int64_t L, Row4d *d8,
-                                        float4 *d4, hipStream_t s) {
+                                        float4 *d4, bool streaming, hipStream_t s) {
     if (L <= 0) return P2P_OK;
     const unsigned g = grid_for(L, 4);
-    if (d4)
-        k_copy_segments_grav<true><<<g, 256, 0, s>>>(sorted, leaf_key, leaf_level, leaf_start, nbr_start,
-                                                     nbr_idx, red_start, L, d8, d4);
-    else
-        k_copy_segments_grav<false><<<g, 256, 0, s>>>(sorted, leaf_key, leaf_level, leaf_start, nbr_start,
-                                                      nbr_idx, red_start, L, d8, d4);
+#define P2P_COPY_GRAV(M, NT)                                                                         \
+    k_copy_segments_grav<M, NT><<<g, 256, 0, s>>>(sorted, leaf_key, leaf_level, leaf_start, nbr_start, \
+                                                  nbr_idx, red_start, L, d8, d4)
+    if (d4) {
+        if (streaming) P2P_COPY_GRAV(true, true); else P2P_COPY_GRAV(true, false);
+    } else {
+        if (streaming) P2P_COPY_GRAV(false, true); else P2P_COPY_GRAV(false, false);
+    }
+#undef P2P_COPY_GRAV
     P2P_LAUNCH_CHECK();
     return P2P_OK;
 }
@@ -370,14 +389,18 @@ p2p_status launch_copy_segments_gravity(const Row4d *sorted, const uint64_t *lea
 template <class T>
 p2p_status launch_copy_segments(const T *sorted, int64_t row_len, const int32_t *leaf_start,
                                 const int64_t *nbr_start, const int32_t *nbr_idx,
-                                const int64_t *red_start, int64_t L, T *dst, hipStream_t s) {
+                                const int64_t *red_start, int64_t L, T *dst, bool streaming,
+                                hipStream_t s) {
     if (L <= 0) return P2P_OK;
     const int64_t rb = row_len * static_cast<int64_t>(sizeof(T));
     switch (unit_bytes(rb)) {
-    case 16: return copy_units<uint4>(sorted, rb, leaf_start, nbr_start, nbr_idx, red_start, L, dst, s);
-    case 8: return copy_units<uint2>(sorted, rb, leaf_start, nbr_start, nbr_idx, red_start, L, dst, s);
+    case 16:
+        return copy_units<uint4>(sorted, rb, leaf_start, nbr_start, nbr_idx, red_start, L, dst, streaming, s);
+    case 8:
+        return copy_units<uint2>(sorted, rb, leaf_start, nbr_start, nbr_idx, red_start, L, dst, streaming, s);
     default:
-        return copy_units<uint32_t>(sorted, rb, leaf_start, nbr_start, nbr_idx, red_start, L, dst, s);
+        return copy_units<uint32_t>(sorted, rb, leaf_start, nbr_start, nbr_idx, red_start, L, dst, streaming,
+                                    s);
     }
 }
 
@@ -389,15 +412,15 @@ template p2p_status launch_permute_rows<double2>(const double2 *, const int32_t 
                                                  double2 *, hipStream_t);
 template p2p_status launch_copy_segments<double>(const double *, int64_t, const int32_t *,
                                                  const int64_t *, const int32_t *, const int64_t *,
-                                                 int64_t, double *, hipStream_t);
+                                                 int64_t, double *, bool, hipStream_t);
 template p2p_status launch_copy_segments<float>(const float *, int64_t, const int32_t *,
                                                 const int64_t *, const int32_t *, const int64_t *,
-                                                int64_t, float *, hipStream_t);
+                                                int64_t, float *, bool, hipStream_t);
 template p2p_status launch_copy_segments<float2>(const float2 *, int64_t, const int32_t *,
                                                  const int64_t *, const int32_t *, const int64_t *,
-                                                 int64_t, float2 *, hipStream_t);
+                                                 int64_t, float2 *, bool, hipStream_t);
 template p2p_status launch_copy_segments<double2>(const double2 *, int64_t, const int32_t *,
                                                   const int64_t *, const int32_t *, const int64_t *,
-                                                  int64_t, double2 *, hipStream_t);
+                                                  int64_t, double2 *, bool, hipStream_t);
 
 }  // namespace p2p
