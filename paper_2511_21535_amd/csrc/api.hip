@@ -220,31 +220,33 @@ extern "C" p2p_status p2p_build_neighbors(const p2p_tree *tree, p2p_nbrs *nbrs, 
     int32_t *dir = ar.take<int32_t>((size_t(1) << neighbor_dir_bits(total_bits)) + 1);
     int32_t *segs = ar.take<int32_t>(L);
     int64_t *seg_scan = ar.take<int64_t>(L + 1);
+    int32_t *slots = ar.take<int32_t>(static_cast<size_t>(L) * kNbrSlotsPerLeaf);
+    int32_t *overflow = ar.take<int32_t>(1);
+    int64_t *totals = ar.take<int64_t>(3);
     p2p_status st;
     if (ws_query(ws, ws_bytes, ar, &st)) return st;
     if (!nbrs->nbr_start) return fail(P2P_EINVAL, "nbrs->nbr_start must not be NULL");
     hipStream_t s = as_stream(stream);
     const int inst_shift = 3 * tree->key_bits;
-    P2P_TRY(launch_key_directory(tree->leaf_key, L, total_bits, dir, s));
-    P2P_TRY(launch_neighbors(tree->leaf_key, tree->leaf_level, L, tree->key_bits, inst_shift, dir,
-                             total_bits, nullptr, counts, nullptr, tree->leaf_start, segs, s));
+    P2P_TRY(launch_key_directory(tree->leaf_key, L, total_bits, dir, overflow, s));
+    P2P_TRY(launch_neighbors_count(tree->leaf_key, tree->leaf_level, L, tree->key_bits, inst_shift, dir,
+                                   total_bits, tree->leaf_start, counts, segs, slots, overflow, s));
     P2P_TRY((exclusive_scan<int32_t, int64_t>(counts, start, L, scan_tmp, s)));
     P2P_TRY((exclusive_scan<int32_t, int64_t>(segs, seg_scan, L, scan_tmp, s)));
-    int64_t E = 0, S = 0;
-    if (L > 0) {
-        P2P_HIP(hipMemcpyAsync(&E, &start[L], sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        P2P_HIP(hipMemcpyAsync(&S, &seg_scan[L], sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    }
+    P2P_TRY(launch_nbr_totals(start, seg_scan, overflow, L, totals, s));
+    int64_t host[3] = {0, 0, 0};
+    P2P_HIP(hipMemcpyAsync(host, totals, sizeof(host), hipMemcpyDeviceToHost, s));
     P2P_HIP(hipStreamSynchronize(s));
-    nbrs->red_entries = S;
+    const int64_t E = host[0];
+    nbrs->red_entries = host[1];
     if (E > nbrs->cap) {
         nbrs->count = E;
         return fail(P2P_ECAPACITY, "nbrs->cap " + std::to_string(nbrs->cap) + " < " + std::to_string(E) + " entries");
     }
     if (E > 0 && !nbrs->nbr_idx) return fail(P2P_EINVAL, "nbrs->nbr_idx must not be NULL");
     P2P_HIP(hipMemcpyAsync(nbrs->nbr_start, start, (L + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
-    P2P_TRY(launch_neighbors(tree->leaf_key, tree->leaf_level, L, tree->key_bits, inst_shift, dir,
-                             total_bits, nbrs->nbr_start, nullptr, nbrs->nbr_idx, nullptr, nullptr, s));
+    P2P_TRY(launch_neighbors_fill(tree->leaf_key, tree->leaf_level, L, tree->key_bits, inst_shift, dir,
+                                  total_bits, counts, slots, host[2] > 0, nbrs->nbr_start, nbrs->nbr_idx, s));
     P2P_HIP(hipStreamSynchronize(s));
     nbrs->count = E;
     return P2P_OK;
@@ -301,32 +303,36 @@ extern "C" p2p_status p2p_restructure_redundant(const p2p_tree *tree, const p2p_
     }
     if (S > 0 && !out->planes[0])
         return fail(P2P_EINVAL, "out->planes must not be NULL");
+    // rows into sorted order first: the longest of the short launches, so the
+    // segment offsets below are already queued when it ends
+    if (grav)
+        P2P_TRY(launch_scatter4(static_cast<const double *>(src[0]), static_cast<const double *>(src[1]),
+                                static_cast<const double *>(src[2]), static_cast<const double *>(src[3]),
+                                tree->iperm, n, s4, s));
+    else if (mixed)
+        P2P_TRY(launch_permute_rows<float2>(static_cast<const float2 *>(src[0]), tree->perm, n, nrhs,
+                                            static_cast<float2 *>(sq), s));
+    else
+        P2P_TRY(launch_permute_rows<double2>(static_cast<const double2 *>(src[0]), tree->perm, n, nrhs,
+                                             static_cast<double2 *>(sq), s));
     P2P_TRY(launch_seg_lengths(tree->leaf_start, nbrs->nbr_start, nbrs->nbr_idx, L, seg_len, out->red_self, s));
     P2P_TRY((exclusive_scan<int32_t, int64_t>(seg_len, out->red_start, L, scan_tmp, s)));
     const int64_t entry_bytes = grav ? (mixed ? 16 : 32) : static_cast<int64_t>(nrhs) * static_cast<int64_t>(csize);
     const bool streaming = S * entry_bytes > kStreamingLayoutBytes;
-    if (grav) {
-        P2P_TRY(launch_scatter4(static_cast<const double *>(src[0]), static_cast<const double *>(src[1]),
-                                static_cast<const double *>(src[2]), static_cast<const double *>(src[3]),
-                                tree->iperm, n, s4, s));
+    if (grav)
         P2P_TRY(launch_copy_segments_gravity(s4, tree->leaf_key, tree->leaf_level, tree->leaf_start,
                                              nbrs->nbr_start, nbrs->nbr_idx, out->red_start, L,
                                              mixed ? nullptr : static_cast<Row4d *>(out->planes[0]),
                                              mixed ? static_cast<float4 *>(out->planes[0]) : nullptr,
                                              streaming, s));
-    } else if (mixed) {
-        P2P_TRY(launch_permute_rows<float2>(static_cast<const float2 *>(src[0]), tree->perm, n, nrhs,
-                                            static_cast<float2 *>(sq), s));
+    else if (mixed)
         P2P_TRY(launch_copy_segments<float2>(static_cast<const float2 *>(sq), nrhs, tree->leaf_start,
                                              nbrs->nbr_start, nbrs->nbr_idx, out->red_start, L,
                                              static_cast<float2 *>(out->planes[0]), streaming, s));
-    } else {
-        P2P_TRY(launch_permute_rows<double2>(static_cast<const double2 *>(src[0]), tree->perm, n, nrhs,
-                                             static_cast<double2 *>(sq), s));
+    else
         P2P_TRY(launch_copy_segments<double2>(static_cast<const double2 *>(sq), nrhs, tree->leaf_start,
                                               nbrs->nbr_start, nbrs->nbr_idx, out->red_start, L,
                                               static_cast<double2 *>(out->planes[0]), streaming, s));
-    }
     out->count = S;
     out->nrhs = nrhs;
     out->kind = grav ? P2P_KIND_GRAVITY : P2P_KIND_HELMHOLTZ;

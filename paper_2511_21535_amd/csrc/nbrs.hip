@@ -23,6 +23,7 @@ namespace p2p {
 namespace {
 
 constexpr int kNbrWaves = 4;
+constexpr int kNbrSlots = kNbrSlotsPerLeaf;
 
 // First index in [lo, hi) with a[i] > v (upper) or a[i] >= v (lower).
 __device__ inline int64_t bound_in(const uint64_t *__restrict__ a, int64_t lo, int64_t hi, uint64_t v,
@@ -41,10 +42,12 @@ __device__ inline int64_t dir_bound(const uint64_t *__restrict__ a, const int32_
     return bound_in(a, dir[p], dir[p + 1], v, upper);
 }
 
+// Also clears the overflow counter of the counting pass that follows.
 __global__ void k_key_directory(const uint64_t *__restrict__ leaf_key, int64_t L, int dir_bits,
-                                int shift, int32_t *__restrict__ dir) {
+                                int shift, int32_t *__restrict__ dir, int32_t *__restrict__ overflow) {
     const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t nb = (int64_t(1) << dir_bits) + 1;
+    if (p == 0) *overflow = 0;
     if (p >= nb) return;
     dir[p] = (p == nb - 1) ? static_cast<int32_t>(L)
                            : static_cast<int32_t>(bound_in(leaf_key, 0, L, static_cast<uint64_t>(p) << shift, false));
@@ -55,16 +58,25 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
+// COUNT: counts[A], segs[A], the first kNbrSlots entries of nbr(A) into
+// slots[A * kNbrSlots ...], and +1 on *overflow for a longer list.
+// FILL: nbr(A) into nbr_idx[nbr_start[A] ...], only for leaves whose list
+// did not fit its slots (counts[A] > kNbrSlots).
+enum { kNbrCount = 0, kNbrFill = 1 };
+
+template <int MODE>
 __global__ __launch_bounds__(64 * kNbrWaves) void k_neighbors(
     const uint64_t *__restrict__ leaf_key, const int8_t *__restrict__ leaf_level, int64_t L,
     int key_bits, int inst_shift, const int32_t *__restrict__ dir, int dir_bits, int dir_shift,
-    const int64_t *__restrict__ nbr_start, int32_t *__restrict__ counts, int32_t *__restrict__ nbr_idx,
-    const int32_t *__restrict__ leaf_start, int32_t *__restrict__ segs) {
+    const int32_t *__restrict__ leaf_start, int32_t *__restrict__ counts, int32_t *__restrict__ segs,
+    int32_t *__restrict__ slots, int32_t *__restrict__ overflow, const int64_t *__restrict__ nbr_start,
+    int32_t *__restrict__ nbr_idx) {
     __shared__ int32_t s_lo[kNbrWaves][32];
     __shared__ int32_t s_pre[kNbrWaves][33];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t A = static_cast<int64_t>(blockIdx.x) * kNbrWaves + w;
     if (A >= L) return;
+    if (MODE == kNbrFill && counts[A] <= kNbrSlots) return;
 
     const uint64_t kA = leaf_key[A];
     const int lA = leaf_level[A];
@@ -94,7 +106,13 @@ __global__ __launch_bounds__(64 * kNbrWaves) void k_neighbors(
                 covers = kC < leaf_key[j] + sj;   // leaf_key[j] <= kC by construction
             }
             lo = covers ? j : j + 1;
-            hi = dir_bound(leaf_key, dir, dir_bits, dir_shift, kC + sizeC, false);
+            // a covering leaf at least as large as the cell holds all of it
+            // (aligned cubes); only a cell split into smaller leaves needs
+            // the search for its end
+            if (covers && leaf_level[j] <= lA)
+                hi = j + 1;
+            else
+                hi = dir_bound(leaf_key, dir, dir_bits, dir_shift, kC + sizeC, false);
             valid = lo < hi;
         }
     }
@@ -132,7 +150,7 @@ __global__ __launch_bounds__(64 * kNbrWaves) void k_neighbors(
     wave_sync();
 
     // ---- test candidates, 64 at a time, in ascending leaf id
-    const int64_t out0 = counts ? 0 : nbr_start[A];
+    const int64_t out0 = (MODE == kNbrFill) ? nbr_start[A] : 0;
     int64_t written = 0;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     int32_t occ_sum = 0;     // points of this lane's adjacent candidates (count pass)
@@ -153,18 +171,44 @@ __global__ __launch_bounds__(64 * kNbrWaves) void k_neighbors(
             for (int d = 0; d < 3; ++d) adj = adj && (a[d] <= b[d] + sB) && (b[d] <= a[d] + sA);
         }
         const uint64_t bal = __ballot(adj);
-        if (!counts && adj) nbr_idx[out0 + written + __popcll(bal & below)] = static_cast<int32_t>(B);
-        if (counts && adj) occ_sum += leaf_start[B + 1] - leaf_start[B];
+        const int64_t pos = written + __popcll(bal & below);
+        if (MODE == kNbrFill && adj) nbr_idx[out0 + pos] = static_cast<int32_t>(B);
+        if (MODE == kNbrCount && adj) {
+            occ_sum += leaf_start[B + 1] - leaf_start[B];
+            if (pos < kNbrSlots) slots[A * kNbrSlots + pos] = static_cast<int32_t>(B);
+        }
         written += __popcll(bal);
     }
-    if (counts) {
+    if (MODE == kNbrCount) {
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) occ_sum += __shfl_xor(occ_sum, o, 64);
         if (lane == 0) {
             counts[A] = static_cast<int32_t>(written);
             segs[A] = occ_sum;
+            if (written > kNbrSlots) atomicAdd(overflow, 1);
         }
     }
+}
+
+// Slots into the CSR lists: thread (A, s) moves entry s of a list that fit.
+__global__ void k_compact_slots(const int32_t *__restrict__ counts, const int32_t *__restrict__ slots,
+                                const int64_t *__restrict__ nbr_start, int64_t L,
+                                int32_t *__restrict__ nbr_idx) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t A = t / kNbrSlots;
+    const int sidx = static_cast<int>(t % kNbrSlots);
+    if (A >= L) return;
+    const int32_t c = counts[A];
+    if (c <= kNbrSlots && sidx < c) nbr_idx[nbr_start[A] + sidx] = slots[t];
+}
+
+// The list totals E and S and the number of overflowing lists, gathered for
+// one read-back.
+__global__ void k_nbr_totals(const int64_t *__restrict__ start, const int64_t *__restrict__ seg_scan,
+                             const int32_t *__restrict__ overflow, int64_t L, int64_t *__restrict__ out) {
+    out[0] = L > 0 ? start[L] : 0;
+    out[1] = L > 0 ? seg_scan[L] : 0;
+    out[2] = *overflow;
 }
 
 }  // namespace
@@ -172,24 +216,48 @@ __global__ __launch_bounds__(64 * kNbrWaves) void k_neighbors(
 int neighbor_dir_bits(int total_key_bits) { return total_key_bits < 18 ? total_key_bits : 18; }
 
 p2p_status launch_key_directory(const uint64_t *leaf_key, int64_t L, int total_key_bits, int32_t *dir,
-                                hipStream_t s) {
+                                int32_t *overflow, hipStream_t s) {
     const int db = neighbor_dir_bits(total_key_bits);
     const int64_t nb = (int64_t(1) << db) + 1;
-    k_key_directory<<<grid_for(nb, 256), 256, 0, s>>>(leaf_key, L, db, total_key_bits - db, dir);
+    k_key_directory<<<grid_for(nb, 256), 256, 0, s>>>(leaf_key, L, db, total_key_bits - db, dir, overflow);
     P2P_LAUNCH_CHECK();
     return P2P_OK;
 }
 
-p2p_status launch_neighbors(const uint64_t *leaf_key, const int8_t *leaf_level, int64_t L,
-                            int key_bits, int inst_shift, const int32_t *dir, int total_key_bits,
-                            const int64_t *nbr_start, int32_t *counts, int32_t *nbr_idx,
-                            const int32_t *leaf_start, int32_t *segs, hipStream_t s) {
+p2p_status launch_neighbors_count(const uint64_t *leaf_key, const int8_t *leaf_level, int64_t L,
+                                  int key_bits, int inst_shift, const int32_t *dir, int total_key_bits,
+                                  const int32_t *leaf_start, int32_t *counts, int32_t *segs,
+                                  int32_t *slots, int32_t *overflow, hipStream_t s) {
     if (L <= 0) return P2P_OK;
     const int db = neighbor_dir_bits(total_key_bits);
-    k_neighbors<<<grid_for(L, kNbrWaves), 64 * kNbrWaves, 0, s>>>(
-        leaf_key, leaf_level, L, key_bits, inst_shift, dir, db, total_key_bits - db, nbr_start, counts,
-        nbr_idx, leaf_start, segs);
+    k_neighbors<kNbrCount><<<grid_for(L, kNbrWaves), 64 * kNbrWaves, 0, s>>>(
+        leaf_key, leaf_level, L, key_bits, inst_shift, dir, db, total_key_bits - db, leaf_start, counts,
+        segs, slots, overflow, nullptr, nullptr);
     P2P_LAUNCH_CHECK();
+    return P2P_OK;
+}
+
+p2p_status launch_nbr_totals(const int64_t *start, const int64_t *seg_scan, const int32_t *overflow,
+                             int64_t L, int64_t *out, hipStream_t s) {
+    k_nbr_totals<<<1, 1, 0, s>>>(start, seg_scan, overflow, L, out);
+    P2P_LAUNCH_CHECK();
+    return P2P_OK;
+}
+
+p2p_status launch_neighbors_fill(const uint64_t *leaf_key, const int8_t *leaf_level, int64_t L,
+                                 int key_bits, int inst_shift, const int32_t *dir, int total_key_bits,
+                                 const int32_t *counts, const int32_t *slots, bool any_overflow,
+                                 const int64_t *nbr_start, int32_t *nbr_idx, hipStream_t s) {
+    if (L <= 0) return P2P_OK;
+    k_compact_slots<<<grid_for(L * kNbrSlots, 256), 256, 0, s>>>(counts, slots, nbr_start, L, nbr_idx);
+    P2P_LAUNCH_CHECK();
+    if (any_overflow) {
+        const int db = neighbor_dir_bits(total_key_bits);
+        k_neighbors<kNbrFill><<<grid_for(L, kNbrWaves), 64 * kNbrWaves, 0, s>>>(
+            leaf_key, leaf_level, L, key_bits, inst_shift, dir, db, total_key_bits - db, nullptr,
+            const_cast<int32_t *>(counts), nullptr, nullptr, nullptr, nbr_start, nbr_idx);
+        P2P_LAUNCH_CHECK();
+    }
     return P2P_OK;
 }
 

@@ -93,11 +93,22 @@ p2p_status launch_leaf_write(const uint64_t *skeys, const int8_t *level, const i
 // entries), then the count pass (nbr_idx == nullptr) or the fill pass.
 int neighbor_dir_bits(int total_key_bits);
 p2p_status launch_key_directory(const uint64_t *leaf_key, int64_t L, int total_key_bits, int32_t *dir,
-                                hipStream_t s);
-p2p_status launch_neighbors(const uint64_t *leaf_key, const int8_t *leaf_level, int64_t L,
-                            int key_bits, int inst_shift, const int32_t *dir, int total_key_bits,
-                            const int64_t *nbr_start, int32_t *counts, int32_t *nbr_idx,
-                            const int32_t *leaf_start, int32_t *segs, hipStream_t s);
+                                int32_t *overflow, hipStream_t s);
+// Near lists in two passes.  The counting pass writes per-leaf counts, segment
+// lengths (points of the leaves in the list) and the first 64 entries of each
+// list into slots[L][64]; after the scan of the counts, the fill moves the
+// slots into the CSR and searches again only for the lists longer than 64.
+constexpr int kNbrSlotsPerLeaf = 64;
+p2p_status launch_neighbors_count(const uint64_t *leaf_key, const int8_t *leaf_level, int64_t L,
+                                  int key_bits, int inst_shift, const int32_t *dir, int total_key_bits,
+                                  const int32_t *leaf_start, int32_t *counts, int32_t *segs,
+                                  int32_t *slots, int32_t *overflow, hipStream_t s);
+p2p_status launch_nbr_totals(const int64_t *start, const int64_t *seg_scan, const int32_t *overflow,
+                             int64_t L, int64_t *out, hipStream_t s);
+p2p_status launch_neighbors_fill(const uint64_t *leaf_key, const int8_t *leaf_level, int64_t L,
+                                 int key_bits, int inst_shift, const int32_t *dir, int total_key_bits,
+                                 const int32_t *counts, const int32_t *slots, bool any_overflow,
+                                 const int64_t *nbr_start, int32_t *nbr_idx, hipStream_t s);
 
 // Restructure (restructure.hip).
 p2p_status launch_seg_lengths(const int32_t *leaf_start, const int64_t *nbr_start,

@@ -9,6 +9,7 @@ namespace {
 constexpr int kScanBlock = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanBlock * kScanItems;   // 2048
+constexpr int64_t kScanFusedBlocks = 4096;            // n up to 8M in two launches
 
 // Exclusive scan of one value per thread across a 256-thread block.
 // Returns the thread's exclusive prefix; *total receives the block sum.
@@ -76,11 +77,24 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_partials(TO *partial, int64
     if (threadIdx.x == 0) partial[nb] = carry;
 }
 
-template <class TI, class TO>
+// Down-sweep.  The block's offset is partial[blockIdx.x] when the partials
+// were scanned by k_scan_partials (FUSED == false); with FUSED the block sums
+// the raw block totals partial[0 .. blockIdx.x) itself (one launch fewer, for
+// grids of up to kScanFusedBlocks blocks), and partial == nullptr means a
+// single block with offset 0.
+template <class TI, class TO, bool FUSED>
 __global__ __launch_bounds__(kScanBlock) void k_scan_down(const TI *in, int64_t n,
                                                           const TO *__restrict__ partial,
                                                           int64_t nb, TO *out) {
     __shared__ TO lds[kScanBlock / 64];
+    TO off = 0, tot;
+    if (FUSED && partial) {
+        for (int64_t i = threadIdx.x; i < blockIdx.x; i += kScanBlock) off += partial[i];
+        block_exclusive_scan<TO>(off, lds, &tot);
+        off = tot;
+    } else if (!FUSED) {
+        off = partial[blockIdx.x];
+    }
     int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile + threadIdx.x * kScanItems;
     TO v[kScanItems];
     TO s = 0;
@@ -89,15 +103,17 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_down(const TI *in, int64_t 
         v[i] = (base + i < n) ? static_cast<TO>(in[base + i]) : TO(0);
         s += v[i];
     }
-    TO tot;
-    TO pre = block_exclusive_scan<TO>(s, lds, &tot) + partial[blockIdx.x];
+    TO pre = block_exclusive_scan<TO>(s, lds, &tot) + off;
     // every read of `in` by this block happened before the barrier inside the scan
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
         if (base + i < n) out[base + i] = pre;
         pre += v[i];
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = partial[nb];
+    if (threadIdx.x == 0) {
+        if (FUSED && blockIdx.x == nb - 1) out[n] = off + tot;
+        if (!FUSED && blockIdx.x == 0) out[n] = partial[nb];
+    }
 }
 
 template <class TO>
@@ -114,13 +130,24 @@ p2p_status exclusive_scan(const TI *in, TO *out, int64_t n, TO *scratch, hipStre
         P2P_LAUNCH_CHECK();
         return P2P_OK;
     }
-    int64_t nb = (n + kScanTile - 1) / kScanTile;
-    k_scan_reduce<TI, TO><<<static_cast<unsigned>(nb), kScanBlock, 0, s>>>(in, n, scratch);
-    P2P_LAUNCH_CHECK();
-    k_scan_partials<TO><<<1, kScanBlock, 0, s>>>(scratch, nb);
-    P2P_LAUNCH_CHECK();
-    k_scan_down<TI, TO><<<static_cast<unsigned>(nb), kScanBlock, 0, s>>>(in, n, scratch, nb, out);
-    P2P_LAUNCH_CHECK();
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    const unsigned g = static_cast<unsigned>(nb);
+    if (nb == 1) {
+        k_scan_down<TI, TO, true><<<1, kScanBlock, 0, s>>>(in, n, nullptr, nb, out);
+        P2P_LAUNCH_CHECK();
+    } else if (nb <= kScanFusedBlocks) {
+        k_scan_reduce<TI, TO><<<g, kScanBlock, 0, s>>>(in, n, scratch);
+        P2P_LAUNCH_CHECK();
+        k_scan_down<TI, TO, true><<<g, kScanBlock, 0, s>>>(in, n, scratch, nb, out);
+        P2P_LAUNCH_CHECK();
+    } else {
+        k_scan_reduce<TI, TO><<<g, kScanBlock, 0, s>>>(in, n, scratch);
+        P2P_LAUNCH_CHECK();
+        k_scan_partials<TO><<<1, kScanBlock, 0, s>>>(scratch, nb);
+        P2P_LAUNCH_CHECK();
+        k_scan_down<TI, TO, false><<<g, kScanBlock, 0, s>>>(in, n, scratch, nb, out);
+        P2P_LAUNCH_CHECK();
+    }
     return P2P_OK;
 }
 

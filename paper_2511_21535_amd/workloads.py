@@ -37,6 +37,23 @@ def uniform_particles(n: int, seed: int):
             np.ascontiguousarray(p[:, 2]), m.astype(np.float64))
 
 
+def slab_particles(n_slab: int, n_sparse: int, width: float, seed: int):
+    """A thin dense slab against a sparse half-space: n_slab points uniform in
+    [0.5, 0.5 + width) x [0,1)^2 and n_sparse uniform in [0, 0.5) x [0,1)^2,
+    masses uniform in [0.5,1.5]/n.  Large sparse leaves then touch hundreds of
+    small slab leaves (long near lists).
+
+    Draw order: slab x, sparse x, then y, z of all points, then masses.
+    """
+    rng = np.random.default_rng(seed)
+    n = n_slab + n_sparse
+    x = np.concatenate([0.5 + rng.random(n_slab) * width, rng.random(n_sparse) * 0.5])
+    y = rng.random(n)
+    z = rng.random(n)
+    m = rng.uniform(0.5, 1.5, n) / n
+    return x, y, z, m.astype(np.float64)
+
+
 def plummer_scale_radii(n_spheres: int = 8):
     """Scale radii a_s = 0.01 * 10**(s/(n_spheres-1)), geometric from 0.01 to 0.1."""
     s = np.arange(n_spheres, dtype=np.float64)

@@ -59,6 +59,7 @@ PARTICLE_CASES = [
     ("plummer", 5000, 9, 20, 8),
     ("plummer", 3001, 10, 20, 1),
     ("plummer", 777, 11, 6, 16),      # depth cap reached
+    ("uniform", 20000, 13, 1, 0),     # 8 leaves of ~2500 points: segments of 20000 rows, >256 targets per leaf
 ]
 
 
@@ -96,7 +97,32 @@ def test_tree_neighbors_restructure_bit_exact(gen, n, seed, depth, cap):
             np.testing.assert_array_equal(_n(red.planes[0])[:S].view(np.uint32), want.view(np.uint32))
 
 
-@pytest.mark.parametrize("gen,n,seed,depth,cap", PARTICLE_CASES[:4])
+def test_long_near_lists():
+    """Lists longer than the 64 entries the counting pass keeps per leaf."""
+    x, y, z, m = W.slab_particles(4000, 16, 5e-4, seed=12)
+    print("case slab 4000+16 cap 4", flush=True)
+    ot = oracle.build_tree_particles(x, y, z, depth=20, leaf_cap=4)
+    os_, oi = oracle.neighbors(ot)
+    assert np.diff(os_).max() > 64          # the case exercises the overflow path
+    gx, gy, gz, gm = (_t(v) for v in (x, y, z, m))
+    gt = api.Tree.build_particles(gx, gy, gz, depth=20, leaf_cap=4)
+    _check_tree(gt, ot)
+    gn = gt.neighbors()
+    np.testing.assert_array_equal(_n(gn.nbr_start), os_)
+    np.testing.assert_array_equal(_n(gn.nbr_idx), oi)
+    rs, rself, S = oracle.red_offsets(ot, os_, oi)
+    assert gn.red_entries == S
+    red = api.restructure_gravity(gt, gn, gx, gy, gz, gm, prec="fp32")
+    np.testing.assert_array_equal(_n(red.red_start), rs)
+    want = oracle.restructure_gravity_rel(ot, os_, oi, rs, x, y, z, m)
+    np.testing.assert_array_equal(_n(red.planes[0])[:S].view(np.uint32), want.view(np.uint32))
+    ref = oracle.gravity(x, y, z, m, 1e-3, ot)
+    for layout in ("gather", "redundant"):
+        o = [_n(v) for v in api.gravity(gt, gn, 1e-3, x=gx, y=gy, z=gz, m=gm, layout=layout, prec="fp32", red=red)]
+        assert _rel(o[0], ref[0]) <= TOL32 and _rel(np.stack(o[1:]), np.stack(ref[1:])) <= TOL32
+
+
+@pytest.mark.parametrize("gen,n,seed,depth,cap", PARTICLE_CASES[:4] + PARTICLE_CASES[6:])
 @pytest.mark.parametrize("eps", [1e-3, 0.0])
 def test_gravity_parity(gen, n, seed, depth, cap, eps):
     x, y, z, m = _particles_case(gen, n, seed, depth, cap)
