@@ -17,7 +17,7 @@ import torch
 
 from . import api
 
-CANDIDATES = [(w, c, r) for w in (1, 2, 4) for c in (1, 2, 4, 8) for r in (32, 64)]
+CANDIDATES = [(w, c, r) for w in (1, 2, 4) for c in (1, 2, 3, 4, 6, 8) for r in (32, 64)]
 
 
 def cache_path() -> str:

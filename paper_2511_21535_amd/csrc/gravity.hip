@@ -3,9 +3,10 @@
 //
 // One 256-thread workgroup owns one target leaf.  Leaves hold 1..64 targets
 // in an adaptive tree, so lanes are split two ways: with tc targets in the
-// current chunk, lane (t, g) = (tid % tc, tid / tc) takes target t and every
-// G-th source, G = 256 / tc, and the G partial sums of a target are reduced
-// through LDS at the end.  Sources are staged through LDS in tiles of 512:
+// current chunk, lane (t, g) = (tid % tc, tid / tc) takes target t and the
+// g-th of G = 256 / tc contiguous runs of every source tile, and the G
+// partial sums of a target are reduced through LDS at the end.  Sources are staged
+// through LDS in tiles of 512:
 //   - redundant: one contiguous segment, read with coalesced loads;
 //   - gather: the near list is walked in chunks; each staged row is located
 //     by a binary search over the prefix of neighbour occupancies.
@@ -25,8 +26,8 @@
 // difference is a float difference of small numbers; the rest of the pair
 // arithmetic is float; each lane sums at most 32 pair terms in float before
 // adding them to double accumulators.  Sources sit in LDS as float4 (x, y, z,
-// m) for FP32_MIXED and double4 for FP64, one address stream per pair, and
-// the strided source loop is unrolled by four.
+// m) for FP32_MIXED and double4 for FP64, and the source loop is unrolled by
+// four with a trip count shared by all lanes.
 #include <type_traits>
 
 #include "p2p_internal.h"
@@ -81,20 +82,22 @@ __device__ inline int g_find_nbr(const int64_t *s_pre, int nc, int64_t p) {
     return lo;
 }
 
-// Walks the sources of leaf A tile by tile, staging each tile into LDS with
-// `stage(dst_index, src_row)` and then calling `body(n_tile)`.  Must be called
-// by the whole block.
-template <bool RED, class Stage, class Body>
+// Walks the sources of leaf A tile by tile: after a barrier, `begin(n_tile)`,
+// then `stage(i, src_row)` for the tile's sources i, a barrier, and
+// `body(n_tile)`.  Must be called by the whole block.
+template <bool RED, class Begin, class Stage, class Body>
 __device__ void for_each_source_tile(int64_t A, const int64_t *__restrict__ red_start,
                                      const int64_t *__restrict__ nbr_start,
                                      const int32_t *__restrict__ nbr_idx,
                                      const int32_t *__restrict__ leaf_start, int64_t *s_pre,
-                                     int32_t *s_first, int64_t *s_w, Stage stage, Body body) {
+                                     int32_t *s_first, int64_t *s_w, Begin begin, Stage stage,
+                                     Body body) {
     if constexpr (RED) {
         const int64_t seg0 = red_start[A], ns = red_start[A + 1] - seg0;
         for (int64_t s0 = 0; s0 < ns; s0 += kGTile) {
             const int nt = static_cast<int>(min<int64_t>(kGTile, ns - s0));
             __syncthreads();
+            begin(nt);
             for (int i = threadIdx.x; i < nt; i += kGBlock) stage(i, seg0 + s0 + i);
             __syncthreads();
             body(nt);
@@ -108,6 +111,7 @@ __device__ void for_each_source_tile(int64_t A, const int64_t *__restrict__ red_
             for (int64_t s0 = 0; s0 < rows; s0 += kGTile) {
                 const int nt = static_cast<int>(min<int64_t>(kGTile, rows - s0));
                 __syncthreads();
+                begin(nt);
                 for (int i = threadIdx.x; i < nt; i += kGBlock) {
                     const int64_t p = s0 + i;
                     const int b = g_find_nbr(s_pre, nc, p);
@@ -133,11 +137,15 @@ __device__ inline void leaf_centre(uint64_t key, int level, double c[3]) {
 template <bool MIXED, bool RED, bool EPS0>
 __device__ __forceinline__ void gravity_body(const GravityArgs &a) {
     using Src = typename std::conditional<MIXED, float4, Row4d>::type;
-    __shared__ Src s_src[kGTile];
-    __shared__ double s_red[4][kGBlock];
+    // a tile of kGTile sources laid out as G runs of `pitch` entries (see
+    // below): at most kGTile + 2 kGBlock entries; the per-target reduction
+    // reuses the same memory after the last tile
+    __shared__ Src s_src[kGTile + 2 * kGBlock];
     __shared__ int64_t s_pre[kGNbrChunk + 1];
     __shared__ int32_t s_first[kGNbrChunk];
     __shared__ int64_t s_w[kGBlock / 64];
+    static_assert(sizeof(s_src) >= 4 * kGBlock * sizeof(double), "reduction does not fit");
+    double(*s_red)[kGBlock] = reinterpret_cast<double(*)[kGBlock]>(s_src);
 
     // gather: neighbouring leaves on one XCD share their sources in its L2
     const int64_t A = RED ? static_cast<int64_t>(blockIdx.x) : p2pd::xcd_contiguous(blockIdx.x, gridDim.x);
@@ -168,23 +176,47 @@ __device__ __forceinline__ void gravity_body(const GravityArgs &a) {
         }
         double p = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
 
-        auto stage = [&](int i, int64_t row) {
-            if constexpr (MIXED) {
-                if constexpr (RED) {
-                    s_src[i] = a.red4[row];
-                } else {
-                    const Row4d v = a.s4[row];
-                    s_src[i] = make_float4(static_cast<float>(v.x - c[0]), static_cast<float>(v.y - c[1]),
-                                           static_cast<float>(v.z - c[2]), static_cast<float>(v.w));
-                }
-            } else {
-                s_src[i] = a.s4[row];
+        // Tile layout: lane group g takes the contiguous run of sources
+        // [g chunk, (g + 1) chunk) of the tile, chunk = ceil(nt / G), stored
+        // at s_src[g pitch ...] with an odd pitch (chunk or chunk + 1), so the
+        // groups of one wavefront read different LDS banks.  The G chunk - nt
+        // entries past the end are zero-mass sources far away (they add exact
+        // zeros), so every lane runs the same trip count and the four reads
+        // of an unrolled step sit at fixed offsets from one address.
+        int chunk = 0, pitch = 0;
+        float inv_chunk = 0.f;
+        auto slot = [&](int i) {
+            const int q = static_cast<int>((static_cast<float>(i) + 0.5f) * inv_chunk);
+            return q * pitch + (i - q * chunk);
+        };
+        auto begin = [&](int nt) {
+            chunk = (nt + G - 1) / G;
+            pitch = chunk | 1;
+            inv_chunk = 1.0f / static_cast<float>(chunk);
+            for (int i = nt + static_cast<int>(threadIdx.x); i < G * chunk; i += kGBlock) {
+                if constexpr (MIXED)
+                    s_src[slot(i)] = make_float4(1e18f, 1e18f, 1e18f, 0.f);
+                else
+                    s_src[slot(i)] = Row4d{1e18, 1e18, 1e18, 0.0};
             }
         };
-        auto body = [&](int nt) {
+        auto stage = [&](int i, int64_t row) {
+            Src *d = s_src + slot(i);
+            if constexpr (MIXED) {
+                if constexpr (RED) {
+                    *d = a.red4[row];
+                } else {
+                    const Row4d v = a.s4[row];
+                    *d = make_float4(static_cast<float>(v.x - c[0]), static_cast<float>(v.y - c[1]),
+                                     static_cast<float>(v.z - c[2]), static_cast<float>(v.w));
+                }
+            } else {
+                *d = a.s4[row];
+            }
+        };
+        auto body = [&](int) {
             if (!active) return;
-            const int cnt = (nt > g) ? (nt - g + G - 1) / G : 0;
-            const Src *sp = s_src + g;
+            const Src *sp = s_src + g * pitch;
             if constexpr (MIXED) {
                 auto pair = [&](const float4 v, float &pf, float &xf, float &yf, float &zf) {
                     const float dx = tv.x - v.x, dy = tv.y - v.y, dz = tv.z - v.z;
@@ -198,19 +230,18 @@ __device__ __forceinline__ void gravity_body(const GravityArgs &a) {
                     yf = fmaf(-mw3, dy, yf);
                     zf = fmaf(-mw3, dz, zf);
                 };
-                for (int k0 = 0; k0 < cnt; k0 += kGFlush) {
-                    const int kk = min(kGFlush, cnt - k0);
+                for (int k0 = 0; k0 < chunk; k0 += kGFlush) {
+                    const int kk = min(kGFlush, chunk - k0);
                     float pf = 0.f, xf = 0.f, yf = 0.f, zf = 0.f;
                     int j = 0;
-                    for (; j + 4 <= kk; j += 4) {
-                        const float4 v0 = sp[0], v1 = sp[G], v2 = sp[2 * G], v3 = sp[3 * G];
+                    for (; j + 4 <= kk; j += 4, sp += 4) {
+                        const float4 v0 = sp[0], v1 = sp[1], v2 = sp[2], v3 = sp[3];
                         pair(v0, pf, xf, yf, zf);
                         pair(v1, pf, xf, yf, zf);
                         pair(v2, pf, xf, yf, zf);
                         pair(v3, pf, xf, yf, zf);
-                        sp += 4 * G;
                     }
-                    for (; j < kk; ++j, sp += G) pair(sp[0], pf, xf, yf, zf);
+                    for (; j < kk; ++j, ++sp) pair(sp[0], pf, xf, yf, zf);
                     p += pf;
                     fx += xf;
                     fy += yf;
@@ -230,19 +261,18 @@ __device__ __forceinline__ void gravity_body(const GravityArgs &a) {
                     fz = fma(-mw3, dz, fz);
                 };
                 int j = 0;
-                for (; j + 4 <= cnt; j += 4) {
-                    const Row4d v0 = sp[0], v1 = sp[G], v2 = sp[2 * G], v3 = sp[3 * G];
+                for (; j + 4 <= chunk; j += 4, sp += 4) {
+                    const Row4d v0 = sp[0], v1 = sp[1], v2 = sp[2], v3 = sp[3];
                     pair(v0);
                     pair(v1);
                     pair(v2);
                     pair(v3);
-                    sp += 4 * G;
                 }
-                for (; j < cnt; ++j, sp += G) pair(sp[0]);
+                for (; j < chunk; ++j, ++sp) pair(sp[0]);
             }
         };
         for_each_source_tile<RED>(A, a.red_start, a.nbr_start, a.nbr_idx, a.leaf_start, s_pre,
-                                  s_first, s_w, stage, body);
+                                  s_first, s_w, begin, stage, body);
 
         __syncthreads();
         s_red[0][threadIdx.x] = active ? p : 0.0;
@@ -277,7 +307,8 @@ __device__ __forceinline__ void gravity_body(const GravityArgs &a) {
 
 // The FP32-mixed redundant kernel fits in 64 VGPRs without spills, so it asks
 // for 8 waves per SIMD (more workgroups in flight hide the tile staging); the
-// other variants keep the compiler's register budget.
+// FP32-mixed gather kernel fits 72 without spills (7 waves per SIMD); the FP64
+// variants keep the compiler's register budget.
 template <bool MIXED, bool RED, bool EPS0>
 __global__ __launch_bounds__(kGBlock) void k_gravity(GravityArgs a) {
     gravity_body<MIXED, RED, EPS0>(a);
@@ -286,6 +317,11 @@ template <bool EPS0>
 __global__ __launch_bounds__(kGBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_gravity_mixed_red(
     GravityArgs a) {
     gravity_body<true, true, EPS0>(a);
+}
+template <bool EPS0>
+__global__ __launch_bounds__(kGBlock) __attribute__((amdgpu_waves_per_eu(7))) void k_gravity_mixed_gather(
+    GravityArgs a) {
+    gravity_body<true, false, EPS0>(a);
 }
 
 // Adjoint of the gravity sums, FP64, gather layout.  For target j and each
@@ -337,7 +373,7 @@ __global__ __launch_bounds__(kGBlock) void k_gravity_adjoint(GravityAdjointArgs 
             }
         };
         for_each_source_tile<false>(A, nullptr, a.nbr_start, a.nbr_idx, a.leaf_start, s_pre,
-                                    s_first, s_w, stage, body);
+                                    s_first, s_w, [](int) {}, stage, body);
         __syncthreads();
         s_red[0 * kGBlock + threadIdx.x] = active ? om : 0.0;
         s_red[1 * kGBlock + threadIdx.x] = active ? ox : 0.0;
@@ -371,7 +407,10 @@ p2p_status launch_gravity(const GravityArgs &a, bool redundant, bool mixed, bool
             if (eps_zero) k_gravity_mixed_red<true><<<g, kGBlock, 0, s>>>(a);
             else k_gravity_mixed_red<false><<<g, kGBlock, 0, s>>>(a);
         }
-        else { if (eps_zero) P2P_GRAV(true, false, true); else P2P_GRAV(true, false, false); }
+        else {
+            if (eps_zero) k_gravity_mixed_gather<true><<<g, kGBlock, 0, s>>>(a);
+            else k_gravity_mixed_gather<false><<<g, kGBlock, 0, s>>>(a);
+        }
     } else {
         if (redundant) { if (eps_zero) P2P_GRAV(false, true, true); else P2P_GRAV(false, true, false); }
         else { if (eps_zero) P2P_GRAV(false, false, true); else P2P_GRAV(false, false, false); }

@@ -206,7 +206,7 @@ struct HelmholtzMfmaArgs {
     const int32_t *inst_table; // per instance: table index
     const float *inst_scale;   // per instance: 1/h
     const int32_t *work;       // box ids in processing order (longest first)
-    int32_t *counter;          // work-queue counter (zeroed by the launcher)
+    int32_t *counter;          // work-queue counters, one per XCD range (zeroed by the launcher)
     int32_t nrhs;
     int32_t conj;
     float2 *u;                 // caller order [n][nrhs]

@@ -137,8 +137,18 @@ __global__ __launch_bounds__(1024) void k_max_level(const int8_t *__restrict__ l
                                                     int32_t *__restrict__ out) {
     __shared__ int s_m[16];
     const int64_t L = fscan[n];
+    // eight independent loads in flight per thread
+    int mm[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int64_t step = 8 * static_cast<int64_t>(blockDim.x);
+    int64_t i0 = threadIdx.x;
+    for (; i0 + 7 * static_cast<int64_t>(blockDim.x) < L; i0 += step) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) mm[k] = max(mm[k], static_cast<int>(leaf_level[i0 + k * blockDim.x]));
+    }
+    for (int64_t i = i0; i < L; i += blockDim.x) mm[0] = max(mm[0], static_cast<int>(leaf_level[i]));
     int m = 0;
-    for (int64_t i = threadIdx.x; i < L; i += blockDim.x) m = max(m, static_cast<int>(leaf_level[i]));
+#pragma unroll
+    for (int k = 0; k < 8; ++k) m = max(m, mm[k]);
     for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, 64));
     if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = m;
     __syncthreads();

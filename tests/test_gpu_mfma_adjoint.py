@@ -41,6 +41,12 @@ def test_helmholtz_mfma_parity(sides, nrhs):
     ref = oracle.helmholtz(sides, q)
     gq = _t(q)
     red = api.restructure(gt, gn, [gq], prec="fp32", nrhs=nrhs)
+    # payload bit-exact (rows of 8 nrhs bytes: the source-major copy)
+    ot = oracle.build_tree_grids(sides)
+    os_, oi = oracle.neighbors(ot)
+    rs, _, S = oracle.red_offsets(ot, os_, oi)
+    assert red.count == S
+    np.testing.assert_array_equal(_n(red.planes[0])[:S], oracle.restructure_rows(ot, os_, oi, rs, q))
     for layout in ("gather", "redundant"):
         u = _n(api.helmholtz(gt, gn, gq, layout=layout, prec="fp32", red=red))
         err = _rel(u, ref)

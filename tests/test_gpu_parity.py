@@ -233,7 +233,7 @@ def test_grid_tree_bit_exact(sides):
     assert gn.red_entries == oracle.red_offsets(ot, os_, oi)[2]
 
 
-@pytest.mark.parametrize("sides,nrhs", [([16], 1), ([20], 1), ([12, 8, 16], 1), ([16], 3)])
+@pytest.mark.parametrize("sides,nrhs", [([16], 1), ([20], 1), ([12, 8, 16], 1), ([16], 3), ([12, 8], 8)])
 def test_helmholtz_parity(sides, nrhs):
     print(f"case helmholtz sides={sides} nrhs={nrhs}", flush=True)
     gt, grids = _grid_tree(sides)
