@@ -13,6 +13,9 @@ value = pairs / (restructure + redundant evaluation), over the K timed steps.
 The line also carries the rate without the restructure, the gather rate, the
 sub-step times, the Locality metric, the roofline of the dominant kernel
 (the redundant evaluation) and the FP64 CPU oracle timed on the workload.
+Gravity lines also time the per-interaction layout (one record per near-list
+entry, results per record summed afterwards) on the same tree and lists,
+outside the timed steps.
 
 --workload selects one of the other configurations for the same measurement
 (their lines are reference measurements, not the headline):
@@ -278,6 +281,26 @@ def run_gravity(wname, args):
                                  "peak": 8000.0, "unit": "GB/s",
                                  "frac": res_bytes / (t_res / K) / 8e12, "bytes": res_bytes},
     })
+    # per-interaction layout (records per near-list entry), timed after the
+    # steps on the same tree and lists: restructure, then evaluation + update
+    inter = api.restructure_interactions(tree, nbrs, gx, gy, gz, gm, prec=prec)
+
+    def step_inter():
+        e = _events(3)
+        e[0].record()
+        api.restructure_interactions(tree, nbrs, gx, gy, gz, gm, prec=prec, out=inter)
+        e[1].record()
+        api.gravity_interactions(tree, nbrs, inter, eps, out=outs)
+        e[2].record()
+        return e
+
+    _, (t_ires, t_ieval) = _timed_steps(step_inter, K, args.warmup)
+    line["rates"].update({"interaction_incl_restructure": pairs * K / (t_ires + t_ieval),
+                          "interaction_excl_restructure": pairs * K / t_ieval})
+    line["ms"].update({"interaction_restructure": t_ires / K * 1e3, "interaction_eval": t_ieval / K * 1e3})
+    line["interaction_layout"] = {"rows": inter.count, "bytes": inter.count * bpe,
+                                  "result_rows": inter.target_rows}
+    del inter
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline_gravity(x, y, z, m, w, args.cpu_leaves)
     return line

@@ -156,6 +156,27 @@ typedef struct {
     int32_t reserved;
 } p2p_redundant;
 
+/* Per-interaction redundant layout (gravity; the thread-level redundancy of
+ * the paper's stellar-dynamics case, Sec. 5.2.1, whose data volumes Table 5
+ * compares): one record per near-list entry e = (A, B) in CSR order, rows
+ * [rec_start[e], rec_start[e+1]): a header row holding occ_A, occ_B, A and B
+ * as integers (int32 bit patterns in the four floats of an FP32_MIXED row,
+ * exact integers in the four doubles of an FP64 row), then the occ_A rows of
+ * A's points (the targets), then the occ_B rows of B's points (the sources),
+ * each in sorted order, with the payload of the box-grain layout (FP32_MIXED:
+ * float4 (x - c_A, y - c_A, z - c_A, m) relative to the centre of A; FP64:
+ * double[4] (x, y, z, m)).  Every record can be evaluated on its own; the
+ * results of the records of one target leaf are then summed (the update). */
+typedef struct {
+    int64_t cap;        /* in: capacity in rows of planes[0] */
+    int64_t count;      /* out: rows = E + sum_e (occ_A + occ_B) (also on P2P_ECAPACITY) */
+    int64_t *rec_start; /* device [E+1] */
+    void *planes[1];    /* device rows: float4 (FP32_MIXED) or double[4] (FP64) */
+    int64_t target_rows;/* out: sum_e occ_A, the result rows the evaluation needs */
+    int32_t prec;       /* out: p2p_precision of the payload */
+    int32_t reserved;
+} p2p_interactions;
+
 /* Locality metric (Definition 1, Formulas (10)-(11) of the paper). */
 typedef struct {
     double d_mean;       /* mean over target leaves of D = runs of consecutive ids in nbr(A) */
@@ -254,6 +275,27 @@ p2p_status p2p_adjoint(int32_t kind, const p2p_tree *tree, const p2p_nbrs *nbrs,
                        int32_t conjugate,
                        const void *const fwd_in[4], const void *const grad_out[4],
                        void *const grad_in[4], void *ws, size_t *ws_bytes, p2p_stream_t stream);
+
+/* Restructure to the per-interaction layout (gravity trees only): src = {x, y,
+ * z, m} caller-order double[n].  out->rec_start must hold E+1 entries.  The
+ * row count is E + 2 S for lists built by p2p_build_neighbors (the near
+ * relation is symmetric, so the targets of all records are S rows too);
+ * otherwise it is counted on the GPU and read back (synchronising `stream`).
+ * P2P_ECAPACITY (out->count = rows) if rows > out->cap. */
+p2p_status p2p_restructure_interactions(const p2p_tree *tree, const p2p_nbrs *nbrs,
+                                        const double *const src[4], p2p_precision prec,
+                                        p2p_interactions *out, void *ws, size_t *ws_bytes,
+                                        p2p_stream_t stream);
+
+/* Near-field gravity from the per-interaction layout: every record's pair sums
+ * (phi, a as in the header comment, eps >= 0, the precision of `inter`) go to
+ * result rows of their own in the workspace (target_rows x 32 bytes), then
+ * each target's results over the records of its leaf are summed in FP64 and
+ * written to phi, ax, ay, az (caller-order double[n], overwritten). */
+p2p_status p2p_eval_gravity_interactions(const p2p_tree *tree, const p2p_nbrs *nbrs,
+                                         const p2p_interactions *inter, double eps,
+                                         double *phi, double *ax, double *ay, double *az,
+                                         void *ws, size_t *ws_bytes, p2p_stream_t stream);
 
 /* Locality metric per configuration (a12; Definition 1 and Formulas (10)-(11),
  * Sec. 3.4).  D per target leaf is counted on the GPU from the near lists;

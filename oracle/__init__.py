@@ -78,6 +78,8 @@ def _declare(lib):
     lib.orc_restructure_rows.argtypes = [I64, P, P, P, P, P, P, I64, P]
     lib.orc_restructure_gravity_rel.restype = None
     lib.orc_restructure_gravity_rel.argtypes = [I64, P, P, P, P, P, P, P, P, P, P, P, P]
+    lib.orc_restructure_interactions.restype = I64
+    lib.orc_restructure_interactions.argtypes = [I64, P, P, P, P, P, P, P, P, P, P, P, P, P]
     lib.orc_gravity_leaves.restype = I64
     lib.orc_gravity_leaves.argtypes = [P, P, P, P, F64, P, P, P, I64, P, P, P, P, P, P, P]
     lib.orc_gravity_adjoint_leaves.restype = I64
@@ -258,6 +260,28 @@ def restructure_gravity_rel(tree: Tree, nbr_start, nbr_idx, red_start, x, y, z, 
                                         _p(_c(red_start, np.int64)), _p(tree.anchor), _p(tree.size),
                                         *[_p(a) for a in arrs], _p(out))
     return out[:S]
+
+
+def restructure_interactions(tree: Tree, nbr_start, nbr_idx, x, y, z, m, prec="fp64"):
+    """Per-interaction layout (Sec. 5.2.1): (rec_start [E+1], rows) with one
+    record per near-list entry (A, B): header (occ_A, occ_B, A, B), A's rows,
+    B's rows.  prec "fp64": float64 [rows, 4], header as doubles; "fp32":
+    float32 [rows, 4] relative to the centre of A, header as int32 bits."""
+    ns, ni = _c(nbr_start, np.int64), _c(nbr_idx, np.int32)
+    E = int(ns[-1])
+    rec = np.zeros(E + 1, dtype=np.int64)
+    arrs = [_c(v, np.float64) for v in (x, y, z, m)]
+    lib = _load()
+    args = (tree.n_leaves, _p(tree.leaf_start), _p(tree.perm), _p(ns), _p(ni), _p(tree.anchor),
+            _p(tree.size), *[_p(a) for a in arrs], _p(rec))
+    rows = lib.orc_restructure_interactions(*args, None, None)
+    if prec == "fp64":
+        out = np.zeros((max(rows, 1), 4), dtype=np.float64)
+        lib.orc_restructure_interactions(*args, _p(out), None)
+    else:
+        out = np.zeros((max(rows, 1), 4), dtype=np.float32)
+        lib.orc_restructure_interactions(*args, None, _p(out))
+    return rec, out[:rows]
 
 
 # ---------------------------------------------------------------------------

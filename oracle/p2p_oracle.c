@@ -360,6 +360,73 @@ void orc_restructure_gravity_rel(int64_t L, const int32_t *leaf_start, const int
     }
 }
 
+/* Per-interaction (thread-level) layout of the stellar-dynamics case (Sec.
+ * 5.2.1): one record per near-list entry e = (A, B) in list order -- a header
+ * row (occ_A, occ_B, A, B), then the rows of A's sorted slots (the targets),
+ * then the rows of B's sorted slots (the sources).  rec_start[0..E] receives
+ * the record offsets; the total row count is returned.  With out8 != NULL the
+ * rows are double[4] (x, y, z, m) and the header holds the integers as
+ * doubles; with out4 != NULL they are float[4] relative to the centre of A,
+ * as in orc_restructure_gravity_rel, and the header holds the int32 bit
+ * patterns.  Either output may be NULL (offsets only). */
+int64_t orc_restructure_interactions(int64_t L, const int32_t *leaf_start, const int32_t *perm,
+                                     const int64_t *nbr_start, const int32_t *nbr_idx,
+                                     const int32_t *anchor, const int32_t *size,
+                                     const double *x, const double *y, const double *z,
+                                     const double *m, int64_t *rec_start, double *out8,
+                                     float *out4)
+{
+    int64_t E = nbr_start[L], w = 0;
+    for (int64_t A = 0; A < L; ++A) {
+        for (int64_t e = nbr_start[A]; e < nbr_start[A + 1]; ++e) {
+            int32_t B = nbr_idx[e];
+            rec_start[e] = w;
+            w += 1 + (leaf_start[A + 1] - leaf_start[A]) + (leaf_start[B + 1] - leaf_start[B]);
+        }
+    }
+    rec_start[E] = w;
+    if (!out8 && !out4) return w;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t A = 0; A < L; ++A) {
+        double c[3];
+        for (int d = 0; d < 3; ++d)
+            c[d] = ((double)anchor[3 * A + d] + 0.5 * (double)size[A]) / (double)(1u << ORC_DEPTH_BITS);
+        int32_t occA = leaf_start[A + 1] - leaf_start[A];
+        for (int64_t e = nbr_start[A]; e < nbr_start[A + 1]; ++e) {
+            int32_t B = nbr_idx[e];
+            int32_t occB = leaf_start[B + 1] - leaf_start[B];
+            int64_t r = rec_start[e];
+            int32_t hdr[4] = {occA, occB, (int32_t)A, B};
+            if (out8)
+                for (int k = 0; k < 4; ++k) out8[4 * r + k] = (double)hdr[k];
+            if (out4)
+                memcpy(&out4[4 * r], hdr, sizeof(hdr));
+            ++r;
+            /* the targets (A's slots), then the sources (B's slots) */
+            for (int part = 0; part < 2; ++part) {
+                int32_t lo = part == 0 ? leaf_start[A] : leaf_start[B];
+                int32_t hi = part == 0 ? leaf_start[A + 1] : leaf_start[B + 1];
+                for (int32_t sl = lo; sl < hi; ++sl, ++r) {
+                    int64_t j = perm[sl];
+                    if (out8) {
+                        out8[4 * r + 0] = x[j];
+                        out8[4 * r + 1] = y[j];
+                        out8[4 * r + 2] = z[j];
+                        out8[4 * r + 3] = m[j];
+                    }
+                    if (out4) {
+                        out4[4 * r + 0] = (float)(x[j] - c[0]);
+                        out4[4 * r + 1] = (float)(y[j] - c[1]);
+                        out4[4 * r + 2] = (float)(z[j] - c[2]);
+                        out4[4 * r + 3] = (float)m[j];
+                    }
+                }
+            }
+        }
+    }
+    return w;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Gravity                                                                  */
 /* ------------------------------------------------------------------------ */

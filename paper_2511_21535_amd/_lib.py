@@ -23,6 +23,7 @@ STATUS_NAMES = {0: "P2P_OK", 1: "P2P_EINVAL", 2: "P2P_EDOMAIN", 3: "P2P_ECAPACIT
 
 EXPORTED = ["p2p_build_tree", "p2p_build_neighbors", "p2p_restructure_redundant",
             "p2p_eval_gravity", "p2p_eval_helmholtz", "p2p_adjoint", "p2p_locality",
+            "p2p_restructure_interactions", "p2p_eval_gravity_interactions",
             "p2p_last_error", "p2p_version"]
 
 
@@ -50,6 +51,12 @@ class p2p_redundant(ctypes.Structure):
     _fields_ = [("cap", ctypes.c_int64), ("count", ctypes.c_int64),
                 ("red_start", ctypes.c_void_p), ("red_self", ctypes.c_void_p),
                 ("planes", ctypes.c_void_p * 4), ("nrhs", ctypes.c_int32), ("kind", ctypes.c_int32),
+                ("prec", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class p2p_interactions(ctypes.Structure):
+    _fields_ = [("cap", ctypes.c_int64), ("count", ctypes.c_int64), ("rec_start", ctypes.c_void_p),
+                ("planes", ctypes.c_void_p * 1), ("target_rows", ctypes.c_int64),
                 ("prec", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
@@ -100,6 +107,14 @@ def load():
                                 ctypes.POINTER(p2p_grid), I32, I32, I32,
                                 ctypes.POINTER(PV4), ctypes.POINTER(PV4), ctypes.POINTER(PV4),
                                 V, SZ, V]
+    lib.p2p_restructure_interactions.restype = st
+    lib.p2p_restructure_interactions.argtypes = [ctypes.POINTER(p2p_tree), ctypes.POINTER(p2p_nbrs),
+                                                 ctypes.POINTER(PV4), I32,
+                                                 ctypes.POINTER(p2p_interactions), V, SZ, V]
+    lib.p2p_eval_gravity_interactions.restype = st
+    lib.p2p_eval_gravity_interactions.argtypes = [ctypes.POINTER(p2p_tree), ctypes.POINTER(p2p_nbrs),
+                                                  ctypes.POINTER(p2p_interactions), F64,
+                                                  V, V, V, V, V, SZ, V]
     lib.p2p_locality.restype = st
     lib.p2p_locality.argtypes = [ctypes.POINTER(p2p_tree), ctypes.POINTER(p2p_nbrs),
                                  ctypes.POINTER(p2p_redundant), F64, F64,
@@ -151,6 +166,14 @@ def p2p_eval_helmholtz(*args):
 
 def p2p_adjoint(*args):
     return load().p2p_adjoint(*args)
+
+
+def p2p_restructure_interactions(*args):
+    return load().p2p_restructure_interactions(*args)
+
+
+def p2p_eval_gravity_interactions(*args):
+    return load().p2p_eval_gravity_interactions(*args)
 
 
 def p2p_locality(*args):

@@ -259,6 +259,75 @@ def restructure_gravity(tree, nbrs, x, y, z, m, prec="fp64", **kw) -> Redundant:
     return restructure(tree, nbrs, [x, y, z, m], prec=prec, **kw)
 
 
+@dataclass
+class Interactions:
+    """Per-interaction layout (gravity): one record per near-list entry."""
+    count: int
+    rec_start: torch.Tensor
+    rows: torch.Tensor
+    target_rows: int
+    prec: int
+
+    def struct(self) -> L.p2p_interactions:
+        s = L.p2p_interactions()
+        s.cap, s.count = self.rows.shape[0], self.count
+        s.rec_start = self.rec_start.data_ptr()
+        s.planes[0] = self.rows.data_ptr()
+        s.target_rows, s.prec = self.target_rows, self.prec
+        return s
+
+
+def restructure_interactions(tree: Tree, nbrs: Nbrs, x, y, z, m, prec="fp64",
+                             out: Optional[Interactions] = None) -> Interactions:
+    """Restructure into the per-interaction layout (rows float32 [rows, 4]
+    for fp32, float64 [rows, 4] for fp64).  Pass `out` to reuse its buffers."""
+    p = PREC[prec]
+    dev = tree.leaf_start.device
+    E = nbrs.count
+    if out is None:
+        if nbrs.red_entries >= 0:
+            rows = E + 2 * nbrs.red_entries
+        else:
+            rows = None
+        cap = rows if rows is not None else 0
+        out = Interactions(count=0, rec_start=torch.empty(E + 1, dtype=torch.int64, device=dev),
+                           rows=torch.empty((max(cap, 1), 4), device=dev,
+                                            dtype=torch.float32 if p == L.P2P_FP32_MIXED else torch.float64),
+                           target_rows=0, prec=p)
+    srcs = L.PV4(*[_ptr(t) for t in (x, y, z, m)])
+    ts, ns = tree.struct(), nbrs.struct()
+    for _ in range(2):
+        rs = out.struct()
+
+        def call(ws, nb):
+            return L.p2p_restructure_interactions(ctypes.byref(ts), ctypes.byref(ns), ctypes.byref(srcs), p,
+                                                  ctypes.byref(rs), ws, nb, _stream())
+        st, _ = _call(call, dev)
+        if st == L.P2P_ECAPACITY:
+            out.rows = torch.empty((int(rs.count), 4), device=dev, dtype=out.rows.dtype)
+            continue
+        L.check(st)
+        out.count, out.target_rows, out.prec = int(rs.count), int(rs.target_rows), int(rs.prec)
+        return out
+    raise L.P2PError(L.P2P_ECAPACITY, "per-interaction capacity retry failed")
+
+
+def gravity_interactions(tree: Tree, nbrs: Nbrs, inter: Interactions, eps: float, out=None):
+    """Near-field potential and acceleration from the per-interaction layout,
+    caller order.  Returns (phi, ax, ay, az)."""
+    dev = tree.leaf_start.device
+    if out is None:
+        out = [torch.empty(tree.n, dtype=torch.float64, device=dev) for _ in range(4)]
+    ts, ns, rs = tree.struct(), nbrs.struct(), inter.struct()
+
+    def call(ws, nb):
+        return L.p2p_eval_gravity_interactions(ctypes.byref(ts), ctypes.byref(ns), ctypes.byref(rs),
+                                               float(eps), *[_ptr(o) for o in out], ws, nb, _stream())
+    st, _ = _call(call, dev)
+    L.check(st)
+    return tuple(out)
+
+
 def gravity(tree: Tree, nbrs: Nbrs, eps: float, x=None, y=None, z=None, m=None,
             layout="gather", prec="fp64", red: Optional[Redundant] = None, out=None):
     """Near-field potential and acceleration, caller order.  Returns (phi, ax, ay, az)."""

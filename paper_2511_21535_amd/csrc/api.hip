@@ -340,6 +340,107 @@ extern "C" p2p_status p2p_restructure_redundant(const p2p_tree *tree, const p2p_
     return P2P_OK;
 }
 
+// ------------------------------------------------- per-interaction layout ---
+extern "C" p2p_status p2p_restructure_interactions(const p2p_tree *tree, const p2p_nbrs *nbrs,
+                                                   const double *const src[4], p2p_precision prec,
+                                                   p2p_interactions *out, void *ws, size_t *ws_bytes,
+                                                   p2p_stream_t stream) {
+    set_error("");
+    if (!ws_bytes) return fail(P2P_EINVAL, "ws_bytes must not be NULL");
+    P2P_TRY(check_tree(tree));
+    if (tree->kind != P2P_TREE_PARTICLES) return fail(P2P_EINVAL, "the per-interaction layout needs a particle tree");
+    P2P_TRY(check_nbrs(tree, nbrs));
+    if (!out) return fail(P2P_EINVAL, "out is NULL");
+    if (prec != P2P_FP64 && prec != P2P_FP32_MIXED) return fail(P2P_EINVAL, "bad precision");
+    const bool mixed = prec == P2P_FP32_MIXED;
+    const int64_t n = tree->n, L = tree->n_leaves, E = nbrs->count;
+    const bool known = nbrs->red_entries >= 0;
+    Arena ar(ws);
+    Row4d *s4 = ar.take<Row4d>(n);
+    int32_t *rec_len = ar.take<int32_t>(E);
+    int32_t *tgt_len = ar.take<int32_t>(known ? 0 : E);
+    int64_t *tgt_scan = ar.take<int64_t>(known ? 0 : E + 1);
+    int64_t *scan_tmp = ar.take<int64_t>(scan_ws_elems(E));
+    p2p_status st;
+    if (ws_query(ws, ws_bytes, ar, &st)) return st;
+    if (!src || (n > 0 && (!src[0] || !src[1] || !src[2] || !src[3])))
+        return fail(P2P_EINVAL, "src arrays must not be NULL");
+    if (!out->rec_start) return fail(P2P_EINVAL, "out->rec_start must not be NULL");
+    if (out->cap < 0) return fail(P2P_EINVAL, "out->cap < 0");
+    hipStream_t s = as_stream(stream);
+    P2P_TRY(launch_scatter4(src[0], src[1], src[2], src[3], tree->iperm, n, s4, s));
+    // rows: E headers plus, per record, its targets and sources; with the
+    // symmetric lists of p2p_build_neighbors both sums are S
+    int64_t rows = 0, trows = 0;
+    if (known) {
+        rows = E + 2 * nbrs->red_entries;
+        trows = nbrs->red_entries;
+    } else {
+        P2P_TRY(launch_record_lengths(tree->leaf_start, nbrs->nbr_start, nbrs->nbr_idx, L, rec_len, tgt_len, s));
+        P2P_TRY((exclusive_scan<int32_t, int64_t>(rec_len, out->rec_start, E, scan_tmp, s)));
+        P2P_TRY((exclusive_scan<int32_t, int64_t>(tgt_len, tgt_scan, E, scan_tmp, s)));
+        if (E > 0) {
+            P2P_HIP(hipMemcpyAsync(&rows, &out->rec_start[E], sizeof(int64_t), hipMemcpyDeviceToHost, s));
+            P2P_HIP(hipMemcpyAsync(&trows, &tgt_scan[E], sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        }
+        P2P_HIP(hipStreamSynchronize(s));
+    }
+    if (rows > out->cap) {
+        out->count = rows;
+        return fail(P2P_ECAPACITY, "out->cap " + std::to_string(out->cap) + " < " + std::to_string(rows) + " rows");
+    }
+    if (rows > 0 && !out->planes[0]) return fail(P2P_EINVAL, "out->planes[0] must not be NULL");
+    if (known) {
+        P2P_TRY(launch_record_lengths(tree->leaf_start, nbrs->nbr_start, nbrs->nbr_idx, L, rec_len, nullptr, s));
+        P2P_TRY((exclusive_scan<int32_t, int64_t>(rec_len, out->rec_start, E, scan_tmp, s)));
+    }
+    const bool streaming = rows * (mixed ? 16 : 32) > kStreamingLayoutBytes;
+    P2P_TRY(launch_copy_records(s4, tree->leaf_key, tree->leaf_level, tree->leaf_start, nbrs->nbr_start,
+                                nbrs->nbr_idx, out->rec_start, L,
+                                mixed ? nullptr : static_cast<Row4d *>(out->planes[0]),
+                                mixed ? static_cast<float4 *>(out->planes[0]) : nullptr, streaming, s));
+    out->count = rows;
+    out->target_rows = trows;
+    out->prec = prec;
+    return P2P_OK;
+}
+
+extern "C" p2p_status p2p_eval_gravity_interactions(const p2p_tree *tree, const p2p_nbrs *nbrs,
+                                                    const p2p_interactions *inter, double eps,
+                                                    double *phi, double *ax, double *ay, double *az,
+                                                    void *ws, size_t *ws_bytes, p2p_stream_t stream) {
+    set_error("");
+    if (!ws_bytes) return fail(P2P_EINVAL, "ws_bytes must not be NULL");
+    P2P_TRY(check_tree(tree));
+    if (tree->kind != P2P_TREE_PARTICLES) return fail(P2P_EINVAL, "gravity needs a particle tree");
+    P2P_TRY(check_nbrs(tree, nbrs));
+    if (!inter) return fail(P2P_EINVAL, "inter is NULL");
+    if (inter->prec != P2P_FP64 && inter->prec != P2P_FP32_MIXED) return fail(P2P_EINVAL, "inter was not built");
+    if (inter->target_rows < 0) return fail(P2P_EINVAL, "inter->target_rows < 0");
+    if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(P2P_EINVAL, "eps must be finite and >= 0");
+    const bool mixed = inter->prec == P2P_FP32_MIXED;
+    const int64_t n = tree->n, L = tree->n_leaves, E = nbrs->count;
+    Arena ar(ws);
+    int32_t *tgt_len = ar.take<int32_t>(E);
+    int64_t *res_start = ar.take<int64_t>(E + 1);
+    int64_t *scan_tmp = ar.take<int64_t>(scan_ws_elems(E));
+    Row4d *res = ar.take<Row4d>(inter->target_rows);
+    p2p_status st;
+    if (ws_query(ws, ws_bytes, ar, &st)) return st;
+    if (n > 0 && (!phi || !ax || !ay || !az)) return fail(P2P_EINVAL, "outputs must not be NULL");
+    if (!inter->rec_start || (inter->count > 0 && !inter->planes[0]))
+        return fail(P2P_EINVAL, "inter arrays must not be NULL");
+    hipStream_t s = as_stream(stream);
+    P2P_TRY(launch_record_lengths(tree->leaf_start, nbrs->nbr_start, nbrs->nbr_idx, L, nullptr, tgt_len, s));
+    P2P_TRY((exclusive_scan<int32_t, int64_t>(tgt_len, res_start, E, scan_tmp, s)));
+    P2P_TRY(launch_eval_records(inter->rec_start, mixed ? nullptr : static_cast<const Row4d *>(inter->planes[0]),
+                                mixed ? static_cast<const float4 *>(inter->planes[0]) : nullptr, E, res_start,
+                                eps * eps, eps == 0.0, res, s));
+    P2P_TRY(launch_reduce_records(tree->leaf_start, nbrs->nbr_start, res_start, tree->perm, L, res, phi, ax,
+                                  ay, az, s));
+    return P2P_OK;
+}
+
 // ---------------------------------------------------------------- a4/a5 ---
 extern "C" p2p_status p2p_eval_gravity(const p2p_tree *tree, const p2p_nbrs *nbrs,
                                        const p2p_redundant *red, p2p_layout layout,

@@ -137,10 +137,10 @@ __device__ inline void leaf_centre(uint64_t key, int level, double c[3]) {
 template <bool MIXED, bool RED, bool EPS0>
 __device__ __forceinline__ void gravity_body(const GravityArgs &a) {
     using Src = typename std::conditional<MIXED, float4, Row4d>::type;
-    // a tile of kGTile sources laid out as G runs of `pitch` entries (see
-    // below): at most kGTile + 2 kGBlock entries; the per-target reduction
-    // reuses the same memory after the last tile
-    __shared__ Src s_src[kGTile + 2 * kGBlock];
+    // a tile of kGTile sources padded to G equal runs (see below): at most
+    // kGTile + kGBlock - 1 entries; the per-target reduction reuses the same
+    // memory after the last tile
+    __shared__ Src s_src[kGTile + kGBlock];
     __shared__ int64_t s_pre[kGNbrChunk + 1];
     __shared__ int32_t s_first[kGNbrChunk];
     __shared__ int64_t s_w[kGBlock / 64];
@@ -177,31 +177,23 @@ __device__ __forceinline__ void gravity_body(const GravityArgs &a) {
         double p = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
 
         // Tile layout: lane group g takes the contiguous run of sources
-        // [g chunk, (g + 1) chunk) of the tile, chunk = ceil(nt / G), stored
-        // at s_src[g pitch ...] with an odd pitch (chunk or chunk + 1), so the
-        // groups of one wavefront read different LDS banks.  The G chunk - nt
-        // entries past the end are zero-mass sources far away (they add exact
-        // zeros), so every lane runs the same trip count and the four reads
-        // of an unrolled step sit at fixed offsets from one address.
-        int chunk = 0, pitch = 0;
-        float inv_chunk = 0.f;
-        auto slot = [&](int i) {
-            const int q = static_cast<int>((static_cast<float>(i) + 0.5f) * inv_chunk);
-            return q * pitch + (i - q * chunk);
-        };
+        // [g chunk, (g + 1) chunk) of the tile, chunk = ceil(nt / G).  The
+        // G chunk - nt entries past the end are zero-mass sources far away
+        // (they add exact zeros), so every lane runs the same trip count and
+        // the four reads of an unrolled step sit at fixed offsets from one
+        // address.
+        int chunk = 0;
         auto begin = [&](int nt) {
             chunk = (nt + G - 1) / G;
-            pitch = chunk | 1;
-            inv_chunk = 1.0f / static_cast<float>(chunk);
             for (int i = nt + static_cast<int>(threadIdx.x); i < G * chunk; i += kGBlock) {
                 if constexpr (MIXED)
-                    s_src[slot(i)] = make_float4(1e18f, 1e18f, 1e18f, 0.f);
+                    s_src[i] = make_float4(1e18f, 1e18f, 1e18f, 0.f);
                 else
-                    s_src[slot(i)] = Row4d{1e18, 1e18, 1e18, 0.0};
+                    s_src[i] = Row4d{1e18, 1e18, 1e18, 0.0};
             }
         };
         auto stage = [&](int i, int64_t row) {
-            Src *d = s_src + slot(i);
+            Src *d = s_src + i;
             if constexpr (MIXED) {
                 if constexpr (RED) {
                     *d = a.red4[row];
@@ -216,7 +208,7 @@ __device__ __forceinline__ void gravity_body(const GravityArgs &a) {
         };
         auto body = [&](int) {
             if (!active) return;
-            const Src *sp = s_src + g * pitch;
+            const Src *sp = s_src + g * chunk;
             if constexpr (MIXED) {
                 auto pair = [&](const float4 v, float &pf, float &xf, float &yf, float &zf) {
                     const float dx = tv.x - v.x, dy = tv.y - v.y, dz = tv.z - v.z;

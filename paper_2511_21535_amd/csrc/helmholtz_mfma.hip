@@ -18,13 +18,9 @@
 // lane k*32 + j, and accumulator register r of lane l holds row
 // 8 (r/4) + 4 (l/32) + r%4, column l%32.
 //
-// Work distribution: the boxes are cut into 8 contiguous ranges of the box
-// order (spatially compact), one per XCD; each range is ordered by decreasing
-// near-list length (longest processing time first) and served by its own
-// atomic counter.  Workgroup w of the persistent grid runs on XCD w % 8
-// (workgroups are dispatched to the XCDs in turn), so the boxes of one range
-// share their neighbours' Q rows in that XCD's L2.  A wave drains its own
-// range, then helps the others, and exits when all are exhausted.
+// Work distribution: waves take boxes from an atomic counter over a list
+// ordered by decreasing near-list length (longest processing time first),
+// and exit when the list is exhausted.
 #include "p2p_internal.h"
 
 namespace p2p {
@@ -63,18 +59,12 @@ __global__ void k_green_blocks(const double *__restrict__ kh, int32_t n_tables,
     blocks[t] = v;
 }
 
-constexpr int kXcds = 8;
-
-// First box of XCD range x: boxes [range_start(x), range_start(x + 1)).
-__host__ __device__ inline int64_t range_start(int64_t x, int64_t L) { return (x * L + kXcds - 1) / kXcds; }
-
 __global__ void k_work_keys(const int64_t *__restrict__ nbr_start, int64_t L,
                             uint64_t *__restrict__ keys, int32_t *__restrict__ vals) {
     const int64_t A = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (A >= L) return;
     const int64_t c = nbr_start[A + 1] - nbr_start[A];
-    const uint64_t x = static_cast<uint64_t>((A * kXcds) / L);       // A's range
-    keys[A] = (x << 8) | static_cast<uint64_t>(255 - min<int64_t>(c, 255));   // longest lists first
+    keys[A] = static_cast<uint64_t>(255 - min<int64_t>(c, 255));   // longest lists first
     vals[A] = static_cast<int32_t>(A);
 }
 
@@ -95,21 +85,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const int half = lane >> 5, col = lane & 31;
     const uint64_t local_mask = (1ull << (3 * key_bits)) - 1ull;
     const int chunks = nrhs / (32 * TJ);
-    int x = static_cast<int>(blockIdx.x % kXcds);   // own range first
-    int tried = 0;
+    const int64_t items = L * chunks;
 
     for (;;) {
-        const int64_t b0 = range_start(x, L), nitems = (range_start(x + 1, L) - b0) * chunks;
-        int64_t item = 0;
-        if (lane == 0) item = atomicAdd(&counter[x], 1);
-        item = __builtin_amdgcn_readfirstlane(static_cast<int>(__shfl(static_cast<int>(item), 0, 64)));
-        if (item >= nitems) {
-            if (++tried == kXcds) break;    // every range is exhausted
-            x = (x + 1) % kXcds;
-            continue;
-        }
-        const int64_t A = work[b0 + item / chunks];
-        const int rhs0 = static_cast<int>(item % chunks) * 32 * TJ;
+        int item = 0;
+        if (lane == 0) item = atomicAdd(counter, 1);
+        item = __builtin_amdgcn_readfirstlane(__shfl(item, 0, 64));
+        if (item >= items) break;
+        const int64_t A = work[item / chunks];
+        const int rhs0 = (item % chunks) * 32 * TJ;
         const uint64_t kA = leaf_key[A];
         const int g = static_cast<int>(kA >> (3 * key_bits));
         const float2 *__restrict__ gbase = blocks + static_cast<int64_t>(inst_table[g]) * (27 * 4096);
@@ -224,7 +208,7 @@ p2p_status launch_work_order(const int64_t *nbr_start, int64_t L, int32_t *work,
     if (L <= 0) return P2P_OK;
     k_work_keys<<<grid_for(L, 256), 256, 0, s>>>(nbr_start, L, keys, work);
     P2P_LAUNCH_CHECK();
-    return radix_sort_pairs(keys, work, keys_tmp, vals_tmp, L, 16, hist, s);   // range, then length
+    return radix_sort_pairs(keys, work, keys_tmp, vals_tmp, L, 8, hist, s);
 }
 
 template <bool RED, bool CONJ, int TJ>
@@ -240,7 +224,7 @@ p2p_status launch_helmholtz_mfma(const HelmholtzMfmaArgs &a, bool redundant, int
     int dev = 0, cus = 0;
     P2P_HIP(hipGetDevice(&dev));
     P2P_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    k_zero_counter<<<1, 64, 0, s>>>(a.counter, kXcds);
+    k_zero_counter<<<1, 64, 0, s>>>(a.counter, 1);
     P2P_LAUNCH_CHECK();
     const unsigned block = 64u * static_cast<unsigned>(waves_per_wg);
     const unsigned grid = static_cast<unsigned>(cus) * static_cast<unsigned>(wg_per_cu);

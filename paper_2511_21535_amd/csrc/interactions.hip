@@ -1,0 +1,327 @@
+// Per-interaction redundant layout for gravity: the thread-level redundancy of
+// the paper's stellar-dynamics case (Sec. 5.2.1), beside the box-grain layout
+// of restructure.hip.
+//
+// One record per near-list entry e = (A, B): a header row (occ_A, occ_B, A, B
+// as integers), A's rows (the targets), then B's rows (the sources).  Every
+// record is self-contained, so the evaluation takes one wavefront per record
+// with no shared state; its pair sums go to result rows of its own (the
+// duplicated results of the paper's design), and a second pass sums each
+// target's rows over the records of its leaf (the update).  Compared with the
+// box grain, the layout stores every target E2 times more and every result
+// E2 times, in exchange for independent, fine-grained work items.
+#include "p2p_internal.h"
+
+namespace p2p {
+namespace {
+
+constexpr int kRecLanes = 16;
+
+__device__ inline float rsq_f32(float x) { return __builtin_amdgcn_rsqf(x); }
+
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+
+template <bool NT>
+__device__ inline void put(float4 *d, const float4 &v) {
+    if constexpr (NT) {
+        const nt_f4 t = {v.x, v.y, v.z, v.w};
+        __builtin_nontemporal_store(t, reinterpret_cast<nt_f4 *>(d));
+    } else {
+        *d = v;
+    }
+}
+template <bool NT>
+__device__ inline void put(Row4d *d, const Row4d &v) {
+    if constexpr (NT) {
+        const nt_d2 a = {v.x, v.y}, b = {v.z, v.w};
+        __builtin_nontemporal_store(a, reinterpret_cast<nt_d2 *>(d));
+        __builtin_nontemporal_store(b, reinterpret_cast<nt_d2 *>(d) + 1);
+    } else {
+        *d = v;
+    }
+}
+
+// rec_len[e] = 1 + occ_A + occ_B and tgt_len[e] = occ_A for the entries of
+// leaf A (16 lanes per leaf).  Either output may be null.
+__global__ __launch_bounds__(256) void k_record_lengths(const int32_t *__restrict__ leaf_start,
+                                                        const int64_t *__restrict__ nbr_start,
+                                                        const int32_t *__restrict__ nbr_idx, int64_t L,
+                                                        int32_t *__restrict__ rec_len,
+                                                        int32_t *__restrict__ tgt_len) {
+    const int sub = threadIdx.x % kRecLanes;
+    const int64_t A = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / kRecLanes;
+    if (A >= L) return;
+    const int32_t occA = leaf_start[A + 1] - leaf_start[A];
+    for (int64_t e = nbr_start[A] + sub; e < nbr_start[A + 1]; e += kRecLanes) {
+        const int32_t B = nbr_idx[e];
+        if (rec_len) rec_len[e] = 1 + occA + leaf_start[B + 1] - leaf_start[B];
+        if (tgt_len) tgt_len[e] = occA;
+    }
+}
+
+// Records of leaf A, one wavefront per leaf: for every entry of nbr(A), the
+// header, A's rows and B's rows, four rows per lane in flight.
+template <bool MIXED, bool NT>
+__global__ __launch_bounds__(256) void k_copy_records(
+    const Row4d *__restrict__ sorted, const uint64_t *__restrict__ leaf_key,
+    const int8_t *__restrict__ leaf_level, const int32_t *__restrict__ leaf_start,
+    const int64_t *__restrict__ nbr_start, const int32_t *__restrict__ nbr_idx,
+    const int64_t *__restrict__ rec_start, int64_t L, Row4d *__restrict__ d8, float4 *__restrict__ d4) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t A = p2pd::xcd_contiguous(blockIdx.x, gridDim.x) * 4 + w;
+    if (A >= L) return;
+    const int32_t a0 = leaf_start[A], occA = leaf_start[A + 1] - a0;
+    double c[3] = {0.0, 0.0, 0.0};
+    if (MIXED) {
+        const uint64_t k = leaf_key[A];
+        const double half = 0.5 * static_cast<double>(1u << (20 - leaf_level[A]));
+        c[0] = (static_cast<double>(p2pd::compact3(k)) + half) * 0x1p-20;
+        c[1] = (static_cast<double>(p2pd::compact3(k >> 1)) + half) * 0x1p-20;
+        c[2] = (static_cast<double>(p2pd::compact3(k >> 2)) + half) * 0x1p-20;
+    }
+    for (int64_t e = nbr_start[A]; e < nbr_start[A + 1]; ++e) {
+        const int32_t B = nbr_idx[e];
+        const int32_t b0 = leaf_start[B], occB = leaf_start[B + 1] - b0;
+        const int64_t d = rec_start[e];
+        if (lane == 0) {
+            if constexpr (MIXED)
+                put<NT>(d4 + d, make_float4(__int_as_float(occA), __int_as_float(occB),
+                                            __int_as_float(static_cast<int32_t>(A)), __int_as_float(B)));
+            else
+                put<NT>(d8 + d, Row4d{static_cast<double>(occA), static_cast<double>(occB),
+                                      static_cast<double>(A), static_cast<double>(B)});
+        }
+        // rows r < occA come from A, the rest from B; lanes past the end
+        // repeat the last row onto itself, so no load or store is conditional
+        const int32_t rows = occA + occB;
+        for (int32_t p0 = 0; p0 < rows; p0 += 256) {
+            Row4d v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int32_t r = min(p0 + 64 * u + lane, rows - 1);
+                v[u] = sorted[r < occA ? a0 + r : b0 + (r - occA)];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t o = d + 1 + min(p0 + 64 * u + lane, rows - 1);
+                if constexpr (MIXED)
+                    put<NT>(d4 + o, make_float4(static_cast<float>(v[u].x - c[0]), static_cast<float>(v[u].y - c[1]),
+                                                static_cast<float>(v[u].z - c[2]), static_cast<float>(v[u].w)));
+                else
+                    put<NT>(d8 + o, v[u]);
+            }
+        }
+    }
+}
+
+constexpr int kEvalWaves = 4;
+constexpr int kRecFlush = 32;
+
+// One wavefront per record.  Targets in chunks of 64; with tc targets in a
+// chunk, lane (t, g) = (lane % tc, lane / tc) takes target t and sources
+// g, g + G, ... (G = 64 / tc) straight from the record (coalesced across the
+// groups), FP32-mixed pair terms summed at most 32 at a time in float into
+// double; the G partials meet in LDS.  Record (A, A) holds every target once
+// as its own source at d = 0; that self term is added back as in the box
+// kernels.
+template <bool MIXED, bool EPS0>
+__global__ __launch_bounds__(64 * kEvalWaves) void k_eval_records(
+    const int64_t *__restrict__ rec_start, const Row4d *__restrict__ r8, const float4 *__restrict__ r4,
+    int64_t E, const int64_t *__restrict__ res_start, double eps2, Row4d *__restrict__ res) {
+    __shared__ double s_red[kEvalWaves][4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * kEvalWaves + w;
+    if (e >= E) return;
+    const int64_t r = rec_start[e];
+    int occA, occB, A, B;
+    if constexpr (MIXED) {
+        const float4 h = r4[r];
+        occA = __float_as_int(h.x);
+        occB = __float_as_int(h.y);
+        A = __float_as_int(h.z);
+        B = __float_as_int(h.w);
+    } else {
+        const Row4d h = r8[r];
+        occA = static_cast<int>(h.x);
+        occB = static_cast<int>(h.y);
+        A = static_cast<int>(h.z);
+        B = static_cast<int>(h.w);
+    }
+    occA = __builtin_amdgcn_readfirstlane(occA);
+    occB = __builtin_amdgcn_readfirstlane(occB);
+    const bool self = __builtin_amdgcn_readfirstlane(A) == __builtin_amdgcn_readfirstlane(B);
+    const int64_t t0 = r + 1, s0 = r + 1 + occA;
+    const float eps2f = static_cast<float>(eps2);
+    const int64_t out0 = res_start[e];
+    for (int tc0 = 0; tc0 < occA; tc0 += 64) {
+        const int tc = min(64, occA - tc0);
+        const int G = 64 / tc;
+        const int t = lane % tc, g = lane / tc;
+        const bool active = g < G;
+        double p = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+        double tm = 0.0;
+        if (active) {
+            if constexpr (MIXED) {
+                const float4 tv = r4[t0 + tc0 + t];
+                tm = tv.w;
+                int j = g;
+                while (j < occB) {
+                    float pf = 0.f, xf = 0.f, yf = 0.f, zf = 0.f;
+                    for (int k = 0; k < kRecFlush && j < occB; ++k, j += G) {
+                        const float4 v = r4[s0 + j];
+                        const float dx = tv.x - v.x, dy = tv.y - v.y, dz = tv.z - v.z;
+                        const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2f)));
+                        float wv = rsq_f32(r2);
+                        if constexpr (EPS0) wv = (r2 > 0.f) ? wv : 0.f;
+                        const float mw = v.w * wv;
+                        const float mw3 = mw * (wv * wv);
+                        pf -= mw;
+                        xf = fmaf(-mw3, dx, xf);
+                        yf = fmaf(-mw3, dy, yf);
+                        zf = fmaf(-mw3, dz, zf);
+                    }
+                    p += pf;
+                    fx += xf;
+                    fy += yf;
+                    fz += zf;
+                }
+            } else {
+                const Row4d tv = r8[t0 + tc0 + t];
+                tm = tv.w;
+                for (int j = g; j < occB; j += G) {
+                    const Row4d v = r8[s0 + j];
+                    const double dx = tv.x - v.x, dy = tv.y - v.y, dz = tv.z - v.z;
+                    const double r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
+                    double wv = rsqrt(r2);
+                    if constexpr (EPS0) wv = (r2 > 0.0) ? wv : 0.0;
+                    const double mw = v.w * wv;
+                    const double mw3 = mw * (wv * wv);
+                    p -= mw;
+                    fx = fma(-mw3, dx, fx);
+                    fy = fma(-mw3, dy, fy);
+                    fz = fma(-mw3, dz, fz);
+                }
+            }
+        }
+        s_red[w][0][lane] = p;
+        s_red[w][1][lane] = fx;
+        s_red[w][2][lane] = fy;
+        s_red[w][3][lane] = fz;
+        wave_sync();
+        if (lane < tc) {
+            double sp = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+            for (int q = 0; q < G; ++q) {
+                sp += s_red[w][0][q * tc + lane];
+                sx += s_red[w][1][q * tc + lane];
+                sy += s_red[w][2][q * tc + lane];
+                sz += s_red[w][3][q * tc + lane];
+            }
+            if (!EPS0 && self) {
+                if constexpr (MIXED)
+                    sp += static_cast<double>(static_cast<float>(tm) * rsq_f32(eps2f));
+                else
+                    sp += tm * rsqrt(eps2);
+            }
+            res[out0 + tc0 + lane] = Row4d{sp, sx, sy, sz};
+        }
+        wave_sync();
+    }
+}
+
+// Update: for every target of leaf A, the sum of its result rows over the
+// records of nbr(A), in list order, written to caller order (wave per leaf).
+__global__ __launch_bounds__(256) void k_reduce_records(const int32_t *__restrict__ leaf_start,
+                                                        const int64_t *__restrict__ nbr_start,
+                                                        const int64_t *__restrict__ res_start,
+                                                        const int32_t *__restrict__ perm, int64_t L,
+                                                        const Row4d *__restrict__ res,
+                                                        double *__restrict__ phi, double *__restrict__ ax,
+                                                        double *__restrict__ ay, double *__restrict__ az) {
+    const int lane = threadIdx.x & 63;
+    const int64_t A = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (A >= L) return;
+    const int32_t a0 = leaf_start[A], occA = leaf_start[A + 1] - a0;
+    const int64_t e0 = nbr_start[A], e1 = nbr_start[A + 1];
+    for (int t = lane; t < occA; t += 64) {
+        double sp = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+        for (int64_t e = e0; e < e1; ++e) {
+            const Row4d v = res[res_start[e] + t];
+            sp += v.x;
+            sx += v.y;
+            sy += v.z;
+            sz += v.w;
+        }
+        const int64_t i = perm[a0 + t];
+        phi[i] = sp;
+        ax[i] = sx;
+        ay[i] = sy;
+        az[i] = sz;
+    }
+}
+
+}  // namespace
+
+p2p_status launch_record_lengths(const int32_t *leaf_start, const int64_t *nbr_start,
+                                 const int32_t *nbr_idx, int64_t L, int32_t *rec_len, int32_t *tgt_len,
+                                 hipStream_t s) {
+    if (L <= 0) return P2P_OK;
+    k_record_lengths<<<grid_for(L * kRecLanes, 256), 256, 0, s>>>(leaf_start, nbr_start, nbr_idx, L,
+                                                                  rec_len, tgt_len);
+    P2P_LAUNCH_CHECK();
+    return P2P_OK;
+}
+
+p2p_status launch_copy_records(const Row4d *sorted, const uint64_t *leaf_key, const int8_t *leaf_level,
+                               const int32_t *leaf_start, const int64_t *nbr_start,
+                               const int32_t *nbr_idx, const int64_t *rec_start, int64_t L, Row4d *d8,
+                               float4 *d4, bool streaming, hipStream_t s) {
+    if (L <= 0) return P2P_OK;
+    const unsigned g = grid_for(L, 4);
+#define P2P_REC(M, NT)                                                                                \
+    k_copy_records<M, NT><<<g, 256, 0, s>>>(sorted, leaf_key, leaf_level, leaf_start, nbr_start, nbr_idx, \
+                                            rec_start, L, d8, d4)
+    if (d4) {
+        if (streaming) P2P_REC(true, true); else P2P_REC(true, false);
+    } else {
+        if (streaming) P2P_REC(false, true); else P2P_REC(false, false);
+    }
+#undef P2P_REC
+    P2P_LAUNCH_CHECK();
+    return P2P_OK;
+}
+
+p2p_status launch_eval_records(const int64_t *rec_start, const Row4d *r8, const float4 *r4, int64_t E,
+                               const int64_t *res_start, double eps2, bool eps_zero, Row4d *res,
+                               hipStream_t s) {
+    if (E <= 0) return P2P_OK;
+    const unsigned g = grid_for(E, kEvalWaves);
+    const unsigned b = 64 * kEvalWaves;
+    if (r4) {
+        if (eps_zero) k_eval_records<true, true><<<g, b, 0, s>>>(rec_start, r8, r4, E, res_start, eps2, res);
+        else k_eval_records<true, false><<<g, b, 0, s>>>(rec_start, r8, r4, E, res_start, eps2, res);
+    } else {
+        if (eps_zero) k_eval_records<false, true><<<g, b, 0, s>>>(rec_start, r8, r4, E, res_start, eps2, res);
+        else k_eval_records<false, false><<<g, b, 0, s>>>(rec_start, r8, r4, E, res_start, eps2, res);
+    }
+    P2P_LAUNCH_CHECK();
+    return P2P_OK;
+}
+
+p2p_status launch_reduce_records(const int32_t *leaf_start, const int64_t *nbr_start,
+                                 const int64_t *res_start, const int32_t *perm, int64_t L,
+                                 const Row4d *res, double *phi, double *ax, double *ay, double *az,
+                                 hipStream_t s) {
+    if (L <= 0) return P2P_OK;
+    k_reduce_records<<<grid_for(L, 4), 256, 0, s>>>(leaf_start, nbr_start, res_start, perm, L, res, phi, ax,
+                                                    ay, az);
+    P2P_LAUNCH_CHECK();
+    return P2P_OK;
+}
+
+}  // namespace p2p

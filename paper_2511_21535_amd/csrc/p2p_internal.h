@@ -117,8 +117,6 @@ p2p_status launch_seg_lengths(const int32_t *leaf_start, const int64_t *nbr_star
 template <class T>
 p2p_status launch_permute_rows(const T *src, const int32_t *perm, int64_t n, int64_t row_len,
                                T *dst, hipStream_t s);
-// out[s] = (a[perm[s]], b[perm[s]], c[perm[s]], d[perm[s]]): four caller-order
-// planes into sorted rows.
 // Caller-order planes (a, b, c, d) into sorted rows: out[iperm[i]] = (a, b, c, d)[i].
 p2p_status launch_scatter4(const double *a, const double *b, const double *c, const double *d,
                            const int32_t *iperm, int64_t n, Row4d *out, hipStream_t s);
@@ -139,6 +137,27 @@ p2p_status launch_copy_segments(const T *sorted, int64_t row_len, const int32_t 
 constexpr int64_t kStreamingLayoutBytes = int64_t(128) << 20;
 
 // Gravity (gravity.hip).
+// Per-interaction layout (gravity): one record per near-list entry e = (A, B),
+// a header row (occ_A, occ_B, A, B as integers) then A's rows then B's rows,
+// FP32_MIXED float4 relative to the centre of A, or FP64 rows.
+p2p_status launch_record_lengths(const int32_t *leaf_start, const int64_t *nbr_start,
+                                 const int32_t *nbr_idx, int64_t L, int32_t *rec_len, int32_t *tgt_len,
+                                 hipStream_t s);
+p2p_status launch_copy_records(const Row4d *sorted, const uint64_t *leaf_key, const int8_t *leaf_level,
+                               const int32_t *leaf_start, const int64_t *nbr_start,
+                               const int32_t *nbr_idx, const int64_t *rec_start, int64_t L, Row4d *d8,
+                               float4 *d4, bool streaming, hipStream_t s);
+// Pair sums of every record into its own result rows res[res_start[e] + t]
+// (phi, ax, ay, az per target, FP64), then the per-target sums over the
+// records of its leaf, written to caller order.
+p2p_status launch_eval_records(const int64_t *rec_start, const Row4d *r8, const float4 *r4, int64_t E,
+                               const int64_t *res_start, double eps2, bool eps_zero, Row4d *res,
+                               hipStream_t s);
+p2p_status launch_reduce_records(const int32_t *leaf_start, const int64_t *nbr_start,
+                                 const int64_t *res_start, const int32_t *perm, int64_t L,
+                                 const Row4d *res, double *phi, double *ax, double *ay, double *az,
+                                 hipStream_t s);
+
 struct GravityArgs {
     int64_t L;
     const int32_t *leaf_start;
@@ -206,7 +225,7 @@ struct HelmholtzMfmaArgs {
     const int32_t *inst_table; // per instance: table index
     const float *inst_scale;   // per instance: 1/h
     const int32_t *work;       // box ids in processing order (longest first)
-    int32_t *counter;          // work-queue counters, one per XCD range (zeroed by the launcher)
+    int32_t *counter;          // work-queue counter (zeroed by the launcher)
     int32_t nrhs;
     int32_t conj;
     float2 *u;                 // caller order [n][nrhs]

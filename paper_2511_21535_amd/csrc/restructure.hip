@@ -289,62 +289,6 @@ __global__ __launch_bounds__(kCopyBlock) void k_copy_segments_units(
     }
 }
 
-// Source-major copy for wide rows (Helmholtz with many right-hand sides),
-// one workgroup per SOURCE leaf B.  The near relation built by
-// p2p_build_neighbors is symmetric, so the segments that hold B's rows are
-// those of the leaves A in nbr(B), at the offset of B in nbr(A): the points of
-// the leaves listed before B, which (the lists being ascending) are the
-// entries of nbr(A) below B.  The threads first work out one destination each
-// (in parallel, into LDS); then B's rows are read once, UN units per thread,
-// and written to every destination.  The target-major copy reads each source
-// row once per segment instead, which for rows of hundreds of bytes is most of
-// the traffic.  A leaf A whose list does not hold B (lists not built by the
-// library) is skipped.
-template <class U, int UN, bool NT>
-__global__ __launch_bounds__(kCopyBlock) void k_copy_segments_by_source(
-    const U *__restrict__ sorted, int64_t upr, const int32_t *__restrict__ leaf_start,
-    const int64_t *__restrict__ nbr_start, const int32_t *__restrict__ nbr_idx,
-    const int64_t *__restrict__ red_start, int64_t L, U *__restrict__ dst) {
-    __shared__ int64_t s_dst[kCopyNbrChunk];     // first row of each destination, -1 if none
-    const int64_t B = p2pd::xcd_contiguous(blockIdx.x, gridDim.x);
-    if (B >= L) return;
-    const int64_t r0 = leaf_start[B];
-    const int64_t units = (leaf_start[B + 1] - r0) * upr;
-    const int64_t eb0 = nbr_start[B], eb1 = nbr_start[B + 1];
-    for (int64_t c0 = eb0; c0 < eb1; c0 += kCopyNbrChunk) {
-        const int nc = static_cast<int>(min<int64_t>(kCopyNbrChunk, eb1 - c0));
-        __syncthreads();
-        if (static_cast<int>(threadIdx.x) < nc) {
-            const int32_t A = nbr_idx[c0 + threadIdx.x];
-            int64_t pos = 0;
-            bool found = false;
-            const int64_t f1 = nbr_start[A + 1];
-#pragma unroll 4
-            for (int64_t f = nbr_start[A]; f < f1; ++f) {
-                const int32_t b = nbr_idx[f];
-                const int32_t occ = leaf_start[b + 1] - leaf_start[b];   // loads without a condition
-                pos += (b < B) ? occ : 0;
-                found = found || b == B;
-            }
-            s_dst[threadIdx.x] = found ? red_start[A] + pos : int64_t(-1);
-        }
-        __syncthreads();
-        for (int64_t u0 = threadIdx.x; u0 < units; u0 += kCopyBlock * UN) {
-            // units past the end repeat the last unit (same bytes, same place)
-            U v[UN];
-#pragma unroll
-            for (int k = 0; k < UN; ++k) v[k] = sorted[r0 * upr + min(u0 + kCopyBlock * k, units - 1)];
-            for (int e = 0; e < nc; ++e) {
-                const int64_t row = s_dst[e];
-                if (row < 0) continue;
-                U *__restrict__ d = dst + row * upr;
-#pragma unroll
-                for (int k = 0; k < UN; ++k) put_row<NT>(d + min(u0 + kCopyBlock * k, units - 1), v[k]);
-            }
-        }
-    }
-}
-
 }  // namespace
 
 p2p_status launch_seg_lengths(const int32_t *leaf_start, const int64_t *nbr_start,
@@ -383,26 +327,11 @@ p2p_status permute_units(const void *src, const int32_t *perm, int64_t n, int64_
     return P2P_OK;
 }
 
-// Rows of at least this many bytes are copied source-major.
-constexpr int64_t kSourceMajorRowBytes = 128;
-
 template <class U>
 p2p_status copy_units(const void *sorted, int64_t row_bytes, const int32_t *leaf_start,
                       const int64_t *nbr_start, const int32_t *nbr_idx, const int64_t *red_start,
                       int64_t L, void *dst, bool streaming, hipStream_t s) {
     const int64_t upr = row_bytes / static_cast<int64_t>(sizeof(U));
-    if (row_bytes >= kSourceMajorRowBytes) {
-        if (streaming)
-            k_copy_segments_by_source<U, 8, true><<<static_cast<unsigned>(L), kCopyBlock, 0, s>>>(
-                static_cast<const U *>(sorted), upr, leaf_start, nbr_start, nbr_idx, red_start, L,
-                static_cast<U *>(dst));
-        else
-            k_copy_segments_by_source<U, 8, false><<<static_cast<unsigned>(L), kCopyBlock, 0, s>>>(
-                static_cast<const U *>(sorted), upr, leaf_start, nbr_start, nbr_idx, red_start, L,
-                static_cast<U *>(dst));
-        P2P_LAUNCH_CHECK();
-        return P2P_OK;
-    }
     if (streaming)
         k_copy_segments_units<U, 4, true><<<static_cast<unsigned>(L), kCopyBlock, 0, s>>>(
             static_cast<const U *>(sorted), upr, leaf_start, nbr_start, nbr_idx, red_start, L,

@@ -116,3 +116,35 @@ def test_adjoint_unsupported_combinations(lib):
     st = lib.p2p_adjoint(5, ctypes.byref(t), ctypes.byref(n), None, L.P2P_GATHER, L.P2P_FP64, 1e-3,
                          None, 0, 1, 0, None, None, None, None, ctypes.byref(nb), None)
     assert st == L.P2P_EINVAL
+
+
+def test_interaction_layout_validation(lib):
+    t = _tree(10, L_=1)
+    t.perm = t.iperm = t.leaf_start = t.leaf_key = t.leaf_level = 0x1000
+    n = L.p2p_nbrs()
+    n.count, n.nbr_start, n.nbr_idx, n.red_entries = 1, 0x1000, 0x1000, 10
+    nb = ctypes.c_size_t(0)
+    inter = L.p2p_interactions()
+    # size query succeeds on host; a grid tree or a bad precision is rejected
+    assert lib.p2p_restructure_interactions(ctypes.byref(t), ctypes.byref(n), None, L.P2P_FP32_MIXED,
+                                            ctypes.byref(inter), None, ctypes.byref(nb), None) == L.P2P_OK
+    assert nb.value > 0
+    assert lib.p2p_restructure_interactions(ctypes.byref(t), ctypes.byref(n), None, 7,
+                                            ctypes.byref(inter), None, ctypes.byref(nb), None) == L.P2P_EINVAL
+    t.kind = L.P2P_TREE_GRIDS
+    st = lib.p2p_restructure_interactions(ctypes.byref(t), ctypes.byref(n), None, L.P2P_FP64,
+                                          ctypes.byref(inter), None, ctypes.byref(nb), None)
+    assert st == L.P2P_EINVAL and "particle tree" in L.last_error()
+    t.kind = L.P2P_TREE_PARTICLES
+    # evaluation: an unbuilt layout, a negative eps, a missing layout
+    z = ctypes.c_void_p(0x1000)
+    inter.prec = 9
+    assert lib.p2p_eval_gravity_interactions(ctypes.byref(t), ctypes.byref(n), ctypes.byref(inter), 1e-3,
+                                             z, z, z, z, None, ctypes.byref(nb), None) == L.P2P_EINVAL
+    inter.prec = L.P2P_FP64
+    assert lib.p2p_eval_gravity_interactions(ctypes.byref(t), ctypes.byref(n), ctypes.byref(inter), -1.0,
+                                             z, z, z, z, None, ctypes.byref(nb), None) == L.P2P_EINVAL
+    assert lib.p2p_eval_gravity_interactions(ctypes.byref(t), ctypes.byref(n), None, 1e-3,
+                                             z, z, z, z, None, ctypes.byref(nb), None) == L.P2P_EINVAL
+    assert lib.p2p_eval_gravity_interactions(ctypes.byref(t), ctypes.byref(n), ctypes.byref(inter), 1e-3,
+                                             z, z, z, z, None, ctypes.byref(nb), None) == L.P2P_OK

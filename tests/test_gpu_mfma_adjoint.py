@@ -41,7 +41,7 @@ def test_helmholtz_mfma_parity(sides, nrhs):
     ref = oracle.helmholtz(sides, q)
     gq = _t(q)
     red = api.restructure(gt, gn, [gq], prec="fp32", nrhs=nrhs)
-    # payload bit-exact (rows of 8 nrhs bytes: the source-major copy)
+    # payload bit-exact (rows of 8 nrhs bytes in 16-byte units)
     ot = oracle.build_tree_grids(sides)
     os_, oi = oracle.neighbors(ot)
     rs, _, S = oracle.red_offsets(ot, os_, oi)

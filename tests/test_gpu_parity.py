@@ -97,6 +97,36 @@ def test_tree_neighbors_restructure_bit_exact(gen, n, seed, depth, cap):
             np.testing.assert_array_equal(_n(red.planes[0])[:S].view(np.uint32), want.view(np.uint32))
 
 
+@pytest.mark.parametrize("gen,n,seed,depth,cap", PARTICLE_CASES[:4] + PARTICLE_CASES[6:])
+@pytest.mark.parametrize("eps", [1e-3, 0.0])
+def test_interaction_layout_parity(gen, n, seed, depth, cap, eps):
+    """Per-interaction layout: records bit-exact against the oracle, sums
+    within the tolerances, with lists that carry S and lists that do not."""
+    x, y, z, m = _particles_case(gen, n, seed, depth, cap)
+    print(f"case interactions {gen} n={n} eps={eps}", flush=True)
+    gx, gy, gz, gm = (_t(v) for v in (x, y, z, m))
+    gt = api.Tree.build_particles(gx, gy, gz, depth=depth, leaf_cap=cap)
+    gn = gt.neighbors()
+    ot = oracle.build_tree_particles(x, y, z, depth=depth, leaf_cap=cap)
+    os_, oi = oracle.neighbors(ot)
+    ref = oracle.gravity(x, y, z, m, eps, ot)
+    for prec, tol in (("fp64", TOL64), ("fp32", TOL32)):
+        rec, rows = oracle.restructure_interactions(ot, os_, oi, x, y, z, m, prec=prec)
+        for lists in (gn, dataclasses.replace(gn, red_entries=-1)):
+            inter = api.restructure_interactions(gt, lists, gx, gy, gz, gm, prec=prec)
+            assert inter.count == len(rows)
+            np.testing.assert_array_equal(_n(inter.rec_start), rec)
+            got = _n(inter.rows)[:len(rows)]
+            if prec == "fp64":
+                np.testing.assert_array_equal(got.view(np.uint64), rows.view(np.uint64))
+            else:
+                np.testing.assert_array_equal(got.view(np.uint32), rows.view(np.uint32))
+        o = [_n(v) for v in api.gravity_interactions(gt, gn, inter, eps)]
+        e_phi, e_a = _rel(o[0], ref[0]), _rel(np.stack(o[1:]), np.stack(ref[1:]))
+        print(f"  {prec}: phi {e_phi:.2e} a {e_a:.2e}", flush=True)
+        assert e_phi <= tol and e_a <= tol
+
+
 def test_long_near_lists():
     """Lists longer than the 64 entries the counting pass keeps per leaf."""
     x, y, z, m = W.slab_particles(4000, 16, 5e-4, seed=12)
@@ -213,6 +243,18 @@ def test_full_size_plummer_2m_sampled():
         assert e_phi <= TOL32 and e_a <= TOL32
     loc = api.locality(gt, gn, red)
     assert loc["entries"] == red.count == int(occ[gi].sum())
+    del red, p4
+    # per-interaction layout at full size: record offsets of the sampled
+    # leaves and the sampled sums
+    inter = api.restructure_interactions(gt, gn, gx, gy, gz, gm, prec="fp32")
+    assert inter.count == len(gi) + 2 * loc["entries"]
+    rec = _n(inter.rec_start)
+    lens = 1 + occ[np.repeat(np.arange(ot.n_leaves), np.diff(gs))] + occ[gi]
+    np.testing.assert_array_equal(rec, np.concatenate([[0], np.cumsum(lens)]))
+    o = [_n(v)[idx] for v in api.gravity_interactions(gt, gn, inter, w["eps"])]
+    e_phi, e_a = _rel(o[0], rp), _rel(np.stack(o[1:]), np.stack([rax, ray, raz]))
+    print(f"  fp32 per-interaction: phi {e_phi:.2e} a {e_a:.2e}", flush=True)
+    assert e_phi <= TOL32 and e_a <= TOL32
 
 
 # --------------------------------------------------------------- Helmholtz

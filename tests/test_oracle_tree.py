@@ -237,3 +237,40 @@ def test_relative_payload_from_rows_and_centres():
         span = np.max(t.size) * 2.0 ** -20
         assert np.all(np.abs(p4[:, d]) <= 1.5 * span + 1e-12)
     np.testing.assert_array_equal(p4[:, 3], oracle.restructure_rows(t, start, idx, rs, m).astype(np.float32))
+
+
+def test_interaction_records_from_segments():
+    # the per-interaction records (Sec. 5.2.1) hold, for every near-list entry
+    # (A, B), a header (occ_A, occ_B, A, B), A's rows and B's rows; the source
+    # part equals B's slice of A's box-grain segment and the target part A's own
+    # slice (at red_self), and with the symmetric near relation the records hold
+    # E headers plus 2 S rows
+    x, y, z, m = W.plummer_mixture(2500, 17)
+    t = oracle.build_tree_particles(x, y, z, depth=20, leaf_cap=24)
+    start, idx = oracle.neighbors(t)
+    rs, rself, S = oracle.red_offsets(t, start, idx)
+    E = len(idx)
+    occ = np.diff(t.leaf_start)
+    rec8, r8 = oracle.restructure_interactions(t, start, idx, x, y, z, m, prec="fp64")
+    rec4, r4 = oracle.restructure_interactions(t, start, idx, x, y, z, m, prec="fp32")
+    np.testing.assert_array_equal(rec8, rec4)
+    assert rec8[-1] == E + 2 * S == len(r8) == len(r4)
+    seg8 = oracle.restructure_rows(t, start, idx, rs, np.stack([x, y, z, m], 1))
+    seg4 = oracle.restructure_gravity_rel(t, start, idx, rs, x, y, z, m)
+    lo, hi = _cube_bounds(t)
+    for A in range(t.n_leaves):
+        off = rs[A]
+        for e in range(start[A], start[A + 1]):
+            B = idx[e]
+            r = rec8[e]
+            assert list(r8[r]) == [occ[A], occ[B], A, B]
+            assert list(r4[r].view(np.int32)) == [occ[A], occ[B], A, B]
+            tgt8, src8 = r8[r + 1:r + 1 + occ[A]], r8[r + 1 + occ[A]:r + 1 + occ[A] + occ[B]]
+            np.testing.assert_array_equal(src8, seg8[off:off + occ[B]])
+            np.testing.assert_array_equal(tgt8, seg8[rs[A] + rself[A]:rs[A] + rself[A] + occ[A]])
+            np.testing.assert_array_equal(r4[r + 1 + occ[A]:r + 1 + occ[A] + occ[B]], seg4[off:off + occ[B]])
+            np.testing.assert_array_equal(r4[r + 1:r + 1 + occ[A]],
+                                          seg4[rs[A] + rself[A]:rs[A] + rself[A] + occ[A]])
+            # the targets lie in A's cube (geometry, independent of the segments)
+            assert np.all((tgt8[:, :3] >= lo[A]) & (tgt8[:, :3] < hi[A]))
+            off += occ[B]
