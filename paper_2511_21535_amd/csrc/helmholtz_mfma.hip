@@ -174,7 +174,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                     load(Gc, Qc, ks, gbuf[ks & 3], qbuf[ks & 3]);
                 else
                     load(Gn, Qn, ks - 32, gbuf[ks & 3], qbuf[ks & 3]);
+                // keep the prefetch where it is: without the barrier the
+                // scheduler sinks each load down to its first use, and every
+                // k-step then waits out a full L2 round trip
+                __builtin_amdgcn_sched_barrier(0);
                 mma(gbuf[kk & 3], qbuf[kk & 3]);
+                __builtin_amdgcn_sched_barrier(0);
             }
             Gc = Gn;
             Qc = Qn;
