@@ -11,7 +11,8 @@ the stream the library launches on.
 
 value = pairs / (restructure + redundant evaluation), over the K timed steps.
 The line also carries the rate without the restructure, the gather rate, the
-sub-step times, the Locality metric, the roofline of the dominant kernel
+sub-step times, the Locality metric with the paper's speedup model evaluated on
+the measured times (Sec. 3.2-3.4), the roofline of the dominant kernel
 (the redundant evaluation) and the FP64 CPU oracle timed on the workload.
 Gravity lines also time the per-interaction layout (one record per near-list
 entry, results per record summed afterwards) on the same tree and lists,
@@ -40,6 +41,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+from paper_2511_21535_amd import speedup_model  # noqa: E402  (host arithmetic only)
+
 DEFAULT_WORKLOAD = "gravity_plummer_2m"
 METRIC = "near-field pair-interactions/s, redundant vs gather layout (incl. restructure)"
 
@@ -57,6 +60,7 @@ SLOTS_PER_PAIR_FP64 = 3 + 3 + 4 + 3 + 1 + 3         # = 17
 # FP32 vector FMA without packed issue: 256 CUs x 64 lanes x 2 flop x 2.4 GHz
 FP32_VALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12  # = 78.6
 FP32_MFMA_PEAK_TFLOPS = 157.3                        # dense FP32 matrix (published)
+CACHE_BYTES = 32.0 * 2 ** 20                         # C of the Locality metric: 8 XCDs x 4 MB L2
 
 
 def parse():
@@ -219,7 +223,7 @@ def run_gravity(wname, args):
 
     tree = api.Tree.build_particles(gx, gy, gz, depth=w["depth"], leaf_cap=w["leaf_cap"])
     nbrs = tree.neighbors()
-    loc = api.locality(tree, nbrs, bytes_per_entry=bpe, cache_bytes=32.0 * 2 ** 20)
+    loc = api.locality(tree, nbrs, bytes_per_entry=bpe, cache_bytes=CACHE_BYTES)
     S, pairs = int(loc["entries"]), int(loc["pairs"])
     red = api.restructure_gravity(tree, nbrs, gx, gy, gz, gm, prec=prec, S=S)
     outs = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(4)]
@@ -272,6 +276,8 @@ def run_gravity(wname, args):
         "ms": {"tree": t_tree / K * 1e3, "neighbors": t_nbr / K * 1e3, "restructure": t_res / K * 1e3,
                "eval_redundant": t_red / K * 1e3, "eval_gather": t_gat / K * 1e3},
         "locality": {k: loc[k] for k in ("d_mean", "d_ratio", "v_ratio", "locality")},
+        "speedup_model": speedup_model.evaluate({"compute": t_gat}, {"collect": t_res, "compute": t_red},
+                                                loc["d_ratio"], loc["v_ratio"], S * bpe, CACHE_BYTES),
         "roofline": {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": peak,
                      "unit": "T VALU lane-slots/s", "frac": achieved / peak,
                      "traffic": traffic["bytes"] if traffic else None,
@@ -323,7 +329,7 @@ def run_helmholtz(wname, args):
     gq = torch.as_tensor(q if nrhs > 1 else q[:, 0].copy(), device=dev)
     tree = api.Tree.build_grids(grids, device=dev)
     nbrs = tree.neighbors()
-    loc = api.locality(tree, nbrs, bytes_per_entry=8.0 * nrhs, cache_bytes=32.0 * 2 ** 20)
+    loc = api.locality(tree, nbrs, bytes_per_entry=8.0 * nrhs, cache_bytes=CACHE_BYTES)
     S, pairs = int(loc["entries"]), int(loc["pairs"])
     red = api.restructure(tree, nbrs, [gq], prec="fp32", nrhs=nrhs, S=S)
     mfma = nrhs % 32 == 0
@@ -382,6 +388,8 @@ def run_helmholtz(wname, args):
         "ms": {"tree": t_tree / K * 1e3, "neighbors": t_nbr / K * 1e3, "restructure": t_res / K * 1e3,
                "eval_redundant": t_red / K * 1e3, "eval_gather": t_gat / K * 1e3},
         "locality": {k: loc[k] for k in ("d_mean", "d_ratio", "v_ratio", "locality")},
+        "speedup_model": speedup_model.evaluate({"compute": t_gat}, {"collect": t_res, "compute": t_red},
+                                                loc["d_ratio"], loc["v_ratio"], S * 8.0 * nrhs, CACHE_BYTES),
         "roofline": roof,
     })
     if not args.no_cpu:
