@@ -191,7 +191,7 @@ extern "C" p2p_status p2p_build_tree(const double *x, const double *y, const dou
         tree->n_leaves = L;
         return fail(P2P_ECAPACITY, "cap_leaves " + std::to_string(tree->cap_leaves) + " < " + std::to_string(L) + " leaves");
     }
-    P2P_TRY(launch_leaf_write(keys, level, flags, flag_scan, n, tree->kind, key_bits, tree->leaf_start,
+    P2P_TRY(launch_leaf_write(keys, level, flags, flag_scan, n, tree->kind, tree->leaf_start,
                               tree->leaf_key, tree->leaf_level, &counters[1], s));
     P2P_TRY(launch_perm_and_inverse(vals, n, tree->perm, tree->iperm, s));
     int32_t maxl = 0;

@@ -46,7 +46,7 @@ __device__ int64_t g_load_nbr_chunk(const int32_t *__restrict__ leaf_start,
                                     const int32_t *__restrict__ nbr_idx, int64_t c0, int nc,
                                     int64_t *s_pre, int32_t *s_first, int64_t *s_w) {
     int32_t occ = 0, first = 0;
-    if (threadIdx.x < nc) {
+    if (static_cast<int>(threadIdx.x) < nc) {
         const int32_t B = nbr_idx[c0 + threadIdx.x];
         first = leaf_start[B];
         occ = leaf_start[B + 1] - first;
@@ -272,7 +272,7 @@ __device__ __forceinline__ void gravity_body(const GravityArgs &a) {
         s_red[2][threadIdx.x] = active ? fy : 0.0;
         s_red[3][threadIdx.x] = active ? fz : 0.0;
         __syncthreads();
-        if (threadIdx.x < tc) {
+        if (static_cast<int>(threadIdx.x) < tc) {
             double sp_ = 0.0, sx_ = 0.0, sy_ = 0.0, sz_ = 0.0;
             for (int q = 0; q < G; ++q) {
                 const int l = q * tc + threadIdx.x;
@@ -372,7 +372,7 @@ __global__ __launch_bounds__(kGBlock) void k_gravity_adjoint(GravityAdjointArgs 
         s_red[2 * kGBlock + threadIdx.x] = active ? oy : 0.0;
         s_red[3 * kGBlock + threadIdx.x] = active ? oz : 0.0;
         __syncthreads();
-        if (threadIdx.x < tc) {
+        if (static_cast<int>(threadIdx.x) < tc) {
             double r[4] = {0.0, 0.0, 0.0, 0.0};
             for (int q = 0; q < G; ++q)
                 for (int c = 0; c < 4; ++c) r[c] += s_red[c * kGBlock + q * tc + threadIdx.x];

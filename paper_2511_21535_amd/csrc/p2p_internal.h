@@ -83,14 +83,15 @@ p2p_status launch_leaf_levels(const uint64_t *skeys, int64_t n, int kind, int de
                               uint8_t *pair_common, int8_t *level, int32_t *flags, hipStream_t s);
 p2p_status launch_perm_and_inverse(const int32_t *vals, int64_t n, int32_t *perm, int32_t *iperm,
                                    hipStream_t s);
+// Leaf arrays from the start flags and their scan, then the deepest level into
+// *max_level.
 p2p_status launch_leaf_write(const uint64_t *skeys, const int8_t *level, const int32_t *flags,
-                             const int32_t *flag_scan, int64_t n, int kind, int key_bits,
-                             int32_t *leaf_start, uint64_t *leaf_key, int8_t *leaf_level,
-                             int32_t *max_level, hipStream_t s);
+                             const int32_t *flag_scan, int64_t n, int kind, int32_t *leaf_start,
+                             uint64_t *leaf_key, int8_t *leaf_level, int32_t *max_level,
+                             hipStream_t s);
 
-// Near lists (nbrs.hip).  count pass (out_idx == nullptr) or fill pass.
-// Directory over the top bits of the leaf keys (dir: (1 << neighbor_dir_bits) + 1
-// entries), then the count pass (nbr_idx == nullptr) or the fill pass.
+// Near lists (nbrs.hip).  Directory over the top bits of the leaf keys (dir:
+// (1 << neighbor_dir_bits) + 1 entries); it also clears the overflow counter.
 int neighbor_dir_bits(int total_key_bits);
 p2p_status launch_key_directory(const uint64_t *leaf_key, int64_t L, int total_key_bits, int32_t *dir,
                                 int32_t *overflow, hipStream_t s);
@@ -136,8 +137,7 @@ p2p_status launch_copy_segments(const T *sorted, int64_t row_len, const int32_t 
 // stores; smaller ones stay in the 256 MB last-level cache for the evaluation.
 constexpr int64_t kStreamingLayoutBytes = int64_t(128) << 20;
 
-// Gravity (gravity.hip).
-// Per-interaction layout (gravity): one record per near-list entry e = (A, B),
+// Per-interaction layout (interactions.hip): one record per near-list entry e = (A, B),
 // a header row (occ_A, occ_B, A, B as integers) then A's rows then B's rows,
 // FP32_MIXED float4 relative to the centre of A, or FP64 rows.
 p2p_status launch_record_lengths(const int32_t *leaf_start, const int64_t *nbr_start,
@@ -158,6 +158,7 @@ p2p_status launch_reduce_records(const int32_t *leaf_start, const int64_t *nbr_s
                                  const Row4d *res, double *phi, double *ax, double *ay, double *az,
                                  hipStream_t s);
 
+// Gravity (gravity.hip).
 struct GravityArgs {
     int64_t L;
     const int32_t *leaf_start;

@@ -123,7 +123,7 @@ __device__ int64_t load_nbr_chunk(const int32_t *__restrict__ leaf_start,
                                   const int32_t *__restrict__ nbr_idx, int64_t c0, int nc,
                                   int64_t *s_pre, int32_t *s_first, int64_t *s_w) {
     int32_t occ = 0, first = 0;
-    if (threadIdx.x < nc) {
+    if (static_cast<int>(threadIdx.x) < nc) {
         const int32_t B = nbr_idx[c0 + threadIdx.x];
         first = leaf_start[B];
         occ = leaf_start[B + 1] - first;

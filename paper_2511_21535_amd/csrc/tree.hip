@@ -113,10 +113,8 @@ __global__ void k_leaf_flag_grids(const uint64_t *__restrict__ sk, int64_t n,
 __global__ void k_leaf_write(const uint64_t *__restrict__ sk, const int8_t *__restrict__ level,
                              const int32_t *__restrict__ flag, const int32_t *__restrict__ fscan,
                              int64_t n, int kind, int32_t *__restrict__ leaf_start,
-                             uint64_t *__restrict__ leaf_key, int8_t *__restrict__ leaf_level,
-                             int32_t *__restrict__ max_level) {
+                             uint64_t *__restrict__ leaf_key, int8_t *__restrict__ leaf_level) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    (void)max_level;
     if (i < n) {
         if (i == 0) leaf_start[fscan[n]] = static_cast<int32_t>(n);
         if (flag[i]) {
@@ -214,13 +212,12 @@ p2p_status launch_leaf_levels(const uint64_t *skeys, int64_t n, int kind, int de
 }
 
 p2p_status launch_leaf_write(const uint64_t *skeys, const int8_t *level, const int32_t *flags,
-                             const int32_t *flag_scan, int64_t n, int kind, int key_bits,
-                             int32_t *leaf_start, uint64_t *leaf_key, int8_t *leaf_level,
-                             int32_t *max_level, hipStream_t s) {
+                             const int32_t *flag_scan, int64_t n, int kind, int32_t *leaf_start,
+                             uint64_t *leaf_key, int8_t *leaf_level, int32_t *max_level,
+                             hipStream_t s) {
     if (n <= 0) return P2P_OK;
-    (void)key_bits;
     k_leaf_write<<<grid_for(n, 256), 256, 0, s>>>(skeys, level, flags, flag_scan, n, kind,
-                                                  leaf_start, leaf_key, leaf_level, max_level);
+                                                  leaf_start, leaf_key, leaf_level);
     P2P_LAUNCH_CHECK();
     k_max_level<<<1, 1024, 0, s>>>(leaf_level, flag_scan, n, max_level);
     P2P_LAUNCH_CHECK();
