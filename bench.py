@@ -333,9 +333,9 @@ def run_helmholtz(wname, args):
     S, pairs = int(loc["entries"]), int(loc["pairs"])
     red = api.restructure(tree, nbrs, [gq], prec="fp32", nrhs=nrhs, S=S)
     mfma = nrhs % 32 == 0
-    tile = None
+    tile, tune_ms = None, {}
     if mfma:
-        tile, _ = autotune.tune_helmholtz(tree, nbrs, q=gq, layout="gather")
+        tile, tune_ms = autotune.tune_helmholtz(tree, nbrs, q=gq, layout="gather")
     out = torch.empty_like(gq)
 
     def step():
@@ -392,6 +392,10 @@ def run_helmholtz(wname, args):
                                                 loc["d_ratio"], loc["v_ratio"], S * 8.0 * nrhs, CACHE_BYTES),
         "roofline": roof,
     })
+    if tile:
+        # the best launch shape with 1, 2, 4 and 8 copies of the G blocks (ms per call)
+        line["g_block_copies_ms"] = {json.loads(k)[3]: v for k, v in tune_ms.items()
+                                     if json.loads(k)[:3] == list(tile[:3])}
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline_helmholtz(sides, q if nrhs > 1 else q[:, 0],
                                                       20000 if nrhs == 1 else 400, unit)

@@ -247,11 +247,13 @@ p2p_status p2p_eval_gravity(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2
  * nrhs a multiple of 32 runs on FP32 matrix cores (v_mfma_f32_32x32x2f32) in
  * one persistent launch over all boxes of all instances, taking boxes from a
  * work queue ordered by decreasing near-list length; instances whose k h
- * agree to 1e-12 share one set of G blocks.  `tile` (host int32[3], may be
- * NULL = default {4, 2, 64 or 32}) is the launch shape the autotuner picked:
+ * agree to 1e-12 share one set of G blocks.  `tile` (host int32[4], may be
+ * NULL = default {4, 2, 64 or 32, 1}) is the launch shape the autotuner picked:
  * tile[0] = waves per workgroup (1, 2 or 4), tile[1] = workgroups per compute
- * unit (1..16), tile[2] = right-hand sides per wave (32 or 64, dividing nrhs);
- * other paths reject a non-NULL tile with P2P_EINVAL. */
+ * unit (1..16), tile[2] = right-hand sides per wave (32 or 64, dividing nrhs),
+ * tile[3] = copies of the G blocks in memory (1, 2, 4 or 8; the block-level
+ * pattern redundancy factor of Sec. 5.1.2, the workgroups of one XCD reading
+ * different copies); other paths reject a non-NULL tile with P2P_EINVAL. */
 p2p_status p2p_eval_helmholtz(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2p_redundant *red,
                               p2p_layout layout, p2p_precision prec,
                               const p2p_grid *grids, int32_t n_grids, int32_t nrhs,

@@ -365,7 +365,8 @@ def helmholtz(tree: Tree, nbrs: Nbrs, q: Optional[torch.Tensor] = None, layout="
     gs, _ = grids_struct(tree.grids)
     ts, ns = tree.struct(), nbrs.struct()
     rs = red.struct() if red is not None else None
-    tl = (ctypes.c_int32 * 3)(*tile) if tile is not None else None
+    # (waves per workgroup, workgroups per CU, RHS per wave[, copies of the G blocks])
+    tl = (ctypes.c_int32 * 4)(*(tuple(tile) + (1,) * (4 - len(tile)))) if tile is not None else None
 
     def call(ws, nb):
         return L.p2p_eval_helmholtz(ctypes.byref(ts), ctypes.byref(ns),

@@ -525,12 +525,15 @@ p2p_status helmholtz_common(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2
     P2P_TRY(check_grids(grids, n_grids, tree->n));
     const bool fp64 = prec == P2P_FP64, redundant = layout == P2P_REDUNDANT;
     const bool mfma = !fp64 && nrhs % 32 == 0;
-    int waves_per_wg = 4, wg_per_cu = 2, rhs_tile = (nrhs % 64 == 0) ? 64 : 32;
+    int waves_per_wg = 4, wg_per_cu = 2, rhs_tile = (nrhs % 64 == 0) ? 64 : 32, copies = 1;
     if (tile) {
         if (!mfma) return fail(P2P_EINVAL, "tile applies to the matrix-core path (FP32_MIXED, nrhs % 32 == 0)");
         waves_per_wg = tile[0];
         wg_per_cu = tile[1];
         rhs_tile = tile[2];
+        copies = tile[3];
+        if (copies != 1 && copies != 2 && copies != 4 && copies != 8)
+            return fail(P2P_EINVAL, "tile[3] (copies of the G blocks) must be 1, 2, 4 or 8");
         if (waves_per_wg != 1 && waves_per_wg != 2 && waves_per_wg != 4)
             return fail(P2P_EINVAL, "tile[0] (waves per workgroup) must be 1, 2 or 4");
         if (wg_per_cu < 1 || wg_per_cu > 16) return fail(P2P_EINVAL, "tile[1] (workgroups per CU) must be in 1..16");
@@ -566,7 +569,7 @@ p2p_status helmholtz_common(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2
     double *d_k = ar.take<double>(n_grids);
     char *table = mfma ? nullptr : ar.take<char>(static_cast<size_t>(n_grids) * kTableLen * csize);
     double *d_kh = mfma ? ar.take<double>(n_tables) : nullptr;
-    float2 *blocks = mfma ? ar.take<float2>(static_cast<size_t>(n_tables) * 27 * 4096) : nullptr;
+    float2 *blocks = mfma ? ar.take<float2>(static_cast<size_t>(n_tables) * copies * 27 * 4096) : nullptr;
     int32_t *d_itab = mfma ? ar.take<int32_t>(n_grids) : nullptr;
     float *d_iscale = mfma ? ar.take<float>(n_grids) : nullptr;
     int32_t *work = mfma ? ar.take<int32_t>(L) : nullptr;
@@ -601,7 +604,7 @@ p2p_status helmholtz_common(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2
         P2P_HIP(hipMemcpyAsync(d_kh, khs.data(), n_tables * sizeof(double), hipMemcpyHostToDevice, s));
         P2P_HIP(hipMemcpyAsync(d_itab, itab.data(), n_grids * sizeof(int32_t), hipMemcpyHostToDevice, s));
         P2P_HIP(hipMemcpyAsync(d_iscale, iscale.data(), n_grids * sizeof(float), hipMemcpyHostToDevice, s));
-        P2P_TRY(launch_green_blocks(d_kh, n_tables, blocks, s));
+        P2P_TRY(launch_green_blocks(d_kh, n_tables, copies, blocks, s));
         P2P_TRY(launch_work_order(nbrs->nbr_start, L, work, wkeys, wkeys_tmp, wvals_tmp, whist, s));
         HelmholtzMfmaArgs a{};
         a.L = L;
@@ -614,6 +617,7 @@ p2p_status helmholtz_common(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2
         a.red_start = redundant ? red->red_start : nullptr;
         a.src = redundant ? static_cast<const float2 *>(red->planes[0]) : reinterpret_cast<const float2 *>(sorted);
         a.blocks = blocks;
+        a.copies = copies;
         a.inst_table = d_itab;
         a.inst_scale = d_iscale;
         a.work = work;

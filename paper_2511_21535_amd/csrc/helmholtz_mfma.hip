@@ -21,6 +21,11 @@
 // Work distribution: waves take boxes from an atomic counter over a list
 // ordered by decreasing near-list length (longest processing time first),
 // and exit when the list is exhausted.
+//
+// The G blocks can be held in several identical copies (the block-level
+// pattern redundancy of the paper's electromagnetic case, Sec. 5.1.2, there
+// with a redundancy factor RF): the workgroups of one XCD then read different
+// copies, spreading the pattern loads over more L2 lines and channels.
 #include "p2p_internal.h"
 
 namespace p2p {
@@ -29,14 +34,15 @@ namespace {
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 constexpr double kPi = 3.14159265358979323846;
 
-// blocks[t][o][s][i] = e^{i kh sqrt(dd)} / (4 pi sqrt(dd)), dd = |l_i - (l_s + 4 o)|^2,
-// zero for dd = 0.  o = (ox+1) + 3 (oy+1) + 9 (oz+1); l_* are local Morton coordinates.
-__global__ void k_green_blocks(const double *__restrict__ kh, int32_t n_tables,
+// blocks[t][c][o][s][i] = e^{i kh sqrt(dd)} / (4 pi sqrt(dd)), dd = |l_i - (l_s + 4 o)|^2,
+// zero for dd = 0, identical for every copy c.  o = (ox+1) + 3 (oy+1) + 9 (oz+1); l_* are
+// local Morton coordinates.
+__global__ void k_green_blocks(const double *__restrict__ kh, int32_t n_tables, int32_t copies,
                                float2 *__restrict__ blocks) {
     const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t per = 27 * 64 * 64;
-    if (t >= per * n_tables) return;
-    const int tab = static_cast<int>(t / per);
+    if (t >= per * n_tables * copies) return;
+    const int tab = static_cast<int>(t / (per * copies));
     const int rem = static_cast<int>(t % per);
     const int o = rem / 4096, s = (rem / 64) % 64, i = rem % 64;
     const int od[3] = {o % 3 - 1, (o / 3) % 3 - 1, o / 9 - 1};
@@ -78,7 +84,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const uint64_t *__restrict__ leaf_key, const int32_t *__restrict__ perm,
     const int64_t *__restrict__ nbr_start, const int32_t *__restrict__ nbr_idx,
     const int64_t *__restrict__ red_start, const float2 *__restrict__ src,
-    const float2 *__restrict__ blocks, const int32_t *__restrict__ inst_table,
+    const float2 *__restrict__ blocks, int32_t copies, const int32_t *__restrict__ inst_table,
     const float *__restrict__ inst_scale, const int32_t *__restrict__ work,
     int32_t *__restrict__ counter, float2 *__restrict__ u) {
     const int lane = threadIdx.x & 63;
@@ -96,7 +102,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         const int rhs0 = (item % chunks) * 32 * TJ;
         const uint64_t kA = leaf_key[A];
         const int g = static_cast<int>(kA >> (3 * key_bits));
-        const float2 *__restrict__ gbase = blocks + static_cast<int64_t>(inst_table[g]) * (27 * 4096);
+        // the workgroups of one XCD (w % 8 equal) spread over the copies
+        const int64_t copy = (blockIdx.x >> 3) % copies;
+        const float2 *__restrict__ gbase = blocks + (static_cast<int64_t>(inst_table[g]) * copies + copy) * (27 * 4096);
         const uint64_t lA = kA & local_mask;
         const int ax = static_cast<int>(p2pd::compact3(lA)), ay = static_cast<int>(p2pd::compact3(lA >> 1)),
                   az = static_cast<int>(p2pd::compact3(lA >> 2));
@@ -200,9 +208,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 
 }  // namespace
 
-p2p_status launch_green_blocks(const double *d_kh, int32_t n_tables, float2 *blocks, hipStream_t s) {
-    const int64_t n = static_cast<int64_t>(n_tables) * 27 * 4096;
-    k_green_blocks<<<grid_for(n, 256), 256, 0, s>>>(d_kh, n_tables, blocks);
+p2p_status launch_green_blocks(const double *d_kh, int32_t n_tables, int32_t copies, float2 *blocks,
+                               hipStream_t s) {
+    const int64_t n = static_cast<int64_t>(n_tables) * copies * 27 * 4096;
+    k_green_blocks<<<grid_for(n, 256), 256, 0, s>>>(d_kh, n_tables, copies, blocks);
     P2P_LAUNCH_CHECK();
     return P2P_OK;
 }
@@ -220,7 +229,7 @@ template <bool RED, bool CONJ, int TJ>
 static void launch_mfma_t(const HelmholtzMfmaArgs &a, unsigned grid, unsigned block, hipStream_t s) {
     k_helm_mfma<RED, CONJ, TJ><<<grid, block, 0, s>>>(
         a.L, a.key_bits, a.nrhs, a.leaf_start, a.leaf_key, a.perm, a.nbr_start, a.nbr_idx,
-        a.red_start, a.src, a.blocks, a.inst_table, a.inst_scale, a.work, a.counter, a.u);
+        a.red_start, a.src, a.blocks, a.copies, a.inst_table, a.inst_scale, a.work, a.counter, a.u);
 }
 
 p2p_status launch_helmholtz_mfma(const HelmholtzMfmaArgs &a, bool redundant, int waves_per_wg,

@@ -222,7 +222,8 @@ struct HelmholtzMfmaArgs {
     const int32_t *nbr_idx;
     const int64_t *red_start;
     const float2 *src;         // sorted q rows (gather) or redundant rows, [.][nrhs]
-    const float2 *blocks;      // [n_tables][27][64 src][64 tgt] complex G blocks (unit spacing)
+    const float2 *blocks;      // [n_tables][copies][27][64 src][64 tgt] complex G blocks (unit spacing)
+    int32_t copies;            // copies of each table; workgroup w reads copy (w / 8) % copies
     const int32_t *inst_table; // per instance: table index
     const float *inst_scale;   // per instance: 1/h
     const int32_t *work;       // box ids in processing order (longest first)
@@ -231,7 +232,8 @@ struct HelmholtzMfmaArgs {
     int32_t conj;
     float2 *u;                 // caller order [n][nrhs]
 };
-p2p_status launch_green_blocks(const double *d_kh, int32_t n_tables, float2 *blocks, hipStream_t s);
+p2p_status launch_green_blocks(const double *d_kh, int32_t n_tables, int32_t copies, float2 *blocks,
+                               hipStream_t s);
 p2p_status launch_work_order(const int64_t *nbr_start, int64_t L, int32_t *work, uint64_t *keys,
                              uint64_t *keys_tmp, int32_t *vals_tmp, uint32_t *hist,
                              hipStream_t s);

@@ -148,3 +148,30 @@ def test_interaction_layout_validation(lib):
                                              z, z, z, z, None, ctypes.byref(nb), None) == L.P2P_EINVAL
     assert lib.p2p_eval_gravity_interactions(ctypes.byref(t), ctypes.byref(n), ctypes.byref(inter), 1e-3,
                                              z, z, z, z, None, ctypes.byref(nb), None) == L.P2P_OK
+
+
+def test_helmholtz_tile_validation(lib):
+    n = 16 ** 3
+    t = _tree(n, L.P2P_TREE_GRIDS, L_=64)
+    t.perm = t.iperm = t.leaf_start = t.leaf_key = t.leaf_level = 0x1000
+    t.n_grids, t.key_bits = 1, 4
+    g = (L.p2p_grid * 1)()
+    g[0].n_side, g[0].h, g[0].k, g[0].point_off = 16, 1 / 16, 1.0, 0
+    nl = L.p2p_nbrs()
+    nl.count, nl.nbr_start, nl.nbr_idx = 64, 0x1000, 0x1000
+    nb = ctypes.c_size_t(0)
+    z = ctypes.c_void_p(0x1000)
+
+    def query(tile, nrhs=64, prec=L.P2P_FP32_MIXED):
+        tl = (ctypes.c_int32 * 4)(*tile) if tile is not None else None
+        return lib.p2p_eval_helmholtz(ctypes.byref(t), ctypes.byref(nl), None, L.P2P_GATHER, prec, g, 1,
+                                      nrhs, z, z, tl, None, ctypes.byref(nb), None)
+    assert query((4, 2, 64, 1)) == L.P2P_OK
+    small = nb.value
+    assert query((4, 2, 64, 8)) == L.P2P_OK and nb.value > small    # eight copies of the G blocks
+    assert query((4, 2, 64, 3)) == L.P2P_EINVAL and "tile[3]" in L.last_error()
+    assert query((3, 2, 64, 1)) == L.P2P_EINVAL and "tile[0]" in L.last_error()
+    assert query((4, 0, 64, 1)) == L.P2P_EINVAL and "tile[1]" in L.last_error()
+    assert query((4, 2, 64, 1), nrhs=32) == L.P2P_EINVAL and "tile[2]" in L.last_error()
+    assert query((4, 2, 32, 1), nrhs=1) == L.P2P_EINVAL          # no tile off the matrix-core path
+    assert query(None, nrhs=1) == L.P2P_OK
