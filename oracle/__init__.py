@@ -73,17 +73,21 @@ def _declare(lib):
     lib.orc_neighbors.restype = I64
     lib.orc_neighbors.argtypes = [I64, P, P, P, P, I64, P, P, I64]
     lib.orc_red_offsets.restype = I64
-    lib.orc_red_offsets.argtypes = [I64, P, P, P, P, P]
+    lib.orc_red_offsets.argtypes = [I64, P, P, P, P, P, P]
     lib.orc_restructure_rows.restype = None
     lib.orc_restructure_rows.argtypes = [I64, P, P, P, P, P, P, I64, P]
     lib.orc_restructure_gravity_rel.restype = None
-    lib.orc_restructure_gravity_rel.argtypes = [I64, P, P, P, P, P, P, P, P, P, P, P, P]
+    lib.orc_restructure_gravity_rel.argtypes = [I64, P, P, P, P, P, P, P, P, P, P, P, P, P]
+    lib.orc_restructure_gravity_rows.restype = None
+    lib.orc_restructure_gravity_rows.argtypes = [I64, P, P, P, P, P, P, P, P, P, P, P]
     lib.orc_restructure_interactions.restype = I64
-    lib.orc_restructure_interactions.argtypes = [I64, P, P, P, P, P, P, P, P, P, P, P, P, P]
+    lib.orc_restructure_interactions.argtypes = [I64, P, P, P, P, P, P, P, P, P, P, P, P, P, P]
+    lib.orc_neighbors_periodic.restype = I64
+    lib.orc_neighbors_periodic.argtypes = [I64, P, P, P, I64, P, P, P, I64]
     lib.orc_gravity_leaves.restype = I64
-    lib.orc_gravity_leaves.argtypes = [P, P, P, P, F64, P, P, P, I64, P, P, P, P, P, P, P]
+    lib.orc_gravity_leaves.argtypes = [P, P, P, P, F64, P, P, P, I64, P, P, P, P, P, P, P, P]
     lib.orc_gravity_adjoint_leaves.restype = I64
-    lib.orc_gravity_adjoint_leaves.argtypes = ([P] * 4 + [F64] + [P] * 4 + [P, P, P, I64, P, P]
+    lib.orc_gravity_adjoint_leaves.argtypes = ([P] * 4 + [F64] + [P] * 4 + [P, P, P, I64, P, P, P]
                                                + [P] * 5)
     lib.orc_helmholtz.restype = None
     lib.orc_helmholtz.argtypes = [I32, P, P, P, P, I32, P, P, I64, P]
@@ -221,17 +225,53 @@ def neighbors(tree: Tree, targets=None):
     return start, idx[:total]
 
 
+def neighbors_periodic(tree: Tree, targets=None):
+    """Periodic near lists on the unit torus (reading R27): every (leaf B,
+    image c) whose cube shifted by image c touches A's, ascending in (c, B);
+    image code c = (sx+1) + 3 (sy+1) + 9 (sz+1) shifts a source by
+    (sx, sy, sz) domain edges, 13 = unshifted.  Brute force.  Returns
+    (nbr_start int64 [T+1], nbr_idx int32 [E], nbr_shift int8 [E])."""
+    if tree.kind != "particles":
+        raise ValueError("periodic images are defined for particle trees only")
+    L = tree.n_leaves
+    if targets is None:
+        targets = np.arange(L, dtype=np.int32)
+    targets = _c(targets, np.int32)
+    T = targets.shape[0]
+    start = np.zeros(T + 1, dtype=np.int64)
+    lib = _load()
+    total = lib.orc_neighbors_periodic(L, _p(tree.anchor), _p(tree.size), _p(targets), T,
+                                       _p(start), None, None, 0)
+    idx = np.zeros(max(total, 1), dtype=np.int32)
+    sh = np.zeros(max(total, 1), dtype=np.int8)
+    lib.orc_neighbors_periodic(L, _p(tree.anchor), _p(tree.size), _p(targets), T, _p(start),
+                               _p(idx), _p(sh), total)
+    return start, idx[:total], sh[:total]
+
+
+def shift_vectors(codes):
+    """Image codes -> shift vectors (sx, sy, sz) in domain edges, float64 [E, 3]."""
+    c = np.asarray(codes, dtype=np.int64)
+    return np.stack([c % 3 - 1, (c // 3) % 3 - 1, c // 9 - 1], axis=-1).astype(np.float64)
+
+
+def _shift_arg(nbr_shift):
+    return None if nbr_shift is None else _p(_c(nbr_shift, np.int8))
+
+
 # ---------------------------------------------------------------------------
 # Redundant layout
 # ---------------------------------------------------------------------------
-def red_offsets(tree: Tree, nbr_start, nbr_idx):
+def red_offsets(tree: Tree, nbr_start, nbr_idx, nbr_shift=None):
     """Segment starts and self offsets of the redundant layout (Sec. 5.2.1:
-    data duplicated so each target reads one contiguous block)."""
+    data duplicated so each target reads one contiguous block).  With image
+    codes the self offset is that of the unshifted image of A."""
     L = tree.n_leaves
     rs = np.zeros(L + 1, dtype=np.int64)
     self_ = np.zeros(max(L, 1), dtype=np.int32)
     S = _load().orc_red_offsets(L, _p(tree.leaf_start), _p(_c(nbr_start, np.int64)),
-                                _p(_c(nbr_idx, np.int32)), _p(rs), _p(self_))
+                                _p(_c(nbr_idx, np.int32)), _shift_arg(nbr_shift), _p(rs),
+                                _p(self_))
     return rs, self_[:L].copy(), int(S)
 
 
@@ -248,21 +288,39 @@ def restructure_rows(tree: Tree, nbr_start, nbr_idx, red_start, src):
     return out
 
 
-def restructure_gravity_rel(tree: Tree, nbr_start, nbr_idx, red_start, x, y, z, m):
-    """FP32-mixed redundant payload: float32 [S, 4] rows (x - c_A, y - c_A,
-    z - c_A, m) with c_A the centre of the segment's target leaf, the
-    difference taken in double and rounded to single."""
+def restructure_gravity_rel(tree: Tree, nbr_start, nbr_idx, red_start, x, y, z, m,
+                            nbr_shift=None):
+    """FP32-mixed redundant payload: float32 [S, 4] rows (x + s - c_A, y + s -
+    c_A, z + s - c_A, m) with c_A the centre of the segment's target leaf and
+    s the entry's image shift, the position taken in double and rounded to
+    single once."""
     S = int(red_start[-1])
     out = np.zeros((max(S, 1), 4), dtype=np.float32)
     arrs = [_c(v, np.float64) for v in (x, y, z, m)]
     _load().orc_restructure_gravity_rel(tree.n_leaves, _p(tree.leaf_start), _p(tree.perm),
                                         _p(_c(nbr_start, np.int64)), _p(_c(nbr_idx, np.int32)),
-                                        _p(_c(red_start, np.int64)), _p(tree.anchor), _p(tree.size),
+                                        _shift_arg(nbr_shift), _p(_c(red_start, np.int64)),
+                                        _p(tree.anchor), _p(tree.size),
                                         *[_p(a) for a in arrs], _p(out))
     return out[:S]
 
 
-def restructure_interactions(tree: Tree, nbr_start, nbr_idx, x, y, z, m, prec="fp64"):
+def restructure_gravity_rows(tree: Tree, nbr_start, nbr_idx, red_start, x, y, z, m,
+                             nbr_shift=None):
+    """FP64 redundant payload: float64 [S, 4] rows (x + s, y + s, z + s, m)
+    with s the entry's image shift (zero without image codes)."""
+    S = int(red_start[-1])
+    out = np.zeros((max(S, 1), 4), dtype=np.float64)
+    arrs = [_c(v, np.float64) for v in (x, y, z, m)]
+    _load().orc_restructure_gravity_rows(tree.n_leaves, _p(tree.leaf_start), _p(tree.perm),
+                                         _p(_c(nbr_start, np.int64)), _p(_c(nbr_idx, np.int32)),
+                                         _shift_arg(nbr_shift), _p(_c(red_start, np.int64)),
+                                         *[_p(a) for a in arrs], _p(out))
+    return out[:S]
+
+
+def restructure_interactions(tree: Tree, nbr_start, nbr_idx, x, y, z, m, prec="fp64",
+                             nbr_shift=None):
     """Per-interaction layout (Sec. 5.2.1): (rec_start [E+1], rows) with one
     record per near-list entry (A, B): header (occ_A, occ_B, A, B), A's rows,
     B's rows.  prec "fp64": float64 [rows, 4], header as doubles; "fp32":
@@ -272,8 +330,8 @@ def restructure_interactions(tree: Tree, nbr_start, nbr_idx, x, y, z, m, prec="f
     rec = np.zeros(E + 1, dtype=np.int64)
     arrs = [_c(v, np.float64) for v in (x, y, z, m)]
     lib = _load()
-    args = (tree.n_leaves, _p(tree.leaf_start), _p(tree.perm), _p(ns), _p(ni), _p(tree.anchor),
-            _p(tree.size), *[_p(a) for a in arrs], _p(rec))
+    args = (tree.n_leaves, _p(tree.leaf_start), _p(tree.perm), _p(ns), _p(ni),
+            _shift_arg(nbr_shift), _p(tree.anchor), _p(tree.size), *[_p(a) for a in arrs], _p(rec))
     rows = lib.orc_restructure_interactions(*args, None, None)
     if prec == "fp64":
         out = np.zeros((max(rows, 1), 4), dtype=np.float64)
@@ -287,9 +345,11 @@ def restructure_interactions(tree: Tree, nbr_start, nbr_idx, x, y, z, m, prec="f
 # ---------------------------------------------------------------------------
 # Gravity
 # ---------------------------------------------------------------------------
-def gravity_leaves(x, y, z, m, eps, tree: Tree, sel, sel_nbr_start, sel_nbr_idx):
+def gravity_leaves(x, y, z, m, eps, tree: Tree, sel, sel_nbr_start, sel_nbr_idx,
+                   sel_nbr_shift=None):
     """Near-field gravity for the particles of the selected leaves (reading R1:
-    G = 1, phi negative, Plummer softening).  Returns (caller idx, phi, ax, ay, az)."""
+    G = 1, phi negative, Plummer softening; with image codes each source sits
+    at x_j + s).  Returns (caller idx, phi, ax, ay, az)."""
     x, y, z, m = (_c(v, np.float64) for v in (x, y, z, m))
     sel = _c(sel, np.int32)
     occ = np.diff(tree.leaf_start)
@@ -299,12 +359,13 @@ def gravity_leaves(x, y, z, m, eps, tree: Tree, sel, sel_nbr_start, sel_nbr_idx)
     _load().orc_gravity_leaves(_p(x), _p(y), _p(z), _p(m), float(eps), _p(tree.perm),
                                _p(tree.leaf_start), _p(sel), sel.shape[0],
                                _p(_c(sel_nbr_start, np.int64)), _p(_c(sel_nbr_idx, np.int32)),
-                               _p(idx), *[_p(o) for o in outs])
+                               _shift_arg(sel_nbr_shift), _p(idx), *[_p(o) for o in outs])
     return (idx[:T],) + tuple(o[:T] for o in outs)
 
 
 def gravity(x, y, z, m, eps, tree: Tree, nbr=None):
-    """Near-field gravity for every particle, in caller order."""
+    """Near-field gravity for every particle, in caller order.  `nbr` is
+    (nbr_start, nbr_idx) or, with periodic images, (.., .., nbr_shift)."""
     if nbr is None:
         nbr = neighbors(tree)
     sel = np.arange(tree.n_leaves, dtype=np.int32)
@@ -317,7 +378,7 @@ def gravity(x, y, z, m, eps, tree: Tree, nbr=None):
 
 
 def gravity_adjoint_leaves(x, y, z, m, eps, gp, gax, gay, gaz, tree: Tree, sel, sel_nbr_start,
-                           sel_nbr_idx):
+                           sel_nbr_idx, sel_nbr_shift=None):
     """Reverse-mode derivative of near-field gravity w.r.t. m and x for the
     particles of the selected leaves.  Returns (caller idx, gm, gx, gy, gz)."""
     arrs = [_c(v, np.float64) for v in (x, y, z, m, gp, gax, gay, gaz)]
@@ -330,7 +391,8 @@ def gravity_adjoint_leaves(x, y, z, m, eps, gp, gax, gay, gaz, tree: Tree, sel, 
                                        *[_p(a) for a in arrs[4:]], _p(tree.perm),
                                        _p(tree.leaf_start), _p(sel), sel.shape[0],
                                        _p(_c(sel_nbr_start, np.int64)),
-                                       _p(_c(sel_nbr_idx, np.int32)), _p(idx),
+                                       _p(_c(sel_nbr_idx, np.int32)),
+                                       _shift_arg(sel_nbr_shift), _p(idx),
                                        *[_p(o) for o in outs])
     return (idx[:T],) + tuple(o[:T] for o in outs)
 

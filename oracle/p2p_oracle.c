@@ -282,23 +282,84 @@ int64_t orc_neighbors(int64_t L, const int32_t *anchor, const int32_t *size, con
     return total;
 }
 
+/* Periodic images (the periodic interactions of the stellar-dynamics case,
+ * Sec. 5.2): image code c = (sx+1) + 3 (sy+1) + 9 (sz+1), sx, sy, sz in
+ * {-1, 0, 1}, shifts a source by (sx, sy, sz) domain edges; code 13 is no
+ * shift.  A NULL shift array means code 13 for every entry. */
+static void orc_shift_of(const int8_t *shift, int64_t e, double s[3])
+{
+    int c = shift ? shift[e] : 13;
+    s[0] = (double)(c % 3 - 1);
+    s[1] = (double)((c / 3) % 3 - 1);
+    s[2] = (double)(c / 9 - 1);
+}
+
+static int orc_shift_code(const int8_t *shift, int64_t e) { return shift ? shift[e] : 13; }
+
+/* Periodic near lists of the leaves listed in `targets` (particles, unit
+ * torus): nbr(A) = every (leaf B, image c) whose closed cube, shifted by
+ * image c, touches A's, in ascending (c, B).  Writes nbr_start and, if the
+ * total fits in `cap`, nbr_idx and nbr_shift.  Returns the entry count. */
+int64_t orc_neighbors_periodic(int64_t L, const int32_t *anchor, const int32_t *size,
+                               const int32_t *targets, int64_t n_targets, int64_t *nbr_start,
+                               int32_t *nbr_idx, int8_t *nbr_shift, int64_t cap)
+{
+    const int64_t dim = (int64_t)1 << ORC_DEPTH_BITS;
+    int64_t *cnt = (int64_t *)calloc((size_t)(n_targets + 1), sizeof(int64_t));
+    for (int pass = 0; pass < 2; ++pass) {
+        if (pass == 1) {
+            nbr_start[0] = 0;
+            for (int64_t t = 0; t < n_targets; ++t) nbr_start[t + 1] = nbr_start[t] + cnt[t];
+            if (nbr_start[n_targets] > cap || !nbr_idx) break;
+        }
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int64_t t = 0; t < n_targets; ++t) {
+            int32_t A = targets[t];
+            int64_t c = 0, w = pass ? nbr_start[t] : 0;
+            for (int code = 0; code < 27; ++code) {
+                int64_t sh[3] = {(code % 3 - 1) * dim, ((code / 3) % 3 - 1) * dim, (code / 9 - 1) * dim};
+                for (int64_t B = 0; B < L; ++B) {
+                    int adj = 1;
+                    for (int d = 0; d < 3; ++d) {
+                        int64_t ad = anchor[3 * A + d], bd = anchor[3 * B + d] + sh[d];
+                        if (!(ad <= bd + size[B] && bd <= ad + size[A])) adj = 0;
+                    }
+                    if (!adj) continue;
+                    if (pass) {
+                        nbr_idx[w] = (int32_t)B;
+                        nbr_shift[w] = (int8_t)code;
+                        ++w;
+                    } else {
+                        ++c;
+                    }
+                }
+            }
+            if (!pass) cnt[t] = c;
+        }
+    }
+    int64_t total = nbr_start[n_targets];
+    free(cnt);
+    return total;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Redundant layout                                                         */
 /* ------------------------------------------------------------------------ */
 
 /* Segment bookkeeping for the redundant layout over all L leaves:
  * red_start = exclusive prefix sum of the segment lengths
- * sum_{B in nbr(A)} occ(B); red_self[A] = offset of A's own sources inside
- * its segment.  Returns S = red_start[L]. */
+ * sum_{B in nbr(A)} occ(B); red_self[A] = offset of A's own sources (the
+ * unshifted image) inside its segment.  Returns S = red_start[L]. */
 int64_t orc_red_offsets(int64_t L, const int32_t *leaf_start, const int64_t *nbr_start,
-                        const int32_t *nbr_idx, int64_t *red_start, int32_t *red_self)
+                        const int32_t *nbr_idx, const int8_t *nbr_shift, int64_t *red_start,
+                        int32_t *red_self)
 {
     red_start[0] = 0;
     for (int64_t A = 0; A < L; ++A) {
         int64_t len = 0, self = -1;
         for (int64_t e = nbr_start[A]; e < nbr_start[A + 1]; ++e) {
             int32_t B = nbr_idx[e];
-            if (B == A) self = len;
+            if (B == A && orc_shift_code(nbr_shift, e) == 13) self = len;
             len += leaf_start[B + 1] - leaf_start[B];
         }
         red_start[A + 1] = red_start[A] + len;
@@ -329,16 +390,43 @@ void orc_restructure_rows(int64_t L, const int32_t *leaf_start, const int32_t *p
     }
 }
 
+/* FP64 gravity payload: the rows (x + s, y + s, z + s, m) of the segments,
+ * s the image shift of the entry (zero without images).  out8: double[S][4]. */
+void orc_restructure_gravity_rows(int64_t L, const int32_t *leaf_start, const int32_t *perm,
+                                  const int64_t *nbr_start, const int32_t *nbr_idx,
+                                  const int8_t *nbr_shift, const int64_t *red_start,
+                                  const double *x, const double *y, const double *z,
+                                  const double *m, double *out8)
+{
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t A = 0; A < L; ++A) {
+        int64_t w = red_start[A];
+        for (int64_t e = nbr_start[A]; e < nbr_start[A + 1]; ++e) {
+            int32_t B = nbr_idx[e];
+            double sh[3];
+            orc_shift_of(nbr_shift, e, sh);
+            for (int32_t s = leaf_start[B]; s < leaf_start[B + 1]; ++s, ++w) {
+                int64_t j = perm[s];
+                out8[4 * w + 0] = x[j] + sh[0];
+                out8[4 * w + 1] = y[j] + sh[1];
+                out8[4 * w + 2] = z[j] + sh[2];
+                out8[4 * w + 3] = m[j];
+            }
+        }
+    }
+}
+
 /* FP32-mixed gravity payload of the redundant layout: for target leaf A with
  * centre c_A = (anchor_A + size_A / 2) 2^-20 (exact in double), every source
  * row of its segment becomes (float)(x - c_A), (float)(y - c_A),
  * (float)(z - c_A), (float)m: the offset removed in double, the result
- * rounded to single.  out4: float[S][4]. */
+ * rounded to single; a source of image c is shifted first, in double
+ * ((x + s) - c_A).  out4: float[S][4]. */
 void orc_restructure_gravity_rel(int64_t L, const int32_t *leaf_start, const int32_t *perm,
                                  const int64_t *nbr_start, const int32_t *nbr_idx,
-                                 const int64_t *red_start, const int32_t *anchor,
-                                 const int32_t *size, const double *x, const double *y,
-                                 const double *z, const double *m, float *out4)
+                                 const int8_t *nbr_shift, const int64_t *red_start,
+                                 const int32_t *anchor, const int32_t *size, const double *x,
+                                 const double *y, const double *z, const double *m, float *out4)
 {
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t A = 0; A < L; ++A) {
@@ -348,11 +436,13 @@ void orc_restructure_gravity_rel(int64_t L, const int32_t *leaf_start, const int
         int64_t w = red_start[A];
         for (int64_t e = nbr_start[A]; e < nbr_start[A + 1]; ++e) {
             int32_t B = nbr_idx[e];
+            double sh[3];
+            orc_shift_of(nbr_shift, e, sh);
             for (int32_t s = leaf_start[B]; s < leaf_start[B + 1]; ++s) {
                 int64_t j = perm[s];
-                out4[4 * w + 0] = (float)(x[j] - c[0]);
-                out4[4 * w + 1] = (float)(y[j] - c[1]);
-                out4[4 * w + 2] = (float)(z[j] - c[2]);
+                out4[4 * w + 0] = (float)((x[j] + sh[0]) - c[0]);
+                out4[4 * w + 1] = (float)((y[j] + sh[1]) - c[1]);
+                out4[4 * w + 2] = (float)((z[j] + sh[2]) - c[2]);
                 out4[4 * w + 3] = (float)m[j];
                 ++w;
             }
@@ -371,7 +461,7 @@ void orc_restructure_gravity_rel(int64_t L, const int32_t *leaf_start, const int
  * patterns.  Either output may be NULL (offsets only). */
 int64_t orc_restructure_interactions(int64_t L, const int32_t *leaf_start, const int32_t *perm,
                                      const int64_t *nbr_start, const int32_t *nbr_idx,
-                                     const int32_t *anchor, const int32_t *size,
+                                     const int8_t *nbr_shift, const int32_t *anchor, const int32_t *size,
                                      const double *x, const double *y, const double *z,
                                      const double *m, int64_t *rec_start, double *out8,
                                      float *out4)
@@ -402,22 +492,25 @@ int64_t orc_restructure_interactions(int64_t L, const int32_t *leaf_start, const
             if (out4)
                 memcpy(&out4[4 * r], hdr, sizeof(hdr));
             ++r;
-            /* the targets (A's slots), then the sources (B's slots) */
+            /* the targets (A's slots), then the sources (B's slots, shifted by
+             * the entry's image) */
             for (int part = 0; part < 2; ++part) {
                 int32_t lo = part == 0 ? leaf_start[A] : leaf_start[B];
                 int32_t hi = part == 0 ? leaf_start[A + 1] : leaf_start[B + 1];
+                double sh[3] = {0.0, 0.0, 0.0};
+                if (part == 1) orc_shift_of(nbr_shift, e, sh);
                 for (int32_t sl = lo; sl < hi; ++sl, ++r) {
                     int64_t j = perm[sl];
                     if (out8) {
-                        out8[4 * r + 0] = x[j];
-                        out8[4 * r + 1] = y[j];
-                        out8[4 * r + 2] = z[j];
+                        out8[4 * r + 0] = x[j] + sh[0];
+                        out8[4 * r + 1] = y[j] + sh[1];
+                        out8[4 * r + 2] = z[j] + sh[2];
                         out8[4 * r + 3] = m[j];
                     }
                     if (out4) {
-                        out4[4 * r + 0] = (float)(x[j] - c[0]);
-                        out4[4 * r + 1] = (float)(y[j] - c[1]);
-                        out4[4 * r + 2] = (float)(z[j] - c[2]);
+                        out4[4 * r + 0] = (float)((x[j] + sh[0]) - c[0]);
+                        out4[4 * r + 1] = (float)((y[j] + sh[1]) - c[1]);
+                        out4[4 * r + 2] = (float)((z[j] + sh[2]) - c[2]);
                         out4[4 * r + 3] = (float)m[j];
                     }
                 }
@@ -438,11 +531,14 @@ int64_t orc_restructure_interactions(int64_t L, const int32_t *leaf_start, const
  * sel_nbr_idx) -- list k belongs to sel[k] -- the targets are the particles
  * of those leaves, in sorted-slot order.  out_idx receives their caller
  * indices; phi/ax/ay/az the values.  Returns the number of targets.
- * With eps == 0 a coincident pair i != j gives inf/nan, as the formula does. */
+ * With eps == 0 a coincident pair i != j gives inf/nan, as the formula does.
+ * sel_nbr_shift (may be NULL) gives each entry's periodic image: the source
+ * then sits at x_j + s, and only the unshifted image of i itself is skipped. */
 int64_t orc_gravity_leaves(const double *x, const double *y, const double *z, const double *m,
                            double eps, const int32_t *perm, const int32_t *leaf_start,
                            const int32_t *sel, int64_t n_sel,
                            const int64_t *sel_nbr_start, const int32_t *sel_nbr_idx,
+                           const int8_t *sel_nbr_shift,
                            int32_t *out_idx, double *phi, double *ax, double *ay, double *az)
 {
     int64_t *off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_sel + 1));
@@ -458,10 +554,13 @@ int64_t orc_gravity_leaves(const double *x, const double *y, const double *z, co
             double p = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
             for (int64_t e = sel_nbr_start[k]; e < sel_nbr_start[k + 1]; ++e) {
                 int32_t B = sel_nbr_idx[e];
+                double sh[3];
+                orc_shift_of(sel_nbr_shift, e, sh);
+                int self_image = orc_shift_code(sel_nbr_shift, e) == 13;
                 for (int32_t t = leaf_start[B]; t < leaf_start[B + 1]; ++t) {
                     int64_t j = perm[t];
-                    if (j == i) continue;
-                    double dx = x[i] - x[j], dy = y[i] - y[j], dz = z[i] - z[j];
+                    if (j == i && self_image) continue;
+                    double dx = x[i] - (x[j] + sh[0]), dy = y[i] - (y[j] + sh[1]), dz = z[i] - (z[j] + sh[2]);
                     double r2 = dx * dx + dy * dy + dz * dz + eps2;
                     double w = 1.0 / sqrt(r2);
                     double w3 = w * w * w;
@@ -501,6 +600,7 @@ int64_t orc_gravity_adjoint_leaves(const double *x, const double *y, const doubl
                                    const int32_t *perm, const int32_t *leaf_start,
                                    const int32_t *sel, int64_t n_sel,
                                    const int64_t *sel_nbr_start, const int32_t *sel_nbr_idx,
+                                   const int8_t *sel_nbr_shift,
                                    int32_t *out_idx, double *gm, double *gx, double *gy,
                                    double *gz)
 {
@@ -517,12 +617,17 @@ int64_t orc_gravity_adjoint_leaves(const double *x, const double *y, const doubl
             double om = 0.0, ox = 0.0, oy = 0.0, oz = 0.0;
             for (int64_t e = sel_nbr_start[k]; e < sel_nbr_start[k + 1]; ++e) {
                 int32_t B = sel_nbr_idx[e];
+                double sh[3];
+                orc_shift_of(sel_nbr_shift, e, sh);
+                int self_image = orc_shift_code(sel_nbr_shift, e) == 13;
                 for (int32_t t = leaf_start[B]; t < leaf_start[B + 1]; ++t) {
                     int64_t q = perm[t];
-                    if (q == j) continue;
+                    if (q == j && self_image) continue;
+                    /* q's image at x_q + s; the reverse pair (target q, source j)
+                     * sees j's image at x_j - s, so both use d = x_j - (x_q + s) */
                     /* pair (target j, source q): derivative w.r.t. x_j = dT/dd */
                     {
-                        double d[3] = {x[j] - x[q], y[j] - y[q], z[j] - z[q]};
+                        double d[3] = {x[j] - (x[q] + sh[0]), y[j] - (y[q] + sh[1]), z[j] - (z[q] + sh[2])};
                         double g[3] = {gax[j], gay[j], gaz[j]};
                         double w = 1.0 / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + eps2);
                         double w3 = w * w * w, w5 = w3 * w * w;
@@ -534,7 +639,7 @@ int64_t orc_gravity_adjoint_leaves(const double *x, const double *y, const doubl
                     }
                     /* pair (target q, source j): derivatives w.r.t. m_j and x_j = -dT/dd */
                     {
-                        double d[3] = {x[q] - x[j], y[q] - y[j], z[q] - z[j]};
+                        double d[3] = {(x[q] + sh[0]) - x[j], (y[q] + sh[1]) - y[j], (z[q] + sh[2]) - z[j]};
                         double g[3] = {gax[q], gay[q], gaz[q]};
                         double w = 1.0 / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + eps2);
                         double w3 = w * w * w, w5 = w3 * w * w;
