@@ -41,8 +41,10 @@
  *  - gravity: G = 1, Plummer softening, phi_i = -sum m_j (r^2+eps^2)^{-1/2},
  *    a_i = -sum m_j (x_i-x_j)(r^2+eps^2)^{-3/2}, the self pair j = i excluded;
  *  - Helmholtz: G(r) = e^{ikr}/(4 pi r) in 3-D, r = 0 excluded;
- *  - near field: leaves whose closed cubes touch, the leaf itself included,
- *    no periodic images;
+ *  - near field: leaves whose closed cubes touch, the leaf itself included;
+ *    optionally (particle trees) on the unit torus, where a leaf's periodic
+ *    images count as leaves of their own (the periodic interactions of the
+ *    stellar-dynamics case, Sec. 5.2);
  *  - the redundancy grain is the target box.
  */
 #ifndef P2P_H
@@ -120,9 +122,18 @@ typedef struct {
 
 /* Near-field lists in CSR form: nbr(A) = nbr_idx[nbr_start[A] .. nbr_start[A+1]),
  * every leaf whose closed cube touches A's (same grid instance), A included,
- * ascending. */
+ * ascending.
+ * Periodic lists (periodic = 1, particle trees only): the domain [0,1)^3 is a
+ * torus.  An entry is a leaf B together with an image code
+ * c = (sx+1) + 3 (sy+1) + 9 (sz+1), sx, sy, sz in {-1, 0, 1}, in
+ * nbr_shift[e]: B's points taken at x + (sx, sy, sz), B's cube shifted the
+ * same way touching A's.  Code 13 is the unshifted leaf.  Entries are in
+ * ascending (c, B); one leaf can appear under several codes (a leaf touching
+ * A across a face of the domain and inside it), and the self pair skipped by
+ * the sums is only the point itself in the unshifted image.  The relation is
+ * symmetric: (B, c) in nbr(A) iff (A, 26 - c) in nbr(B). */
 typedef struct {
-    int64_t cap;         /* in: capacity of nbr_idx */
+    int64_t cap;         /* in: capacity of nbr_idx (and nbr_shift) */
     int64_t count;       /* out: E = total entries (also on P2P_ECAPACITY) */
     int64_t *nbr_start;  /* device [L+1] */
     int32_t *nbr_idx;    /* device [cap] */
@@ -130,11 +141,17 @@ typedef struct {
                             nbr(A), the size of the redundant layout over these
                             lists; a caller that fills the lists itself sets -1
                             (unknown) */
+    int32_t periodic;    /* in: 0 = plain lists, 1 = periodic images (above) */
+    int32_t reserved;    /* must be 0 */
+    int8_t *nbr_shift;   /* device [cap]: image code per entry; used only when
+                            periodic = 1 (then required once E > 0) */
 } p2p_nbrs;
 
 /* Redundant layout.  Segment A = entries [red_start[A], red_start[A+1]) holds,
  * for B in nbr(A) in order, the rows of B's sorted slots in order; A's own
- * rows start at red_start[A] + red_self[A].  S = red_start[L] entries.
+ * rows (the unshifted image) start at red_start[A] + red_self[A].
+ * S = red_start[L] entries.  With periodic lists the gravity rows of an entry
+ * hold the shifted positions x + s.
  * Payload planes (device):
  *   gravity FP64: planes[0] = double[S][4] rows (x, y, z, m), 32-byte rows;
  *   gravity FP32_MIXED: planes[0] = float4[S] (x - c, y - c, z - c, m), where c
@@ -165,7 +182,9 @@ typedef struct {
  * A's points (the targets), then the occ_B rows of B's points (the sources),
  * each in sorted order, with the payload of the box-grain layout (FP32_MIXED:
  * float4 (x - c_A, y - c_A, z - c_A, m) relative to the centre of A; FP64:
- * double[4] (x, y, z, m)).  Every record can be evaluated on its own; the
+ * double[4] (x, y, z, m); with periodic lists B's rows hold the shifted
+ * positions x + s).  Every record can be evaluated on its own (the evaluation
+ * reads the entry's image code only to tell the self record (A, A, 13)); the
  * results of the records of one target leaf are then summed (the update). */
 typedef struct {
     int64_t cap;        /* in: capacity in rows of planes[0] */
@@ -207,8 +226,10 @@ p2p_status p2p_build_tree(const double *x, const double *y, const double *z,
 
 /* Near-field lists of every leaf (a2: the E2 neighbourhood, Sec. 5.1;
  * Fig. 8 counts them for irregular trees).  nbrs->nbr_start must hold L+1
- * entries.  Also sets nbrs->red_entries.  Synchronises `stream`;
- * P2P_ECAPACITY if E > nbrs->cap (count and red_entries are still set). */
+ * entries; nbrs->periodic selects periodic images (P2P_EINVAL on a grid
+ * tree), which also fills nbrs->nbr_shift.  Also sets nbrs->red_entries.
+ * Synchronises `stream`; P2P_ECAPACITY if E > nbrs->cap (count and
+ * red_entries are still set). */
 p2p_status p2p_build_neighbors(const p2p_tree *tree, p2p_nbrs *nbrs,
                                void *ws, size_t *ws_bytes, p2p_stream_t stream);
 

@@ -44,7 +44,8 @@ class p2p_tree(ctypes.Structure):
 class p2p_nbrs(ctypes.Structure):
     _fields_ = [("cap", ctypes.c_int64), ("count", ctypes.c_int64),
                 ("nbr_start", ctypes.c_void_p), ("nbr_idx", ctypes.c_void_p),
-                ("red_entries", ctypes.c_int64)]
+                ("red_entries", ctypes.c_int64), ("periodic", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("nbr_shift", ctypes.c_void_p)]
 
 
 class p2p_redundant(ctypes.Structure):

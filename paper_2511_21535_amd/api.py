@@ -147,8 +147,8 @@ class Tree:
         n = sum(int(g.n_side) ** 3 for g in grids)
         return Tree._build(None, None, None, list(grids), n, 0, 0, torch.device(device))
 
-    def neighbors(self, cap: Optional[int] = None) -> "Nbrs":
-        return build_neighbors(self, cap)
+    def neighbors(self, cap: Optional[int] = None, periodic: bool = False) -> "Nbrs":
+        return build_neighbors(self, cap, periodic)
 
 
 @dataclass
@@ -157,26 +157,38 @@ class Nbrs:
     nbr_start: torch.Tensor
     nbr_idx: torch.Tensor
     red_entries: int = -1      # S of the redundant layout over these lists (-1: unknown)
+    nbr_shift: Optional[torch.Tensor] = None   # int8 image codes of periodic lists
+
+    @property
+    def periodic(self) -> bool:
+        return self.nbr_shift is not None
 
     def struct(self) -> L.p2p_nbrs:
         s = L.p2p_nbrs()
         s.cap, s.count = self.nbr_idx.numel(), self.count
         s.nbr_start, s.nbr_idx = self.nbr_start.data_ptr(), self.nbr_idx.data_ptr()
         s.red_entries = self.red_entries
+        if self.nbr_shift is not None:
+            s.periodic, s.nbr_shift = 1, self.nbr_shift.data_ptr()
         return s
 
 
-def build_neighbors(tree: Tree, cap: Optional[int] = None) -> Nbrs:
+def build_neighbors(tree: Tree, cap: Optional[int] = None, periodic: bool = False) -> Nbrs:
+    """Near lists of every leaf; periodic=True: on the unit torus (particle
+    trees), with an image code per entry in nbr_shift."""
     dev = tree.leaf_start.device
     Lv = tree.n_leaves
     if cap is None:
-        cap = 32 * max(Lv, 1)
+        cap = (48 if periodic else 32) * max(Lv, 1)
     ts = tree.struct()
     for _ in range(2):
         start = torch.empty(Lv + 1, dtype=torch.int64, device=dev)
         idx = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        sh = torch.empty(max(cap, 1), dtype=torch.int8, device=dev) if periodic else None
         s = L.p2p_nbrs()
         s.cap, s.nbr_start, s.nbr_idx = cap, start.data_ptr(), idx.data_ptr()
+        if periodic:
+            s.periodic, s.nbr_shift = 1, sh.data_ptr()
 
         def call(ws, nb):
             return L.p2p_build_neighbors(ctypes.byref(ts), ctypes.byref(s), ws, nb, _stream())
@@ -185,8 +197,9 @@ def build_neighbors(tree: Tree, cap: Optional[int] = None) -> Nbrs:
             cap = int(s.count)
             continue
         L.check(st)
-        return Nbrs(count=int(s.count), nbr_start=start, nbr_idx=idx[: int(s.count)],
-                    red_entries=int(s.red_entries))
+        E = int(s.count)
+        return Nbrs(count=E, nbr_start=start, nbr_idx=idx[:E], red_entries=int(s.red_entries),
+                    nbr_shift=sh[:E] if periodic else None)
     raise L.P2PError(L.P2P_ECAPACITY, "near-list capacity retry failed")
 
 

@@ -84,12 +84,25 @@ p2p_status check_tree(const p2p_tree *t) {
     return P2P_OK;
 }
 
+p2p_status check_periodic(const p2p_tree *t, const p2p_nbrs *nb) {
+    if (nb->periodic != 0 && nb->periodic != 1) return fail(P2P_EINVAL, "nbrs->periodic must be 0 or 1");
+    if (nb->reserved != 0) return fail(P2P_EINVAL, "nbrs->reserved must be 0");
+    if (nb->periodic && t->kind != P2P_TREE_PARTICLES)
+        return fail(P2P_EINVAL, "periodic near lists are defined for particle trees only");
+    return P2P_OK;
+}
+
 p2p_status check_nbrs(const p2p_tree *t, const p2p_nbrs *nb) {
     if (!nb) return fail(P2P_EINVAL, "nbrs is NULL");
+    P2P_TRY(check_periodic(t, nb));
     if (t->n_leaves > 0 && (!nb->nbr_start || !nb->nbr_idx)) return fail(P2P_EINVAL, "nbrs: NULL array (not built?)");
+    if (t->n_leaves > 0 && nb->periodic && !nb->nbr_shift) return fail(P2P_EINVAL, "nbrs: periodic lists without nbr_shift");
     if (nb->count < t->n_leaves) return fail(P2P_EINVAL, "nbrs: count < n_leaves (not built?)");
     return P2P_OK;
 }
+
+// Image codes of periodic lists, null for plain ones.
+const int8_t *shifts(const p2p_nbrs *nb) { return nb->periodic ? nb->nbr_shift : nullptr; }
 
 }  // namespace
 }  // namespace p2p
@@ -210,6 +223,8 @@ extern "C" p2p_status p2p_build_neighbors(const p2p_tree *tree, p2p_nbrs *nbrs, 
     P2P_TRY(check_tree(tree));
     if (!nbrs) return fail(P2P_EINVAL, "nbrs is NULL");
     if (nbrs->cap < 0) return fail(P2P_EINVAL, "nbrs->cap < 0");
+    P2P_TRY(check_periodic(tree, nbrs));
+    const bool per = nbrs->periodic != 0;
     const int64_t L = tree->n_leaves;
     // total key bits: 3 per axis, plus the instance index for grids
     const int total_bits = 3 * tree->key_bits + (tree->kind == P2P_TREE_GRIDS ? bits_for(tree->n_grids) : 0);
@@ -221,6 +236,7 @@ extern "C" p2p_status p2p_build_neighbors(const p2p_tree *tree, p2p_nbrs *nbrs, 
     int32_t *segs = ar.take<int32_t>(L);
     int64_t *seg_scan = ar.take<int64_t>(L + 1);
     int32_t *slots = ar.take<int32_t>(static_cast<size_t>(L) * kNbrSlotsPerLeaf);
+    int8_t *slot_code = ar.take<int8_t>(per ? static_cast<size_t>(L) * kNbrSlotsPerLeaf : 0);
     int32_t *overflow = ar.take<int32_t>(1);
     int64_t *totals = ar.take<int64_t>(3);
     p2p_status st;
@@ -230,7 +246,8 @@ extern "C" p2p_status p2p_build_neighbors(const p2p_tree *tree, p2p_nbrs *nbrs, 
     const int inst_shift = 3 * tree->key_bits;
     P2P_TRY(launch_key_directory(tree->leaf_key, L, total_bits, dir, overflow, s));
     P2P_TRY(launch_neighbors_count(tree->leaf_key, tree->leaf_level, L, tree->key_bits, inst_shift, dir,
-                                   total_bits, tree->leaf_start, counts, segs, slots, overflow, s));
+                                   total_bits, tree->leaf_start, counts, segs, slots,
+                                   per ? slot_code : nullptr, overflow, s));
     P2P_TRY((exclusive_scan<int32_t, int64_t>(counts, start, L, scan_tmp, s)));
     P2P_TRY((exclusive_scan<int32_t, int64_t>(segs, seg_scan, L, scan_tmp, s)));
     P2P_TRY(launch_nbr_totals(start, seg_scan, overflow, L, totals, s));
@@ -244,9 +261,11 @@ extern "C" p2p_status p2p_build_neighbors(const p2p_tree *tree, p2p_nbrs *nbrs, 
         return fail(P2P_ECAPACITY, "nbrs->cap " + std::to_string(nbrs->cap) + " < " + std::to_string(E) + " entries");
     }
     if (E > 0 && !nbrs->nbr_idx) return fail(P2P_EINVAL, "nbrs->nbr_idx must not be NULL");
+    if (E > 0 && per && !nbrs->nbr_shift) return fail(P2P_EINVAL, "nbrs->nbr_shift must not be NULL for periodic lists");
     P2P_HIP(hipMemcpyAsync(nbrs->nbr_start, start, (L + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
     P2P_TRY(launch_neighbors_fill(tree->leaf_key, tree->leaf_level, L, tree->key_bits, inst_shift, dir,
-                                  total_bits, counts, slots, host[2] > 0, nbrs->nbr_start, nbrs->nbr_idx, s));
+                                  total_bits, counts, slots, per ? slot_code : nullptr, host[2] > 0,
+                                  nbrs->nbr_start, nbrs->nbr_idx, per ? nbrs->nbr_shift : nullptr, s));
     P2P_HIP(hipStreamSynchronize(s));
     nbrs->count = E;
     return P2P_OK;
@@ -291,7 +310,8 @@ extern "C" p2p_status p2p_restructure_redundant(const p2p_tree *tree, const p2p_
     // S: carried by the near lists, else counted here and read back
     int64_t S = nbrs->red_entries;
     if (S < 0) {
-        P2P_TRY(launch_seg_lengths(tree->leaf_start, nbrs->nbr_start, nbrs->nbr_idx, L, seg_len, count_self, s));
+        P2P_TRY(launch_seg_lengths(tree->leaf_start, nbrs->nbr_start, nbrs->nbr_idx, shifts(nbrs), L, seg_len,
+                                   count_self, s));
         P2P_TRY((exclusive_scan<int32_t, int64_t>(seg_len, count_start, L, scan_tmp, s)));
         S = 0;
         if (L > 0) P2P_HIP(hipMemcpyAsync(&S, &count_start[L], sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -315,13 +335,14 @@ extern "C" p2p_status p2p_restructure_redundant(const p2p_tree *tree, const p2p_
     else
         P2P_TRY(launch_permute_rows<double2>(static_cast<const double2 *>(src[0]), tree->perm, n, nrhs,
                                              static_cast<double2 *>(sq), s));
-    P2P_TRY(launch_seg_lengths(tree->leaf_start, nbrs->nbr_start, nbrs->nbr_idx, L, seg_len, out->red_self, s));
+    P2P_TRY(launch_seg_lengths(tree->leaf_start, nbrs->nbr_start, nbrs->nbr_idx, shifts(nbrs), L, seg_len,
+                               out->red_self, s));
     P2P_TRY((exclusive_scan<int32_t, int64_t>(seg_len, out->red_start, L, scan_tmp, s)));
     const int64_t entry_bytes = grav ? (mixed ? 16 : 32) : static_cast<int64_t>(nrhs) * static_cast<int64_t>(csize);
     const bool streaming = S * entry_bytes > kStreamingLayoutBytes;
     if (grav)
         P2P_TRY(launch_copy_segments_gravity(s4, tree->leaf_key, tree->leaf_level, tree->leaf_start,
-                                             nbrs->nbr_start, nbrs->nbr_idx, out->red_start, L,
+                                             nbrs->nbr_start, nbrs->nbr_idx, shifts(nbrs), out->red_start, L,
                                              mixed ? nullptr : static_cast<Row4d *>(out->planes[0]),
                                              mixed ? static_cast<float4 *>(out->planes[0]) : nullptr,
                                              streaming, s));
@@ -396,7 +417,7 @@ extern "C" p2p_status p2p_restructure_interactions(const p2p_tree *tree, const p
     }
     const bool streaming = rows * (mixed ? 16 : 32) > kStreamingLayoutBytes;
     P2P_TRY(launch_copy_records(s4, tree->leaf_key, tree->leaf_level, tree->leaf_start, nbrs->nbr_start,
-                                nbrs->nbr_idx, out->rec_start, L,
+                                nbrs->nbr_idx, shifts(nbrs), out->rec_start, L,
                                 mixed ? nullptr : static_cast<Row4d *>(out->planes[0]),
                                 mixed ? static_cast<float4 *>(out->planes[0]) : nullptr, streaming, s));
     out->count = rows;
@@ -434,8 +455,8 @@ extern "C" p2p_status p2p_eval_gravity_interactions(const p2p_tree *tree, const 
     P2P_TRY(launch_record_lengths(tree->leaf_start, nbrs->nbr_start, nbrs->nbr_idx, L, nullptr, tgt_len, s));
     P2P_TRY((exclusive_scan<int32_t, int64_t>(tgt_len, res_start, E, scan_tmp, s)));
     P2P_TRY(launch_eval_records(inter->rec_start, mixed ? nullptr : static_cast<const Row4d *>(inter->planes[0]),
-                                mixed ? static_cast<const float4 *>(inter->planes[0]) : nullptr, E, res_start,
-                                eps * eps, eps == 0.0, res, s));
+                                mixed ? static_cast<const float4 *>(inter->planes[0]) : nullptr, shifts(nbrs), E,
+                                res_start, eps * eps, eps == 0.0, res, s));
     P2P_TRY(launch_reduce_records(tree->leaf_start, nbrs->nbr_start, res_start, tree->perm, L, res, phi, ax,
                                   ay, az, s));
     return P2P_OK;
@@ -481,6 +502,7 @@ extern "C" p2p_status p2p_eval_gravity(const p2p_tree *tree, const p2p_nbrs *nbr
     a.leaf_level = tree->leaf_level;
     a.nbr_start = nbrs->nbr_start;
     a.nbr_idx = nbrs->nbr_idx;
+    a.nbr_shift = shifts(nbrs);
     a.eps2 = eps * eps;
     a.phi = phi;
     a.ax = ax;
@@ -710,6 +732,7 @@ extern "C" p2p_status p2p_adjoint(int32_t kind, const p2p_tree *tree, const p2p_
     a.perm = tree->perm;
     a.nbr_start = nbrs->nbr_start;
     a.nbr_idx = nbrs->nbr_idx;
+    a.nbr_shift = shifts(nbrs);
     a.s4 = s4;
     a.g4 = g4;
     a.eps2 = eps * eps;

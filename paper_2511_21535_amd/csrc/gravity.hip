@@ -19,6 +19,10 @@
 // computed in the same arithmetic); the self term of a is exactly zero.
 // With eps == 0 pairs at zero distance contribute nothing instead.
 //
+// Periodic lists (gather and adjoint): a staged source row of an entry with
+// image code c is shifted by (sx, sy, sz) domain edges, x + s in double, before
+// the conversion; the redundant layout already holds shifted rows.
+//
 // FP32_MIXED: coordinates are taken relative to the centre of the target leaf
 // in double and rounded to float once per (target leaf, source) -- the
 // redundant layout stores them that way, the gather layout converts while
@@ -41,15 +45,19 @@ constexpr int kGNbrChunk = 256;
 constexpr int kGFlush = 32;
 
 // Block-wide: loads one chunk of the near list of A into LDS (first sorted
-// slot of each neighbour and exclusive prefix of their occupancies).
+// slot of each neighbour, exclusive prefix of their occupancies and, with
+// PER, the image codes).
+template <bool PER>
 __device__ int64_t g_load_nbr_chunk(const int32_t *__restrict__ leaf_start,
-                                    const int32_t *__restrict__ nbr_idx, int64_t c0, int nc,
-                                    int64_t *s_pre, int32_t *s_first, int64_t *s_w) {
+                                    const int32_t *__restrict__ nbr_idx,
+                                    const int8_t *__restrict__ nbr_shift, int64_t c0, int nc,
+                                    int64_t *s_pre, int32_t *s_first, int8_t *s_code, int64_t *s_w) {
     int32_t occ = 0, first = 0;
     if (static_cast<int>(threadIdx.x) < nc) {
         const int32_t B = nbr_idx[c0 + threadIdx.x];
         first = leaf_start[B];
         occ = leaf_start[B + 1] - first;
+        if constexpr (PER) s_code[threadIdx.x] = nbr_shift[c0 + threadIdx.x];
     }
     s_first[threadIdx.x] = first;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -83,22 +91,24 @@ __device__ inline int g_find_nbr(const int64_t *s_pre, int nc, int64_t p) {
 }
 
 // Walks the sources of leaf A tile by tile: after a barrier, `begin(n_tile)`,
-// then `stage(i, src_row)` for the tile's sources i, a barrier, and
-// `body(n_tile)`.  Must be called by the whole block.
-template <bool RED, class Begin, class Stage, class Body>
+// then `stage(i, src_row, image_code)` for the tile's sources i (code 13
+// unless PER), a barrier, and `body(n_tile)`.  Must be called by the whole
+// block.
+template <bool RED, bool PER, class Begin, class Stage, class Body>
 __device__ void for_each_source_tile(int64_t A, const int64_t *__restrict__ red_start,
                                      const int64_t *__restrict__ nbr_start,
                                      const int32_t *__restrict__ nbr_idx,
+                                     const int8_t *__restrict__ nbr_shift,
                                      const int32_t *__restrict__ leaf_start, int64_t *s_pre,
-                                     int32_t *s_first, int64_t *s_w, Begin begin, Stage stage,
-                                     Body body) {
+                                     int32_t *s_first, int8_t *s_code, int64_t *s_w, Begin begin,
+                                     Stage stage, Body body) {
     if constexpr (RED) {
         const int64_t seg0 = red_start[A], ns = red_start[A + 1] - seg0;
         for (int64_t s0 = 0; s0 < ns; s0 += kGTile) {
             const int nt = static_cast<int>(min<int64_t>(kGTile, ns - s0));
             __syncthreads();
             begin(nt);
-            for (int i = threadIdx.x; i < nt; i += kGBlock) stage(i, seg0 + s0 + i);
+            for (int i = threadIdx.x; i < nt; i += kGBlock) stage(i, seg0 + s0 + i, 13);
             __syncthreads();
             body(nt);
         }
@@ -107,7 +117,8 @@ __device__ void for_each_source_tile(int64_t A, const int64_t *__restrict__ red_
         for (int64_t c0 = e0; c0 < e1; c0 += kGNbrChunk) {
             const int nc = static_cast<int>(min<int64_t>(kGNbrChunk, e1 - c0));
             __syncthreads();
-            const int64_t rows = g_load_nbr_chunk(leaf_start, nbr_idx, c0, nc, s_pre, s_first, s_w);
+            const int64_t rows =
+                g_load_nbr_chunk<PER>(leaf_start, nbr_idx, nbr_shift, c0, nc, s_pre, s_first, s_code, s_w);
             for (int64_t s0 = 0; s0 < rows; s0 += kGTile) {
                 const int nt = static_cast<int>(min<int64_t>(kGTile, rows - s0));
                 __syncthreads();
@@ -115,13 +126,21 @@ __device__ void for_each_source_tile(int64_t A, const int64_t *__restrict__ red_
                 for (int i = threadIdx.x; i < nt; i += kGBlock) {
                     const int64_t p = s0 + i;
                     const int b = g_find_nbr(s_pre, nc, p);
-                    stage(i, s_first[b] + (p - s_pre[b]));
+                    stage(i, s_first[b] + (p - s_pre[b]), PER ? static_cast<int>(s_code[b]) : 13);
                 }
                 __syncthreads();
                 body(nt);
             }
         }
     }
+}
+
+// Source row of an entry with image code c, placed at x + s in double.
+__device__ inline Row4d shifted(Row4d v, int c) {
+    v.x += static_cast<double>(c % 3 - 1);
+    v.y += static_cast<double>((c / 3) % 3 - 1);
+    v.z += static_cast<double>(c / 9 - 1);
+    return v;
 }
 
 __device__ inline float rsq_f32(float x) { return __builtin_amdgcn_rsqf(x); }
@@ -134,7 +153,7 @@ __device__ inline void leaf_centre(uint64_t key, int level, double c[3]) {
     c[2] = (static_cast<double>(p2pd::compact3(key >> 2)) + half) * 0x1p-20;
 }
 
-template <bool MIXED, bool RED, bool EPS0>
+template <bool MIXED, bool RED, bool EPS0, bool PER>
 __device__ __forceinline__ void gravity_body(const GravityArgs &a) {
     using Src = typename std::conditional<MIXED, float4, Row4d>::type;
     // a tile of kGTile sources padded to G equal runs (see below): at most
@@ -143,6 +162,7 @@ __device__ __forceinline__ void gravity_body(const GravityArgs &a) {
     __shared__ Src s_src[kGTile + kGBlock];
     __shared__ int64_t s_pre[kGNbrChunk + 1];
     __shared__ int32_t s_first[kGNbrChunk];
+    __shared__ int8_t s_code[PER ? kGNbrChunk : 1];
     __shared__ int64_t s_w[kGBlock / 64];
     static_assert(sizeof(s_src) >= 4 * kGBlock * sizeof(double), "reduction does not fit");
     double(*s_red)[kGBlock] = reinterpret_cast<double(*)[kGBlock]>(s_src);
@@ -192,18 +212,22 @@ __device__ __forceinline__ void gravity_body(const GravityArgs &a) {
                     s_src[i] = Row4d{1e18, 1e18, 1e18, 0.0};
             }
         };
-        auto stage = [&](int i, int64_t row) {
+        auto stage = [&](int i, int64_t row, int code) {
             Src *d = s_src + i;
             if constexpr (MIXED) {
                 if constexpr (RED) {
                     *d = a.red4[row];
                 } else {
-                    const Row4d v = a.s4[row];
+                    Row4d v = a.s4[row];
+                    if constexpr (PER) v = shifted(v, code);
                     *d = make_float4(static_cast<float>(v.x - c[0]), static_cast<float>(v.y - c[1]),
                                      static_cast<float>(v.z - c[2]), static_cast<float>(v.w));
                 }
             } else {
-                *d = a.s4[row];
+                if constexpr (PER && !RED)
+                    *d = shifted(a.s4[row], code);
+                else
+                    *d = a.s4[row];
             }
         };
         auto body = [&](int) {
@@ -263,8 +287,8 @@ __device__ __forceinline__ void gravity_body(const GravityArgs &a) {
                 for (; j < chunk; ++j, ++sp) pair(sp[0]);
             }
         };
-        for_each_source_tile<RED>(A, a.red_start, a.nbr_start, a.nbr_idx, a.leaf_start, s_pre,
-                                  s_first, s_w, begin, stage, body);
+        for_each_source_tile<RED, PER>(A, a.red_start, a.nbr_start, a.nbr_idx, a.nbr_shift, a.leaf_start,
+                                       s_pre, s_first, s_code, s_w, begin, stage, body);
 
         __syncthreads();
         s_red[0][threadIdx.x] = active ? p : 0.0;
@@ -300,20 +324,20 @@ __device__ __forceinline__ void gravity_body(const GravityArgs &a) {
 // The FP32-mixed redundant kernel fits in 64 VGPRs without spills, so it asks
 // for 8 waves per SIMD (more workgroups in flight hide the tile staging); the
 // FP32-mixed gather kernel fits 72 without spills (7 waves per SIMD); the FP64
-// variants keep the compiler's register budget.
-template <bool MIXED, bool RED, bool EPS0>
+// variants keep the compiler's register budget.  PER: periodic gather.
+template <bool MIXED, bool RED, bool EPS0, bool PER>
 __global__ __launch_bounds__(kGBlock) void k_gravity(GravityArgs a) {
-    gravity_body<MIXED, RED, EPS0>(a);
+    gravity_body<MIXED, RED, EPS0, PER>(a);
 }
 template <bool EPS0>
 __global__ __launch_bounds__(kGBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_gravity_mixed_red(
     GravityArgs a) {
-    gravity_body<true, true, EPS0>(a);
+    gravity_body<true, true, EPS0, false>(a);
 }
-template <bool EPS0>
+template <bool EPS0, bool PER>
 __global__ __launch_bounds__(kGBlock) __attribute__((amdgpu_waves_per_eu(7))) void k_gravity_mixed_gather(
     GravityArgs a) {
-    gravity_body<true, false, EPS0>(a);
+    gravity_body<true, false, EPS0, PER>(a);
 }
 
 // Adjoint of the gravity sums, FP64, gather layout.  For target j and each
@@ -324,11 +348,13 @@ __global__ __launch_bounds__(kGBlock) __attribute__((amdgpu_waves_per_eu(7))) vo
 // (the derivative of L = sum_i gp_i phi_i + ga_i . a_i through both the pair
 // (j, k) and the pair (k, j)).  The self pair adds zero to g_x and
 // -gp_j/eps to g_m, which is added back.
+template <bool PER>
 __global__ __launch_bounds__(kGBlock) void k_gravity_adjoint(GravityAdjointArgs a) {
     __shared__ Row4d s_p[kGTile];    // sources (x, y, z, m)
     __shared__ Row4d s_g[kGTile];    // their upstream gradients (g_phi, g_ax, g_ay, g_az)
     __shared__ int64_t s_pre[kGNbrChunk + 1];
     __shared__ int32_t s_first[kGNbrChunk];
+    __shared__ int8_t s_code[kGNbrChunk];
     __shared__ int64_t s_w[kGBlock / 64];
     double *s_red = reinterpret_cast<double *>(s_g);   // reused after the last tile
 
@@ -344,8 +370,10 @@ __global__ __launch_bounds__(kGBlock) void k_gravity_adjoint(GravityAdjointArgs 
         const int64_t tr = t0 + tc0 + t;
         const Row4d pj = a.s4[tr], gj = a.g4[tr];
         double om = 0.0, ox = 0.0, oy = 0.0, oz = 0.0;
-        auto stage = [&](int i, int64_t row) {
-            s_p[i] = a.s4[row];
+        // a periodic source image at x_k + s: both pair directions see the
+        // same d = x_j - (x_k + s) (the reverse entry carries -s)
+        auto stage = [&](int i, int64_t row, int code) {
+            s_p[i] = PER ? shifted(a.s4[row], code) : a.s4[row];
             s_g[i] = a.g4[row];
         };
         auto body = [&](int nt) {
@@ -364,8 +392,8 @@ __global__ __launch_bounds__(kGBlock) void k_gravity_adjoint(GravityAdjointArgs 
                 om -= gk.x * w - w3 * gdk;
             }
         };
-        for_each_source_tile<false>(A, nullptr, a.nbr_start, a.nbr_idx, a.leaf_start, s_pre,
-                                    s_first, s_w, [](int) {}, stage, body);
+        for_each_source_tile<false, PER>(A, nullptr, a.nbr_start, a.nbr_idx, a.nbr_shift, a.leaf_start,
+                                         s_pre, s_first, s_code, s_w, [](int) {}, stage, body);
         __syncthreads();
         s_red[0 * kGBlock + threadIdx.x] = active ? om : 0.0;
         s_red[1 * kGBlock + threadIdx.x] = active ? ox : 0.0;
@@ -393,20 +421,29 @@ p2p_status launch_gravity(const GravityArgs &a, bool redundant, bool mixed, bool
                           hipStream_t s) {
     if (a.L <= 0) return P2P_OK;
     const unsigned g = static_cast<unsigned>(a.L);
-#define P2P_GRAV(M, R, E) k_gravity<M, R, E><<<g, kGBlock, 0, s>>>(a)
+    // the redundant layout holds shifted rows already; only the gather stages images
+    const bool per = !redundant && a.nbr_shift != nullptr;
+#define P2P_GRAV(M, R, E, P) k_gravity<M, R, E, P><<<g, kGBlock, 0, s>>>(a)
+#define P2P_GRAV_MG(E, P) k_gravity_mixed_gather<E, P><<<g, kGBlock, 0, s>>>(a)
     if (mixed) {
         if (redundant) {
             if (eps_zero) k_gravity_mixed_red<true><<<g, kGBlock, 0, s>>>(a);
             else k_gravity_mixed_red<false><<<g, kGBlock, 0, s>>>(a);
-        }
-        else {
-            if (eps_zero) k_gravity_mixed_gather<true><<<g, kGBlock, 0, s>>>(a);
-            else k_gravity_mixed_gather<false><<<g, kGBlock, 0, s>>>(a);
+        } else if (per) {
+            if (eps_zero) P2P_GRAV_MG(true, true); else P2P_GRAV_MG(false, true);
+        } else {
+            if (eps_zero) P2P_GRAV_MG(true, false); else P2P_GRAV_MG(false, false);
         }
     } else {
-        if (redundant) { if (eps_zero) P2P_GRAV(false, true, true); else P2P_GRAV(false, true, false); }
-        else { if (eps_zero) P2P_GRAV(false, false, true); else P2P_GRAV(false, false, false); }
+        if (redundant) {
+            if (eps_zero) P2P_GRAV(false, true, true, false); else P2P_GRAV(false, true, false, false);
+        } else if (per) {
+            if (eps_zero) P2P_GRAV(false, false, true, true); else P2P_GRAV(false, false, false, true);
+        } else {
+            if (eps_zero) P2P_GRAV(false, false, true, false); else P2P_GRAV(false, false, false, false);
+        }
     }
+#undef P2P_GRAV_MG
 #undef P2P_GRAV
     P2P_LAUNCH_CHECK();
     return P2P_OK;
@@ -414,7 +451,10 @@ p2p_status launch_gravity(const GravityArgs &a, bool redundant, bool mixed, bool
 
 p2p_status launch_gravity_adjoint(const GravityAdjointArgs &a, hipStream_t s) {
     if (a.L <= 0) return P2P_OK;
-    k_gravity_adjoint<<<static_cast<unsigned>(a.L), kGBlock, 0, s>>>(a);
+    if (a.nbr_shift)
+        k_gravity_adjoint<true><<<static_cast<unsigned>(a.L), kGBlock, 0, s>>>(a);
+    else
+        k_gravity_adjoint<false><<<static_cast<unsigned>(a.L), kGBlock, 0, s>>>(a);
     P2P_LAUNCH_CHECK();
     return P2P_OK;
 }

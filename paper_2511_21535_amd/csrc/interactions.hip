@@ -66,13 +66,15 @@ __global__ __launch_bounds__(256) void k_record_lengths(const int32_t *__restric
 }
 
 // Records of leaf A, one wavefront per leaf: for every entry of nbr(A), the
-// header, A's rows and B's rows, four rows per lane in flight.
+// header, A's rows and B's rows, four rows per lane in flight.  B's rows are
+// placed at x + s, s the entry's image (zero without image codes).
 template <bool MIXED, bool NT>
 __global__ __launch_bounds__(256) void k_copy_records(
     const Row4d *__restrict__ sorted, const uint64_t *__restrict__ leaf_key,
     const int8_t *__restrict__ leaf_level, const int32_t *__restrict__ leaf_start,
     const int64_t *__restrict__ nbr_start, const int32_t *__restrict__ nbr_idx,
-    const int64_t *__restrict__ rec_start, int64_t L, Row4d *__restrict__ d8, float4 *__restrict__ d4) {
+    const int8_t *__restrict__ nbr_shift, const int64_t *__restrict__ rec_start, int64_t L,
+    Row4d *__restrict__ d8, float4 *__restrict__ d4) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t A = p2pd::xcd_contiguous(blockIdx.x, gridDim.x) * 4 + w;
     if (A >= L) return;
@@ -89,6 +91,9 @@ __global__ __launch_bounds__(256) void k_copy_records(
         const int32_t B = nbr_idx[e];
         const int32_t b0 = leaf_start[B], occB = leaf_start[B + 1] - b0;
         const int64_t d = rec_start[e];
+        const int code = nbr_shift ? nbr_shift[e] : 13;
+        const double sh[3] = {static_cast<double>(code % 3 - 1), static_cast<double>((code / 3) % 3 - 1),
+                              static_cast<double>(code / 9 - 1)};
         if (lane == 0) {
             if constexpr (MIXED)
                 put<NT>(d4 + d, make_float4(__int_as_float(occA), __int_as_float(occB),
@@ -106,6 +111,10 @@ __global__ __launch_bounds__(256) void k_copy_records(
             for (int u = 0; u < 4; ++u) {
                 const int32_t r = min(p0 + 64 * u + lane, rows - 1);
                 v[u] = sorted[r < occA ? a0 + r : b0 + (r - occA)];
+                const bool source = r >= occA;
+                v[u].x += source ? sh[0] : 0.0;
+                v[u].y += source ? sh[1] : 0.0;
+                v[u].z += source ? sh[2] : 0.0;
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -129,11 +138,13 @@ constexpr int kRecFlush = 32;
 // groups), FP32-mixed pair terms summed at most 32 at a time in float into
 // double; the G partials meet in LDS.  Record (A, A) holds every target once
 // as its own source at d = 0; that self term is added back as in the box
-// kernels.
+// kernels.  With image codes only the unshifted record (A, A) is the self
+// record: a point meets its own image elsewhere at a nonzero distance.
 template <bool MIXED, bool EPS0>
 __global__ __launch_bounds__(64 * kEvalWaves) void k_eval_records(
     const int64_t *__restrict__ rec_start, const Row4d *__restrict__ r8, const float4 *__restrict__ r4,
-    int64_t E, const int64_t *__restrict__ res_start, double eps2, Row4d *__restrict__ res) {
+    const int8_t *__restrict__ nbr_shift, int64_t E, const int64_t *__restrict__ res_start, double eps2,
+    Row4d *__restrict__ res) {
     __shared__ double s_red[kEvalWaves][4][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t e = static_cast<int64_t>(blockIdx.x) * kEvalWaves + w;
@@ -155,7 +166,8 @@ __global__ __launch_bounds__(64 * kEvalWaves) void k_eval_records(
     }
     occA = __builtin_amdgcn_readfirstlane(occA);
     occB = __builtin_amdgcn_readfirstlane(occB);
-    const bool self = __builtin_amdgcn_readfirstlane(A) == __builtin_amdgcn_readfirstlane(B);
+    const bool self = __builtin_amdgcn_readfirstlane(A) == __builtin_amdgcn_readfirstlane(B) &&
+                      (nbr_shift == nullptr || nbr_shift[e] == 13);
     const int64_t t0 = r + 1, s0 = r + 1 + occA;
     const float eps2f = static_cast<float>(eps2);
     const int64_t out0 = res_start[e];
@@ -279,13 +291,13 @@ p2p_status launch_record_lengths(const int32_t *leaf_start, const int64_t *nbr_s
 
 p2p_status launch_copy_records(const Row4d *sorted, const uint64_t *leaf_key, const int8_t *leaf_level,
                                const int32_t *leaf_start, const int64_t *nbr_start,
-                               const int32_t *nbr_idx, const int64_t *rec_start, int64_t L, Row4d *d8,
-                               float4 *d4, bool streaming, hipStream_t s) {
+                               const int32_t *nbr_idx, const int8_t *nbr_shift, const int64_t *rec_start,
+                               int64_t L, Row4d *d8, float4 *d4, bool streaming, hipStream_t s) {
     if (L <= 0) return P2P_OK;
     const unsigned g = grid_for(L, 4);
 #define P2P_REC(M, NT)                                                                                \
     k_copy_records<M, NT><<<g, 256, 0, s>>>(sorted, leaf_key, leaf_level, leaf_start, nbr_start, nbr_idx, \
-                                            rec_start, L, d8, d4)
+                                            nbr_shift, rec_start, L, d8, d4)
     if (d4) {
         if (streaming) P2P_REC(true, true); else P2P_REC(true, false);
     } else {
@@ -296,19 +308,20 @@ p2p_status launch_copy_records(const Row4d *sorted, const uint64_t *leaf_key, co
     return P2P_OK;
 }
 
-p2p_status launch_eval_records(const int64_t *rec_start, const Row4d *r8, const float4 *r4, int64_t E,
-                               const int64_t *res_start, double eps2, bool eps_zero, Row4d *res,
-                               hipStream_t s) {
+p2p_status launch_eval_records(const int64_t *rec_start, const Row4d *r8, const float4 *r4,
+                               const int8_t *nbr_shift, int64_t E, const int64_t *res_start, double eps2,
+                               bool eps_zero, Row4d *res, hipStream_t s) {
     if (E <= 0) return P2P_OK;
     const unsigned g = grid_for(E, kEvalWaves);
     const unsigned b = 64 * kEvalWaves;
+#define P2P_EVAL_REC(M, E0) \
+    k_eval_records<M, E0><<<g, b, 0, s>>>(rec_start, r8, r4, nbr_shift, E, res_start, eps2, res)
     if (r4) {
-        if (eps_zero) k_eval_records<true, true><<<g, b, 0, s>>>(rec_start, r8, r4, E, res_start, eps2, res);
-        else k_eval_records<true, false><<<g, b, 0, s>>>(rec_start, r8, r4, E, res_start, eps2, res);
+        if (eps_zero) P2P_EVAL_REC(true, true); else P2P_EVAL_REC(true, false);
     } else {
-        if (eps_zero) k_eval_records<false, true><<<g, b, 0, s>>>(rec_start, r8, r4, E, res_start, eps2, res);
-        else k_eval_records<false, false><<<g, b, 0, s>>>(rec_start, r8, r4, E, res_start, eps2, res);
+        if (eps_zero) P2P_EVAL_REC(false, true); else P2P_EVAL_REC(false, false);
     }
+#undef P2P_EVAL_REC
     P2P_LAUNCH_CHECK();
     return P2P_OK;
 }

@@ -17,6 +17,13 @@
 // The searches start from a directory over the top bits of the key: dir[p]
 // is the first leaf whose key is at least p << shift, so a key's bucket bounds
 // its search to the leaves of that bucket.
+//
+// Periodic lists (particles on the unit torus): a cell past a face of the
+// domain wraps to the opposite side and carries the image code of that wrap,
+// c = (sx+1) + 3 (sy+1) + 9 (sz+1); its leaves are tested shifted by
+// (sx, sy, sz) domain edges.  Ranges are deduplicated and ordered by (c, lo),
+// so the list comes out ascending in (c, B); one leaf may appear under
+// several codes.
 #include "p2p_internal.h"
 
 namespace p2p {
@@ -64,15 +71,17 @@ __device__ inline void wave_sync() {
 // did not fit its slots (counts[A] > kNbrSlots).
 enum { kNbrCount = 0, kNbrFill = 1 };
 
-template <int MODE>
+// PER: periodic lists; slot_code / nbr_shift receive the image codes.
+template <int MODE, bool PER>
 __global__ __launch_bounds__(64 * kNbrWaves) void k_neighbors(
     const uint64_t *__restrict__ leaf_key, const int8_t *__restrict__ leaf_level, int64_t L,
     int key_bits, int inst_shift, const int32_t *__restrict__ dir, int dir_bits, int dir_shift,
     const int32_t *__restrict__ leaf_start, int32_t *__restrict__ counts, int32_t *__restrict__ segs,
-    int32_t *__restrict__ slots, int32_t *__restrict__ overflow, const int64_t *__restrict__ nbr_start,
-    int32_t *__restrict__ nbr_idx) {
+    int32_t *__restrict__ slots, int8_t *__restrict__ slot_code, int32_t *__restrict__ overflow,
+    const int64_t *__restrict__ nbr_start, int32_t *__restrict__ nbr_idx, int8_t *__restrict__ nbr_shift) {
     __shared__ int32_t s_lo[kNbrWaves][32];
     __shared__ int32_t s_pre[kNbrWaves][33];
+    __shared__ int32_t s_code[kNbrWaves][32];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t A = static_cast<int64_t>(blockIdx.x) * kNbrWaves + w;
     if (A >= L) return;
@@ -91,10 +100,23 @@ __global__ __launch_bounds__(64 * kNbrWaves) void k_neighbors(
     // ---- one cell per lane
     int64_t lo = 0, hi = 0;
     bool valid = false;
+    int code = 13;
     if (lane < 27) {
-        const int64_t c[3] = {a[0] + (lane % 3 - 1) * sA, a[1] + ((lane / 3) % 3 - 1) * sA,
-                              a[2] + (lane / 9 - 1) * sA};
-        if (c[0] >= 0 && c[1] >= 0 && c[2] >= 0 && c[0] < dim && c[1] < dim && c[2] < dim) {
+        int64_t c[3] = {a[0] + (lane % 3 - 1) * sA, a[1] + ((lane / 3) % 3 - 1) * sA,
+                        a[2] + (lane / 9 - 1) * sA};
+        bool inside = c[0] >= 0 && c[1] >= 0 && c[2] >= 0 && c[0] < dim && c[1] < dim && c[2] < dim;
+        if constexpr (PER) {
+            // c lies in [-sA, dim + sA) with sA <= dim: one wrap per axis
+            int wrap[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                wrap[d] = c[d] < 0 ? -1 : (c[d] >= dim ? 1 : 0);
+                c[d] -= wrap[d] * dim;
+            }
+            code = (wrap[0] + 1) + 3 * (wrap[1] + 1) + 9 * (wrap[2] + 1);
+            inside = true;
+        }
+        if (inside) {
             const uint64_t kC = inst_bits | p2pd::morton3(static_cast<uint32_t>(c[0]),
                                                           static_cast<uint32_t>(c[1]),
                                                           static_cast<uint32_t>(c[2]));
@@ -116,23 +138,27 @@ __global__ __launch_bounds__(64 * kNbrWaves) void k_neighbors(
             valid = lo < hi;
         }
     }
-    // ---- drop duplicate ranges (one large leaf covering several cells), rank by lo
+    // ---- drop duplicate ranges (one large leaf covering several cells of
+    // one image), rank by (code, lo)
     bool first = valid;
     for (int q = 0; q < 27; ++q) {
         const int64_t loq = __shfl(lo, q, 64);
         const int vq = __shfl(static_cast<int>(valid), q, 64);
-        if (vq && q < lane && loq == lo) first = false;
+        const int cq = PER ? __shfl(code, q, 64) : 13;
+        if (vq && q < lane && loq == lo && cq == code) first = false;
     }
     int rank = 0;
     for (int q = 0; q < 27; ++q) {
         const int64_t loq = __shfl(lo, q, 64);
         const int fq = __shfl(static_cast<int>(first), q, 64);
-        if (fq && loq < lo) ++rank;
+        const int cq = PER ? __shfl(code, q, 64) : 13;
+        if (fq && (cq < code || (cq == code && loq < lo))) ++rank;
     }
     const int K = __popcll(__ballot(first));
     if (first) {
         s_lo[w][rank] = static_cast<int32_t>(lo);
         s_pre[w][rank] = static_cast<int32_t>(hi - lo);
+        if constexpr (PER) s_code[w][rank] = code;
     }
     wave_sync();
     // exclusive prefix of the range lengths in sorted order
@@ -158,24 +184,36 @@ __global__ __launch_bounds__(64 * kNbrWaves) void k_neighbors(
         const int32_t cidx = base + lane;
         bool adj = false;
         int64_t B = 0;
+        int cB = 13;
         if (cidx < total) {
             int r = 0;
             while (r + 1 < K && s_pre[w][r + 1] <= cidx) ++r;
             B = s_lo[w][r] + (cidx - s_pre[w][r]);
             const uint64_t kB = leaf_key[B] & local_mask;
             const int64_t sB = int64_t(1) << (key_bits - leaf_level[B]);
-            const int64_t b[3] = {p2pd::compact3(kB), p2pd::compact3(kB >> 1),
-                                  p2pd::compact3(kB >> 2)};
+            int64_t b[3] = {p2pd::compact3(kB), p2pd::compact3(kB >> 1), p2pd::compact3(kB >> 2)};
+            if constexpr (PER) {
+                cB = s_code[w][r];
+                b[0] += (cB % 3 - 1) * dim;
+                b[1] += ((cB / 3) % 3 - 1) * dim;
+                b[2] += (cB / 9 - 1) * dim;
+            }
             adj = true;
 #pragma unroll
             for (int d = 0; d < 3; ++d) adj = adj && (a[d] <= b[d] + sB) && (b[d] <= a[d] + sA);
         }
         const uint64_t bal = __ballot(adj);
         const int64_t pos = written + __popcll(bal & below);
-        if (MODE == kNbrFill && adj) nbr_idx[out0 + pos] = static_cast<int32_t>(B);
+        if (MODE == kNbrFill && adj) {
+            nbr_idx[out0 + pos] = static_cast<int32_t>(B);
+            if constexpr (PER) nbr_shift[out0 + pos] = static_cast<int8_t>(cB);
+        }
         if (MODE == kNbrCount && adj) {
             occ_sum += leaf_start[B + 1] - leaf_start[B];
-            if (pos < kNbrSlots) slots[A * kNbrSlots + pos] = static_cast<int32_t>(B);
+            if (pos < kNbrSlots) {
+                slots[A * kNbrSlots + pos] = static_cast<int32_t>(B);
+                if constexpr (PER) slot_code[A * kNbrSlots + pos] = static_cast<int8_t>(cB);
+            }
         }
         written += __popcll(bal);
     }
@@ -190,16 +228,21 @@ __global__ __launch_bounds__(64 * kNbrWaves) void k_neighbors(
     }
 }
 
-// Slots into the CSR lists: thread (A, s) moves entry s of a list that fit.
+// Slots into the CSR lists: thread (A, s) moves entry s of a list that fit
+// (and its image code, if slot_code is not null).
 __global__ void k_compact_slots(const int32_t *__restrict__ counts, const int32_t *__restrict__ slots,
+                                const int8_t *__restrict__ slot_code,
                                 const int64_t *__restrict__ nbr_start, int64_t L,
-                                int32_t *__restrict__ nbr_idx) {
+                                int32_t *__restrict__ nbr_idx, int8_t *__restrict__ nbr_shift) {
     const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t A = t / kNbrSlots;
     const int sidx = static_cast<int>(t % kNbrSlots);
     if (A >= L) return;
     const int32_t c = counts[A];
-    if (c <= kNbrSlots && sidx < c) nbr_idx[nbr_start[A] + sidx] = slots[t];
+    if (c <= kNbrSlots && sidx < c) {
+        nbr_idx[nbr_start[A] + sidx] = slots[t];
+        if (slot_code) nbr_shift[nbr_start[A] + sidx] = slot_code[t];
+    }
 }
 
 // The list totals E and S and the number of overflowing lists, gathered for
@@ -227,12 +270,15 @@ p2p_status launch_key_directory(const uint64_t *leaf_key, int64_t L, int total_k
 p2p_status launch_neighbors_count(const uint64_t *leaf_key, const int8_t *leaf_level, int64_t L,
                                   int key_bits, int inst_shift, const int32_t *dir, int total_key_bits,
                                   const int32_t *leaf_start, int32_t *counts, int32_t *segs,
-                                  int32_t *slots, int32_t *overflow, hipStream_t s) {
+                                  int32_t *slots, int8_t *slot_code, int32_t *overflow, hipStream_t s) {
     if (L <= 0) return P2P_OK;
     const int db = neighbor_dir_bits(total_key_bits);
-    k_neighbors<kNbrCount><<<grid_for(L, kNbrWaves), 64 * kNbrWaves, 0, s>>>(
-        leaf_key, leaf_level, L, key_bits, inst_shift, dir, db, total_key_bits - db, leaf_start, counts,
-        segs, slots, overflow, nullptr, nullptr);
+#define P2P_NBR_COUNT(PER)                                                                           \
+    k_neighbors<kNbrCount, PER><<<grid_for(L, kNbrWaves), 64 * kNbrWaves, 0, s>>>(                  \
+        leaf_key, leaf_level, L, key_bits, inst_shift, dir, db, total_key_bits - db, leaf_start, counts, \
+        segs, slots, slot_code, overflow, nullptr, nullptr, nullptr)
+    if (slot_code) P2P_NBR_COUNT(true); else P2P_NBR_COUNT(false);
+#undef P2P_NBR_COUNT
     P2P_LAUNCH_CHECK();
     return P2P_OK;
 }
@@ -246,16 +292,21 @@ p2p_status launch_nbr_totals(const int64_t *start, const int64_t *seg_scan, cons
 
 p2p_status launch_neighbors_fill(const uint64_t *leaf_key, const int8_t *leaf_level, int64_t L,
                                  int key_bits, int inst_shift, const int32_t *dir, int total_key_bits,
-                                 const int32_t *counts, const int32_t *slots, bool any_overflow,
-                                 const int64_t *nbr_start, int32_t *nbr_idx, hipStream_t s) {
+                                 const int32_t *counts, const int32_t *slots, const int8_t *slot_code,
+                                 bool any_overflow, const int64_t *nbr_start, int32_t *nbr_idx,
+                                 int8_t *nbr_shift, hipStream_t s) {
     if (L <= 0) return P2P_OK;
-    k_compact_slots<<<grid_for(L * kNbrSlots, 256), 256, 0, s>>>(counts, slots, nbr_start, L, nbr_idx);
+    k_compact_slots<<<grid_for(L * kNbrSlots, 256), 256, 0, s>>>(counts, slots, slot_code, nbr_start, L,
+                                                                 nbr_idx, nbr_shift);
     P2P_LAUNCH_CHECK();
     if (any_overflow) {
         const int db = neighbor_dir_bits(total_key_bits);
-        k_neighbors<kNbrFill><<<grid_for(L, kNbrWaves), 64 * kNbrWaves, 0, s>>>(
-            leaf_key, leaf_level, L, key_bits, inst_shift, dir, db, total_key_bits - db, nullptr,
-            const_cast<int32_t *>(counts), nullptr, nullptr, nullptr, nbr_start, nbr_idx);
+#define P2P_NBR_FILL(PER)                                                                             \
+        k_neighbors<kNbrFill, PER><<<grid_for(L, kNbrWaves), 64 * kNbrWaves, 0, s>>>(                \
+            leaf_key, leaf_level, L, key_bits, inst_shift, dir, db, total_key_bits - db, nullptr,     \
+            const_cast<int32_t *>(counts), nullptr, nullptr, nullptr, nullptr, nbr_start, nbr_idx, nbr_shift)
+        if (slot_code) P2P_NBR_FILL(true); else P2P_NBR_FILL(false);
+#undef P2P_NBR_FILL
         P2P_LAUNCH_CHECK();
     }
     return P2P_OK;

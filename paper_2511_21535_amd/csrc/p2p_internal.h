@@ -99,22 +99,26 @@ p2p_status launch_key_directory(const uint64_t *leaf_key, int64_t L, int total_k
 // lengths (points of the leaves in the list) and the first 64 entries of each
 // list into slots[L][64]; after the scan of the counts, the fill moves the
 // slots into the CSR and searches again only for the lists longer than 64.
+// A non-null slot_code selects periodic lists (particles on the unit torus):
+// slot_code[L][64] and nbr_shift then receive the image codes.
 constexpr int kNbrSlotsPerLeaf = 64;
 p2p_status launch_neighbors_count(const uint64_t *leaf_key, const int8_t *leaf_level, int64_t L,
                                   int key_bits, int inst_shift, const int32_t *dir, int total_key_bits,
                                   const int32_t *leaf_start, int32_t *counts, int32_t *segs,
-                                  int32_t *slots, int32_t *overflow, hipStream_t s);
+                                  int32_t *slots, int8_t *slot_code, int32_t *overflow, hipStream_t s);
 p2p_status launch_nbr_totals(const int64_t *start, const int64_t *seg_scan, const int32_t *overflow,
                              int64_t L, int64_t *out, hipStream_t s);
 p2p_status launch_neighbors_fill(const uint64_t *leaf_key, const int8_t *leaf_level, int64_t L,
                                  int key_bits, int inst_shift, const int32_t *dir, int total_key_bits,
-                                 const int32_t *counts, const int32_t *slots, bool any_overflow,
-                                 const int64_t *nbr_start, int32_t *nbr_idx, hipStream_t s);
+                                 const int32_t *counts, const int32_t *slots, const int8_t *slot_code,
+                                 bool any_overflow, const int64_t *nbr_start, int32_t *nbr_idx,
+                                 int8_t *nbr_shift, hipStream_t s);
 
 // Restructure (restructure.hip).
+// nbr_shift (image codes, may be null) places the unshifted self image.
 p2p_status launch_seg_lengths(const int32_t *leaf_start, const int64_t *nbr_start,
-                              const int32_t *nbr_idx, int64_t L, int32_t *seg_len,
-                              int32_t *red_self, hipStream_t s);
+                              const int32_t *nbr_idx, const int8_t *nbr_shift, int64_t L,
+                              int32_t *seg_len, int32_t *red_self, hipStream_t s);
 template <class T>
 p2p_status launch_permute_rows(const T *src, const int32_t *perm, int64_t n, int64_t row_len,
                                T *dst, hipStream_t s);
@@ -123,11 +127,12 @@ p2p_status launch_scatter4(const double *a, const double *b, const double *c, co
                            const int32_t *iperm, int64_t n, Row4d *out, hipStream_t s);
 // Gravity payload from sorted rows: FP64 rows (d8) or, for FP32_MIXED, float4
 // (x - c_A, y - c_A, z - c_A, m) relative to the centre of target leaf A (d4).
+// With image codes (nbr_shift not null) each source is placed at x + s.
 p2p_status launch_copy_segments_gravity(const Row4d *sorted, const uint64_t *leaf_key,
                                         const int8_t *leaf_level, const int32_t *leaf_start,
                                         const int64_t *nbr_start, const int32_t *nbr_idx,
-                                        const int64_t *red_start, int64_t L, Row4d *d8,
-                                        float4 *d4, bool streaming, hipStream_t s);
+                                        const int8_t *nbr_shift, const int64_t *red_start, int64_t L,
+                                        Row4d *d8, float4 *d4, bool streaming, hipStream_t s);
 template <class T>
 p2p_status launch_copy_segments(const T *sorted, int64_t row_len, const int32_t *leaf_start,
                                 const int64_t *nbr_start, const int32_t *nbr_idx,
@@ -139,20 +144,22 @@ constexpr int64_t kStreamingLayoutBytes = int64_t(128) << 20;
 
 // Per-interaction layout (interactions.hip): one record per near-list entry e = (A, B),
 // a header row (occ_A, occ_B, A, B as integers) then A's rows then B's rows,
-// FP32_MIXED float4 relative to the centre of A, or FP64 rows.
+// FP32_MIXED float4 relative to the centre of A, or FP64 rows; with image codes
+// (nbr_shift not null) B's rows sit at x + s.
 p2p_status launch_record_lengths(const int32_t *leaf_start, const int64_t *nbr_start,
                                  const int32_t *nbr_idx, int64_t L, int32_t *rec_len, int32_t *tgt_len,
                                  hipStream_t s);
 p2p_status launch_copy_records(const Row4d *sorted, const uint64_t *leaf_key, const int8_t *leaf_level,
                                const int32_t *leaf_start, const int64_t *nbr_start,
-                               const int32_t *nbr_idx, const int64_t *rec_start, int64_t L, Row4d *d8,
-                               float4 *d4, bool streaming, hipStream_t s);
+                               const int32_t *nbr_idx, const int8_t *nbr_shift, const int64_t *rec_start,
+                               int64_t L, Row4d *d8, float4 *d4, bool streaming, hipStream_t s);
 // Pair sums of every record into its own result rows res[res_start[e] + t]
 // (phi, ax, ay, az per target, FP64), then the per-target sums over the
-// records of its leaf, written to caller order.
-p2p_status launch_eval_records(const int64_t *rec_start, const Row4d *r8, const float4 *r4, int64_t E,
-                               const int64_t *res_start, double eps2, bool eps_zero, Row4d *res,
-                               hipStream_t s);
+// records of its leaf, written to caller order.  The self record is (A, A)
+// in the unshifted image (nbr_shift null or code 13).
+p2p_status launch_eval_records(const int64_t *rec_start, const Row4d *r8, const float4 *r4,
+                               const int8_t *nbr_shift, int64_t E, const int64_t *res_start, double eps2,
+                               bool eps_zero, Row4d *res, hipStream_t s);
 p2p_status launch_reduce_records(const int32_t *leaf_start, const int64_t *nbr_start,
                                  const int64_t *res_start, const int32_t *perm, int64_t L,
                                  const Row4d *res, double *phi, double *ax, double *ay, double *az,
@@ -167,6 +174,7 @@ struct GravityArgs {
     const int8_t *leaf_level;
     const int64_t *nbr_start;
     const int32_t *nbr_idx;
+    const int8_t *nbr_shift;          // image codes of periodic lists (gather), else null
     const int64_t *red_start;
     const int32_t *red_self;
     const Row4d *s4;                  // FP64 rows (x, y, z, m): sorted (gather) or redundant (FP64)
@@ -183,6 +191,7 @@ struct GravityAdjointArgs {
     const int32_t *perm;
     const int64_t *nbr_start;
     const int32_t *nbr_idx;
+    const int8_t *nbr_shift;                // image codes of periodic lists, else null
     const Row4d *s4;                        // sorted rows (x, y, z, m)
     const Row4d *g4;                        // sorted upstream gradients (g_phi, g_ax, g_ay, g_az)
     double eps2;

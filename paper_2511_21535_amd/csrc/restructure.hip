@@ -49,14 +49,15 @@ __device__ inline void put_row(T *d, const T &v) {
 }
 
 // Segment length of every target leaf A (the points of the leaves in nbr(A))
-// and the offset of A's own rows in it (the points of the neighbours listed
-// before A, the lists being ascending): 16 lanes per leaf, lanes across the
-// list, two sums over the 16 lanes.
+// and the offset of A's own rows in it (the points of the entries listed
+// before A's unshifted image, the lists being ascending in (image code, B)):
+// 16 lanes per leaf, lanes across the list, two sums over the 16 lanes.
 constexpr int kSegLanes = 16;
 
 __global__ __launch_bounds__(256) void k_seg_lengths(const int32_t *__restrict__ leaf_start,
                                                      const int64_t *__restrict__ nbr_start,
-                                                     const int32_t *__restrict__ nbr_idx, int64_t L,
+                                                     const int32_t *__restrict__ nbr_idx,
+                                                     const int8_t *__restrict__ nbr_shift, int64_t L,
                                                      int32_t *__restrict__ seg_len,
                                                      int32_t *__restrict__ red_self) {
     const int sub = threadIdx.x % kSegLanes;
@@ -65,9 +66,10 @@ __global__ __launch_bounds__(256) void k_seg_lengths(const int32_t *__restrict__
     int32_t len = 0, before = 0;
     for (int64_t e = nbr_start[A] + sub; e < nbr_start[A + 1]; e += kSegLanes) {
         const int32_t B = nbr_idx[e];
+        const int code = nbr_shift ? nbr_shift[e] : 13;
         const int32_t occ = leaf_start[B + 1] - leaf_start[B];
         len += occ;
-        if (B < A) before += occ;
+        if (code < 13 || (code == 13 && B < A)) before += occ;
     }
 #pragma unroll
     for (int o = kSegLanes / 2; o > 0; o >>= 1) {
@@ -157,19 +159,21 @@ __device__ int64_t load_nbr_chunk(const int32_t *__restrict__ leaf_start,
 // source through the map (or, for a chunk of more than kMapRows rows, by a
 // forward walk over the prefix).  FP32_MIXED rows are written as float4
 // (x - c_A, y - c_A, z - c_A, m) with c_A the centre of the target leaf, the
-// difference taken in double.
+// difference taken in double.  PER (periodic lists): each row is first
+// shifted by its entry's image, (x + s) in double.
 constexpr int kMapRows = 4096;
 constexpr int kRowsPerLane = 8;
 
-template <bool MIXED, bool NT>
+template <bool MIXED, bool NT, bool PER>
 __global__ __launch_bounds__(256) void k_copy_segments_grav(
     const Row4d *__restrict__ sorted, const uint64_t *__restrict__ leaf_key,
     const int8_t *__restrict__ leaf_level, const int32_t *__restrict__ leaf_start,
     const int64_t *__restrict__ nbr_start, const int32_t *__restrict__ nbr_idx,
-    const int64_t *__restrict__ red_start, int64_t L, Row4d *__restrict__ d8,
-    float4 *__restrict__ d4) {
+    const int8_t *__restrict__ nbr_shift, const int64_t *__restrict__ red_start, int64_t L,
+    Row4d *__restrict__ d8, float4 *__restrict__ d4) {
     __shared__ int32_t s_pre[4][65];
     __shared__ int32_t s_first[4][64];
+    __shared__ int32_t s_code[PER ? 4 : 1][64];
     __shared__ uint8_t s_map[4][kMapRows];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t A = p2pd::xcd_contiguous(blockIdx.x, gridDim.x) * 4 + w;
@@ -186,11 +190,12 @@ __global__ __launch_bounds__(256) void k_copy_segments_grav(
     int64_t out = red_start[A];
     for (int64_t c0 = e0; c0 < e1; c0 += 64) {
         const int nc = static_cast<int>(min<int64_t>(64, e1 - c0));
-        int32_t occ = 0, first = 0;
+        int32_t occ = 0, first = 0, code = 13;
         if (lane < nc) {
             const int32_t B = nbr_idx[c0 + lane];
             first = leaf_start[B];
             occ = leaf_start[B + 1] - first;
+            if constexpr (PER) code = nbr_shift[c0 + lane];
         }
         int32_t inc = occ;
 #pragma unroll
@@ -200,6 +205,7 @@ __global__ __launch_bounds__(256) void k_copy_segments_grav(
         }
         s_pre[w][lane] = inc - occ;
         s_first[w][lane] = first;
+        if constexpr (PER) s_code[w][lane] = code;
         const int32_t rows = __shfl(inc, 63, 64);
         if (lane == 0) s_pre[w][64] = rows;
         const bool use_map = rows <= kMapRows;
@@ -209,12 +215,21 @@ __global__ __launch_bounds__(256) void k_copy_segments_grav(
         __builtin_amdgcn_wave_barrier();
         int b = 0;
         auto src_row = [&](int32_t p) {
+            int bb;
             if (use_map) {
-                const int bb = s_map[w][p];
-                return sorted[s_first[w][bb] + (p - s_pre[w][bb])];
+                bb = s_map[w][p];
+            } else {
+                while (b + 1 < nc && s_pre[w][b + 1] <= p) ++b;
+                bb = b;
             }
-            while (b + 1 < nc && s_pre[w][b + 1] <= p) ++b;
-            return sorted[s_first[w][b] + (p - s_pre[w][b])];
+            Row4d v = sorted[s_first[w][bb] + (p - s_pre[w][bb])];
+            if constexpr (PER) {
+                const int cd = s_code[w][bb];
+                v.x += static_cast<double>(cd % 3 - 1);
+                v.y += static_cast<double>((cd / 3) % 3 - 1);
+                v.z += static_cast<double>(cd / 9 - 1);
+            }
+            return v;
         };
         // all loads of a group are issued before any of its stores; lanes
         // past the end take the last row again and store it to its own place
@@ -292,11 +307,11 @@ __global__ __launch_bounds__(kCopyBlock) void k_copy_segments_units(
 }  // namespace
 
 p2p_status launch_seg_lengths(const int32_t *leaf_start, const int64_t *nbr_start,
-                              const int32_t *nbr_idx, int64_t L, int32_t *seg_len,
-                              int32_t *red_self, hipStream_t s) {
+                              const int32_t *nbr_idx, const int8_t *nbr_shift, int64_t L,
+                              int32_t *seg_len, int32_t *red_self, hipStream_t s) {
     if (L <= 0) return P2P_OK;
-    k_seg_lengths<<<grid_for(L * kSegLanes, 256), 256, 0, s>>>(leaf_start, nbr_start, nbr_idx, L, seg_len,
-                                                                red_self);
+    k_seg_lengths<<<grid_for(L * kSegLanes, 256), 256, 0, s>>>(leaf_start, nbr_start, nbr_idx, nbr_shift, L,
+                                                                seg_len, red_self);
     P2P_LAUNCH_CHECK();
     return P2P_OK;
 }
@@ -369,18 +384,21 @@ p2p_status launch_scatter4(const double *a, const double *b, const double *c, co
 p2p_status launch_copy_segments_gravity(const Row4d *sorted, const uint64_t *leaf_key,
                                         const int8_t *leaf_level, const int32_t *leaf_start,
                                         const int64_t *nbr_start, const int32_t *nbr_idx,
-                                        const int64_t *red_start, int64_t L, Row4d *d8,
-                                        float4 *d4, bool streaming, hipStream_t s) {
+                                        const int8_t *nbr_shift, const int64_t *red_start, int64_t L,
+                                        Row4d *d8, float4 *d4, bool streaming, hipStream_t s) {
     if (L <= 0) return P2P_OK;
     const unsigned g = grid_for(L, 4);
-#define P2P_COPY_GRAV(M, NT)                                                                         \
-    k_copy_segments_grav<M, NT><<<g, 256, 0, s>>>(sorted, leaf_key, leaf_level, leaf_start, nbr_start, \
-                                                  nbr_idx, red_start, L, d8, d4)
-    if (d4) {
-        if (streaming) P2P_COPY_GRAV(true, true); else P2P_COPY_GRAV(true, false);
+#define P2P_COPY_GRAV(M, NT, PER)                                                                    \
+    k_copy_segments_grav<M, NT, PER><<<g, 256, 0, s>>>(sorted, leaf_key, leaf_level, leaf_start,    \
+                                                       nbr_start, nbr_idx, nbr_shift, red_start, L, d8, d4)
+#define P2P_COPY_GRAV_NT(M, PER) \
+    if (streaming) P2P_COPY_GRAV(M, true, PER); else P2P_COPY_GRAV(M, false, PER)
+    if (nbr_shift) {
+        if (d4) P2P_COPY_GRAV_NT(true, true); else P2P_COPY_GRAV_NT(false, true);
     } else {
-        if (streaming) P2P_COPY_GRAV(false, true); else P2P_COPY_GRAV(false, false);
+        if (d4) P2P_COPY_GRAV_NT(true, false); else P2P_COPY_GRAV_NT(false, false);
     }
+#undef P2P_COPY_GRAV_NT
 #undef P2P_COPY_GRAV
     P2P_LAUNCH_CHECK();
     return P2P_OK;

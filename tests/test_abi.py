@@ -175,3 +175,36 @@ def test_helmholtz_tile_validation(lib):
     assert query((4, 2, 64, 1), nrhs=32) == L.P2P_EINVAL and "tile[2]" in L.last_error()
     assert query((4, 2, 32, 1), nrhs=1) == L.P2P_EINVAL          # no tile off the matrix-core path
     assert query(None, nrhs=1) == L.P2P_OK
+
+
+def test_periodic_list_validation(lib):
+    t = _tree(10, L_=1)
+    t.perm = t.iperm = t.leaf_start = t.leaf_key = t.leaf_level = 0x1000
+    n = L.p2p_nbrs()
+    n.count, n.nbr_start, n.nbr_idx = 1, 0x1000, 0x1000
+    nb = ctypes.c_size_t(0)
+    z = ctypes.c_void_p(0x1000)
+
+    def grav():
+        return lib.p2p_eval_gravity(ctypes.byref(t), ctypes.byref(n), None, L.P2P_GATHER, L.P2P_FP64, 1e-3,
+                                    z, z, z, z, z, z, z, z, None, ctypes.byref(nb), None)
+    assert grav() == L.P2P_OK
+    n.periodic = 1                       # periodic lists need their image codes
+    assert grav() == L.P2P_EINVAL and "nbr_shift" in L.last_error()
+    n.nbr_shift = 0x1000
+    assert grav() == L.P2P_OK
+    n.periodic = 2
+    assert grav() == L.P2P_EINVAL and "periodic" in L.last_error()
+    n.periodic, n.reserved = 1, 1
+    assert grav() == L.P2P_EINVAL and "reserved" in L.last_error()
+    n.reserved = 0
+    # the torus is defined for particle trees only
+    t.kind = L.P2P_TREE_GRIDS
+    st = lib.p2p_build_neighbors(ctypes.byref(t), ctypes.byref(n), None, ctypes.byref(nb), None)
+    assert st == L.P2P_EINVAL and "particle trees" in L.last_error()
+    t.kind = L.P2P_TREE_PARTICLES
+    assert lib.p2p_build_neighbors(ctypes.byref(t), ctypes.byref(n), None, ctypes.byref(nb), None) == L.P2P_OK
+    plain = nb.value
+    n.periodic = 0
+    assert lib.p2p_build_neighbors(ctypes.byref(t), ctypes.byref(n), None, ctypes.byref(nb), None) == L.P2P_OK
+    assert plain > nb.value             # room for the slot image codes
