@@ -15,8 +15,9 @@ sub-step times, the Locality metric with the paper's speedup model evaluated on
 the measured times (Sec. 3.2-3.4), the roofline of the dominant kernel
 (the redundant evaluation) and the FP64 CPU oracle timed on the workload.
 Gravity lines also time the per-interaction layout (one record per near-list
-entry, results per record summed afterwards) on the same tree and lists,
-outside the timed steps.
+entry, results per record summed afterwards) on the same tree and lists, and
+the same tree on the unit torus (periodic images), both outside the timed
+steps.
 
 --workload selects one of the other configurations for the same measurement
 (their lines are reference measurements, not the headline):
@@ -307,9 +308,58 @@ def run_gravity(wname, args):
     line["interaction_layout"] = {"rows": inter.count, "bytes": inter.count * bpe,
                                   "result_rows": inter.target_rows}
     del inter
+    line["periodic"] = periodic_leg(tree, (gx, gy, gz, gm), w, K, args.warmup, bpe,
+                                    {"neighbors": t_nbr, "restructure": t_res, "eval_redundant": t_red,
+                                     "eval_gather": t_gat})
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline_gravity(x, y, z, m, w, args.cpu_leaves)
     return line
+
+
+def periodic_leg(tree, src, w, K, W, bpe, plain):
+    """The same tree on the unit torus (periodic images, Sec. 5.2): periodic
+    near lists, restructure, redundant and gather evaluations, timed after the
+    headline steps.  Eq. (15): the local share of the near-field time is the
+    plain (local-only) evaluation time over the periodic one; Eq. (14), read as
+    Eq. (4) on the local part, gives the speedup had only the local part been
+    restructured, beside the measured speedup of restructuring both."""
+    import torch
+    from paper_2511_21535_amd import api
+    eps, prec = w["eps"], w["prec"]
+    nbp = tree.neighbors(periodic=True)
+    loc = api.locality(tree, nbp, bytes_per_entry=bpe, cache_bytes=CACHE_BYTES)
+    S, pairs = int(loc["entries"]), int(loc["pairs"])
+    red = api.restructure_gravity(tree, nbp, *src, prec=prec, S=S)
+    outs = [torch.empty(tree.n, dtype=torch.float64, device=src[0].device) for _ in range(4)]
+
+    def step():
+        e = _events(5)
+        e[0].record()
+        nb = tree.neighbors(cap=nbp.count, periodic=True)
+        e[1].record()
+        r = api.restructure_gravity(tree, nb, *src, prec=prec, out=red)
+        e[2].record()
+        api.gravity(tree, nb, eps, layout="redundant", prec=prec, red=r, out=outs)
+        e[3].record()
+        api.gravity(tree, nb, eps, *src, layout="gather", prec=prec, out=outs)
+        e[4].record()
+        return e
+
+    _, (t_nbr, t_res, t_red, t_gat) = _timed_steps(step, K, W)
+    del red
+    share = speedup_model.local_share(plain["eval_gather"], 0.0, t_gat - plain["eval_gather"])
+    x_local = plain["eval_gather"] / (plain["restructure"] + plain["eval_redundant"])
+    return {
+        "near_entries": nbp.count, "redundant_entries": S, "pairs": pairs,
+        "periodic_entries": int((nbp.nbr_shift != 13).sum().item()),
+        "rates": {"redundant_incl_restructure": pairs * K / (t_res + t_red),
+                  "redundant_excl_restructure": pairs * K / t_red, "gather": pairs * K / t_gat},
+        "ms": {"neighbors": t_nbr / K * 1e3, "restructure": t_res / K * 1e3,
+               "eval_redundant": t_red / K * 1e3, "eval_gather": t_gat / K * 1e3},
+        "local_share_eq15": share,
+        "speedup_local_only_eq14": speedup_model.op_speedup(share, x_local),
+        "speedup_both_measured": t_gat / (t_res + t_red),
+    }
 
 
 # --------------------------------------------------------------- Helmholtz
