@@ -22,7 +22,7 @@ steps.
 --workload selects one of the other configurations for the same measurement
 (their lines are reference measurements, not the headline):
   gravity_uniform_4096      4096 uniform particles, uniform depth 3, FP64
-  helmholtz_grid_64         64^3 grid, 1 RHS, FP32 (VALU table kernel)
+  helmholtz_grid_64         64^3 grid, 1 RHS, FP32 matrix cores (target boxes as columns)
   helmholtz_batched_128x64  128 grids 16^3..48^3, 64 RHS, FP32 matrix cores, autotuned
   adjoint_gravity_256k      2^18 Plummer particles, forward + adjoint, FP64
 
@@ -413,6 +413,15 @@ def run_helmholtz(wname, args):
         roof = {"bound": "mfma", "peak": FP32_MFMA_PEAK_TFLOPS, "instruction": "v_mfma_f32_32x32x2f32"}
         # sorted right-hand sides read once, results written once (complex64)
         alg_bytes = 2 * tree.n * nrhs * 8
+    elif nrhs == 1:
+        # one right-hand side on the matrix cores, target boxes as the columns; the
+        # redundant evaluation call also uploads its parameters and builds the G
+        # blocks (two short launches before the product), all inside t_red
+        kern, src, t_dom = "k_helm_mfma_cols_red", "helmholtz_mfma.hip", t_red / K
+        roof = {"bound": "mfma", "peak": FP32_MFMA_PEAK_TFLOPS, "instruction": "v_mfma_f32_16x16x4f32",
+                "timed": "the redundant evaluation call (parameter upload, G blocks, product)"}
+        # redundant rows read once, results written once (complex64), G blocks read once
+        alg_bytes = S * 8 + tree.n * 8 + 27 * 4096 * 8
     else:
         kern, src, t_dom = "k_helmholtz_red", "helmholtz.hip", t_red / K
         roof = {"bound": "alu", "peak": FP32_VALU_PEAK_TFLOPS}

@@ -2,7 +2,8 @@
 
 Candidates are (waves per workgroup, workgroups per CU, right-hand sides per
 wave); the best of them is then tried with 2, 4 and 8 copies of the G blocks
-in memory (the pattern redundancy factor).  Each candidate is timed on the
+in memory (the pattern redundancy factor), and the fewest copies within 2% of
+the fastest time are kept.  Each candidate is timed on the
 actual problem with HIP events (one warm-up, then the median of `reps` calls)
 and the fastest is cached in a JSON file keyed by device name, grid sizes,
 nrhs and layout.  The cache path is
@@ -22,6 +23,8 @@ from . import api
 CANDIDATES = [(w, c, r) for w in (1, 2, 4) for c in (1, 2, 3, 4, 6, 8) for r in (32, 64)]
 # copies of the G blocks (the pattern redundancy factor), tuned on the best shape
 COPIES = (1, 2, 4, 8)
+# a copy count is kept over a smaller one only if it is faster by more than this
+COPY_MARGIN = 0.02
 
 
 def cache_path() -> str:
@@ -69,6 +72,19 @@ def time_call(fn, reps: int = 3) -> float:
     return ts[len(ts) // 2]
 
 
+def pick_copies(timings: Dict[str, float], shape: Sequence[int], copies: Sequence[int] = COPIES
+                ) -> Tuple[int, int, int, int]:
+    """The tile for the launch shape `shape`: more copies of the G blocks cost
+    memory and HBM traffic (each copy misses in L2 on its own), so the fewest
+    copies whose time is within COPY_MARGIN of the fastest timing are kept."""
+    best_ms = min(timings.values())
+    for c in sorted(copies):
+        k = str(list(shape) + [c])
+        if k in timings and timings[k] <= best_ms * (1.0 + COPY_MARGIN):
+            return tuple(shape) + (c,)
+    return tuple(json.loads(min(timings, key=timings.get)))
+
+
 def tune_helmholtz(tree: api.Tree, nbrs: api.Nbrs, q: Optional[torch.Tensor] = None,
                    red: Optional[api.Redundant] = None, layout: str = "gather",
                    candidates: Sequence[Tuple[int, int, int]] = CANDIDATES, reps: int = 3,
@@ -99,8 +115,7 @@ def tune_helmholtz(tree: api.Tree, nbrs: api.Nbrs, q: Optional[torch.Tensor] = N
     for c in copies:
         if c != 1:
             run(tuple(shape) + (c,))
-    best = min(timings, key=timings.get)
-    tile = tuple(json.loads(best))
+    tile = pick_copies(timings, shape, copies)
     if use_cache:
         cache = _load_cache()
         cache[key] = {"tile": list(tile), "ms": timings}

@@ -547,6 +547,8 @@ p2p_status helmholtz_common(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2
     P2P_TRY(check_grids(grids, n_grids, tree->n));
     const bool fp64 = prec == P2P_FP64, redundant = layout == P2P_REDUNDANT;
     const bool mfma = !fp64 && nrhs % 32 == 0;
+    // one RHS in FP32: matrix cores with the target boxes as columns
+    const bool cols = !fp64 && nrhs == 1;
     int waves_per_wg = 4, wg_per_cu = 2, rhs_tile = (nrhs % 64 == 0) ? 64 : 32, copies = 1;
     if (tile) {
         if (!mfma) return fail(P2P_EINVAL, "tile applies to the matrix-core path (FP32_MIXED, nrhs % 32 == 0)");
@@ -586,14 +588,33 @@ p2p_status helmholtz_common(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2
     }
     const int32_t n_tables = static_cast<int32_t>(khs.size());
 
+    const bool blk = mfma || cols;
+    const int32_t n_tiles = cols ? helmholtz_cols_tiles(grids, n_grids, nullptr) : 0;
+    if (cols) {
+        // every box of a grid instance is a leaf, instances in order
+        int64_t boxes = 0;
+        for (int32_t g = 0; g < n_grids; ++g)
+            boxes += static_cast<int64_t>(grids[g].n_side / 4) * (grids[g].n_side / 4) * (grids[g].n_side / 4);
+        if (boxes != L) return fail(P2P_EINVAL, "tree leaves do not match the grids' boxes");
+    }
+    // the per-call host parameters (h and k per instance, k h per table, the table
+    // and 1/h of each instance, the column tiles) travel in one copy: each small
+    // copy costs a blit launch, a sizeable part of a call on a small grid
+    const size_t o_k = 8 * static_cast<size_t>(n_grids), o_kh = o_k + 8 * static_cast<size_t>(n_grids);
+    const size_t o_itab = o_kh + 8 * static_cast<size_t>(n_tables);
+    const size_t o_isc = o_itab + 4 * static_cast<size_t>(n_grids);
+    const size_t o_tiles = o_isc + 4 * static_cast<size_t>(n_grids);
+    const size_t param_bytes = o_tiles + 8 * static_cast<size_t>(n_tiles);
     Arena ar(ws);
-    double *d_h = ar.take<double>(n_grids);
-    double *d_k = ar.take<double>(n_grids);
-    char *table = mfma ? nullptr : ar.take<char>(static_cast<size_t>(n_grids) * kTableLen * csize);
-    double *d_kh = mfma ? ar.take<double>(n_tables) : nullptr;
-    float2 *blocks = mfma ? ar.take<float2>(static_cast<size_t>(n_tables) * copies * 27 * 4096) : nullptr;
-    int32_t *d_itab = mfma ? ar.take<int32_t>(n_grids) : nullptr;
-    float *d_iscale = mfma ? ar.take<float>(n_grids) : nullptr;
+    char *params = ar.take<char>(param_bytes);
+    double *d_h = reinterpret_cast<double *>(params);
+    double *d_k = reinterpret_cast<double *>(params + o_k);
+    double *d_kh = reinterpret_cast<double *>(params + o_kh);
+    int32_t *d_itab = reinterpret_cast<int32_t *>(params + o_itab);
+    float *d_iscale = reinterpret_cast<float *>(params + o_isc);
+    int32_t *d_tiles = reinterpret_cast<int32_t *>(params + o_tiles);
+    char *table = blk ? nullptr : ar.take<char>(static_cast<size_t>(n_grids) * kTableLen * csize);
+    float2 *blocks = blk ? ar.take<float2>(static_cast<size_t>(n_tables) * copies * 27 * 4096) : nullptr;
     int32_t *work = mfma ? ar.take<int32_t>(L) : nullptr;
     uint64_t *wkeys = mfma ? ar.take<uint64_t>(L) : nullptr;
     uint64_t *wkeys_tmp = mfma ? ar.take<uint64_t>(L) : nullptr;
@@ -622,11 +643,38 @@ p2p_status helmholtz_common(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2
             P2P_TRY(launch_permute_rows<float2>(static_cast<const float2 *>(q), tree->perm, n, nrhs,
                                                 reinterpret_cast<float2 *>(sorted), s));
     }
+    std::vector<char> hp(param_bytes);
+    for (int32_t g = 0; g < n_grids; ++g) {
+        std::memcpy(hp.data() + 8 * g, &grids[g].h, 8);
+        std::memcpy(hp.data() + o_k + 8 * g, &grids[g].k, 8);
+    }
+    std::memcpy(hp.data() + o_kh, khs.data(), 8 * static_cast<size_t>(n_tables));
+    std::memcpy(hp.data() + o_itab, itab.data(), 4 * static_cast<size_t>(n_grids));
+    std::memcpy(hp.data() + o_isc, iscale.data(), 4 * static_cast<size_t>(n_grids));
+    if (cols) helmholtz_cols_tiles(grids, n_grids, reinterpret_cast<int32_t *>(hp.data() + o_tiles));
+    P2P_HIP(hipMemcpyAsync(params, hp.data(), param_bytes, hipMemcpyHostToDevice, s));
+    if (blk) P2P_TRY(launch_green_blocks(d_kh, n_tables, copies, blocks, s));
+    if (cols) {
+        HelmholtzMfmaArgs a{};
+        a.L = L;
+        a.key_bits = tree->key_bits;
+        a.leaf_start = tree->leaf_start;
+        a.leaf_key = tree->leaf_key;
+        a.perm = tree->perm;
+        a.nbr_start = nbrs->nbr_start;
+        a.nbr_idx = nbrs->nbr_idx;
+        a.red_start = redundant ? red->red_start : nullptr;
+        a.src = redundant ? static_cast<const float2 *>(red->planes[0]) : reinterpret_cast<const float2 *>(sorted);
+        a.blocks = blocks;
+        a.copies = 1;
+        a.inst_table = d_itab;
+        a.inst_scale = d_iscale;
+        a.nrhs = 1;
+        a.conj = conj;
+        a.u = static_cast<float2 *>(u);
+        return launch_helmholtz_mfma_cols(a, d_tiles, n_tiles, redundant, s);
+    }
     if (mfma) {
-        P2P_HIP(hipMemcpyAsync(d_kh, khs.data(), n_tables * sizeof(double), hipMemcpyHostToDevice, s));
-        P2P_HIP(hipMemcpyAsync(d_itab, itab.data(), n_grids * sizeof(int32_t), hipMemcpyHostToDevice, s));
-        P2P_HIP(hipMemcpyAsync(d_iscale, iscale.data(), n_grids * sizeof(float), hipMemcpyHostToDevice, s));
-        P2P_TRY(launch_green_blocks(d_kh, n_tables, copies, blocks, s));
         P2P_TRY(launch_work_order(nbrs->nbr_start, L, work, wkeys, wkeys_tmp, wvals_tmp, whist, s));
         HelmholtzMfmaArgs a{};
         a.L = L;
@@ -649,13 +697,6 @@ p2p_status helmholtz_common(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2
         a.u = static_cast<float2 *>(u);
         return launch_helmholtz_mfma(a, redundant, waves_per_wg, wg_per_cu, rhs_tile, s);
     }
-    std::vector<double> hk(2 * n_grids);
-    for (int32_t g = 0; g < n_grids; ++g) {
-        hk[g] = grids[g].h;
-        hk[n_grids + g] = grids[g].k;
-    }
-    P2P_HIP(hipMemcpyAsync(d_h, hk.data(), n_grids * sizeof(double), hipMemcpyHostToDevice, s));
-    P2P_HIP(hipMemcpyAsync(d_k, hk.data() + n_grids, n_grids * sizeof(double), hipMemcpyHostToDevice, s));
     P2P_TRY(launch_green_tables(d_h, d_k, n_grids, fp64, table, s));
     HelmholtzArgs a{};
     a.L = L;

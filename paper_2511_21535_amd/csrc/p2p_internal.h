@@ -248,6 +248,13 @@ p2p_status launch_work_order(const int64_t *nbr_start, int64_t L, int32_t *work,
                              hipStream_t s);
 p2p_status launch_helmholtz_mfma(const HelmholtzMfmaArgs &a, bool redundant, int waves_per_wg,
                                  int wg_per_cu, int rhs_tile, hipStream_t s);
+// Single RHS on matrix cores, target boxes as the columns: tiles of up to 16
+// consecutive boxes of one instance, (first leaf, count) pairs; returns their
+// number (tiles may be null to count).  Uses blocks, inst_table, inst_scale,
+// conj and u of the arguments (copies 1, no work queue).
+int32_t helmholtz_cols_tiles(const p2p_grid *grids, int32_t n_grids, int32_t *tiles);
+p2p_status launch_helmholtz_mfma_cols(const HelmholtzMfmaArgs &a, const int32_t *tiles, int32_t n_tiles,
+                                      bool redundant, hipStream_t s);
 
 // Locality (locality.hip).
 p2p_status launch_locality_stats(const int32_t *leaf_start, const int64_t *nbr_start,

@@ -342,6 +342,21 @@ def test_helmholtz_adjoint_transpose():
     assert _rel(outc, np.conj(oracle.helmholtz_transpose(sides, np.conj(g)))) <= TOL64
 
 
+def test_helmholtz_single_rhs_fp32_adjoint_and_ragged_tiles():
+    """One RHS in FP32 runs on the matrix cores with target boxes as columns,
+    in tiles of 16 boxes that never straddle two instances: instances of 27, 8
+    and 125 boxes (ragged last tiles), plain and conjugated action."""
+    sides = [12, 8, 20]
+    gt, _ = _grid_tree(sides)
+    gn = gt.neighbors()
+    g = W.grid_rhs(gt.n, 1, seed=43)[:, 0].astype(np.complex64)
+    out = _n(api.helmholtz(gt, gn, _t(g), prec="fp32"))
+    assert _rel(out, oracle.helmholtz(sides, g[:, None])[:, 0]) <= TOL32
+    outc = _n(api.helmholtz_adjoint(gt, gn, _t(g), prec="fp32", conjugate=True))
+    refc = np.conj(oracle.helmholtz_transpose(sides, np.conj(g)))
+    assert _rel(outc, refc) <= TOL32
+
+
 # --------------------------------------------------------------- edge cases
 def test_edge_cases():
     # one particle; all particles in one leaf; duplicate points
