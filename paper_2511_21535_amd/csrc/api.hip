@@ -643,17 +643,38 @@ p2p_status helmholtz_common(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2
             P2P_TRY(launch_permute_rows<float2>(static_cast<const float2 *>(q), tree->perm, n, nrhs,
                                                 reinterpret_cast<float2 *>(sorted), s));
     }
-    std::vector<char> hp(param_bytes);
-    for (int32_t g = 0; g < n_grids; ++g) {
-        std::memcpy(hp.data() + 8 * g, &grids[g].h, 8);
-        std::memcpy(hp.data() + o_k + 8 * g, &grids[g].k, 8);
+    // a single-RHS call on a grid of few instances takes its parameters in the
+    // kernel arguments; every other call uploads them
+    HelmInline inl{};
+    if (cols && n_grids <= kInlineGrids && n_tables <= kInlineGrids) {
+        inl.n_grids = n_grids;
+        inl.n_tables = n_tables;
+        int32_t tf = 0, lf = 0;
+        for (int32_t g = 0; g < n_grids; ++g) {
+            const int32_t nb = (grids[g].n_side / 4) * (grids[g].n_side / 4) * (grids[g].n_side / 4);
+            inl.tile_first[g] = tf;
+            inl.leaf_first[g] = lf;
+            inl.itab[g] = itab[g];
+            inl.iscale[g] = iscale[g];
+            tf += (nb + kHelmColBoxes - 1) / kHelmColBoxes;
+            lf += nb;
+        }
+        inl.tile_first[n_grids] = tf;
+        inl.leaf_first[n_grids] = lf;
+        for (int32_t t = 0; t < n_tables; ++t) inl.kh[t] = khs[t];
+    } else {
+        std::vector<char> hp(param_bytes);
+        for (int32_t g = 0; g < n_grids; ++g) {
+            std::memcpy(hp.data() + 8 * g, &grids[g].h, 8);
+            std::memcpy(hp.data() + o_k + 8 * g, &grids[g].k, 8);
+        }
+        std::memcpy(hp.data() + o_kh, khs.data(), 8 * static_cast<size_t>(n_tables));
+        std::memcpy(hp.data() + o_itab, itab.data(), 4 * static_cast<size_t>(n_grids));
+        std::memcpy(hp.data() + o_isc, iscale.data(), 4 * static_cast<size_t>(n_grids));
+        if (cols) helmholtz_cols_tiles(grids, n_grids, reinterpret_cast<int32_t *>(hp.data() + o_tiles));
+        P2P_HIP(hipMemcpyAsync(params, hp.data(), param_bytes, hipMemcpyHostToDevice, s));
     }
-    std::memcpy(hp.data() + o_kh, khs.data(), 8 * static_cast<size_t>(n_tables));
-    std::memcpy(hp.data() + o_itab, itab.data(), 4 * static_cast<size_t>(n_grids));
-    std::memcpy(hp.data() + o_isc, iscale.data(), 4 * static_cast<size_t>(n_grids));
-    if (cols) helmholtz_cols_tiles(grids, n_grids, reinterpret_cast<int32_t *>(hp.data() + o_tiles));
-    P2P_HIP(hipMemcpyAsync(params, hp.data(), param_bytes, hipMemcpyHostToDevice, s));
-    if (blk) P2P_TRY(launch_green_blocks(d_kh, n_tables, copies, blocks, s));
+    if (blk) P2P_TRY(launch_green_blocks(d_kh, inl, n_tables, copies, blocks, s));
     if (cols) {
         HelmholtzMfmaArgs a{};
         a.L = L;
@@ -672,7 +693,7 @@ p2p_status helmholtz_common(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2
         a.nrhs = 1;
         a.conj = conj;
         a.u = static_cast<float2 *>(u);
-        return launch_helmholtz_mfma_cols(a, d_tiles, n_tiles, redundant, s);
+        return launch_helmholtz_mfma_cols(a, d_tiles, inl, n_tiles, redundant, s);
     }
     if (mfma) {
         P2P_TRY(launch_work_order(nbrs->nbr_start, L, work, wkeys, wkeys_tmp, wvals_tmp, whist, s));

@@ -39,12 +39,21 @@ constexpr double kPi = 3.14159265358979323846;
 // blocks[t][c][o][s][i] = e^{i kh sqrt(dd)} / (4 pi sqrt(dd)), dd = |l_i - (l_s + 4 o)|^2,
 // zero for dd = 0, identical for every copy c.  o = (ox+1) + 3 (oy+1) + 9 (oz+1); l_* are
 // local Morton coordinates.
-__global__ void k_green_blocks(const double *__restrict__ kh, int32_t n_tables, int32_t copies,
-                               float2 *__restrict__ blocks) {
+__global__ void k_green_blocks(const double *__restrict__ kh_dev, HelmInline inl, int32_t n_tables,
+                               int32_t copies, float2 *__restrict__ blocks) {
     const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t per = 27 * 64 * 64;
     if (t >= per * n_tables * copies) return;
     const int tab = static_cast<int>(t / (per * copies));
+    double khv = 0.0;
+    if (inl.n_grids > 0) {
+        // compile-time indices only, so the argument array stays in the kernel arguments
+#pragma unroll
+        for (int i = 0; i < kInlineGrids; ++i)
+            if (i == tab) khv = inl.kh[i];
+    } else {
+        khv = kh_dev[tab];
+    }
     const int rem = static_cast<int>(t % per);
     const int o = rem / 4096, s = (rem / 64) % 64, i = rem % 64;
     const int od[3] = {o % 3 - 1, (o / 3) % 3 - 1, o / 9 - 1};
@@ -61,7 +70,7 @@ __global__ void k_green_blocks(const double *__restrict__ kh, int32_t n_tables, 
         const double r = sqrt(static_cast<double>(dd));
         const double a = 1.0 / (4.0 * kPi * r);
         double sn, cs;
-        sincos(kh[tab] * r, &sn, &cs);
+        sincos(khv * r, &sn, &cs);
         v = make_float2(static_cast<float>(cs * a), static_cast<float>(sn * a));
     }
     blocks[t] = v;
@@ -224,7 +233,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // column) to the first row of its sources -- the sorted rows of the neighbour
 // box (gather) or its place in the target's segment (redundant) -- from the
 // tile's near lists, which are one contiguous run of the CSR.
-constexpr int kColBoxes = 16;
+constexpr int kColBoxes = kHelmColBoxes;
 constexpr int kColWaves = 4;
 constexpr int kColOffsets = (27 + kColWaves - 1) / kColWaves;
 #ifndef P2P_COL_BUFS
@@ -234,7 +243,7 @@ constexpr int kColBufs = P2P_COL_BUFS;   // operand buffers of the prefetch pipe
 
 template <bool RED, bool CONJ>
 __global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols(
-    int key_bits, const int32_t *__restrict__ tiles, const int32_t *__restrict__ leaf_start,
+    int key_bits, const int32_t *__restrict__ tiles, HelmInline inl, const int32_t *__restrict__ leaf_start,
     const uint64_t *__restrict__ leaf_key, const int32_t *__restrict__ perm,
     const int64_t *__restrict__ nbr_start, const int32_t *__restrict__ nbr_idx,
     const int64_t *__restrict__ red_start, const float2 *__restrict__ src,
@@ -247,8 +256,33 @@ __global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols(
     __shared__ floatx4 s_red[kColWaves - 1][4][2][64];    // partial sums of waves 1.. for wave 0
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int32_t A0 = tiles[2 * blockIdx.x], cnt = tiles[2 * blockIdx.x + 1];
     const uint64_t local_mask = (1ull << (3 * key_bits)) - 1ull;
+    // the tile: its first box, its box count, the G table and 1/h of its instance
+    int32_t A0, cnt, tab;
+    float sc;
+    if (inl.n_grids > 0) {
+        const int32_t b = static_cast<int32_t>(blockIdx.x);
+        int32_t tf = 0, lf = 0, lf1 = 0;
+        tab = 0;
+        sc = 1.f;
+#pragma unroll
+        for (int i = 0; i < kInlineGrids; ++i)
+            if (i < inl.n_grids && b >= inl.tile_first[i]) {
+                tf = inl.tile_first[i];
+                lf = inl.leaf_first[i];
+                lf1 = inl.leaf_first[i + 1];
+                tab = inl.itab[i];
+                sc = inl.iscale[i];
+            }
+        A0 = lf + kColBoxes * (b - tf);
+        cnt = min(kColBoxes, lf1 - A0);
+    } else {
+        A0 = tiles[2 * blockIdx.x];
+        cnt = tiles[2 * blockIdx.x + 1];
+        const int g = static_cast<int>(leaf_key[A0] >> (3 * key_bits));
+        tab = inst_table[g];
+        sc = inst_scale[g];
+    }
 
     for (int i = tid; i < 27 * kColBoxes; i += 64 * kColWaves) s_row[i / kColBoxes][i % kColBoxes] = -1;
     if (tid <= cnt) s_nstart[tid] = nbr_start[A0 + tid];
@@ -280,8 +314,7 @@ __global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols(
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
 
-    const int g = static_cast<int>(leaf_key[A0] >> (3 * key_bits));
-    const float2 *__restrict__ gbase = blocks + static_cast<int64_t>(inst_table[g]) * (27 * 4096);
+    const float2 *__restrict__ gbase = blocks + static_cast<int64_t>(tab) * (27 * 4096);
     // pointers of the wave's idx-th offset: lane (k, i) reads G_o[source 4 kk + k][target 16 rt + i]
     // for the four row tiles rt and source 4 kk + k of column i; a column without that
     // neighbour reads row 0 and is zeroed
@@ -369,7 +402,6 @@ __global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols(
     }
     __syncthreads();
     if (w == 0 && li < cnt) {
-        const float sc = inst_scale[g];
         const int32_t t0 = leaf_start[A0 + li];
 #pragma unroll
         for (int rt = 0; rt < 4; ++rt) {
@@ -389,10 +421,10 @@ __global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols(
 
 }  // namespace
 
-p2p_status launch_green_blocks(const double *d_kh, int32_t n_tables, int32_t copies, float2 *blocks,
-                               hipStream_t s) {
+p2p_status launch_green_blocks(const double *d_kh, const HelmInline &inl, int32_t n_tables, int32_t copies,
+                               float2 *blocks, hipStream_t s) {
     const int64_t n = static_cast<int64_t>(n_tables) * copies * 27 * 4096;
-    k_green_blocks<<<grid_for(n, 256), 256, 0, s>>>(d_kh, n_tables, copies, blocks);
+    k_green_blocks<<<grid_for(n, 256), 256, 0, s>>>(d_kh, inl, n_tables, copies, blocks);
     P2P_LAUNCH_CHECK();
     return P2P_OK;
 }
@@ -458,12 +490,12 @@ int32_t helmholtz_cols_tiles(const p2p_grid *grids, int32_t n_grids, int32_t *ti
     return t;
 }
 
-p2p_status launch_helmholtz_mfma_cols(const HelmholtzMfmaArgs &a, const int32_t *tiles, int32_t n_tiles,
-                                      bool redundant, hipStream_t s) {
+p2p_status launch_helmholtz_mfma_cols(const HelmholtzMfmaArgs &a, const int32_t *tiles, const HelmInline &inl,
+                                      int32_t n_tiles, bool redundant, hipStream_t s) {
     if (n_tiles <= 0) return P2P_OK;
 #define P2P_MFC(R, C)                                                                                   \
     k_helm_mfma_cols<R, C><<<static_cast<unsigned>(n_tiles), 64 * kColWaves, 0, s>>>(                  \
-        a.key_bits, tiles, a.leaf_start, a.leaf_key, a.perm, a.nbr_start, a.nbr_idx, a.red_start, a.src, \
+        a.key_bits, tiles, inl, a.leaf_start, a.leaf_key, a.perm, a.nbr_start, a.nbr_idx, a.red_start, a.src, \
         a.blocks, a.inst_table, a.inst_scale, a.u)
     const bool cj = a.conj != 0;
     if (redundant) { if (cj) P2P_MFC(true, true); else P2P_MFC(true, false); }

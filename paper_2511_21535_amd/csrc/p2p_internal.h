@@ -241,8 +241,23 @@ struct HelmholtzMfmaArgs {
     int32_t conj;
     float2 *u;                 // caller order [n][nrhs]
 };
-p2p_status launch_green_blocks(const double *d_kh, int32_t n_tables, int32_t copies, float2 *blocks,
-                               hipStream_t s);
+// Per-call parameters of a grid with at most kInlineGrids instances, passed by
+// value in the kernel arguments (no upload, no extra launch): n_grids = 0
+// means the device arrays are used instead.
+constexpr int kInlineGrids = 8;
+constexpr int kHelmColBoxes = 16;           // target boxes (columns) per tile of the single-RHS path
+struct HelmInline {
+    int32_t n_grids;
+    int32_t n_tables;
+    int32_t tile_first[kInlineGrids + 1];   // first column tile of each instance
+    int32_t leaf_first[kInlineGrids + 1];   // first box (leaf) of each instance
+    int32_t itab[kInlineGrids];             // G table of each instance
+    float iscale[kInlineGrids];             // 1/h of each instance
+    double kh[kInlineGrids];                // k h of each table
+};
+// G blocks for the k h values of d_kh, or of inl.kh when inl.n_grids > 0.
+p2p_status launch_green_blocks(const double *d_kh, const HelmInline &inl, int32_t n_tables, int32_t copies,
+                               float2 *blocks, hipStream_t s);
 p2p_status launch_work_order(const int64_t *nbr_start, int64_t L, int32_t *work, uint64_t *keys,
                              uint64_t *keys_tmp, int32_t *vals_tmp, uint32_t *hist,
                              hipStream_t s);
@@ -253,8 +268,8 @@ p2p_status launch_helmholtz_mfma(const HelmholtzMfmaArgs &a, bool redundant, int
 // number (tiles may be null to count).  Uses blocks, inst_table, inst_scale,
 // conj and u of the arguments (copies 1, no work queue).
 int32_t helmholtz_cols_tiles(const p2p_grid *grids, int32_t n_grids, int32_t *tiles);
-p2p_status launch_helmholtz_mfma_cols(const HelmholtzMfmaArgs &a, const int32_t *tiles, int32_t n_tiles,
-                                      bool redundant, hipStream_t s);
+p2p_status launch_helmholtz_mfma_cols(const HelmholtzMfmaArgs &a, const int32_t *tiles, const HelmInline &inl,
+                                      int32_t n_tiles, bool redundant, hipStream_t s);
 
 // Locality (locality.hip).
 p2p_status launch_locality_stats(const int32_t *leaf_start, const int64_t *nbr_start,
