@@ -237,20 +237,21 @@ extern "C" p2p_status p2p_build_neighbors(const p2p_tree *tree, p2p_nbrs *nbrs, 
     int64_t *seg_scan = ar.take<int64_t>(L + 1);
     int32_t *slots = ar.take<int32_t>(static_cast<size_t>(L) * kNbrSlotsPerLeaf);
     int8_t *slot_code = ar.take<int8_t>(per ? static_cast<size_t>(L) * kNbrSlotsPerLeaf : 0);
-    int32_t *overflow = ar.take<int32_t>(1);
+    int32_t *counters = ar.take<int32_t>(2);
+    int32_t *heavy = ar.take<int32_t>(L);
     int64_t *totals = ar.take<int64_t>(3);
     p2p_status st;
     if (ws_query(ws, ws_bytes, ar, &st)) return st;
     if (!nbrs->nbr_start) return fail(P2P_EINVAL, "nbrs->nbr_start must not be NULL");
     hipStream_t s = as_stream(stream);
     const int inst_shift = 3 * tree->key_bits;
-    P2P_TRY(launch_key_directory(tree->leaf_key, L, total_bits, dir, overflow, s));
+    P2P_TRY(launch_key_directory(tree->leaf_key, L, total_bits, dir, counters, s));
     P2P_TRY(launch_neighbors_count(tree->leaf_key, tree->leaf_level, L, tree->key_bits, inst_shift, dir,
                                    total_bits, tree->leaf_start, counts, segs, slots,
-                                   per ? slot_code : nullptr, overflow, s));
+                                   per ? slot_code : nullptr, counters, heavy, s));
     P2P_TRY((exclusive_scan<int32_t, int64_t>(counts, start, L, scan_tmp, s)));
     P2P_TRY((exclusive_scan<int32_t, int64_t>(segs, seg_scan, L, scan_tmp, s)));
-    P2P_TRY(launch_nbr_totals(start, seg_scan, overflow, L, totals, s));
+    P2P_TRY(launch_nbr_totals(start, seg_scan, counters, L, totals, s));
     int64_t host[3] = {0, 0, 0};
     P2P_HIP(hipMemcpyAsync(host, totals, sizeof(host), hipMemcpyDeviceToHost, s));
     P2P_HIP(hipStreamSynchronize(s));
@@ -264,7 +265,7 @@ extern "C" p2p_status p2p_build_neighbors(const p2p_tree *tree, p2p_nbrs *nbrs, 
     if (E > 0 && per && !nbrs->nbr_shift) return fail(P2P_EINVAL, "nbrs->nbr_shift must not be NULL for periodic lists");
     P2P_HIP(hipMemcpyAsync(nbrs->nbr_start, start, (L + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
     P2P_TRY(launch_neighbors_fill(tree->leaf_key, tree->leaf_level, L, tree->key_bits, inst_shift, dir,
-                                  total_bits, counts, slots, per ? slot_code : nullptr, host[2] > 0,
+                                  total_bits, counts, slots, per ? slot_code : nullptr, counters, heavy, host[2] > 0,
                                   nbrs->nbr_start, nbrs->nbr_idx, per ? nbrs->nbr_shift : nullptr, s));
     P2P_HIP(hipStreamSynchronize(s));
     nbrs->count = E;

@@ -93,26 +93,30 @@ p2p_status launch_leaf_write(const uint64_t *skeys, const int8_t *level, const i
 // Near lists (nbrs.hip).  Directory over the top bits of the leaf keys (dir:
 // (1 << neighbor_dir_bits) + 1 entries); it also clears the overflow counter.
 int neighbor_dir_bits(int total_key_bits);
+// counters[2]: lists over kNbrSlotsPerLeaf entries, heavy leaves (cleared here).
 p2p_status launch_key_directory(const uint64_t *leaf_key, int64_t L, int total_key_bits, int32_t *dir,
-                                int32_t *overflow, hipStream_t s);
+                                int32_t *counters, hipStream_t s);
 // Near lists in two passes.  The counting pass writes per-leaf counts, segment
 // lengths (points of the leaves in the list) and the first 64 entries of each
 // list into slots[L][64]; after the scan of the counts, the fill moves the
 // slots into the CSR and searches again only for the lists longer than 64.
+// Leaves with many candidates are listed in heavy[L] and searched by a whole
+// workgroup each.
 // A non-null slot_code selects periodic lists (particles on the unit torus):
 // slot_code[L][64] and nbr_shift then receive the image codes.
 constexpr int kNbrSlotsPerLeaf = 64;
 p2p_status launch_neighbors_count(const uint64_t *leaf_key, const int8_t *leaf_level, int64_t L,
                                   int key_bits, int inst_shift, const int32_t *dir, int total_key_bits,
                                   const int32_t *leaf_start, int32_t *counts, int32_t *segs,
-                                  int32_t *slots, int8_t *slot_code, int32_t *overflow, hipStream_t s);
-p2p_status launch_nbr_totals(const int64_t *start, const int64_t *seg_scan, const int32_t *overflow,
+                                  int32_t *slots, int8_t *slot_code, int32_t *counters, int32_t *heavy,
+                                  hipStream_t s);
+p2p_status launch_nbr_totals(const int64_t *start, const int64_t *seg_scan, const int32_t *counters,
                              int64_t L, int64_t *out, hipStream_t s);
 p2p_status launch_neighbors_fill(const uint64_t *leaf_key, const int8_t *leaf_level, int64_t L,
                                  int key_bits, int inst_shift, const int32_t *dir, int total_key_bits,
                                  const int32_t *counts, const int32_t *slots, const int8_t *slot_code,
-                                 bool any_overflow, const int64_t *nbr_start, int32_t *nbr_idx,
-                                 int8_t *nbr_shift, hipStream_t s);
+                                 int32_t *counters, const int32_t *heavy, bool any_overflow,
+                                 const int64_t *nbr_start, int32_t *nbr_idx, int8_t *nbr_shift, hipStream_t s);
 
 // Restructure (restructure.hip).
 // nbr_shift (image codes, may be null) places the unshifted self image.

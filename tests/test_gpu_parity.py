@@ -152,6 +152,32 @@ def test_long_near_lists():
         assert _rel(o[0], ref[0]) <= TOL32 and _rel(np.stack(o[1:]), np.stack(ref[1:])) <= TOL32
 
 
+@pytest.mark.parametrize("periodic", [False, True])
+def test_heavy_leaf_lists(periodic):
+    """Large sparse leaves beside a finely split slab: thousands of candidate
+    leaves for one list, which the search hands to a whole workgroup; lists,
+    image codes, S and the sums against the oracle."""
+    x, y, z, m = W.slab_particles(20000, 16, 5e-4, seed=12)
+    print(f"case slab 20000+16 cap 4 periodic={periodic}", flush=True)
+    ot = oracle.build_tree_particles(x, y, z, depth=20, leaf_cap=4)
+    nb = oracle.neighbors_periodic(ot) if periodic else oracle.neighbors(ot)
+    assert np.diff(nb[0]).max() > 2000
+    g = [_t(v) for v in (x, y, z, m)]
+    gt = api.Tree.build_particles(*g[:3], depth=20, leaf_cap=4)
+    gn = gt.neighbors(periodic=periodic)
+    np.testing.assert_array_equal(_n(gn.nbr_start), nb[0])
+    np.testing.assert_array_equal(_n(gn.nbr_idx), nb[1])
+    if periodic:
+        np.testing.assert_array_equal(_n(gn.nbr_shift), nb[2])
+    _, _, S = oracle.red_offsets(ot, *nb)
+    assert gn.red_entries == S
+    ref = oracle.gravity(x, y, z, m, 1e-3, ot, nb)
+    red = api.restructure_gravity(gt, gn, *g, prec="fp32")
+    for layout in ("gather", "redundant"):
+        o = [_n(v) for v in api.gravity(gt, gn, 1e-3, *g, layout=layout, prec="fp32", red=red)]
+        assert _rel(o[0], ref[0]) <= TOL32 and _rel(np.stack(o[1:]), np.stack(ref[1:])) <= TOL32
+
+
 @pytest.mark.parametrize("gen,n,seed,depth,cap", PARTICLE_CASES[:4] + PARTICLE_CASES[6:])
 @pytest.mark.parametrize("eps", [1e-3, 0.0])
 def test_gravity_parity(gen, n, seed, depth, cap, eps):
