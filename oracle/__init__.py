@@ -82,6 +82,10 @@ def _declare(lib):
     lib.orc_restructure_gravity_rows.argtypes = [I64, P, P, P, P, P, P, P, P, P, P, P]
     lib.orc_restructure_interactions.restype = I64
     lib.orc_restructure_interactions.argtypes = [I64, P, P, P, P, P, P, P, P, P, P, P, P, P, P]
+    lib.orc_neighbors_cross.restype = I64
+    lib.orc_neighbors_cross.argtypes = [I64, P, P, I64, P, P, I32, P, P, P, I64]
+    lib.orc_gravity_remote.restype = None
+    lib.orc_gravity_remote.argtypes = [I64, P, P, P, P, P, P, P, P, P, P, P, F64, P, P, P, P, P, P, P]
     lib.orc_neighbors_periodic.restype = I64
     lib.orc_neighbors_periodic.argtypes = [I64, P, P, P, I64, P, P, P, I64]
     lib.orc_gravity_leaves.restype = I64
@@ -247,6 +251,39 @@ def neighbors_periodic(tree: Tree, targets=None):
     lib.orc_neighbors_periodic(L, _p(tree.anchor), _p(tree.size), _p(targets), T, _p(start),
                                _p(idx), _p(sh), total)
     return start, idx[:total], sh[:total]
+
+
+def neighbors_remote(tree: Tree, src_tree: Tree, periodic: bool = False):
+    """Remote near lists (Sec. 5.2, remote interactions): for every leaf of
+    `tree`, the leaves of `src_tree` (another particle set) whose cubes touch
+    it, through the periodic images when `periodic`, ascending in (code, B).
+    Returns (nbr_start, nbr_idx, nbr_shift)."""
+    if tree.kind != "particles" or src_tree.kind != "particles":
+        raise ValueError("remote lists are defined for particle trees")
+    Lt, Ls = tree.n_leaves, src_tree.n_leaves
+    start = np.zeros(Lt + 1, dtype=np.int64)
+    lib = _load()
+    args = (Lt, _p(tree.anchor), _p(tree.size), Ls, _p(src_tree.anchor), _p(src_tree.size), int(periodic))
+    total = lib.orc_neighbors_cross(*args, _p(start), None, None, 0)
+    idx = np.zeros(max(total, 1), dtype=np.int32)
+    sh = np.zeros(max(total, 1), dtype=np.int8)
+    lib.orc_neighbors_cross(*args, _p(start), _p(idx), _p(sh), total)
+    return start, idx[:total], sh[:total]
+
+
+def gravity_remote(x, y, z, tree: Tree, sx, sy, sz, sm, src_tree: Tree, eps, nbr):
+    """Remote gravity: for every point of the target set (caller order), the
+    sums over the source points of the leaves in its leaf's remote list, each
+    at its image; no pair is skipped.  Returns (phi, ax, ay, az)."""
+    x, y, z = (_c(v, np.float64) for v in (x, y, z))
+    sx, sy, sz, sm = (_c(v, np.float64) for v in (sx, sy, sz, sm))
+    start, idx, sh = nbr
+    outs = [np.zeros(len(x)) for _ in range(4)]
+    _load().orc_gravity_remote(tree.n_leaves, _p(tree.perm), _p(tree.leaf_start), _p(x), _p(y), _p(z),
+                               _p(src_tree.perm), _p(src_tree.leaf_start), _p(sx), _p(sy), _p(sz), _p(sm),
+                               float(eps), _p(_c(start, np.int64)), _p(_c(idx, np.int32)),
+                               _shift_arg(sh), *[_p(o) for o in outs])
+    return tuple(outs)
 
 
 def shift_vectors(codes):

@@ -342,6 +342,55 @@ int64_t orc_neighbors_periodic(int64_t L, const int32_t *anchor, const int32_t *
     return total;
 }
 
+/* Remote near lists (the remote interactions of the stellar-dynamics case,
+ * Sec. 5.2: sources received from another domain): for every leaf A of the
+ * target tree (Lt leaves), every leaf B of a second, source tree (Ls leaves,
+ * another particle set in the same unit cube) whose closed cube touches A's;
+ * with periodic != 0 also through the 26 shifted images (codes as in
+ * orc_neighbors_periodic), else code 13 only.  Entries in ascending (code, B).
+ * Writes nbr_start and, if the total fits in `cap`, nbr_idx and nbr_shift
+ * (which may be NULL).  Returns the entry count. */
+int64_t orc_neighbors_cross(int64_t Lt, const int32_t *t_anchor, const int32_t *t_size, int64_t Ls,
+                            const int32_t *s_anchor, const int32_t *s_size, int32_t periodic,
+                            int64_t *nbr_start, int32_t *nbr_idx, int8_t *nbr_shift, int64_t cap)
+{
+    const int64_t dim = (int64_t)1 << ORC_DEPTH_BITS;
+    int64_t *cnt = (int64_t *)calloc((size_t)(Lt + 1), sizeof(int64_t));
+    for (int pass = 0; pass < 2; ++pass) {
+        if (pass == 1) {
+            nbr_start[0] = 0;
+            for (int64_t A = 0; A < Lt; ++A) nbr_start[A + 1] = nbr_start[A] + cnt[A];
+            if (nbr_start[Lt] > cap || !nbr_idx) break;
+        }
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int64_t A = 0; A < Lt; ++A) {
+            int64_t c = 0, w = pass ? nbr_start[A] : 0;
+            for (int code = periodic ? 0 : 13; code <= (periodic ? 26 : 13); ++code) {
+                int64_t sh[3] = {(code % 3 - 1) * dim, ((code / 3) % 3 - 1) * dim, (code / 9 - 1) * dim};
+                for (int64_t B = 0; B < Ls; ++B) {
+                    int adj = 1;
+                    for (int d = 0; d < 3; ++d) {
+                        int64_t ad = t_anchor[3 * A + d], bd = s_anchor[3 * B + d] + sh[d];
+                        if (!(ad <= bd + s_size[B] && bd <= ad + t_size[A])) adj = 0;
+                    }
+                    if (!adj) continue;
+                    if (pass) {
+                        nbr_idx[w] = (int32_t)B;
+                        if (nbr_shift) nbr_shift[w] = (int8_t)code;
+                        ++w;
+                    } else {
+                        ++c;
+                    }
+                }
+            }
+            if (!pass) cnt[A] = c;
+        }
+    }
+    int64_t total = nbr_start[Lt];
+    free(cnt);
+    return total;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Redundant layout                                                         */
 /* ------------------------------------------------------------------------ */
@@ -578,6 +627,46 @@ int64_t orc_gravity_leaves(const double *x, const double *y, const double *z, co
     int64_t total = off[n_sel];
     free(off);
     return total;
+}
+
+/* Remote gravity: for every target point i (caller order of the target set,
+ * n_t points, tree (t_perm, t_leaf_start) with Lt leaves), the sums of
+ * orc_gravity_leaves over the source points j of the leaves in its leaf's
+ * remote list (source set sx, sy, sz, sm, tree (s_perm, s_leaf_start)), each
+ * at its image x_j + s.  The two sets are distinct, so no pair is skipped.
+ * Writes phi, ax, ay, az [n_t]. */
+void orc_gravity_remote(int64_t Lt, const int32_t *t_perm, const int32_t *t_leaf_start,
+                        const double *tx, const double *ty, const double *tz,
+                        const int32_t *s_perm, const int32_t *s_leaf_start, const double *sx,
+                        const double *sy, const double *sz, const double *sm, double eps,
+                        const int64_t *nbr_start, const int32_t *nbr_idx, const int8_t *nbr_shift,
+                        double *phi, double *ax, double *ay, double *az)
+{
+    const double eps2 = eps * eps;
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t A = 0; A < Lt; ++A) {
+        for (int32_t s = t_leaf_start[A]; s < t_leaf_start[A + 1]; ++s) {
+            int64_t i = t_perm[s];
+            double p = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+            for (int64_t e = nbr_start[A]; e < nbr_start[A + 1]; ++e) {
+                int32_t B = nbr_idx[e];
+                double sh[3];
+                orc_shift_of(nbr_shift, e, sh);
+                for (int32_t t = s_leaf_start[B]; t < s_leaf_start[B + 1]; ++t) {
+                    int64_t j = s_perm[t];
+                    double dx = tx[i] - (sx[j] + sh[0]), dy = ty[i] - (sy[j] + sh[1]), dz = tz[i] - (sz[j] + sh[2]);
+                    double r2 = dx * dx + dy * dy + dz * dz + eps2;
+                    double w = 1.0 / sqrt(r2);
+                    double w3 = w * w * w;
+                    p -= sm[j] * w;
+                    gx -= sm[j] * w3 * dx;
+                    gy -= sm[j] * w3 * dy;
+                    gz -= sm[j] * w3 * dz;
+                }
+            }
+            phi[i] = p; ax[i] = gx; ay[i] = gy; az[i] = gz;
+        }
+    }
 }
 
 /* Reverse-mode derivative of the gravity sums.  With upstream gradients
