@@ -320,6 +320,45 @@ p2p_status p2p_eval_gravity_interactions(const p2p_tree *tree, const p2p_nbrs *n
                                          double *phi, double *ax, double *ay, double *az,
                                          void *ws, size_t *ws_bytes, p2p_stream_t stream);
 
+/* Remote interactions (the remote type of the stellar-dynamics case, Sec. 5.2,
+ * computed in its own launch beside the local and periodic ones: targets of
+ * this domain, sources received from another).  `tree` holds the targets,
+ * `src_tree` the sources, another particle set in the same unit cube with its
+ * own tree; both are particle trees and distinct structures.  The lists of
+ * p2p_build_neighbors_remote are CSR over the leaves of `tree` (nbr_start has
+ * L+1 entries) with entries that index the leaves of `src_tree`: every source
+ * leaf whose closed cube touches the target leaf, ascending, through the
+ * periodic images when nbrs->periodic (codes and order as for periodic plain
+ * lists).  A list may be empty.  red_entries counts the source points in the
+ * lists.  Synchronises `stream`; P2P_ECAPACITY as p2p_build_neighbors. */
+p2p_status p2p_build_neighbors_remote(const p2p_tree *tree, const p2p_tree *src_tree, p2p_nbrs *nbrs,
+                                      void *ws, size_t *ws_bytes, p2p_stream_t stream);
+
+/* Redundant layout of the remote sources: as p2p_restructure_redundant for
+ * gravity, the segment of target leaf A holding the rows of the source points
+ * of the leaves in its remote list (src = the source set's caller-order x, y,
+ * z, m; FP32_MIXED rows relative to the centre of A).  red_self is -1 (the
+ * targets are not among the sources).  Synchronises `stream` only when
+ * nbrs->red_entries < 0. */
+p2p_status p2p_restructure_remote(const p2p_tree *tree, const p2p_tree *src_tree, const p2p_nbrs *nbrs,
+                                  const double *const src[4], p2p_precision prec, p2p_redundant *out,
+                                  void *ws, size_t *ws_bytes, p2p_stream_t stream);
+
+/* Remote gravity: for every target point i, the sums of the header comment
+ * over the source points j of its leaf's remote list (each at its image), no
+ * pair skipped (the two sets are distinct; eps == 0 drops pairs at zero
+ * distance), ADDED to phi, ax, ay, az (caller order of the targets), so that a
+ * remote call after the local one completes the near field.  x, y, z: the
+ * targets' caller-order positions (always read); sx, sy, sz, sm: the
+ * sources' (GATHER; REDUNDANT reads `red`, built by p2p_restructure_remote
+ * with the same precision). */
+p2p_status p2p_eval_gravity_remote(const p2p_tree *tree, const p2p_tree *src_tree, const p2p_nbrs *nbrs,
+                                   const p2p_redundant *red, p2p_layout layout, p2p_precision prec,
+                                   double eps, const double *x, const double *y, const double *z,
+                                   const double *sx, const double *sy, const double *sz, const double *sm,
+                                   double *phi, double *ax, double *ay, double *az,
+                                   void *ws, size_t *ws_bytes, p2p_stream_t stream);
+
 /* Locality metric per configuration (a12; Definition 1 and Formulas (10)-(11),
  * Sec. 3.4).  D per target leaf is counted on the GPU from the near lists;
  * the rest is host arithmetic.  red may be NULL (S is then computed from the

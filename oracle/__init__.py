@@ -271,6 +271,30 @@ def neighbors_remote(tree: Tree, src_tree: Tree, periodic: bool = False):
     return start, idx[:total], sh[:total]
 
 
+def restructure_remote(tree: Tree, src_tree: Tree, nbr, sx, sy, sz, sm, prec="fp64"):
+    """Redundant layout of remote sources: (red_start, rows) with the segment
+    of target leaf A holding, for the entries of its remote list in order, the
+    source points of leaf B of `src_tree` at their image: float64 [S, 4]
+    (x + s, y + s, z + s, m), or for "fp32" float32 relative to the centre of
+    A as in restructure_gravity_rel."""
+    start, idx, sh = nbr
+    occ = np.diff(src_tree.leaf_start).astype(np.int64)
+    seg = np.array([occ[idx[start[a]:start[a + 1]]].sum() for a in range(tree.n_leaves)], dtype=np.int64)
+    rs = np.concatenate([[0], np.cumsum(seg)]).astype(np.int64)
+    S = int(rs[-1])
+    arrs = [_c(v, np.float64) for v in (sx, sy, sz, sm)]
+    args = (tree.n_leaves, _p(src_tree.leaf_start), _p(src_tree.perm), _p(_c(start, np.int64)),
+            _p(_c(idx, np.int32)), _shift_arg(sh), _p(rs))
+    if prec == "fp64":
+        out = np.zeros((max(S, 1), 4), dtype=np.float64)
+        _load().orc_restructure_gravity_rows(*args, *[_p(a) for a in arrs], _p(out))
+    else:
+        out = np.zeros((max(S, 1), 4), dtype=np.float32)
+        _load().orc_restructure_gravity_rel(*args, _p(tree.anchor), _p(tree.size), *[_p(a) for a in arrs],
+                                            _p(out))
+    return rs, out[:S]
+
+
 def gravity_remote(x, y, z, tree: Tree, sx, sy, sz, sm, src_tree: Tree, eps, nbr):
     """Remote gravity: for every point of the target set (caller order), the
     sums over the source points of the leaves in its leaf's remote list, each

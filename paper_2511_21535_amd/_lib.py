@@ -24,6 +24,7 @@ STATUS_NAMES = {0: "P2P_OK", 1: "P2P_EINVAL", 2: "P2P_EDOMAIN", 3: "P2P_ECAPACIT
 EXPORTED = ["p2p_build_tree", "p2p_build_neighbors", "p2p_restructure_redundant",
             "p2p_eval_gravity", "p2p_eval_helmholtz", "p2p_adjoint", "p2p_locality",
             "p2p_restructure_interactions", "p2p_eval_gravity_interactions",
+            "p2p_build_neighbors_remote", "p2p_restructure_remote", "p2p_eval_gravity_remote",
             "p2p_last_error", "p2p_version"]
 
 
@@ -116,6 +117,13 @@ def load():
     lib.p2p_eval_gravity_interactions.argtypes = [ctypes.POINTER(p2p_tree), ctypes.POINTER(p2p_nbrs),
                                                   ctypes.POINTER(p2p_interactions), F64,
                                                   V, V, V, V, V, SZ, V]
+    T, N, R = ctypes.POINTER(p2p_tree), ctypes.POINTER(p2p_nbrs), ctypes.POINTER(p2p_redundant)
+    lib.p2p_build_neighbors_remote.restype = st
+    lib.p2p_build_neighbors_remote.argtypes = [T, T, N, V, SZ, V]
+    lib.p2p_restructure_remote.restype = st
+    lib.p2p_restructure_remote.argtypes = [T, T, N, ctypes.POINTER(PV4), I32, R, V, SZ, V]
+    lib.p2p_eval_gravity_remote.restype = st
+    lib.p2p_eval_gravity_remote.argtypes = [T, T, N, R, I32, I32, F64] + [V] * 11 + [V, SZ, V]
     lib.p2p_locality.restype = st
     lib.p2p_locality.argtypes = [ctypes.POINTER(p2p_tree), ctypes.POINTER(p2p_nbrs),
                                  ctypes.POINTER(p2p_redundant), F64, F64,
@@ -175,6 +183,18 @@ def p2p_restructure_interactions(*args):
 
 def p2p_eval_gravity_interactions(*args):
     return load().p2p_eval_gravity_interactions(*args)
+
+
+def p2p_build_neighbors_remote(*args):
+    return load().p2p_build_neighbors_remote(*args)
+
+
+def p2p_restructure_remote(*args):
+    return load().p2p_restructure_remote(*args)
+
+
+def p2p_eval_gravity_remote(*args):
+    return load().p2p_eval_gravity_remote(*args)
 
 
 def p2p_locality(*args):

@@ -173,14 +173,17 @@ class Nbrs:
         return s
 
 
-def build_neighbors(tree: Tree, cap: Optional[int] = None, periodic: bool = False) -> Nbrs:
+def build_neighbors(tree: Tree, cap: Optional[int] = None, periodic: bool = False,
+                    src_tree: Optional[Tree] = None) -> Nbrs:
     """Near lists of every leaf; periodic=True: on the unit torus (particle
-    trees), with an image code per entry in nbr_shift."""
+    trees), with an image code per entry in nbr_shift.  With src_tree: the
+    remote lists of the leaves of `tree` over the leaves of `src_tree`."""
     dev = tree.leaf_start.device
     Lv = tree.n_leaves
     if cap is None:
         cap = (48 if periodic else 32) * max(Lv, 1)
     ts = tree.struct()
+    ss = src_tree.struct() if src_tree is not None else None
     for _ in range(2):
         start = torch.empty(Lv + 1, dtype=torch.int64, device=dev)
         idx = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
@@ -191,6 +194,9 @@ def build_neighbors(tree: Tree, cap: Optional[int] = None, periodic: bool = Fals
             s.periodic, s.nbr_shift = 1, sh.data_ptr()
 
         def call(ws, nb):
+            if ss is not None:
+                return L.p2p_build_neighbors_remote(ctypes.byref(ts), ctypes.byref(ss), ctypes.byref(s), ws, nb,
+                                                    _stream())
             return L.p2p_build_neighbors(ctypes.byref(ts), ctypes.byref(s), ws, nb, _stream())
         st, _ = _call(call, dev)
         if st == L.P2P_ECAPACITY:
@@ -270,6 +276,53 @@ def restructure(tree: Tree, nbrs: Nbrs, src: Sequence[Optional[torch.Tensor]], p
 
 def restructure_gravity(tree, nbrs, x, y, z, m, prec="fp64", **kw) -> Redundant:
     return restructure(tree, nbrs, [x, y, z, m], prec=prec, **kw)
+
+
+def restructure_remote(tree: Tree, src_tree: Tree, nbrs: Nbrs, sx, sy, sz, sm, prec="fp64",
+                       out: Optional[Redundant] = None) -> Redundant:
+    """Redundant layout of the remote sources (points of `src_tree`) for the
+    leaves of `tree`, over remote lists from build_neighbors(src_tree=...)."""
+    p = PREC[prec]
+    dev = tree.leaf_start.device
+    if out is None:
+        S = nbrs.red_entries
+        if S < 0:
+            raise ValueError("remote lists without their size")
+        out = Redundant(count=0, red_start=torch.empty(tree.n_leaves + 1, dtype=torch.int64, device=dev),
+                        red_self=torch.empty(max(tree.n_leaves, 1), dtype=torch.int32, device=dev),
+                        planes=_alloc_red(tree, L.P2P_KIND_GRAVITY, p, S, 1, dev), nrhs=1,
+                        kind=L.P2P_KIND_GRAVITY, prec=p)
+    srcs = L.PV4(*[_ptr(t) for t in (sx, sy, sz, sm)])
+    ts, ss, ns, rs = tree.struct(), src_tree.struct(), nbrs.struct(), out.struct()
+
+    def call(ws, nb):
+        return L.p2p_restructure_remote(ctypes.byref(ts), ctypes.byref(ss), ctypes.byref(ns),
+                                        ctypes.byref(srcs), p, ctypes.byref(rs), ws, nb, _stream())
+    st, _ = _call(call, dev)
+    L.check(st)
+    out.count, out.nrhs, out.kind, out.prec = int(rs.count), int(rs.nrhs), int(rs.kind), int(rs.prec)
+    return out
+
+
+def gravity_remote(tree: Tree, src_tree: Tree, nbrs: Nbrs, eps: float, x, y, z, sx=None, sy=None,
+                   sz=None, sm=None, layout="gather", prec="fp64", red: Optional[Redundant] = None, out=None):
+    """Remote near-field potential and acceleration of the points of `tree`
+    (caller order), added to `out` (zeros when not given).  Returns (phi, ax, ay, az)."""
+    dev = tree.leaf_start.device
+    if out is None:
+        out = [torch.zeros(tree.n, dtype=torch.float64, device=dev) for _ in range(4)]
+    ts, ss, ns = tree.struct(), src_tree.struct(), nbrs.struct()
+    rs = red.struct() if red is not None else None
+
+    def call(ws, nb):
+        return L.p2p_eval_gravity_remote(ctypes.byref(ts), ctypes.byref(ss), ctypes.byref(ns),
+                                         ctypes.byref(rs) if rs is not None else None,
+                                         LAYOUT[layout], PREC[prec], float(eps), _ptr(x), _ptr(y), _ptr(z),
+                                         _ptr(sx), _ptr(sy), _ptr(sz), _ptr(sm), *[_ptr(o) for o in out],
+                                         ws, nb, _stream())
+    st, _ = _call(call, dev)
+    L.check(st)
+    return tuple(out)
 
 
 @dataclass

@@ -92,12 +92,26 @@ p2p_status check_periodic(const p2p_tree *t, const p2p_nbrs *nb) {
     return P2P_OK;
 }
 
-p2p_status check_nbrs(const p2p_tree *t, const p2p_nbrs *nb) {
+// remote: lists over another tree's leaves, which may be empty (a plain list
+// always holds the leaf itself)
+p2p_status check_nbrs(const p2p_tree *t, const p2p_nbrs *nb, bool remote = false) {
     if (!nb) return fail(P2P_EINVAL, "nbrs is NULL");
     P2P_TRY(check_periodic(t, nb));
-    if (t->n_leaves > 0 && (!nb->nbr_start || !nb->nbr_idx)) return fail(P2P_EINVAL, "nbrs: NULL array (not built?)");
-    if (t->n_leaves > 0 && nb->periodic && !nb->nbr_shift) return fail(P2P_EINVAL, "nbrs: periodic lists without nbr_shift");
-    if (nb->count < t->n_leaves) return fail(P2P_EINVAL, "nbrs: count < n_leaves (not built?)");
+    if (t->n_leaves > 0 && (!nb->nbr_start || (!remote && !nb->nbr_idx)))
+        return fail(P2P_EINVAL, "nbrs: NULL array (not built?)");
+    if (nb->count > 0 && (!nb->nbr_idx || (nb->periodic && !nb->nbr_shift)))
+        return fail(P2P_EINVAL, "nbrs: NULL nbr_idx or nbr_shift (not built?)");
+    if (nb->count < (remote ? 0 : t->n_leaves)) return fail(P2P_EINVAL, "nbrs: count < n_leaves (not built?)");
+    return P2P_OK;
+}
+
+p2p_status check_remote_trees(const p2p_tree *tree, const p2p_tree *src_tree) {
+    P2P_TRY(check_tree(tree));
+    if (!src_tree) return fail(P2P_EINVAL, "src_tree is NULL");
+    P2P_TRY(check_tree(src_tree));
+    if (src_tree == tree) return fail(P2P_EINVAL, "src_tree must be another tree");
+    if (tree->kind != P2P_TREE_PARTICLES || src_tree->kind != P2P_TREE_PARTICLES)
+        return fail(P2P_EINVAL, "remote interactions need two particle trees");
     return P2P_OK;
 }
 
@@ -216,18 +230,28 @@ extern "C" p2p_status p2p_build_tree(const double *x, const double *y, const dou
 }
 
 // ------------------------------------------------------------------ a2 ----
-extern "C" p2p_status p2p_build_neighbors(const p2p_tree *tree, p2p_nbrs *nbrs, void *ws,
-                                          size_t *ws_bytes, p2p_stream_t stream) {
-    set_error("");
+namespace p2p {
+namespace {
+
+// Near lists of the leaves of `tree` over the leaves of `src` (the same tree for
+// plain lists, another particle tree for remote lists).
+p2p_status neighbors_common(const p2p_tree *tree, const p2p_tree *src, p2p_nbrs *nbrs, void *ws,
+                            size_t *ws_bytes, hipStream_t s) {
     if (!ws_bytes) return fail(P2P_EINVAL, "ws_bytes must not be NULL");
     P2P_TRY(check_tree(tree));
+    const bool remote = src != tree;
+    if (remote) {
+        P2P_TRY(check_tree(src));
+        if (tree->kind != P2P_TREE_PARTICLES || src->kind != P2P_TREE_PARTICLES)
+            return fail(P2P_EINVAL, "remote lists need two particle trees");
+    }
     if (!nbrs) return fail(P2P_EINVAL, "nbrs is NULL");
     if (nbrs->cap < 0) return fail(P2P_EINVAL, "nbrs->cap < 0");
     P2P_TRY(check_periodic(tree, nbrs));
     const bool per = nbrs->periodic != 0;
-    const int64_t L = tree->n_leaves;
+    const int64_t L = tree->n_leaves, Ls = src->n_leaves;
     // total key bits: 3 per axis, plus the instance index for grids
-    const int total_bits = 3 * tree->key_bits + (tree->kind == P2P_TREE_GRIDS ? bits_for(tree->n_grids) : 0);
+    const int total_bits = 3 * src->key_bits + (src->kind == P2P_TREE_GRIDS ? bits_for(src->n_grids) : 0);
     Arena ar(ws);
     int32_t *counts = ar.take<int32_t>(L);
     int64_t *start = ar.take<int64_t>(L + 1);
@@ -243,12 +267,13 @@ extern "C" p2p_status p2p_build_neighbors(const p2p_tree *tree, p2p_nbrs *nbrs, 
     p2p_status st;
     if (ws_query(ws, ws_bytes, ar, &st)) return st;
     if (!nbrs->nbr_start) return fail(P2P_EINVAL, "nbrs->nbr_start must not be NULL");
-    hipStream_t s = as_stream(stream);
-    const int inst_shift = 3 * tree->key_bits;
-    P2P_TRY(launch_key_directory(tree->leaf_key, L, total_bits, dir, counters, s));
-    P2P_TRY(launch_neighbors_count(tree->leaf_key, tree->leaf_level, L, tree->key_bits, inst_shift, dir,
-                                   total_bits, tree->leaf_start, counts, segs, slots,
-                                   per ? slot_code : nullptr, counters, heavy, s));
+    const int inst_shift = 3 * src->key_bits;
+    const NbrTargets tg{tree->leaf_key, tree->leaf_level, L};
+    const NbrTargets *tgp = remote ? &tg : nullptr;
+    P2P_TRY(launch_key_directory(src->leaf_key, Ls, total_bits, dir, counters, s));
+    P2P_TRY(launch_neighbors_count(src->leaf_key, src->leaf_level, Ls, src->key_bits, inst_shift, dir,
+                                   total_bits, src->leaf_start, counts, segs, slots,
+                                   per ? slot_code : nullptr, counters, heavy, s, tgp));
     P2P_TRY((exclusive_scan<int32_t, int64_t>(counts, start, L, scan_tmp, s)));
     P2P_TRY((exclusive_scan<int32_t, int64_t>(segs, seg_scan, L, scan_tmp, s)));
     P2P_TRY(launch_nbr_totals(start, seg_scan, counters, L, totals, s));
@@ -264,30 +289,56 @@ extern "C" p2p_status p2p_build_neighbors(const p2p_tree *tree, p2p_nbrs *nbrs, 
     if (E > 0 && !nbrs->nbr_idx) return fail(P2P_EINVAL, "nbrs->nbr_idx must not be NULL");
     if (E > 0 && per && !nbrs->nbr_shift) return fail(P2P_EINVAL, "nbrs->nbr_shift must not be NULL for periodic lists");
     P2P_HIP(hipMemcpyAsync(nbrs->nbr_start, start, (L + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
-    P2P_TRY(launch_neighbors_fill(tree->leaf_key, tree->leaf_level, L, tree->key_bits, inst_shift, dir,
+    P2P_TRY(launch_neighbors_fill(src->leaf_key, src->leaf_level, Ls, src->key_bits, inst_shift, dir,
                                   total_bits, counts, slots, per ? slot_code : nullptr, counters, heavy, host[2] > 0,
-                                  nbrs->nbr_start, nbrs->nbr_idx, per ? nbrs->nbr_shift : nullptr, s));
+                                  nbrs->nbr_start, nbrs->nbr_idx, per ? nbrs->nbr_shift : nullptr, s, tgp));
     P2P_HIP(hipStreamSynchronize(s));
     nbrs->count = E;
     return P2P_OK;
 }
 
-// ------------------------------------------------------------------ a3 ----
-extern "C" p2p_status p2p_restructure_redundant(const p2p_tree *tree, const p2p_nbrs *nbrs,
-                                                const void *const src[4], int32_t nrhs,
-                                                p2p_precision prec, p2p_redundant *out, void *ws,
-                                                size_t *ws_bytes, p2p_stream_t stream) {
+}  // namespace
+}  // namespace p2p
+
+extern "C" p2p_status p2p_build_neighbors(const p2p_tree *tree, p2p_nbrs *nbrs, void *ws,
+                                          size_t *ws_bytes, p2p_stream_t stream) {
     set_error("");
+    return neighbors_common(tree, tree, nbrs, ws, ws_bytes, as_stream(stream));
+}
+
+extern "C" p2p_status p2p_build_neighbors_remote(const p2p_tree *tree, const p2p_tree *src_tree,
+                                                 p2p_nbrs *nbrs, void *ws, size_t *ws_bytes,
+                                                 p2p_stream_t stream) {
+    set_error("");
+    if (!src_tree) return fail(P2P_EINVAL, "src_tree is NULL");
+    if (src_tree == tree) return fail(P2P_EINVAL, "src_tree must be another tree (plain lists: p2p_build_neighbors)");
+    return neighbors_common(tree, src_tree, nbrs, ws, ws_bytes, as_stream(stream));
+}
+
+// ------------------------------------------------------------------ a3 ----
+namespace p2p {
+namespace {
+
+// Segments of the targets of `tree` filled from the points of `srct` (the same
+// tree, or the source tree of remote lists).
+p2p_status restructure_common(const p2p_tree *tree, const p2p_tree *srct, const p2p_nbrs *nbrs,
+                              const void *const src[4], int32_t nrhs, p2p_precision prec, p2p_redundant *out,
+                              void *ws, size_t *ws_bytes, hipStream_t s) {
+    const bool remote = srct != tree;
     if (!ws_bytes) return fail(P2P_EINVAL, "ws_bytes must not be NULL");
-    P2P_TRY(check_tree(tree));
-    P2P_TRY(check_nbrs(tree, nbrs));
+    if (remote)
+        P2P_TRY(check_remote_trees(tree, srct));
+    else
+        P2P_TRY(check_tree(tree));
+    P2P_TRY(check_nbrs(tree, nbrs, remote));
     if (!out) return fail(P2P_EINVAL, "out is NULL");
     if (prec != P2P_FP64 && prec != P2P_FP32_MIXED) return fail(P2P_EINVAL, "bad precision");
     const bool grav = tree->kind == P2P_TREE_PARTICLES;
     if (!grav && nrhs < 1) return fail(P2P_EINVAL, "nrhs must be >= 1");
     if (grav) nrhs = 1;
     const bool mixed = prec == P2P_FP32_MIXED;
-    const int64_t n = tree->n, L = tree->n_leaves;
+    // n: the source rows; L: the target leaves
+    const int64_t n = srct->n, L = tree->n_leaves;
     const size_t csize = mixed ? sizeof(float2) : sizeof(double2);
     Arena ar(ws);
     int32_t *seg_len = ar.take<int32_t>(L);
@@ -307,12 +358,11 @@ extern "C" p2p_status p2p_restructure_redundant(const p2p_tree *tree, const p2p_
         return fail(P2P_EINVAL, "src arrays must not be NULL");
     if (!out->red_start || (L > 0 && !out->red_self)) return fail(P2P_EINVAL, "out->red_start/red_self must not be NULL");
     if (out->cap < 0) return fail(P2P_EINVAL, "out->cap < 0");
-    hipStream_t s = as_stream(stream);
     // S: carried by the near lists, else counted here and read back
     int64_t S = nbrs->red_entries;
     if (S < 0) {
-        P2P_TRY(launch_seg_lengths(tree->leaf_start, nbrs->nbr_start, nbrs->nbr_idx, shifts(nbrs), L, seg_len,
-                                   count_self, s));
+        P2P_TRY(launch_seg_lengths(srct->leaf_start, nbrs->nbr_start, nbrs->nbr_idx, shifts(nbrs), L, seg_len,
+                                   count_self, !remote, s));
         P2P_TRY((exclusive_scan<int32_t, int64_t>(seg_len, count_start, L, scan_tmp, s)));
         S = 0;
         if (L > 0) P2P_HIP(hipMemcpyAsync(&S, &count_start[L], sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -329,20 +379,20 @@ extern "C" p2p_status p2p_restructure_redundant(const p2p_tree *tree, const p2p_
     if (grav)
         P2P_TRY(launch_scatter4(static_cast<const double *>(src[0]), static_cast<const double *>(src[1]),
                                 static_cast<const double *>(src[2]), static_cast<const double *>(src[3]),
-                                tree->iperm, n, s4, s));
+                                srct->iperm, n, s4, s));
     else if (mixed)
         P2P_TRY(launch_permute_rows<float2>(static_cast<const float2 *>(src[0]), tree->perm, n, nrhs,
                                             static_cast<float2 *>(sq), s));
     else
         P2P_TRY(launch_permute_rows<double2>(static_cast<const double2 *>(src[0]), tree->perm, n, nrhs,
                                              static_cast<double2 *>(sq), s));
-    P2P_TRY(launch_seg_lengths(tree->leaf_start, nbrs->nbr_start, nbrs->nbr_idx, shifts(nbrs), L, seg_len,
-                               out->red_self, s));
+    P2P_TRY(launch_seg_lengths(srct->leaf_start, nbrs->nbr_start, nbrs->nbr_idx, shifts(nbrs), L, seg_len,
+                               out->red_self, !remote, s));
     P2P_TRY((exclusive_scan<int32_t, int64_t>(seg_len, out->red_start, L, scan_tmp, s)));
     const int64_t entry_bytes = grav ? (mixed ? 16 : 32) : static_cast<int64_t>(nrhs) * static_cast<int64_t>(csize);
     const bool streaming = S * entry_bytes > kStreamingLayoutBytes;
     if (grav)
-        P2P_TRY(launch_copy_segments_gravity(s4, tree->leaf_key, tree->leaf_level, tree->leaf_start,
+        P2P_TRY(launch_copy_segments_gravity(s4, tree->leaf_key, tree->leaf_level, srct->leaf_start,
                                              nbrs->nbr_start, nbrs->nbr_idx, shifts(nbrs), out->red_start, L,
                                              mixed ? nullptr : static_cast<Row4d *>(out->planes[0]),
                                              mixed ? static_cast<float4 *>(out->planes[0]) : nullptr,
@@ -360,6 +410,29 @@ extern "C" p2p_status p2p_restructure_redundant(const p2p_tree *tree, const p2p_
     out->kind = grav ? P2P_KIND_GRAVITY : P2P_KIND_HELMHOLTZ;
     out->prec = prec;
     return P2P_OK;
+}
+
+}  // namespace
+}  // namespace p2p
+
+extern "C" p2p_status p2p_restructure_redundant(const p2p_tree *tree, const p2p_nbrs *nbrs,
+                                                const void *const src[4], int32_t nrhs,
+                                                p2p_precision prec, p2p_redundant *out, void *ws,
+                                                size_t *ws_bytes, p2p_stream_t stream) {
+    set_error("");
+    return restructure_common(tree, tree, nbrs, src, nrhs, prec, out, ws, ws_bytes, as_stream(stream));
+}
+
+extern "C" p2p_status p2p_restructure_remote(const p2p_tree *tree, const p2p_tree *src_tree,
+                                             const p2p_nbrs *nbrs, const double *const src[4],
+                                             p2p_precision prec, p2p_redundant *out, void *ws,
+                                             size_t *ws_bytes, p2p_stream_t stream) {
+    set_error("");
+    if (!src_tree) return fail(P2P_EINVAL, "src_tree is NULL");
+    const void *const s4[4] = {src ? src[0] : nullptr, src ? src[1] : nullptr, src ? src[2] : nullptr,
+                               src ? src[3] : nullptr};
+    return restructure_common(tree, src_tree, nbrs, src ? s4 : nullptr, 1, prec, out, ws, ws_bytes,
+                              as_stream(stream));
 }
 
 // ------------------------------------------------- per-interaction layout ---
@@ -498,6 +571,7 @@ extern "C" p2p_status p2p_eval_gravity(const p2p_tree *tree, const p2p_nbrs *nbr
     GravityArgs a{};
     a.L = tree->n_leaves;
     a.leaf_start = tree->leaf_start;
+    a.src_leaf_start = tree->leaf_start;
     a.perm = tree->perm;
     a.leaf_key = tree->leaf_key;
     a.leaf_level = tree->leaf_level;
@@ -521,6 +595,70 @@ extern "C" p2p_status p2p_eval_gravity(const p2p_tree *tree, const p2p_nbrs *nbr
         a.s4 = s4;
     }
     return launch_gravity(a, redundant, mixed, eps == 0.0, s);
+}
+
+extern "C" p2p_status p2p_eval_gravity_remote(const p2p_tree *tree, const p2p_tree *src_tree,
+                                              const p2p_nbrs *nbrs, const p2p_redundant *red,
+                                              p2p_layout layout, p2p_precision prec, double eps,
+                                              const double *x, const double *y, const double *z,
+                                              const double *sx, const double *sy, const double *sz,
+                                              const double *sm, double *phi, double *ax, double *ay,
+                                              double *az, void *ws, size_t *ws_bytes, p2p_stream_t stream) {
+    set_error("");
+    if (!ws_bytes) return fail(P2P_EINVAL, "ws_bytes must not be NULL");
+    P2P_TRY(check_remote_trees(tree, src_tree));
+    P2P_TRY(check_nbrs(tree, nbrs, true));
+    if (layout != P2P_GATHER && layout != P2P_REDUNDANT) return fail(P2P_EINVAL, "bad layout");
+    if (prec != P2P_FP64 && prec != P2P_FP32_MIXED) return fail(P2P_EINVAL, "bad precision");
+    if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(P2P_EINVAL, "eps must be finite and >= 0");
+    const bool mixed = prec == P2P_FP32_MIXED, redundant = layout == P2P_REDUNDANT;
+    const int64_t n = tree->n, ns = src_tree->n;
+    Arena ar(ws);
+    Row4d *t4 = ar.take<Row4d>(n);
+    Row4d *s4 = redundant ? nullptr : ar.take<Row4d>(ns);
+    p2p_status st;
+    if (ws_query(ws, ws_bytes, ar, &st)) return st;
+    if (n > 0 && (!phi || !ax || !ay || !az)) return fail(P2P_EINVAL, "outputs must not be NULL");
+    if (n > 0 && (!x || !y || !z)) return fail(P2P_EINVAL, "x, y, z (targets) must not be NULL");
+    if (redundant) {
+        if (!red) return fail(P2P_EINVAL, "REDUNDANT layout needs red");
+        if (red->kind != P2P_KIND_GRAVITY) return fail(P2P_EINVAL, "red was not built for gravity");
+        if (red->prec != prec) return fail(P2P_EINVAL, "red was built with another precision");
+        if (!red->red_start || (red->count > 0 && !red->planes[0]))
+            return fail(P2P_EINVAL, "red arrays must not be NULL");
+    } else if (ns > 0 && (!sx || !sy || !sz || !sm)) {
+        return fail(P2P_EINVAL, "GATHER layout needs sx, sy, sz, sm");
+    }
+    hipStream_t s = as_stream(stream);
+    GravityArgs a{};
+    a.L = tree->n_leaves;
+    a.leaf_start = tree->leaf_start;
+    a.src_leaf_start = src_tree->leaf_start;
+    a.perm = tree->perm;
+    a.leaf_key = tree->leaf_key;
+    a.leaf_level = tree->leaf_level;
+    a.nbr_start = nbrs->nbr_start;
+    a.nbr_idx = nbrs->nbr_idx;
+    a.nbr_shift = shifts(nbrs);
+    a.eps2 = eps * eps;
+    a.phi = phi;
+    a.ax = ax;
+    a.ay = ay;
+    a.az = az;
+    // the targets' rows (the fourth plane is not read)
+    P2P_TRY(launch_scatter4(x, y, z, x, tree->iperm, n, t4, s));
+    a.t4 = t4;
+    if (redundant) {
+        a.red_start = red->red_start;
+        if (mixed)
+            a.red4 = static_cast<const float4 *>(red->planes[0]);
+        else
+            a.s4 = static_cast<const Row4d *>(red->planes[0]);
+    } else {
+        P2P_TRY(launch_scatter4(sx, sy, sz, sm, src_tree->iperm, ns, s4, s));
+        a.s4 = s4;
+    }
+    return launch_gravity_remote(a, redundant, mixed, eps == 0.0, s);
 }
 
 // ---------------------------------------------------------------- a7/a9 ---

@@ -19,6 +19,11 @@
 // computed in the same arithmetic); the self term of a is exactly zero.
 // With eps == 0 pairs at zero distance contribute nothing instead.
 //
+// Remote lists (sources of another particle set, REMOTE): the targets are read
+// from their own sorted rows, the sources through the source tree's leaf
+// starts (gather) or from the remote segments (redundant); no self pair is
+// added back, and the sums are added to the outputs.
+//
 // Periodic lists (gather and adjoint): a staged source row of an entry with
 // image code c is shifted by (sx, sy, sz) domain edges, x + s in double, before
 // the conversion; the redundant layout already holds shifted rows.
@@ -153,7 +158,7 @@ __device__ inline void leaf_centre(uint64_t key, int level, double c[3]) {
     c[2] = (static_cast<double>(p2pd::compact3(key >> 2)) + half) * 0x1p-20;
 }
 
-template <bool MIXED, bool RED, bool EPS0, bool PER>
+template <bool MIXED, bool RED, bool EPS0, bool PER, bool REMOTE>
 __device__ __forceinline__ void gravity_body(const GravityArgs &a) {
     using Src = typename std::conditional<MIXED, float4, Row4d>::type;
     // a tile of kGTile sources padded to G equal runs (see below): at most
@@ -183,7 +188,14 @@ __device__ __forceinline__ void gravity_body(const GravityArgs &a) {
         const bool active = g < G;
         // target position (relative to the leaf centre for FP32_MIXED) and mass
         Src tv;
-        if constexpr (MIXED) {
+        if constexpr (REMOTE) {
+            const Row4d v = a.t4[t0 + tc0 + t];
+            if constexpr (MIXED)
+                tv = make_float4(static_cast<float>(v.x - c[0]), static_cast<float>(v.y - c[1]),
+                                 static_cast<float>(v.z - c[2]), static_cast<float>(v.w));
+            else
+                tv = v;
+        } else if constexpr (MIXED) {
             if constexpr (RED) {
                 tv = a.red4[a.red_start[A] + a.red_self[A] + tc0 + t];
             } else {
@@ -287,7 +299,7 @@ __device__ __forceinline__ void gravity_body(const GravityArgs &a) {
                 for (; j < chunk; ++j, ++sp) pair(sp[0]);
             }
         };
-        for_each_source_tile<RED, PER>(A, a.red_start, a.nbr_start, a.nbr_idx, a.nbr_shift, a.leaf_start,
+        for_each_source_tile<RED, PER>(A, a.red_start, a.nbr_start, a.nbr_idx, a.nbr_shift, a.src_leaf_start,
                                        s_pre, s_first, s_code, s_w, begin, stage, body);
 
         __syncthreads();
@@ -306,17 +318,24 @@ __device__ __forceinline__ void gravity_body(const GravityArgs &a) {
                 sz_ += s_red[3][l];
             }
             // add back the self pair (d = 0), computed in the same arithmetic
-            if constexpr (!EPS0) {
+            if constexpr (!EPS0 && !REMOTE) {
                 if constexpr (MIXED)
                     sp_ += static_cast<double>(tv.w * rsq_f32(eps2f));
                 else
                     sp_ += tv.w * rsqrt(eps2);
             }
             const int64_t i = a.perm[t0 + tc0 + threadIdx.x];
-            a.phi[i] = sp_;
-            a.ax[i] = sx_;
-            a.ay[i] = sy_;
-            a.az[i] = sz_;
+            if constexpr (REMOTE) {
+                a.phi[i] += sp_;
+                a.ax[i] += sx_;
+                a.ay[i] += sy_;
+                a.az[i] += sz_;
+            } else {
+                a.phi[i] = sp_;
+                a.ax[i] = sx_;
+                a.ay[i] = sy_;
+                a.az[i] = sz_;
+            }
         }
     }
 }
@@ -325,19 +344,19 @@ __device__ __forceinline__ void gravity_body(const GravityArgs &a) {
 // for 8 waves per SIMD (more workgroups in flight hide the tile staging); the
 // FP32-mixed gather kernel fits 72 without spills (7 waves per SIMD); the FP64
 // variants keep the compiler's register budget.  PER: periodic gather.
-template <bool MIXED, bool RED, bool EPS0, bool PER>
+template <bool MIXED, bool RED, bool EPS0, bool PER, bool REMOTE>
 __global__ __launch_bounds__(kGBlock) void k_gravity(GravityArgs a) {
-    gravity_body<MIXED, RED, EPS0, PER>(a);
+    gravity_body<MIXED, RED, EPS0, PER, REMOTE>(a);
 }
 template <bool EPS0>
 __global__ __launch_bounds__(kGBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_gravity_mixed_red(
     GravityArgs a) {
-    gravity_body<true, true, EPS0, false>(a);
+    gravity_body<true, true, EPS0, false, false>(a);
 }
 template <bool EPS0, bool PER>
 __global__ __launch_bounds__(kGBlock) __attribute__((amdgpu_waves_per_eu(7))) void k_gravity_mixed_gather(
     GravityArgs a) {
-    gravity_body<true, false, EPS0, PER>(a);
+    gravity_body<true, false, EPS0, PER, false>(a);
 }
 
 // Adjoint of the gravity sums, FP64, gather layout.  For target j and each
@@ -423,7 +442,7 @@ p2p_status launch_gravity(const GravityArgs &a, bool redundant, bool mixed, bool
     const unsigned g = static_cast<unsigned>(a.L);
     // the redundant layout holds shifted rows already; only the gather stages images
     const bool per = !redundant && a.nbr_shift != nullptr;
-#define P2P_GRAV(M, R, E, P) k_gravity<M, R, E, P><<<g, kGBlock, 0, s>>>(a)
+#define P2P_GRAV(M, R, E, P) k_gravity<M, R, E, P, false><<<g, kGBlock, 0, s>>>(a)
 #define P2P_GRAV_MG(E, P) k_gravity_mixed_gather<E, P><<<g, kGBlock, 0, s>>>(a)
     if (mixed) {
         if (redundant) {
@@ -445,6 +464,23 @@ p2p_status launch_gravity(const GravityArgs &a, bool redundant, bool mixed, bool
     }
 #undef P2P_GRAV_MG
 #undef P2P_GRAV
+    P2P_LAUNCH_CHECK();
+    return P2P_OK;
+}
+
+p2p_status launch_gravity_remote(const GravityArgs &a, bool redundant, bool mixed, bool eps_zero,
+                                 hipStream_t s) {
+    if (a.L <= 0) return P2P_OK;
+    const unsigned g = static_cast<unsigned>(a.L);
+    const bool per = !redundant && a.nbr_shift != nullptr;
+#define P2P_GRAV_R(M, R, E, P) k_gravity<M, R, E, P, true><<<g, kGBlock, 0, s>>>(a)
+#define P2P_GRAV_RM(M)                                                                                  \
+    if (redundant) { if (eps_zero) P2P_GRAV_R(M, true, true, false); else P2P_GRAV_R(M, true, false, false); } \
+    else if (per) { if (eps_zero) P2P_GRAV_R(M, false, true, true); else P2P_GRAV_R(M, false, false, true); } \
+    else { if (eps_zero) P2P_GRAV_R(M, false, true, false); else P2P_GRAV_R(M, false, false, false); }
+    if (mixed) { P2P_GRAV_RM(true) } else { P2P_GRAV_RM(false) }
+#undef P2P_GRAV_RM
+#undef P2P_GRAV_R
     P2P_LAUNCH_CHECK();
     return P2P_OK;
 }

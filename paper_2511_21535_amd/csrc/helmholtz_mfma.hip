@@ -236,10 +236,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 constexpr int kColBoxes = kHelmColBoxes;
 constexpr int kColWaves = 4;
 constexpr int kColOffsets = (27 + kColWaves - 1) / kColWaves;
-#ifndef P2P_COL_BUFS
-#define P2P_COL_BUFS 8
-#endif
-constexpr int kColBufs = P2P_COL_BUFS;   // operand buffers of the prefetch pipeline (<= 16)
+// operand buffers of the prefetch pipeline; the rotation runs on across offsets
+// of 16 k-steps each, so the count divides 16
+constexpr int kColBufs = 4;
+static_assert(16 % kColBufs == 0, "the buffer rotation must restart with every offset");
 
 template <bool RED, bool CONJ>
 __global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols(

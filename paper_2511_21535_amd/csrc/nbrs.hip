@@ -78,20 +78,22 @@ enum { kNbrCount = 0, kNbrFill = 1 };
 // A leaf with more candidates than this (a large leaf beside a finely split
 // region) is left to k_neighbors_heavy, which spreads its candidates over a
 // whole workgroup; in one wavefront it would set the time of the whole pass.
-#ifndef P2P_NBR_HEAVY
-#define P2P_NBR_HEAVY 1024
-#endif
-constexpr int32_t kHeavyCands = P2P_NBR_HEAVY;
+constexpr int32_t kHeavyCands = 1024;
 constexpr int kHeavyWaves = 16;
 constexpr unsigned kHeavyGrid = 512;
 
-// What one leaf's search needs: the tree arrays and the key layout.
+// What one leaf's search needs: the candidate (source) tree's arrays and key
+// directory, the target leaves' keys and levels (the same tree for plain
+// lists, another one for remote lists), and the key layout.
 struct NbrTree {
     const uint64_t *leaf_key;
     const int8_t *leaf_level;
     const int32_t *leaf_start;
     const int32_t *dir;
     int64_t L;
+    const uint64_t *tkey;
+    const int8_t *tlevel;
+    int64_t Lt;
     int key_bits, inst_shift, dir_bits, dir_shift;
 };
 
@@ -105,8 +107,8 @@ struct NbrLeaf {
 
 __device__ inline NbrLeaf nbr_leaf(const NbrTree &t, int64_t A) {
     NbrLeaf f;
-    const uint64_t kA = t.leaf_key[A];
-    f.lA = t.leaf_level[A];
+    const uint64_t kA = t.tkey[A];
+    f.lA = t.tlevel[A];
     f.dim = int64_t(1) << t.key_bits;
     f.sA = int64_t(1) << (t.key_bits - f.lA);
     f.local_mask = (3 * t.key_bits >= 64) ? ~0ull : ((1ull << (3 * t.key_bits)) - 1ull);
@@ -261,7 +263,7 @@ __global__ __launch_bounds__(64 * kNbrWaves) void k_neighbors(
     __shared__ int32_t s_code[kNbrWaves][32];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t A = static_cast<int64_t>(blockIdx.x) * kNbrWaves + w;
-    if (A >= t.L) return;
+    if (A >= t.Lt) return;
     if (MODE == kNbrFill && counts[A] <= kNbrSlots) return;
     const NbrLeaf f = nbr_leaf(t, A);
     int K = 0;
@@ -431,13 +433,16 @@ p2p_status launch_key_directory(const uint64_t *leaf_key, int64_t L, int total_k
 
 namespace {
 NbrTree make_tree(const uint64_t *leaf_key, const int8_t *leaf_level, const int32_t *leaf_start, int64_t L,
-                  int key_bits, int inst_shift, const int32_t *dir, int total_key_bits) {
+                  int key_bits, int inst_shift, const int32_t *dir, int total_key_bits, const NbrTargets *tg) {
     NbrTree t;
     t.leaf_key = leaf_key;
     t.leaf_level = leaf_level;
     t.leaf_start = leaf_start;
     t.dir = dir;
     t.L = L;
+    t.tkey = tg ? tg->leaf_key : leaf_key;
+    t.tlevel = tg ? tg->leaf_level : leaf_level;
+    t.Lt = tg ? tg->L : L;
     t.key_bits = key_bits;
     t.inst_shift = inst_shift;
     t.dir_bits = neighbor_dir_bits(total_key_bits);
@@ -450,11 +455,11 @@ p2p_status launch_neighbors_count(const uint64_t *leaf_key, const int8_t *leaf_l
                                   int key_bits, int inst_shift, const int32_t *dir, int total_key_bits,
                                   const int32_t *leaf_start, int32_t *counts, int32_t *segs,
                                   int32_t *slots, int8_t *slot_code, int32_t *counters, int32_t *heavy,
-                                  hipStream_t s) {
-    if (L <= 0) return P2P_OK;
-    const NbrTree t = make_tree(leaf_key, leaf_level, leaf_start, L, key_bits, inst_shift, dir, total_key_bits);
+                                  hipStream_t s, const NbrTargets *tg) {
+    const NbrTree t = make_tree(leaf_key, leaf_level, leaf_start, L, key_bits, inst_shift, dir, total_key_bits, tg);
+    if (t.Lt <= 0) return P2P_OK;
 #define P2P_NBR_COUNT(PER)                                                                             \
-    k_neighbors<kNbrCount, PER><<<grid_for(L, kNbrWaves), 64 * kNbrWaves, 0, s>>>(                    \
+    k_neighbors<kNbrCount, PER><<<grid_for(t.Lt, kNbrWaves), 64 * kNbrWaves, 0, s>>>(                 \
         t, counts, segs, slots, slot_code, counters, heavy, nullptr, nullptr, nullptr);                 \
     P2P_LAUNCH_CHECK();                                                                                \
     k_neighbors_heavy<kNbrCount, PER><<<kHeavyGrid, 64 * kHeavyWaves, 0, s>>>(                        \
@@ -476,16 +481,17 @@ p2p_status launch_neighbors_fill(const uint64_t *leaf_key, const int8_t *leaf_le
                                  int key_bits, int inst_shift, const int32_t *dir, int total_key_bits,
                                  const int32_t *counts, const int32_t *slots, const int8_t *slot_code,
                                  int32_t *counters, const int32_t *heavy, bool any_overflow,
-                                 const int64_t *nbr_start, int32_t *nbr_idx, int8_t *nbr_shift, hipStream_t s) {
-    if (L <= 0) return P2P_OK;
-    k_compact_slots<<<grid_for(L * kNbrSlots, 256), 256, 0, s>>>(counts, slots, slot_code, nbr_start, L,
-                                                                 nbr_idx, nbr_shift);
+                                 const int64_t *nbr_start, int32_t *nbr_idx, int8_t *nbr_shift, hipStream_t s,
+                                 const NbrTargets *tg) {
+    const NbrTree t = make_tree(leaf_key, leaf_level, nullptr, L, key_bits, inst_shift, dir, total_key_bits, tg);
+    if (t.Lt <= 0) return P2P_OK;
+    k_compact_slots<<<grid_for(t.Lt * kNbrSlots, 256), 256, 0, s>>>(counts, slots, slot_code, nbr_start, t.Lt,
+                                                                    nbr_idx, nbr_shift);
     P2P_LAUNCH_CHECK();
     if (any_overflow) {
-        const NbrTree t = make_tree(leaf_key, leaf_level, nullptr, L, key_bits, inst_shift, dir, total_key_bits);
         int32_t *cn = const_cast<int32_t *>(counts);
 #define P2P_NBR_FILL(PER)                                                                              \
-        k_neighbors<kNbrFill, PER><<<grid_for(L, kNbrWaves), 64 * kNbrWaves, 0, s>>>(                 \
+        k_neighbors<kNbrFill, PER><<<grid_for(t.Lt, kNbrWaves), 64 * kNbrWaves, 0, s>>>(              \
             t, cn, nullptr, nullptr, nullptr, counters, nullptr, nbr_start, nbr_idx, nbr_shift);       \
         P2P_LAUNCH_CHECK();                                                                            \
         k_neighbors_heavy<kNbrFill, PER><<<kHeavyGrid, 64 * kHeavyWaves, 0, s>>>(                     \

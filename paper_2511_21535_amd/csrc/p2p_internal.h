@@ -101,7 +101,14 @@ p2p_status launch_key_directory(const uint64_t *leaf_key, int64_t L, int total_k
 // list into slots[L][64]; after the scan of the counts, the fill moves the
 // slots into the CSR and searches again only for the lists longer than 64.
 // Leaves with many candidates are listed in heavy[L] and searched by a whole
-// workgroup each.
+// workgroup each.  With tg set, the lists belong to tg's leaves (counts, segs,
+// slots, heavy, nbr_start sized by tg->L) and the candidates are the leaves of
+// the tree passed as leaf_key/leaf_level/leaf_start/L (remote lists).
+struct NbrTargets {
+    const uint64_t *leaf_key;
+    const int8_t *leaf_level;
+    int64_t L;
+};
 // A non-null slot_code selects periodic lists (particles on the unit torus):
 // slot_code[L][64] and nbr_shift then receive the image codes.
 constexpr int kNbrSlotsPerLeaf = 64;
@@ -109,20 +116,23 @@ p2p_status launch_neighbors_count(const uint64_t *leaf_key, const int8_t *leaf_l
                                   int key_bits, int inst_shift, const int32_t *dir, int total_key_bits,
                                   const int32_t *leaf_start, int32_t *counts, int32_t *segs,
                                   int32_t *slots, int8_t *slot_code, int32_t *counters, int32_t *heavy,
-                                  hipStream_t s);
+                                  hipStream_t s, const NbrTargets *tg = nullptr);
 p2p_status launch_nbr_totals(const int64_t *start, const int64_t *seg_scan, const int32_t *counters,
                              int64_t L, int64_t *out, hipStream_t s);
 p2p_status launch_neighbors_fill(const uint64_t *leaf_key, const int8_t *leaf_level, int64_t L,
                                  int key_bits, int inst_shift, const int32_t *dir, int total_key_bits,
                                  const int32_t *counts, const int32_t *slots, const int8_t *slot_code,
                                  int32_t *counters, const int32_t *heavy, bool any_overflow,
-                                 const int64_t *nbr_start, int32_t *nbr_idx, int8_t *nbr_shift, hipStream_t s);
+                                 const int64_t *nbr_start, int32_t *nbr_idx, int8_t *nbr_shift, hipStream_t s,
+                                 const NbrTargets *tg = nullptr);
 
 // Restructure (restructure.hip).
-// nbr_shift (image codes, may be null) places the unshifted self image.
+// Segment lengths of L target leaves over the source leaves of leaf_start.
+// nbr_shift (image codes, may be null) places the unshifted self image; with
+// self_in_list false (remote lists) red_self is -1.
 p2p_status launch_seg_lengths(const int32_t *leaf_start, const int64_t *nbr_start,
                               const int32_t *nbr_idx, const int8_t *nbr_shift, int64_t L,
-                              int32_t *seg_len, int32_t *red_self, hipStream_t s);
+                              int32_t *seg_len, int32_t *red_self, bool self_in_list, hipStream_t s);
 template <class T>
 p2p_status launch_permute_rows(const T *src, const int32_t *perm, int64_t n, int64_t row_len,
                                T *dst, hipStream_t s);
@@ -179,6 +189,8 @@ struct GravityArgs {
     const int64_t *nbr_start;
     const int32_t *nbr_idx;
     const int8_t *nbr_shift;          // image codes of periodic lists (gather), else null
+    const int32_t *src_leaf_start;    // leaf starts of the source tree (leaf_start unless remote)
+    const Row4d *t4;                  // remote: the targets' sorted rows
     const int64_t *red_start;
     const int32_t *red_self;
     const Row4d *s4;                  // FP64 rows (x, y, z, m): sorted (gather) or redundant (FP64)
@@ -188,6 +200,11 @@ struct GravityArgs {
 };
 p2p_status launch_gravity(const GravityArgs &a, bool redundant, bool mixed, bool eps_zero,
                           hipStream_t s);
+// Remote lists: targets from a.t4 (sorted rows of the target tree), sources of
+// the source tree (a.src_leaf_start, a.s4 sorted source rows or the remote
+// segments), no self pair, sums added to phi, ax, ay, az.
+p2p_status launch_gravity_remote(const GravityArgs &a, bool redundant, bool mixed, bool eps_zero,
+                                 hipStream_t s);
 
 struct GravityAdjointArgs {
     int64_t L;

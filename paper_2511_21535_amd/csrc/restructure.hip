@@ -59,7 +59,7 @@ __global__ __launch_bounds__(256) void k_seg_lengths(const int32_t *__restrict__
                                                      const int32_t *__restrict__ nbr_idx,
                                                      const int8_t *__restrict__ nbr_shift, int64_t L,
                                                      int32_t *__restrict__ seg_len,
-                                                     int32_t *__restrict__ red_self) {
+                                                     int32_t *__restrict__ red_self, int self_in_list) {
     const int sub = threadIdx.x % kSegLanes;
     const int64_t A = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / kSegLanes;
     if (A >= L) return;     // whole 16-lane groups leave together
@@ -78,7 +78,7 @@ __global__ __launch_bounds__(256) void k_seg_lengths(const int32_t *__restrict__
     }
     if (sub == 0) {
         seg_len[A] = len;
-        red_self[A] = before;
+        red_self[A] = self_in_list ? before : -1;
     }
 }
 
@@ -308,10 +308,10 @@ __global__ __launch_bounds__(kCopyBlock) void k_copy_segments_units(
 
 p2p_status launch_seg_lengths(const int32_t *leaf_start, const int64_t *nbr_start,
                               const int32_t *nbr_idx, const int8_t *nbr_shift, int64_t L,
-                              int32_t *seg_len, int32_t *red_self, hipStream_t s) {
+                              int32_t *seg_len, int32_t *red_self, bool self_in_list, hipStream_t s) {
     if (L <= 0) return P2P_OK;
     k_seg_lengths<<<grid_for(L * kSegLanes, 256), 256, 0, s>>>(leaf_start, nbr_start, nbr_idx, nbr_shift, L,
-                                                                seg_len, red_self);
+                                                                seg_len, red_self, self_in_list ? 1 : 0);
     P2P_LAUNCH_CHECK();
     return P2P_OK;
 }

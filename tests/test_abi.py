@@ -208,3 +208,39 @@ def test_periodic_list_validation(lib):
     n.periodic = 0
     assert lib.p2p_build_neighbors(ctypes.byref(t), ctypes.byref(n), None, ctypes.byref(nb), None) == L.P2P_OK
     assert plain > nb.value             # room for the slot image codes
+
+
+def test_remote_validation(lib):
+    t = _tree(10, L_=1)
+    t.perm = t.iperm = t.leaf_start = t.leaf_key = t.leaf_level = 0x1000
+    u = _tree(12, L_=2)
+    u.perm = u.iperm = u.leaf_start = u.leaf_key = u.leaf_level = 0x2000
+    n = L.p2p_nbrs()
+    nb = ctypes.c_size_t(0)
+    z = ctypes.c_void_p(0x1000)
+    # size queries work on the host; a missing or identical source tree is rejected
+    assert lib.p2p_build_neighbors_remote(ctypes.byref(t), ctypes.byref(u), ctypes.byref(n), None,
+                                          ctypes.byref(nb), None) == L.P2P_OK
+    assert lib.p2p_build_neighbors_remote(ctypes.byref(t), None, ctypes.byref(n), None,
+                                          ctypes.byref(nb), None) == L.P2P_EINVAL
+    assert lib.p2p_build_neighbors_remote(ctypes.byref(t), ctypes.byref(t), ctypes.byref(n), None,
+                                          ctypes.byref(nb), None) == L.P2P_EINVAL
+    u.kind = L.P2P_TREE_GRIDS
+    assert lib.p2p_build_neighbors_remote(ctypes.byref(t), ctypes.byref(u), ctypes.byref(n), None,
+                                          ctypes.byref(nb), None) == L.P2P_EINVAL
+    assert "particle trees" in L.last_error()
+    u.kind = L.P2P_TREE_PARTICLES
+    # remote lists may be empty: count 0 is accepted by the evaluation
+    n.count, n.nbr_start = 0, 0x1000
+
+    def ev(layout=L.P2P_GATHER, eps=1e-3):
+        return lib.p2p_eval_gravity_remote(ctypes.byref(t), ctypes.byref(u), ctypes.byref(n), None, layout,
+                                           L.P2P_FP32_MIXED, eps, z, z, z, z, z, z, z, z, z, z, z, None,
+                                           ctypes.byref(nb), None)
+    assert ev() == L.P2P_OK and nb.value > 0
+    assert ev(eps=-1.0) == L.P2P_EINVAL
+    nb.value = 1 << 20
+    st = lib.p2p_eval_gravity_remote(ctypes.byref(t), ctypes.byref(u), ctypes.byref(n), None, L.P2P_REDUNDANT,
+                                     L.P2P_FP64, 1e-3, z, z, z, z, z, z, z, z, z, z, z,
+                                     ctypes.c_void_p(0x100000), ctypes.byref(nb), None)
+    assert st == L.P2P_EINVAL and "needs red" in L.last_error()
