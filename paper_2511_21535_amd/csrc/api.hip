@@ -347,10 +347,11 @@ p2p_status restructure_common(const p2p_tree *tree, const p2p_tree *srct, const 
     int32_t *count_self = ar.take<int32_t>(nbrs->red_entries < 0 ? L : 0);
     Row4d *s4 = nullptr;
     void *sq = nullptr;
-    if (grav)
-        s4 = ar.take<Row4d>(n);
-    else
+    if (grav) {
+        if (!remote) s4 = ar.take<Row4d>(n);
+    } else {
         sq = ar.take<char>(static_cast<size_t>(n) * nrhs * csize);
+    }
     p2p_status st;
     if (ws_query(ws, ws_bytes, ar, &st)) return st;
     if (!src) return fail(P2P_EINVAL, "src is NULL");
@@ -375,12 +376,17 @@ p2p_status restructure_common(const p2p_tree *tree, const p2p_tree *srct, const 
     if (S > 0 && !out->planes[0])
         return fail(P2P_EINVAL, "out->planes must not be NULL");
     // rows into sorted order first: the longest of the short launches, so the
-    // segment offsets below are already queued when it ends
-    if (grav)
-        P2P_TRY(launch_scatter4(static_cast<const double *>(src[0]), static_cast<const double *>(src[1]),
-                                static_cast<const double *>(src[2]), static_cast<const double *>(src[3]),
-                                srct->iperm, n, s4, s));
-    else if (mixed)
+    // segment offsets below are already queued when it ends.  Remote sources
+    // are not sorted: the copy reads them through the source tree's perm (a
+    // thin layer of the other domain is used)
+    const PermRows pr{static_cast<const double *>(src[0]), static_cast<const double *>(src[1]),
+                      static_cast<const double *>(src[2]), static_cast<const double *>(src[3]), srct->perm};
+    if (grav) {
+        if (!remote)
+            P2P_TRY(launch_scatter4(static_cast<const double *>(src[0]), static_cast<const double *>(src[1]),
+                                    static_cast<const double *>(src[2]), static_cast<const double *>(src[3]),
+                                    srct->iperm, n, s4, s));
+    } else if (mixed)
         P2P_TRY(launch_permute_rows<float2>(static_cast<const float2 *>(src[0]), tree->perm, n, nrhs,
                                             static_cast<float2 *>(sq), s));
     else
@@ -396,7 +402,7 @@ p2p_status restructure_common(const p2p_tree *tree, const p2p_tree *srct, const 
                                              nbrs->nbr_start, nbrs->nbr_idx, shifts(nbrs), out->red_start, L,
                                              mixed ? nullptr : static_cast<Row4d *>(out->planes[0]),
                                              mixed ? static_cast<float4 *>(out->planes[0]) : nullptr,
-                                             streaming, s));
+                                             streaming, s, remote ? &pr : nullptr));
     else if (mixed)
         P2P_TRY(launch_copy_segments<float2>(static_cast<const float2 *>(sq), nrhs, tree->leaf_start,
                                              nbrs->nbr_start, nbrs->nbr_idx, out->red_start, L,
@@ -614,8 +620,6 @@ extern "C" p2p_status p2p_eval_gravity_remote(const p2p_tree *tree, const p2p_tr
     const bool mixed = prec == P2P_FP32_MIXED, redundant = layout == P2P_REDUNDANT;
     const int64_t n = tree->n, ns = src_tree->n;
     Arena ar(ws);
-    Row4d *t4 = ar.take<Row4d>(n);
-    Row4d *s4 = redundant ? nullptr : ar.take<Row4d>(ns);
     p2p_status st;
     if (ws_query(ws, ws_bytes, ar, &st)) return st;
     if (n > 0 && (!phi || !ax || !ay || !az)) return fail(P2P_EINVAL, "outputs must not be NULL");
@@ -645,9 +649,9 @@ extern "C" p2p_status p2p_eval_gravity_remote(const p2p_tree *tree, const p2p_tr
     a.ax = ax;
     a.ay = ay;
     a.az = az;
-    // the targets' rows (the fourth plane is not read)
-    P2P_TRY(launch_scatter4(x, y, z, x, tree->iperm, n, t4, s));
-    a.t4 = t4;
+    a.tx = x;
+    a.ty = y;
+    a.tz = z;
     if (redundant) {
         a.red_start = red->red_start;
         if (mixed)
@@ -655,8 +659,11 @@ extern "C" p2p_status p2p_eval_gravity_remote(const p2p_tree *tree, const p2p_tr
         else
             a.s4 = static_cast<const Row4d *>(red->planes[0]);
     } else {
-        P2P_TRY(launch_scatter4(sx, sy, sz, sm, src_tree->iperm, ns, s4, s));
-        a.s4 = s4;
+        a.sx = sx;
+        a.sy = sy;
+        a.sz = sz;
+        a.sm = sm;
+        a.src_perm = src_tree->perm;
     }
     return launch_gravity_remote(a, redundant, mixed, eps == 0.0, s);
 }

@@ -19,9 +19,11 @@
 // computed in the same arithmetic); the self term of a is exactly zero.
 // With eps == 0 pairs at zero distance contribute nothing instead.
 //
-// Remote lists (sources of another particle set, REMOTE): the targets are read
-// from their own sorted rows, the sources through the source tree's leaf
-// starts (gather) or from the remote segments (redundant); no self pair is
+// Remote lists (sources of another particle set, REMOTE): most target leaves
+// of a domain have no remote source and leave at once; the others read their
+// targets and (gather) their sources through the trees' permutations straight
+// from the caller-order arrays, since only a thin layer at the domain's faces
+// takes part; the redundant layout reads the remote segments.  No self pair is
 // added back, and the sums are added to the outputs.
 //
 // Periodic lists (gather and adjoint): a staged source row of an entry with
@@ -158,6 +160,18 @@ __device__ inline void leaf_centre(uint64_t key, int level, double c[3]) {
     c[2] = (static_cast<double>(p2pd::compact3(key >> 2)) + half) * 0x1p-20;
 }
 
+// Source row at sorted slot `row` of the gather layout: the sorted rows, or for
+// remote sources the caller-order arrays through the source tree's perm.
+template <bool REMOTE>
+__device__ inline Row4d source_row(const GravityArgs &a, int64_t row) {
+    if constexpr (REMOTE) {
+        const int64_t j = a.src_perm[row];
+        return Row4d{a.sx[j], a.sy[j], a.sz[j], a.sm[j]};
+    } else {
+        return a.s4[row];
+    }
+}
+
 template <bool MIXED, bool RED, bool EPS0, bool PER, bool REMOTE>
 __device__ __forceinline__ void gravity_body(const GravityArgs &a) {
     using Src = typename std::conditional<MIXED, float4, Row4d>::type;
@@ -174,6 +188,9 @@ __device__ __forceinline__ void gravity_body(const GravityArgs &a) {
 
     // gather: neighbouring leaves on one XCD share their sources in its L2
     const int64_t A = RED ? static_cast<int64_t>(blockIdx.x) : p2pd::xcd_contiguous(blockIdx.x, gridDim.x);
+    if constexpr (REMOTE) {
+        if (a.nbr_start[A] == a.nbr_start[A + 1]) return;   // the whole workgroup: no barrier is skipped
+    }
     const int32_t t0 = a.leaf_start[A];
     const int32_t ntar = a.leaf_start[A + 1] - t0;
     const double eps2 = a.eps2;
@@ -189,7 +206,8 @@ __device__ __forceinline__ void gravity_body(const GravityArgs &a) {
         // target position (relative to the leaf centre for FP32_MIXED) and mass
         Src tv;
         if constexpr (REMOTE) {
-            const Row4d v = a.t4[t0 + tc0 + t];
+            const int64_t i = a.perm[t0 + tc0 + t];
+            const Row4d v{a.tx[i], a.ty[i], a.tz[i], 0.0};
             if constexpr (MIXED)
                 tv = make_float4(static_cast<float>(v.x - c[0]), static_cast<float>(v.y - c[1]),
                                  static_cast<float>(v.z - c[2]), static_cast<float>(v.w));
@@ -230,16 +248,18 @@ __device__ __forceinline__ void gravity_body(const GravityArgs &a) {
                 if constexpr (RED) {
                     *d = a.red4[row];
                 } else {
-                    Row4d v = a.s4[row];
+                    Row4d v = source_row<REMOTE>(a, row);
                     if constexpr (PER) v = shifted(v, code);
                     *d = make_float4(static_cast<float>(v.x - c[0]), static_cast<float>(v.y - c[1]),
                                      static_cast<float>(v.z - c[2]), static_cast<float>(v.w));
                 }
             } else {
-                if constexpr (PER && !RED)
-                    *d = shifted(a.s4[row], code);
-                else
+                if constexpr (RED)
                     *d = a.s4[row];
+                else if constexpr (PER)
+                    *d = shifted(source_row<REMOTE>(a, row), code);
+                else
+                    *d = source_row<REMOTE>(a, row);
             }
         };
         auto body = [&](int) {

@@ -142,11 +142,18 @@ p2p_status launch_scatter4(const double *a, const double *b, const double *c, co
 // Gravity payload from sorted rows: FP64 rows (d8) or, for FP32_MIXED, float4
 // (x - c_A, y - c_A, z - c_A, m) relative to the centre of target leaf A (d4).
 // With image codes (nbr_shift not null) each source is placed at x + s.
+// With pr set, the source rows are read through pr->perm (sorted slot -> caller
+// index) from the caller-order planes pr->x, y, z, m instead of `sorted`.
+struct PermRows {
+    const double *x, *y, *z, *m;
+    const int32_t *perm;
+};
 p2p_status launch_copy_segments_gravity(const Row4d *sorted, const uint64_t *leaf_key,
                                         const int8_t *leaf_level, const int32_t *leaf_start,
                                         const int64_t *nbr_start, const int32_t *nbr_idx,
                                         const int8_t *nbr_shift, const int64_t *red_start, int64_t L,
-                                        Row4d *d8, float4 *d4, bool streaming, hipStream_t s);
+                                        Row4d *d8, float4 *d4, bool streaming, hipStream_t s,
+                                        const PermRows *pr = nullptr);
 template <class T>
 p2p_status launch_copy_segments(const T *sorted, int64_t row_len, const int32_t *leaf_start,
                                 const int64_t *nbr_start, const int32_t *nbr_idx,
@@ -190,7 +197,9 @@ struct GravityArgs {
     const int32_t *nbr_idx;
     const int8_t *nbr_shift;          // image codes of periodic lists (gather), else null
     const int32_t *src_leaf_start;    // leaf starts of the source tree (leaf_start unless remote)
-    const Row4d *t4;                  // remote: the targets' sorted rows
+    const double *tx, *ty, *tz;       // remote: the targets' caller-order positions
+    const double *sx, *sy, *sz, *sm;  // remote gather: the sources' caller-order arrays
+    const int32_t *src_perm;          // remote gather: the source tree's perm
     const int64_t *red_start;
     const int32_t *red_self;
     const Row4d *s4;                  // FP64 rows (x, y, z, m): sorted (gather) or redundant (FP64)
@@ -200,9 +209,10 @@ struct GravityArgs {
 };
 p2p_status launch_gravity(const GravityArgs &a, bool redundant, bool mixed, bool eps_zero,
                           hipStream_t s);
-// Remote lists: targets from a.t4 (sorted rows of the target tree), sources of
-// the source tree (a.src_leaf_start, a.s4 sorted source rows or the remote
-// segments), no self pair, sums added to phi, ax, ay, az.
+// Remote lists: targets read through perm from a.tx/ty/tz, sources of the
+// source tree (gather: through a.src_perm from a.sx/sy/sz/sm; redundant: the
+// remote segments), leaves with an empty list skipped, no self pair, sums
+// added to phi, ax, ay, az.
 p2p_status launch_gravity_remote(const GravityArgs &a, bool redundant, bool mixed, bool eps_zero,
                                  hipStream_t s);
 

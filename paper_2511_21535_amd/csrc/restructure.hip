@@ -164,9 +164,12 @@ __device__ int64_t load_nbr_chunk(const int32_t *__restrict__ leaf_start,
 constexpr int kMapRows = 4096;
 constexpr int kRowsPerLane = 8;
 
-template <bool MIXED, bool NT, bool PER>
+// GATH (remote sources, a thin layer of another domain): rows read through the
+// source tree's perm from the caller-order planes, instead of sorting all of
+// that domain's points first.
+template <bool MIXED, bool NT, bool PER, bool GATH>
 __global__ __launch_bounds__(256) void k_copy_segments_grav(
-    const Row4d *__restrict__ sorted, const uint64_t *__restrict__ leaf_key,
+    const Row4d *__restrict__ sorted, PermRows pr, const uint64_t *__restrict__ leaf_key,
     const int8_t *__restrict__ leaf_level, const int32_t *__restrict__ leaf_start,
     const int64_t *__restrict__ nbr_start, const int32_t *__restrict__ nbr_idx,
     const int8_t *__restrict__ nbr_shift, const int64_t *__restrict__ red_start, int64_t L,
@@ -222,7 +225,14 @@ __global__ __launch_bounds__(256) void k_copy_segments_grav(
                 while (b + 1 < nc && s_pre[w][b + 1] <= p) ++b;
                 bb = b;
             }
-            Row4d v = sorted[s_first[w][bb] + (p - s_pre[w][bb])];
+            const int64_t slot = s_first[w][bb] + (p - s_pre[w][bb]);
+            Row4d v;
+            if constexpr (GATH) {
+                const int64_t j = pr.perm[slot];
+                v = Row4d{pr.x[j], pr.y[j], pr.z[j], pr.m[j]};
+            } else {
+                v = sorted[slot];
+            }
             if constexpr (PER) {
                 const int cd = s_code[w][bb];
                 v.x += static_cast<double>(cd % 3 - 1);
@@ -365,6 +375,7 @@ template <class T>
 p2p_status launch_permute_rows(const T *src, const int32_t *perm, int64_t n, int64_t row_len,
                                T *dst, hipStream_t s) {
     if (n <= 0) return P2P_OK;
+    if (!src || !perm || !dst) return fail(P2P_EINVAL, "internal: row permutation with a null array");
     const int64_t rb = row_len * static_cast<int64_t>(sizeof(T));
     switch (unit_bytes(rb)) {
     case 16: return permute_units<uint4>(src, perm, n, rb, dst, s);
@@ -376,6 +387,7 @@ p2p_status launch_permute_rows(const T *src, const int32_t *perm, int64_t n, int
 p2p_status launch_scatter4(const double *a, const double *b, const double *c, const double *d,
                            const int32_t *iperm, int64_t n, Row4d *out, hipStream_t s) {
     if (n <= 0) return P2P_OK;
+    if (!a || !b || !c || !d || !iperm || !out) return fail(P2P_EINVAL, "internal: row scatter with a null array");
     k_scatter4<<<grid_for(n, 256), 256, 0, s>>>(a, b, c, d, iperm, n, out);
     P2P_LAUNCH_CHECK();
     return P2P_OK;
@@ -385,19 +397,24 @@ p2p_status launch_copy_segments_gravity(const Row4d *sorted, const uint64_t *lea
                                         const int8_t *leaf_level, const int32_t *leaf_start,
                                         const int64_t *nbr_start, const int32_t *nbr_idx,
                                         const int8_t *nbr_shift, const int64_t *red_start, int64_t L,
-                                        Row4d *d8, float4 *d4, bool streaming, hipStream_t s) {
+                                        Row4d *d8, float4 *d4, bool streaming, hipStream_t s,
+                                        const PermRows *pr) {
     if (L <= 0) return P2P_OK;
     const unsigned g = grid_for(L, 4);
-#define P2P_COPY_GRAV(M, NT, PER)                                                                    \
-    k_copy_segments_grav<M, NT, PER><<<g, 256, 0, s>>>(sorted, leaf_key, leaf_level, leaf_start,    \
-                                                       nbr_start, nbr_idx, nbr_shift, red_start, L, d8, d4)
-#define P2P_COPY_GRAV_NT(M, PER) \
-    if (streaming) P2P_COPY_GRAV(M, true, PER); else P2P_COPY_GRAV(M, false, PER)
+    const PermRows prv = pr ? *pr : PermRows{};
+#define P2P_COPY_GRAV(M, NT, PER, G)                                                                      \
+    k_copy_segments_grav<M, NT, PER, G><<<g, 256, 0, s>>>(sorted, prv, leaf_key, leaf_level, leaf_start, \
+                                                          nbr_start, nbr_idx, nbr_shift, red_start, L, d8, d4)
+#define P2P_COPY_GRAV_NT(M, PER, G) \
+    if (streaming) P2P_COPY_GRAV(M, true, PER, G); else P2P_COPY_GRAV(M, false, PER, G)
+#define P2P_COPY_GRAV_G(M, PER) \
+    if (pr) { P2P_COPY_GRAV_NT(M, PER, true); } else { P2P_COPY_GRAV_NT(M, PER, false); }
     if (nbr_shift) {
-        if (d4) P2P_COPY_GRAV_NT(true, true); else P2P_COPY_GRAV_NT(false, true);
+        if (d4) { P2P_COPY_GRAV_G(true, true) } else { P2P_COPY_GRAV_G(false, true) }
     } else {
-        if (d4) P2P_COPY_GRAV_NT(true, false); else P2P_COPY_GRAV_NT(false, false);
+        if (d4) { P2P_COPY_GRAV_G(true, false) } else { P2P_COPY_GRAV_G(false, false) }
     }
+#undef P2P_COPY_GRAV_G
 #undef P2P_COPY_GRAV_NT
 #undef P2P_COPY_GRAV
     P2P_LAUNCH_CHECK();

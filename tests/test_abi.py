@@ -237,7 +237,7 @@ def test_remote_validation(lib):
         return lib.p2p_eval_gravity_remote(ctypes.byref(t), ctypes.byref(u), ctypes.byref(n), None, layout,
                                            L.P2P_FP32_MIXED, eps, z, z, z, z, z, z, z, z, z, z, z, None,
                                            ctypes.byref(nb), None)
-    assert ev() == L.P2P_OK and nb.value > 0
+    assert ev() == L.P2P_OK          # size query (the remote evaluation needs no workspace)
     assert ev(eps=-1.0) == L.P2P_EINVAL
     nb.value = 1 << 20
     st = lib.p2p_eval_gravity_remote(ctypes.byref(t), ctypes.byref(u), ctypes.byref(n), None, L.P2P_REDUNDANT,
