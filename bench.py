@@ -15,8 +15,9 @@ sub-step times, the Locality metric with the paper's speedup model evaluated on
 the measured times (Sec. 3.2-3.4), the roofline of the dominant kernel
 (the redundant evaluation) and the FP64 CPU oracle timed on the workload.
 Gravity lines also time the per-interaction layout (one record per near-list
-entry, results per record summed afterwards) on the same tree and lists, and
-the same tree on the unit torus (periodic images), both outside the timed
+entry, results per record summed afterwards) on the same tree and lists, the
+same tree on the unit torus (periodic images), and the local, remote and
+periodic interaction types of one half of the domain, all outside the timed
 steps.
 
 --workload selects one of the other configurations for the same measurement
@@ -311,9 +312,93 @@ def run_gravity(wname, args):
     line["periodic"] = periodic_leg(tree, (gx, gy, gz, gm), w, K, args.warmup, bpe,
                                     {"neighbors": t_nbr, "restructure": t_res, "eval_redundant": t_red,
                                      "eval_gather": t_gat})
+    line["interaction_types"] = interaction_types_leg((gx, gy, gz, gm), w, K, args.warmup)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline_gravity(x, y, z, m, w, args.cpu_leaves)
     return line
+
+
+def interaction_types_leg(src, w, K, W):
+    """Local, remote and periodic interactions (Sec. 5.2) of one domain: the
+    particles are cut at x = 0.5 into two domains with trees of their own; the
+    first domain's targets take local sources (its own tree), remote sources
+    (the other domain's points, received in a sharded run) and, on the torus,
+    periodic images of both.  Each type is timed as restructure + redundant
+    evaluation and as a gather evaluation, the remote type in launches of its
+    own (its sums added to the local ones), the periodic images inside the
+    local and remote lists.  Eq. (15) gives the local share of the time; Eq.
+    (14), read as Eq. (4) on the local part, the speedup had only the local
+    part been restructured, beside the measured speedup of restructuring all."""
+    import torch
+    from paper_2511_21535_amd import api
+    eps, prec = w["eps"], w["prec"]
+    cut = src[0] < 0.5
+    da, db = [v[cut].contiguous() for v in src], [v[~cut].contiguous() for v in src]
+    ta = api.Tree.build_particles(*da[:3], depth=w["depth"], leaf_cap=w["leaf_cap"])
+    tb = api.Tree.build_particles(*db[:3], depth=w["depth"], leaf_cap=w["leaf_cap"])
+    occ = torch.diff(ta.leaf_start).to(torch.int64)
+    lists = {"local": ta.neighbors(), "remote": api.build_neighbors(ta, src_tree=tb),
+             "local_periodic": ta.neighbors(periodic=True),
+             "remote_periodic": api.build_neighbors(ta, periodic=True, src_tree=tb)}
+    reds = {k: (api.restructure_remote(ta, tb, nb, *db, prec=prec) if k.startswith("remote")
+                else api.restructure_gravity(ta, nb, *da, prec=prec)) for k, nb in lists.items()}
+    pairs = {k: int((torch.diff(r.red_start) * occ).sum().item()) - (0 if k.startswith("remote") else ta.n)
+             for k, r in reds.items()}
+    outs = [torch.empty(ta.n, dtype=torch.float64, device=src[0].device) for _ in range(4)]
+
+    def run(k, layout):
+        nb, r = lists[k], reds[k]
+        if k.startswith("remote"):
+            if layout == "restructure":
+                api.restructure_remote(ta, tb, nb, *db, prec=prec, out=r)
+            else:
+                api.gravity_remote(ta, tb, nb, eps, *da[:3], *db, layout=layout, prec=prec, red=r, out=outs)
+        else:
+            if layout == "restructure":
+                api.restructure_gravity(ta, nb, *da, prec=prec, out=r)
+            else:
+                api.gravity(ta, nb, eps, *da, layout=layout, prec=prec, red=r, out=outs)
+
+    keys = list(lists)
+    seq = [(k, lay) for k in keys for lay in ("restructure", "redundant", "gather")]
+
+    def step():
+        e = _events(len(seq) + 1)
+        e[0].record()
+        for i, (k, lay) in enumerate(seq):
+            run(k, lay)
+            e[i + 1].record()
+        return e
+
+    _, t = _timed_steps(step, K, W)
+    ms = {f"{k}_{lay}": t[i] / K * 1e3 for i, (k, lay) in enumerate(seq)}
+    red_t = {k: ms[f"{k}_restructure"] + ms[f"{k}_redundant"] for k in keys}
+    gat_t = {k: ms[f"{k}_gather"] for k in keys}
+    # periodic part: the periodic lists' time beyond the plain lists' (local and remote)
+    T = {}
+    for name, tt in (("redundant_incl_restructure", red_t), ("gather", gat_t)):
+        loc, rem = tt["local"], tt["remote"]
+        per = (tt["local_periodic"] - loc) + (tt["remote_periodic"] - rem)
+        T[name] = {"local": loc, "remote": rem, "periodic": per,
+                   "local_share_eq15": speedup_model.local_share(loc, rem, per)}
+    share = T["gather"]["local_share_eq15"]
+    x_local = gat_t["local"] / red_t["local"]
+    all_gat = gat_t["local_periodic"] + gat_t["remote_periodic"]
+    all_red = red_t["local_periodic"] + red_t["remote_periodic"]
+    return {
+        "domain": "x < 0.5 of the workload (targets); sources: its own points, the other domain's, "
+                  "and the periodic images of both",
+        "targets": ta.n, "target_leaves": ta.n_leaves, "source_points_remote": tb.n,
+        "near_entries": {k: nb.count for k, nb in lists.items()},
+        "pairs": pairs,
+        "ms": ms,
+        "ms_by_type": T,
+        "speedup_local_only_eq14": speedup_model.op_speedup(share, x_local),
+        "speedup_local_measured": x_local,
+        "speedup_all_measured": all_gat / all_red,
+        "launches": "local and remote each run in launches of their own (restructure, evaluation); the 26 "
+                    "periodic images ride in the local and remote lists",
+    }
 
 
 def periodic_leg(tree, src, w, K, W, bpe, plain):
