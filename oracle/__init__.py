@@ -253,17 +253,22 @@ def neighbors_periodic(tree: Tree, targets=None):
     return start, idx[:total], sh[:total]
 
 
-def neighbors_remote(tree: Tree, src_tree: Tree, periodic: bool = False):
+def neighbors_remote(tree: Tree, src_tree: Tree, periodic: bool = False, targets=None):
     """Remote near lists (Sec. 5.2, remote interactions): for every leaf of
-    `tree`, the leaves of `src_tree` (another particle set) whose cubes touch
-    it, through the periodic images when `periodic`, ascending in (code, B).
-    Returns (nbr_start, nbr_idx, nbr_shift)."""
+    `tree` (or the leaves `targets`, in that order), the leaves of `src_tree`
+    (another particle set) whose cubes touch it, through the periodic images
+    when `periodic`, ascending in (code, B).  Returns (nbr_start, nbr_idx,
+    nbr_shift)."""
     if tree.kind != "particles" or src_tree.kind != "particles":
         raise ValueError("remote lists are defined for particle trees")
-    Lt, Ls = tree.n_leaves, src_tree.n_leaves
+    anchor, size = tree.anchor, tree.size
+    if targets is not None:
+        sel = np.asarray(targets, dtype=np.int64)
+        anchor, size = _c(anchor[sel], np.int32), _c(size[sel], np.int32)
+    Lt, Ls = anchor.shape[0], src_tree.n_leaves
     start = np.zeros(Lt + 1, dtype=np.int64)
     lib = _load()
-    args = (Lt, _p(tree.anchor), _p(tree.size), Ls, _p(src_tree.anchor), _p(src_tree.size), int(periodic))
+    args = (Lt, _p(anchor), _p(size), Ls, _p(src_tree.anchor), _p(src_tree.size), int(periodic))
     total = lib.orc_neighbors_cross(*args, _p(start), None, None, 0)
     idx = np.zeros(max(total, 1), dtype=np.int32)
     sh = np.zeros(max(total, 1), dtype=np.int8)
