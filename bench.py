@@ -53,12 +53,15 @@ VALU_PEAK_SLOTS = 256 * 4 * 16 * 2.4e9               # = 3.93e13
 # Minimal VALU issue slots per FP32-mixed gravity pair, coordinates already
 # relative to the target leaf's centre (the double subtraction of the offset
 # is per (target leaf, source), not per pair): 3 FP32 differences, 3 FMA for
-# r^2 + eps^2, 1 quarter-rate rsqrt (4 slots), 3 multiplies (w^2, m w,
-# m w^3), 1 add (phi) and 3 FMA (a).
-SLOTS_PER_PAIR_MIXED = 3 + 3 + 4 + 3 + 1 + 3        # = 17
-# FP64 gravity pair: 3 differences, 3 FMA for r^2 + eps^2, rsqrt (4 slots),
-# 3 multiplies, 1 add, 3 FMA.
-SLOTS_PER_PAIR_FP64 = 3 + 3 + 4 + 3 + 1 + 3         # = 17
+# r^2 + eps^2, 1 v_rsq_f32 (2 slots: it issues at half rate, measured by
+# `bench.py --peaks`), 3 multiplies (w^2, m w, m w^3), 1 FMA (phi) and 3 FMA
+# (a).
+SLOTS_PER_PAIR_MIXED = 3 + 3 + 2 + 3 + 1 + 3        # = 15
+# FP64 gravity pair: the instructions hipcc emits per pair, each taken as one
+# slot: 3 differences, 3 FMA for r^2 + eps^2, 3 multiplies, 1 FMA (phi),
+# 3 FMA (a), and 9 for the reciprocal square root (v_rsq_f64, Newton steps to
+# full precision, a special-case test and two selects).
+SLOTS_PER_PAIR_FP64 = 3 + 3 + 3 + 1 + 3 + 9         # = 22
 # FP32 vector FMA without packed issue: 256 CUs x 64 lanes x 2 flop x 2.4 GHz
 FP32_VALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12  # = 78.6
 FP32_MFMA_PEAK_TFLOPS = 157.3                        # dense FP32 matrix (published)
@@ -77,6 +80,9 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain device copies of 1 GiB, the reference for scaling the "
                          "FETCH_SIZE / WRITE_SIZE counters, and print the copy and fill rates")
+    ap.add_argument("--peaks", action="store_true",
+                    help="only run the microbenchmarks of libp2p_peaks (FP32 FMA issue, v_rsq_f32 issue, "
+                         "FP32 matrix cores) and print the measured rates")
     return ap.parse_args()
 
 
@@ -105,6 +111,50 @@ def copy_calibration():
                       "fill_GBps_write": nb * 5 / ev[1].elapsed_time(ev[2]) / 1e6}), flush=True)
 
 
+PEAK_BLOCKS = 8192          # 256-thread workgroups per microbenchmark launch (4 per CU slot, 4 rounds)
+PEAK_ITERS = {"fma": 1000, "rsq": 1000, "mfma": 500}
+
+
+def peaks():
+    """Measured denominators beside the published peaks: an FP32 FMA loop
+    (lane-slots/s), a v_rsq_f32 loop (its cost in lane-slots is the FMA rate
+    over its rate) and a v_mfma_f32_16x16x4f32 loop (TFLOP/s), each launch
+    timed with HIP events on the stream it runs on (median of 5, after 2)."""
+    import ctypes
+    import torch
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2511_21535_amd", "libp2p_peaks.so"))
+    out = torch.empty(PEAK_BLOCKS * 256, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    res = {}
+    for name, fn in (("fma", lib.p2pk_valu_fma), ("rsq", lib.p2pk_valu_rsq), ("mfma", lib.p2pk_mfma_f32)):
+        fn.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p]
+        fn.restype = ctypes.c_int
+        it = PEAK_ITERS[name]
+        times = []
+        for rep in range(7):
+            ev = _events(2)
+            ev[0].record()
+            rc = fn(ctypes.c_void_p(out.data_ptr()), PEAK_BLOCKS, it, ctypes.c_void_p(stream))
+            ev[1].record()
+            if rc != 0:
+                raise RuntimeError(f"p2pk {name}: launch returned {rc}")
+            torch.cuda.synchronize()
+            if rep >= 2:
+                times.append(ev[0].elapsed_time(ev[1]) / 1e3)
+        t = float(np.median(times))
+        threads = PEAK_BLOCKS * 256
+        if name == "fma":
+            res["valu_fma_T_lane_slots_per_s"] = threads * it * 128 / t / 1e12
+        elif name == "rsq":
+            res["valu_rsq_T_per_s"] = threads * it * 64 / t / 1e12
+        else:
+            res["mfma_f32_TFLOPs"] = (threads // 64) * it * 32 * 2048 / t / 1e12
+        res[f"{name}_ms"] = t * 1e3
+    res["rsq_lane_slots"] = res["valu_fma_T_lane_slots_per_s"] / res["valu_rsq_T_per_s"]
+    res["published"] = {"valu_T_lane_slots_per_s": VALU_PEAK_SLOTS / 1e12, "mfma_f32_TFLOPs": FP32_MFMA_PEAK_TFLOPS}
+    print(json.dumps(res), flush=True)
+
+
 def pmc_traffic(kernel, workload, source):
     """HBM bytes per launch of `kernel` on `workload`, from the FETCH_SIZE and
     WRITE_SIZE counter summary kept in profiles/<kernel>_<workload>_hbm_counters.md,
@@ -123,6 +173,31 @@ def pmc_traffic(kernel, workload, source):
     return {"bytes": rec["fetch_kib"] * 1024 * rec["fetch_scale"] + rec["write_kib"] * 1024 * rec["write_scale"],
             "read_bytes": rec["fetch_kib"] * 1024 * rec["fetch_scale"],
             "write_bytes": rec["write_kib"] * 1024 * rec["write_scale"]}
+
+
+def measured_peaks():
+    """Measured denominators kept in profiles/measured_peaks.md (written from
+    `bench.py --peaks` and `--copy-calibration`): FP32 VALU lane-slots/s,
+    FP32 matrix TFLOP/s, HBM fill GB/s; None when the record is missing or
+    the microbenchmarks' source has changed since."""
+    path = os.path.join(ROOT, "profiles", "measured_peaks.md")
+    try:
+        rec = next(json.loads(l.split("record:", 1)[1]) for l in open(path) if l.startswith("record:"))
+        with open(os.path.join(ROOT, rec["source"]), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
+                return None
+    except (OSError, StopIteration, ValueError, KeyError):
+        return None
+    return rec
+
+
+def with_measured_peak(roof, key):
+    """Adds the measured peak of the same unit beside the published one."""
+    rec = measured_peaks()
+    if rec is not None:
+        roof["peak_measured"] = rec[key]
+        roof["frac_of_measured_peak"] = roof["achieved"] / rec[key]
+    return roof
 
 
 def _timed_steps(step, K, W):
@@ -280,14 +355,15 @@ def run_gravity(wname, args):
         "locality": {k: loc[k] for k in ("d_mean", "d_ratio", "v_ratio", "locality")},
         "speedup_model": speedup_model.evaluate({"compute": t_gat}, {"collect": t_res, "compute": t_red},
                                                 loc["d_ratio"], loc["v_ratio"], S * bpe, CACHE_BYTES),
-        "roofline": {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": peak,
-                     "unit": "T VALU lane-slots/s", "frac": achieved / peak,
-                     "traffic": traffic["bytes"] if traffic else None,
-                     "traffic_detail": dict(traffic, algorithmic_bytes=eval_bytes) if traffic else None,
-                     "algorithmic_per_pair": slots},
-        "restructure_roofline": {"bound": "hbm", "achieved": res_bytes / (t_res / K) / 1e9,
-                                 "peak": 8000.0, "unit": "GB/s",
-                                 "frac": res_bytes / (t_res / K) / 8e12, "bytes": res_bytes},
+        "roofline": with_measured_peak(
+            {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": peak,
+             "unit": "T VALU lane-slots/s", "frac": achieved / peak,
+             "traffic": traffic["bytes"] if traffic else None,
+             "traffic_detail": dict(traffic, algorithmic_bytes=eval_bytes) if traffic else None,
+             "algorithmic_per_pair": slots}, "valu_T_lane_slots_per_s"),
+        "restructure_roofline": with_measured_peak(
+            {"bound": "hbm", "achieved": res_bytes / (t_res / K) / 1e9, "peak": 8000.0, "unit": "GB/s",
+             "frac": res_bytes / (t_res / K) / 8e12, "bytes": res_bytes}, "hbm_fill_GBps"),
     })
     # per-interaction layout (records per near-list entry), timed after the
     # steps on the same tree and lists: restructure, then evaluation + update
@@ -534,7 +610,7 @@ def run_helmholtz(wname, args):
         "locality": {k: loc[k] for k in ("d_mean", "d_ratio", "v_ratio", "locality")},
         "speedup_model": speedup_model.evaluate({"compute": t_gat}, {"collect": t_res, "compute": t_red},
                                                 loc["d_ratio"], loc["v_ratio"], S * 8.0 * nrhs, CACHE_BYTES),
-        "roofline": roof,
+        "roofline": with_measured_peak(roof, "mfma_f32_TFLOPs") if roof["bound"] == "mfma" else roof,
     })
     if tile:
         # the best launch shape with 1, 2, 4 and 8 copies of the G blocks (ms per call)
@@ -594,6 +670,9 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.peaks:
+        peaks()
         return
     wl = args.workload
     if wl.startswith("helmholtz"):

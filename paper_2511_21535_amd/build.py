@@ -1,7 +1,8 @@
 """Build libp2p.so (gfx950) in-tree with hipcc.
 
 Every HIP source under csrc/ is compiled for gfx950 only, with packed FP32
-instructions disabled, then linked into paper_2511_21535_amd/libp2p.so.
+instructions disabled, then linked into paper_2511_21535_amd/libp2p.so; the
+microbenchmarks under peaks/ become libp2p_peaks.so.
 Run ``python -m paper_2511_21535_amd.build`` (or __graft_entry__.build()).
 """
 from __future__ import annotations
@@ -18,6 +19,9 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INC = os.path.join(ROOT, "include")
 OUT = os.path.join(PKG, "libp2p.so")
+# microbenchmarks for measured roofline denominators (not part of the operator)
+PEAKS_SRC = os.path.join(PKG, "peaks", "peaks.hip")
+PEAKS_OUT = os.path.join(PKG, "libp2p_peaks.so")
 BUILD = os.path.join(PKG, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -51,8 +55,13 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
     os.replace(tmp, OUT)
+    tmp = PEAKS_OUT + ".tmp"
+    r = subprocess.run([HIPCC, *FLAGS, "-shared", PEAKS_SRC, "-o", tmp], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed on {PEAKS_SRC}:\n{r.stderr}")
+    os.replace(tmp, PEAKS_OUT)
     if verbose:
-        print(f"built {OUT}")
+        print(f"built {OUT} and {PEAKS_OUT}")
     return OUT
 
 

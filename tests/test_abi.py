@@ -244,3 +244,25 @@ def test_remote_validation(lib):
                                      L.P2P_FP64, 1e-3, z, z, z, z, z, z, z, z, z, z, z,
                                      ctypes.c_void_p(0x100000), ctypes.byref(nb), None)
     assert st == L.P2P_EINVAL and "needs red" in L.last_error()
+
+
+def test_peaks_library_exports_and_rejects_bad_arguments():
+    """The microbenchmark library exports every p2pk_ symbol its header
+    declares, and refuses bad arguments on the host (no launch, no device)."""
+    import ctypes
+    src = open(os.path.join(ROOT, "include", "p2p_peaks.h")).read()
+    decl = sorted(set(re.findall(r"^\S.*?\b(p2pk_[a-z0-9_]+)\(", src, flags=re.M)))
+    assert decl == ["p2pk_mfma_f32", "p2pk_valu_fma", "p2pk_valu_rsq"]
+    path = os.path.join(ROOT, "paper_2511_21535_amd", "libp2p_peaks.so")
+    if not os.path.exists(path):
+        from paper_2511_21535_amd import build
+        build.build()
+    pk = ctypes.CDLL(path)
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: the checks come first
+    for name in decl:
+        fn = getattr(pk, name)
+        fn.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p]
+        fn.restype = ctypes.c_int
+        assert fn(None, 8, 1, None) == -1
+        assert fn(fake, 0, 1, None) == -1
+        assert fn(fake, 8, 0, None) == -1
