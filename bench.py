@@ -213,6 +213,29 @@ def _timed_steps(step, K, W):
     return wall, ms.sum(0) / 1e3        # seconds summed over the K steps, per sub-step
 
 
+B2B_CALLS = 100
+
+
+def back_to_back(fns, calls=B2B_CALLS):
+    """Mean microseconds per call of each function over `calls` calls issued
+    back to back between two events (the queue stays full, so the launch
+    gaps of a single timed call are hidden); for the microsecond-scale
+    workloads."""
+    import torch
+    out = {}
+    for name, fn in fns.items():
+        fn()
+        torch.cuda.synchronize()
+        ev = _events(2)
+        ev[0].record()
+        for _ in range(calls):
+            fn()
+        ev[1].record()
+        torch.cuda.synchronize()
+        out[name] = ev[0].elapsed_time(ev[1]) * 1e3 / calls
+    return out
+
+
 def _events(k):
     import torch
     return [torch.cuda.Event(enable_timing=True) for _ in range(k)]
@@ -253,10 +276,34 @@ def cpu_baseline_gravity(x, y, z, m, w, n_leaves_sample, min_seconds=10.0, max_r
         oracle.gravity_leaves(x, y, z, m, w["eps"], ot, sel, ss, si)
         times.append(time.perf_counter() - t0)
     t_eval = float(np.median(times))
-    return {"value": pairs / t_eval, "unit": "pair-interactions/s", "cores": oracle.threads(),
-            "kind": "oracle",
+    cores = oracle.threads()
+    # one thread, on the first leaves of the same selection (about 0.2 s)
+    k1 = min(5000, len(sel))
+    s1, i1 = ss[:k1 + 1], si[:ss[k1]]
+    pairs1 = int((occ[sel[:k1]] * seg[:k1]).sum() - occ[sel[:k1]].sum())
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.gravity_leaves(x, y, z, m, w["eps"], ot, sel[:k1], s1, i1)
+        t1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(cores)
+    return {"value": pairs / t_eval, "unit": "pair-interactions/s", "cores": cores,
+            "kind": "oracle", **host_cpu(),
+            "value_1_thread": pairs1 / t1,
             "sample": f"{what}, {pairs} pairs, FP64 plain loops, median of {len(times)} evaluations "
-                      f"of {t_eval:.2f} s (oracle tree build {t_tree:.2f} s and near lists not counted)"}
+                      f"of {t_eval:.2f} s (oracle tree build {t_tree:.2f} s and near lists not counted); "
+                      f"1 thread: the first {k1} of those leaves, {pairs1} pairs, {t1:.2f} s"}
+
+
+def host_cpu():
+    """The host's processor model and logical CPU count."""
+    model = None
+    try:
+        model = next(l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count()}
 
 
 def cpu_baseline_helmholtz(sides, q, n_targets, unit):
@@ -279,7 +326,7 @@ def cpu_baseline_helmholtz(sides, q, n_targets, unit):
     oracle.helmholtz(sides, q, targets=tg)
     dt = time.perf_counter() - t0
     nrhs = 1 if q.ndim == 1 else q.shape[1]
-    return {"value": pairs * nrhs / dt, "unit": unit, "cores": oracle.threads(), "kind": "oracle",
+    return {"value": pairs * nrhs / dt, "unit": unit, "cores": oracle.threads(), "kind": "oracle", **host_cpu(),
             "sample": f"{len(tg)} of {n} targets drawn uniformly (seed 123), {pairs} pairs x {nrhs} "
                       f"RHS, complex128, {dt:.2f} s"}
 
@@ -365,6 +412,14 @@ def run_gravity(wname, args):
             {"bound": "hbm", "achieved": res_bytes / (t_res / K) / 1e9, "peak": 8000.0, "unit": "GB/s",
              "frac": res_bytes / (t_res / K) / 8e12, "bytes": res_bytes}, "hbm_fill_GBps"),
     })
+    if t_red / K < 2e-4:
+        b2b = back_to_back({
+            "restructure_us": lambda: api.restructure_gravity(tree, nbrs, gx, gy, gz, gm, prec=prec, out=red),
+            "eval_redundant_us": lambda: api.gravity(tree, nbrs, eps, layout="redundant", prec=prec, red=red,
+                                                     out=outs),
+            "eval_gather_us": lambda: api.gravity(tree, nbrs, eps, x=gx, y=gy, z=gz, m=gm, layout="gather",
+                                                  prec=prec, out=outs)})
+        line["back_to_back"] = dict(b2b, calls=B2B_CALLS)
     # per-interaction layout (records per near-list entry), timed after the
     # steps on the same tree and lists: restructure, then evaluation + update
     inter = api.restructure_interactions(tree, nbrs, gx, gy, gz, gm, prec=prec)
@@ -612,6 +667,16 @@ def run_helmholtz(wname, args):
                                                 loc["d_ratio"], loc["v_ratio"], S * 8.0 * nrhs, CACHE_BYTES),
         "roofline": with_measured_peak(roof, "mfma_f32_TFLOPs") if roof["bound"] == "mfma" else roof,
     })
+    if t_red / K < 2e-4:
+        b2b = back_to_back({
+            "restructure_us": lambda: api.restructure(tree, nbrs, [gq], prec="fp32", nrhs=nrhs, out=red),
+            "eval_redundant_us": lambda: api.helmholtz(tree, nbrs, None, layout="redundant", prec="fp32", red=red,
+                                                       nrhs=nrhs, tile=tile, out=out),
+            "eval_gather_us": lambda: api.helmholtz(tree, nbrs, gq, layout="gather", prec="fp32", tile=tile,
+                                                    out=out)})
+        line["back_to_back"] = dict(b2b, calls=B2B_CALLS)
+        if kern == "k_helm_mfma_cols_red":
+            line["roofline"]["achieved_back_to_back"] = flops / (b2b["eval_redundant_us"] * 1e-6) / 1e12
     if tile:
         # the best launch shape with 1, 2, 4 and 8 copies of the G blocks (ms per call)
         line["g_block_copies_ms"] = {json.loads(k)[3]: v for k, v in tune_ms.items()

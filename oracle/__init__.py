@@ -58,6 +58,8 @@ F64 = ctypes.c_double
 def _declare(lib):
     lib.orc_threads.restype = ctypes.c_int
     lib.orc_threads.argtypes = []
+    lib.orc_set_threads.restype = None
+    lib.orc_set_threads.argtypes = [ctypes.c_int]
     lib.orc_morton3.restype = ctypes.c_uint64
     lib.orc_morton3.argtypes = [ctypes.c_uint32] * 3 + [ctypes.c_int]
     lib.orc_particle_keys.restype = I64
@@ -112,6 +114,11 @@ def _c(a, dtype):
 def threads() -> int:
     """OpenMP threads the oracle's parallel loops use."""
     return int(_load().orc_threads())
+
+
+def set_threads(n: int) -> None:
+    """Sets the OpenMP threads of the oracle's parallel loops."""
+    _load().orc_set_threads(int(n))
 
 
 # ---------------------------------------------------------------------------

@@ -31,6 +31,16 @@
 #define ORC_DEPTH_BITS 20           /* particle keys: 20 bits per axis */
 #define ORC_PI 3.14159265358979323846
 
+/* Sets the number of OpenMP threads of the parallel loops below (n >= 1). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* Number of OpenMP threads the parallel loops below use. */
 int orc_threads(void)
 {

@@ -152,6 +152,18 @@ __device__ inline Row4d shifted(Row4d v, int c) {
 
 __device__ inline float rsq_f32(float x) { return __builtin_amdgcn_rsqf(x); }
 
+// Lane split of a workgroup for tc targets (1 <= tc <= 256): G = 256 / tc
+// groups, lane tid = t + g tc, without integer division.  For 0 <= v <= 256,
+// (v + 1/2) / tc lies at least 1/(2 tc) from an integer, far beyond the error
+// of the approximate reciprocal and one rounding (under 5e-5 / tc), so
+// truncation gives floor(v / tc) exactly.
+__device__ inline void lane_split(int tc, int &G, int &t, int &g) {
+    const float rtc = __builtin_amdgcn_rcpf(static_cast<float>(tc));
+    G = static_cast<int>((static_cast<float>(kGBlock) + 0.5f) * rtc);
+    g = static_cast<int>((static_cast<float>(threadIdx.x) + 0.5f) * rtc);
+    t = static_cast<int>(threadIdx.x) - g * tc;
+}
+
 // Centre of a particle leaf (exact in double: integers below 2^21 times 2^-20).
 __device__ inline void leaf_centre(uint64_t key, int level, double c[3]) {
     const double half = 0.5 * static_cast<double>(1u << (20 - level));
@@ -200,8 +212,8 @@ __device__ __forceinline__ void gravity_body(const GravityArgs &a) {
 
     for (int tc0 = 0; tc0 < ntar; tc0 += kGBlock) {
         const int tc = min(kGBlock, ntar - tc0);
-        const int G = kGBlock / tc;
-        const int t = threadIdx.x % tc, g = threadIdx.x / tc;
+        int G, t, g;
+        lane_split(tc, G, t, g);
         const bool active = g < G;
         // target position (relative to the leaf centre for FP32_MIXED) and mass
         Src tv;
@@ -403,8 +415,8 @@ __global__ __launch_bounds__(kGBlock) void k_gravity_adjoint(GravityAdjointArgs 
     const double eps2 = a.eps2;
     for (int tc0 = 0; tc0 < ntar; tc0 += kGBlock) {
         const int tc = min(kGBlock, ntar - tc0);
-        const int G = kGBlock / tc;
-        const int t = threadIdx.x % tc, g = threadIdx.x / tc;
+        int G, t, g;
+        lane_split(tc, G, t, g);
         const bool active = g < G;
         const int64_t tr = t0 + tc0 + t;
         const Row4d pj = a.s4[tr], gj = a.g4[tr];
