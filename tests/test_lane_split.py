@@ -1,0 +1,19 @@
+"""The gravity kernels split a 256-lane workgroup over tc targets without
+integer division: G = trunc((256 + 1/2) r), g = trunc((tid + 1/2) r) with
+r an FP32 reciprocal of tc accurate to one ulp.  Emulated here in FP32 with
+the reciprocal off by up to two ulps either way: every quotient is exact."""
+import numpy as np
+
+
+def test_float_lane_split_is_exact():
+    v = np.arange(0, 257, dtype=np.float32)
+    want_all = np.arange(0, 257)
+    for tc in range(1, 257):
+        r0 = np.float32(1.0) / np.float32(tc)
+        for ulps in (-2, -1, 0, 1, 2):
+            r = r0
+            for _ in range(abs(ulps)):
+                r = np.nextafter(r, np.float32(np.inf if ulps > 0 else 0), dtype=np.float32)
+            q = ((v + np.float32(0.5)) * r).astype(np.float32)
+            got = q.astype(np.int64)                      # truncation, as the kernel's cast
+            np.testing.assert_array_equal(got, want_all // tc)
