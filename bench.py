@@ -216,6 +216,27 @@ def _timed_steps(step, K, W):
 B2B_CALLS = 100
 
 
+def graph_leg(res_fn, eval_fn, work, K, W):
+    """The restructure and the redundant evaluation, each recorded once into a
+    HIP graph (api.Graph) and replayed: the same kernels on the same arrays,
+    without the host launch gaps between them; timed like the steps."""
+    from paper_2511_21535_amd import api
+    g_res, g_eval = api.Graph(res_fn), api.Graph(eval_fn)
+
+    def step():
+        e = _events(3)
+        e[0].record()
+        g_res.replay()
+        e[1].record()
+        g_eval.replay()
+        e[2].record()
+        return e
+
+    _, (t_res, t_red) = _timed_steps(step, K, W)
+    return {"ms": {"restructure": t_res / K * 1e3, "eval_redundant": t_red / K * 1e3},
+            "rate_incl_restructure": work * K / (t_res + t_red), "rate_excl_restructure": work * K / t_red}
+
+
 def back_to_back(fns, calls=B2B_CALLS):
     """Mean microseconds per call of each function over `calls` calls issued
     back to back between two events (the queue stays full, so the launch
@@ -412,6 +433,9 @@ def run_gravity(wname, args):
             {"bound": "hbm", "achieved": res_bytes / (t_res / K) / 1e9, "peak": 8000.0, "unit": "GB/s",
              "frac": res_bytes / (t_res / K) / 8e12, "bytes": res_bytes}, "hbm_fill_GBps"),
     })
+    line["graph"] = graph_leg(
+        lambda: api.restructure_gravity(tree, nbrs, gx, gy, gz, gm, prec=prec, out=red),
+        lambda: api.gravity(tree, nbrs, eps, layout="redundant", prec=prec, red=red, out=outs), pairs, K, args.warmup)
     if t_red / K < 2e-4:
         b2b = back_to_back({
             "restructure_us": lambda: api.restructure_gravity(tree, nbrs, gx, gy, gz, gm, prec=prec, out=red),
@@ -667,6 +691,12 @@ def run_helmholtz(wname, args):
                                                 loc["d_ratio"], loc["v_ratio"], S * 8.0 * nrhs, CACHE_BYTES),
         "roofline": with_measured_peak(roof, "mfma_f32_TFLOPs") if roof["bound"] == "mfma" else roof,
     })
+    if kern == "k_helm_mfma_cols_red" and len(sides) <= 8:
+        # parameters in the kernel arguments: the evaluation can be captured
+        line["graph"] = graph_leg(
+            lambda: api.restructure(tree, nbrs, [gq], prec="fp32", nrhs=nrhs, out=red),
+            lambda: api.helmholtz(tree, nbrs, None, layout="redundant", prec="fp32", red=red, nrhs=nrhs,
+                                  tile=tile, out=out), work, K, args.warmup)
     if t_red / K < 2e-4:
         b2b = back_to_back({
             "restructure_us": lambda: api.restructure(tree, nbrs, [gq], prec="fp32", nrhs=nrhs, out=red),

@@ -35,6 +35,15 @@
  *  - p2p_last_error() describes the last failure on the calling thread.
  *  - Calls on different streams may run concurrently; calls that share a
  *    workspace buffer must not overlap.
+ *  - HIP graphs: every evaluation, the adjoint and the restructures over near
+ *    lists that carry their size only enqueue kernels and may be captured
+ *    into a graph and replayed (with the same arrays and workspace).  Calls
+ *    that read counts back, synchronise or copy from host memory -- building
+ *    trees and near lists, p2p_locality, restructures over lists without
+ *    their size, and Helmholtz evaluations that upload their parameters (more
+ *    than 8 grid instances or G tables, several right-hand sides, FP64) --
+ *    return P2P_EUNSUPPORTED while `stream` is capturing, before queueing
+ *    anything.
  *
  * Readings of the paper (it gives no kernel formulas; these are the ones this
  * library adopts):

@@ -498,3 +498,29 @@ def locality(tree: Tree, nbrs: Nbrs, red: Optional[Redundant] = None, bytes_per_
     st, _ = _call(call, dev)
     L.check(st)
     return {f: getattr(out, f) for f, _ in L.p2p_locality_t._fields_}
+
+
+class Graph:
+    """Library calls recorded once into a HIP graph (through
+    torch.cuda.CUDAGraph) and replayed with one launch each time, which
+    removes the host launch gaps between the short kernels of a step.  Every
+    replay runs the kernels recorded at capture on the same arrays: the tree,
+    lists, layouts, inputs and outputs the calls used must stay alive and in
+    place, and new input values are written into those arrays.  Workspaces
+    taken during capture stay reserved for the graph.  Calls that read back,
+    synchronise or copy from host memory raise P2PError (P2P_EUNSUPPORTED)
+    during capture."""
+
+    def __init__(self, fn, warmup: int = 1):
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            for _ in range(warmup):
+                fn()
+        torch.cuda.current_stream().wait_stream(side)
+        self._graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self._graph):
+            fn()
+
+    def replay(self) -> None:
+        self._graph.replay()

@@ -43,6 +43,18 @@ bool ws_query(void *ws, size_t *ws_bytes, const Arena &need, p2p_status *st) {
     return false;
 }
 
+// Steps that read counts back, synchronise or copy from host memory cannot be
+// recorded into a HIP graph (a recorded host copy would read freed memory at
+// replay): they are refused while `s` is capturing, before any work is queued.
+p2p_status no_capture(hipStream_t s, const char *what) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess) return fail(P2P_EHIP, "hipStreamIsCapturing failed");
+    if (cs != hipStreamCaptureStatusNone)
+        return fail(P2P_EUNSUPPORTED, std::string(what) + " reads back, synchronises or copies from host memory: "
+                                                          "it cannot be captured into a graph");
+    return P2P_OK;
+}
+
 int grid_bits_of(const p2p_grid *grids, int32_t n_grids) {
     int mx = 4;
     for (int32_t g = 0; g < n_grids; ++g) mx = grids[g].n_side > mx ? grids[g].n_side : mx;
@@ -175,6 +187,7 @@ extern "C" p2p_status p2p_build_tree(const double *x, const double *y, const dou
         return fail(P2P_EINVAL, "tree arrays must not be NULL");
     if (!tree->leaf_start) return fail(P2P_EINVAL, "tree->leaf_start must not be NULL");
     hipStream_t s = as_stream(stream);
+    P2P_TRY(no_capture(s, "p2p_build_tree"));
 
     tree->kind = particles ? P2P_TREE_PARTICLES : P2P_TREE_GRIDS;
     tree->key_bits = key_bits;
@@ -267,6 +280,7 @@ p2p_status neighbors_common(const p2p_tree *tree, const p2p_tree *src, p2p_nbrs 
     p2p_status st;
     if (ws_query(ws, ws_bytes, ar, &st)) return st;
     if (!nbrs->nbr_start) return fail(P2P_EINVAL, "nbrs->nbr_start must not be NULL");
+    P2P_TRY(no_capture(s, "building near lists"));
     const int inst_shift = 3 * src->key_bits;
     const NbrTargets tg{tree->leaf_key, tree->leaf_level, L};
     const NbrTargets *tgp = remote ? &tg : nullptr;
@@ -362,6 +376,7 @@ p2p_status restructure_common(const p2p_tree *tree, const p2p_tree *srct, const 
     // S: carried by the near lists, else counted here and read back
     int64_t S = nbrs->red_entries;
     if (S < 0) {
+        P2P_TRY(no_capture(s, "a restructure over near lists without their size"));
         P2P_TRY(launch_seg_lengths(srct->leaf_start, nbrs->nbr_start, nbrs->nbr_idx, shifts(nbrs), L, seg_len,
                                    count_self, !remote, s));
         P2P_TRY((exclusive_scan<int32_t, int64_t>(seg_len, count_start, L, scan_tmp, s)));
@@ -469,6 +484,7 @@ extern "C" p2p_status p2p_restructure_interactions(const p2p_tree *tree, const p
     if (!out->rec_start) return fail(P2P_EINVAL, "out->rec_start must not be NULL");
     if (out->cap < 0) return fail(P2P_EINVAL, "out->cap < 0");
     hipStream_t s = as_stream(stream);
+    if (!known) P2P_TRY(no_capture(s, "an interaction restructure over near lists without their size"));
     P2P_TRY(launch_scatter4(src[0], src[1], src[2], src[3], tree->iperm, n, s4, s));
     // rows: E headers plus, per record, its targets and sources; with the
     // symmetric lists of p2p_build_neighbors both sums are S
@@ -781,6 +797,10 @@ p2p_status helmholtz_common(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2
     } else if (n > 0 && !q) {
         return fail(P2P_EINVAL, "q must not be NULL");
     }
+    // a single-RHS call on a grid of few instances takes its parameters in the
+    // kernel arguments; every other call uploads them
+    const bool inline_params = cols && n_grids <= kInlineGrids && n_tables <= kInlineGrids;
+    if (!inline_params) P2P_TRY(no_capture(s, "a Helmholtz evaluation that uploads its parameters"));
     if (!redundant) {
         if (fp64)
             P2P_TRY(launch_permute_rows<double2>(static_cast<const double2 *>(q), tree->perm, n, nrhs,
@@ -789,10 +809,8 @@ p2p_status helmholtz_common(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2
             P2P_TRY(launch_permute_rows<float2>(static_cast<const float2 *>(q), tree->perm, n, nrhs,
                                                 reinterpret_cast<float2 *>(sorted), s));
     }
-    // a single-RHS call on a grid of few instances takes its parameters in the
-    // kernel arguments; every other call uploads them
     HelmInline inl{};
-    if (cols && n_grids <= kInlineGrids && n_tables <= kInlineGrids) {
+    if (inline_params) {
         inl.n_grids = n_grids;
         inl.n_tables = n_tables;
         int32_t tf = 0, lf = 0;
@@ -967,6 +985,7 @@ extern "C" p2p_status p2p_locality(const p2p_tree *tree, const p2p_nbrs *nbrs,
     if (ws_query(ws, ws_bytes, ar, &st)) return st;
     if (!out) return fail(P2P_EINVAL, "out is NULL");
     hipStream_t s = as_stream(stream);
+    P2P_TRY(no_capture(s, "p2p_locality"));
     const int64_t L = tree->n_leaves;
     P2P_HIP(hipMemsetAsync(sums, 0, 3 * sizeof(unsigned long long), s));
     P2P_TRY(launch_locality_stats(tree->leaf_start, nbrs->nbr_start, nbrs->nbr_idx, L, sums, s));
