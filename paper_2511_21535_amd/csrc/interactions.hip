@@ -10,6 +10,8 @@
 // target's rows over the records of its leaf (the update).  Compared with the
 // box grain, the layout stores every target E2 times more and every result
 // E2 times, in exchange for independent, fine-grained work items.
+#include <type_traits>
+
 #include "p2p_internal.h"
 
 namespace p2p {
@@ -132,12 +134,14 @@ __global__ __launch_bounds__(256) void k_copy_records(
 constexpr int kEvalWaves = 4;
 constexpr int kRecFlush = 32;
 
-// One wavefront per record.  Targets in chunks of 64; with tc targets in a
-// chunk, lane (t, g) = (lane % tc, lane / tc) takes target t and sources
-// g, g + G, ... (G = 64 / tc) straight from the record (coalesced across the
-// groups), FP32-mixed pair terms summed at most 32 at a time in float into
-// double; the G partials meet in LDS.  Record (A, A) holds every target once
-// as its own source at d = 0; that self term is added back as in the box
+// One wavefront per record.  The record's sources are staged through LDS 64
+// rows at a time with one coalesced load per lane (a load per pair straight
+// from the record left every wave waiting out a memory round trip per pair
+// group).  Targets in chunks of 64; with tc targets in a chunk, lane (t, g) =
+// (lane % tc, lane / tc) takes target t and staged sources g, g + G, ...
+// (G = 64 / tc), FP32-mixed pair terms summed at most 32 at a time in float
+// into double; the G partials meet in LDS.  Record (A, A) holds every target
+// once as its own source at d = 0; that self term is added back as in the box
 // kernels.  With image codes only the unshifted record (A, A) is the self
 // record: a point meets its own image elsewhere at a nonzero distance.
 template <bool MIXED, bool EPS0>
@@ -145,7 +149,9 @@ __global__ __launch_bounds__(64 * kEvalWaves) void k_eval_records(
     const int64_t *__restrict__ rec_start, const Row4d *__restrict__ r8, const float4 *__restrict__ r4,
     const int8_t *__restrict__ nbr_shift, int64_t E, const int64_t *__restrict__ res_start, double eps2,
     Row4d *__restrict__ res) {
+    using Src = typename std::conditional<MIXED, float4, Row4d>::type;
     __shared__ double s_red[kEvalWaves][4][64];
+    __shared__ Src s_src[kEvalWaves][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t e = static_cast<int64_t>(blockIdx.x) * kEvalWaves + w;
     if (e >= E) return;
@@ -178,49 +184,63 @@ __global__ __launch_bounds__(64 * kEvalWaves) void k_eval_records(
         const bool active = g < G;
         double p = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
         double tm = 0.0;
-        if (active) {
-            if constexpr (MIXED) {
-                const float4 tv = r4[t0 + tc0 + t];
-                tm = tv.w;
-                int j = g;
-                while (j < occB) {
-                    float pf = 0.f, xf = 0.f, yf = 0.f, zf = 0.f;
-                    for (int k = 0; k < kRecFlush && j < occB; ++k, j += G) {
-                        const float4 v = r4[s0 + j];
-                        const float dx = tv.x - v.x, dy = tv.y - v.y, dz = tv.z - v.z;
-                        const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2f)));
-                        float wv = rsq_f32(r2);
-                        if constexpr (EPS0) wv = (r2 > 0.f) ? wv : 0.f;
-                        const float mw = v.w * wv;
-                        const float mw3 = mw * (wv * wv);
-                        pf -= mw;
-                        xf = fmaf(-mw3, dx, xf);
-                        yf = fmaf(-mw3, dy, yf);
-                        zf = fmaf(-mw3, dz, zf);
+        Src tv;
+        if constexpr (MIXED)
+            tv = r4[t0 + tc0 + t];
+        else
+            tv = r8[t0 + tc0 + t];
+        tm = tv.w;
+        for (int b0 = 0; b0 < occB; b0 += 64) {
+            const int nb = min(64, occB - b0);
+            if (lane < nb) {
+                if constexpr (MIXED)
+                    s_src[w][lane] = r4[s0 + b0 + lane];
+                else
+                    s_src[w][lane] = r8[s0 + b0 + lane];
+            }
+            wave_sync();
+            if (active) {
+                if constexpr (MIXED) {
+                    int j = g;
+                    while (j < nb) {
+                        float pf = 0.f, xf = 0.f, yf = 0.f, zf = 0.f;
+                        for (int k = 0; k < kRecFlush && j < nb; ++k, j += G) {
+                            const float4 v = s_src[w][j];
+                            const float dx = tv.x - v.x, dy = tv.y - v.y, dz = tv.z - v.z;
+                            const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2f)));
+                            float wv = rsq_f32(r2);
+                            if constexpr (EPS0) wv = (r2 > 0.f) ? wv : 0.f;
+                            const float mw = v.w * wv;
+                            const float mw3 = mw * (wv * wv);
+                            pf -= mw;
+                            xf = fmaf(-mw3, dx, xf);
+                            yf = fmaf(-mw3, dy, yf);
+                            zf = fmaf(-mw3, dz, zf);
+                        }
+                        p += pf;
+                        fx += xf;
+                        fy += yf;
+                        fz += zf;
                     }
-                    p += pf;
-                    fx += xf;
-                    fy += yf;
-                    fz += zf;
-                }
-            } else {
-                const Row4d tv = r8[t0 + tc0 + t];
-                tm = tv.w;
-                for (int j = g; j < occB; j += G) {
-                    const Row4d v = r8[s0 + j];
-                    const double dx = tv.x - v.x, dy = tv.y - v.y, dz = tv.z - v.z;
-                    const double r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
-                    double wv = rsqrt(r2);
-                    if constexpr (EPS0) wv = (r2 > 0.0) ? wv : 0.0;
-                    const double mw = v.w * wv;
-                    const double mw3 = mw * (wv * wv);
-                    p -= mw;
-                    fx = fma(-mw3, dx, fx);
-                    fy = fma(-mw3, dy, fy);
-                    fz = fma(-mw3, dz, fz);
+                } else {
+                    for (int j = g; j < nb; j += G) {
+                        const Row4d v = s_src[w][j];
+                        const double dx = tv.x - v.x, dy = tv.y - v.y, dz = tv.z - v.z;
+                        const double r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
+                        double wv = rsqrt(r2);
+                        if constexpr (EPS0) wv = (r2 > 0.0) ? wv : 0.0;
+                        const double mw = v.w * wv;
+                        const double mw3 = mw * (wv * wv);
+                        p -= mw;
+                        fx = fma(-mw3, dx, fx);
+                        fy = fma(-mw3, dy, fy);
+                        fz = fma(-mw3, dz, fz);
+                    }
                 }
             }
+            wave_sync();   // every lane has read this chunk before the next overwrites it
         }
+        if (!active) p = fx = fy = fz = 0.0;
         s_red[w][0][lane] = p;
         s_red[w][1][lane] = fx;
         s_red[w][2][lane] = fy;
