@@ -275,25 +275,47 @@ __global__ __launch_bounds__(256) void k_reduce_records(const int32_t *__restric
                                                         const Row4d *__restrict__ res,
                                                         double *__restrict__ phi, double *__restrict__ ax,
                                                         double *__restrict__ ay, double *__restrict__ az) {
-    const int lane = threadIdx.x & 63;
-    const int64_t A = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    // the result offsets of up to 64 records, staged once per chunk so that
+    // the row loads do not each wait for their offset first
+    __shared__ int64_t s_off[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t A = static_cast<int64_t>(blockIdx.x) * 4 + w;
     if (A >= L) return;
     const int32_t a0 = leaf_start[A], occA = leaf_start[A + 1] - a0;
     const int64_t e0 = nbr_start[A], e1 = nbr_start[A + 1];
-    for (int t = lane; t < occA; t += 64) {
+    for (int t0 = 0; t0 < occA; t0 += 64) {
+        const int t = t0 + lane;
+        const bool act = t < occA;
         double sp = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
-        for (int64_t e = e0; e < e1; ++e) {
-            const Row4d v = res[res_start[e] + t];
-            sp += v.x;
-            sx += v.y;
-            sy += v.z;
-            sz += v.w;
+        for (int64_t c0 = e0; c0 < e1; c0 += 64) {
+            const int nc = static_cast<int>(min<int64_t>(64, e1 - c0));
+            if (lane < nc) s_off[w][lane] = res_start[c0 + lane];
+            wave_sync();
+            if (act) {
+                // four rows in flight, added in list order
+                int k = 0;
+                for (; k + 4 <= nc; k += 4) {
+                    const Row4d v0 = res[s_off[w][k] + t], v1 = res[s_off[w][k + 1] + t];
+                    const Row4d v2 = res[s_off[w][k + 2] + t], v3 = res[s_off[w][k + 3] + t];
+                    sp += v0.x; sx += v0.y; sy += v0.z; sz += v0.w;
+                    sp += v1.x; sx += v1.y; sy += v1.z; sz += v1.w;
+                    sp += v2.x; sx += v2.y; sy += v2.z; sz += v2.w;
+                    sp += v3.x; sx += v3.y; sy += v3.z; sz += v3.w;
+                }
+                for (; k < nc; ++k) {
+                    const Row4d v = res[s_off[w][k] + t];
+                    sp += v.x; sx += v.y; sy += v.z; sz += v.w;
+                }
+            }
+            wave_sync();   // every lane has read the offsets before the next chunk overwrites them
         }
-        const int64_t i = perm[a0 + t];
-        phi[i] = sp;
-        ax[i] = sx;
-        ay[i] = sy;
-        az[i] = sz;
+        if (act) {
+            const int64_t i = perm[a0 + t];
+            phi[i] = sp;
+            ax[i] = sx;
+            ay[i] = sy;
+            az[i] = sz;
+        }
     }
 }
 
