@@ -403,10 +403,18 @@ def test_edge_cases():
     P = np.array([[0.5, 0.5, 1.0]])
     with pytest.raises(Exception, match="EDOMAIN"):
         api.Tree.build_particles(*[_t(P[:, d].copy()) for d in range(3)])
-    # empty input
+    # empty input: no leaves, empty lists and layouts, empty outputs
     e = _t(np.zeros(0))
     gt = api.Tree.build_particles(e, e, e)
     assert gt.n_leaves == 0
+    gn = gt.neighbors()
+    assert gn.count == 0 and gn.red_entries == 0 and _n(gn.nbr_start).tolist() == [0]
+    for prec in ("fp64", "fp32"):
+        red = api.restructure_gravity(gt, gn, e, e, e, e, prec=prec)
+        assert red.count == 0 and _n(red.red_start).tolist() == [0]
+        for layout in ("gather", "redundant"):
+            out = api.gravity(gt, gn, 1e-3, e, e, e, e, layout=layout, prec=prec, red=red)
+            assert all(o.numel() == 0 for o in out)
 
 
 def test_locality_matches_oracle():
