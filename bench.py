@@ -724,6 +724,8 @@ def run_adjoint(wname, args):
     from paper_2511_21535_amd import workloads as W
     dev = torch.device("cuda:0")
     w = W.WORKLOADS[wname]
+    if w["kind"] == "helmholtz":
+        return run_adjoint_helmholtz(wname, args)
     x, y, z, m = W.particles(wname)
     n = len(x)
     g = [torch.as_tensor(W.normal_like(n, seed=w["seed"] + 10 * k), device=dev) for k in range(1, 5)]
@@ -747,6 +749,42 @@ def run_adjoint(wname, args):
     line = _base("near-field pair-interactions/s, forward + adjoint (gather, FP64)", value,
                  "pair-interactions/s", K, args.warmup, wall, "f64",
                  {"workload": wname, "n": n, "leaves": tree.n_leaves, "pairs": pairs,
+                  "parallelism": "single GPU"})
+    line["ms"] = {"forward": t_fwd / K * 1e3, "adjoint": t_adj / K * 1e3}
+    return line
+
+
+def run_adjoint_helmholtz(wname, args):
+    """Forward and adjoint (A^T g, the transpose action; A is symmetric by
+    reciprocity) of the grid operator, FP64 gather, one right-hand side."""
+    import torch
+    from paper_2511_21535_amd import api
+    from paper_2511_21535_amd import workloads as W
+    dev = torch.device("cuda:0")
+    w = W.WORKLOADS[wname]
+    n_side = w["n_side"]
+    grids = [api.Grid(n_side, *W.grid_geometry(n_side))]
+    tree = api.Tree.build_grids(grids, device=dev)
+    nbrs = tree.neighbors()
+    pairs = int(api.locality(tree, nbrs)["pairs"])
+    q = torch.as_tensor(W.grid_rhs(tree.n, 1, seed=w["seed"])[:, 0].astype(np.complex128), device=dev)
+    g = torch.as_tensor(W.grid_rhs(tree.n, 1, seed=w["seed"] + 10)[:, 0].astype(np.complex128), device=dev)
+
+    def step():
+        e = _events(3)
+        e[0].record()
+        api.helmholtz(tree, nbrs, q, prec="fp64")
+        e[1].record()
+        api.helmholtz_adjoint(tree, nbrs, g, prec="fp64")
+        e[2].record()
+        return e
+
+    K = args.steps
+    wall, (t_fwd, t_adj) = _timed_steps(step, K, args.warmup)
+    value = pairs * K / (t_fwd + t_adj)
+    line = _base("near-field pair-interactions/s, forward + adjoint (gather, FP64)", value,
+                 "pair-interactions/s", K, args.warmup, wall, "f64 (complex128)",
+                 {"workload": wname, "n": tree.n, "boxes": tree.n_leaves, "pairs": pairs,
                   "parallelism": "single GPU"})
     line["ms"] = {"forward": t_fwd / K * 1e3, "adjoint": t_adj / K * 1e3}
     return line

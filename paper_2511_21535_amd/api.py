@@ -34,6 +34,38 @@ def _require_device(t: torch.Tensor, name: str, dtype=None):
     return t
 
 
+def _vec(t: Optional[torch.Tensor], name: str, n: int, dtype=torch.float64, optional: bool = False):
+    """A per-point array the kernels index up to n: a contiguous GPU tensor of
+    that dtype with exactly n elements (n x nrhs for right-hand sides); a host
+    pointer or a short array would reach the kernels unchecked."""
+    if t is None:
+        if optional:
+            return None
+        raise ValueError(f"{name} is required")
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor")
+    if t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    return t
+
+
+def _outs(out, n: int, dev):
+    """The four float64 result arrays: allocated, or the caller's, checked."""
+    if out is None:
+        return [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(4)]
+    if len(out) != 4:
+        raise ValueError("out must hold four arrays (phi, ax, ay, az)")
+    for nm, o in zip(("phi", "ax", "ay", "az"), out):
+        _vec(o, nm, n)
+    return out
+
+
 def _ptr(t: Optional[torch.Tensor]):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
@@ -256,6 +288,15 @@ def restructure(tree: Tree, nbrs: Nbrs, src: Sequence[Optional[torch.Tensor]], p
     p = PREC[prec]
     dev = tree.leaf_start.device
     kind = L.P2P_KIND_GRAVITY if tree.kind == L.P2P_TREE_PARTICLES else L.P2P_KIND_HELMHOLTZ
+    if kind == L.P2P_KIND_GRAVITY:
+        if len(src) != 4:
+            raise ValueError("gravity sources are x, y, z, m")
+        for nm, t in zip("xyzm", src):
+            _vec(t, nm, tree.n)
+    else:
+        if len(src) != 1:
+            raise ValueError("Helmholtz sources are one array q")
+        _vec(src[0], "q", tree.n * nrhs, torch.complex64 if p == L.P2P_FP32_MIXED else torch.complex128)
     if out is None:
         if S is None:
             S = redundant_entries(tree, nbrs)
@@ -284,6 +325,8 @@ def restructure_remote(tree: Tree, src_tree: Tree, nbrs: Nbrs, sx, sy, sz, sm, p
     leaves of `tree`, over remote lists from build_neighbors(src_tree=...)."""
     p = PREC[prec]
     dev = tree.leaf_start.device
+    for nm, t in (("sx", sx), ("sy", sy), ("sz", sz), ("sm", sm)):
+        _vec(t, nm, src_tree.n)
     if out is None:
         S = nbrs.red_entries
         if S < 0:
@@ -309,8 +352,13 @@ def gravity_remote(tree: Tree, src_tree: Tree, nbrs: Nbrs, eps: float, x, y, z, 
     """Remote near-field potential and acceleration of the points of `tree`
     (caller order), added to `out` (zeros when not given).  Returns (phi, ax, ay, az)."""
     dev = tree.leaf_start.device
+    for nm, t in (("x", x), ("y", y), ("z", z)):
+        _vec(t, nm, tree.n)
+    for nm, t in (("sx", sx), ("sy", sy), ("sz", sz), ("sm", sm)):
+        _vec(t, nm, src_tree.n, optional=layout == "redundant")
     if out is None:
         out = [torch.zeros(tree.n, dtype=torch.float64, device=dev) for _ in range(4)]
+    out = _outs(out, tree.n, dev)
     ts, ss, ns = tree.struct(), src_tree.struct(), nbrs.struct()
     rs = red.struct() if red is not None else None
 
@@ -349,6 +397,8 @@ def restructure_interactions(tree: Tree, nbrs: Nbrs, x, y, z, m, prec="fp64",
     for fp32, float64 [rows, 4] for fp64).  Pass `out` to reuse its buffers."""
     p = PREC[prec]
     dev = tree.leaf_start.device
+    for nm, t in (("x", x), ("y", y), ("z", z), ("m", m)):
+        _vec(t, nm, tree.n)
     E = nbrs.count
     if out is None:
         if nbrs.red_entries >= 0:
@@ -382,8 +432,7 @@ def gravity_interactions(tree: Tree, nbrs: Nbrs, inter: Interactions, eps: float
     """Near-field potential and acceleration from the per-interaction layout,
     caller order.  Returns (phi, ax, ay, az)."""
     dev = tree.leaf_start.device
-    if out is None:
-        out = [torch.empty(tree.n, dtype=torch.float64, device=dev) for _ in range(4)]
+    out = _outs(out, tree.n, dev)
     ts, ns, rs = tree.struct(), nbrs.struct(), inter.struct()
 
     def call(ws, nb):
@@ -399,8 +448,9 @@ def gravity(tree: Tree, nbrs: Nbrs, eps: float, x=None, y=None, z=None, m=None,
     """Near-field potential and acceleration, caller order.  Returns (phi, ax, ay, az)."""
     dev = tree.leaf_start.device
     n = tree.n
-    if out is None:
-        out = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(4)]
+    for nm, t in (("x", x), ("y", y), ("z", z), ("m", m)):
+        _vec(t, nm, n, optional=layout == "redundant")
+    out = _outs(out, n, dev)
     ts, ns = tree.struct(), nbrs.struct()
     rs = red.struct() if red is not None else None
 
@@ -423,11 +473,11 @@ def helmholtz(tree: Tree, nbrs: Nbrs, q: Optional[torch.Tensor] = None, layout="
     if nrhs is None:
         nrhs = red.nrhs if red is not None else (1 if q.dim() == 1 else q.shape[1])
     cd = torch.complex64 if PREC[prec] == L.P2P_FP32_MIXED else torch.complex128
-    if q is not None:
-        _require_device(q, "q", cd)
+    _vec(q, "q", tree.n * nrhs, cd, optional=layout == "redundant")
     if out is None:
         shape = (tree.n,) if (q is not None and q.dim() == 1) or (q is None and nrhs == 1) else (tree.n, nrhs)
         out = torch.empty(shape, dtype=cd, device=dev)
+    _vec(out, "out", tree.n * nrhs, cd)
     gs, _ = grids_struct(tree.grids)
     ts, ns = tree.struct(), nbrs.struct()
     rs = red.struct() if red is not None else None
@@ -447,6 +497,9 @@ def helmholtz(tree: Tree, nbrs: Nbrs, q: Optional[torch.Tensor] = None, layout="
 def gravity_adjoint(tree: Tree, nbrs: Nbrs, eps: float, x, y, z, m, g_phi, g_ax, g_ay, g_az):
     """Gradients (g_x, g_y, g_z, g_m) of sum g_phi.phi + g_a.a, FP64, tree frozen."""
     dev = tree.leaf_start.device
+    for nm, t in (("x", x), ("y", y), ("z", z), ("m", m), ("g_phi", g_phi), ("g_ax", g_ax), ("g_ay", g_ay),
+                  ("g_az", g_az)):
+        _vec(t, nm, tree.n)
     outs = [torch.empty(tree.n, dtype=torch.float64, device=dev) for _ in range(4)]
     fin = L.PV4(*[_ptr(t) for t in (x, y, z, m)])
     gout = L.PV4(*[_ptr(t) for t in (g_phi, g_ax, g_ay, g_az)])
@@ -467,6 +520,7 @@ def helmholtz_adjoint(tree: Tree, nbrs: Nbrs, g: torch.Tensor, prec="fp64", conj
     """A^T g (conjugate=False) or A^H g = conj(A^T conj(g)) (conjugate=True)."""
     dev = tree.leaf_start.device
     nrhs = 1 if g.dim() == 1 else g.shape[1]
+    _vec(g, "g", tree.n * nrhs, torch.complex64 if PREC[prec] == L.P2P_FP32_MIXED else torch.complex128)
     out = torch.empty_like(g)
     gs, _ = grids_struct(tree.grids)
     gout = L.PV4(_ptr(g), None, None, None)
