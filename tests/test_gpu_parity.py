@@ -430,3 +430,38 @@ def test_locality_matches_oracle():
     assert loc["pairs"] == oracle.pair_count(ot, os_, oi)
     for k_g, k_o in (("d_mean", "D_mean"), ("v_ratio", "V_ratio"), ("locality", "locality")):
         assert abs(loc[k_g] - ref[k_o]) <= 1e-12 * abs(ref[k_o])
+
+
+def test_capacity_errors_leave_outputs_untouched():
+    """Near lists and a redundant layout given too little room: P2P_ECAPACITY
+    with the required size reported, nothing written; the binding's retry
+    gives the same lists."""
+    import ctypes
+    from paper_2511_21535_amd import _lib as L
+    x, y, z, m = W.plummer_mixture(3000, 61)
+    print("case capacity errors", flush=True)
+    g = [_t(v) for v in (x, y, z, m)]
+    gt = api.Tree.build_particles(*g[:3], depth=20, leaf_cap=16)
+    ref = gt.neighbors()
+    idx = torch.full((5,), -7, dtype=torch.int32, device=DEV)
+    start = torch.full((gt.n_leaves + 1,), -7, dtype=torch.int64, device=DEV)
+    s = L.p2p_nbrs()
+    s.cap, s.nbr_start, s.nbr_idx = 5, start.data_ptr(), idx.data_ptr()
+    ts = gt.struct()
+    st, _ = api._call(lambda ws, nb: L.p2p_build_neighbors(ctypes.byref(ts), ctypes.byref(s), ws, nb,
+                                                           api._stream()), gt.leaf_start.device)
+    torch.cuda.synchronize()
+    assert st == L.P2P_ECAPACITY and s.count == ref.count
+    assert torch.all(idx == -7) and torch.all(start == -7)
+    nb = api.build_neighbors(gt, cap=5)
+    assert torch.equal(nb.nbr_idx, ref.nbr_idx) and torch.equal(nb.nbr_start, ref.nbr_start)
+    S = ref.red_entries
+    short = api.Redundant(count=0, red_start=torch.full((gt.n_leaves + 1,), -7, dtype=torch.int64, device=DEV),
+                          red_self=torch.empty(gt.n_leaves, dtype=torch.int32, device=DEV),
+                          planes=[torch.full((S - 1, 4), 3.0, dtype=torch.float64, device=DEV), None, None, None],
+                          nrhs=1, kind=L.P2P_KIND_GRAVITY, prec=L.P2P_FP64)
+    with pytest.raises(L.P2PError) as err:
+        api.restructure_gravity(gt, ref, *g, prec="fp64", out=short)
+    torch.cuda.synchronize()
+    assert err.value.status == L.P2P_ECAPACITY
+    assert torch.all(short.planes[0] == 3.0) and torch.all(short.red_start == -7)
