@@ -132,18 +132,22 @@ __global__ __launch_bounds__(256) void k_copy_records(
 }
 
 constexpr int kEvalWaves = 4;
+constexpr int kRecPerWave = 8;   // consecutive records per wavefront (at most 64: one lane each)
 constexpr int kRecFlush = 32;
 
-// One wavefront per record.  The record's sources are staged through LDS 64
-// rows at a time with one coalesced load per lane (a load per pair straight
-// from the record left every wave waiting out a memory round trip per pair
-// group).  Targets in chunks of 64; with tc targets in a chunk, lane (t, g) =
-// (lane % tc, lane / tc) takes target t and staged sources g, g + G, ...
-// (G = 64 / tc), FP32-mixed pair terms summed at most 32 at a time in float
-// into double; the G partials meet in LDS.  Record (A, A) holds every target
-// once as its own source at d = 0; that self term is added back as in the box
-// kernels.  With image codes only the unshifted record (A, A) is the self
-// record: a point meets its own image elsewhere at a nonzero distance.
+// A wavefront takes kRecPerWave consecutive records.  Its lanes first load
+// the starts, headers and result offsets of all of them at once, so that each
+// record then waits for one memory round trip (its rows), not three in a
+// chain.  A record's sources are staged through LDS 64 rows at a time with one
+// coalesced load per lane (a load per pair straight from the record left
+// every wave waiting out a memory round trip per pair group).  Targets in
+// chunks of 64; with tc targets in a chunk, lane (t, g) = (lane % tc,
+// lane / tc) takes target t and staged sources g, g + G, ... (G = 64 / tc),
+// FP32-mixed pair terms summed at most 32 at a time in float into double;
+// the G partials meet in LDS.  Record (A, A) holds every target once as its
+// own source at d = 0; that self term is added back as in the box kernels.
+// With image codes only the unshifted record (A, A) is the self record: a
+// point meets its own image elsewhere at a nonzero distance.
 template <bool MIXED, bool EPS0>
 __global__ __launch_bounds__(64 * kEvalWaves) void k_eval_records(
     const int64_t *__restrict__ rec_start, const Row4d *__restrict__ r8, const float4 *__restrict__ r4,
@@ -153,116 +157,127 @@ __global__ __launch_bounds__(64 * kEvalWaves) void k_eval_records(
     __shared__ double s_red[kEvalWaves][4][64];
     __shared__ Src s_src[kEvalWaves][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t e = static_cast<int64_t>(blockIdx.x) * kEvalWaves + w;
-    if (e >= E) return;
-    const int64_t r = rec_start[e];
-    int occA, occB, A, B;
-    if constexpr (MIXED) {
-        const float4 h = r4[r];
-        occA = __float_as_int(h.x);
-        occB = __float_as_int(h.y);
-        A = __float_as_int(h.z);
-        B = __float_as_int(h.w);
-    } else {
-        const Row4d h = r8[r];
-        occA = static_cast<int>(h.x);
-        occB = static_cast<int>(h.y);
-        A = static_cast<int>(h.z);
-        B = static_cast<int>(h.w);
+    const int64_t eb = (static_cast<int64_t>(blockIdx.x) * kEvalWaves + w) * kRecPerWave;
+    if (eb >= E) return;
+    const int nrec = static_cast<int>(min<int64_t>(kRecPerWave, E - eb));
+    // lane k < nrec: record eb + k
+    int64_t my_r = 0, my_out = 0;
+    int my_occA = 0, my_occB = 0, my_self = 0;
+    if (lane < nrec) {
+        const int64_t e = eb + lane;
+        my_r = rec_start[e];
+        my_out = res_start[e];
+        int A, B;
+        if constexpr (MIXED) {
+            const float4 h = r4[my_r];
+            my_occA = __float_as_int(h.x);
+            my_occB = __float_as_int(h.y);
+            A = __float_as_int(h.z);
+            B = __float_as_int(h.w);
+        } else {
+            const Row4d h = r8[my_r];
+            my_occA = static_cast<int>(h.x);
+            my_occB = static_cast<int>(h.y);
+            A = static_cast<int>(h.z);
+            B = static_cast<int>(h.w);
+        }
+        my_self = (A == B && (nbr_shift == nullptr || nbr_shift[e] == 13)) ? 1 : 0;
     }
-    occA = __builtin_amdgcn_readfirstlane(occA);
-    occB = __builtin_amdgcn_readfirstlane(occB);
-    const bool self = __builtin_amdgcn_readfirstlane(A) == __builtin_amdgcn_readfirstlane(B) &&
-                      (nbr_shift == nullptr || nbr_shift[e] == 13);
-    const int64_t t0 = r + 1, s0 = r + 1 + occA;
     const float eps2f = static_cast<float>(eps2);
-    const int64_t out0 = res_start[e];
-    for (int tc0 = 0; tc0 < occA; tc0 += 64) {
-        const int tc = min(64, occA - tc0);
-        const int G = 64 / tc;
-        const int t = lane % tc, g = lane / tc;
-        const bool active = g < G;
-        double p = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
-        double tm = 0.0;
-        Src tv;
-        if constexpr (MIXED)
-            tv = r4[t0 + tc0 + t];
-        else
-            tv = r8[t0 + tc0 + t];
-        tm = tv.w;
-        for (int b0 = 0; b0 < occB; b0 += 64) {
-            const int nb = min(64, occB - b0);
-            if (lane < nb) {
-                if constexpr (MIXED)
-                    s_src[w][lane] = r4[s0 + b0 + lane];
-                else
-                    s_src[w][lane] = r8[s0 + b0 + lane];
-            }
-            wave_sync();
-            if (active) {
-                if constexpr (MIXED) {
-                    int j = g;
-                    while (j < nb) {
-                        float pf = 0.f, xf = 0.f, yf = 0.f, zf = 0.f;
-                        for (int k = 0; k < kRecFlush && j < nb; ++k, j += G) {
-                            const float4 v = s_src[w][j];
-                            const float dx = tv.x - v.x, dy = tv.y - v.y, dz = tv.z - v.z;
-                            const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2f)));
-                            float wv = rsq_f32(r2);
-                            if constexpr (EPS0) wv = (r2 > 0.f) ? wv : 0.f;
-                            const float mw = v.w * wv;
-                            const float mw3 = mw * (wv * wv);
-                            pf -= mw;
-                            xf = fmaf(-mw3, dx, xf);
-                            yf = fmaf(-mw3, dy, yf);
-                            zf = fmaf(-mw3, dz, zf);
+    for (int k = 0; k < nrec; ++k) {
+        const int64_t r = static_cast<int64_t>(__shfl(static_cast<long long>(my_r), k, 64));
+        const int64_t out0 = static_cast<int64_t>(__shfl(static_cast<long long>(my_out), k, 64));
+        const int occA = __builtin_amdgcn_readfirstlane(__shfl(my_occA, k, 64));
+        const int occB = __builtin_amdgcn_readfirstlane(__shfl(my_occB, k, 64));
+        const bool self = __builtin_amdgcn_readfirstlane(__shfl(my_self, k, 64)) != 0;
+        const int64_t t0 = r + 1, s0 = r + 1 + occA;
+        for (int tc0 = 0; tc0 < occA; tc0 += 64) {
+            const int tc = min(64, occA - tc0);
+            const int G = 64 / tc;
+            const int t = lane % tc, g = lane / tc;
+            const bool active = g < G;
+            double p = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+            double tm = 0.0;
+            Src tv;
+            if constexpr (MIXED)
+                tv = r4[t0 + tc0 + t];
+            else
+                tv = r8[t0 + tc0 + t];
+            tm = tv.w;
+            for (int b0 = 0; b0 < occB; b0 += 64) {
+                const int nb = min(64, occB - b0);
+                if (lane < nb) {
+                    if constexpr (MIXED)
+                        s_src[w][lane] = r4[s0 + b0 + lane];
+                    else
+                        s_src[w][lane] = r8[s0 + b0 + lane];
+                }
+                wave_sync();
+                if (active) {
+                    if constexpr (MIXED) {
+                        int j = g;
+                        while (j < nb) {
+                            float pf = 0.f, xf = 0.f, yf = 0.f, zf = 0.f;
+                            for (int k = 0; k < kRecFlush && j < nb; ++k, j += G) {
+                                const float4 v = s_src[w][j];
+                                const float dx = tv.x - v.x, dy = tv.y - v.y, dz = tv.z - v.z;
+                                const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2f)));
+                                float wv = rsq_f32(r2);
+                                if constexpr (EPS0) wv = (r2 > 0.f) ? wv : 0.f;
+                                const float mw = v.w * wv;
+                                const float mw3 = mw * (wv * wv);
+                                pf -= mw;
+                                xf = fmaf(-mw3, dx, xf);
+                                yf = fmaf(-mw3, dy, yf);
+                                zf = fmaf(-mw3, dz, zf);
+                            }
+                            p += pf;
+                            fx += xf;
+                            fy += yf;
+                            fz += zf;
                         }
-                        p += pf;
-                        fx += xf;
-                        fy += yf;
-                        fz += zf;
-                    }
-                } else {
-                    for (int j = g; j < nb; j += G) {
-                        const Row4d v = s_src[w][j];
-                        const double dx = tv.x - v.x, dy = tv.y - v.y, dz = tv.z - v.z;
-                        const double r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
-                        double wv = rsqrt(r2);
-                        if constexpr (EPS0) wv = (r2 > 0.0) ? wv : 0.0;
-                        const double mw = v.w * wv;
-                        const double mw3 = mw * (wv * wv);
-                        p -= mw;
-                        fx = fma(-mw3, dx, fx);
-                        fy = fma(-mw3, dy, fy);
-                        fz = fma(-mw3, dz, fz);
+                    } else {
+                        for (int j = g; j < nb; j += G) {
+                            const Row4d v = s_src[w][j];
+                            const double dx = tv.x - v.x, dy = tv.y - v.y, dz = tv.z - v.z;
+                            const double r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
+                            double wv = rsqrt(r2);
+                            if constexpr (EPS0) wv = (r2 > 0.0) ? wv : 0.0;
+                            const double mw = v.w * wv;
+                            const double mw3 = mw * (wv * wv);
+                            p -= mw;
+                            fx = fma(-mw3, dx, fx);
+                            fy = fma(-mw3, dy, fy);
+                            fz = fma(-mw3, dz, fz);
+                        }
                     }
                 }
+                wave_sync();   // every lane has read this chunk before the next overwrites it
             }
-            wave_sync();   // every lane has read this chunk before the next overwrites it
+            if (!active) p = fx = fy = fz = 0.0;
+            s_red[w][0][lane] = p;
+            s_red[w][1][lane] = fx;
+            s_red[w][2][lane] = fy;
+            s_red[w][3][lane] = fz;
+            wave_sync();
+            if (lane < tc) {
+                double sp = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
+                for (int q = 0; q < G; ++q) {
+                    sp += s_red[w][0][q * tc + lane];
+                    sx += s_red[w][1][q * tc + lane];
+                    sy += s_red[w][2][q * tc + lane];
+                    sz += s_red[w][3][q * tc + lane];
+                }
+                if (!EPS0 && self) {
+                    if constexpr (MIXED)
+                        sp += static_cast<double>(static_cast<float>(tm) * rsq_f32(eps2f));
+                    else
+                        sp += tm * rsqrt(eps2);
+                }
+                res[out0 + tc0 + lane] = Row4d{sp, sx, sy, sz};
+            }
+            wave_sync();
         }
-        if (!active) p = fx = fy = fz = 0.0;
-        s_red[w][0][lane] = p;
-        s_red[w][1][lane] = fx;
-        s_red[w][2][lane] = fy;
-        s_red[w][3][lane] = fz;
-        wave_sync();
-        if (lane < tc) {
-            double sp = 0.0, sx = 0.0, sy = 0.0, sz = 0.0;
-            for (int q = 0; q < G; ++q) {
-                sp += s_red[w][0][q * tc + lane];
-                sx += s_red[w][1][q * tc + lane];
-                sy += s_red[w][2][q * tc + lane];
-                sz += s_red[w][3][q * tc + lane];
-            }
-            if (!EPS0 && self) {
-                if constexpr (MIXED)
-                    sp += static_cast<double>(static_cast<float>(tm) * rsq_f32(eps2f));
-                else
-                    sp += tm * rsqrt(eps2);
-            }
-            res[out0 + tc0 + lane] = Row4d{sp, sx, sy, sz};
-        }
-        wave_sync();
     }
 }
 
@@ -354,7 +369,7 @@ p2p_status launch_eval_records(const int64_t *rec_start, const Row4d *r8, const 
                                const int8_t *nbr_shift, int64_t E, const int64_t *res_start, double eps2,
                                bool eps_zero, Row4d *res, hipStream_t s) {
     if (E <= 0) return P2P_OK;
-    const unsigned g = grid_for(E, kEvalWaves);
+    const unsigned g = grid_for((E + kRecPerWave - 1) / kRecPerWave, kEvalWaves);
     const unsigned b = 64 * kEvalWaves;
 #define P2P_EVAL_REC(M, E0) \
     k_eval_records<M, E0><<<g, b, 0, s>>>(rec_start, r8, r4, nbr_shift, E, res_start, eps2, res)
