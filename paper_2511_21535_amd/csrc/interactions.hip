@@ -67,9 +67,19 @@ __global__ __launch_bounds__(256) void k_record_lengths(const int32_t *__restric
     }
 }
 
-// Records of leaf A, one wavefront per leaf: for every entry of nbr(A), the
-// header, A's rows and B's rows, four rows per lane in flight.  B's rows are
-// placed at x + s, s the entry's image (zero without image codes).
+// Records of leaf A, one wavefront per leaf.  The records of A's entries are
+// consecutive, so A's part of the layout is one run of rows.  For each chunk
+// of 64 entries the lanes load the entries' source leaves and image codes at
+// once, form the record starts by a wave prefix of the record lengths
+// (1 + occ_A + occ_B) and mark an LDS map from row to entry; every output row
+// then finds its entry through the map (or by a forward walk over the
+// starts when the chunk has more than kRecMapRows rows) and is the record's
+// header, a row of A, or a row of B placed at x + s (s the entry's image),
+// eight rows per lane loaded before any store.  Lanes past the end repeat the
+// last row onto itself, so no load or store is conditional.
+constexpr int kRecMapRows = 4096;
+constexpr int kRecRows = 8;
+
 template <bool MIXED, bool NT>
 __global__ __launch_bounds__(256) void k_copy_records(
     const Row4d *__restrict__ sorted, const uint64_t *__restrict__ leaf_key,
@@ -77,6 +87,12 @@ __global__ __launch_bounds__(256) void k_copy_records(
     const int64_t *__restrict__ nbr_start, const int32_t *__restrict__ nbr_idx,
     const int8_t *__restrict__ nbr_shift, const int64_t *__restrict__ rec_start, int64_t L,
     Row4d *__restrict__ d8, float4 *__restrict__ d4) {
+    __shared__ int32_t s_pre[4][64];     // record starts within the chunk, in rows
+    __shared__ int32_t s_b0[4][64];      // first sorted slot of B
+    __shared__ int32_t s_occB[4][64];
+    __shared__ int32_t s_B[4][64];
+    __shared__ int32_t s_code[4][64];
+    __shared__ uint8_t s_map[4][kRecMapRows];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t A = p2pd::xcd_contiguous(blockIdx.x, gridDim.x) * 4 + w;
     if (A >= L) return;
@@ -89,45 +105,81 @@ __global__ __launch_bounds__(256) void k_copy_records(
         c[1] = (static_cast<double>(p2pd::compact3(k >> 1)) + half) * 0x1p-20;
         c[2] = (static_cast<double>(p2pd::compact3(k >> 2)) + half) * 0x1p-20;
     }
-    for (int64_t e = nbr_start[A]; e < nbr_start[A + 1]; ++e) {
-        const int32_t B = nbr_idx[e];
-        const int32_t b0 = leaf_start[B], occB = leaf_start[B + 1] - b0;
-        const int64_t d = rec_start[e];
-        const int code = nbr_shift ? nbr_shift[e] : 13;
-        const double sh[3] = {static_cast<double>(code % 3 - 1), static_cast<double>((code / 3) % 3 - 1),
-                              static_cast<double>(code / 9 - 1)};
-        if (lane == 0) {
-            if constexpr (MIXED)
-                put<NT>(d4 + d, make_float4(__int_as_float(occA), __int_as_float(occB),
-                                            __int_as_float(static_cast<int32_t>(A)), __int_as_float(B)));
-            else
-                put<NT>(d8 + d, Row4d{static_cast<double>(occA), static_cast<double>(occB),
-                                      static_cast<double>(A), static_cast<double>(B)});
+    const int64_t e0 = nbr_start[A], e1 = nbr_start[A + 1];
+    for (int64_t c0 = e0; c0 < e1; c0 += 64) {
+        const int nc = static_cast<int>(min<int64_t>(64, e1 - c0));
+        int32_t len = 0, B = 0, b0 = 0, occB = 0, code = 13;
+        if (lane < nc) {
+            B = nbr_idx[c0 + lane];
+            b0 = leaf_start[B];
+            occB = leaf_start[B + 1] - b0;
+            if (nbr_shift) code = nbr_shift[c0 + lane];
+            len = 1 + occA + occB;
         }
-        // rows r < occA come from A, the rest from B; lanes past the end
-        // repeat the last row onto itself, so no load or store is conditional
-        const int32_t rows = occA + occB;
-        for (int32_t p0 = 0; p0 < rows; p0 += 256) {
-            Row4d v[4];
+        int32_t inc = len;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int32_t r = min(p0 + 64 * u + lane, rows - 1);
-                v[u] = sorted[r < occA ? a0 + r : b0 + (r - occA)];
-                const bool source = r >= occA;
-                v[u].x += source ? sh[0] : 0.0;
-                v[u].y += source ? sh[1] : 0.0;
-                v[u].z += source ? sh[2] : 0.0;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int32_t y = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += y;
+        }
+        s_pre[w][lane] = inc - len;
+        s_b0[w][lane] = b0;
+        s_occB[w][lane] = occB;
+        s_B[w][lane] = B;
+        s_code[w][lane] = code;
+        const int32_t rows = __shfl(inc, 63, 64);
+        const bool use_map = rows <= kRecMapRows;
+        if (use_map)
+            for (int32_t r = inc - len; r < inc; ++r) s_map[w][r] = static_cast<uint8_t>(lane);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const int64_t d = rec_start[c0];
+        int b = 0;
+        for (int32_t p0 = 0; p0 < rows; p0 += 64 * kRecRows) {
+            Row4d v[kRecRows];
+            int32_t jq[kRecRows], rq[kRecRows];
+#pragma unroll
+            for (int u = 0; u < kRecRows; ++u) {
+                const int32_t q = min(p0 + 64 * u + lane, rows - 1);
+                int j;
+                if (use_map) {
+                    j = s_map[w][q];
+                } else {
+                    while (b + 1 < nc && s_pre[w][b + 1] <= q) ++b;
+                    j = b;
+                }
+                const int32_t r = q - s_pre[w][j];    // 0: header, 1..occA: A's rows, then B's
+                jq[u] = j;
+                rq[u] = r;
+                const int32_t slot = r <= occA ? a0 + max(r - 1, 0) : s_b0[w][j] + (r - 1 - occA);
+                v[u] = sorted[slot];
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int64_t o = d + 1 + min(p0 + 64 * u + lane, rows - 1);
-                if constexpr (MIXED)
-                    put<NT>(d4 + o, make_float4(static_cast<float>(v[u].x - c[0]), static_cast<float>(v[u].y - c[1]),
-                                                static_cast<float>(v[u].z - c[2]), static_cast<float>(v[u].w)));
-                else
-                    put<NT>(d8 + o, v[u]);
+            for (int u = 0; u < kRecRows; ++u) {
+                const int32_t q = min(p0 + 64 * u + lane, rows - 1);
+                const int j = jq[u], r = rq[u];
+                const int64_t o = d + q;
+                if (r > occA) {     // a source row at its image
+                    const int cd = s_code[w][j];
+                    v[u].x += static_cast<double>(cd % 3 - 1);
+                    v[u].y += static_cast<double>((cd / 3) % 3 - 1);
+                    v[u].z += static_cast<double>(cd / 9 - 1);
+                }
+                if constexpr (MIXED) {
+                    const float4 row = make_float4(static_cast<float>(v[u].x - c[0]), static_cast<float>(v[u].y - c[1]),
+                                                   static_cast<float>(v[u].z - c[2]), static_cast<float>(v[u].w));
+                    const float4 hdr = make_float4(__int_as_float(occA), __int_as_float(s_occB[w][j]),
+                                                   __int_as_float(static_cast<int32_t>(A)), __int_as_float(s_B[w][j]));
+                    put<NT>(d4 + o, r == 0 ? hdr : row);
+                } else {
+                    const Row4d hdr{static_cast<double>(occA), static_cast<double>(s_occB[w][j]),
+                                    static_cast<double>(A), static_cast<double>(s_B[w][j])};
+                    put<NT>(d8 + o, r == 0 ? hdr : v[u]);
+                }
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
