@@ -294,7 +294,9 @@ p2p_status p2p_eval_helmholtz(const p2p_tree *tree, const p2p_nbrs *nbrs, const 
  *  kind == P2P_KIND_GRAVITY: fwd_in = {x, y, z, m}, grad_out = {g_phi, g_ax,
  *    g_ay, g_az}, grad_in = {g_x, g_y, g_z, g_m}, all caller-order double[n]:
  *    the gradients of L = sum_i g_phi_i phi_i + g_a_i . a_i with respect to
- *    positions and masses (tree frozen), eps > 0.  GATHER layout.
+ *    positions and masses (tree frozen), eps > 0.  GATHER layout; FP64, or
+ *    FP32_MIXED (positions relative to the target leaf's centre, float pair
+ *    terms, double accumulation, as in the forward evaluation).
  *  kind == P2P_KIND_HELMHOLTZ: grad_out[0] = g (caller order [n][nrhs]
  *    complex), grad_in[0] = A^T g, or conj(A^T conj(g)) = A^H g when
  *    `conjugate` is 1 (PyTorch's convention for complex gradients).  The

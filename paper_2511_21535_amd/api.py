@@ -494,8 +494,9 @@ def helmholtz(tree: Tree, nbrs: Nbrs, q: Optional[torch.Tensor] = None, layout="
     return out
 
 
-def gravity_adjoint(tree: Tree, nbrs: Nbrs, eps: float, x, y, z, m, g_phi, g_ax, g_ay, g_az):
-    """Gradients (g_x, g_y, g_z, g_m) of sum g_phi.phi + g_a.a, FP64, tree frozen."""
+def gravity_adjoint(tree: Tree, nbrs: Nbrs, eps: float, x, y, z, m, g_phi, g_ax, g_ay, g_az, prec="fp64"):
+    """Gradients (g_x, g_y, g_z, g_m) of sum g_phi.phi + g_a.a, tree frozen;
+    prec "fp64" or "fp32" (FP32-mixed pair terms)."""
     dev = tree.leaf_start.device
     for nm, t in (("x", x), ("y", y), ("z", z), ("m", m), ("g_phi", g_phi), ("g_ax", g_ax), ("g_ay", g_ay),
                   ("g_az", g_az)):
@@ -508,7 +509,7 @@ def gravity_adjoint(tree: Tree, nbrs: Nbrs, eps: float, x, y, z, m, g_phi, g_ax,
 
     def call(ws, nb):
         return L.p2p_adjoint(L.P2P_KIND_GRAVITY, ctypes.byref(ts), ctypes.byref(ns), None,
-                             L.P2P_GATHER, L.P2P_FP64, float(eps), None, 0, 1, 0,
+                             L.P2P_GATHER, PREC[prec], float(eps), None, 0, 1, 0,
                              ctypes.byref(fin), ctypes.byref(gout), ctypes.byref(gin), ws, nb,
                              _stream())
     st, ws = _call(call, dev)

@@ -937,7 +937,7 @@ extern "C" p2p_status p2p_adjoint(int32_t kind, const p2p_tree *tree, const p2p_
     if (tree->kind != P2P_TREE_PARTICLES) return fail(P2P_EINVAL, "gravity needs a particle tree");
     P2P_TRY(check_nbrs(tree, nbrs));
     if (layout != P2P_GATHER) return fail(P2P_EUNSUPPORTED, "gravity adjoint uses the GATHER layout");
-    if (prec != P2P_FP64) return fail(P2P_EUNSUPPORTED, "gravity adjoint runs in FP64");
+    if (prec != P2P_FP64 && prec != P2P_FP32_MIXED) return fail(P2P_EINVAL, "bad precision");
     if (!(eps > 0.0) || !std::isfinite(eps)) return fail(P2P_EINVAL, "gravity adjoint needs eps > 0");
     const int64_t n = tree->n;
     Arena ar(ws);
@@ -961,12 +961,14 @@ extern "C" p2p_status p2p_adjoint(int32_t kind, const p2p_tree *tree, const p2p_
     a.nbr_shift = shifts(nbrs);
     a.s4 = s4;
     a.g4 = g4;
+    a.leaf_key = tree->leaf_key;
+    a.leaf_level = tree->leaf_level;
     a.eps2 = eps * eps;
     a.gx = static_cast<double *>(grad_in[0]);
     a.gy = static_cast<double *>(grad_in[1]);
     a.gz = static_cast<double *>(grad_in[2]);
     a.gm = static_cast<double *>(grad_in[3]);
-    return launch_gravity_adjoint(a, s);
+    return launch_gravity_adjoint(a, prec == P2P_FP32_MIXED, s);
 }
 
 // ------------------------------------------------------------------ a12 ---

@@ -391,56 +391,109 @@ __global__ __launch_bounds__(kGBlock) __attribute__((amdgpu_waves_per_eu(7))) vo
     gravity_body<true, false, EPS0, PER, false>(a);
 }
 
-// Adjoint of the gravity sums, FP64, gather layout.  For target j and each
-// near source k (d = x_j - x_k, w = (|d|^2+eps^2)^{-1/2}):
+// Adjoint of the gravity sums, gather layout.  For target j and each near
+// source k (d = x_j - x_k, w = (|d|^2+eps^2)^{-1/2}):
 //   g_x_j += [ m_k (gp_j w^3 + 3 w^5 ga_j.d) + m_j (gp_k w^3 - 3 w^5 ga_k.d) ] d
 //            + w^3 (m_j ga_k - m_k ga_j)
 //   g_m_j += -(gp_k w - w^3 ga_k.d)
 // (the derivative of L = sum_i gp_i phi_i + ga_i . a_i through both the pair
 // (j, k) and the pair (k, j)).  The self pair adds zero to g_x and
-// -gp_j/eps to g_m, which is added back.
-template <bool PER>
+// -gp_j/eps to g_m, which is added back.  FP32_MIXED as in the forward
+// kernels: positions relative to the target leaf's centre, taken in double
+// and rounded to float once per staged source, float pair terms summed at
+// most 32 at a time before they are added to double accumulators.
+template <bool PER, bool MIXED>
 __global__ __launch_bounds__(kGBlock) void k_gravity_adjoint(GravityAdjointArgs a) {
-    __shared__ Row4d s_p[kGTile];    // sources (x, y, z, m)
-    __shared__ Row4d s_g[kGTile];    // their upstream gradients (g_phi, g_ax, g_ay, g_az)
+    using Src = typename std::conditional<MIXED, float4, Row4d>::type;
+    __shared__ Src s_p[kGTile];    // sources (x, y, z, m)
+    __shared__ Src s_g[kGTile];    // their upstream gradients (g_phi, g_ax, g_ay, g_az)
     __shared__ int64_t s_pre[kGNbrChunk + 1];
     __shared__ int32_t s_first[kGNbrChunk];
     __shared__ int8_t s_code[kGNbrChunk];
     __shared__ int64_t s_w[kGBlock / 64];
+    static_assert(sizeof(s_g) >= 4 * kGBlock * sizeof(double), "reduction does not fit");
     double *s_red = reinterpret_cast<double *>(s_g);   // reused after the last tile
 
     const int64_t A = blockIdx.x;
     const int32_t t0 = a.leaf_start[A];
     const int32_t ntar = a.leaf_start[A + 1] - t0;
     const double eps2 = a.eps2;
+    const float eps2f = static_cast<float>(eps2);
+    double c[3] = {0.0, 0.0, 0.0};
+    if (MIXED) leaf_centre(a.leaf_key[A], a.leaf_level[A], c);
+    auto rel = [&](const Row4d &v) {
+        return make_float4(static_cast<float>(v.x - c[0]), static_cast<float>(v.y - c[1]),
+                           static_cast<float>(v.z - c[2]), static_cast<float>(v.w));
+    };
+    auto grad = [](const Row4d &v) {
+        return make_float4(static_cast<float>(v.x), static_cast<float>(v.y), static_cast<float>(v.z),
+                           static_cast<float>(v.w));
+    };
     for (int tc0 = 0; tc0 < ntar; tc0 += kGBlock) {
         const int tc = min(kGBlock, ntar - tc0);
         int G, t, g;
         lane_split(tc, G, t, g);
         const bool active = g < G;
         const int64_t tr = t0 + tc0 + t;
-        const Row4d pj = a.s4[tr], gj = a.g4[tr];
+        Src pj, gj;
+        if constexpr (MIXED) {
+            pj = rel(a.s4[tr]);
+            gj = grad(a.g4[tr]);
+        } else {
+            pj = a.s4[tr];
+            gj = a.g4[tr];
+        }
         double om = 0.0, ox = 0.0, oy = 0.0, oz = 0.0;
         // a periodic source image at x_k + s: both pair directions see the
         // same d = x_j - (x_k + s) (the reverse entry carries -s)
         auto stage = [&](int i, int64_t row, int code) {
-            s_p[i] = PER ? shifted(a.s4[row], code) : a.s4[row];
-            s_g[i] = a.g4[row];
+            const Row4d v = PER ? shifted(a.s4[row], code) : a.s4[row];
+            if constexpr (MIXED) {
+                s_p[i] = rel(v);
+                s_g[i] = grad(a.g4[row]);
+            } else {
+                s_p[i] = v;
+                s_g[i] = a.g4[row];
+            }
         };
         auto body = [&](int nt) {
             if (!active) return;
-            for (int s = g; s < nt; s += G) {
-                const Row4d pk = s_p[s], gk = s_g[s];
-                const double dx = pj.x - pk.x, dy = pj.y - pk.y, dz = pj.z - pk.z;
-                const double w = rsqrt(fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2))));
-                const double w3 = w * w * w, w5 = w3 * w * w;
-                const double gdj = gj.y * dx + gj.z * dy + gj.w * dz;
-                const double gdk = gk.y * dx + gk.z * dy + gk.w * dz;
-                const double c = pk.w * (gj.x * w3 + 3.0 * w5 * gdj) + pj.w * (gk.x * w3 - 3.0 * w5 * gdk);
-                ox += c * dx + w3 * (pj.w * gk.y - pk.w * gj.y);
-                oy += c * dy + w3 * (pj.w * gk.z - pk.w * gj.z);
-                oz += c * dz + w3 * (pj.w * gk.w - pk.w * gj.w);
-                om -= gk.x * w - w3 * gdk;
+            if constexpr (MIXED) {
+                int s = g;
+                while (s < nt) {
+                    float fm = 0.f, fx = 0.f, fy = 0.f, fz = 0.f;
+                    for (int k = 0; k < kGFlush && s < nt; ++k, s += G) {
+                        const float4 pk = s_p[s], gk = s_g[s];
+                        const float dx = pj.x - pk.x, dy = pj.y - pk.y, dz = pj.z - pk.z;
+                        const float w = rsq_f32(fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2f))));
+                        const float w2 = w * w, w3 = w2 * w, w5 = w3 * w2;
+                        const float gdj = fmaf(gj.y, dx, fmaf(gj.z, dy, gj.w * dz));
+                        const float gdk = fmaf(gk.y, dx, fmaf(gk.z, dy, gk.w * dz));
+                        const float cc = pk.w * fmaf(3.f * w5, gdj, gj.x * w3) + pj.w * fmaf(-3.f * w5, gdk, gk.x * w3);
+                        fx += fmaf(cc, dx, w3 * (pj.w * gk.y - pk.w * gj.y));
+                        fy += fmaf(cc, dy, w3 * (pj.w * gk.z - pk.w * gj.z));
+                        fz += fmaf(cc, dz, w3 * (pj.w * gk.w - pk.w * gj.w));
+                        fm -= gk.x * w - w3 * gdk;
+                    }
+                    om += fm;
+                    ox += fx;
+                    oy += fy;
+                    oz += fz;
+                }
+            } else {
+                for (int s = g; s < nt; s += G) {
+                    const Row4d pk = s_p[s], gk = s_g[s];
+                    const double dx = pj.x - pk.x, dy = pj.y - pk.y, dz = pj.z - pk.z;
+                    const double w = rsqrt(fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2))));
+                    const double w3 = w * w * w, w5 = w3 * w * w;
+                    const double gdj = gj.y * dx + gj.z * dy + gj.w * dz;
+                    const double gdk = gk.y * dx + gk.z * dy + gk.w * dz;
+                    const double cc = pk.w * (gj.x * w3 + 3.0 * w5 * gdj) + pj.w * (gk.x * w3 - 3.0 * w5 * gdk);
+                    ox += cc * dx + w3 * (pj.w * gk.y - pk.w * gj.y);
+                    oy += cc * dy + w3 * (pj.w * gk.z - pk.w * gj.z);
+                    oz += cc * dz + w3 * (pj.w * gk.w - pk.w * gj.w);
+                    om -= gk.x * w - w3 * gdk;
+                }
             }
         };
         for_each_source_tile<false, PER>(A, nullptr, a.nbr_start, a.nbr_idx, a.nbr_shift, a.leaf_start,
@@ -454,8 +507,12 @@ __global__ __launch_bounds__(kGBlock) void k_gravity_adjoint(GravityAdjointArgs 
         if (static_cast<int>(threadIdx.x) < tc) {
             double r[4] = {0.0, 0.0, 0.0, 0.0};
             for (int q = 0; q < G; ++q)
-                for (int c = 0; c < 4; ++c) r[c] += s_red[c * kGBlock + q * tc + threadIdx.x];
-            r[0] += gj.x * rsqrt(eps2);   // the self pair added -g_phi_j / eps to g_m
+                for (int cI = 0; cI < 4; ++cI) r[cI] += s_red[cI * kGBlock + q * tc + threadIdx.x];
+            // the self pair added -g_phi_j / eps to g_m, in the same arithmetic
+            if constexpr (MIXED)
+                r[0] += static_cast<double>(gj.x * rsq_f32(eps2f));
+            else
+                r[0] += gj.x * rsqrt(eps2);
             const int64_t i = a.perm[t0 + tc0 + threadIdx.x];
             a.gm[i] = r[0];
             a.gx[i] = r[1];
@@ -517,12 +574,16 @@ p2p_status launch_gravity_remote(const GravityArgs &a, bool redundant, bool mixe
     return P2P_OK;
 }
 
-p2p_status launch_gravity_adjoint(const GravityAdjointArgs &a, hipStream_t s) {
+p2p_status launch_gravity_adjoint(const GravityAdjointArgs &a, bool mixed, hipStream_t s) {
     if (a.L <= 0) return P2P_OK;
-    if (a.nbr_shift)
-        k_gravity_adjoint<true><<<static_cast<unsigned>(a.L), kGBlock, 0, s>>>(a);
-    else
-        k_gravity_adjoint<false><<<static_cast<unsigned>(a.L), kGBlock, 0, s>>>(a);
+    const unsigned g = static_cast<unsigned>(a.L);
+    if (a.nbr_shift) {
+        if (mixed) k_gravity_adjoint<true, true><<<g, kGBlock, 0, s>>>(a);
+        else k_gravity_adjoint<true, false><<<g, kGBlock, 0, s>>>(a);
+    } else {
+        if (mixed) k_gravity_adjoint<false, true><<<g, kGBlock, 0, s>>>(a);
+        else k_gravity_adjoint<false, false><<<g, kGBlock, 0, s>>>(a);
+    }
     P2P_LAUNCH_CHECK();
     return P2P_OK;
 }

@@ -225,10 +225,12 @@ struct GravityAdjointArgs {
     const int8_t *nbr_shift;                // image codes of periodic lists, else null
     const Row4d *s4;                        // sorted rows (x, y, z, m)
     const Row4d *g4;                        // sorted upstream gradients (g_phi, g_ax, g_ay, g_az)
+    const uint64_t *leaf_key;               // FP32-mixed: the target leaf's centre
+    const int8_t *leaf_level;
     double eps2;
     double *gx, *gy, *gz, *gm;              // caller order
 };
-p2p_status launch_gravity_adjoint(const GravityAdjointArgs &a, hipStream_t s);
+p2p_status launch_gravity_adjoint(const GravityAdjointArgs &a, bool mixed, hipStream_t s);
 
 // Helmholtz (helmholtz.hip).
 struct HelmholtzArgs {

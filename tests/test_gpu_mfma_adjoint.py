@@ -158,6 +158,10 @@ def test_adjoint_gravity_256k():
                                                         sel, ss, si)
     assert _rel(adj[3][idx], rm) <= TOL64
     assert _rel(np.stack([a[idx] for a in adj[:3]]), np.stack([rx, ry, rz])) <= TOL64
+    # the FP32-mixed adjoint against the same oracle values
+    adj32 = [_n(v) for v in api.gravity_adjoint(tree, nbrs, w["eps"], gx_, gy_, gz_, gm_, *gg, prec="fp32")]
+    assert _rel(adj32[3][idx], rm) <= TOL32
+    assert _rel(np.stack([a[idx] for a in adj32[:3]]), np.stack([rx, ry, rz])) <= TOL32
     # central differences of the GPU forward; outputs untouched by the move are bitwise equal
     h = 1e-6
     scale = max(np.abs(a).max() for a in adj[:3])

@@ -343,17 +343,20 @@ def test_helmholtz_full_64_sampled():
 
 
 # --------------------------------------------------------------- adjoint
-def test_gravity_adjoint_parity():
+@pytest.mark.parametrize("prec,tol", [("fp64", TOL64), ("fp32", TOL32)])
+def test_gravity_adjoint_parity(prec, tol):
     x, y, z, m = W.plummer_mixture(3000, 31)
     gp, gax, gay, gaz = (W.normal_like(3000, seed=s) for s in (32, 33, 34, 35))
     gx, gy, gz, gm = (_t(v) for v in (x, y, z, m))
     gt = api.Tree.build_particles(gx, gy, gz, depth=20, leaf_cap=64)
     gn = gt.neighbors()
-    out = [_n(v) for v in api.gravity_adjoint(gt, gn, 1e-3, gx, gy, gz, gm, *(_t(v) for v in (gp, gax, gay, gaz)))]
+    out = [_n(v) for v in api.gravity_adjoint(gt, gn, 1e-3, gx, gy, gz, gm, *(_t(v) for v in (gp, gax, gay, gaz)),
+                                              prec=prec)]
     ot = oracle.build_tree_particles(x, y, z, depth=20, leaf_cap=64)
     rm, rx, ry, rz = oracle.gravity_adjoint(x, y, z, m, 1e-3, gp, gax, gay, gaz, ot)
-    assert _rel(out[3], rm) <= TOL64
-    assert _rel(np.stack(out[:3]), np.stack([rx, ry, rz])) <= TOL64
+    e_m, e_x = _rel(out[3], rm), _rel(np.stack(out[:3]), np.stack([rx, ry, rz]))
+    print(f"  adjoint {prec}: g_m {e_m:.2e} g_x {e_x:.2e}", flush=True)
+    assert e_m <= tol and e_x <= tol
 
 
 def test_helmholtz_adjoint_transpose():

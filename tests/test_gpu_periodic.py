@@ -127,18 +127,20 @@ def test_periodic_gather_equals_redundant_bitwise(prec):
         np.testing.assert_array_equal(_n(u), _n(v))
 
 
-def test_periodic_adjoint_parity():
+@pytest.mark.parametrize("prec,tol", [("fp64", TOL64), ("fp32", TOL32)])
+def test_periodic_adjoint_parity(prec, tol):
     x, y, z, m = W.plummer_mixture(3000, 31)
     gp, gax, gay, gaz = (W.normal_like(3000, seed=s) for s in (32, 33, 34, 35))
     g = [_t(v) for v in (x, y, z, m)]
     gt = api.Tree.build_particles(*g[:3], depth=20, leaf_cap=64)
     gn = gt.neighbors(periodic=True)
-    out = [_n(v) for v in api.gravity_adjoint(gt, gn, 1e-3, *g, *(_t(v) for v in (gp, gax, gay, gaz)))]
+    out = [_n(v) for v in api.gravity_adjoint(gt, gn, 1e-3, *g, *(_t(v) for v in (gp, gax, gay, gaz)),
+                                              prec=prec)]
     ot = oracle.build_tree_particles(x, y, z, depth=20, leaf_cap=64)
     rm, rx, ry, rz = oracle.gravity_adjoint(x, y, z, m, 1e-3, gp, gax, gay, gaz, ot,
                                             oracle.neighbors_periodic(ot))
-    assert _rel(out[3], rm) <= TOL64
-    assert _rel(np.stack(out[:3]), np.stack([rx, ry, rz])) <= TOL64
+    assert _rel(out[3], rm) <= tol
+    assert _rel(np.stack(out[:3]), np.stack([rx, ry, rz])) <= tol
 
 
 @pytest.mark.slow
