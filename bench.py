@@ -735,22 +735,24 @@ def run_adjoint(wname, args):
     pairs = int(api.locality(tree, nbrs)["pairs"])
 
     def step():
-        e = _events(3)
+        e = _events(4)
         e[0].record()
         api.gravity(tree, nbrs, w["eps"], x=gx, y=gy, z=gz, m=gm, prec="fp64")
         e[1].record()
         api.gravity_adjoint(tree, nbrs, w["eps"], gx, gy, gz, gm, *g)
         e[2].record()
+        api.gravity_adjoint(tree, nbrs, w["eps"], gx, gy, gz, gm, *g, prec="fp32")
+        e[3].record()
         return e
 
     K = args.steps
-    wall, (t_fwd, t_adj) = _timed_steps(step, K, args.warmup)
+    wall, (t_fwd, t_adj, t_adj32) = _timed_steps(step, K, args.warmup)
     value = pairs * K / (t_fwd + t_adj)
     line = _base("near-field pair-interactions/s, forward + adjoint (gather, FP64)", value,
                  "pair-interactions/s", K, args.warmup, wall, "f64",
                  {"workload": wname, "n": n, "leaves": tree.n_leaves, "pairs": pairs,
                   "parallelism": "single GPU"})
-    line["ms"] = {"forward": t_fwd / K * 1e3, "adjoint": t_adj / K * 1e3}
+    line["ms"] = {"forward": t_fwd / K * 1e3, "adjoint": t_adj / K * 1e3, "adjoint_fp32_mixed": t_adj32 / K * 1e3}
     return line
 
 
