@@ -407,9 +407,18 @@ p2p_status restructure_common(const p2p_tree *tree, const p2p_tree *srct, const 
     else
         P2P_TRY(launch_permute_rows<double2>(static_cast<const double2 *>(src[0]), tree->perm, n, nrhs,
                                              static_cast<double2 *>(sq), s));
-    P2P_TRY(launch_seg_lengths(srct->leaf_start, nbrs->nbr_start, nbrs->nbr_idx, shifts(nbrs), L, seg_len,
-                               out->red_self, !remote, s));
-    P2P_TRY((exclusive_scan<int32_t, int64_t>(seg_len, out->red_start, L, scan_tmp, s)));
+    // grid boxes all hold 64 points: the copy writes the segment offsets itself
+    BoxSegments boxes{};
+    if (tree->kind == P2P_TREE_GRIDS) {
+        boxes.red_start = out->red_start;
+        boxes.red_self = out->red_self;
+        boxes.box_rows = 64;
+        if (L == 0) P2P_TRY((exclusive_scan<int32_t, int64_t>(seg_len, out->red_start, 0, scan_tmp, s)));
+    } else {
+        P2P_TRY(launch_seg_lengths(srct->leaf_start, nbrs->nbr_start, nbrs->nbr_idx, shifts(nbrs), L, seg_len,
+                                   out->red_self, !remote, s));
+        P2P_TRY((exclusive_scan<int32_t, int64_t>(seg_len, out->red_start, L, scan_tmp, s)));
+    }
     const int64_t entry_bytes = grav ? (mixed ? 16 : 32) : static_cast<int64_t>(nrhs) * static_cast<int64_t>(csize);
     const bool streaming = S * entry_bytes > kStreamingLayoutBytes;
     if (grav)
@@ -421,11 +430,11 @@ p2p_status restructure_common(const p2p_tree *tree, const p2p_tree *srct, const 
     else if (mixed)
         P2P_TRY(launch_copy_segments<float2>(static_cast<const float2 *>(sq), nrhs, tree->leaf_start,
                                              nbrs->nbr_start, nbrs->nbr_idx, out->red_start, L,
-                                             static_cast<float2 *>(out->planes[0]), streaming, s));
+                                             static_cast<float2 *>(out->planes[0]), streaming, s, boxes));
     else
         P2P_TRY(launch_copy_segments<double2>(static_cast<const double2 *>(sq), nrhs, tree->leaf_start,
                                               nbrs->nbr_start, nbrs->nbr_idx, out->red_start, L,
-                                              static_cast<double2 *>(out->planes[0]), streaming, s));
+                                              static_cast<double2 *>(out->planes[0]), streaming, s, boxes));
     out->count = S;
     out->nrhs = nrhs;
     out->kind = grav ? P2P_KIND_GRAVITY : P2P_KIND_HELMHOLTZ;

@@ -154,11 +154,20 @@ p2p_status launch_copy_segments_gravity(const Row4d *sorted, const uint64_t *lea
                                         const int8_t *nbr_shift, const int64_t *red_start, int64_t L,
                                         Row4d *d8, float4 *d4, bool streaming, hipStream_t s,
                                         const PermRows *pr = nullptr);
+// Segment offsets of layouts whose leaves all hold box_rows points (grid
+// boxes): red_start[A] = box_rows nbr_start[A] and red_self[A] = box_rows
+// times A's place in its list, written by the copy itself (box_rows = 0: the
+// copy reads red_start computed beforehand).
+struct BoxSegments {
+    int64_t *red_start = nullptr;
+    int32_t *red_self = nullptr;
+    int32_t box_rows = 0;
+};
 template <class T>
 p2p_status launch_copy_segments(const T *sorted, int64_t row_len, const int32_t *leaf_start,
                                 const int64_t *nbr_start, const int32_t *nbr_idx,
                                 const int64_t *red_start, int64_t L, T *dst, bool streaming,
-                                hipStream_t s);
+                                hipStream_t s, BoxSegments boxes = {});
 // Redundant layouts larger than this are written with streaming (nontemporal)
 // stores; smaller ones stay in the 256 MB last-level cache for the evaluation.
 constexpr int64_t kStreamingLayoutBytes = int64_t(128) << 20;

@@ -277,14 +277,26 @@ template <class U, int UN, bool NT>
 __global__ __launch_bounds__(kCopyBlock) void k_copy_segments_units(
     const U *__restrict__ sorted, int64_t upr, const int32_t *__restrict__ leaf_start,
     const int64_t *__restrict__ nbr_start, const int32_t *__restrict__ nbr_idx,
-    const int64_t *__restrict__ red_start, int64_t L, U *__restrict__ dst) {
+    const int64_t *__restrict__ red_start, int64_t L, U *__restrict__ dst, BoxSegments boxes) {
     __shared__ int64_t s_pre[kCopyNbrChunk + 1];
     __shared__ int32_t s_first[kCopyNbrChunk];
     __shared__ int64_t s_w[kCopyBlock / 64];
     const int64_t A = p2pd::xcd_contiguous(blockIdx.x, gridDim.x);
     if (A >= L) return;
     const int64_t e0 = nbr_start[A], e1 = nbr_start[A + 1];
-    int64_t out = red_start[A];
+    int64_t out;
+    if (boxes.box_rows > 0) {
+        // full boxes: the offsets follow from the list positions, no scan needed
+        out = static_cast<int64_t>(boxes.box_rows) * e0;
+        if (threadIdx.x == 0) {
+            boxes.red_start[A] = out;
+            if (A == L - 1) boxes.red_start[L] = static_cast<int64_t>(boxes.box_rows) * e1;
+        }
+        for (int64_t e = e0 + threadIdx.x; e < e1; e += kCopyBlock)
+            if (nbr_idx[e] == A) boxes.red_self[A] = boxes.box_rows * static_cast<int32_t>(e - e0);
+    } else {
+        out = red_start[A];
+    }
     for (int64_t c0 = e0; c0 < e1; c0 += kCopyNbrChunk) {
         const int nc = static_cast<int>(min<int64_t>(kCopyNbrChunk, e1 - c0));
         const int64_t rows = load_nbr_chunk(leaf_start, nbr_idx, c0, nc, s_pre, s_first, s_w);
@@ -355,16 +367,16 @@ p2p_status permute_units(const void *src, const int32_t *perm, int64_t n, int64_
 template <class U>
 p2p_status copy_units(const void *sorted, int64_t row_bytes, const int32_t *leaf_start,
                       const int64_t *nbr_start, const int32_t *nbr_idx, const int64_t *red_start,
-                      int64_t L, void *dst, bool streaming, hipStream_t s) {
+                      int64_t L, void *dst, bool streaming, hipStream_t s, BoxSegments boxes) {
     const int64_t upr = row_bytes / static_cast<int64_t>(sizeof(U));
     if (streaming)
         k_copy_segments_units<U, 4, true><<<static_cast<unsigned>(L), kCopyBlock, 0, s>>>(
             static_cast<const U *>(sorted), upr, leaf_start, nbr_start, nbr_idx, red_start, L,
-            static_cast<U *>(dst));
+            static_cast<U *>(dst), boxes);
     else
         k_copy_segments_units<U, 4, false><<<static_cast<unsigned>(L), kCopyBlock, 0, s>>>(
             static_cast<const U *>(sorted), upr, leaf_start, nbr_start, nbr_idx, red_start, L,
-            static_cast<U *>(dst));
+            static_cast<U *>(dst), boxes);
     P2P_LAUNCH_CHECK();
     return P2P_OK;
 }
@@ -425,17 +437,21 @@ template <class T>
 p2p_status launch_copy_segments(const T *sorted, int64_t row_len, const int32_t *leaf_start,
                                 const int64_t *nbr_start, const int32_t *nbr_idx,
                                 const int64_t *red_start, int64_t L, T *dst, bool streaming,
-                                hipStream_t s) {
+                                hipStream_t s, BoxSegments boxes) {
     if (L <= 0) return P2P_OK;
+    if (boxes.box_rows > 0 && (!boxes.red_start || !boxes.red_self))
+        return fail(P2P_EINVAL, "internal: box segments without their arrays");
     const int64_t rb = row_len * static_cast<int64_t>(sizeof(T));
     switch (unit_bytes(rb)) {
     case 16:
-        return copy_units<uint4>(sorted, rb, leaf_start, nbr_start, nbr_idx, red_start, L, dst, streaming, s);
+        return copy_units<uint4>(sorted, rb, leaf_start, nbr_start, nbr_idx, red_start, L, dst, streaming, s,
+                                 boxes);
     case 8:
-        return copy_units<uint2>(sorted, rb, leaf_start, nbr_start, nbr_idx, red_start, L, dst, streaming, s);
+        return copy_units<uint2>(sorted, rb, leaf_start, nbr_start, nbr_idx, red_start, L, dst, streaming, s,
+                                 boxes);
     default:
         return copy_units<uint32_t>(sorted, rb, leaf_start, nbr_start, nbr_idx, red_start, L, dst, streaming,
-                                    s);
+                                    s, boxes);
     }
 }
 
@@ -447,15 +463,15 @@ template p2p_status launch_permute_rows<double2>(const double2 *, const int32_t 
                                                  double2 *, hipStream_t);
 template p2p_status launch_copy_segments<double>(const double *, int64_t, const int32_t *,
                                                  const int64_t *, const int32_t *, const int64_t *,
-                                                 int64_t, double *, bool, hipStream_t);
+                                                 int64_t, double *, bool, hipStream_t, BoxSegments);
 template p2p_status launch_copy_segments<float>(const float *, int64_t, const int32_t *,
                                                 const int64_t *, const int32_t *, const int64_t *,
-                                                int64_t, float *, bool, hipStream_t);
+                                                int64_t, float *, bool, hipStream_t, BoxSegments);
 template p2p_status launch_copy_segments<float2>(const float2 *, int64_t, const int32_t *,
                                                  const int64_t *, const int32_t *, const int64_t *,
-                                                 int64_t, float2 *, bool, hipStream_t);
+                                                 int64_t, float2 *, bool, hipStream_t, BoxSegments);
 template p2p_status launch_copy_segments<double2>(const double2 *, int64_t, const int32_t *,
                                                   const int64_t *, const int32_t *, const int64_t *,
-                                                  int64_t, double2 *, bool, hipStream_t);
+                                                  int64_t, double2 *, bool, hipStream_t, BoxSegments);
 
 }  // namespace p2p

@@ -314,7 +314,9 @@ def test_helmholtz_parity(sides, nrhs):
         red = api.restructure(gt, gn, [gq], prec=prec, nrhs=nrhs)
         ot = oracle.build_tree_grids(sides)
         os_, oi = oracle.neighbors(ot)
-        rs, _, S = oracle.red_offsets(ot, os_, oi)
+        rs, rself, S = oracle.red_offsets(ot, os_, oi)
+        np.testing.assert_array_equal(_n(red.red_start), rs)
+        np.testing.assert_array_equal(_n(red.red_self), rself)
         np.testing.assert_array_equal(_n(red.planes[0])[:S], oracle.restructure_rows(ot, os_, oi, rs, q.astype(cd)))
         for layout in ("gather", "redundant"):
             u = _n(api.helmholtz(gt, gn, gq, layout=layout, prec=prec, red=red))
