@@ -334,13 +334,39 @@ __device__ __forceinline__ void gravity_body(const GravityArgs &a) {
         for_each_source_tile<RED, PER>(A, a.red_start, a.nbr_start, a.nbr_idx, a.nbr_shift, a.src_leaf_start,
                                        s_pre, s_first, s_code, s_w, begin, stage, body);
 
+        // Per-target sums of the G partials, in the order q = 0..G-1.  Lanes
+        // with g >= G never accumulate and are never read.  When 4 tc <= 256,
+        // lane (t, g) with g < 4 sums component g of target t (it already
+        // holds target t's row), so the four sums of a target run in four
+        // lanes; otherwise lane t sums all four.
         __syncthreads();
-        s_red[0][threadIdx.x] = active ? p : 0.0;
-        s_red[1][threadIdx.x] = active ? fx : 0.0;
-        s_red[2][threadIdx.x] = active ? fy : 0.0;
-        s_red[3][threadIdx.x] = active ? fz : 0.0;
+        s_red[0][threadIdx.x] = p;
+        s_red[1][threadIdx.x] = fx;
+        s_red[2][threadIdx.x] = fy;
+        s_red[3][threadIdx.x] = fz;
         __syncthreads();
-        if (static_cast<int>(threadIdx.x) < tc) {
+        // the self pair (d = 0) of phi, computed in the same arithmetic
+        auto self_phi = [&]() -> double {
+            if constexpr (MIXED)
+                return static_cast<double>(tv.w * rsq_f32(eps2f));
+            else
+                return tv.w * rsqrt(eps2);
+        };
+        if (4 * tc <= kGBlock) {
+            if (g < 4) {
+                double s = 0.0;
+                for (int q = 0; q < G; ++q) s += s_red[g][q * tc + t];
+                if constexpr (!EPS0 && !REMOTE) {
+                    if (g == 0) s += self_phi();
+                }
+                double *out = g == 0 ? a.phi : g == 1 ? a.ax : g == 2 ? a.ay : a.az;
+                const int64_t i = a.perm[t0 + tc0 + t];
+                if constexpr (REMOTE)
+                    out[i] += s;
+                else
+                    out[i] = s;
+            }
+        } else if (static_cast<int>(threadIdx.x) < tc) {
             double sp_ = 0.0, sx_ = 0.0, sy_ = 0.0, sz_ = 0.0;
             for (int q = 0; q < G; ++q) {
                 const int l = q * tc + threadIdx.x;
@@ -349,13 +375,7 @@ __device__ __forceinline__ void gravity_body(const GravityArgs &a) {
                 sy_ += s_red[2][l];
                 sz_ += s_red[3][l];
             }
-            // add back the self pair (d = 0), computed in the same arithmetic
-            if constexpr (!EPS0 && !REMOTE) {
-                if constexpr (MIXED)
-                    sp_ += static_cast<double>(tv.w * rsq_f32(eps2f));
-                else
-                    sp_ += tv.w * rsqrt(eps2);
-            }
+            if constexpr (!EPS0 && !REMOTE) sp_ += self_phi();
             const int64_t i = a.perm[t0 + tc0 + threadIdx.x];
             if constexpr (REMOTE) {
                 a.phi[i] += sp_;
@@ -374,8 +394,9 @@ __device__ __forceinline__ void gravity_body(const GravityArgs &a) {
 
 // The FP32-mixed redundant kernel fits in 64 VGPRs without spills, so it asks
 // for 8 waves per SIMD (more workgroups in flight hide the tile staging); the
-// FP32-mixed gather kernel fits 72 without spills (7 waves per SIMD); the FP64
-// variants keep the compiler's register budget.  PER: periodic gather.
+// FP32-mixed gather kernel fits 72 without spills (7 waves per SIMD), its
+// periodic form 80 (6 waves per SIMD; at 72 it spills); the FP64 variants keep
+// the compiler's register budget.  PER: periodic gather.
 template <bool MIXED, bool RED, bool EPS0, bool PER, bool REMOTE>
 __global__ __launch_bounds__(kGBlock) void k_gravity(GravityArgs a) {
     gravity_body<MIXED, RED, EPS0, PER, REMOTE>(a);
@@ -385,10 +406,15 @@ __global__ __launch_bounds__(kGBlock) __attribute__((amdgpu_waves_per_eu(8))) vo
     GravityArgs a) {
     gravity_body<true, true, EPS0, false, false>(a);
 }
-template <bool EPS0, bool PER>
+template <bool EPS0>
 __global__ __launch_bounds__(kGBlock) __attribute__((amdgpu_waves_per_eu(7))) void k_gravity_mixed_gather(
     GravityArgs a) {
-    gravity_body<true, false, EPS0, PER, false>(a);
+    gravity_body<true, false, EPS0, false, false>(a);
+}
+template <bool EPS0>
+__global__ __launch_bounds__(kGBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_gravity_mixed_gather_per(
+    GravityArgs a) {
+    gravity_body<true, false, EPS0, true, false>(a);
 }
 
 // Adjoint of the gravity sums, gather layout.  For target j and each near
@@ -532,15 +558,16 @@ p2p_status launch_gravity(const GravityArgs &a, bool redundant, bool mixed, bool
     // the redundant layout holds shifted rows already; only the gather stages images
     const bool per = !redundant && a.nbr_shift != nullptr;
 #define P2P_GRAV(M, R, E, P) k_gravity<M, R, E, P, false><<<g, kGBlock, 0, s>>>(a)
-#define P2P_GRAV_MG(E, P) k_gravity_mixed_gather<E, P><<<g, kGBlock, 0, s>>>(a)
     if (mixed) {
         if (redundant) {
             if (eps_zero) k_gravity_mixed_red<true><<<g, kGBlock, 0, s>>>(a);
             else k_gravity_mixed_red<false><<<g, kGBlock, 0, s>>>(a);
         } else if (per) {
-            if (eps_zero) P2P_GRAV_MG(true, true); else P2P_GRAV_MG(false, true);
+            if (eps_zero) k_gravity_mixed_gather_per<true><<<g, kGBlock, 0, s>>>(a);
+            else k_gravity_mixed_gather_per<false><<<g, kGBlock, 0, s>>>(a);
         } else {
-            if (eps_zero) P2P_GRAV_MG(true, false); else P2P_GRAV_MG(false, false);
+            if (eps_zero) k_gravity_mixed_gather<true><<<g, kGBlock, 0, s>>>(a);
+            else k_gravity_mixed_gather<false><<<g, kGBlock, 0, s>>>(a);
         }
     } else {
         if (redundant) {
@@ -551,7 +578,6 @@ p2p_status launch_gravity(const GravityArgs &a, bool redundant, bool mixed, bool
             if (eps_zero) P2P_GRAV(false, false, true, false); else P2P_GRAV(false, false, false, false);
         }
     }
-#undef P2P_GRAV_MG
 #undef P2P_GRAV
     P2P_LAUNCH_CHECK();
     return P2P_OK;
