@@ -217,7 +217,9 @@ typedef struct {
     int64_t entries;     /* S */
 } p2p_locality_t;
 
-/* Build the tree (a1: binning; Sec. 5.2, "tree rebuilding at each time step").
+/* Build the tree (binning; the stellar-dynamics code of Sec. 4 rebuilds it
+ * every time step, and Sec. 1.1 names tree building, the data collection, a
+ * major overhead).
  *  Particles: x, y, z caller-order double[n] in [0,1) (else P2P_EDOMAIN),
  *    grids == NULL, n_grids == 0.  leaf_cap == 0: uniform tree of depth
  *    `depth` (0..20, empty leaves dropped).  leaf_cap > 0: adaptive tree, a
@@ -233,7 +235,7 @@ p2p_status p2p_build_tree(const double *x, const double *y, const double *z,
                           int32_t depth, int32_t leaf_cap,
                           p2p_tree *tree, void *ws, size_t *ws_bytes, p2p_stream_t stream);
 
-/* Near-field lists of every leaf (a2: the E2 neighbourhood, Sec. 5.1;
+/* Near-field lists of every leaf (the E2 neighbourhood, Sec. 5.1;
  * Fig. 8 counts them for irregular trees).  nbrs->nbr_start must hold L+1
  * entries; nbrs->periodic selects periodic images (P2P_EINVAL on a grid
  * tree), which also fills nbrs->nbr_shift.  Also sets nbrs->red_entries.
@@ -242,7 +244,7 @@ p2p_status p2p_build_tree(const double *x, const double *y, const double *z,
 p2p_status p2p_build_neighbors(const p2p_tree *tree, p2p_nbrs *nbrs,
                                void *ws, size_t *ws_bytes, p2p_stream_t stream);
 
-/* Restructure to the redundant layout (a3: data redundancy, Sec. 1.1 and
+/* Restructure to the redundant layout (data redundancy, Sec. 1.1 and
  * Sec. 5.2.1; its cost is the "collect" term of Eq. 2).
  *  Gravity trees (particles): src = {x, y, z, m} caller-order double[n];
  *    the payload follows `prec` (FP32_MIXED stores m rounded to float).
@@ -257,7 +259,9 @@ p2p_status p2p_restructure_redundant(const p2p_tree *tree, const p2p_nbrs *nbrs,
                                      p2p_precision prec, p2p_redundant *out,
                                      void *ws, size_t *ws_bytes, p2p_stream_t stream);
 
-/* Near-field gravity (a4 GATHER / a5 REDUNDANT, update a6 fused): for every
+/* Near-field gravity (the P2P compute step of Eq. 2, Sec. 3.2, from the
+ * GATHER layout -- the SoA + indexing baseline of Sec. 5.2.1 -- or from the
+ * REDUNDANT layout of Sec. 5.2.1; the update step of Eq. 2 fused): for every
  * particle i, phi_i and a_i as in the header comment, eps >= 0 (eps == 0
  * drops pairs at zero distance).  x, y, z, m: caller-order double[n] (needed
  * for GATHER; ignored for REDUNDANT, which reads `red`, built with the same
@@ -268,7 +272,9 @@ p2p_status p2p_eval_gravity(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2
                             double *phi, double *ax, double *ay, double *az,
                             void *ws, size_t *ws_bytes, p2p_stream_t stream);
 
-/* Near-field Helmholtz on grid trees (a7 single RHS, a9 multi-RHS, a10
+/* Near-field Helmholtz on grid trees (the dense regular case of Sec. 5.1, the
+ * near-field part of the MLFMA call of Sec. 4-5.1, with precomputed
+ * interaction patterns; single RHS, multi-RHS, and many instances in one
  * batched persistent launch): u_I = sum_{J near I, J != I} e^{ik r}/(4 pi r) q_J
  * for each of the nrhs columns, with h and k of I's instance.  grids: the host
  * array the tree was built from.  q (GATHER) and u: caller order [n][nrhs],
@@ -290,7 +296,8 @@ p2p_status p2p_eval_helmholtz(const p2p_tree *tree, const p2p_nbrs *nbrs, const 
                               const void *q, void *u, const int32_t *tile,
                               void *ws, size_t *ws_bytes, p2p_stream_t stream);
 
-/* Adjoint (a11; not in the paper).
+/* Adjoint (not in the paper; the gradient that the DBIM inversion of Sec. 4
+ * descends along, and the stellar-dynamics forces differentiated).
  *  kind == P2P_KIND_GRAVITY: fwd_in = {x, y, z, m}, grad_out = {g_phi, g_ax,
  *    g_ay, g_az}, grad_in = {g_x, g_y, g_z, g_m}, all caller-order double[n]:
  *    the gradients of L = sum_i g_phi_i phi_i + g_a_i . a_i with respect to
@@ -370,7 +377,7 @@ p2p_status p2p_eval_gravity_remote(const p2p_tree *tree, const p2p_tree *src_tre
                                    double *phi, double *ax, double *ay, double *az,
                                    void *ws, size_t *ws_bytes, p2p_stream_t stream);
 
-/* Locality metric per configuration (a12; Definition 1 and Formulas (10)-(11),
+/* Locality metric per configuration (Definition 1 and Formulas (10)-(11),
  * Sec. 3.4).  D per target leaf is counted on the GPU from the near lists;
  * the rest is host arithmetic.  red may be NULL (S is then computed from the
  * lists).  Synchronises `stream`. */

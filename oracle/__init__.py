@@ -28,15 +28,32 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
+_FLAGS = ["-O3", "-std=c11", "-fopenmp", "-fPIC", "-shared"]
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (OpenMP, -O2; no -march=native so the
-    library runs on any x86-64 host)."""
+    """Compile the oracle with gcc (OpenMP, -O3; no -march=native, so the
+    library built here runs on any x86-64 host)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
-                               _SRC, "-o", tmp, "-lm"])
+        subprocess.check_call(["gcc", *_FLAGS, _SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
+
+
+def use_native(directory: str) -> str:
+    """Compile the same source with -O3 -march=native for the host it runs on,
+    into `directory`, and load that build in place of the portable one (for
+    timing the oracle on the host's cores; the arithmetic is the same C code).
+    Returns the gcc command line."""
+    global _lib
+    out = os.path.join(directory, "liboracle_native.so")
+    cmd = ["gcc", *_FLAGS, "-march=native", _SRC, "-o", out, "-lm"]
+    subprocess.check_call(cmd)
+    lib = ctypes.CDLL(out)
+    _declare(lib)
+    _lib = lib
+    return " ".join(cmd[:-4] + ["p2p_oracle.c"])
 
 
 def _load():
@@ -125,8 +142,8 @@ def set_threads(n: int) -> None:
 # Keys and trees
 # ---------------------------------------------------------------------------
 def morton3(x: int, y: int, z: int, bits: int) -> int:
-    """Bit interleave, x least significant (reading R10 of the near-field
-    ordering: leaves in ascending key order)."""
+    """Bit interleave, x least significant (the ordering this
+    library reads into the paper, which fixes none: leaves in ascending key order)."""
     return int(_load().orc_morton3(x, y, z, bits))
 
 
@@ -177,7 +194,8 @@ class Tree:
 
 def build_tree_particles(x, y, z, depth: int, leaf_cap: int) -> Tree:
     """Octree over the unit cube (Sec. 5.2: an irregular tree rebuilt every
-    step; reading R8: split iff count > leaf_cap and level < depth; leaf_cap = 0
+    step; the split rule the paper leaves open is read as: split iff
+    count > leaf_cap and level < depth; leaf_cap = 0
     means a uniform tree of depth `depth`)."""
     key, bad = particle_keys(x, y, z)
     if bad:
@@ -217,7 +235,7 @@ def build_tree_grids(n_side) -> Tree:
 
 
 def neighbors(tree: Tree, targets=None):
-    """Near lists (the E2 neighbourhood, Sec. 5.1; reading R5: leaves whose
+    """Near lists (the E2 neighbourhood, Sec. 5.1, read for adaptive trees as: leaves whose
     closed cubes touch, the leaf itself included, ascending).  Brute force
     over all leaves.  Returns (nbr_start int64 [T+1], nbr_idx int32 [E])."""
     L = tree.n_leaves
@@ -237,7 +255,8 @@ def neighbors(tree: Tree, targets=None):
 
 
 def neighbors_periodic(tree: Tree, targets=None):
-    """Periodic near lists on the unit torus (reading R27): every (leaf B,
+    """Periodic near lists on the unit torus (the periodic interactions of
+    Sec. 5.2, read as): every (leaf B,
     image c) whose cube shifted by image c touches A's, ascending in (c, B);
     image code c = (sx+1) + 3 (sy+1) + 9 (sz+1) shifts a source by
     (sx, sy, sz) domain edges, 13 = unshifted.  Brute force.  Returns
@@ -420,8 +439,8 @@ def restructure_interactions(tree: Tree, nbr_start, nbr_idx, x, y, z, m, prec="f
 # ---------------------------------------------------------------------------
 def gravity_leaves(x, y, z, m, eps, tree: Tree, sel, sel_nbr_start, sel_nbr_idx,
                    sel_nbr_shift=None):
-    """Near-field gravity for the particles of the selected leaves (reading R1:
-    G = 1, phi negative, Plummer softening; with image codes each source sits
+    """Near-field gravity for the particles of the selected leaves (the paper
+    gives no gravity law; read as G = 1, phi negative, Plummer softening; with image codes each source sits
     at x_j + s).  Returns (caller idx, phi, ax, ay, az)."""
     x, y, z, m = (_c(v, np.float64) for v in (x, y, z, m))
     sel = _c(sel, np.int32)
@@ -498,7 +517,7 @@ def _grid_args(n_side, h=None, kw=None):
 
 def helmholtz(n_side, q, targets=None, h=None, kw=None):
     """u_I = sum_{J near I, J != I} e^{ik r}/(4 pi r) q_J on regular grids
-    (Sec. 5.1; reading R3/R4: 3-D kernel, cell-centred points, k = 2 pi/(10 h)).
+    (Sec. 5.1, read as the 3-D kernel on cell-centred points, k = 2 pi/(10 h)).
     q: complex [N, nrhs] (or [N]) in caller order.  Returns complex128
     [len(targets), nrhs] (or [len(targets)])."""
     n_side, h, kw, off = _grid_args(n_side, h, kw)
@@ -533,7 +552,7 @@ def helmholtz_transpose(n_side, g, h=None, kw=None):
 # Locality
 # ---------------------------------------------------------------------------
 def locality(nbr_start, nbr_idx, n, S, bytes_per_entry, cache_bytes):
-    """Definition 1 with Formulas (10)/(11) (Sec. 3.4); reading R19: D = runs
+    """Definition 1 with Formulas (10)/(11) (Sec. 3.4), read as: D = runs
     of consecutive leaf ids, V = whole footprint per layout, C = cache bytes."""
     out = np.zeros(6)
     nbr_start = _c(nbr_start, np.int64)

@@ -127,6 +127,28 @@ p2p_status check_remote_trees(const p2p_tree *tree, const p2p_tree *src_tree) {
     return P2P_OK;
 }
 
+// Softening length of the gravity sums.  eps == 0 drops pairs at zero
+// distance.  A positive eps keeps every pair: the kernels sum the target's own
+// d = 0 term m_i / eps with the others and subtract it again afterwards, so
+// the rounding of the sum that held it, about 2^-24 m_i / eps in a
+// single-precision partial (FP32_MIXED) or 2^-53 m_i / eps (FP64), stays in
+// phi_i.  Against a near-field potential of a few thousand m_i (a sparse
+// target: tens of neighbours at a few hundredths) that stays within the
+// stated tolerances (1e-5 relative in FP32_MIXED, 1e-12 in FP64) for
+// eps >= 1e-4 and eps >= 1e-8 respectively; smaller positive eps is refused
+// rather than summed inexactly (eps == 0 remains available).
+constexpr double kMinEpsMixed = 1e-4;
+constexpr double kMinEpsFp64 = 1e-8;
+
+p2p_status check_eps(double eps, bool mixed, bool positive = false) {
+    if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(P2P_EINVAL, "eps must be finite and >= 0");
+    if (positive && eps == 0.0) return fail(P2P_EINVAL, "the gravity adjoint needs eps > 0");
+    const double lo = mixed ? kMinEpsMixed : kMinEpsFp64;
+    if (eps > 0.0 && eps < lo)
+        return fail(P2P_EINVAL, std::string("eps must be 0 or >= ") + (mixed ? "1e-4 with P2P_FP32_MIXED" : "1e-8 with P2P_FP64"));
+    return P2P_OK;
+}
+
 // Image codes of periodic lists, null for plain ones.
 const int8_t *shifts(const p2p_nbrs *nb) { return nb->periodic ? nb->nbr_shift : nullptr; }
 
@@ -138,7 +160,7 @@ using namespace p2p;
 extern "C" const char *p2p_last_error(void) { return g_err.c_str(); }
 extern "C" const char *p2p_version(void) { return "libp2p 0.1.0 (gfx950)"; }
 
-// ------------------------------------------------------------------ a1 ----
+// ---------------------------------------------------------------- tree ----
 extern "C" p2p_status p2p_build_tree(const double *x, const double *y, const double *z,
                                      const p2p_grid *grids, int32_t n_grids, int32_t depth,
                                      int32_t leaf_cap, p2p_tree *tree, void *ws, size_t *ws_bytes,
@@ -242,7 +264,7 @@ extern "C" p2p_status p2p_build_tree(const double *x, const double *y, const dou
     return P2P_OK;
 }
 
-// ------------------------------------------------------------------ a2 ----
+// ---------------------------------------------------------- near lists ----
 namespace p2p {
 namespace {
 
@@ -329,7 +351,7 @@ extern "C" p2p_status p2p_build_neighbors_remote(const p2p_tree *tree, const p2p
     return neighbors_common(tree, src_tree, nbrs, ws, ws_bytes, as_stream(stream));
 }
 
-// ------------------------------------------------------------------ a3 ----
+// --------------------------------------------------------- restructure ----
 namespace p2p {
 namespace {
 
@@ -543,8 +565,8 @@ extern "C" p2p_status p2p_eval_gravity_interactions(const p2p_tree *tree, const 
     if (!inter) return fail(P2P_EINVAL, "inter is NULL");
     if (inter->prec != P2P_FP64 && inter->prec != P2P_FP32_MIXED) return fail(P2P_EINVAL, "inter was not built");
     if (inter->target_rows < 0) return fail(P2P_EINVAL, "inter->target_rows < 0");
-    if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(P2P_EINVAL, "eps must be finite and >= 0");
     const bool mixed = inter->prec == P2P_FP32_MIXED;
+    P2P_TRY(check_eps(eps, mixed));
     const int64_t n = tree->n, L = tree->n_leaves, E = nbrs->count;
     Arena ar(ws);
     int32_t *tgt_len = ar.take<int32_t>(E);
@@ -567,7 +589,7 @@ extern "C" p2p_status p2p_eval_gravity_interactions(const p2p_tree *tree, const 
     return P2P_OK;
 }
 
-// ---------------------------------------------------------------- a4/a5 ---
+// ------------------------------------------------------------- gravity ----
 extern "C" p2p_status p2p_eval_gravity(const p2p_tree *tree, const p2p_nbrs *nbrs,
                                        const p2p_redundant *red, p2p_layout layout,
                                        p2p_precision prec, double eps, const double *x,
@@ -581,8 +603,8 @@ extern "C" p2p_status p2p_eval_gravity(const p2p_tree *tree, const p2p_nbrs *nbr
     P2P_TRY(check_nbrs(tree, nbrs));
     if (layout != P2P_GATHER && layout != P2P_REDUNDANT) return fail(P2P_EINVAL, "bad layout");
     if (prec != P2P_FP64 && prec != P2P_FP32_MIXED) return fail(P2P_EINVAL, "bad precision");
-    if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(P2P_EINVAL, "eps must be finite and >= 0");
     const bool mixed = prec == P2P_FP32_MIXED, redundant = layout == P2P_REDUNDANT;
+    P2P_TRY(check_eps(eps, mixed));
     const int64_t n = tree->n;
     Arena ar(ws);
     Row4d *s4 = redundant ? nullptr : ar.take<Row4d>(n);
@@ -641,8 +663,8 @@ extern "C" p2p_status p2p_eval_gravity_remote(const p2p_tree *tree, const p2p_tr
     P2P_TRY(check_nbrs(tree, nbrs, true));
     if (layout != P2P_GATHER && layout != P2P_REDUNDANT) return fail(P2P_EINVAL, "bad layout");
     if (prec != P2P_FP64 && prec != P2P_FP32_MIXED) return fail(P2P_EINVAL, "bad precision");
-    if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(P2P_EINVAL, "eps must be finite and >= 0");
     const bool mixed = prec == P2P_FP32_MIXED, redundant = layout == P2P_REDUNDANT;
+    P2P_TRY(check_eps(eps, mixed));
     const int64_t n = tree->n, ns = src_tree->n;
     Arena ar(ws);
     p2p_status st;
@@ -693,7 +715,7 @@ extern "C" p2p_status p2p_eval_gravity_remote(const p2p_tree *tree, const p2p_tr
     return launch_gravity_remote(a, redundant, mixed, eps == 0.0, s);
 }
 
-// ---------------------------------------------------------------- a7/a9 ---
+// ----------------------------------------------------------- Helmholtz ----
 namespace {
 
 struct HelmPlan {
@@ -921,7 +943,7 @@ extern "C" p2p_status p2p_eval_helmholtz(const p2p_tree *tree, const p2p_nbrs *n
                             ws_bytes, as_stream(stream));
 }
 
-// ------------------------------------------------------------------ a11 ---
+// ------------------------------------------------------------- adjoint ----
 extern "C" p2p_status p2p_adjoint(int32_t kind, const p2p_tree *tree, const p2p_nbrs *nbrs,
                                   const p2p_redundant *red, p2p_layout layout, p2p_precision prec,
                                   double eps, const p2p_grid *grids, int32_t n_grids, int32_t nrhs,
@@ -947,7 +969,7 @@ extern "C" p2p_status p2p_adjoint(int32_t kind, const p2p_tree *tree, const p2p_
     P2P_TRY(check_nbrs(tree, nbrs));
     if (layout != P2P_GATHER) return fail(P2P_EUNSUPPORTED, "gravity adjoint uses the GATHER layout");
     if (prec != P2P_FP64 && prec != P2P_FP32_MIXED) return fail(P2P_EINVAL, "bad precision");
-    if (!(eps > 0.0) || !std::isfinite(eps)) return fail(P2P_EINVAL, "gravity adjoint needs eps > 0");
+    P2P_TRY(check_eps(eps, prec == P2P_FP32_MIXED, true));
     const int64_t n = tree->n;
     Arena ar(ws);
     Row4d *s4 = ar.take<Row4d>(n);
@@ -980,7 +1002,7 @@ extern "C" p2p_status p2p_adjoint(int32_t kind, const p2p_tree *tree, const p2p_
     return launch_gravity_adjoint(a, prec == P2P_FP32_MIXED, s);
 }
 
-// ------------------------------------------------------------------ a12 ---
+// ------------------------------------------------------------ Locality ----
 extern "C" p2p_status p2p_locality(const p2p_tree *tree, const p2p_nbrs *nbrs,
                                    const p2p_redundant *red, double bytes_per_entry,
                                    double cache_bytes, p2p_locality_t *out, void *ws,

@@ -1,5 +1,5 @@
-// Near-field gravity (a4 gather, a5 redundant, a6 fused update, a8 mixed
-// precision) and its adjoint (a11).
+// Near-field gravity (gather and redundant layouts, Sec. 5.2.1, with the
+// update fused; FP64 or FP32-mixed) and its adjoint.
 //
 // One 256-thread workgroup owns one target leaf.  Leaves hold 1..64 targets
 // in an adaptive tree, so lanes are split two ways: with tc targets in the

@@ -1,5 +1,5 @@
-// Near-field Helmholtz on regular grids, VALU path (a7; also the FP64 and
-// ragged-RHS fallback of a9).
+// Near-field Helmholtz on regular grids, VALU path (Sec. 5.1; FP64, and
+// right-hand-side counts the matrix-core kernels do not take).
 //
 // Grid leaves are boxes of 4x4x4 points.  One wavefront owns one target box:
 // lane l holds the target at local Morton index l.  For each near box B the

@@ -1,5 +1,6 @@
-// Multi-RHS near-field Helmholtz on FP32 matrix cores (a9) in one persistent
-// launch over every box of every grid instance (a10).
+// Multi-RHS near-field Helmholtz on FP32 matrix cores in one persistent
+// launch over every box of every grid instance (the dense regular case of
+// Sec. 5.1, many instances batched).
 //
 // For target box b (64 points) and R right-hand sides:
 //     U_b (64 x R) = sum_{o in near offsets} G_o (64 x 64) Q_{b+o} (64 x R),

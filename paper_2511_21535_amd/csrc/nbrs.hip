@@ -1,4 +1,4 @@
-// Near-field lists (a2): for every leaf A, every leaf B whose closed cube
+// Near-field lists (the E2 neighbourhood, Sec. 5.1): for every leaf A, every leaf B whose closed cube
 // touches A's, A included, in ascending leaf id.
 //
 // One wavefront per leaf.  Lanes 0..26 each take one of the 27 cells of A's

@@ -1,4 +1,4 @@
-// Restructure to the redundant layout (a3) and the gather-to-sorted-order
+// Restructure to the redundant layout (Sec. 1.1, Sec. 5.2.1) and the gather-to-sorted-order
 // permutations it and the gather layout share.
 //
 // The redundant segment of target leaf A is the concatenation, for B in

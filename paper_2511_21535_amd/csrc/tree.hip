@@ -1,4 +1,5 @@
-// Tree binning (a1): integer keys, and leaf boundaries over the sorted keys.
+// Tree binning (Sec. 4: the stellar-dynamics tree is rebuilt every step):
+// integer keys, and leaf boundaries over the sorted keys.
 //
 // Particles: c_d = floor(x_d 2^20), key = Morton(c).  The sort itself is
 // radix_sort_pairs.  Leaves of an adaptive tree are found without walking

@@ -101,6 +101,33 @@ def test_eval_rejects_bad_modes(lib):
     assert lib.p2p_eval_gravity(*args(L.P2P_GATHER, L.P2P_FP64, 1e-3)) == L.P2P_EINVAL
 
 
+@pytest.mark.parametrize("prec,eps,ok", [
+    (L.P2P_FP32_MIXED, 0.0, True), (L.P2P_FP32_MIXED, 1e-4, True), (L.P2P_FP32_MIXED, 9.9e-5, False),
+    (L.P2P_FP32_MIXED, 1e-30, False), (L.P2P_FP64, 1e-8, True), (L.P2P_FP64, 1e-3, True),
+    (L.P2P_FP64, 9.9e-9, False), (L.P2P_FP64, 5e-324, False)])
+def test_eval_rejects_tiny_softening(lib, prec, eps, ok):
+    """A positive eps whose own d = 0 term m/eps, summed and subtracted again,
+    would leave more rounding in phi than the stated tolerance (below 1e-4 in
+    FP32_MIXED, 1e-8 in FP64) is refused on the host, by every gravity entry
+    point that takes eps; eps = 0 stays available."""
+    t = _tree(10, L_=1)
+    t.perm = t.iperm = t.leaf_start = t.leaf_key = t.leaf_level = 0x1000
+    n = L.p2p_nbrs()
+    n.count, n.nbr_start, n.nbr_idx = 1, 0x1000, 0x1000
+    nb = ctypes.c_size_t(0)
+    z = ctypes.c_void_p(0x1000)
+    want = L.P2P_OK if ok else L.P2P_EINVAL       # OK: the workspace size query went through
+    st = lib.p2p_eval_gravity(ctypes.byref(t), ctypes.byref(n), None, L.P2P_GATHER, prec, eps,
+                              z, z, z, z, z, z, z, z, None, ctypes.byref(nb), None)
+    assert st == want, L.last_error()
+    if not ok:
+        assert "eps must be 0 or >=" in L.last_error()
+    if eps > 0:
+        st = lib.p2p_adjoint(L.P2P_KIND_GRAVITY, ctypes.byref(t), ctypes.byref(n), None, L.P2P_GATHER,
+                             prec, eps, None, 0, 1, 0, None, None, None, None, ctypes.byref(nb), None)
+        assert st == want, L.last_error()
+
+
 def test_adjoint_unsupported_combinations(lib):
     t = _tree(10, L_=1)
     t.perm = t.iperm = t.leaf_start = t.leaf_key = t.leaf_level = 0x1000

@@ -178,9 +178,21 @@ def test_heavy_leaf_lists(periodic):
         assert _rel(o[0], ref[0]) <= TOL32 and _rel(np.stack(o[1:]), np.stack(ref[1:])) <= TOL32
 
 
+# the smallest positive softening each precision accepts
+EPS_MIN = {"fp64": 1e-8, "fp32": 1e-4}
+
+
 @pytest.mark.parametrize("gen,n,seed,depth,cap", PARTICLE_CASES[:4] + PARTICLE_CASES[6:])
-@pytest.mark.parametrize("eps", [1e-3, 0.0])
+@pytest.mark.parametrize("eps", [1e-3, 0.0, "min"])
 def test_gravity_parity(gen, n, seed, depth, cap, eps):
+    if eps == "min":
+        for prec, tol in (("fp64", TOL64), ("fp32", TOL32)):
+            _gravity_case(gen, n, seed, depth, cap, EPS_MIN[prec], [(prec, tol)])
+    else:
+        _gravity_case(gen, n, seed, depth, cap, eps, [("fp64", TOL64), ("fp32", TOL32)])
+
+
+def _gravity_case(gen, n, seed, depth, cap, eps, precs):
     x, y, z, m = _particles_case(gen, n, seed, depth, cap)
     if eps == 0.0:
         # distinct points only (eps = 0 drops zero-distance pairs; the definition diverges there)
@@ -191,7 +203,7 @@ def test_gravity_parity(gen, n, seed, depth, cap, eps):
     gn = gt.neighbors()
     ot = oracle.build_tree_particles(x, y, z, depth=depth, leaf_cap=cap)
     ref = oracle.gravity(x, y, z, m, eps, ot)
-    for prec, tol in (("fp64", TOL64), ("fp32", TOL32)):
+    for prec, tol in precs:
         red = api.restructure_gravity(gt, gn, gx, gy, gz, gm, prec=prec)
         for layout in ("gather", "redundant"):
             out = api.gravity(gt, gn, eps, x=gx, y=gy, z=gz, m=gm, layout=layout, prec=prec, red=red)
@@ -426,15 +438,20 @@ def test_locality_matches_oracle():
     x, y, z, m = W.plummer_mixture(20000, 51)
     gt = api.Tree.build_particles(_t(x), _t(y), _t(z), depth=20, leaf_cap=64)
     gn = gt.neighbors()
-    loc = api.locality(gt, gn, bytes_per_entry=28.0, cache_bytes=32 * 2 ** 20)
     ot = oracle.build_tree_particles(x, y, z, depth=20, leaf_cap=64)
     os_, oi = oracle.neighbors(ot)
     _, _, S = oracle.red_offsets(ot, os_, oi)
-    ref = oracle.locality(os_, oi, len(x), S, 28.0, 32 * 2 ** 20)
-    assert loc["entries"] == S
-    assert loc["pairs"] == oracle.pair_count(ot, os_, oi)
-    for k_g, k_o in (("d_mean", "D_mean"), ("v_ratio", "V_ratio"), ("locality", "locality")):
-        assert abs(loc[k_g] - ref[k_o]) <= 1e-12 * abs(ref[k_o])
+    v_red = S * 28.0
+    # Formula (10) (the layout fits: 32 MB, and the equality edge) and Formula (11)
+    # (a cache below the layout's size)
+    for cache in (32 * 2 ** 20, v_red, v_red - 1.0, v_red / 4):
+        loc = api.locality(gt, gn, bytes_per_entry=28.0, cache_bytes=cache)
+        ref = oracle.locality(os_, oi, len(x), S, 28.0, cache)
+        assert loc["entries"] == S
+        assert loc["pairs"] == oracle.pair_count(ot, os_, oi)
+        for k_g, k_o in (("d_mean", "D_mean"), ("v_ratio", "V_ratio"), ("locality", "locality")):
+            assert abs(loc[k_g] - ref[k_o]) <= 1e-12 * abs(ref[k_o]), (cache, k_g)
+    assert v_red < 32 * 2 ** 20 and ref["D_ratio"] > 2.0     # the branches give different values here
 
 
 def test_capacity_errors_leave_outputs_untouched():

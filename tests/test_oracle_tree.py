@@ -215,8 +215,33 @@ def test_locality_hand_values():
     assert S == 8 * len(x)
     loc = oracle.locality(s1, i1, len(x), S, 32.0, cache_bytes=1e12)
     assert loc["D_mean"] == 1.0 and loc["V_ratio"] == 0.125 and loc["locality"] == 0.125
-    loc = oracle.locality(s1, i1, len(x), S, 32.0, cache_bytes=1.0)
-    assert loc["locality"] == 0.125 / 1.0 * 1.0 / 1.0 or loc["locality"] == 0.125
+
+
+def test_locality_formula_branches():
+    """Formula (10) D'V' while the redundant layout fits the cache (V_red <= C,
+    the equality included), Formula (11) V'/D' beyond it, on a case where the
+    two differ (D' != 1).  One particle at the centre of every leaf of a full
+    uniform depth-2 tree (4x4x4 leaves): N = 64, S = (3*4 - 2)^3 = 1000, so
+    V' = 64/1000.  The runs of consecutive Morton ids in the 64 near lists,
+    counted by hand from the lattice (corner leaves 1 run ... 13 runs for the
+    most scattered interior leaves), total 344, so D' = 344/64 = 5.375."""
+    c = (np.arange(4) + 0.5) / 4
+    x, y, z = (a.ravel() for a in np.meshgrid(c, c, c, indexing="ij"))
+    t = oracle.build_tree_particles(x, y, z, depth=2, leaf_cap=0)
+    start, idx = oracle.neighbors(t)
+    _, _, S = oracle.red_offsets(t, start, idx)
+    assert t.n_leaves == 64 and S == 1000
+    b = 32.0
+    v_red = S * b
+    d_p, v_p = 344 / 64, 64 / 1000
+    for cache, want in ((1e12, d_p * v_p), (v_red, d_p * v_p),                   # (10): fits, and the edge
+                        (v_red - 1.0, v_p / d_p), (1.0, v_p / d_p)):             # (11): exceeds
+        loc = oracle.locality(start, idx, 64, S, b, cache_bytes=cache)
+        assert loc["D_mean"] == 5.375 and loc["D_ratio"] == 5.375
+        assert abs(loc["V_ratio"] - 0.064) <= 1e-15
+        assert abs(loc["locality"] - want) <= 1e-15 * want, (cache, loc["locality"], want)
+    # the two branches really differ here: 0.344 against about 0.0119
+    assert abs(d_p * v_p - 0.344) < 1e-15 and abs(v_p / d_p - 0.011906976744186046) < 1e-15
 
 
 def test_relative_payload_from_rows_and_centres():
