@@ -116,6 +116,8 @@ def _declare(lib):
     lib.orc_helmholtz.argtypes = [I32, P, P, P, P, I32, P, P, I64, P]
     lib.orc_helmholtz_transpose.restype = None
     lib.orc_helmholtz_transpose.argtypes = [I32, P, P, P, P, I64, I32, P, P]
+    lib.orc_tile_layout.restype = I64
+    lib.orc_tile_layout.argtypes = [I64, P, P, P, I32, P, P, P, P, P, P, P, I64, P]
     lib.orc_locality.restype = None
     lib.orc_locality.argtypes = [I64, P, P, I64, I64, F64, F64, P]
 
@@ -377,6 +379,45 @@ def restructure_rows(tree: Tree, nbr_start, nbr_idx, red_start, src):
     _load().orc_restructure_rows(tree.n_leaves, _p(tree.leaf_start), _p(tree.perm),
                                  _p(_c(nbr_start, np.int64)), _p(_c(nbr_idx, np.int32)),
                                  _p(_c(red_start, np.int64)), _p(src), row_bytes, _p(out))
+    return out
+
+
+def tile_layout(tree: Tree, nbr_start, nbr_idx, grain: int):
+    """Block-level redundancy on a grid tree (Sec. 3.5: for dense, regular
+    distributions, data duplicated per thread block rather than per thread):
+    tiles of grain^3 boxes, each with one segment holding the rows of the union
+    of its boxes' near lists.  Returns (tile_first int32 [T+1], halo_start
+    int64 [T+1], halo_idx int32 [H], seg_start int64 [T+1], red_row int64 [E]):
+    the tiles' first boxes, the halo boxes of each tile (ascending), the first
+    row of each tile's segment, and for every near-list entry (A, B) the first
+    row of B in the segment of A's tile."""
+    if tree.kind != "grids":
+        raise ValueError("tiles are defined on grid trees")
+    L = tree.n_leaves
+    nbr_start, nbr_idx = _c(nbr_start, np.int64), _c(nbr_idx, np.int32)
+    tf = np.zeros(L + 1, dtype=np.int32)
+    hs = np.zeros(L + 1, dtype=np.int64)
+    ss = np.zeros(L + 1, dtype=np.int64)
+    H = ctypes.c_int64(0)
+    lib = _load()
+    args = (L, _p(tree.anchor), _p(tree.inst), _p(tree.leaf_start), int(grain), _p(nbr_start), _p(nbr_idx),
+            _p(tf), _p(hs), _p(ss))
+    lib.orc_tile_layout(*args, None, None, 0, ctypes.byref(H))
+    hi = np.zeros(max(H.value, 1), dtype=np.int32)
+    rr = np.zeros(max(nbr_idx.shape[0], 1), dtype=np.int64)
+    T = lib.orc_tile_layout(*args, _p(hi), _p(rr), H.value, ctypes.byref(H))
+    return tf[:T + 1].copy(), hs[:T + 1].copy(), hi[:H.value].copy(), ss[:T + 1].copy(), rr[:nbr_idx.shape[0]].copy()
+
+
+def restructure_tile_rows(tree: Tree, halo_start, halo_idx, seg_start, src):
+    """The payload of the tile segments: for each tile, the rows of `src`
+    (caller order) of its halo boxes' sorted slots, bit for bit."""
+    src = np.ascontiguousarray(src)
+    row_bytes = src.strides[0] if src.ndim > 0 else src.itemsize
+    out = np.zeros((int(seg_start[-1]),) + src.shape[1:], dtype=src.dtype)
+    _load().orc_restructure_rows(len(halo_start) - 1, _p(tree.leaf_start), _p(tree.perm),
+                                 _p(_c(halo_start, np.int64)), _p(_c(halo_idx, np.int32)),
+                                 _p(_c(seg_start, np.int64)), _p(src), row_bytes, _p(out))
     return out
 
 

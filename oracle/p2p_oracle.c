@@ -867,6 +867,109 @@ void orc_helmholtz_transpose(int32_t n_grids, const int32_t *n_side, const doubl
 }
 
 /* ------------------------------------------------------------------------ */
+/* Block-level redundancy on grid trees (Sec. 3.5)                          */
+/* ------------------------------------------------------------------------ */
+
+static int orc_cmp_i32(const void *a, const void *b)
+{
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+/* For dense, regular distributions Sec. 3.5 duplicates data per thread block
+ * instead of per thread.  Here the block is a tile of grid boxes: box (i, j, k)
+ * of an instance (the indices of its first point divided by 4) belongs to tile
+ * (i / grain, j / grain, k / grain) of that instance.  Tiles are numbered in
+ * ascending order of their smallest box id, tile_first[t] being that id.  The
+ * halo of tile t is the union of the near lists of its boxes, in ascending box
+ * id: halo_idx[halo_start[t] .. halo_start[t+1]).  The tile's segment holds
+ * the rows of its halo boxes in that order, from row seg_start[t] on (rows =
+ * sorted slots, so a box contributes its occupancy).  For entry e = (A, B) of
+ * A's near list, red_row[e] is the first row of B in the segment of A's tile.
+ * grain = 1 gives the box-grain segments.  Writes tile_first, halo_start and
+ * seg_start (n_tiles + 1 entries each, capacity L + 1) and, if the halo total
+ * fits in `cap`, halo_idx and red_row.  Returns n_tiles; *halo_total = H. */
+int64_t orc_tile_layout(int64_t L, const int32_t *anchor, const int32_t *inst, const int32_t *leaf_start,
+                        int32_t grain, const int64_t *nbr_start, const int32_t *nbr_idx,
+                        int32_t *tile_first, int64_t *halo_start, int64_t *seg_start,
+                        int32_t *halo_idx, int64_t *red_row, int64_t cap, int64_t *halo_total)
+{
+    /* group the boxes by tile key; a group's first box is its smallest id */
+    orc_pair *pr = (orc_pair *)malloc(sizeof(orc_pair) * (size_t)(L > 0 ? L : 1));
+    for (int64_t A = 0; A < L; ++A) {
+        uint64_t g = inst ? (uint64_t)inst[A] : 0;
+        uint64_t ti = (uint64_t)(anchor[3 * A + 0] / 4 / grain);
+        uint64_t tj = (uint64_t)(anchor[3 * A + 1] / 4 / grain);
+        uint64_t tk = (uint64_t)(anchor[3 * A + 2] / 4 / grain);
+        pr[A].key = ((g * 1024u + ti) * 1024u + tj) * 1024u + tk;
+        pr[A].idx = A;
+    }
+    qsort(pr, (size_t)L, sizeof(orc_pair), orc_cmp_pair);
+    int64_t *tile_of = (int64_t *)malloc(sizeof(int64_t) * (size_t)(L > 0 ? L : 1));
+    orc_pair *first = (orc_pair *)malloc(sizeof(orc_pair) * (size_t)(L > 0 ? L : 1));
+    int64_t T = 0;
+    for (int64_t s = 0; s < L; ++s) {
+        if (s == 0 || pr[s].key != pr[s - 1].key) {
+            first[T].key = (uint64_t)pr[s].idx;   /* sorted by (key, idx): the smallest id */
+            first[T].idx = T;
+            ++T;
+        }
+    }
+    /* tiles in ascending order of their first box */
+    qsort(first, (size_t)T, sizeof(orc_pair), orc_cmp_pair);
+    int64_t *rank = (int64_t *)malloc(sizeof(int64_t) * (size_t)(T > 0 ? T : 1));
+    for (int64_t t = 0; t < T; ++t) { rank[first[t].idx] = t; tile_first[t] = (int32_t)first[t].key; }
+    tile_first[T] = (int32_t)L;
+    int64_t grp = -1;
+    for (int64_t s = 0; s < L; ++s) {
+        if (s == 0 || pr[s].key != pr[s - 1].key) ++grp;
+        tile_of[pr[s].idx] = rank[grp];
+    }
+    /* halo of each tile: its boxes' list entries, sorted, duplicates dropped */
+    int64_t *hcount = (int64_t *)calloc((size_t)(T > 0 ? T : 1), sizeof(int64_t));
+    int32_t **hal = (int32_t **)calloc((size_t)(T > 0 ? T : 1), sizeof(int32_t *));
+    int64_t *hlen = (int64_t *)calloc((size_t)(T > 0 ? T : 1), sizeof(int64_t));
+    for (int64_t A = 0; A < L; ++A) hcount[tile_of[A]] += nbr_start[A + 1] - nbr_start[A];
+    for (int64_t t = 0; t < T; ++t) hal[t] = (int32_t *)malloc(sizeof(int32_t) * (size_t)(hcount[t] > 0 ? hcount[t] : 1));
+    for (int64_t A = 0; A < L; ++A) {
+        int64_t t = tile_of[A];
+        for (int64_t e = nbr_start[A]; e < nbr_start[A + 1]; ++e) hal[t][hlen[t]++] = nbr_idx[e];
+    }
+    halo_start[0] = 0;
+    seg_start[0] = 0;
+    for (int64_t t = 0; t < T; ++t) {
+        qsort(hal[t], (size_t)hlen[t], sizeof(int32_t), orc_cmp_i32);
+        int64_t u = 0;
+        for (int64_t h = 0; h < hlen[t]; ++h)
+            if (h == 0 || hal[t][h] != hal[t][h - 1]) hal[t][u++] = hal[t][h];
+        hlen[t] = u;
+        int64_t rows = 0;
+        for (int64_t h = 0; h < u; ++h) rows += leaf_start[hal[t][h] + 1] - leaf_start[hal[t][h]];
+        halo_start[t + 1] = halo_start[t] + u;
+        seg_start[t + 1] = seg_start[t] + rows;
+    }
+    int64_t H = halo_start[T];
+    *halo_total = H;
+    if (H <= cap && halo_idx && red_row) {
+        for (int64_t t = 0; t < T; ++t)
+            for (int64_t h = 0; h < hlen[t]; ++h) halo_idx[halo_start[t] + h] = hal[t][h];
+        for (int64_t A = 0; A < L; ++A) {
+            int64_t t = tile_of[A];
+            for (int64_t e = nbr_start[A]; e < nbr_start[A + 1]; ++e) {
+                /* rows of the halo boxes before B in the tile's segment */
+                int64_t row = seg_start[t];
+                for (int64_t h = 0; h < hlen[t] && hal[t][h] != nbr_idx[e]; ++h)
+                    row += leaf_start[hal[t][h] + 1] - leaf_start[hal[t][h]];
+                red_row[e] = row;
+            }
+        }
+    }
+    for (int64_t t = 0; t < T; ++t) free(hal[t]);
+    free(hal); free(hlen); free(hcount); free(rank); free(first); free(tile_of); free(pr);
+    return T;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Locality (Definition 1, Formulas (10)-(11))                              */
 /* ------------------------------------------------------------------------ */
 
