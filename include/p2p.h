@@ -84,9 +84,16 @@ typedef enum { P2P_GATHER = 0, P2P_REDUNDANT = 1 } p2p_layout;
  * for removing the large offset from coordinates (gravity: each position is
  * taken relative to the centre of the target leaf in double and rounded to
  * single once per (target leaf, source)) and for the per-target accumulation
- * of single-precision partial sums (at most 32 pair terms each).  Helmholtz
- * multi-RHS blocks run on FP32 matrix cores. */
-typedef enum { P2P_FP64 = 0, P2P_FP32_MIXED = 1 } p2p_precision;
+ * of single-precision partial sums (gravity: at most 32 pair terms each;
+ * Helmholtz: the 64 terms of one near box, each box's FP32 partial product
+ * added into a double sum per target and right-hand side).  Helmholtz
+ * blocks run on FP32 matrix cores when there is one right-hand side or a
+ * multiple of 32.
+ * P2P_FP32 (Helmholtz only; gravity calls return P2P_EUNSUPPORTED): as
+ * FP32_MIXED, but the sums over all near boxes stay in single precision.
+ * Layouts built with FP32_MIXED and FP32 hold the same payload and serve
+ * either. */
+typedef enum { P2P_FP64 = 0, P2P_FP32_MIXED = 1, P2P_FP32 = 2 } p2p_precision;
 
 enum { P2P_TREE_PARTICLES = 0, P2P_TREE_GRIDS = 1 };
 enum { P2P_KIND_GRAVITY = 0, P2P_KIND_HELMHOLTZ = 1 };
@@ -156,11 +163,24 @@ typedef struct {
                             periodic = 1 (then required once E > 0) */
 } p2p_nbrs;
 
-/* Redundant layout.  Segment A = entries [red_start[A], red_start[A+1]) holds,
- * for B in nbr(A) in order, the rows of B's sorted slots in order; A's own
- * rows (the unshifted image) start at red_start[A] + red_self[A].
- * S = red_start[L] entries.  With periodic lists the gravity rows of an entry
- * hold the shifted positions x + s.
+/* Redundant layout.
+ * Box grain (grain 0 or 1; the per-target redundancy of Sec. 5.2.1):
+ * segment A = entries [red_start[A], red_start[A+1]) holds, for B in nbr(A)
+ * in order, the rows of B's sorted slots in order; A's own rows (the
+ * unshifted image) start at red_start[A] + red_self[A].  S = red_start[L]
+ * entries.  With periodic lists the gravity rows of an entry hold the shifted
+ * positions x + s.
+ * Tile grain (grain 2 or 4, grid trees only; the per-block redundancy that
+ * Sec. 3.5 names for dense regular distributions): the boxes of an instance
+ * are grouped into tiles, aligned blocks of grain^3 boxes (fewer at the upper
+ * faces), each one contiguous run of leaves in key order.  A tile's segment
+ * holds the rows of its halo -- the union of its boxes' near lists -- box by
+ * box in ascending leaf id, 64 rows per box; tiles follow each other in leaf
+ * order.  red_start[A] is the first row of the segment of A's tile (so
+ * red_start[L] = S), and red_row[e], for entry e = (A, B) of the near lists,
+ * the first row of B in that segment.  red_self is not written.  A box's
+ * sources are read through red_row; the layout holds about
+ * ((grain+2)/grain)^3 copies of each box instead of 27.
  * Payload planes (device):
  *   gravity FP64: planes[0] = double[S][4] rows (x, y, z, m), 32-byte rows;
  *   gravity FP32_MIXED: planes[0] = float4[S] (x - c, y - c, z - c, m), where c
@@ -179,7 +199,8 @@ typedef struct {
     int32_t nrhs;       /* out: RHS per row (Helmholtz) */
     int32_t kind;       /* out: P2P_KIND_* */
     int32_t prec;       /* out: p2p_precision of the payload */
-    int32_t reserved;
+    int32_t grain;      /* in: 0 or 1 = box grain; 2 or 4 = tiles of grain^3 boxes (grid trees) */
+    int64_t *red_row;   /* device [E] (tile grain): first row of each near-list entry's source box */
 } p2p_redundant;
 
 /* Per-interaction redundant layout (gravity; the thread-level redundancy of
@@ -253,7 +274,12 @@ p2p_status p2p_build_neighbors(const p2p_tree *tree, p2p_nbrs *nbrs,
  * out->red_start (L+1), out->red_self (L) and the planes must be allocated;
  * P2P_ECAPACITY (out->count = S) if S > out->cap.  S is taken from
  * nbrs->red_entries; only if that is negative is it counted on the GPU and
- * read back (synchronising `stream`). */
+ * read back (synchronising `stream`).
+ * out->grain selects the redundancy grain (see p2p_redundant): 0 or 1 box
+ * grain; 2 or 4 tiles (grid trees only, else P2P_EINVAL), which needs
+ * out->red_row (nbrs->count entries); the tile layout's size is counted on
+ * the GPU and read back (synchronising `stream`), and its rows are read from
+ * q through tree->perm (no sorted copy). */
 p2p_status p2p_restructure_redundant(const p2p_tree *tree, const p2p_nbrs *nbrs,
                                      const void *const src[4], int32_t nrhs,
                                      p2p_precision prec, p2p_redundant *out,

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(_HERE, "libp2p.so")
 
 P2P_OK, P2P_EINVAL, P2P_EDOMAIN, P2P_ECAPACITY, P2P_EHIP, P2P_EUNSUPPORTED = range(6)
 P2P_GATHER, P2P_REDUNDANT = 0, 1
-P2P_FP64, P2P_FP32_MIXED = 0, 1
+P2P_FP64, P2P_FP32_MIXED, P2P_FP32 = 0, 1, 2
 P2P_TREE_PARTICLES, P2P_TREE_GRIDS = 0, 1
 P2P_KIND_GRAVITY, P2P_KIND_HELMHOLTZ = 0, 1
 
@@ -53,7 +53,7 @@ class p2p_redundant(ctypes.Structure):
     _fields_ = [("cap", ctypes.c_int64), ("count", ctypes.c_int64),
                 ("red_start", ctypes.c_void_p), ("red_self", ctypes.c_void_p),
                 ("planes", ctypes.c_void_p * 4), ("nrhs", ctypes.c_int32), ("kind", ctypes.c_int32),
-                ("prec", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("prec", ctypes.c_int32), ("grain", ctypes.c_int32), ("red_row", ctypes.c_void_p)]
 
 
 class p2p_interactions(ctypes.Structure):

@@ -20,7 +20,9 @@ import torch
 
 from . import _lib as L
 
-PREC = {"fp64": L.P2P_FP64, "fp32": L.P2P_FP32_MIXED, "fp32_mixed": L.P2P_FP32_MIXED}
+# "fp32" and "fp32_mixed": single-precision pair terms, double-precision
+# per-target sums; "fp32_plain" (Helmholtz): single precision throughout
+PREC = {"fp64": L.P2P_FP64, "fp32": L.P2P_FP32_MIXED, "fp32_mixed": L.P2P_FP32_MIXED, "fp32_plain": L.P2P_FP32}
 LAYOUT = {"gather": L.P2P_GATHER, "redundant": L.P2P_REDUNDANT}
 
 
@@ -250,6 +252,8 @@ class Redundant:
     nrhs: int
     kind: int
     prec: int
+    grain: int = 1                         # 1 box grain; 2 or 4 tiles of grain^3 grid boxes
+    red_row: Optional[torch.Tensor] = None  # tile grain: first row of each near-list entry's source
 
     def struct(self) -> L.p2p_redundant:
         s = L.p2p_redundant()
@@ -258,7 +262,8 @@ class Redundant:
         s.red_start, s.red_self = self.red_start.data_ptr(), self.red_self.data_ptr()
         for i in range(4):
             s.planes[i] = self.planes[i].data_ptr() if self.planes[i] is not None else None
-        s.nrhs, s.kind, s.prec = self.nrhs, self.kind, self.prec
+        s.nrhs, s.kind, s.prec, s.grain = self.nrhs, self.kind, self.prec, self.grain
+        s.red_row = self.red_row.data_ptr() if self.red_row is not None else None
         return s
 
 
@@ -270,21 +275,39 @@ def redundant_entries(tree: Tree, nbrs: Nbrs) -> int:
     return locality(tree, nbrs)["entries"]
 
 
+def tile_entries(tree: "Tree", grain: int) -> int:
+    """S of the tile-grain layout of a grid tree: every tile of grain^3 boxes
+    holds the boxes of its window of (grain+2)^3 box cells that exist, 64
+    rows each.  The halo size of a tile is the product over the three axes
+    of the window's extent inside the grid, so the sum over the tiles of an
+    instance is the cube of the sum over one axis (host arithmetic for
+    sizing the buffers)."""
+    total = 0
+    for g in tree.grids:
+        nb = g.n_side // 4
+        axis = sum(min(o + grain, nb - 1) - max(o - 1, 0) + 1 for o in range(0, nb, grain))
+        total += axis ** 3
+    return 64 * total
+
+
 def _alloc_red(tree, kind, prec, S, nrhs, dev):
     if kind == L.P2P_KIND_GRAVITY and prec == L.P2P_FP32_MIXED:
         planes = [torch.empty((max(S, 1), 4), dtype=torch.float32, device=dev), None, None, None]
     elif kind == L.P2P_KIND_GRAVITY:
         planes = [torch.empty((max(S, 1), 4), dtype=torch.float64, device=dev), None, None, None]
     else:
-        cd = torch.complex64 if prec == L.P2P_FP32_MIXED else torch.complex128
+        cd = torch.complex128 if prec == L.P2P_FP64 else torch.complex64
         planes = [torch.empty((max(S, 1), nrhs), dtype=cd, device=dev), None, None, None]
     return planes
 
 
 def restructure(tree: Tree, nbrs: Nbrs, src: Sequence[Optional[torch.Tensor]], prec="fp64",
-                nrhs: int = 1, S: Optional[int] = None, out: Optional[Redundant] = None) -> Redundant:
+                nrhs: int = 1, S: Optional[int] = None, out: Optional[Redundant] = None,
+                grain: int = 1) -> Redundant:
     """Restructure into the redundant layout.  Pass `out` (a Redundant of the
-    right capacity) to reuse its buffers; pass S to skip the size query."""
+    right capacity) to reuse its buffers; pass S to skip the size query.
+    grain 1: one segment per target box (leaf); grain 2 or 4 (grid trees):
+    one segment per tile of grain^3 boxes."""
     p = PREC[prec]
     dev = tree.leaf_start.device
     kind = L.P2P_KIND_GRAVITY if tree.kind == L.P2P_TREE_PARTICLES else L.P2P_KIND_HELMHOLTZ
@@ -296,13 +319,16 @@ def restructure(tree: Tree, nbrs: Nbrs, src: Sequence[Optional[torch.Tensor]], p
     else:
         if len(src) != 1:
             raise ValueError("Helmholtz sources are one array q")
-        _vec(src[0], "q", tree.n * nrhs, torch.complex64 if p == L.P2P_FP32_MIXED else torch.complex128)
+        _vec(src[0], "q", tree.n * nrhs, torch.complex128 if p == L.P2P_FP64 else torch.complex64)
     if out is None:
         if S is None:
-            S = redundant_entries(tree, nbrs)
+            S = redundant_entries(tree, nbrs) if grain <= 1 else tile_entries(tree, grain)
         out = Redundant(count=0, red_start=torch.empty(tree.n_leaves + 1, dtype=torch.int64, device=dev),
                         red_self=torch.empty(max(tree.n_leaves, 1), dtype=torch.int32, device=dev),
-                        planes=_alloc_red(tree, kind, p, S, nrhs, dev), nrhs=nrhs, kind=kind, prec=p)
+                        planes=_alloc_red(tree, kind, p, S, nrhs, dev), nrhs=nrhs, kind=kind, prec=p,
+                        grain=grain,
+                        red_row=(torch.empty(max(nbrs.count, 1), dtype=torch.int64, device=dev)
+                                 if grain > 1 else None))
     srcs = L.PV4(*[_ptr(t) if t is not None else None for t in list(src) + [None] * (4 - len(src))])
     ts, ns, rs = tree.struct(), nbrs.struct(), out.struct()
 
@@ -472,7 +498,7 @@ def helmholtz(tree: Tree, nbrs: Nbrs, q: Optional[torch.Tensor] = None, layout="
     dev = tree.leaf_start.device
     if nrhs is None:
         nrhs = red.nrhs if red is not None else (1 if q.dim() == 1 else q.shape[1])
-    cd = torch.complex64 if PREC[prec] == L.P2P_FP32_MIXED else torch.complex128
+    cd = torch.complex128 if PREC[prec] == L.P2P_FP64 else torch.complex64
     _vec(q, "q", tree.n * nrhs, cd, optional=layout == "redundant")
     if out is None:
         shape = (tree.n,) if (q is not None and q.dim() == 1) or (q is None and nrhs == 1) else (tree.n, nrhs)
@@ -521,7 +547,7 @@ def helmholtz_adjoint(tree: Tree, nbrs: Nbrs, g: torch.Tensor, prec="fp64", conj
     """A^T g (conjugate=False) or A^H g = conj(A^T conj(g)) (conjugate=True)."""
     dev = tree.leaf_start.device
     nrhs = 1 if g.dim() == 1 else g.shape[1]
-    _vec(g, "g", tree.n * nrhs, torch.complex64 if PREC[prec] == L.P2P_FP32_MIXED else torch.complex128)
+    _vec(g, "g", tree.n * nrhs, torch.complex128 if PREC[prec] == L.P2P_FP64 else torch.complex64)
     out = torch.empty_like(g)
     gs, _ = grids_struct(tree.grids)
     gout = L.PV4(_ptr(g), None, None, None)

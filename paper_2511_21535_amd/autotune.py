@@ -32,11 +32,11 @@ def cache_path() -> str:
                           os.path.join(os.path.expanduser("~"), ".cache", "p2p_mi355x_autotune.json"))
 
 
-def problem_key(tree: api.Tree, nrhs: int, layout: str) -> str:
+def problem_key(tree: api.Tree, nrhs: int, layout: str, prec: str = "fp32") -> str:
     dev = torch.cuda.get_device_name(tree.leaf_start.device)
     sizes = ",".join(str(g.n_side) for g in tree.grids)
     h = hashlib.sha1(sizes.encode()).hexdigest()[:16]
-    return f"{dev}|grids={len(tree.grids)}:{h}|nrhs={nrhs}|{layout}"
+    return f"{dev}|grids={len(tree.grids)}:{h}|nrhs={nrhs}|{layout}|{prec}"
 
 
 def _load_cache() -> Dict[str, dict]:
@@ -88,13 +88,14 @@ def pick_copies(timings: Dict[str, float], shape: Sequence[int], copies: Sequenc
 def tune_helmholtz(tree: api.Tree, nbrs: api.Nbrs, q: Optional[torch.Tensor] = None,
                    red: Optional[api.Redundant] = None, layout: str = "gather",
                    candidates: Sequence[Tuple[int, int, int]] = CANDIDATES, reps: int = 3,
-                   use_cache: bool = True, copies: Sequence[int] = COPIES
+                   use_cache: bool = True, copies: Sequence[int] = COPIES, prec: str = "fp32"
                    ) -> Tuple[Tuple[int, int, int, int], Dict[str, float]]:
     """Pick the fastest launch shape, then the number of copies of the G
     blocks; returns (tile, timings), tile = (waves per workgroup, workgroups
-    per CU, RHS per wave, copies)."""
+    per CU, RHS per wave, copies).  prec: "fp32" (FP64 per-target sums of the
+    per-box partial products) or "fp32_plain"."""
     nrhs = red.nrhs if red is not None else q.shape[1]
-    key = problem_key(tree, nrhs, layout)
+    key = problem_key(tree, nrhs, layout, prec)
     cache = _load_cache() if use_cache else {}
     if key in cache:
         e = cache[key]
@@ -103,7 +104,7 @@ def tune_helmholtz(tree: api.Tree, nbrs: api.Nbrs, q: Optional[torch.Tensor] = N
     timings = {}
 
     def run(cand):
-        fn = lambda: api.helmholtz(tree, nbrs, q, layout=layout, prec="fp32", red=red, nrhs=nrhs,
+        fn = lambda: api.helmholtz(tree, nbrs, q, layout=layout, prec=prec, red=red, nrhs=nrhs,
                                    tile=cand, out=out)
         timings[str(list(cand))] = time_call(fn, reps)
 
@@ -121,3 +122,30 @@ def tune_helmholtz(tree: api.Tree, nbrs: api.Nbrs, q: Optional[torch.Tensor] = N
         cache[key] = {"tile": list(tile), "ms": timings}
         _save_cache(cache)
     return tile, timings
+
+
+# redundancy grains: one segment per box (1), or per tile of 2^3 or 4^3 boxes
+GRAINS = (1, 2, 4)
+
+
+def tune_grain(tree: api.Tree, nbrs: api.Nbrs, q: torch.Tensor, nrhs: int, prec: str = "fp32",
+               tile: Optional[Sequence[int]] = None, grains: Sequence[int] = GRAINS, reps: int = 3
+               ) -> Tuple[int, Dict[int, Dict[str, float]]]:
+    """The redundancy grain of a grid batch (Sec. 3.5: per-block redundancy
+    for dense regular data): for each grain, the restructure and the
+    redundant evaluation are timed on the actual problem (median of `reps`
+    after a warm-up), each layout allocated, timed and freed in turn.
+    Returns (grain with the least restructure + evaluation time, timings in
+    ms per grain)."""
+    out = torch.empty_like(q)
+    res = {}
+    for g in grains:
+        red = api.restructure(tree, nbrs, [q], prec=prec, nrhs=nrhs, grain=g)
+        t_res = time_call(lambda: api.restructure(tree, nbrs, [q], prec=prec, nrhs=nrhs, out=red), reps)
+        t_ev = time_call(lambda: api.helmholtz(tree, nbrs, None, layout="redundant", prec=prec, red=red,
+                                               nrhs=nrhs, tile=tile, out=out), reps)
+        res[g] = {"restructure_ms": t_res, "eval_redundant_ms": t_ev, "entries": red.count}
+        del red
+        torch.cuda.empty_cache()
+    best = min(res, key=lambda g: res[g]["restructure_ms"] + res[g]["eval_redundant_ms"])
+    return best, res

@@ -149,6 +149,14 @@ p2p_status check_eps(double eps, bool mixed, bool positive = false) {
     return P2P_OK;
 }
 
+// Precision of the gravity paths: FP64 or FP32_MIXED (P2P_FP32, single
+// precision throughout, is provided for the Helmholtz paths only).
+p2p_status check_gravity_prec(p2p_precision prec) {
+    if (prec == P2P_FP32) return fail(P2P_EUNSUPPORTED, "P2P_FP32 is provided for the Helmholtz paths only");
+    if (prec != P2P_FP64 && prec != P2P_FP32_MIXED) return fail(P2P_EINVAL, "bad precision");
+    return P2P_OK;
+}
+
 // Image codes of periodic lists, null for plain ones.
 const int8_t *shifts(const p2p_nbrs *nb) { return nb->periodic ? nb->nbr_shift : nullptr; }
 
@@ -357,6 +365,51 @@ namespace {
 
 // Segments of the targets of `tree` filled from the points of `srct` (the same
 // tree, or the source tree of remote lists).
+// Tile grain on a grid tree: halo sizes per tile, their scan, the total read
+// back (the capacity check needs it), then the halo lists with the row of
+// every near-list entry, and the copy of the halo boxes' rows from caller
+// order.
+p2p_status restructure_tiles(const p2p_tree *tree, const p2p_nbrs *nbrs, const void *const src[4], int32_t nrhs,
+                             p2p_precision prec, p2p_redundant *out, void *ws, size_t *ws_bytes, hipStream_t s) {
+    const int grain = out->grain;
+    if (grain != 2 && grain != 4) return fail(P2P_EINVAL, "out->grain must be 0, 1 (box grain), 2 or 4 (tiles)");
+    const bool mixed = prec != P2P_FP64;
+    const int64_t L = tree->n_leaves, E = nbrs->count;
+    const int64_t row_bytes = static_cast<int64_t>(nrhs) * (mixed ? 8 : 16);
+    Arena ar(ws);
+    int64_t *cnt = ar.take<int64_t>(L);
+    int64_t *hs = ar.take<int64_t>(L + 1);
+    int64_t *scan_tmp = ar.take<int64_t>(scan_ws_elems(L));
+    int32_t *halo = ar.take<int32_t>(E);
+    p2p_status st;
+    if (ws_query(ws, ws_bytes, ar, &st)) return st;
+    if (!src || (tree->n > 0 && !src[0])) return fail(P2P_EINVAL, "src[0] (q) must not be NULL");
+    if (!out->red_start || (E > 0 && !out->red_row)) return fail(P2P_EINVAL, "out->red_start/red_row must not be NULL");
+    if (out->cap < 0) return fail(P2P_EINVAL, "out->cap < 0");
+    P2P_TRY(no_capture(s, "a tile-grain restructure"));
+    P2P_TRY(launch_tile_halo(tree->leaf_key, nbrs->nbr_start, nbrs->nbr_idx, L, tree->key_bits, grain, cnt,
+                             nullptr, nullptr, nullptr, nullptr, s));
+    P2P_TRY((exclusive_scan<int64_t, int64_t>(cnt, hs, L, scan_tmp, s)));
+    int64_t H = 0;
+    if (L > 0) P2P_HIP(hipMemcpyAsync(&H, hs + L, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    P2P_HIP(hipStreamSynchronize(s));
+    const int64_t S = 64 * H;
+    if (S > out->cap) {
+        out->count = S;
+        return fail(P2P_ECAPACITY, "out->cap " + std::to_string(out->cap) + " < " + std::to_string(S) + " entries");
+    }
+    if (S > 0 && !out->planes[0]) return fail(P2P_EINVAL, "out->planes must not be NULL");
+    P2P_TRY(launch_tile_halo(tree->leaf_key, nbrs->nbr_start, nbrs->nbr_idx, L, tree->key_bits, grain, nullptr,
+                             hs, halo, out->red_row, out->red_start, s));
+    P2P_TRY(launch_tile_copy(src[0], row_bytes, tree->leaf_start, tree->perm, halo, H, out->planes[0],
+                             S * row_bytes > kStreamingLayoutBytes, s));
+    out->count = S;
+    out->nrhs = nrhs;
+    out->kind = P2P_KIND_HELMHOLTZ;
+    out->prec = prec;
+    return P2P_OK;
+}
+
 p2p_status restructure_common(const p2p_tree *tree, const p2p_tree *srct, const p2p_nbrs *nbrs,
                               const void *const src[4], int32_t nrhs, p2p_precision prec, p2p_redundant *out,
                               void *ws, size_t *ws_bytes, hipStream_t s) {
@@ -368,11 +421,17 @@ p2p_status restructure_common(const p2p_tree *tree, const p2p_tree *srct, const 
         P2P_TRY(check_tree(tree));
     P2P_TRY(check_nbrs(tree, nbrs, remote));
     if (!out) return fail(P2P_EINVAL, "out is NULL");
-    if (prec != P2P_FP64 && prec != P2P_FP32_MIXED) return fail(P2P_EINVAL, "bad precision");
     const bool grav = tree->kind == P2P_TREE_PARTICLES;
+    if (grav) P2P_TRY(check_gravity_prec(prec));
+    else if (prec != P2P_FP64 && prec != P2P_FP32_MIXED && prec != P2P_FP32) return fail(P2P_EINVAL, "bad precision");
     if (!grav && nrhs < 1) return fail(P2P_EINVAL, "nrhs must be >= 1");
     if (grav) nrhs = 1;
-    const bool mixed = prec == P2P_FP32_MIXED;
+    if (out->grain != 0 && out->grain != 1) {
+        if (grav || remote) return fail(P2P_EINVAL, "out->grain > 1 (tiles) is defined on grid trees only");
+        return restructure_tiles(tree, nbrs, src, nrhs, prec, out, ws, ws_bytes, s);
+    }
+    // single-precision payload: leaf-relative float rows (gravity), complex64 (Helmholtz)
+    const bool mixed = prec != P2P_FP64;
     // n: the source rows; L: the target leaves
     const int64_t n = srct->n, L = tree->n_leaves;
     const size_t csize = mixed ? sizeof(float2) : sizeof(double2);
@@ -498,7 +557,7 @@ extern "C" p2p_status p2p_restructure_interactions(const p2p_tree *tree, const p
     if (tree->kind != P2P_TREE_PARTICLES) return fail(P2P_EINVAL, "the per-interaction layout needs a particle tree");
     P2P_TRY(check_nbrs(tree, nbrs));
     if (!out) return fail(P2P_EINVAL, "out is NULL");
-    if (prec != P2P_FP64 && prec != P2P_FP32_MIXED) return fail(P2P_EINVAL, "bad precision");
+    P2P_TRY(check_gravity_prec(prec));
     const bool mixed = prec == P2P_FP32_MIXED;
     const int64_t n = tree->n, L = tree->n_leaves, E = nbrs->count;
     const bool known = nbrs->red_entries >= 0;
@@ -590,26 +649,24 @@ extern "C" p2p_status p2p_eval_gravity_interactions(const p2p_tree *tree, const 
 }
 
 // ------------------------------------------------------------- gravity ----
-extern "C" p2p_status p2p_eval_gravity(const p2p_tree *tree, const p2p_nbrs *nbrs,
-                                       const p2p_redundant *red, p2p_layout layout,
-                                       p2p_precision prec, double eps, const double *x,
-                                       const double *y, const double *z, const double *m,
-                                       double *phi, double *ax, double *ay, double *az, void *ws,
-                                       size_t *ws_bytes, p2p_stream_t stream) {
-    set_error("");
-    if (!ws_bytes) return fail(P2P_EINVAL, "ws_bytes must not be NULL");
+namespace p2p {
+
+p2p_status gravity_check_args(const p2p_tree *tree, const p2p_nbrs *nbrs, p2p_layout layout,
+                              p2p_precision prec, double eps) {
     P2P_TRY(check_tree(tree));
     if (tree->kind != P2P_TREE_PARTICLES) return fail(P2P_EINVAL, "gravity needs a particle tree");
     P2P_TRY(check_nbrs(tree, nbrs));
     if (layout != P2P_GATHER && layout != P2P_REDUNDANT) return fail(P2P_EINVAL, "bad layout");
-    if (prec != P2P_FP64 && prec != P2P_FP32_MIXED) return fail(P2P_EINVAL, "bad precision");
+    P2P_TRY(check_gravity_prec(prec));
+    return check_eps(eps, prec == P2P_FP32_MIXED);
+}
+
+p2p_status gravity_run(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2p_redundant *red,
+                       p2p_layout layout, p2p_precision prec, double eps, const double *x,
+                       const double *y, const double *z, const double *m, double *phi, double *ax,
+                       double *ay, double *az, Row4d *s4, hipStream_t s) {
     const bool mixed = prec == P2P_FP32_MIXED, redundant = layout == P2P_REDUNDANT;
-    P2P_TRY(check_eps(eps, mixed));
     const int64_t n = tree->n;
-    Arena ar(ws);
-    Row4d *s4 = redundant ? nullptr : ar.take<Row4d>(n);
-    p2p_status st;
-    if (ws_query(ws, ws_bytes, ar, &st)) return st;
     if (n > 0 && (!phi || !ax || !ay || !az)) return fail(P2P_EINVAL, "outputs must not be NULL");
     if (redundant) {
         if (!red) return fail(P2P_EINVAL, "REDUNDANT layout needs red");
@@ -620,7 +677,6 @@ extern "C" p2p_status p2p_eval_gravity(const p2p_tree *tree, const p2p_nbrs *nbr
     } else if (n > 0 && (!x || !y || !z || !m)) {
         return fail(P2P_EINVAL, "GATHER layout needs x, y, z, m");
     }
-    hipStream_t s = as_stream(stream);
     GravityArgs a{};
     a.L = tree->n_leaves;
     a.leaf_start = tree->leaf_start;
@@ -650,6 +706,24 @@ extern "C" p2p_status p2p_eval_gravity(const p2p_tree *tree, const p2p_nbrs *nbr
     return launch_gravity(a, redundant, mixed, eps == 0.0, s);
 }
 
+}  // namespace p2p
+
+extern "C" p2p_status p2p_eval_gravity(const p2p_tree *tree, const p2p_nbrs *nbrs,
+                                       const p2p_redundant *red, p2p_layout layout,
+                                       p2p_precision prec, double eps, const double *x,
+                                       const double *y, const double *z, const double *m,
+                                       double *phi, double *ax, double *ay, double *az, void *ws,
+                                       size_t *ws_bytes, p2p_stream_t stream) {
+    set_error("");
+    if (!ws_bytes) return fail(P2P_EINVAL, "ws_bytes must not be NULL");
+    P2P_TRY(gravity_check_args(tree, nbrs, layout, prec, eps));
+    Arena ar(ws);
+    Row4d *s4 = layout == P2P_REDUNDANT ? nullptr : ar.take<Row4d>(tree->n);
+    p2p_status st;
+    if (ws_query(ws, ws_bytes, ar, &st)) return st;
+    return gravity_run(tree, nbrs, red, layout, prec, eps, x, y, z, m, phi, ax, ay, az, s4, as_stream(stream));
+}
+
 extern "C" p2p_status p2p_eval_gravity_remote(const p2p_tree *tree, const p2p_tree *src_tree,
                                               const p2p_nbrs *nbrs, const p2p_redundant *red,
                                               p2p_layout layout, p2p_precision prec, double eps,
@@ -662,7 +736,7 @@ extern "C" p2p_status p2p_eval_gravity_remote(const p2p_tree *tree, const p2p_tr
     P2P_TRY(check_remote_trees(tree, src_tree));
     P2P_TRY(check_nbrs(tree, nbrs, true));
     if (layout != P2P_GATHER && layout != P2P_REDUNDANT) return fail(P2P_EINVAL, "bad layout");
-    if (prec != P2P_FP64 && prec != P2P_FP32_MIXED) return fail(P2P_EINVAL, "bad precision");
+    P2P_TRY(check_gravity_prec(prec));
     const bool mixed = prec == P2P_FP32_MIXED, redundant = layout == P2P_REDUNDANT;
     P2P_TRY(check_eps(eps, mixed));
     const int64_t n = tree->n, ns = src_tree->n;
@@ -734,7 +808,7 @@ p2p_status helmholtz_common(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2
     if (tree->kind != P2P_TREE_GRIDS) return fail(P2P_EINVAL, "Helmholtz needs a grid tree");
     P2P_TRY(check_nbrs(tree, nbrs));
     if (layout != P2P_GATHER && layout != P2P_REDUNDANT) return fail(P2P_EINVAL, "bad layout");
-    if (prec != P2P_FP64 && prec != P2P_FP32_MIXED) return fail(P2P_EINVAL, "bad precision");
+    if (prec != P2P_FP64 && prec != P2P_FP32_MIXED && prec != P2P_FP32) return fail(P2P_EINVAL, "bad precision");
     if (nrhs < 1) return fail(P2P_EINVAL, "nrhs must be >= 1");
     if (n_grids != tree->n_grids) return fail(P2P_EINVAL, "n_grids differs from the tree's");
     P2P_TRY(check_grids(grids, n_grids, tree->n));
@@ -821,13 +895,18 @@ p2p_status helmholtz_common(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2
     if (redundant) {
         if (!red) return fail(P2P_EINVAL, "REDUNDANT layout needs red");
         if (red->kind != P2P_KIND_HELMHOLTZ) return fail(P2P_EINVAL, "red was not built for Helmholtz");
-        if (red->prec != prec) return fail(P2P_EINVAL, "red was built with another precision");
+        if ((red->prec == P2P_FP64) != fp64) return fail(P2P_EINVAL, "red was built with another payload precision");
         if (red->nrhs != nrhs) return fail(P2P_EINVAL, "red was built with another nrhs");
         if (!red->red_start || (red->count > 0 && !red->planes[0])) return fail(P2P_EINVAL, "red arrays must not be NULL");
+        if (red->grain != 0 && red->grain != 1 && red->grain != 2 && red->grain != 4)
+            return fail(P2P_EINVAL, "red->grain must be 0, 1, 2 or 4");
+        if (red->grain > 1 && nbrs->count > 0 && !red->red_row)
+            return fail(P2P_EINVAL, "a tile-grain layout needs red->red_row");
         if (conj) return fail(P2P_EUNSUPPORTED, "conjugated action needs the GATHER layout");
     } else if (n > 0 && !q) {
         return fail(P2P_EINVAL, "q must not be NULL");
     }
+    const bool tiled = redundant && red->grain > 1;
     // a single-RHS call on a grid of few instances takes its parameters in the
     // kernel arguments; every other call uploads them
     const bool inline_params = cols && n_grids <= kInlineGrids && n_tables <= kInlineGrids;
@@ -880,6 +959,7 @@ p2p_status helmholtz_common(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2
         a.nbr_start = nbrs->nbr_start;
         a.nbr_idx = nbrs->nbr_idx;
         a.red_start = redundant ? red->red_start : nullptr;
+        a.red_row = tiled ? red->red_row : nullptr;
         a.src = redundant ? static_cast<const float2 *>(red->planes[0]) : reinterpret_cast<const float2 *>(sorted);
         a.blocks = blocks;
         a.copies = 1;
@@ -887,6 +967,7 @@ p2p_status helmholtz_common(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2
         a.inst_scale = d_iscale;
         a.nrhs = 1;
         a.conj = conj;
+        a.comp = prec == P2P_FP32_MIXED;
         a.u = static_cast<float2 *>(u);
         return launch_helmholtz_mfma_cols(a, d_tiles, inl, n_tiles, redundant, s);
     }
@@ -901,6 +982,7 @@ p2p_status helmholtz_common(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2
         a.nbr_start = nbrs->nbr_start;
         a.nbr_idx = nbrs->nbr_idx;
         a.red_start = redundant ? red->red_start : nullptr;
+        a.red_row = tiled ? red->red_row : nullptr;
         a.src = redundant ? static_cast<const float2 *>(red->planes[0]) : reinterpret_cast<const float2 *>(sorted);
         a.blocks = blocks;
         a.copies = copies;
@@ -910,6 +992,7 @@ p2p_status helmholtz_common(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2
         a.counter = counter;
         a.nrhs = nrhs;
         a.conj = conj;
+        a.comp = prec == P2P_FP32_MIXED;
         a.u = static_cast<float2 *>(u);
         return launch_helmholtz_mfma(a, redundant, waves_per_wg, wg_per_cu, rhs_tile, s);
     }
@@ -923,10 +1006,12 @@ p2p_status helmholtz_common(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2
     a.nbr_start = nbrs->nbr_start;
     a.nbr_idx = nbrs->nbr_idx;
     a.red_start = redundant ? red->red_start : nullptr;
+    a.red_row = tiled ? red->red_row : nullptr;
     a.src = redundant ? red->planes[0] : sorted;
     a.table = table;
     a.nrhs = nrhs;
     a.conj = conj;
+    a.comp = prec == P2P_FP32_MIXED;
     a.u = u;
     return launch_helmholtz(a, redundant, fp64, s);
 }
@@ -968,7 +1053,7 @@ extern "C" p2p_status p2p_adjoint(int32_t kind, const p2p_tree *tree, const p2p_
     if (tree->kind != P2P_TREE_PARTICLES) return fail(P2P_EINVAL, "gravity needs a particle tree");
     P2P_TRY(check_nbrs(tree, nbrs));
     if (layout != P2P_GATHER) return fail(P2P_EUNSUPPORTED, "gravity adjoint uses the GATHER layout");
-    if (prec != P2P_FP64 && prec != P2P_FP32_MIXED) return fail(P2P_EINVAL, "bad precision");
+    P2P_TRY(check_gravity_prec(prec));
     P2P_TRY(check_eps(eps, prec == P2P_FP32_MIXED, true));
     const int64_t n = tree->n;
     Arena ar(ws);

@@ -16,6 +16,8 @@
 // to the four wavefronts of its workgroup (box e to wave e % 4), which gives
 // four times the waves to hide the scalar loads of the sources; the four
 // partial sums meet in LDS.
+#include <type_traits>
+
 #include "p2p_internal.h"
 
 namespace p2p {
@@ -54,16 +56,19 @@ __device__ inline int lane_axis(int l, int axis) {
 
 constexpr int kHWaves = 4;
 
-template <class C, bool RED, bool CONJ, bool ONE>
+// COMP (FP32 payload): each near box's 64-term FP32 partial sum is added into
+// an FP64 per-target sum; otherwise all terms accumulate in the payload's type.
+template <class C, bool RED, bool CONJ, bool ONE, bool COMP>
 __global__ __launch_bounds__(64 * kHWaves) void k_helmholtz(
     int64_t L, int key_bits, int32_t nrhs, const int32_t *__restrict__ leaf_start,
     const uint64_t *__restrict__ leaf_key, const int32_t *__restrict__ perm,
     const int64_t *__restrict__ nbr_start, const int32_t *__restrict__ nbr_idx,
-    const int64_t *__restrict__ red_start, const C *__restrict__ src,
+    const int64_t *__restrict__ red_start, const int64_t *__restrict__ red_row, const C *__restrict__ src,
     const C *__restrict__ tables, C *__restrict__ u) {
     using R = typename Real<C>::T;
+    using P = typename std::conditional<COMP, double2, C>::type;   // partial sums across waves
     __shared__ C s_tab[kTableLen];
-    __shared__ C s_part[kHWaves][64];
+    __shared__ P s_part[kHWaves][64];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t A = blockIdx.x;
@@ -84,13 +89,16 @@ __global__ __launch_bounds__(64 * kHWaves) void k_helmholtz(
     const int64_t stride = ONE ? 1 : nrhs;
     for (int32_t r = 0; r < (ONE ? 1 : nrhs); ++r) {
         R ur = 0, ui = 0;
+        double cr = 0.0, ci = 0.0;
         for (int64_t e = e0 + wv; e < e1; e += kHWaves) {
             const int32_t B = nbr_idx[e];
             const uint64_t lB = leaf_key[B] & local_mask;
             const int o[3] = {(static_cast<int>(p2pd::compact3(lB)) - ax) / 4,
                               (static_cast<int>(p2pd::compact3(lB >> 1)) - ay) / 4,
                               (static_cast<int>(p2pd::compact3(lB >> 2)) - az) / 4};
-            const int64_t row0 = RED ? red_start[A] + 64 * (e - e0) : leaf_start[B];
+            // redundant rows: the entry's place in A's segment (box grain) or
+            // in the segment of A's tile (red_row, tile grain)
+            const int64_t row0 = RED ? (red_row ? red_row[e] : red_start[A] + 64 * (e - e0)) : leaf_start[B];
             const C *__restrict__ qb = src + row0 * stride + r;
             int sq[3][4];
 #pragma unroll
@@ -116,21 +124,35 @@ __global__ __launch_bounds__(64 * kHWaves) void k_helmholtz(
                 ui = fma(gv.x, q.y, ui);
                 ui = fma(gi, q.x, ui);
             }
+            if constexpr (COMP) {
+                cr += static_cast<double>(ur);
+                ci += static_cast<double>(ui);
+                ur = 0;
+                ui = 0;
+            }
         }
-        C part;
-        part.x = ur;
-        part.y = ui;
+        P part;
+        if constexpr (COMP) {
+            part.x = cr;
+            part.y = ci;
+        } else {
+            part.x = ur;
+            part.y = ui;
+        }
         s_part[wv][lane] = part;
         __syncthreads();
         if (wv == 0) {
-            C out = s_part[0][lane];
+            P out = s_part[0][lane];
 #pragma unroll
             for (int q = 1; q < kHWaves; ++q) {
                 out.x += s_part[q][lane].x;
                 out.y += s_part[q][lane].y;
             }
             const int64_t i = perm[leaf_start[A] + lane];
-            u[i * stride + r] = out;
+            C o;
+            o.x = static_cast<R>(out.x);
+            o.y = static_cast<R>(out.y);
+            u[i * stride + r] = o;
         }
         __syncthreads();
     }
@@ -151,18 +173,26 @@ p2p_status launch_green_tables(const double *d_h, const double *d_k, int32_t n_g
     return P2P_OK;
 }
 
-template <class C, bool RED, bool CONJ>
-static void launch_helm_t(const HelmholtzArgs &a, hipStream_t s) {
+template <class C, bool RED, bool CONJ, bool COMP>
+static void launch_helm_c(const HelmholtzArgs &a, hipStream_t s) {
     if (a.nrhs == 1)
-        k_helmholtz<C, RED, CONJ, true><<<static_cast<unsigned>(a.L), 64 * kHWaves, 0, s>>>(
+        k_helmholtz<C, RED, CONJ, true, COMP><<<static_cast<unsigned>(a.L), 64 * kHWaves, 0, s>>>(
             a.L, a.key_bits, a.nrhs, a.leaf_start, a.leaf_key, a.perm, a.nbr_start, a.nbr_idx,
-            a.red_start, static_cast<const C *>(a.src), static_cast<const C *>(a.table),
+            a.red_start, a.red_row, static_cast<const C *>(a.src), static_cast<const C *>(a.table),
             static_cast<C *>(a.u));
     else
-        k_helmholtz<C, RED, CONJ, false><<<static_cast<unsigned>(a.L), 64 * kHWaves, 0, s>>>(
+        k_helmholtz<C, RED, CONJ, false, COMP><<<static_cast<unsigned>(a.L), 64 * kHWaves, 0, s>>>(
             a.L, a.key_bits, a.nrhs, a.leaf_start, a.leaf_key, a.perm, a.nbr_start, a.nbr_idx,
-            a.red_start, static_cast<const C *>(a.src), static_cast<const C *>(a.table),
+            a.red_start, a.red_row, static_cast<const C *>(a.src), static_cast<const C *>(a.table),
             static_cast<C *>(a.u));
+}
+
+template <class C, bool RED, bool CONJ>
+static void launch_helm_t(const HelmholtzArgs &a, hipStream_t s) {
+    if (a.comp && std::is_same<C, float2>::value)
+        launch_helm_c<C, RED, CONJ, true>(a, s);
+    else
+        launch_helm_c<C, RED, CONJ, false>(a, s);
 }
 
 p2p_status launch_helmholtz(const HelmholtzArgs &a, bool redundant, bool fp64, hipStream_t s) {

@@ -90,12 +90,16 @@ __global__ void k_zero_counter(int32_t *c, int n) {
     if (static_cast<int>(threadIdx.x) < n) c[threadIdx.x] = 0;
 }
 
-template <bool RED, bool CONJ, int TJ>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_helm_mfma(
+// COMP: the accumulators restart from zero for every near box, and each
+// box's 64-term FP32 partial product is added into FP64 per-target sums (the
+// per-target accumulation in double of FP32 partial sums); otherwise the
+// products of all near boxes accumulate in FP32.
+template <bool RED, bool CONJ, int TJ, bool COMP>
+__device__ __forceinline__ void helm_mfma_body(
     int64_t L, int key_bits, int32_t nrhs, const int32_t *__restrict__ leaf_start,
     const uint64_t *__restrict__ leaf_key, const int32_t *__restrict__ perm,
     const int64_t *__restrict__ nbr_start, const int32_t *__restrict__ nbr_idx,
-    const int64_t *__restrict__ red_start, const float2 *__restrict__ src,
+    const int64_t *__restrict__ red_start, const int64_t *__restrict__ red_row, const float2 *__restrict__ src,
     const float2 *__restrict__ blocks, int32_t copies, const int32_t *__restrict__ inst_table,
     const float *__restrict__ inst_scale, const int32_t *__restrict__ work,
     int32_t *__restrict__ counter, float2 *__restrict__ u) {
@@ -134,7 +138,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             const int oy = (static_cast<int>(p2pd::compact3(lB >> 1)) - ay) / 4;
             const int oz = (static_cast<int>(p2pd::compact3(lB >> 2)) - az) / 4;
             my_goff = ((ox + 1) + 3 * (oy + 1) + 9 * (oz + 1)) * 4096;
-            const int64_t row0 = RED ? red_start[A] + 64 * static_cast<int64_t>(lane) : leaf_start[B];
+            // redundant rows: the entry's place in A's segment (box grain) or
+            // in the segment of A's tile (red_row, tile grain)
+            const int64_t row0 = RED ? (red_row ? red_row[e0 + lane] : red_start[A] + 64 * static_cast<int64_t>(lane))
+                                     : leaf_start[B];
             my_row_lo = static_cast<int>(row0 & 0xffffffff);
             my_row_hi = static_cast<int>(row0 >> 32);
         }
@@ -154,6 +161,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                 ur[a][b] = floatx16{0};
                 ui[a][b] = floatx16{0};
             }
+        // FP64 per-target sums of the per-box partial products (COMP)
+        constexpr int CN = COMP ? 16 : 1;
+        double cr[2][TJ][CN], ci[2][TJ][CN];
+        if constexpr (COMP) {
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < TJ; ++b)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) cr[a][b][r] = ci[a][b][r] = 0.0;
+        }
 
         const int64_t qstep = 2 * static_cast<int64_t>(nrhs);   // two source rows per k-step
         auto load = [&](const float2 *Gp, const float2 *Qp, int kk, float2 (&gv)[2], float2 (&qv)[TJ]) {
@@ -162,14 +180,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
             for (int b = 0; b < TJ; ++b) qv[b] = Qp[kk * qstep + 32 * b];
         };
-        auto mma = [&](const float2 (&gv)[2], const float2 (&qv)[TJ]) {
+        // fresh: the first k-step of a box under COMP starts from zero accumulators
+        auto mma = [&](const float2 (&gv)[2], const float2 (&qv)[TJ], bool fresh) {
+            const floatx16 zero = floatx16{0};
 #pragma unroll
             for (int a = 0; a < 2; ++a) {
                 const float gr = gv[a].x, gi = CONJ ? -gv[a].y : gv[a].y;
 #pragma unroll
                 for (int b = 0; b < TJ; ++b) {
-                    ur[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(gr, qv[b].x, ur[a][b], 0, 0, 0);
-                    ui[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(gr, qv[b].y, ui[a][b], 0, 0, 0);
+                    ur[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(gr, qv[b].x, fresh ? zero : ur[a][b], 0, 0, 0);
+                    ui[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(gr, qv[b].y, fresh ? zero : ui[a][b], 0, 0, 0);
                     ur[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(-gi, qv[b].y, ur[a][b], 0, 0, 0);
                     ui[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(gi, qv[b].x, ui[a][b], 0, 0, 0);
                 }
@@ -198,8 +218,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                 // scheduler sinks each load down to its first use, and every
                 // k-step then waits out a full L2 round trip
                 __builtin_amdgcn_sched_barrier(0);
-                mma(gbuf[kk & 3], qbuf[kk & 3]);
+                mma(gbuf[kk & 3], qbuf[kk & 3], COMP && kk == 0);
                 __builtin_amdgcn_sched_barrier(0);
+            }
+            if constexpr (COMP) {
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < TJ; ++b)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) {
+                            cr[a][b][r] += static_cast<double>(ur[a][b][r]);
+                            ci[a][b][r] += static_cast<double>(ui[a][b][r]);
+                        }
             }
             Gc = Gn;
             Qc = Qn;
@@ -213,9 +244,41 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                 const int i = 32 * a + 8 * (r / 4) + 4 * half + (r % 4);
                 const int64_t row = static_cast<int64_t>(perm[t0 + i]) * nrhs + rhs0 + col;
 #pragma unroll
-                for (int b = 0; b < TJ; ++b) u[row + 32 * b] = make_float2(ur[a][b][r] * sc, ui[a][b][r] * sc);
+                for (int b = 0; b < TJ; ++b) {
+                    if constexpr (COMP)
+                        u[row + 32 * b] = make_float2(static_cast<float>(cr[a][b][r] * sc),
+                                                      static_cast<float>(ci[a][b][r] * sc));
+                    else
+                        u[row + 32 * b] = make_float2(ur[a][b][r] * sc, ui[a][b][r] * sc);
+                }
             }
     }
+}
+
+#define P2P_HELM_MFMA_PARAMS                                                                            \
+    int64_t L, int key_bits, int32_t nrhs, const int32_t *__restrict__ leaf_start,                      \
+        const uint64_t *__restrict__ leaf_key, const int32_t *__restrict__ perm,                        \
+        const int64_t *__restrict__ nbr_start, const int32_t *__restrict__ nbr_idx,                     \
+        const int64_t *__restrict__ red_start, const int64_t *__restrict__ red_row,                     \
+        const float2 *__restrict__ src, const float2 *__restrict__ blocks, int32_t copies,              \
+        const int32_t *__restrict__ inst_table, const float *__restrict__ inst_scale,                   \
+        const int32_t *__restrict__ work, int32_t *__restrict__ counter, float2 *__restrict__ u
+#define P2P_HELM_MFMA_ARGS                                                                              \
+    L, key_bits, nrhs, leaf_start, leaf_key, perm, nbr_start, nbr_idx, red_start, red_row, src, blocks, \
+        copies, inst_table, inst_scale, work, counter, u
+
+// Two waves per SIMD.
+template <bool RED, bool CONJ, int TJ, bool COMP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_helm_mfma(P2P_HELM_MFMA_PARAMS) {
+    helm_mfma_body<RED, CONJ, TJ, COMP>(P2P_HELM_MFMA_ARGS);
+}
+
+// 64 right-hand sides per wave with FP64 sums: the 128 doubles per lane of the
+// sums do not fit beside the accumulators at two waves per SIMD, so one.
+template <bool RED, bool CONJ>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1))) void k_helm_mfma_wide(
+    P2P_HELM_MFMA_PARAMS) {
+    helm_mfma_body<RED, CONJ, 2, true>(P2P_HELM_MFMA_ARGS);
 }
 
 // Single right-hand side on matrix cores: the target boxes become the columns
@@ -242,19 +305,21 @@ constexpr int kColOffsets = (27 + kColWaves - 1) / kColWaves;
 constexpr int kColBufs = 4;
 static_assert(16 % kColBufs == 0, "the buffer rotation must restart with every offset");
 
-template <bool RED, bool CONJ>
+template <bool RED, bool CONJ, bool COMP>
 __global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols(
     int key_bits, const int32_t *__restrict__ tiles, HelmInline inl, const int32_t *__restrict__ leaf_start,
     const uint64_t *__restrict__ leaf_key, const int32_t *__restrict__ perm,
     const int64_t *__restrict__ nbr_start, const int32_t *__restrict__ nbr_idx,
-    const int64_t *__restrict__ red_start, const float2 *__restrict__ src,
+    const int64_t *__restrict__ red_start, const int64_t *__restrict__ red_row, const float2 *__restrict__ src,
     const float2 *__restrict__ blocks, const int32_t *__restrict__ inst_table,
     const float *__restrict__ inst_scale, float2 *__restrict__ u) {
     typedef float floatx4 __attribute__((ext_vector_type(4)));
     __shared__ int64_t s_row[27][kColBoxes];             // first source row of (offset, column); -1: none
     __shared__ int64_t s_nstart[kColBoxes + 1];
     __shared__ int32_t s_offs[kColWaves][kColOffsets];    // each wave's offsets that some column has
-    __shared__ floatx4 s_red[kColWaves - 1][4][2][64];    // partial sums of waves 1.. for wave 0
+    // partial sums of waves 1.. for wave 0: FP32 tiles, or FP64 sums under COMP
+    __shared__ floatx4 s_red[COMP ? 1 : kColWaves - 1][4][2][64];
+    __shared__ double s_redd[COMP ? (kColWaves - 1) * 4 * 2 * 4 * 64 : 1];
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const uint64_t local_mask = (1ull << (3 * key_bits)) - 1ull;
@@ -299,7 +364,8 @@ __global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols(
         const int oy = (static_cast<int>(p2pd::compact3(lB >> 1)) - static_cast<int>(p2pd::compact3(lA >> 1))) / 4;
         const int oz = (static_cast<int>(p2pd::compact3(lB >> 2)) - static_cast<int>(p2pd::compact3(lA >> 2))) / 4;
         const int o = (ox + 1) + 3 * (oy + 1) + 9 * (oz + 1);
-        s_row[o][j] = RED ? red_start[A] + 64 * (e - s_nstart[j]) : static_cast<int64_t>(leaf_start[B]);
+        s_row[o][j] = RED ? (red_row ? red_row[e] : red_start[A] + 64 * (e - s_nstart[j]))
+                          : static_cast<int64_t>(leaf_start[B]);
     }
     __syncthreads();
 
@@ -340,14 +406,25 @@ __global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols(
         ur[rt] = floatx4{0.f, 0.f, 0.f, 0.f};
         ui[rt] = floatx4{0.f, 0.f, 0.f, 0.f};
     }
+    // COMP: FP64 per-target sums of the per-offset FP32 partial products
+    constexpr int CN = COMP ? 4 : 1;
+    double cr[4][CN], ci[4][CN];
+    if constexpr (COMP) {
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) cr[rt][r] = ci[rt][r] = 0.0;
+    }
     // the Re G products of all four row tiles, then the Im G products: eight
-    // independent instructions between the two updates of an accumulator
-    auto mma = [&](const float2 (&gv)[4], const float2 q, float valid) {
+    // independent instructions between the two updates of an accumulator;
+    // fresh: the first k-step of an offset under COMP starts from zero
+    auto mma = [&](const float2 (&gv)[4], const float2 q, float valid, bool fresh) {
         const float2 qv = make_float2(q.x * valid, q.y * valid);
+        const floatx4 zero = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int rt = 0; rt < 4; ++rt) {
-            ur[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[rt].x, qv.x, ur[rt], 0, 0, 0);
-            ui[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[rt].x, qv.y, ui[rt], 0, 0, 0);
+            ur[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[rt].x, qv.x, fresh ? zero : ur[rt], 0, 0, 0);
+            ui[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[rt].x, qv.y, fresh ? zero : ui[rt], 0, 0, 0);
         }
 #pragma unroll
         for (int rt = 0; rt < 4; ++rt) {
@@ -386,19 +463,39 @@ __global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols(
                     vbuf[ks % kColBufs] = vn;
                 }
                 __builtin_amdgcn_sched_barrier(0);
-                mma(gbuf[kk % kColBufs], qbuf[kk % kColBufs], vbuf[kk % kColBufs]);
+                mma(gbuf[kk % kColBufs], qbuf[kk % kColBufs], vbuf[kk % kColBufs], COMP && kk == 0);
                 __builtin_amdgcn_sched_barrier(0);
+            }
+            if constexpr (COMP) {
+#pragma unroll
+                for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        cr[rt][r] += static_cast<double>(ur[rt][r]);
+                        ci[rt][r] += static_cast<double>(ui[rt][r]);
+                    }
             }
             Gc = Gn;
             Qc = Qn;
             vc = vn;
         }
     }
+    auto red_at = [&](int q, int rt, int im, int r) -> double & {
+        return s_redd[(((q * 4 + rt) * 2 + im) * 4 + r) * 64 + lane];
+    };
     if (w > 0) {
 #pragma unroll
         for (int rt = 0; rt < 4; ++rt) {
-            s_red[w - 1][rt][0][lane] = ur[rt];
-            s_red[w - 1][rt][1][lane] = ui[rt];
+            if constexpr (COMP) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    red_at(w - 1, rt, 0, r) = cr[rt][r];
+                    red_at(w - 1, rt, 1, r) = ci[rt][r];
+                }
+            } else {
+                s_red[w - 1][rt][0][lane] = ur[rt];
+                s_red[w - 1][rt][1][lane] = ui[rt];
+            }
         }
     }
     __syncthreads();
@@ -408,13 +505,24 @@ __global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols(
         for (int rt = 0; rt < 4; ++rt) {
 #pragma unroll
             for (int q = 0; q < kColWaves - 1; ++q) {
-                ur[rt] += s_red[q][rt][0][lane];
-                ui[rt] += s_red[q][rt][1][lane];
+                if constexpr (COMP) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        cr[rt][r] += red_at(q, rt, 0, r);
+                        ci[rt][r] += red_at(q, rt, 1, r);
+                    }
+                } else {
+                    ur[rt] += s_red[q][rt][0][lane];
+                    ui[rt] += s_red[q][rt][1][lane];
+                }
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int i = 16 * rt + 4 * kq + r;
-                u[perm[t0 + i]] = make_float2(ur[rt][r] * sc, ui[rt][r] * sc);
+                if constexpr (COMP)
+                    u[perm[t0 + i]] = make_float2(static_cast<float>(cr[rt][r] * sc), static_cast<float>(ci[rt][r] * sc));
+                else
+                    u[perm[t0 + i]] = make_float2(ur[rt][r] * sc, ui[rt][r] * sc);
             }
         }
     }
@@ -439,11 +547,16 @@ p2p_status launch_work_order(const int64_t *nbr_start, int64_t L, int32_t *work,
     return radix_sort_pairs(keys, work, keys_tmp, vals_tmp, L, 8, hist, s);
 }
 
-template <bool RED, bool CONJ, int TJ>
+template <bool RED, bool CONJ, int TJ, bool COMP>
 static void launch_mfma_t(const HelmholtzMfmaArgs &a, unsigned grid, unsigned block, hipStream_t s) {
-    k_helm_mfma<RED, CONJ, TJ><<<grid, block, 0, s>>>(
-        a.L, a.key_bits, a.nrhs, a.leaf_start, a.leaf_key, a.perm, a.nbr_start, a.nbr_idx,
-        a.red_start, a.src, a.blocks, a.copies, a.inst_table, a.inst_scale, a.work, a.counter, a.u);
+    if constexpr (TJ == 2 && COMP)
+        k_helm_mfma_wide<RED, CONJ><<<grid, block, 0, s>>>(
+            a.L, a.key_bits, a.nrhs, a.leaf_start, a.leaf_key, a.perm, a.nbr_start, a.nbr_idx,
+            a.red_start, a.red_row, a.src, a.blocks, a.copies, a.inst_table, a.inst_scale, a.work, a.counter, a.u);
+    else
+        k_helm_mfma<RED, CONJ, TJ, COMP><<<grid, block, 0, s>>>(
+            a.L, a.key_bits, a.nrhs, a.leaf_start, a.leaf_key, a.perm, a.nbr_start, a.nbr_idx,
+            a.red_start, a.red_row, a.src, a.blocks, a.copies, a.inst_table, a.inst_scale, a.work, a.counter, a.u);
 }
 
 p2p_status launch_helmholtz_mfma(const HelmholtzMfmaArgs &a, bool redundant, int waves_per_wg,
@@ -458,7 +571,8 @@ p2p_status launch_helmholtz_mfma(const HelmholtzMfmaArgs &a, bool redundant, int
     const unsigned grid = static_cast<unsigned>(cus) * static_cast<unsigned>(wg_per_cu);
     const bool cj = a.conj != 0;
     const int TJ = (rhs_tile == 64) ? 2 : 1;
-#define P2P_MF(R, C, T) launch_mfma_t<R, C, T>(a, grid, block, s)
+#define P2P_MF(R, C, T) \
+    (a.comp ? launch_mfma_t<R, C, T, true>(a, grid, block, s) : launch_mfma_t<R, C, T, false>(a, grid, block, s))
     if (TJ == 2) {
         if (redundant) { if (cj) P2P_MF(true, true, 2); else P2P_MF(true, false, 2); }
         else { if (cj) P2P_MF(false, true, 2); else P2P_MF(false, false, 2); }
@@ -494,14 +608,16 @@ int32_t helmholtz_cols_tiles(const p2p_grid *grids, int32_t n_grids, int32_t *ti
 p2p_status launch_helmholtz_mfma_cols(const HelmholtzMfmaArgs &a, const int32_t *tiles, const HelmInline &inl,
                                       int32_t n_tiles, bool redundant, hipStream_t s) {
     if (n_tiles <= 0) return P2P_OK;
-#define P2P_MFC(R, C)                                                                                   \
-    k_helm_mfma_cols<R, C><<<static_cast<unsigned>(n_tiles), 64 * kColWaves, 0, s>>>(                  \
-        a.key_bits, tiles, inl, a.leaf_start, a.leaf_key, a.perm, a.nbr_start, a.nbr_idx, a.red_start, a.src, \
+#define P2P_MFC2(R, C, M)                                                                               \
+    k_helm_mfma_cols<R, C, M><<<static_cast<unsigned>(n_tiles), 64 * kColWaves, 0, s>>>(               \
+        a.key_bits, tiles, inl, a.leaf_start, a.leaf_key, a.perm, a.nbr_start, a.nbr_idx, a.red_start, a.red_row, a.src, \
         a.blocks, a.inst_table, a.inst_scale, a.u)
+#define P2P_MFC(R, C) if (a.comp) P2P_MFC2(R, C, true); else P2P_MFC2(R, C, false)
     const bool cj = a.conj != 0;
-    if (redundant) { if (cj) P2P_MFC(true, true); else P2P_MFC(true, false); }
-    else { if (cj) P2P_MFC(false, true); else P2P_MFC(false, false); }
+    if (redundant) { if (cj) { P2P_MFC(true, true); } else { P2P_MFC(true, false); } }
+    else { if (cj) { P2P_MFC(false, true); } else { P2P_MFC(false, false); } }
 #undef P2P_MFC
+#undef P2P_MFC2
     P2P_LAUNCH_CHECK();
     return P2P_OK;
 }

@@ -168,6 +168,17 @@ p2p_status launch_copy_segments(const T *sorted, int64_t row_len, const int32_t 
                                 const int64_t *nbr_start, const int32_t *nbr_idx,
                                 const int64_t *red_start, int64_t L, T *dst, bool streaming,
                                 hipStream_t s, BoxSegments boxes = {});
+// Tile grain on grid trees (restructure.hip).  Without hs: cnt[A] = halo size
+// (boxes) of the tile whose first leaf is A, 0 for other leaves.  With hs (the
+// exclusive scan of cnt, hs[L] = H): the halo lists into halo_idx, red_row for
+// every near-list entry, red_start for every leaf and red_start[L].
+p2p_status launch_tile_halo(const uint64_t *leaf_key, const int64_t *nbr_start, const int32_t *nbr_idx,
+                            int64_t L, int key_bits, int grain, int64_t *cnt, const int64_t *hs,
+                            int32_t *halo_idx, int64_t *red_row, int64_t *red_start, hipStream_t s);
+// The tile segments: halo box j's 64 rows (caller rows of row_bytes each, read
+// through perm) to rows [64 j, 64 j + 64) of dst.
+p2p_status launch_tile_copy(const void *q, int64_t row_bytes, const int32_t *leaf_start, const int32_t *perm,
+                            const int32_t *halo_idx, int64_t H, void *dst, bool streaming, hipStream_t s);
 // Redundant layouts larger than this are written with streaming (nontemporal)
 // stores; smaller ones stay in the 256 MB last-level cache for the evaluation.
 constexpr int64_t kStreamingLayoutBytes = int64_t(128) << 20;
@@ -218,6 +229,16 @@ struct GravityArgs {
 };
 p2p_status launch_gravity(const GravityArgs &a, bool redundant, bool mixed, bool eps_zero,
                           hipStream_t s);
+// The evaluation behind p2p_eval_gravity (api.hip), split at the workspace:
+// the argument checks that come before the workspace query, then the checks
+// of the arrays and the launches, with the GATHER layout's sorted rows in s4
+// (tree->n rows; unused for REDUNDANT).
+p2p_status gravity_check_args(const p2p_tree *tree, const p2p_nbrs *nbrs, p2p_layout layout,
+                              p2p_precision prec, double eps);
+p2p_status gravity_run(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2p_redundant *red,
+                       p2p_layout layout, p2p_precision prec, double eps, const double *x,
+                       const double *y, const double *z, const double *m, double *phi, double *ax,
+                       double *ay, double *az, Row4d *s4, hipStream_t s);
 // Remote lists: targets read through perm from a.tx/ty/tz, sources of the
 // source tree (gather: through a.src_perm from a.sx/sy/sz/sm; redundant: the
 // remote segments), leaves with an empty list skipped, no self pair, sums
@@ -251,10 +272,12 @@ struct HelmholtzArgs {
     const int64_t *nbr_start;
     const int32_t *nbr_idx;
     const int64_t *red_start;
+    const int64_t *red_row;  // tile-grain layout: first row of each entry's source box (else null)
     const void *src;       // sorted q rows (gather) or redundant rows
     const void *table;     // per-instance G(dd) tables, [n_grids][kTableLen] complex
     int32_t nrhs;
     int32_t conj;          // 1: conj(q) in, conj(u) out
+    int32_t comp;          // FP32 payload: 1 = each near box's partial sum added into FP64 per target
     void *u;               // caller order
 };
 constexpr int kTableLen = 148;   // dd = 0..147 inside a 3x3x3-box neighbourhood of 4^3 boxes
@@ -272,6 +295,7 @@ struct HelmholtzMfmaArgs {
     const int64_t *nbr_start;
     const int32_t *nbr_idx;
     const int64_t *red_start;
+    const int64_t *red_row;    // tile-grain layout: first row of each entry's source box (else null)
     const float2 *src;         // sorted q rows (gather) or redundant rows, [.][nrhs]
     const float2 *blocks;      // [n_tables][copies][27][64 src][64 tgt] complex G blocks (unit spacing)
     int32_t copies;            // copies of each table; workgroup w reads copy (w / 8) % copies
@@ -281,6 +305,7 @@ struct HelmholtzMfmaArgs {
     int32_t *counter;          // work-queue counter (zeroed by the launcher)
     int32_t nrhs;
     int32_t conj;
+    int32_t comp;              // 1: each near box's FP32 partial product summed into FP64 per target
     float2 *u;                 // caller order [n][nrhs]
 };
 // Per-call parameters of a grid with at most kInlineGrids instances, passed by

@@ -6,6 +6,8 @@
 // order into sorted order (one pass, N rows), then every segment is filled
 // with coalesced copies, walking the segment in row order and locating the
 // source leaf of each row in the prefix of neighbour occupancies kept in LDS.
+#include <algorithm>
+
 #include "p2p_internal.h"
 
 namespace p2p {
@@ -326,6 +328,149 @@ __global__ __launch_bounds__(kCopyBlock) void k_copy_segments_units(
     }
 }
 
+// ---------------------------------------------------------------- tiles --
+// Block-level redundancy on grid trees (Sec. 3.5: for dense, regular
+// distributions the data are duplicated per block of work, not per thread).
+// A tile is the set of boxes of one instance whose box coordinates agree after
+// division by the grain g (a power of two): an aligned g x g x g block, which
+// in Morton order is one contiguous run of leaves, and whose first leaf is the
+// block's lower corner.  The tile's segment holds the rows of the union of its
+// boxes' near lists (its halo: the boxes of the window of (g+2)^3 box cells
+// around it that exist), in ascending leaf id, every box 64 rows.
+constexpr int kTileMaxGrain = 4;
+constexpr int kTileWin = (kTileMaxGrain + 2) * (kTileMaxGrain + 2) * (kTileMaxGrain + 2);
+
+__device__ inline void box_cell(uint64_t key, uint64_t local_mask, int c[3]) {
+    const uint64_t l = key & local_mask;
+    c[0] = static_cast<int>(p2pd::compact3(l)) >> 2;
+    c[1] = static_cast<int>(p2pd::compact3(l >> 1)) >> 2;
+    c[2] = static_cast<int>(p2pd::compact3(l >> 2)) >> 2;
+}
+
+// One 64-lane workgroup per leaf; only the first leaf of a tile works.  The
+// halo is marked in a window of box cells (every entry of the tile's lists
+// writes its source's id into its cell; entries naming one box write the same
+// value), then each marked cell is ranked among the marked ones by id.
+// FILL = false: cnt[A] = halo size at the tile's first leaf A, 0 elsewhere.
+// FILL = true: with hs = the exclusive scan of cnt, the tile's halo ids go to
+// halo_idx[hs[A] ..], every entry e of its lists gets red_row[e] = 64 (hs[A]
+// + rank of its source), and every leaf of the tile red_start = 64 hs[A].
+template <bool FILL>
+__global__ __launch_bounds__(64) void k_tile_halo(const uint64_t *__restrict__ leaf_key,
+                                                  const int64_t *__restrict__ nbr_start,
+                                                  const int32_t *__restrict__ nbr_idx, int64_t L, int key_bits,
+                                                  int lg, int64_t *__restrict__ cnt,
+                                                  const int64_t *__restrict__ hs, int32_t *__restrict__ halo_idx,
+                                                  int64_t *__restrict__ red_row, int64_t *__restrict__ red_start) {
+    __shared__ int32_t s_id[kTileWin];
+    __shared__ int32_t s_rank[kTileWin];
+    const int64_t A = blockIdx.x;
+    if (A >= L) return;
+    const int lane = threadIdx.x;
+    const int shift = 3 * (2 + lg);
+    const uint64_t kA = leaf_key[A];
+    const uint64_t tk = kA >> shift;
+    const bool first = A == 0 || (leaf_key[A - 1] >> shift) != tk;
+    if (!first) {
+        if (!FILL && lane == 0) cnt[A] = 0;
+        return;
+    }
+    const int g = 1 << lg, gw = g + 2, W = gw * gw * gw;
+    // the tile's leaves: A .. A + nb - 1 (contiguous in key order, at most g^3 <= 64)
+    const bool mine = lane < g * g * g && A + lane < L && (leaf_key[A + lane] >> shift) == tk;
+    const int nb = __popcll(__ballot(mine));
+    const uint64_t local_mask = (1ull << (3 * key_bits)) - 1ull;
+    int o[3];
+    box_cell(kA, local_mask, o);
+    for (int c = lane; c < W; c += 64) s_id[c] = -1;
+    __syncthreads();
+    const int64_t e0 = nbr_start[A], e1 = nbr_start[A + nb];
+    auto cell_of = [&](int32_t B) {
+        int c[3];
+        box_cell(leaf_key[B], local_mask, c);
+        return (c[0] - o[0] + 1) + gw * ((c[1] - o[1] + 1) + gw * (c[2] - o[2] + 1));
+    };
+    for (int64_t e = e0 + lane; e < e1; e += 64) {
+        const int32_t B = nbr_idx[e];
+        s_id[cell_of(B)] = B;
+    }
+    __syncthreads();
+    int marked = 0;
+    for (int c = lane; c < W; c += 64) {
+        const int32_t id = s_id[c];
+        int r = 0;
+        if (id >= 0)
+            for (int d = 0; d < W; ++d) {
+                const int32_t v = s_id[d];
+                r += (v >= 0 && v < id) ? 1 : 0;
+            }
+        s_rank[c] = r;
+        marked += id >= 0 ? 1 : 0;
+    }
+    if constexpr (!FILL) {
+        for (int off = 32; off > 0; off >>= 1) marked += __shfl_xor(marked, off, 64);
+        if (lane == 0) cnt[A] = marked;
+    } else {
+        __syncthreads();
+        const int64_t h0 = hs[A];
+        for (int c = lane; c < W; c += 64)
+            if (s_id[c] >= 0) halo_idx[h0 + s_rank[c]] = s_id[c];
+        for (int64_t e = e0 + lane; e < e1; e += 64) red_row[e] = 64 * (h0 + s_rank[cell_of(nbr_idx[e])]);
+        if (lane < nb) red_start[A + lane] = 64 * h0;
+        if (lane == 0 && A + nb == L) red_start[L] = 64 * hs[L];
+    }
+}
+
+// The tile segments' rows: box halo_idx[j] goes to rows [64 j, 64 j + 64),
+// read from caller order through perm (a grid box's rows are runs of 4
+// consecutive caller rows, whole rows of upr units each).  Workgroups stride
+// over the halo boxes; each thread keeps UN units in flight.
+template <class U, int UN, bool NT>
+__global__ __launch_bounds__(kCopyBlock) void k_tile_copy(const U *__restrict__ q, int64_t upr, int lg_upr,
+                                                         const int32_t *__restrict__ leaf_start,
+                                                         const int32_t *__restrict__ perm,
+                                                         const int32_t *__restrict__ halo_idx, int64_t H,
+                                                         U *__restrict__ dst) {
+    const int64_t units = 64 * upr;
+    for (int64_t j = blockIdx.x; j < H; j += gridDim.x) {
+        const int32_t r0 = leaf_start[halo_idx[j]];
+        U *__restrict__ d = dst + j * units;
+        for (int64_t u0 = threadIdx.x; u0 < units; u0 += kCopyBlock * UN) {
+            U v[UN];
+#pragma unroll
+            for (int k = 0; k < UN; ++k) {
+                // units past the end repeat the last unit (same bytes, same place)
+                const int64_t u = min(u0 + kCopyBlock * k, units - 1);
+                const int64_t row = lg_upr >= 0 ? (u >> lg_upr) : u / upr;
+                v[k] = q[static_cast<int64_t>(perm[r0 + row]) * upr + (u - row * upr)];
+            }
+#pragma unroll
+            for (int k = 0; k < UN; ++k) put_row<NT>(d + min(u0 + kCopyBlock * k, units - 1), v[k]);
+        }
+    }
+}
+
+template <class U>
+p2p_status tile_copy_units(const void *q, int64_t row_bytes, const int32_t *leaf_start, const int32_t *perm,
+                           const int32_t *halo_idx, int64_t H, void *dst, bool streaming, hipStream_t s) {
+    const int64_t upr = row_bytes / static_cast<int64_t>(sizeof(U));
+    int lg = -1;
+    for (int b = 0; b < 40; ++b)
+        if ((int64_t(1) << b) == upr) lg = b;
+    int dev = 0, cus = 0;
+    P2P_HIP(hipGetDevice(&dev));
+    P2P_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const unsigned grid = static_cast<unsigned>(std::min<int64_t>(H, static_cast<int64_t>(cus) * 8));
+    if (streaming)
+        k_tile_copy<U, 4, true><<<grid, kCopyBlock, 0, s>>>(static_cast<const U *>(q), upr, lg, leaf_start, perm,
+                                                            halo_idx, H, static_cast<U *>(dst));
+    else
+        k_tile_copy<U, 4, false><<<grid, kCopyBlock, 0, s>>>(static_cast<const U *>(q), upr, lg, leaf_start, perm,
+                                                             halo_idx, H, static_cast<U *>(dst));
+    P2P_LAUNCH_CHECK();
+    return P2P_OK;
+}
+
 }  // namespace
 
 p2p_status launch_seg_lengths(const int32_t *leaf_start, const int64_t *nbr_start,
@@ -452,6 +597,33 @@ p2p_status launch_copy_segments(const T *sorted, int64_t row_len, const int32_t 
     default:
         return copy_units<uint32_t>(sorted, rb, leaf_start, nbr_start, nbr_idx, red_start, L, dst, streaming,
                                     s, boxes);
+    }
+}
+
+p2p_status launch_tile_halo(const uint64_t *leaf_key, const int64_t *nbr_start, const int32_t *nbr_idx,
+                            int64_t L, int key_bits, int grain, int64_t *cnt, const int64_t *hs,
+                            int32_t *halo_idx, int64_t *red_row, int64_t *red_start, hipStream_t s) {
+    if (L <= 0) return P2P_OK;
+    int lg = 0;
+    while ((1 << lg) < grain) ++lg;
+    if ((1 << lg) != grain || grain > kTileMaxGrain) return fail(P2P_EINVAL, "internal: tile grain");
+    if (!hs)
+        k_tile_halo<false><<<static_cast<unsigned>(L), 64, 0, s>>>(leaf_key, nbr_start, nbr_idx, L, key_bits, lg,
+                                                                   cnt, nullptr, nullptr, nullptr, nullptr);
+    else
+        k_tile_halo<true><<<static_cast<unsigned>(L), 64, 0, s>>>(leaf_key, nbr_start, nbr_idx, L, key_bits, lg,
+                                                                  nullptr, hs, halo_idx, red_row, red_start);
+    P2P_LAUNCH_CHECK();
+    return P2P_OK;
+}
+
+p2p_status launch_tile_copy(const void *q, int64_t row_bytes, const int32_t *leaf_start, const int32_t *perm,
+                            const int32_t *halo_idx, int64_t H, void *dst, bool streaming, hipStream_t s) {
+    if (H <= 0) return P2P_OK;
+    switch (unit_bytes(row_bytes)) {
+    case 16: return tile_copy_units<uint4>(q, row_bytes, leaf_start, perm, halo_idx, H, dst, streaming, s);
+    case 8: return tile_copy_units<uint2>(q, row_bytes, leaf_start, perm, halo_idx, H, dst, streaming, s);
+    default: return tile_copy_units<uint32_t>(q, row_bytes, leaf_start, perm, halo_idx, H, dst, streaming, s);
     }
 }
 

@@ -91,6 +91,9 @@ def test_eval_rejects_bad_modes(lib):
     assert lib.p2p_eval_gravity(*args(L.P2P_GATHER, L.P2P_FP64, -1.0)) == L.P2P_EINVAL
     assert lib.p2p_eval_gravity(*args(L.P2P_GATHER, L.P2P_FP64, float("nan"))) == L.P2P_EINVAL
     assert lib.p2p_eval_gravity(*args(L.P2P_GATHER, L.P2P_FP64, 1e-3)) == L.P2P_OK   # size query
+    # single precision throughout is a Helmholtz mode: gravity refuses it
+    assert lib.p2p_eval_gravity(*args(L.P2P_GATHER, L.P2P_FP32, 1e-3)) == L.P2P_EUNSUPPORTED
+    assert "Helmholtz paths only" in L.last_error()
     # redundant layout without a redundant structure: rejected once the workspace is given
     nb.value = 1 << 20
     st = lib.p2p_eval_gravity(ctypes.byref(t), ctypes.byref(n), None, L.P2P_REDUNDANT, L.P2P_FP64,
@@ -202,6 +205,39 @@ def test_helmholtz_tile_validation(lib):
     assert query((4, 2, 64, 1), nrhs=32) == L.P2P_EINVAL and "tile[2]" in L.last_error()
     assert query((4, 2, 32, 1), nrhs=1) == L.P2P_EINVAL          # no tile off the matrix-core path
     assert query(None, nrhs=1) == L.P2P_OK
+    assert query((4, 2, 64, 1), prec=L.P2P_FP32) == L.P2P_OK      # single precision throughout
+    assert query(None, prec=7) == L.P2P_EINVAL
+
+
+def test_tile_grain_restructure_validation(lib):
+    """The tile grain is refused on particle trees and for grains other than
+    2 and 4; a tile-grain layout without its entry rows is refused."""
+    t = _tree(1000, L_=10)
+    t.perm = t.iperm = t.leaf_start = t.leaf_key = t.leaf_level = 0x1000
+    nl = L.p2p_nbrs()
+    nl.count, nl.nbr_start, nl.nbr_idx, nl.red_entries = 10, 0x1000, 0x1000, 100
+    z = ctypes.c_void_p(0x1000)
+    srcs = L.PV4(z, z, z, z)
+    nb = ctypes.c_size_t(0)
+    red = L.p2p_redundant()
+    red.red_start = red.red_self = 0x1000
+    red.grain = 2
+    st = lib.p2p_restructure_redundant(ctypes.byref(t), ctypes.byref(nl), ctypes.byref(srcs), 1, L.P2P_FP64,
+                                       ctypes.byref(red), None, ctypes.byref(nb), None)
+    assert st == L.P2P_EINVAL and "grid trees only" in L.last_error()
+    t.kind, t.n_grids, t.key_bits = L.P2P_TREE_GRIDS, 1, 4
+    red.grain = 3
+    st = lib.p2p_restructure_redundant(ctypes.byref(t), ctypes.byref(nl), ctypes.byref(srcs), 1, L.P2P_FP32,
+                                       ctypes.byref(red), None, ctypes.byref(nb), None)
+    assert st == L.P2P_EINVAL and "grain" in L.last_error()
+    red.grain = 4
+    st = lib.p2p_restructure_redundant(ctypes.byref(t), ctypes.byref(nl), ctypes.byref(srcs), 1, L.P2P_FP32,
+                                       ctypes.byref(red), None, ctypes.byref(nb), None)
+    assert st == L.P2P_OK and nb.value > 0                        # workspace size
+    nb.value = 1 << 20
+    st = lib.p2p_restructure_redundant(ctypes.byref(t), ctypes.byref(nl), ctypes.byref(srcs), 1, L.P2P_FP32,
+                                       ctypes.byref(red), ctypes.c_void_p(0x100000), ctypes.byref(nb), None)
+    assert st == L.P2P_EINVAL and "red_row" in L.last_error()
 
 
 def test_periodic_list_validation(lib):

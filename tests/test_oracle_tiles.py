@@ -96,3 +96,19 @@ def test_entries_point_at_their_source_rows(grain):
         np.testing.assert_array_equal(pay[rr[e]:rr[e] + 64], src[t.perm[t.leaf_start[B]:t.leaf_start[B + 1]]])
     # the tile segments hold nothing else: every row is some entry's source row
     assert pay.shape[0] == ss[-1] and len(np.unique(rr)) == len(hi)
+
+
+@pytest.mark.parametrize("grain", [2, 4])
+def test_binding_sizes_the_tile_layout_like_the_oracle(grain):
+    """The Python binding sizes the tile-grain buffers from the grids alone
+    (per-axis window extents); the oracle's segment total must match it."""
+    from paper_2511_21535_amd import api
+    from paper_2511_21535_amd import workloads as W
+    for sides in ([12, 8, 20, 4], [16], [48, 36, 28], list(W.batched_grid_sides(9, 7))):
+        t = oracle.build_tree_grids(sides)
+        s, i = oracle.neighbors(t)
+        _, _, _, ss, _ = oracle.tile_layout(t, s, i, grain)
+        fake = api.Tree(n=0, n_leaves=0, kind=0, key_bits=0, max_level=0, perm=None, leaf_start=None,
+                        leaf_key=None, leaf_level=None, iperm=None,
+                        grids=[api.Grid(int(n), 1.0 / n, 0.0) for n in sides])
+        assert api.tile_entries(fake, grain) == ss[-1], sides
