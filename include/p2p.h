@@ -289,7 +289,10 @@ p2p_status p2p_restructure_redundant(const p2p_tree *tree, const p2p_nbrs *nbrs,
  * GATHER layout -- the SoA + indexing baseline of Sec. 5.2.1 -- or from the
  * REDUNDANT layout of Sec. 5.2.1; the update step of Eq. 2 fused): for every
  * particle i, phi_i and a_i as in the header comment, eps >= 0 (eps == 0
- * drops pairs at zero distance).  x, y, z, m: caller-order double[n] (needed
+ * drops pairs at zero distance; a positive eps must be >= 1e-4 with
+ * FP32_MIXED, whose add-back of the target's own term m_i/eps leaves its
+ * float rounding in phi_i, and >= 2^-511 with FP64, which drops that pair by
+ * position; smaller positive eps is P2P_EINVAL).  x, y, z, m: caller-order double[n] (needed
  * for GATHER; ignored for REDUNDANT, which reads `red`, built with the same
  * precision).  Outputs phi, ax, ay, az: caller-order double[n], overwritten. */
 p2p_status p2p_eval_gravity(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2p_redundant *red,
@@ -322,12 +325,59 @@ p2p_status p2p_eval_helmholtz(const p2p_tree *tree, const p2p_nbrs *nbrs, const 
                               const void *q, void *u, const int32_t *tile,
                               void *ws, size_t *ws_bytes, p2p_stream_t stream);
 
+/* Precomputed interaction patterns for the Helmholtz evaluation (the dense
+ * regular case of Sec. 5.1, where the near-field patterns are computed once and
+ * reused by every box and every call).  A plan holds, in a caller-owned device
+ * buffer, what p2p_eval_helmholtz otherwise rebuilds on every call: the
+ * instances' parameters, the G blocks of every distinct k h built in double
+ * precision and rounded to single (matrix-core paths) or the G(d^2) tables
+ * (vector path), and the work-queue order by decreasing near-list length
+ * (several right-hand sides).  Host struct. */
+typedef struct {
+    void *buf;            /* in: device buffer, 256-byte aligned; NULL asks for the size */
+    size_t bytes;         /* in: size of buf; out (buf == NULL): bytes needed */
+    int32_t prec;         /* out: p2p_precision the plan serves */
+    int32_t nrhs;         /* out: right-hand sides per call */
+    int32_t tile[4];      /* out: launch shape (as for p2p_eval_helmholtz) */
+    int32_t tiled;        /* out: 1 if a tile was given to p2p_helmholtz_prepare */
+    int32_t reserved;
+    uint64_t fingerprint; /* out: of the sizes of tree and lists, the grids, prec,
+                             nrhs and tile; 0 = not prepared */
+} p2p_helmholtz_plan;
+
+/* Build a plan for evaluations on `tree`/`nbrs` with these grids, precision,
+ * nrhs and tile (arguments as for p2p_eval_helmholtz).  With plan->buf ==
+ * NULL only plan->bytes is written.  Otherwise the set-up is queued on
+ * `stream` into plan->buf (P2P_EINVAL if plan->bytes is too small).  Plans
+ * whose parameters do not travel in the kernel arguments (more than 8
+ * instances or G tables, several right-hand sides, FP64) copy them from host
+ * memory: P2P_EUNSUPPORTED while `stream` is capturing.  The plan stays
+ * valid while the tree, the lists and the grids stay as they were. */
+p2p_status p2p_helmholtz_prepare(const p2p_tree *tree, const p2p_nbrs *nbrs, p2p_precision prec,
+                                 const p2p_grid *grids, int32_t n_grids, int32_t nrhs,
+                                 const int32_t *tile, p2p_helmholtz_plan *plan, p2p_stream_t stream);
+
+/* p2p_eval_helmholtz from a plan: the same results, with the precision, nrhs
+ * and tile of the plan, and no set-up work: a REDUNDANT call is one product
+ * launch (two with several right-hand sides: the work-queue counter is
+ * zeroed first), a GATHER call adds the copy of q into box order.  The
+ * workspace holds only that copy and the counter.  P2P_EINVAL if the plan was
+ * prepared for other sizes, grids, precision, nrhs or tile.  Never copies
+ * from host memory or synchronises, so it may be captured into a HIP graph.
+ * Calls that share one plan may overlap (the plan is only read). */
+p2p_status p2p_eval_helmholtz_prepared(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2p_redundant *red,
+                                       p2p_layout layout, const p2p_grid *grids, int32_t n_grids,
+                                       const p2p_helmholtz_plan *plan, const void *q, void *u,
+                                       void *ws, size_t *ws_bytes, p2p_stream_t stream);
+
 /* Adjoint (not in the paper; the gradient that the DBIM inversion of Sec. 4
  * descends along, and the stellar-dynamics forces differentiated).
  *  kind == P2P_KIND_GRAVITY: fwd_in = {x, y, z, m}, grad_out = {g_phi, g_ax,
  *    g_ay, g_az}, grad_in = {g_x, g_y, g_z, g_m}, all caller-order double[n]:
  *    the gradients of L = sum_i g_phi_i phi_i + g_a_i . a_i with respect to
- *    positions and masses (tree frozen), eps > 0.  GATHER layout; FP64, or
+ *    positions and masses (tree frozen), eps > 0 (FP64: eps >= 2^-511;
+ *    FP32_MIXED: eps >= 1e-3, since the float rounding of the w^5 terms of
+ *    close pairs grows as eps shrinks; else P2P_EINVAL).  GATHER layout; FP64, or
  *    FP32_MIXED (positions relative to the target leaf's centre, float pair
  *    terms, double accumulation, as in the forward evaluation).
  *  kind == P2P_KIND_HELMHOLTZ: grad_out[0] = g (caller order [n][nrhs]

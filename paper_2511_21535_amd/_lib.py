@@ -25,6 +25,7 @@ EXPORTED = ["p2p_build_tree", "p2p_build_neighbors", "p2p_restructure_redundant"
             "p2p_eval_gravity", "p2p_eval_helmholtz", "p2p_adjoint", "p2p_locality",
             "p2p_restructure_interactions", "p2p_eval_gravity_interactions",
             "p2p_build_neighbors_remote", "p2p_restructure_remote", "p2p_eval_gravity_remote",
+            "p2p_helmholtz_prepare", "p2p_eval_helmholtz_prepared",
             "p2p_last_error", "p2p_version"]
 
 
@@ -67,6 +68,12 @@ class p2p_locality_t(ctypes.Structure):
                 ("v_red", ctypes.c_double), ("d_ratio", ctypes.c_double),
                 ("v_ratio", ctypes.c_double), ("locality", ctypes.c_double),
                 ("pairs", ctypes.c_int64), ("entries", ctypes.c_int64)]
+
+
+class p2p_helmholtz_plan(ctypes.Structure):
+    _fields_ = [("buf", ctypes.c_void_p), ("bytes", ctypes.c_size_t), ("prec", ctypes.c_int32),
+                ("nrhs", ctypes.c_int32), ("tile", ctypes.c_int32 * 4), ("tiled", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("fingerprint", ctypes.c_uint64)]
 
 
 _lib = None
@@ -124,6 +131,11 @@ def load():
     lib.p2p_restructure_remote.argtypes = [T, T, N, ctypes.POINTER(PV4), I32, R, V, SZ, V]
     lib.p2p_eval_gravity_remote.restype = st
     lib.p2p_eval_gravity_remote.argtypes = [T, T, N, R, I32, I32, F64] + [V] * 11 + [V, SZ, V]
+    HP, GP = ctypes.POINTER(p2p_helmholtz_plan), ctypes.POINTER(p2p_grid)
+    lib.p2p_helmholtz_prepare.restype = st
+    lib.p2p_helmholtz_prepare.argtypes = [T, N, I32, GP, I32, I32, ctypes.POINTER(ctypes.c_int32), HP, V]
+    lib.p2p_eval_helmholtz_prepared.restype = st
+    lib.p2p_eval_helmholtz_prepared.argtypes = [T, N, R, I32, GP, I32, HP, V, V, V, SZ, V]
     lib.p2p_locality.restype = st
     lib.p2p_locality.argtypes = [ctypes.POINTER(p2p_tree), ctypes.POINTER(p2p_nbrs),
                                  ctypes.POINTER(p2p_redundant), F64, F64,
@@ -195,6 +207,14 @@ def p2p_restructure_remote(*args):
 
 def p2p_eval_gravity_remote(*args):
     return load().p2p_eval_gravity_remote(*args)
+
+
+def p2p_helmholtz_prepare(*args):
+    return load().p2p_helmholtz_prepare(*args)
+
+
+def p2p_eval_helmholtz_prepared(*args):
+    return load().p2p_eval_helmholtz_prepared(*args)
 
 
 def p2p_locality(*args):

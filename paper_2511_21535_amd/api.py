@@ -492,10 +492,15 @@ def gravity(tree: Tree, nbrs: Nbrs, eps: float, x=None, y=None, z=None, m=None,
 
 def helmholtz(tree: Tree, nbrs: Nbrs, q: Optional[torch.Tensor] = None, layout="gather",
               prec="fp32", red: Optional[Redundant] = None, nrhs: Optional[int] = None,
-              tile: Optional[Sequence[int]] = None, out: Optional[torch.Tensor] = None):
+              tile: Optional[Sequence[int]] = None, out: Optional[torch.Tensor] = None,
+              plan: Optional["HelmholtzPlan"] = None):
     """Near-field Helmholtz on the grids of `tree`.  q, u: [n, nrhs] (or [n])
-    complex64 (fp32) or complex128 (fp64), caller order."""
+    complex64 (fp32) or complex128 (fp64), caller order.  With `plan`
+    (HelmholtzPlan) the precision, nrhs and tile are the plan's and the call
+    does no set-up (p2p_eval_helmholtz_prepared)."""
     dev = tree.leaf_start.device
+    if plan is not None:
+        prec, nrhs = plan.prec, plan.nrhs
     if nrhs is None:
         nrhs = red.nrhs if red is not None else (1 if q.dim() == 1 else q.shape[1])
     cd = torch.complex128 if PREC[prec] == L.P2P_FP64 else torch.complex64
@@ -504,6 +509,8 @@ def helmholtz(tree: Tree, nbrs: Nbrs, q: Optional[torch.Tensor] = None, layout="
         shape = (tree.n,) if (q is not None and q.dim() == 1) or (q is None and nrhs == 1) else (tree.n, nrhs)
         out = torch.empty(shape, dtype=cd, device=dev)
     _vec(out, "out", tree.n * nrhs, cd)
+    if plan is not None:
+        return _helmholtz_prepared(tree, nbrs, plan, q, out, layout, red)
     gs, _ = grids_struct(tree.grids)
     ts, ns = tree.struct(), nbrs.struct()
     rs = red.struct() if red is not None else None
@@ -516,6 +523,43 @@ def helmholtz(tree: Tree, nbrs: Nbrs, q: Optional[torch.Tensor] = None, layout="
                                     LAYOUT[layout], PREC[prec], gs, len(tree.grids), nrhs, _ptr(q),
                                     _ptr(out), tl, ws, nb, _stream())
     st, ws = _call(call, dev)
+    L.check(st)
+    return out
+
+
+class HelmholtzPlan:
+    """The set-up of the Helmholtz evaluation built once (p2p_helmholtz_prepare):
+    parameters, FP64-built G blocks or tables, work-queue order, in a device
+    buffer owned here.  Pass it to helmholtz(..., plan=...)."""
+
+    def __init__(self, tree: Tree, nbrs: Nbrs, prec="fp32", nrhs: int = 1,
+                 tile: Optional[Sequence[int]] = None):
+        dev = tree.leaf_start.device
+        self.prec, self.nrhs = prec, int(nrhs)
+        gs, _ = grids_struct(tree.grids)
+        ts, ns = tree.struct(), nbrs.struct()
+        tl = (ctypes.c_int32 * 4)(*(tuple(tile) + (1,) * (4 - len(tile)))) if tile is not None else None
+        p = L.p2p_helmholtz_plan()
+        L.check(L.p2p_helmholtz_prepare(ctypes.byref(ts), ctypes.byref(ns), PREC[prec], gs,
+                                               len(tree.grids), self.nrhs, tl, ctypes.byref(p), _stream()))
+        self.buf = torch.empty(max(int(p.bytes), 1), dtype=torch.uint8, device=dev)
+        p.buf = self.buf.data_ptr()
+        L.check(L.p2p_helmholtz_prepare(ctypes.byref(ts), ctypes.byref(ns), PREC[prec], gs,
+                                               len(tree.grids), self.nrhs, tl, ctypes.byref(p), _stream()))
+        self.struct = p
+
+
+def _helmholtz_prepared(tree, nbrs, plan, q, out, layout, red):
+    gs, _ = grids_struct(tree.grids)
+    ts, ns = tree.struct(), nbrs.struct()
+    rs = red.struct() if red is not None else None
+
+    def call(ws, nb):
+        return L.p2p_eval_helmholtz_prepared(ctypes.byref(ts), ctypes.byref(ns),
+                                             ctypes.byref(rs) if rs is not None else None, LAYOUT[layout], gs,
+                                             len(tree.grids), ctypes.byref(plan.struct), _ptr(q), _ptr(out), ws,
+                                             nb, _stream())
+    st, _ = _call(call, tree.leaf_start.device)
     L.check(st)
     return out
 

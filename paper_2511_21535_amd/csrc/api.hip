@@ -128,24 +128,33 @@ p2p_status check_remote_trees(const p2p_tree *tree, const p2p_tree *src_tree) {
 }
 
 // Softening length of the gravity sums.  eps == 0 drops pairs at zero
-// distance.  A positive eps keeps every pair: the kernels sum the target's own
-// d = 0 term m_i / eps with the others and subtract it again afterwards, so
-// the rounding of the sum that held it, about 2^-24 m_i / eps in a
-// single-precision partial (FP32_MIXED) or 2^-53 m_i / eps (FP64), stays in
-// phi_i.  Against a near-field potential of a few thousand m_i (a sparse
-// target: tens of neighbours at a few hundredths) that stays within the
-// stated tolerances (1e-5 relative in FP32_MIXED, 1e-12 in FP64) for
-// eps >= 1e-4 and eps >= 1e-8 respectively; smaller positive eps is refused
-// rather than summed inexactly (eps == 0 remains available).
+// distance.  A positive eps keeps every pair of distinct points.  FP64 drops
+// the target's own pair by position, so any positive eps whose square is a
+// normal double (eps >= 2^-511) is exact to rounding.  FP32_MIXED sums the
+// target's own d = 0 term m_i / eps into a float partial of at most 32 pair
+// terms and subtracts it again afterwards, so the rounding of that partial,
+// up to about 32 * 2^-24 m_i / eps, stays in phi_i.  Against a near-field
+// potential of a few thousand m_i (a sparse target: tens of neighbours at a
+// few hundredths) that stays within 1e-5 relative for eps >= 1e-4; smaller
+// positive eps is refused in FP32_MIXED rather than summed inexactly (eps ==
+// 0, or FP64, remain available).  The FP32_MIXED adjoint needs eps >= 1e-3:
+// its position gradient carries w^5 (d . g) d terms of close pairs, whose
+// float rounding measured 2.9e-5 relative at eps = 1e-4 on a 3000-particle
+// Plummer mixture (leaf cap 64) and stays within 1e-5 at 1e-3.
 constexpr double kMinEpsMixed = 1e-4;
-constexpr double kMinEpsFp64 = 1e-8;
+constexpr double kMinEpsMixedAdjoint = 1e-3;
+constexpr double kMinEpsFp64 = 0x1p-511;
 
-p2p_status check_eps(double eps, bool mixed, bool positive = false) {
+// adjoint: the gravity adjoint's bounds (eps > 0, and 1e-3 in FP32_MIXED)
+p2p_status check_eps(double eps, bool mixed, bool adjoint = false) {
     if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(P2P_EINVAL, "eps must be finite and >= 0");
-    if (positive && eps == 0.0) return fail(P2P_EINVAL, "the gravity adjoint needs eps > 0");
-    const double lo = mixed ? kMinEpsMixed : kMinEpsFp64;
+    if (adjoint && eps == 0.0) return fail(P2P_EINVAL, "the gravity adjoint needs eps > 0");
+    const double lo = mixed ? (adjoint ? kMinEpsMixedAdjoint : kMinEpsMixed) : kMinEpsFp64;
     if (eps > 0.0 && eps < lo)
-        return fail(P2P_EINVAL, std::string("eps must be 0 or >= ") + (mixed ? "1e-4 with P2P_FP32_MIXED" : "1e-8 with P2P_FP64"));
+        return fail(P2P_EINVAL, std::string("eps must be 0 or >= ") +
+                                    (mixed ? (adjoint ? "1e-3 with P2P_FP32_MIXED in the adjoint"
+                                                      : "1e-4 with P2P_FP32_MIXED")
+                                           : "2^-511 (eps^2 a normal double) with P2P_FP64"));
     return P2P_OK;
 }
 
@@ -792,110 +801,185 @@ extern "C" p2p_status p2p_eval_gravity_remote(const p2p_tree *tree, const p2p_tr
 // ----------------------------------------------------------- Helmholtz ----
 namespace {
 
-struct HelmPlan {
-    bool fp64, redundant;
-    const double *d_h, *d_k;
-    void *table;
-    void *sorted;
+// Everything a Helmholtz evaluation derives from its arguments on the host:
+// the path (matrix cores multi-RHS or single RHS, or the vector kernel), the
+// launch shape, the distinct k h values (one G table or set of G blocks each),
+// and the layout of the set-up buffer.  The set-up buffer (the plan) holds the
+// instances' parameters, the G tables or blocks and the work-queue order; it
+// is filled by helm_fill, either on every call (p2p_eval_helmholtz, in the
+// workspace) or once (p2p_helmholtz_prepare, in a caller buffer).
+struct HelmSetup {
+    p2p_precision prec;
+    int32_t nrhs;
+    bool fp64, mfma, cols, blk, inline_params;
+    int waves_per_wg = 4, wg_per_cu = 2, rhs_tile = 32, copies = 1;
+    int32_t n_grids = 0, n_tables = 0, n_tiles = 0;
+    std::vector<double> khs;
+    std::vector<int32_t> itab;
+    std::vector<float> iscale;
+    size_t o_k = 0, o_kh = 0, o_itab = 0, o_isc = 0, o_tiles = 0, param_bytes = 0;
+    HelmInline inl{};
 };
 
-p2p_status helmholtz_common(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2p_redundant *red,
-                            p2p_layout layout, p2p_precision prec, const p2p_grid *grids,
-                            int32_t n_grids, int32_t nrhs, const void *q, void *u, int32_t conj,
-                            const int32_t *tile, void *ws, size_t *ws_bytes, hipStream_t s) {
-    if (!ws_bytes) return fail(P2P_EINVAL, "ws_bytes must not be NULL");
+// Device arrays of the set-up inside an arena (null pointers when sizing).
+struct HelmSetupBufs {
+    char *params = nullptr;
+    char *table = nullptr;
+    float2 *blocks = nullptr;
+    int32_t *work = nullptr;
+    uint64_t *wkeys = nullptr, *wkeys_tmp = nullptr;
+    int32_t *wvals_tmp = nullptr;
+    uint32_t *whist = nullptr;
+};
+
+p2p_status helm_setup(const p2p_tree *tree, const p2p_nbrs *nbrs, p2p_precision prec, const p2p_grid *grids,
+                      int32_t n_grids, int32_t nrhs, const int32_t *tile, HelmSetup *h) {
     P2P_TRY(check_tree(tree));
     if (tree->kind != P2P_TREE_GRIDS) return fail(P2P_EINVAL, "Helmholtz needs a grid tree");
     P2P_TRY(check_nbrs(tree, nbrs));
-    if (layout != P2P_GATHER && layout != P2P_REDUNDANT) return fail(P2P_EINVAL, "bad layout");
     if (prec != P2P_FP64 && prec != P2P_FP32_MIXED && prec != P2P_FP32) return fail(P2P_EINVAL, "bad precision");
     if (nrhs < 1) return fail(P2P_EINVAL, "nrhs must be >= 1");
     if (n_grids != tree->n_grids) return fail(P2P_EINVAL, "n_grids differs from the tree's");
     P2P_TRY(check_grids(grids, n_grids, tree->n));
-    const bool fp64 = prec == P2P_FP64, redundant = layout == P2P_REDUNDANT;
-    const bool mfma = !fp64 && nrhs % 32 == 0;
+    h->prec = prec;
+    h->nrhs = nrhs;
+    h->n_grids = n_grids;
+    h->fp64 = prec == P2P_FP64;
+    h->mfma = !h->fp64 && nrhs % 32 == 0;
     // one RHS in FP32: matrix cores with the target boxes as columns
-    const bool cols = !fp64 && nrhs == 1;
-    int waves_per_wg = 4, wg_per_cu = 2, rhs_tile = (nrhs % 64 == 0) ? 64 : 32, copies = 1;
+    h->cols = !h->fp64 && nrhs == 1;
+    h->rhs_tile = (nrhs % 64 == 0) ? 64 : 32;
     if (tile) {
-        if (!mfma) return fail(P2P_EINVAL, "tile applies to the matrix-core path (FP32_MIXED, nrhs % 32 == 0)");
-        waves_per_wg = tile[0];
-        wg_per_cu = tile[1];
-        rhs_tile = tile[2];
-        copies = tile[3];
-        if (copies != 1 && copies != 2 && copies != 4 && copies != 8)
+        if (!h->mfma) return fail(P2P_EINVAL, "tile applies to the matrix-core path (FP32_MIXED, nrhs % 32 == 0)");
+        h->waves_per_wg = tile[0];
+        h->wg_per_cu = tile[1];
+        h->rhs_tile = tile[2];
+        h->copies = tile[3];
+        if (h->copies != 1 && h->copies != 2 && h->copies != 4 && h->copies != 8)
             return fail(P2P_EINVAL, "tile[3] (copies of the G blocks) must be 1, 2, 4 or 8");
-        if (waves_per_wg != 1 && waves_per_wg != 2 && waves_per_wg != 4)
+        if (h->waves_per_wg != 1 && h->waves_per_wg != 2 && h->waves_per_wg != 4)
             return fail(P2P_EINVAL, "tile[0] (waves per workgroup) must be 1, 2 or 4");
-        if (wg_per_cu < 1 || wg_per_cu > 16) return fail(P2P_EINVAL, "tile[1] (workgroups per CU) must be in 1..16");
-        if ((rhs_tile != 32 && rhs_tile != 64) || nrhs % rhs_tile != 0)
+        if (h->wg_per_cu < 1 || h->wg_per_cu > 16) return fail(P2P_EINVAL, "tile[1] (workgroups per CU) must be in 1..16");
+        if ((h->rhs_tile != 32 && h->rhs_tile != 64) || nrhs % h->rhs_tile != 0)
             return fail(P2P_EINVAL, "tile[2] (RHS tile) must be 32 or 64 and divide nrhs");
     }
-    const size_t csize = fp64 ? sizeof(double2) : sizeof(float2);
-    const int64_t n = tree->n, L = tree->n_leaves;
-
     // distinct k h values share one set of unit-spacing G blocks (relative tolerance 1e-12)
-    std::vector<double> khs;
-    std::vector<int32_t> itab(n_grids);
-    std::vector<float> iscale(n_grids);
+    h->itab.resize(n_grids);
+    h->iscale.resize(n_grids);
     for (int32_t g = 0; g < n_grids; ++g) {
         const double kh = grids[g].k * grids[g].h;
         int32_t t = -1;
-        for (size_t j = 0; j < khs.size(); ++j)
-            if (std::fabs(khs[j] - kh) <= 1e-12 * std::fmax(std::fabs(kh), 1e-300) || khs[j] == kh) {
+        for (size_t j = 0; j < h->khs.size(); ++j)
+            if (std::fabs(h->khs[j] - kh) <= 1e-12 * std::fmax(std::fabs(kh), 1e-300) || h->khs[j] == kh) {
                 t = static_cast<int32_t>(j);
                 break;
             }
         if (t < 0) {
-            t = static_cast<int32_t>(khs.size());
-            khs.push_back(kh);
+            t = static_cast<int32_t>(h->khs.size());
+            h->khs.push_back(kh);
         }
-        itab[g] = t;
-        iscale[g] = static_cast<float>(1.0 / grids[g].h);
+        h->itab[g] = t;
+        h->iscale[g] = static_cast<float>(1.0 / grids[g].h);
     }
-    const int32_t n_tables = static_cast<int32_t>(khs.size());
-
-    const bool blk = mfma || cols;
-    const int32_t n_tiles = cols ? helmholtz_cols_tiles(grids, n_grids, nullptr) : 0;
-    if (cols) {
+    h->n_tables = static_cast<int32_t>(h->khs.size());
+    h->blk = h->mfma || h->cols;
+    h->n_tiles = h->cols ? helmholtz_cols_tiles(grids, n_grids, nullptr) : 0;
+    if (h->cols) {
         // every box of a grid instance is a leaf, instances in order
         int64_t boxes = 0;
         for (int32_t g = 0; g < n_grids; ++g)
             boxes += static_cast<int64_t>(grids[g].n_side / 4) * (grids[g].n_side / 4) * (grids[g].n_side / 4);
-        if (boxes != L) return fail(P2P_EINVAL, "tree leaves do not match the grids' boxes");
+        if (boxes != tree->n_leaves) return fail(P2P_EINVAL, "tree leaves do not match the grids' boxes");
     }
-    // the per-call host parameters (h and k per instance, k h per table, the table
-    // and 1/h of each instance, the column tiles) travel in one copy: each small
+    // the host parameters (h and k per instance, k h per table, the table and
+    // 1/h of each instance, the column tiles) travel in one copy: each small
     // copy costs a blit launch, a sizeable part of a call on a small grid
-    const size_t o_k = 8 * static_cast<size_t>(n_grids), o_kh = o_k + 8 * static_cast<size_t>(n_grids);
-    const size_t o_itab = o_kh + 8 * static_cast<size_t>(n_tables);
-    const size_t o_isc = o_itab + 4 * static_cast<size_t>(n_grids);
-    const size_t o_tiles = o_isc + 4 * static_cast<size_t>(n_grids);
-    const size_t param_bytes = o_tiles + 8 * static_cast<size_t>(n_tiles);
-    Arena ar(ws);
-    char *params = ar.take<char>(param_bytes);
-    double *d_h = reinterpret_cast<double *>(params);
-    double *d_k = reinterpret_cast<double *>(params + o_k);
-    double *d_kh = reinterpret_cast<double *>(params + o_kh);
-    int32_t *d_itab = reinterpret_cast<int32_t *>(params + o_itab);
-    float *d_iscale = reinterpret_cast<float *>(params + o_isc);
-    int32_t *d_tiles = reinterpret_cast<int32_t *>(params + o_tiles);
-    char *table = blk ? nullptr : ar.take<char>(static_cast<size_t>(n_grids) * kTableLen * csize);
-    float2 *blocks = blk ? ar.take<float2>(static_cast<size_t>(n_tables) * copies * 27 * 4096) : nullptr;
-    int32_t *work = mfma ? ar.take<int32_t>(L) : nullptr;
-    uint64_t *wkeys = mfma ? ar.take<uint64_t>(L) : nullptr;
-    uint64_t *wkeys_tmp = mfma ? ar.take<uint64_t>(L) : nullptr;
-    int32_t *wvals_tmp = mfma ? ar.take<int32_t>(L) : nullptr;
-    uint32_t *whist = mfma ? ar.take<uint32_t>(radix_hist_elems(L)) : nullptr;
-    int32_t *counter = mfma ? ar.take<int32_t>(64) : nullptr;
-    char *sorted = redundant ? nullptr : ar.take<char>(static_cast<size_t>(n) * nrhs * csize);
-    p2p_status st;
-    if (ws_query(ws, ws_bytes, ar, &st)) return st;
+    h->o_k = 8 * static_cast<size_t>(n_grids);
+    h->o_kh = h->o_k + 8 * static_cast<size_t>(n_grids);
+    h->o_itab = h->o_kh + 8 * static_cast<size_t>(h->n_tables);
+    h->o_isc = h->o_itab + 4 * static_cast<size_t>(n_grids);
+    h->o_tiles = h->o_isc + 4 * static_cast<size_t>(n_grids);
+    h->param_bytes = h->o_tiles + 8 * static_cast<size_t>(h->n_tiles);
+    // a single-RHS call on a grid of few instances takes its parameters in the
+    // kernel arguments; every other call uploads them
+    h->inline_params = h->cols && n_grids <= kInlineGrids && h->n_tables <= kInlineGrids;
+    if (h->inline_params) {
+        HelmInline &inl = h->inl;
+        inl.n_grids = n_grids;
+        inl.n_tables = h->n_tables;
+        int32_t tf = 0, lf = 0;
+        for (int32_t g = 0; g < n_grids; ++g) {
+            const int32_t nb = (grids[g].n_side / 4) * (grids[g].n_side / 4) * (grids[g].n_side / 4);
+            inl.tile_first[g] = tf;
+            inl.leaf_first[g] = lf;
+            inl.itab[g] = h->itab[g];
+            inl.iscale[g] = h->iscale[g];
+            tf += (nb + kHelmColBoxes - 1) / kHelmColBoxes;
+            lf += nb;
+        }
+        inl.tile_first[n_grids] = tf;
+        inl.leaf_first[n_grids] = lf;
+        for (int32_t t = 0; t < h->n_tables; ++t) inl.kh[t] = h->khs[t];
+    }
+    return P2P_OK;
+}
+
+HelmSetupBufs helm_take(Arena &ar, const HelmSetup &h, int64_t L) {
+    const size_t csize = h.fp64 ? sizeof(double2) : sizeof(float2);
+    HelmSetupBufs b;
+    b.params = ar.take<char>(h.param_bytes);
+    if (!h.blk) b.table = ar.take<char>(static_cast<size_t>(h.n_grids) * kTableLen * csize);
+    if (h.blk) b.blocks = ar.take<float2>(static_cast<size_t>(h.n_tables) * h.copies * 27 * 4096);
+    if (h.mfma) {
+        b.work = ar.take<int32_t>(L);
+        b.wkeys = ar.take<uint64_t>(L);
+        b.wkeys_tmp = ar.take<uint64_t>(L);
+        b.wvals_tmp = ar.take<int32_t>(L);
+        b.whist = ar.take<uint32_t>(radix_hist_elems(L));
+    }
+    return b;
+}
+
+// Fill the set-up buffer: parameters uploaded (unless they travel inline),
+// the G tables (vector path) or blocks (matrix cores), the work order.
+p2p_status helm_fill(const HelmSetup &h, const HelmSetupBufs &b, const p2p_tree *tree, const p2p_nbrs *nbrs,
+                     const p2p_grid *grids, hipStream_t s) {
+    double *d_h = reinterpret_cast<double *>(b.params);
+    double *d_k = reinterpret_cast<double *>(b.params + h.o_k);
+    double *d_kh = reinterpret_cast<double *>(b.params + h.o_kh);
+    if (!h.inline_params) {
+        P2P_TRY(no_capture(s, "a Helmholtz set-up that uploads its parameters"));
+        std::vector<char> hp(h.param_bytes);
+        for (int32_t g = 0; g < h.n_grids; ++g) {
+            std::memcpy(hp.data() + 8 * g, &grids[g].h, 8);
+            std::memcpy(hp.data() + h.o_k + 8 * g, &grids[g].k, 8);
+        }
+        std::memcpy(hp.data() + h.o_kh, h.khs.data(), 8 * static_cast<size_t>(h.n_tables));
+        std::memcpy(hp.data() + h.o_itab, h.itab.data(), 4 * static_cast<size_t>(h.n_grids));
+        std::memcpy(hp.data() + h.o_isc, h.iscale.data(), 4 * static_cast<size_t>(h.n_grids));
+        if (h.cols) helmholtz_cols_tiles(grids, h.n_grids, reinterpret_cast<int32_t *>(hp.data() + h.o_tiles));
+        // a copy from pageable memory has read its source when it returns
+        P2P_HIP(hipMemcpyAsync(b.params, hp.data(), h.param_bytes, hipMemcpyHostToDevice, s));
+    }
+    if (h.blk) P2P_TRY(launch_green_blocks(d_kh, h.inl, h.n_tables, h.copies, b.blocks, s));
+    else P2P_TRY(launch_green_tables(d_h, d_k, h.n_grids, h.fp64, b.table, s));
+    if (h.mfma)
+        P2P_TRY(launch_work_order(nbrs->nbr_start, tree->n_leaves, b.work, b.wkeys, b.wkeys_tmp, b.wvals_tmp,
+                                  b.whist, s));
+    return P2P_OK;
+}
+
+// Argument checks of an evaluation that come after the workspace query.
+p2p_status helm_check_call(const HelmSetup &h, const p2p_tree *tree, const p2p_nbrs *nbrs,
+                           const p2p_redundant *red, p2p_layout layout, const void *q, void *u, int32_t conj) {
+    const bool redundant = layout == P2P_REDUNDANT;
+    const int64_t n = tree->n;
+    const int32_t nrhs = h.nrhs;
     if (n > 0 && !u) return fail(P2P_EINVAL, "u must not be NULL");
     if (redundant) {
         if (!red) return fail(P2P_EINVAL, "REDUNDANT layout needs red");
         if (red->kind != P2P_KIND_HELMHOLTZ) return fail(P2P_EINVAL, "red was not built for Helmholtz");
-        if ((red->prec == P2P_FP64) != fp64) return fail(P2P_EINVAL, "red was built with another payload precision");
+        if ((red->prec == P2P_FP64) != h.fp64) return fail(P2P_EINVAL, "red was built with another payload precision");
         if (red->nrhs != nrhs) return fail(P2P_EINVAL, "red was built with another nrhs");
         if (!red->red_start || (red->count > 0 && !red->planes[0])) return fail(P2P_EINVAL, "red arrays must not be NULL");
         if (red->grain != 0 && red->grain != 1 && red->grain != 2 && red->grain != 4)
@@ -906,50 +990,31 @@ p2p_status helmholtz_common(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2
     } else if (n > 0 && !q) {
         return fail(P2P_EINVAL, "q must not be NULL");
     }
+    return P2P_OK;
+}
+
+// The evaluation from a filled set-up: the sorted copy of q (GATHER), then one
+// product launch (the matrix-core queue's counter is zeroed first).
+p2p_status helm_run(const HelmSetup &h, const HelmSetupBufs &b, int32_t *counter, char *sorted,
+                    const p2p_tree *tree, const p2p_nbrs *nbrs, const p2p_redundant *red, p2p_layout layout,
+                    const void *q, void *u, int32_t conj, hipStream_t s) {
+    P2P_TRY(helm_check_call(h, tree, nbrs, red, layout, q, u, conj));
+    const bool redundant = layout == P2P_REDUNDANT;
+    const int64_t n = tree->n, L = tree->n_leaves;
+    const int32_t nrhs = h.nrhs;
     const bool tiled = redundant && red->grain > 1;
-    // a single-RHS call on a grid of few instances takes its parameters in the
-    // kernel arguments; every other call uploads them
-    const bool inline_params = cols && n_grids <= kInlineGrids && n_tables <= kInlineGrids;
-    if (!inline_params) P2P_TRY(no_capture(s, "a Helmholtz evaluation that uploads its parameters"));
     if (!redundant) {
-        if (fp64)
+        if (h.fp64)
             P2P_TRY(launch_permute_rows<double2>(static_cast<const double2 *>(q), tree->perm, n, nrhs,
                                                  reinterpret_cast<double2 *>(sorted), s));
         else
             P2P_TRY(launch_permute_rows<float2>(static_cast<const float2 *>(q), tree->perm, n, nrhs,
                                                 reinterpret_cast<float2 *>(sorted), s));
     }
-    HelmInline inl{};
-    if (inline_params) {
-        inl.n_grids = n_grids;
-        inl.n_tables = n_tables;
-        int32_t tf = 0, lf = 0;
-        for (int32_t g = 0; g < n_grids; ++g) {
-            const int32_t nb = (grids[g].n_side / 4) * (grids[g].n_side / 4) * (grids[g].n_side / 4);
-            inl.tile_first[g] = tf;
-            inl.leaf_first[g] = lf;
-            inl.itab[g] = itab[g];
-            inl.iscale[g] = iscale[g];
-            tf += (nb + kHelmColBoxes - 1) / kHelmColBoxes;
-            lf += nb;
-        }
-        inl.tile_first[n_grids] = tf;
-        inl.leaf_first[n_grids] = lf;
-        for (int32_t t = 0; t < n_tables; ++t) inl.kh[t] = khs[t];
-    } else {
-        std::vector<char> hp(param_bytes);
-        for (int32_t g = 0; g < n_grids; ++g) {
-            std::memcpy(hp.data() + 8 * g, &grids[g].h, 8);
-            std::memcpy(hp.data() + o_k + 8 * g, &grids[g].k, 8);
-        }
-        std::memcpy(hp.data() + o_kh, khs.data(), 8 * static_cast<size_t>(n_tables));
-        std::memcpy(hp.data() + o_itab, itab.data(), 4 * static_cast<size_t>(n_grids));
-        std::memcpy(hp.data() + o_isc, iscale.data(), 4 * static_cast<size_t>(n_grids));
-        if (cols) helmholtz_cols_tiles(grids, n_grids, reinterpret_cast<int32_t *>(hp.data() + o_tiles));
-        P2P_HIP(hipMemcpyAsync(params, hp.data(), param_bytes, hipMemcpyHostToDevice, s));
-    }
-    if (blk) P2P_TRY(launch_green_blocks(d_kh, inl, n_tables, copies, blocks, s));
-    if (cols) {
+    const int32_t *d_itab = reinterpret_cast<const int32_t *>(b.params + h.o_itab);
+    const float *d_iscale = reinterpret_cast<const float *>(b.params + h.o_isc);
+    const int32_t *d_tiles = reinterpret_cast<const int32_t *>(b.params + h.o_tiles);
+    if (h.cols || h.mfma) {
         HelmholtzMfmaArgs a{};
         a.L = L;
         a.key_bits = tree->key_bits;
@@ -961,42 +1026,23 @@ p2p_status helmholtz_common(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2
         a.red_start = redundant ? red->red_start : nullptr;
         a.red_row = tiled ? red->red_row : nullptr;
         a.src = redundant ? static_cast<const float2 *>(red->planes[0]) : reinterpret_cast<const float2 *>(sorted);
-        a.blocks = blocks;
-        a.copies = 1;
+        a.blocks = b.blocks;
         a.inst_table = d_itab;
         a.inst_scale = d_iscale;
-        a.nrhs = 1;
         a.conj = conj;
-        a.comp = prec == P2P_FP32_MIXED;
+        a.comp = h.prec == P2P_FP32_MIXED;
         a.u = static_cast<float2 *>(u);
-        return launch_helmholtz_mfma_cols(a, d_tiles, inl, n_tiles, redundant, s);
-    }
-    if (mfma) {
-        P2P_TRY(launch_work_order(nbrs->nbr_start, L, work, wkeys, wkeys_tmp, wvals_tmp, whist, s));
-        HelmholtzMfmaArgs a{};
-        a.L = L;
-        a.key_bits = tree->key_bits;
-        a.leaf_start = tree->leaf_start;
-        a.leaf_key = tree->leaf_key;
-        a.perm = tree->perm;
-        a.nbr_start = nbrs->nbr_start;
-        a.nbr_idx = nbrs->nbr_idx;
-        a.red_start = redundant ? red->red_start : nullptr;
-        a.red_row = tiled ? red->red_row : nullptr;
-        a.src = redundant ? static_cast<const float2 *>(red->planes[0]) : reinterpret_cast<const float2 *>(sorted);
-        a.blocks = blocks;
-        a.copies = copies;
-        a.inst_table = d_itab;
-        a.inst_scale = d_iscale;
-        a.work = work;
+        if (h.cols) {
+            a.copies = 1;
+            a.nrhs = 1;
+            return launch_helmholtz_mfma_cols(a, d_tiles, h.inl, h.n_tiles, redundant, s);
+        }
+        a.copies = h.copies;
+        a.work = b.work;
         a.counter = counter;
         a.nrhs = nrhs;
-        a.conj = conj;
-        a.comp = prec == P2P_FP32_MIXED;
-        a.u = static_cast<float2 *>(u);
-        return launch_helmholtz_mfma(a, redundant, waves_per_wg, wg_per_cu, rhs_tile, s);
+        return launch_helmholtz_mfma(a, redundant, h.waves_per_wg, h.wg_per_cu, h.rhs_tile, s);
     }
-    P2P_TRY(launch_green_tables(d_h, d_k, n_grids, fp64, table, s));
     HelmholtzArgs a{};
     a.L = L;
     a.key_bits = tree->key_bits;
@@ -1008,12 +1054,76 @@ p2p_status helmholtz_common(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2
     a.red_start = redundant ? red->red_start : nullptr;
     a.red_row = tiled ? red->red_row : nullptr;
     a.src = redundant ? red->planes[0] : sorted;
-    a.table = table;
+    a.table = b.table;
     a.nrhs = nrhs;
     a.conj = conj;
-    a.comp = prec == P2P_FP32_MIXED;
+    a.comp = h.prec == P2P_FP32_MIXED;
     a.u = u;
-    return launch_helmholtz(a, redundant, fp64, s);
+    return launch_helmholtz(a, redundant, h.fp64, s);
+}
+
+// Per-call scratch of an evaluation beside the set-up: the queue counter
+// (matrix cores, several RHS) and the sorted copy of q (GATHER).
+void helm_take_call(Arena &ar, const HelmSetup &h, int64_t n, bool redundant, int32_t **counter, char **sorted) {
+    const size_t csize = h.fp64 ? sizeof(double2) : sizeof(float2);
+    *counter = h.mfma ? ar.take<int32_t>(64) : nullptr;
+    *sorted = redundant ? nullptr : ar.take<char>(static_cast<size_t>(n) * h.nrhs * csize);
+}
+
+p2p_status helmholtz_common(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2p_redundant *red,
+                            p2p_layout layout, p2p_precision prec, const p2p_grid *grids,
+                            int32_t n_grids, int32_t nrhs, const void *q, void *u, int32_t conj,
+                            const int32_t *tile, void *ws, size_t *ws_bytes, hipStream_t s) {
+    if (!ws_bytes) return fail(P2P_EINVAL, "ws_bytes must not be NULL");
+    HelmSetup h;
+    P2P_TRY(helm_setup(tree, nbrs, prec, grids, n_grids, nrhs, tile, &h));
+    if (layout != P2P_GATHER && layout != P2P_REDUNDANT) return fail(P2P_EINVAL, "bad layout");
+    Arena ar(ws);
+    const HelmSetupBufs b = helm_take(ar, h, tree->n_leaves);
+    int32_t *counter;
+    char *sorted;
+    helm_take_call(ar, h, tree->n, layout == P2P_REDUNDANT, &counter, &sorted);
+    p2p_status st;
+    if (ws_query(ws, ws_bytes, ar, &st)) return st;
+    // every argument is checked before the set-up is queued
+    P2P_TRY(helm_check_call(h, tree, nbrs, red, layout, q, u, conj));
+    P2P_TRY(helm_fill(h, b, tree, nbrs, grids, s));
+    return helm_run(h, b, counter, sorted, tree, nbrs, red, layout, q, u, conj, s);
+}
+
+// FNV-1a over the arguments a set-up depends on.
+struct Fnv {
+    uint64_t v = 1469598103934665603ull;
+    template <class T>
+    void add(const T &x) {
+        const unsigned char *p = reinterpret_cast<const unsigned char *>(&x);
+        for (size_t i = 0; i < sizeof(T); ++i) {
+            v ^= p[i];
+            v *= 1099511628211ull;
+        }
+    }
+};
+
+uint64_t helm_fingerprint(const HelmSetup &h, const p2p_tree *tree, const p2p_nbrs *nbrs, const p2p_grid *grids) {
+    Fnv f;
+    f.add(tree->n);
+    f.add(tree->n_leaves);
+    f.add(tree->key_bits);
+    f.add(nbrs->count);
+    f.add(static_cast<int32_t>(h.prec));
+    f.add(h.nrhs);
+    f.add(h.waves_per_wg);
+    f.add(h.wg_per_cu);
+    f.add(h.rhs_tile);
+    f.add(h.copies);
+    f.add(h.n_grids);
+    for (int32_t g = 0; g < h.n_grids; ++g) {
+        f.add(grids[g].n_side);
+        f.add(grids[g].h);
+        f.add(grids[g].k);
+        f.add(grids[g].point_off);
+    }
+    return f.v == 0 ? 1 : f.v;
 }
 
 }  // namespace
@@ -1026,6 +1136,62 @@ extern "C" p2p_status p2p_eval_helmholtz(const p2p_tree *tree, const p2p_nbrs *n
     set_error("");
     return helmholtz_common(tree, nbrs, red, layout, prec, grids, n_grids, nrhs, q, u, 0, tile, ws,
                             ws_bytes, as_stream(stream));
+}
+
+extern "C" p2p_status p2p_helmholtz_prepare(const p2p_tree *tree, const p2p_nbrs *nbrs, p2p_precision prec,
+                                            const p2p_grid *grids, int32_t n_grids, int32_t nrhs,
+                                            const int32_t *tile, p2p_helmholtz_plan *plan,
+                                            p2p_stream_t stream) {
+    set_error("");
+    if (!plan) return fail(P2P_EINVAL, "plan is NULL");
+    HelmSetup h;
+    P2P_TRY(helm_setup(tree, nbrs, prec, grids, n_grids, nrhs, tile, &h));
+    Arena ar(plan->buf);
+    const HelmSetupBufs b = helm_take(ar, h, tree->n_leaves);
+    if (!plan->buf) {
+        plan->bytes = ar.used;
+        return P2P_OK;
+    }
+    if (plan->bytes < ar.used)
+        return fail(P2P_EINVAL, "plan->bytes too small: need " + std::to_string(ar.used) + ", got " +
+                                    std::to_string(plan->bytes));
+    if ((reinterpret_cast<uintptr_t>(plan->buf) & 255u) != 0) return fail(P2P_EINVAL, "plan->buf must be 256-byte aligned");
+    P2P_TRY(helm_fill(h, b, tree, nbrs, grids, as_stream(stream)));
+    plan->prec = prec;
+    plan->nrhs = nrhs;
+    plan->tile[0] = h.waves_per_wg;
+    plan->tile[1] = h.wg_per_cu;
+    plan->tile[2] = h.rhs_tile;
+    plan->tile[3] = h.copies;
+    plan->tiled = tile ? 1 : 0;
+    plan->fingerprint = helm_fingerprint(h, tree, nbrs, grids);
+    return P2P_OK;
+}
+
+extern "C" p2p_status p2p_eval_helmholtz_prepared(const p2p_tree *tree, const p2p_nbrs *nbrs,
+                                                  const p2p_redundant *red, p2p_layout layout,
+                                                  const p2p_grid *grids, int32_t n_grids,
+                                                  const p2p_helmholtz_plan *plan, const void *q, void *u,
+                                                  void *ws, size_t *ws_bytes, p2p_stream_t stream) {
+    set_error("");
+    if (!ws_bytes) return fail(P2P_EINVAL, "ws_bytes must not be NULL");
+    if (!plan || !plan->buf || plan->fingerprint == 0) return fail(P2P_EINVAL, "plan was not prepared");
+    if (layout != P2P_GATHER && layout != P2P_REDUNDANT) return fail(P2P_EINVAL, "bad layout");
+    HelmSetup h;
+    P2P_TRY(helm_setup(tree, nbrs, static_cast<p2p_precision>(plan->prec), grids, n_grids, plan->nrhs,
+                       plan->tiled ? plan->tile : nullptr, &h));
+    if (helm_fingerprint(h, tree, nbrs, grids) != plan->fingerprint)
+        return fail(P2P_EINVAL, "plan was prepared for another tree, grid set, precision, nrhs or tile");
+    Arena pa(plan->buf);
+    const HelmSetupBufs b = helm_take(pa, h, tree->n_leaves);
+    if (plan->bytes < pa.used) return fail(P2P_EINVAL, "plan->bytes smaller than the set-up");
+    Arena ar(ws);
+    int32_t *counter;
+    char *sorted;
+    helm_take_call(ar, h, tree->n, layout == P2P_REDUNDANT, &counter, &sorted);
+    p2p_status st;
+    if (ws_query(ws, ws_bytes, ar, &st)) return st;
+    return helm_run(h, b, counter, sorted, tree, nbrs, red, layout, q, u, 0, as_stream(stream));
 }
 
 // ------------------------------------------------------------- adjoint ----

@@ -13,10 +13,16 @@
 // Results are written straight to caller order through perm (the update
 // step).  No atomics: each output has one owner.
 //
-// Self pair: instead of a per-pair index test, the kernel sums over all
-// sources of the near field, which holds the target itself exactly once with
-// d = 0, and afterwards adds back the self term of phi (m_i (eps^2)^{-1/2},
-// computed in the same arithmetic); the self term of a is exactly zero.
+// Self pair: the near field holds the target itself exactly once, at d = 0.
+// FP64 drops it by position: the workgroup knows where its own leaf's rows
+// sit among the staged sources, so each lane knows the one step of its run
+// that is its target's own row and gives that pair weight zero (a compare
+// and a select per pair, and the sums hold only the pairs of the
+// definition).  FP32_MIXED saves those two slots of its fifteen: it sums over
+// all sources and afterwards adds back the self term of phi (m_i
+// (eps^2)^{-1/2}, computed in the same arithmetic; the self term of a is
+// exactly zero), which leaves the rounding of the float partial that held
+// -m_i/eps in phi_i (bounded by the smallest eps the entry points accept).
 // With eps == 0 pairs at zero distance contribute nothing instead.
 //
 // Remote lists (sources of another particle set, REMOTE): most target leaves
@@ -54,17 +60,27 @@ constexpr int kGFlush = 32;
 // Block-wide: loads one chunk of the near list of A into LDS (first sorted
 // slot of each neighbour, exclusive prefix of their occupancies and, with
 // PER, the image codes).
+// *s_self: the first chunk row of the entry (A, unshifted), the target leaf's
+// own rows, or -1 when the chunk does not hold it.
 template <bool PER>
 __device__ int64_t g_load_nbr_chunk(const int32_t *__restrict__ leaf_start,
                                     const int32_t *__restrict__ nbr_idx,
-                                    const int8_t *__restrict__ nbr_shift, int64_t c0, int nc,
-                                    int64_t *s_pre, int32_t *s_first, int8_t *s_code, int64_t *s_w) {
+                                    const int8_t *__restrict__ nbr_shift, int64_t A, int64_t c0, int nc,
+                                    int64_t *s_pre, int32_t *s_first, int8_t *s_code, int64_t *s_w,
+                                    int64_t *s_self) {
     int32_t occ = 0, first = 0;
+    bool self = false;
+    if (threadIdx.x == 0) *s_self = -1;
     if (static_cast<int>(threadIdx.x) < nc) {
         const int32_t B = nbr_idx[c0 + threadIdx.x];
         first = leaf_start[B];
         occ = leaf_start[B + 1] - first;
-        if constexpr (PER) s_code[threadIdx.x] = nbr_shift[c0 + threadIdx.x];
+        int code = 13;
+        if constexpr (PER) {
+            code = nbr_shift[c0 + threadIdx.x];
+            s_code[threadIdx.x] = static_cast<int8_t>(code);
+        }
+        self = B == A && code == 13;
     }
     s_first[threadIdx.x] = first;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -83,6 +99,7 @@ __device__ int64_t g_load_nbr_chunk(const int32_t *__restrict__ leaf_start,
         tot += s_w[q];
     }
     s_pre[threadIdx.x] = woff + x - occ;
+    if (self) *s_self = woff + x - occ;
     if (threadIdx.x == 0) s_pre[nc] = tot;
     __syncthreads();
     return tot;
@@ -97,35 +114,44 @@ __device__ inline int g_find_nbr(const int64_t *s_pre, int nc, int64_t p) {
     return lo;
 }
 
+// Tile position given to `body` when the tile holds none of the target
+// leaf's own rows.
+constexpr int64_t kNoSelf = -(int64_t(1) << 40);
+
 // Walks the sources of leaf A tile by tile: after a barrier, `begin(n_tile)`,
 // then `stage(i, src_row, image_code)` for the tile's sources i (code 13
-// unless PER), a barrier, and `body(n_tile)`.  Must be called by the whole
-// block.
+// unless PER), a barrier, and `body(n_tile, self)`, where tile position
+// self + r holds row r of A's own rows (the unshifted entry A of its list;
+// kNoSelf where no tile position does; the redundant layout takes it from
+// red_self, or none if red_self is null).  Must be called by the whole block.
 template <bool RED, bool PER, class Begin, class Stage, class Body>
 __device__ void for_each_source_tile(int64_t A, const int64_t *__restrict__ red_start,
+                                     const int32_t *__restrict__ red_self,
                                      const int64_t *__restrict__ nbr_start,
                                      const int32_t *__restrict__ nbr_idx,
                                      const int8_t *__restrict__ nbr_shift,
                                      const int32_t *__restrict__ leaf_start, int64_t *s_pre,
-                                     int32_t *s_first, int8_t *s_code, int64_t *s_w, Begin begin,
-                                     Stage stage, Body body) {
+                                     int32_t *s_first, int8_t *s_code, int64_t *s_w, int64_t *s_self,
+                                     Begin begin, Stage stage, Body body) {
     if constexpr (RED) {
         const int64_t seg0 = red_start[A], ns = red_start[A + 1] - seg0;
+        const int64_t self = red_self ? static_cast<int64_t>(red_self[A]) : int64_t(-1);
         for (int64_t s0 = 0; s0 < ns; s0 += kGTile) {
             const int nt = static_cast<int>(min<int64_t>(kGTile, ns - s0));
             __syncthreads();
             begin(nt);
             for (int i = threadIdx.x; i < nt; i += kGBlock) stage(i, seg0 + s0 + i, 13);
             __syncthreads();
-            body(nt);
+            body(nt, self >= 0 ? self - s0 : kNoSelf);
         }
     } else {
         const int64_t e0 = nbr_start[A], e1 = nbr_start[A + 1];
         for (int64_t c0 = e0; c0 < e1; c0 += kGNbrChunk) {
             const int nc = static_cast<int>(min<int64_t>(kGNbrChunk, e1 - c0));
             __syncthreads();
-            const int64_t rows =
-                g_load_nbr_chunk<PER>(leaf_start, nbr_idx, nbr_shift, c0, nc, s_pre, s_first, s_code, s_w);
+            const int64_t rows = g_load_nbr_chunk<PER>(leaf_start, nbr_idx, nbr_shift, A, c0, nc, s_pre, s_first,
+                                                       s_code, s_w, s_self);
+            const int64_t self = *s_self;
             for (int64_t s0 = 0; s0 < rows; s0 += kGTile) {
                 const int nt = static_cast<int>(min<int64_t>(kGTile, rows - s0));
                 __syncthreads();
@@ -136,7 +162,7 @@ __device__ void for_each_source_tile(int64_t A, const int64_t *__restrict__ red_
                     stage(i, s_first[b] + (p - s_pre[b]), PER ? static_cast<int>(s_code[b]) : 13);
                 }
                 __syncthreads();
-                body(nt);
+                body(nt, self >= 0 ? self - s0 : kNoSelf);
             }
         }
     }
@@ -195,8 +221,11 @@ __device__ __forceinline__ void gravity_body(const GravityArgs &a) {
     __shared__ int32_t s_first[kGNbrChunk];
     __shared__ int8_t s_code[PER ? kGNbrChunk : 1];
     __shared__ int64_t s_w[kGBlock / 64];
+    __shared__ int64_t s_self;
     static_assert(sizeof(s_src) >= 4 * kGBlock * sizeof(double), "reduction does not fit");
     double(*s_red)[kGBlock] = reinterpret_cast<double(*)[kGBlock]>(s_src);
+    // FP64 with eps > 0 drops the target's own pair by position (see the top)
+    constexpr bool MASK = !MIXED && !EPS0 && !REMOTE;
 
     // gather: neighbouring leaves on one XCD share their sources in its L2
     const int64_t A = RED ? static_cast<int64_t>(blockIdx.x) : p2pd::xcd_contiguous(blockIdx.x, gridDim.x);
@@ -274,9 +303,16 @@ __device__ __forceinline__ void gravity_body(const GravityArgs &a) {
                     *d = source_row<REMOTE>(a, row);
             }
         };
-        auto body = [&](int) {
+        auto body = [&](int nt, int64_t self) {
             if (!active) return;
             const Src *sp = s_src + g * chunk;
+            // MASK: the step of this lane's run at its target's own row, else -1
+            int selfj = -1;
+            if constexpr (MASK) {
+                const int64_t pos = self + tc0 + t;
+                const int64_t j = pos - static_cast<int64_t>(g) * chunk;
+                if (pos >= 0 && pos < nt && j >= 0 && j < chunk) selfj = static_cast<int>(j);
+            }
             if constexpr (MIXED) {
                 auto pair = [&](const float4 v, float &pf, float &xf, float &yf, float &zf) {
                     const float dx = tv.x - v.x, dy = tv.y - v.y, dz = tv.z - v.z;
@@ -308,11 +344,12 @@ __device__ __forceinline__ void gravity_body(const GravityArgs &a) {
                     fz += zf;
                 }
             } else {
-                auto pair = [&](const Row4d v) {
+                auto pair = [&](const Row4d v, int j) {
                     const double dx = tv.x - v.x, dy = tv.y - v.y, dz = tv.z - v.z;
                     const double r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
                     double w = rsqrt(r2);
                     if constexpr (EPS0) w = (r2 > 0.0) ? w : 0.0;
+                    if constexpr (MASK) w = (j == selfj) ? 0.0 : w;
                     const double mw = v.w * w;
                     const double mw3 = mw * (w * w);
                     p -= mw;
@@ -323,16 +360,17 @@ __device__ __forceinline__ void gravity_body(const GravityArgs &a) {
                 int j = 0;
                 for (; j + 4 <= chunk; j += 4, sp += 4) {
                     const Row4d v0 = sp[0], v1 = sp[1], v2 = sp[2], v3 = sp[3];
-                    pair(v0);
-                    pair(v1);
-                    pair(v2);
-                    pair(v3);
+                    pair(v0, j);
+                    pair(v1, j + 1);
+                    pair(v2, j + 2);
+                    pair(v3, j + 3);
                 }
-                for (; j < chunk; ++j, ++sp) pair(sp[0]);
+                for (; j < chunk; ++j, ++sp) pair(sp[0], j);
             }
         };
-        for_each_source_tile<RED, PER>(A, a.red_start, a.nbr_start, a.nbr_idx, a.nbr_shift, a.src_leaf_start,
-                                       s_pre, s_first, s_code, s_w, begin, stage, body);
+        for_each_source_tile<RED, PER>(A, a.red_start, REMOTE ? nullptr : a.red_self, a.nbr_start, a.nbr_idx,
+                                       a.nbr_shift, a.src_leaf_start, s_pre, s_first, s_code, s_w, &s_self,
+                                       begin, stage, body);
 
         // Per-target sums of the G partials, in the order q = 0..G-1.  Lanes
         // with g >= G never accumulate and are never read.  When 4 tc <= 256,
@@ -345,7 +383,7 @@ __device__ __forceinline__ void gravity_body(const GravityArgs &a) {
         s_red[2][threadIdx.x] = fy;
         s_red[3][threadIdx.x] = fz;
         __syncthreads();
-        // the self pair (d = 0) of phi, computed in the same arithmetic
+        // FP32_MIXED: the self pair (d = 0) of phi, computed in the same arithmetic
         auto self_phi = [&]() -> double {
             if constexpr (MIXED)
                 return static_cast<double>(tv.w * rsq_f32(eps2f));
@@ -356,7 +394,7 @@ __device__ __forceinline__ void gravity_body(const GravityArgs &a) {
             if (g < 4) {
                 double s = 0.0;
                 for (int q = 0; q < G; ++q) s += s_red[g][q * tc + t];
-                if constexpr (!EPS0 && !REMOTE) {
+                if constexpr (MIXED && !EPS0 && !REMOTE) {
                     if (g == 0) s += self_phi();
                 }
                 double *out = g == 0 ? a.phi : g == 1 ? a.ax : g == 2 ? a.ay : a.az;
@@ -375,7 +413,7 @@ __device__ __forceinline__ void gravity_body(const GravityArgs &a) {
                 sy_ += s_red[2][l];
                 sz_ += s_red[3][l];
             }
-            if constexpr (!EPS0 && !REMOTE) sp_ += self_phi();
+            if constexpr (MIXED && !EPS0 && !REMOTE) sp_ += self_phi();
             const int64_t i = a.perm[t0 + tc0 + threadIdx.x];
             if constexpr (REMOTE) {
                 a.phi[i] += sp_;
@@ -424,7 +462,8 @@ __global__ __launch_bounds__(kGBlock) __attribute__((amdgpu_waves_per_eu(6))) vo
 //   g_m_j += -(gp_k w - w^3 ga_k.d)
 // (the derivative of L = sum_i gp_i phi_i + ga_i . a_i through both the pair
 // (j, k) and the pair (k, j)).  The self pair adds zero to g_x and
-// -gp_j/eps to g_m, which is added back.  FP32_MIXED as in the forward
+// -gp_j/eps to g_m: FP64 drops it by position, FP32_MIXED adds it back, as in
+// the forward kernels.  FP32_MIXED as in the forward
 // kernels: positions relative to the target leaf's centre, taken in double
 // and rounded to float once per staged source, float pair terms summed at
 // most 32 at a time before they are added to double accumulators.
@@ -437,6 +476,7 @@ __global__ __launch_bounds__(kGBlock) void k_gravity_adjoint(GravityAdjointArgs 
     __shared__ int32_t s_first[kGNbrChunk];
     __shared__ int8_t s_code[kGNbrChunk];
     __shared__ int64_t s_w[kGBlock / 64];
+    __shared__ int64_t s_self;
     static_assert(sizeof(s_g) >= 4 * kGBlock * sizeof(double), "reduction does not fit");
     double *s_red = reinterpret_cast<double *>(s_g);   // reused after the last tile
 
@@ -482,7 +522,7 @@ __global__ __launch_bounds__(kGBlock) void k_gravity_adjoint(GravityAdjointArgs 
                 s_g[i] = a.g4[row];
             }
         };
-        auto body = [&](int nt) {
+        auto body = [&](int nt, int64_t self) {
             if (!active) return;
             if constexpr (MIXED) {
                 int s = g;
@@ -507,10 +547,14 @@ __global__ __launch_bounds__(kGBlock) void k_gravity_adjoint(GravityAdjointArgs 
                     oz += fz;
                 }
             } else {
+                // the tile position of the target's own row, whose pair is dropped
+                const int64_t pos = self + tc0 + t;
+                const int selfs = (pos >= 0 && pos < nt) ? static_cast<int>(pos) : -1;
                 for (int s = g; s < nt; s += G) {
                     const Row4d pk = s_p[s], gk = s_g[s];
                     const double dx = pj.x - pk.x, dy = pj.y - pk.y, dz = pj.z - pk.z;
-                    const double w = rsqrt(fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2))));
+                    double w = rsqrt(fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2))));
+                    w = (s == selfs) ? 0.0 : w;
                     const double w3 = w * w * w, w5 = w3 * w * w;
                     const double gdj = gj.y * dx + gj.z * dy + gj.w * dz;
                     const double gdk = gk.y * dx + gk.z * dy + gk.w * dz;
@@ -522,8 +566,8 @@ __global__ __launch_bounds__(kGBlock) void k_gravity_adjoint(GravityAdjointArgs 
                 }
             }
         };
-        for_each_source_tile<false, PER>(A, nullptr, a.nbr_start, a.nbr_idx, a.nbr_shift, a.leaf_start,
-                                         s_pre, s_first, s_code, s_w, [](int) {}, stage, body);
+        for_each_source_tile<false, PER>(A, nullptr, nullptr, a.nbr_start, a.nbr_idx, a.nbr_shift, a.leaf_start,
+                                         s_pre, s_first, s_code, s_w, &s_self, [](int) {}, stage, body);
         __syncthreads();
         s_red[0 * kGBlock + threadIdx.x] = active ? om : 0.0;
         s_red[1 * kGBlock + threadIdx.x] = active ? ox : 0.0;
@@ -534,11 +578,8 @@ __global__ __launch_bounds__(kGBlock) void k_gravity_adjoint(GravityAdjointArgs 
             double r[4] = {0.0, 0.0, 0.0, 0.0};
             for (int q = 0; q < G; ++q)
                 for (int cI = 0; cI < 4; ++cI) r[cI] += s_red[cI * kGBlock + q * tc + threadIdx.x];
-            // the self pair added -g_phi_j / eps to g_m, in the same arithmetic
-            if constexpr (MIXED)
-                r[0] += static_cast<double>(gj.x * rsq_f32(eps2f));
-            else
-                r[0] += gj.x * rsqrt(eps2);
+            // FP32_MIXED: the self pair added -g_phi_j / eps to g_m, in the same arithmetic
+            if constexpr (MIXED) r[0] += static_cast<double>(gj.x * rsq_f32(eps2f));
             const int64_t i = a.perm[t0 + tc0 + threadIdx.x];
             a.gm[i] = r[0];
             a.gx[i] = r[1];

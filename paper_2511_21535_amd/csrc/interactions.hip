@@ -197,7 +197,8 @@ constexpr int kRecFlush = 32;
 // lane / tc) takes target t and staged sources g, g + G, ... (G = 64 / tc),
 // FP32-mixed pair terms summed at most 32 at a time in float into double;
 // the G partials meet in LDS.  Record (A, A) holds every target once as its
-// own source at d = 0; that self term is added back as in the box kernels.
+// own source at d = 0, source row tc0 + t of target t: FP64 drops that pair
+// by position, FP32-mixed adds its term back, as in the box kernels.
 // With image codes only the unshifted record (A, A) is the self record: a
 // point meets its own image elsewhere at a nonzero distance.
 template <bool MIXED, bool EPS0>
@@ -289,12 +290,15 @@ __global__ __launch_bounds__(64 * kEvalWaves) void k_eval_records(
                             fz += zf;
                         }
                     } else {
+                        // the chunk step of the target's own row in the self record, else -1
+                        const int selfj = (!EPS0 && self) ? tc0 + t - b0 : -1;
                         for (int j = g; j < nb; j += G) {
                             const Row4d v = s_src[w][j];
                             const double dx = tv.x - v.x, dy = tv.y - v.y, dz = tv.z - v.z;
                             const double r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
                             double wv = rsqrt(r2);
                             if constexpr (EPS0) wv = (r2 > 0.0) ? wv : 0.0;
+                            wv = (j == selfj) ? 0.0 : wv;
                             const double mw = v.w * wv;
                             const double mw3 = mw * (wv * wv);
                             p -= mw;
@@ -320,12 +324,7 @@ __global__ __launch_bounds__(64 * kEvalWaves) void k_eval_records(
                     sy += s_red[w][2][q * tc + lane];
                     sz += s_red[w][3][q * tc + lane];
                 }
-                if (!EPS0 && self) {
-                    if constexpr (MIXED)
-                        sp += static_cast<double>(static_cast<float>(tm) * rsq_f32(eps2f));
-                    else
-                        sp += tm * rsqrt(eps2);
-                }
+                if (MIXED && !EPS0 && self) sp += static_cast<double>(static_cast<float>(tm) * rsq_f32(eps2f));
                 res[out0 + tc0 + lane] = Row4d{sp, sx, sy, sz};
             }
             wave_sync();

@@ -32,6 +32,9 @@ def test_exports_every_declared_symbol(lib):
     for name in decl:
         assert hasattr(lib, name), name
     assert set(decl) == set(L.EXPORTED)
+    # the binding offers every entry point under its C name
+    for name in L.EXPORTED:
+        assert callable(getattr(L, name, None)), name
     assert "gfx950" in L.p2p_version()
 
 
@@ -106,13 +109,17 @@ def test_eval_rejects_bad_modes(lib):
 
 @pytest.mark.parametrize("prec,eps,ok", [
     (L.P2P_FP32_MIXED, 0.0, True), (L.P2P_FP32_MIXED, 1e-4, True), (L.P2P_FP32_MIXED, 9.9e-5, False),
+    (L.P2P_FP32_MIXED, 1e-3, True),
     (L.P2P_FP32_MIXED, 1e-30, False), (L.P2P_FP64, 1e-8, True), (L.P2P_FP64, 1e-3, True),
-    (L.P2P_FP64, 9.9e-9, False), (L.P2P_FP64, 5e-324, False)])
+    (L.P2P_FP64, 1e-30, True), (L.P2P_FP64, 2.0 ** -511, True), (L.P2P_FP64, 1e-160, False),
+    (L.P2P_FP64, 5e-324, False)])
 def test_eval_rejects_tiny_softening(lib, prec, eps, ok):
-    """A positive eps whose own d = 0 term m/eps, summed and subtracted again,
-    would leave more rounding in phi than the stated tolerance (below 1e-4 in
-    FP32_MIXED, 1e-8 in FP64) is refused on the host, by every gravity entry
-    point that takes eps; eps = 0 stays available."""
+    """FP32_MIXED sums the target's own d = 0 term m/eps into a float partial
+    and subtracts it again, so a positive eps below 1e-4 would leave more
+    rounding in phi than 1e-5 and is refused on the host; FP64 drops that pair
+    by position and takes any eps whose square is a normal double (>= 2^-511).
+    The same by every gravity entry point that takes eps; eps = 0 stays
+    available."""
     t = _tree(10, L_=1)
     t.perm = t.iperm = t.leaf_start = t.leaf_key = t.leaf_level = 0x1000
     n = L.p2p_nbrs()
@@ -126,9 +133,11 @@ def test_eval_rejects_tiny_softening(lib, prec, eps, ok):
     if not ok:
         assert "eps must be 0 or >=" in L.last_error()
     if eps > 0:
+        # the FP32_MIXED adjoint needs eps >= 1e-3 (its w^5 terms of close pairs)
+        adj_ok = ok and not (prec == L.P2P_FP32_MIXED and eps < 1e-3)
         st = lib.p2p_adjoint(L.P2P_KIND_GRAVITY, ctypes.byref(t), ctypes.byref(n), None, L.P2P_GATHER,
                              prec, eps, None, 0, 1, 0, None, None, None, None, ctypes.byref(nb), None)
-        assert st == want, L.last_error()
+        assert st == (L.P2P_OK if adj_ok else L.P2P_EINVAL), L.last_error()
 
 
 def test_adjoint_unsupported_combinations(lib):
@@ -329,3 +338,35 @@ def test_peaks_library_exports_and_rejects_bad_arguments():
         assert fn(None, 8, 1, None) == -1
         assert fn(fake, 0, 1, None) == -1
         assert fn(fake, 8, 0, None) == -1
+
+
+def test_helmholtz_plan_host_checks(lib):
+    """p2p_helmholtz_prepare with plan->buf == NULL only sizes the plan (the
+    G blocks of every distinct k h, the work order with several RHS); an
+    unprepared plan, or one whose fingerprint is of other arguments, is refused
+    on the host by p2p_eval_helmholtz_prepared."""
+    n = 16 ** 3
+    t = _tree(n, L.P2P_TREE_GRIDS, L_=64)
+    t.perm = t.iperm = t.leaf_start = t.leaf_key = t.leaf_level = 0x1000
+    t.n_grids, t.key_bits = 1, 4
+    g = (L.p2p_grid * 1)()
+    g[0].n_side, g[0].h, g[0].k, g[0].point_off = 16, 1 / 16, 1.0, 0
+    nl = L.p2p_nbrs()
+    nl.count, nl.nbr_start, nl.nbr_idx = 64, 0x1000, 0x1000
+    z = ctypes.c_void_p(0x1000)
+    p = L.p2p_helmholtz_plan()
+    assert lib.p2p_helmholtz_prepare(ctypes.byref(t), ctypes.byref(nl), L.P2P_FP32_MIXED, g, 1, 1, None,
+                                     ctypes.byref(p), None) == L.P2P_OK
+    one = p.bytes
+    assert one >= 27 * 64 * 64 * 8 and p.fingerprint == 0     # one set of G blocks; nothing prepared
+    assert lib.p2p_helmholtz_prepare(ctypes.byref(t), ctypes.byref(nl), L.P2P_FP32_MIXED, g, 1, 64, None,
+                                     ctypes.byref(p), None) == L.P2P_OK
+    assert p.bytes > one                                       # plus the work order of the queue
+    nb = ctypes.c_size_t(0)
+    st = lib.p2p_eval_helmholtz_prepared(ctypes.byref(t), ctypes.byref(nl), None, L.P2P_GATHER, g, 1,
+                                         ctypes.byref(p), z, z, None, ctypes.byref(nb), None)
+    assert st == L.P2P_EINVAL and "not prepared" in L.last_error()
+    p.buf, p.fingerprint, p.prec, p.nrhs = 0x1000, 12345, L.P2P_FP32_MIXED, 1
+    st = lib.p2p_eval_helmholtz_prepared(ctypes.byref(t), ctypes.byref(nl), None, L.P2P_GATHER, g, 1,
+                                         ctypes.byref(p), z, z, None, ctypes.byref(nb), None)
+    assert st == L.P2P_EINVAL and "prepared for another" in L.last_error()

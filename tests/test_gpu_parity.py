@@ -98,19 +98,20 @@ def test_tree_neighbors_restructure_bit_exact(gen, n, seed, depth, cap):
 
 
 @pytest.mark.parametrize("gen,n,seed,depth,cap", PARTICLE_CASES[:4] + PARTICLE_CASES[6:])
-@pytest.mark.parametrize("eps", [1e-3, 0.0])
-def test_interaction_layout_parity(gen, n, seed, depth, cap, eps):
+@pytest.mark.parametrize("eps_arg", [1e-3, 0.0, "min"])
+def test_interaction_layout_parity(gen, n, seed, depth, cap, eps_arg):
     """Per-interaction layout: records bit-exact against the oracle, sums
     within the tolerances, with lists that carry S and lists that do not."""
     x, y, z, m = _particles_case(gen, n, seed, depth, cap)
-    print(f"case interactions {gen} n={n} eps={eps}", flush=True)
+    print(f"case interactions {gen} n={n} eps={eps_arg}", flush=True)
     gx, gy, gz, gm = (_t(v) for v in (x, y, z, m))
     gt = api.Tree.build_particles(gx, gy, gz, depth=depth, leaf_cap=cap)
     gn = gt.neighbors()
     ot = oracle.build_tree_particles(x, y, z, depth=depth, leaf_cap=cap)
     os_, oi = oracle.neighbors(ot)
-    ref = oracle.gravity(x, y, z, m, eps, ot)
     for prec, tol in (("fp64", TOL64), ("fp32", TOL32)):
+        eps = EPS_MIN[prec] if eps_arg == "min" else eps_arg
+        ref = oracle.gravity(x, y, z, m, eps, ot)
         rec, rows = oracle.restructure_interactions(ot, os_, oi, x, y, z, m, prec=prec)
         for lists in (gn, dataclasses.replace(gn, red_entries=-1)):
             inter = api.restructure_interactions(gt, lists, gx, gy, gz, gm, prec=prec)
@@ -178,8 +179,11 @@ def test_heavy_leaf_lists(periodic):
         assert _rel(o[0], ref[0]) <= TOL32 and _rel(np.stack(o[1:]), np.stack(ref[1:])) <= TOL32
 
 
-# the smallest positive softening each precision accepts
-EPS_MIN = {"fp64": 1e-8, "fp32": 1e-4}
+# a tiny softening: FP64 takes any eps with a normal square (1e-30, far below every
+# pair distance here), FP32_MIXED down to 1e-4
+EPS_MIN = {"fp64": 1e-30, "fp32": 1e-4}
+# the FP32_MIXED adjoint's smallest accepted eps
+ADJ_EPS_MIN = {"fp64": 1e-30, "fp32": 1e-3}
 
 
 @pytest.mark.parametrize("gen,n,seed,depth,cap", PARTICLE_CASES[:4] + PARTICLE_CASES[6:])
@@ -358,16 +362,19 @@ def test_helmholtz_full_64_sampled():
 
 # --------------------------------------------------------------- adjoint
 @pytest.mark.parametrize("prec,tol", [("fp64", TOL64), ("fp32", TOL32)])
-def test_gravity_adjoint_parity(prec, tol):
+@pytest.mark.parametrize("eps", [1e-3, "min"])
+def test_gravity_adjoint_parity(prec, tol, eps):
+    eps = ADJ_EPS_MIN[prec] if eps == "min" else eps
+    print(f"case gravity adjoint {prec} eps={eps}", flush=True)
     x, y, z, m = W.plummer_mixture(3000, 31)
     gp, gax, gay, gaz = (W.normal_like(3000, seed=s) for s in (32, 33, 34, 35))
     gx, gy, gz, gm = (_t(v) for v in (x, y, z, m))
     gt = api.Tree.build_particles(gx, gy, gz, depth=20, leaf_cap=64)
     gn = gt.neighbors()
-    out = [_n(v) for v in api.gravity_adjoint(gt, gn, 1e-3, gx, gy, gz, gm, *(_t(v) for v in (gp, gax, gay, gaz)),
+    out = [_n(v) for v in api.gravity_adjoint(gt, gn, eps, gx, gy, gz, gm, *(_t(v) for v in (gp, gax, gay, gaz)),
                                               prec=prec)]
     ot = oracle.build_tree_particles(x, y, z, depth=20, leaf_cap=64)
-    rm, rx, ry, rz = oracle.gravity_adjoint(x, y, z, m, 1e-3, gp, gax, gay, gaz, ot)
+    rm, rx, ry, rz = oracle.gravity_adjoint(x, y, z, m, eps, gp, gax, gay, gaz, ot)
     e_m, e_x = _rel(out[3], rm), _rel(np.stack(out[:3]), np.stack([rx, ry, rz]))
     print(f"  adjoint {prec}: g_m {e_m:.2e} g_x {e_x:.2e}", flush=True)
     assert e_m <= tol and e_x <= tol

@@ -44,7 +44,8 @@ def _check_layout(gt, gn, red, sides, grain, q):
     np.testing.assert_array_equal(got[:gt.n_leaves], want)
     assert got[gt.n_leaves] == S
     np.testing.assert_array_equal(_n(red.red_row)[:gn.count], rr)
-    np.testing.assert_array_equal(_n(red.planes[0])[:S], oracle.restructure_tile_rows(ot, hs, hi, ss, q))
+    np.testing.assert_array_equal(_n(red.planes[0])[:S].reshape(S, -1),
+                                  oracle.restructure_tile_rows(ot, hs, hi, ss, q).reshape(S, -1))
 
 
 CASES = [([12, 8, 20, 4], 2), ([12, 8, 20, 4], 4), ([16], 2), ([16], 4), ([28, 4, 24], 2)]
