@@ -301,6 +301,23 @@ p2p_status p2p_eval_gravity(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2
                             double *phi, double *ax, double *ay, double *az,
                             void *ws, size_t *ws_bytes, p2p_stream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * evaluation as p2p_eval_gravity, same arguments and results, without a
+ * workspace.  The GATHER layout's box-sorted rows go to a static scratch array
+ * inside the library, 2^21 rows of 32 bytes (64 MiB), one copy per GPU, held
+ * until the process ends; REDUNDANT needs no scratch.  tree->n above 2^21 with
+ * GATHER returns P2P_EUNSUPPORTED before anything is queued.  Calls on one GPU
+ * share that GPU's scratch: two calls that overlap in time on one GPU (on
+ * different streams, or from different threads) race and give undefined
+ * results; calls ordered on one stream are safe.  Every scratch row that is
+ * read is first written by the same call.  Allocates nothing. */
+p2p_status p2p_eval_gravity_noalloc(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2p_redundant *red,
+                                    p2p_layout layout, p2p_precision prec, double eps,
+                                    const double *x, const double *y, const double *z, const double *m,
+                                    double *phi, double *ax, double *ay, double *az,
+                                    p2p_stream_t stream);
+
 /* Near-field Helmholtz on grid trees (the dense regular case of Sec. 5.1, the
  * near-field part of the MLFMA call of Sec. 4-5.1, with precomputed
  * interaction patterns; single RHS, multi-RHS, and many instances in one

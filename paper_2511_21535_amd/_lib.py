@@ -25,7 +25,7 @@ EXPORTED = ["p2p_build_tree", "p2p_build_neighbors", "p2p_restructure_redundant"
             "p2p_eval_gravity", "p2p_eval_helmholtz", "p2p_adjoint", "p2p_locality",
             "p2p_restructure_interactions", "p2p_eval_gravity_interactions",
             "p2p_build_neighbors_remote", "p2p_restructure_remote", "p2p_eval_gravity_remote",
-            "p2p_helmholtz_prepare", "p2p_eval_helmholtz_prepared",
+            "p2p_eval_gravity_noalloc", "p2p_helmholtz_prepare", "p2p_eval_helmholtz_prepared",
             "p2p_last_error", "p2p_version"]
 
 
@@ -131,6 +131,8 @@ def load():
     lib.p2p_restructure_remote.argtypes = [T, T, N, ctypes.POINTER(PV4), I32, R, V, SZ, V]
     lib.p2p_eval_gravity_remote.restype = st
     lib.p2p_eval_gravity_remote.argtypes = [T, T, N, R, I32, I32, F64] + [V] * 11 + [V, SZ, V]
+    lib.p2p_eval_gravity_noalloc.restype = st
+    lib.p2p_eval_gravity_noalloc.argtypes = [T, N, R, I32, I32, F64] + [V] * 8 + [V]
     HP, GP = ctypes.POINTER(p2p_helmholtz_plan), ctypes.POINTER(p2p_grid)
     lib.p2p_helmholtz_prepare.restype = st
     lib.p2p_helmholtz_prepare.argtypes = [T, N, I32, GP, I32, I32, ctypes.POINTER(ctypes.c_int32), HP, V]
@@ -207,6 +209,10 @@ def p2p_restructure_remote(*args):
 
 def p2p_eval_gravity_remote(*args):
     return load().p2p_eval_gravity_remote(*args)
+
+
+def p2p_eval_gravity_noalloc(*args):
+    return load().p2p_eval_gravity_noalloc(*args)
 
 
 def p2p_helmholtz_prepare(*args):

@@ -490,6 +490,26 @@ def gravity(tree: Tree, nbrs: Nbrs, eps: float, x=None, y=None, z=None, m=None,
     return tuple(out)
 
 
+def gravity_noalloc(tree: Tree, nbrs: Nbrs, eps: float, x=None, y=None, z=None, m=None,
+                    layout="gather", prec="fp64", red: Optional[Redundant] = None, out=None):
+    """As gravity(), through p2p_eval_gravity_noalloc: no workspace is
+    allocated (the GATHER rows go to the library's static scratch, at most
+    2^21 particles).  Calls that overlap on one GPU race on that scratch."""
+    dev = tree.leaf_start.device
+    n = tree.n
+    for nm, t in (("x", x), ("y", y), ("z", z), ("m", m)):
+        _vec(t, nm, n, optional=layout == "redundant")
+    out = _outs(out, n, dev)
+    ts, ns = tree.struct(), nbrs.struct()
+    rs = red.struct() if red is not None else None
+    st = L.p2p_eval_gravity_noalloc(ctypes.byref(ts), ctypes.byref(ns),
+                                           ctypes.byref(rs) if rs is not None else None,
+                                           LAYOUT[layout], PREC[prec], float(eps), _ptr(x), _ptr(y), _ptr(z),
+                                           _ptr(m), *[_ptr(o) for o in out], _stream())
+    L.check(st)
+    return tuple(out)
+
+
 def helmholtz(tree: Tree, nbrs: Nbrs, q: Optional[torch.Tensor] = None, layout="gather",
               prec="fp32", red: Optional[Redundant] = None, nrhs: Optional[int] = None,
               tile: Optional[Sequence[int]] = None, out: Optional[torch.Tensor] = None,
