@@ -34,9 +34,15 @@ FLAGS = [
 ]
 
 
+# flags of single sources: the single-RHS matrix-core kernel keeps its
+# accumulators in ordinary vector registers, so its per-offset FP64 flush needs
+# no copies out of the accumulation registers
+FILE_FLAGS = {"helmholtz_cols.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src).replace(".hip", ".o"))
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *FLAGS, *FILE_FLAGS.get(os.path.basename(src), []), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr}")

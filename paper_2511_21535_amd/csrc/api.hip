@@ -929,7 +929,8 @@ HelmSetupBufs helm_take(Arena &ar, const HelmSetup &h, int64_t L) {
     HelmSetupBufs b;
     b.params = ar.take<char>(h.param_bytes);
     if (!h.blk) b.table = ar.take<char>(static_cast<size_t>(h.n_grids) * kTableLen * csize);
-    if (h.blk) b.blocks = ar.take<float2>(static_cast<size_t>(h.n_tables) * h.copies * 27 * 4096);
+    // the G blocks and 64 zero entries after them
+    if (h.blk) b.blocks = ar.take<float2>(static_cast<size_t>(h.n_tables) * h.copies * 27 * 4096 + 64);
     if (h.mfma) {
         b.work = ar.take<int32_t>(L);
         b.wkeys = ar.take<uint64_t>(L);
@@ -961,7 +962,7 @@ p2p_status helm_fill(const HelmSetup &h, const HelmSetupBufs &b, const p2p_tree 
         // a copy from pageable memory has read its source when it returns
         P2P_HIP(hipMemcpyAsync(b.params, hp.data(), h.param_bytes, hipMemcpyHostToDevice, s));
     }
-    if (h.blk) P2P_TRY(launch_green_blocks(d_kh, h.inl, h.n_tables, h.copies, b.blocks, s));
+    if (h.blk) P2P_TRY(launch_green_blocks(d_kh, h.inl, h.n_tables, h.copies, h.cols, b.blocks, s));
     else P2P_TRY(launch_green_tables(d_h, d_k, h.n_grids, h.fp64, b.table, s));
     if (h.mfma)
         P2P_TRY(launch_work_order(nbrs->nbr_start, tree->n_leaves, b.work, b.wkeys, b.wkeys_tmp, b.wvals_tmp,
@@ -1027,6 +1028,7 @@ p2p_status helm_run(const HelmSetup &h, const HelmSetupBufs &b, int32_t *counter
         a.red_row = tiled ? red->red_row : nullptr;
         a.src = redundant ? static_cast<const float2 *>(red->planes[0]) : reinterpret_cast<const float2 *>(sorted);
         a.blocks = b.blocks;
+        a.zeros = b.blocks + static_cast<int64_t>(h.n_tables) * h.copies * 27 * 4096;
         a.inst_table = d_itab;
         a.inst_scale = d_iscale;
         a.conj = conj;

@@ -1,0 +1,311 @@
+// Single right-hand side of the near-field Helmholtz sum on FP32 matrix cores
+// (the dense regular case of Sec. 5.1 with one right-hand side), the target
+// boxes taken as the columns of the product.  Kept in a file of its own: it is
+// compiled with the matrix accumulators in ordinary vector registers
+// (-amdgpu-mfma-vgpr-form), so its per-offset FP64 flush reads them without a
+// copy out of the accumulation registers.
+#include <algorithm>
+
+#include "p2p_internal.h"
+
+namespace p2p {
+namespace {
+
+// Single right-hand side on matrix cores: the target boxes become the columns
+// of the product.  For a tile of up to 16 boxes b_0..b_15 of one instance,
+//     U (64 x 16) = sum_o G_o (64 x 64) Q_o (64 x 16),
+// column j of Q_o holding the 64 sources of the box at offset o from b_j (a
+// zero column where b_j has no such neighbour, at the faces of the grid), so
+// every column of an instruction shares the one G_o.  v_mfma_f32_16x16x4f32,
+// complex as four real products as above; lane l supplies A[l%16][l/16] and
+// B[l/16][l%16], and accumulator register r of lane l holds row 4 (l/16) + r,
+// column l%16.  A workgroup of 4 wavefronts owns a tile; wave w takes the
+// offsets o = w, w + 4, ... for all 64 targets (four row tiles, 16
+// instructions per k-step of 4 sources) with a deep operand prefetch, and the
+// four partial products
+// are summed through LDS at the end.  The workgroup first maps every (offset,
+// column) to the first row of its sources -- the sorted rows of the neighbour
+// box (gather) or its place in the target's segment (redundant) -- from the
+// tile's near lists, which are one contiguous run of the CSR.
+constexpr int kColBoxes = kHelmColBoxes;
+constexpr int kColWaves = 4;
+constexpr int kColOffsets = (27 + kColWaves - 1) / kColWaves;
+// operand buffers of the prefetch pipeline; the rotation runs on across offsets
+// of 16 k-steps each, so the count divides 16
+// prefetch distances of the G and Q operands, in k-steps
+constexpr int kColPrefG = 3;
+constexpr int kColPrefQ = 7;
+
+// The column tile of workgroup b: its first box A0, box count cnt, G table tab
+// and 1/h of its instance.
+__device__ inline void col_tile(int key_bits, const int32_t *__restrict__ tiles, const HelmInline &inl,
+                                const uint64_t *__restrict__ leaf_key, const int32_t *__restrict__ inst_table,
+                                const float *__restrict__ inst_scale, int32_t b, int32_t &A0, int32_t &cnt,
+                                int32_t &tab, float &sc) {
+    if (inl.n_grids > 0) {
+        int32_t tf = 0, lf = 0, lf1 = 0;
+        tab = 0;
+        sc = 1.f;
+#pragma unroll
+        for (int i = 0; i < kInlineGrids; ++i)
+            if (i < inl.n_grids && b >= inl.tile_first[i]) {
+                tf = inl.tile_first[i];
+                lf = inl.leaf_first[i];
+                lf1 = inl.leaf_first[i + 1];
+                tab = inl.itab[i];
+                sc = inl.iscale[i];
+            }
+        A0 = lf + kColBoxes * (b - tf);
+        cnt = min(kColBoxes, lf1 - A0);
+    } else {
+        A0 = tiles[2 * b];
+        cnt = tiles[2 * b + 1];
+        const int g = static_cast<int>(leaf_key[A0] >> (3 * key_bits));
+        tab = inst_table ? inst_table[g] : 0;
+        sc = inst_scale ? inst_scale[g] : 1.f;
+    }
+}
+
+template <bool RED, bool CONJ, bool COMP>
+__global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols(
+    int key_bits, const int32_t *__restrict__ tiles, HelmInline inl, const int32_t *__restrict__ leaf_start,
+    const uint64_t *__restrict__ leaf_key, const int32_t *__restrict__ perm,
+    const int64_t *__restrict__ nbr_start, const int32_t *__restrict__ nbr_idx,
+    const int64_t *__restrict__ red_start, const int64_t *__restrict__ red_row, const float2 *__restrict__ src,
+    const float2 *__restrict__ blocks, const float2 *__restrict__ zeros, const int32_t *__restrict__ inst_table,
+    const float *__restrict__ inst_scale, float2 *__restrict__ u) {
+    typedef float floatx4 __attribute__((ext_vector_type(4)));
+    __shared__ int64_t s_row[27][kColBoxes];             // first source row of (offset, column); -1: none
+    __shared__ int64_t s_nstart[kColBoxes + 1];
+    // partial sums of waves 1.. for wave 0: FP32 tiles, or FP64 sums under COMP
+    __shared__ floatx4 s_red[COMP ? 1 : kColWaves - 1][4][2][64];
+    __shared__ double s_redd[COMP ? (kColWaves - 1) * 4 * 2 * 4 * 64 : 1];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    // the tile: its first box, its box count, the G table and 1/h of its instance
+    int32_t A0, cnt, tab;
+    float sc;
+    col_tile(key_bits, tiles, inl, leaf_key, inst_table, inst_scale, static_cast<int32_t>(blockIdx.x), A0, cnt, tab,
+             sc);
+    // first source row of every (offset, column), from the tile's near lists
+    // (one contiguous run of the CSR); -1 where the column has no such neighbour
+    const uint64_t local_mask = (1ull << (3 * key_bits)) - 1ull;
+    for (int i = tid; i < 27 * kColBoxes; i += 64 * kColWaves) s_row[i / kColBoxes][i % kColBoxes] = -1;
+    if (tid <= cnt) s_nstart[tid] = nbr_start[A0 + tid];
+    __syncthreads();
+    const int64_t e_lo = s_nstart[0], e_hi = s_nstart[cnt];
+    for (int64_t e = e_lo + tid; e < e_hi; e += 64 * kColWaves) {
+        int j = 0;
+        while (j + 1 < cnt && s_nstart[j + 1] <= e) ++j;
+        const int64_t A = A0 + j;
+        const int32_t B = nbr_idx[e];
+        const uint64_t lA = leaf_key[A] & local_mask, lB = leaf_key[B] & local_mask;
+        const int ox = (static_cast<int>(p2pd::compact3(lB)) - static_cast<int>(p2pd::compact3(lA))) / 4;
+        const int oy = (static_cast<int>(p2pd::compact3(lB >> 1)) - static_cast<int>(p2pd::compact3(lA >> 1))) / 4;
+        const int oz = (static_cast<int>(p2pd::compact3(lB >> 2)) - static_cast<int>(p2pd::compact3(lA >> 2))) / 4;
+        const int o = (ox + 1) + 3 * (oy + 1) + 9 * (oz + 1);
+        s_row[o][j] = RED ? (red_row ? red_row[e] : red_start[A] + 64 * (e - s_nstart[j]))
+                          : static_cast<int64_t>(leaf_start[B]);
+    }
+    __syncthreads();
+
+    const int li = lane & 15, kq = lane >> 4;
+    const float2 *__restrict__ gbase = blocks + static_cast<int64_t>(tab) * (27 * 4096);
+    // Every instruction of the k-step loop that is not a matrix product or a load
+    // takes issue cycles from the matrix cores (the vector and matrix units share
+    // them), so the loop holds none: the G base of an offset is uniform (scalar
+    // registers, a lane adds only its fixed offset), a lane's four row-tile
+    // values of G sit in one 32-byte run (the single-RHS layout), a column
+    // without the neighbour reads 64 zero rows instead of being masked, and the
+    // sign of Im G is applied once at the end (Re U = sum Re G Re Q - sum Im G
+    // Im Q from two accumulators).  Lane (k, i) reads, at k-step kk, G_o[source
+    // 4 kk + k][targets i, 16 + i, 32 + i, 48 + i] and Q[source 4 kk + k] of
+    // column i.
+    // Wave w takes the offsets o = w + 4 idx, idx = 0..6, without a branch: the
+    // one slot past the 27 offsets (wave 3's last) and every column without the
+    // neighbour read the zero rows, which add exact zeros.  A branch would let
+    // the compiler sink the next offset's prefetch loads below it and drain the
+    // load pipeline at every offset.
+    const int goff = (kq * 16 + li) * 4;
+    auto ptrs = [&](int idx, const float2 *&Gs, const float2 *&Qp) {
+        const int o = w + kColWaves * idx;
+        const int64_t row = o < 27 ? s_row[o][li] : int64_t(-1);
+        Gs = gbase + (o < 27 ? o : 0) * 4096;
+        Qp = (row >= 0 ? src + row : zeros) + kq;
+    };
+    // ar = sum Re G Re Q, br = sum Im G Im Q, ai = sum Re G Im Q, bi = sum Im G Re Q
+    floatx4 ar[4], br[4], ai[4], bi[4];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) ar[rt] = br[rt] = ai[rt] = bi[rt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    // U = G Q: Re = ar - br, Im = ai + bi; with CONJ (conj G): Re = ar + br, Im = ai - bi
+    auto re_of = [&](int rt, int r) { return CONJ ? ar[rt][r] + br[rt][r] : ar[rt][r] - br[rt][r]; };
+    auto im_of = [&](int rt, int r) { return CONJ ? ai[rt][r] - bi[rt][r] : ai[rt][r] + bi[rt][r]; };
+    // COMP: FP64 per-target sums of the per-offset FP32 partial products
+    constexpr int CN = COMP ? 4 : 1;
+    double cr[4][CN], ci[4][CN];
+    if constexpr (COMP) {
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) cr[rt][r] = ci[rt][r] = 0.0;
+    }
+    // fresh: the first k-step of an offset under COMP starts from zero
+    auto mma = [&](const float2 (&gv)[4], const float2 q, bool fresh) {
+        const floatx4 zero = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) {
+            ar[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[rt].x, q.x, fresh ? zero : ar[rt], 0, 0, 0);
+            ai[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[rt].x, q.y, fresh ? zero : ai[rt], 0, 0, 0);
+        }
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) {
+            br[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[rt].y, q.y, fresh ? zero : br[rt], 0, 0, 0);
+            bi[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[rt].y, q.x, fresh ? zero : bi[rt], 0, 0, 0);
+        }
+    };
+    {
+        // The wave's 7 x 16 k-steps, unrolled as one sequence (a loop would carry
+        // the sixteen accumulators across its back edge, which the register
+        // allocator pays for with copies on every iteration).  G is read from
+        // L2 and issued kColPrefG steps ahead; the Q rows (the redundant layout
+        // streams from HBM) kColPrefQ steps ahead, each step's G loads issued
+        // before its Q load so that waiting for a step's G never waits for a
+        // younger Q.  Scheduling barriers keep the loads where they are.
+        const float2 *Gs[kColOffsets], *Qs[kColOffsets];
+#pragma unroll
+        for (int idx = 0; idx < kColOffsets; ++idx) ptrs(idx, Gs[idx], Qs[idx]);
+        constexpr int NS = kColOffsets * 16;
+        float2 gbuf[kColPrefG + 1][4], qbuf[kColPrefQ + 1];
+        auto load_g = [&](int st) {
+            const float4 *g4 = reinterpret_cast<const float4 *>(Gs[st / 16] + (st % 16) * 256 + goff);
+            const float4 lo = g4[0], hi = g4[1];
+            float2(&gv)[4] = gbuf[st % (kColPrefG + 1)];
+            gv[0] = make_float2(lo.x, lo.y);
+            gv[1] = make_float2(lo.z, lo.w);
+            gv[2] = make_float2(hi.x, hi.y);
+            gv[3] = make_float2(hi.z, hi.w);
+        };
+        auto load_q = [&](int st) { qbuf[st % (kColPrefQ + 1)] = Qs[st / 16][(st % 16) * 4]; };
+#pragma unroll
+        for (int st = 0; st < kColPrefG; ++st) load_g(st);
+#pragma unroll
+        for (int st = 0; st < kColPrefQ; ++st) load_q(st);
+        // (two nested unrolled loops: one loop of 112 steps exceeds the unroller's limit)
+#pragma unroll
+        for (int idx = 0; idx < kColOffsets; ++idx) {
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk) {
+                const int st = idx * 16 + kk;
+                if (st + kColPrefG < NS) load_g(st + kColPrefG);
+                if (st + kColPrefQ < NS) load_q(st + kColPrefQ);
+                __builtin_amdgcn_sched_barrier(0);
+                mma(gbuf[st % (kColPrefG + 1)], qbuf[st % (kColPrefQ + 1)], COMP && kk == 0);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if constexpr (COMP) {
+                // each offset's 64-term FP32 partial product into the FP64 sums
+#pragma unroll
+                for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        cr[rt][r] += static_cast<double>(re_of(rt, r));
+                        ci[rt][r] += static_cast<double>(im_of(rt, r));
+                    }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    }
+    floatx4 ur[4], ui[4];
+    if constexpr (!COMP) {
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                ur[rt][r] = re_of(rt, r);
+                ui[rt][r] = im_of(rt, r);
+            }
+    }
+    auto red_at = [&](int q, int rt, int im, int r) -> double & {
+        return s_redd[(((q * 4 + rt) * 2 + im) * 4 + r) * 64 + lane];
+    };
+    if (w > 0) {
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) {
+            if constexpr (COMP) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    red_at(w - 1, rt, 0, r) = cr[rt][r];
+                    red_at(w - 1, rt, 1, r) = ci[rt][r];
+                }
+            } else {
+                s_red[w - 1][rt][0][lane] = ur[rt];
+                s_red[w - 1][rt][1][lane] = ui[rt];
+            }
+        }
+    }
+    __syncthreads();
+    if (w == 0 && li < cnt) {
+        const int32_t t0 = leaf_start[A0 + li];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) {
+#pragma unroll
+            for (int q = 0; q < kColWaves - 1; ++q) {
+                if constexpr (COMP) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        cr[rt][r] += red_at(q, rt, 0, r);
+                        ci[rt][r] += red_at(q, rt, 1, r);
+                    }
+                } else {
+                    ur[rt] += s_red[q][rt][0][lane];
+                    ui[rt] += s_red[q][rt][1][lane];
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = 16 * rt + 4 * kq + r;
+                if constexpr (COMP)
+                    u[perm[t0 + i]] = make_float2(static_cast<float>(cr[rt][r] * sc), static_cast<float>(ci[rt][r] * sc));
+                else
+                    u[perm[t0 + i]] = make_float2(ur[rt][r] * sc, ui[rt][r] * sc);
+            }
+        }
+    }
+}
+
+}  // namespace
+
+int32_t helmholtz_cols_tiles(const p2p_grid *grids, int32_t n_grids, int32_t *tiles) {
+    int64_t first = 0;
+    int32_t t = 0;
+    for (int32_t g = 0; g < n_grids; ++g) {
+        const int64_t nb = static_cast<int64_t>(grids[g].n_side / 4) * (grids[g].n_side / 4) * (grids[g].n_side / 4);
+        for (int64_t b = 0; b < nb; b += kColBoxes, ++t) {
+            if (tiles) {
+                tiles[2 * t] = static_cast<int32_t>(first + b);
+                tiles[2 * t + 1] = static_cast<int32_t>(std::min<int64_t>(kColBoxes, nb - b));
+            }
+        }
+        first += nb;
+    }
+    return t;
+}
+
+p2p_status launch_helmholtz_mfma_cols(const HelmholtzMfmaArgs &a, const int32_t *tiles, const HelmInline &inl,
+                                      int32_t n_tiles, bool redundant, hipStream_t s) {
+    if (n_tiles <= 0) return P2P_OK;
+#define P2P_MFC2(R, C, M)                                                                               \
+    k_helm_mfma_cols<R, C, M><<<static_cast<unsigned>(n_tiles), 64 * kColWaves, 0, s>>>(               \
+        a.key_bits, tiles, inl, a.leaf_start, a.leaf_key, a.perm, a.nbr_start, a.nbr_idx, a.red_start, a.red_row, a.src, \
+        a.blocks, a.zeros, a.inst_table, a.inst_scale, a.u)
+#define P2P_MFC(R, C) if (a.comp) P2P_MFC2(R, C, true); else P2P_MFC2(R, C, false)
+    const bool cj = a.conj != 0;
+    if (redundant) { if (cj) { P2P_MFC(true, true); } else { P2P_MFC(true, false); } }
+    else { if (cj) { P2P_MFC(false, true); } else { P2P_MFC(false, false); } }
+#undef P2P_MFC
+#undef P2P_MFC2
+    P2P_LAUNCH_CHECK();
+    return P2P_OK;
+}
+
+}  // namespace p2p

@@ -37,14 +37,22 @@ namespace {
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 constexpr double kPi = 3.14159265358979323846;
 
-// blocks[t][c][o][s][i] = e^{i kh sqrt(dd)} / (4 pi sqrt(dd)), dd = |l_i - (l_s + 4 o)|^2,
-// zero for dd = 0, identical for every copy c.  o = (ox+1) + 3 (oy+1) + 9 (oz+1); l_* are
-// local Morton coordinates.
+// G(t, o, s, i) = e^{i kh sqrt(dd)} / (4 pi sqrt(dd)), dd = |l_i - (l_s + 4 o)|^2, zero for
+// dd = 0, for table t, offset o = (ox+1) + 3 (oy+1) + 9 (oz+1), source s and target i (l_*
+// are local Morton coordinates).  Multi-RHS layout: blocks[t][c][o][s][i], identical for
+// every copy c.  Single-RHS (COLS) layout: blocks[t][o][s][i % 16][i / 16], the four
+// row tiles of a target column next to each other, so a lane reads the four it needs
+// in one 32-byte run.  After the tables, 64 zeros (the source rows of an absent
+// neighbour).
 __global__ void k_green_blocks(const double *__restrict__ kh_dev, HelmInline inl, int32_t n_tables,
-                               int32_t copies, float2 *__restrict__ blocks) {
+                               int32_t copies, bool cols, float2 *__restrict__ blocks) {
     const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int64_t per = 27 * 64 * 64;
-    if (t >= per * n_tables * copies) return;
+    const int64_t per = 27 * 64 * 64, total = per * n_tables * copies;
+    if (t >= total + 64) return;
+    if (t >= total) {
+        blocks[t] = make_float2(0.f, 0.f);
+        return;
+    }
     const int tab = static_cast<int>(t / (per * copies));
     double khv = 0.0;
     if (inl.n_grids > 0) {
@@ -74,7 +82,10 @@ __global__ void k_green_blocks(const double *__restrict__ kh_dev, HelmInline inl
         sincos(khv * r, &sn, &cs);
         v = make_float2(static_cast<float>(cs * a), static_cast<float>(sn * a));
     }
-    blocks[t] = v;
+    if (cols)
+        blocks[static_cast<int64_t>(tab) * per + o * 4096 + s * 64 + (i % 16) * 4 + i / 16] = v;
+    else
+        blocks[t] = v;
 }
 
 __global__ void k_work_keys(const int64_t *__restrict__ nbr_start, int64_t L,
@@ -281,259 +292,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1))) void k
     helm_mfma_body<RED, CONJ, 2, true>(P2P_HELM_MFMA_ARGS);
 }
 
-// Single right-hand side on matrix cores: the target boxes become the columns
-// of the product.  For a tile of up to 16 boxes b_0..b_15 of one instance,
-//     U (64 x 16) = sum_o G_o (64 x 64) Q_o (64 x 16),
-// column j of Q_o holding the 64 sources of the box at offset o from b_j (a
-// zero column where b_j has no such neighbour, at the faces of the grid), so
-// every column of an instruction shares the one G_o.  v_mfma_f32_16x16x4f32,
-// complex as four real products as above; lane l supplies A[l%16][l/16] and
-// B[l/16][l%16], and accumulator register r of lane l holds row 4 (l/16) + r,
-// column l%16.  A workgroup of 4 wavefronts owns a tile; wave w takes the
-// offsets o = w, w + 4, ... for all 64 targets (four row tiles, 16
-// instructions per k-step of 4 sources) with a deep operand prefetch, and the
-// four partial products
-// are summed through LDS at the end.  The workgroup first maps every (offset,
-// column) to the first row of its sources -- the sorted rows of the neighbour
-// box (gather) or its place in the target's segment (redundant) -- from the
-// tile's near lists, which are one contiguous run of the CSR.
-constexpr int kColBoxes = kHelmColBoxes;
-constexpr int kColWaves = 4;
-constexpr int kColOffsets = (27 + kColWaves - 1) / kColWaves;
-// operand buffers of the prefetch pipeline; the rotation runs on across offsets
-// of 16 k-steps each, so the count divides 16
-constexpr int kColBufs = 4;
-static_assert(16 % kColBufs == 0, "the buffer rotation must restart with every offset");
-
-template <bool RED, bool CONJ, bool COMP>
-__global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols(
-    int key_bits, const int32_t *__restrict__ tiles, HelmInline inl, const int32_t *__restrict__ leaf_start,
-    const uint64_t *__restrict__ leaf_key, const int32_t *__restrict__ perm,
-    const int64_t *__restrict__ nbr_start, const int32_t *__restrict__ nbr_idx,
-    const int64_t *__restrict__ red_start, const int64_t *__restrict__ red_row, const float2 *__restrict__ src,
-    const float2 *__restrict__ blocks, const int32_t *__restrict__ inst_table,
-    const float *__restrict__ inst_scale, float2 *__restrict__ u) {
-    typedef float floatx4 __attribute__((ext_vector_type(4)));
-    __shared__ int64_t s_row[27][kColBoxes];             // first source row of (offset, column); -1: none
-    __shared__ int64_t s_nstart[kColBoxes + 1];
-    __shared__ int32_t s_offs[kColWaves][kColOffsets];    // each wave's offsets that some column has
-    // partial sums of waves 1.. for wave 0: FP32 tiles, or FP64 sums under COMP
-    __shared__ floatx4 s_red[COMP ? 1 : kColWaves - 1][4][2][64];
-    __shared__ double s_redd[COMP ? (kColWaves - 1) * 4 * 2 * 4 * 64 : 1];
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const uint64_t local_mask = (1ull << (3 * key_bits)) - 1ull;
-    // the tile: its first box, its box count, the G table and 1/h of its instance
-    int32_t A0, cnt, tab;
-    float sc;
-    if (inl.n_grids > 0) {
-        const int32_t b = static_cast<int32_t>(blockIdx.x);
-        int32_t tf = 0, lf = 0, lf1 = 0;
-        tab = 0;
-        sc = 1.f;
-#pragma unroll
-        for (int i = 0; i < kInlineGrids; ++i)
-            if (i < inl.n_grids && b >= inl.tile_first[i]) {
-                tf = inl.tile_first[i];
-                lf = inl.leaf_first[i];
-                lf1 = inl.leaf_first[i + 1];
-                tab = inl.itab[i];
-                sc = inl.iscale[i];
-            }
-        A0 = lf + kColBoxes * (b - tf);
-        cnt = min(kColBoxes, lf1 - A0);
-    } else {
-        A0 = tiles[2 * blockIdx.x];
-        cnt = tiles[2 * blockIdx.x + 1];
-        const int g = static_cast<int>(leaf_key[A0] >> (3 * key_bits));
-        tab = inst_table[g];
-        sc = inst_scale[g];
-    }
-
-    for (int i = tid; i < 27 * kColBoxes; i += 64 * kColWaves) s_row[i / kColBoxes][i % kColBoxes] = -1;
-    if (tid <= cnt) s_nstart[tid] = nbr_start[A0 + tid];
-    __syncthreads();
-    const int64_t e_lo = s_nstart[0], e_hi = s_nstart[cnt];
-    for (int64_t e = e_lo + tid; e < e_hi; e += 64 * kColWaves) {
-        int j = 0;
-        while (j + 1 < cnt && s_nstart[j + 1] <= e) ++j;
-        const int64_t A = A0 + j;
-        const int32_t B = nbr_idx[e];
-        const uint64_t lA = leaf_key[A] & local_mask, lB = leaf_key[B] & local_mask;
-        const int ox = (static_cast<int>(p2pd::compact3(lB)) - static_cast<int>(p2pd::compact3(lA))) / 4;
-        const int oy = (static_cast<int>(p2pd::compact3(lB >> 1)) - static_cast<int>(p2pd::compact3(lA >> 1))) / 4;
-        const int oz = (static_cast<int>(p2pd::compact3(lB >> 2)) - static_cast<int>(p2pd::compact3(lA >> 2))) / 4;
-        const int o = (ox + 1) + 3 * (oy + 1) + 9 * (oz + 1);
-        s_row[o][j] = RED ? (red_row ? red_row[e] : red_start[A] + 64 * (e - s_nstart[j]))
-                          : static_cast<int64_t>(leaf_start[B]);
-    }
-    __syncthreads();
-
-    const int li = lane & 15, kq = lane >> 4;
-    int nv = 0;
-    for (int o = w; o < 27; o += kColWaves) {
-        const bool any = __ballot(li < cnt && s_row[o][li] >= 0) != 0;
-        if (any) {
-            if (lane == 0) s_offs[w][nv] = o;
-            ++nv;
-        }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-
-    const float2 *__restrict__ gbase = blocks + static_cast<int64_t>(tab) * (27 * 4096);
-    // pointers of the wave's idx-th offset: lane (k, i) reads G_o[source 4 kk + k][target 16 rt + i]
-    // for the four row tiles rt and source 4 kk + k of column i; a column without that
-    // neighbour reads row 0 and is zeroed
-    // (the zeroing is a multiply by 0 or 1 at the use: a select would be turned
-    // into a masked load behind a branch, and zeroing at the load would wait
-    // for it there)
-    auto ptrs = [&](int idx, const float2 *&Gp, const float2 *&Qp, float &valid) {
-        const int o = s_offs[w][idx];
-        const int64_t row = s_row[o][li];
-        valid = row >= 0 ? 1.f : 0.f;
-        Gp = gbase + o * 4096 + kq * 64 + li;
-        Qp = src + (row >= 0 ? row : 0) + kq;
-    };
-    auto load = [&](const float2 *Gp, const float2 *Qp, int kk, float2 (&gv)[4], float2 &qv) {
-#pragma unroll
-        for (int rt = 0; rt < 4; ++rt) gv[rt] = Gp[kk * 256 + 16 * rt];
-        qv = Qp[kk * 4];
-    };
-    floatx4 ur[4], ui[4];
-#pragma unroll
-    for (int rt = 0; rt < 4; ++rt) {
-        ur[rt] = floatx4{0.f, 0.f, 0.f, 0.f};
-        ui[rt] = floatx4{0.f, 0.f, 0.f, 0.f};
-    }
-    // COMP: FP64 per-target sums of the per-offset FP32 partial products
-    constexpr int CN = COMP ? 4 : 1;
-    double cr[4][CN], ci[4][CN];
-    if constexpr (COMP) {
-#pragma unroll
-        for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) cr[rt][r] = ci[rt][r] = 0.0;
-    }
-    // the Re G products of all four row tiles, then the Im G products: eight
-    // independent instructions between the two updates of an accumulator;
-    // fresh: the first k-step of an offset under COMP starts from zero
-    auto mma = [&](const float2 (&gv)[4], const float2 q, float valid, bool fresh) {
-        const float2 qv = make_float2(q.x * valid, q.y * valid);
-        const floatx4 zero = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int rt = 0; rt < 4; ++rt) {
-            ur[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[rt].x, qv.x, fresh ? zero : ur[rt], 0, 0, 0);
-            ui[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[rt].x, qv.y, fresh ? zero : ui[rt], 0, 0, 0);
-        }
-#pragma unroll
-        for (int rt = 0; rt < 4; ++rt) {
-            const float gi = CONJ ? -gv[rt].y : gv[rt].y;
-            ur[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(-gi, qv.y, ur[rt], 0, 0, 0);
-            ui[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(gi, qv.x, ui[rt], 0, 0, 0);
-        }
-    };
-    if (nv > 0) {
-        // kColBufs operand buffers in rotation, the loads of k-step kk + kColBufs - 1
-        // issued while step kk runs, across offset boundaries (the last offset
-        // prefetches its own first steps again, harmlessly); scheduling barriers
-        // keep them there.  One wavefront per SIMD leaves registers for a deep
-        // pipeline.
-        constexpr int PF = kColBufs - 1;
-        const float2 *Gc, *Qc, *Gn, *Qn;
-        float vc, vn;
-        ptrs(0, Gc, Qc, vc);
-        float2 gbuf[kColBufs][4], qbuf[kColBufs];
-        float vbuf[kColBufs];
-#pragma unroll
-        for (int kk = 0; kk < PF; ++kk) {
-            load(Gc, Qc, kk, gbuf[kk], qbuf[kk]);
-            vbuf[kk] = vc;
-        }
-        for (int idx = 0; idx < nv; ++idx) {
-            ptrs(idx + 1 < nv ? idx + 1 : idx, Gn, Qn, vn);
-#pragma unroll
-            for (int kk = 0; kk < 16; ++kk) {
-                const int ks = kk + PF;
-                if (ks < 16) {
-                    load(Gc, Qc, ks, gbuf[ks % kColBufs], qbuf[ks % kColBufs]);
-                    vbuf[ks % kColBufs] = vc;
-                } else {
-                    load(Gn, Qn, ks - 16, gbuf[ks % kColBufs], qbuf[ks % kColBufs]);
-                    vbuf[ks % kColBufs] = vn;
-                }
-                __builtin_amdgcn_sched_barrier(0);
-                mma(gbuf[kk % kColBufs], qbuf[kk % kColBufs], vbuf[kk % kColBufs], COMP && kk == 0);
-                __builtin_amdgcn_sched_barrier(0);
-            }
-            if constexpr (COMP) {
-#pragma unroll
-                for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        cr[rt][r] += static_cast<double>(ur[rt][r]);
-                        ci[rt][r] += static_cast<double>(ui[rt][r]);
-                    }
-            }
-            Gc = Gn;
-            Qc = Qn;
-            vc = vn;
-        }
-    }
-    auto red_at = [&](int q, int rt, int im, int r) -> double & {
-        return s_redd[(((q * 4 + rt) * 2 + im) * 4 + r) * 64 + lane];
-    };
-    if (w > 0) {
-#pragma unroll
-        for (int rt = 0; rt < 4; ++rt) {
-            if constexpr (COMP) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    red_at(w - 1, rt, 0, r) = cr[rt][r];
-                    red_at(w - 1, rt, 1, r) = ci[rt][r];
-                }
-            } else {
-                s_red[w - 1][rt][0][lane] = ur[rt];
-                s_red[w - 1][rt][1][lane] = ui[rt];
-            }
-        }
-    }
-    __syncthreads();
-    if (w == 0 && li < cnt) {
-        const int32_t t0 = leaf_start[A0 + li];
-#pragma unroll
-        for (int rt = 0; rt < 4; ++rt) {
-#pragma unroll
-            for (int q = 0; q < kColWaves - 1; ++q) {
-                if constexpr (COMP) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        cr[rt][r] += red_at(q, rt, 0, r);
-                        ci[rt][r] += red_at(q, rt, 1, r);
-                    }
-                } else {
-                    ur[rt] += s_red[q][rt][0][lane];
-                    ui[rt] += s_red[q][rt][1][lane];
-                }
-            }
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = 16 * rt + 4 * kq + r;
-                if constexpr (COMP)
-                    u[perm[t0 + i]] = make_float2(static_cast<float>(cr[rt][r] * sc), static_cast<float>(ci[rt][r] * sc));
-                else
-                    u[perm[t0 + i]] = make_float2(ur[rt][r] * sc, ui[rt][r] * sc);
-            }
-        }
-    }
-}
-
 }  // namespace
 
 p2p_status launch_green_blocks(const double *d_kh, const HelmInline &inl, int32_t n_tables, int32_t copies,
-                               float2 *blocks, hipStream_t s) {
-    const int64_t n = static_cast<int64_t>(n_tables) * copies * 27 * 4096;
-    k_green_blocks<<<grid_for(n, 256), 256, 0, s>>>(d_kh, inl, n_tables, copies, blocks);
+                               bool cols, float2 *blocks, hipStream_t s) {
+    if (cols && copies != 1) return fail(P2P_EINVAL, "internal: the single-RHS G layout has one copy");
+    const int64_t n = static_cast<int64_t>(n_tables) * copies * 27 * 4096 + 64;
+    k_green_blocks<<<grid_for(n, 256), 256, 0, s>>>(d_kh, inl, n_tables, copies, cols, blocks);
     P2P_LAUNCH_CHECK();
     return P2P_OK;
 }
@@ -581,43 +346,6 @@ p2p_status launch_helmholtz_mfma(const HelmholtzMfmaArgs &a, bool redundant, int
         else { if (cj) P2P_MF(false, true, 1); else P2P_MF(false, false, 1); }
     }
 #undef P2P_MF
-    P2P_LAUNCH_CHECK();
-    return P2P_OK;
-}
-
-}  // namespace p2p
-
-namespace p2p {
-
-int32_t helmholtz_cols_tiles(const p2p_grid *grids, int32_t n_grids, int32_t *tiles) {
-    int64_t first = 0;
-    int32_t t = 0;
-    for (int32_t g = 0; g < n_grids; ++g) {
-        const int64_t nb = static_cast<int64_t>(grids[g].n_side / 4) * (grids[g].n_side / 4) * (grids[g].n_side / 4);
-        for (int64_t b = 0; b < nb; b += kColBoxes, ++t) {
-            if (tiles) {
-                tiles[2 * t] = static_cast<int32_t>(first + b);
-                tiles[2 * t + 1] = static_cast<int32_t>(std::min<int64_t>(kColBoxes, nb - b));
-            }
-        }
-        first += nb;
-    }
-    return t;
-}
-
-p2p_status launch_helmholtz_mfma_cols(const HelmholtzMfmaArgs &a, const int32_t *tiles, const HelmInline &inl,
-                                      int32_t n_tiles, bool redundant, hipStream_t s) {
-    if (n_tiles <= 0) return P2P_OK;
-#define P2P_MFC2(R, C, M)                                                                               \
-    k_helm_mfma_cols<R, C, M><<<static_cast<unsigned>(n_tiles), 64 * kColWaves, 0, s>>>(               \
-        a.key_bits, tiles, inl, a.leaf_start, a.leaf_key, a.perm, a.nbr_start, a.nbr_idx, a.red_start, a.red_row, a.src, \
-        a.blocks, a.inst_table, a.inst_scale, a.u)
-#define P2P_MFC(R, C) if (a.comp) P2P_MFC2(R, C, true); else P2P_MFC2(R, C, false)
-    const bool cj = a.conj != 0;
-    if (redundant) { if (cj) { P2P_MFC(true, true); } else { P2P_MFC(true, false); } }
-    else { if (cj) { P2P_MFC(false, true); } else { P2P_MFC(false, false); } }
-#undef P2P_MFC
-#undef P2P_MFC2
     P2P_LAUNCH_CHECK();
     return P2P_OK;
 }
