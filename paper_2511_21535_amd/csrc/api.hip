@@ -929,8 +929,10 @@ HelmSetupBufs helm_take(Arena &ar, const HelmSetup &h, int64_t L) {
     HelmSetupBufs b;
     b.params = ar.take<char>(h.param_bytes);
     if (!h.blk) b.table = ar.take<char>(static_cast<size_t>(h.n_grids) * kTableLen * csize);
-    // the G blocks and 64 zero entries after them
-    if (h.blk) b.blocks = ar.take<float2>(static_cast<size_t>(h.n_tables) * h.copies * 27 * 4096 + 64);
+    // the G blocks: multi-RHS float4 entries; single RHS float2 entries and 64 zero entries after them
+    if (h.blk)
+        b.blocks = ar.take<float2>(h.cols ? static_cast<size_t>(h.n_tables) * 27 * 4096 + 64
+                                          : static_cast<size_t>(h.n_tables) * h.copies * 27 * 4096 * 2);
     if (h.mfma) {
         b.work = ar.take<int32_t>(L);
         b.wkeys = ar.take<uint64_t>(L);
@@ -1028,7 +1030,7 @@ p2p_status helm_run(const HelmSetup &h, const HelmSetupBufs &b, int32_t *counter
         a.red_row = tiled ? red->red_row : nullptr;
         a.src = redundant ? static_cast<const float2 *>(red->planes[0]) : reinterpret_cast<const float2 *>(sorted);
         a.blocks = b.blocks;
-        a.zeros = b.blocks + static_cast<int64_t>(h.n_tables) * h.copies * 27 * 4096;
+        a.zeros = h.cols ? b.blocks + static_cast<int64_t>(h.n_tables) * 27 * 4096 : nullptr;
         a.inst_table = d_itab;
         a.inst_scale = d_iscale;
         a.conj = conj;

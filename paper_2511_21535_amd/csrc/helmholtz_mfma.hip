@@ -39,18 +39,20 @@ constexpr double kPi = 3.14159265358979323846;
 
 // G(t, o, s, i) = e^{i kh sqrt(dd)} / (4 pi sqrt(dd)), dd = |l_i - (l_s + 4 o)|^2, zero for
 // dd = 0, for table t, offset o = (ox+1) + 3 (oy+1) + 9 (oz+1), source s and target i (l_*
-// are local Morton coordinates).  Multi-RHS layout: blocks[t][c][o][s][i], identical for
-// every copy c.  Single-RHS (COLS) layout: blocks[t][o][s][i % 16][i / 16], the four
-// row tiles of a target column next to each other, so a lane reads the four it needs
-// in one 32-byte run.  After the tables, 64 zeros (the source rows of an absent
+// are local Morton coordinates).  Multi-RHS layout: float4 (Re G, Im G, Re G + Im G,
+// Re G - Im G) at [t][c][o][s][i], identical for every copy c (the three-product form of
+// the complex product reads the sum, its conjugate the difference; both are formed in
+// double and rounded once).  Single-RHS (COLS) layout: float2 at [t][o][s][i % 16][i / 16],
+// the four row tiles of a target column next to each other, so a lane reads the four it
+// needs in one 32-byte run, followed by 64 zero entries (the source rows of an absent
 // neighbour).
 __global__ void k_green_blocks(const double *__restrict__ kh_dev, HelmInline inl, int32_t n_tables,
-                               int32_t copies, bool cols, float2 *__restrict__ blocks) {
+                               int32_t copies, bool cols, void *__restrict__ out) {
     const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t per = 27 * 64 * 64, total = per * n_tables * copies;
-    if (t >= total + 64) return;
+    if (t >= total + (cols ? 64 : 0)) return;
     if (t >= total) {
-        blocks[t] = make_float2(0.f, 0.f);
+        static_cast<float2 *>(out)[t] = make_float2(0.f, 0.f);
         return;
     }
     const int tab = static_cast<int>(t / (per * copies));
@@ -74,18 +76,21 @@ __global__ void k_green_blocks(const double *__restrict__ kh_dev, HelmInline inl
         const int diff = li - (ls + 4 * od[d]);
         dd += diff * diff;
     }
-    float2 v = make_float2(0.f, 0.f);
+    double gr = 0.0, gi = 0.0;
     if (dd > 0) {
         const double r = sqrt(static_cast<double>(dd));
         const double a = 1.0 / (4.0 * kPi * r);
         double sn, cs;
         sincos(khv * r, &sn, &cs);
-        v = make_float2(static_cast<float>(cs * a), static_cast<float>(sn * a));
+        gr = cs * a;
+        gi = sn * a;
     }
     if (cols)
-        blocks[static_cast<int64_t>(tab) * per + o * 4096 + s * 64 + (i % 16) * 4 + i / 16] = v;
+        static_cast<float2 *>(out)[static_cast<int64_t>(tab) * per + o * 4096 + s * 64 + (i % 16) * 4 + i / 16] =
+            make_float2(static_cast<float>(gr), static_cast<float>(gi));
     else
-        blocks[t] = v;
+        static_cast<float4 *>(out)[t] = make_float4(static_cast<float>(gr), static_cast<float>(gi),
+                                                    static_cast<float>(gr + gi), static_cast<float>(gr - gi));
 }
 
 __global__ void k_work_keys(const int64_t *__restrict__ nbr_start, int64_t L,
@@ -105,13 +110,19 @@ __global__ void k_zero_counter(int32_t *c, int n) {
 // box's 64-term FP32 partial product is added into FP64 per-target sums (the
 // per-target accumulation in double of FP32 partial sums); otherwise the
 // products of all near boxes accumulate in FP32.
-template <bool RED, bool CONJ, int TJ, bool COMP>
+// M3: the complex product takes three real products per tile instead of four
+// (the 3M form): A = Re G Re Q, B = Im G Im Q, C = (Re G + Im G)(Re Q + Im Q), then
+// Re U = A - B and Im U = C - A - B; with CONJ (conj G), C takes Re G - Im G and
+// Re U = A + B, Im U = C - A + B.  One addition per Q value and k-step (Re Q +
+// Im Q); G brings its sum and difference with it.  Otherwise four products:
+// Re U = Re G Re Q - Im G Im Q, Im U = Re G Im Q + Im G Re Q.
+template <bool RED, bool CONJ, int TJ, bool COMP, bool M3>
 __device__ __forceinline__ void helm_mfma_body(
     int64_t L, int key_bits, int32_t nrhs, const int32_t *__restrict__ leaf_start,
     const uint64_t *__restrict__ leaf_key, const int32_t *__restrict__ perm,
     const int64_t *__restrict__ nbr_start, const int32_t *__restrict__ nbr_idx,
     const int64_t *__restrict__ red_start, const int64_t *__restrict__ red_row, const float2 *__restrict__ src,
-    const float2 *__restrict__ blocks, int32_t copies, const int32_t *__restrict__ inst_table,
+    const float4 *__restrict__ blocks, int32_t copies, const int32_t *__restrict__ inst_table,
     const float *__restrict__ inst_scale, const int32_t *__restrict__ work,
     int32_t *__restrict__ counter, float2 *__restrict__ u) {
     const int lane = threadIdx.x & 63;
@@ -131,7 +142,7 @@ __device__ __forceinline__ void helm_mfma_body(
         const int g = static_cast<int>(kA >> (3 * key_bits));
         // the workgroups of one XCD (w % 8 equal) spread over the copies
         const int64_t copy = (blockIdx.x >> 3) % copies;
-        const float2 *__restrict__ gbase = blocks + (static_cast<int64_t>(inst_table[g]) * copies + copy) * (27 * 4096);
+        const float4 *__restrict__ gbase = blocks + (static_cast<int64_t>(inst_table[g]) * copies + copy) * (27 * 4096);
         const uint64_t lA = kA & local_mask;
         const int ax = static_cast<int>(p2pd::compact3(lA)), ay = static_cast<int>(p2pd::compact3(lA >> 1)),
                   az = static_cast<int>(p2pd::compact3(lA >> 2));
@@ -156,7 +167,7 @@ __device__ __forceinline__ void helm_mfma_body(
             my_row_lo = static_cast<int>(row0 & 0xffffffff);
             my_row_hi = static_cast<int>(row0 >> 32);
         }
-        auto box_ptrs = [&](int e, const float2 *&Gp, const float2 *&Qp) {
+        auto box_ptrs = [&](int e, const float4 *&Gp, const float2 *&Qp) {
             const int goff = __builtin_amdgcn_readlane(my_goff, e);
             const int64_t row0 = (static_cast<int64_t>(__builtin_amdgcn_readlane(my_row_hi, e)) << 32) |
                                  static_cast<uint32_t>(__builtin_amdgcn_readlane(my_row_lo, e));
@@ -164,14 +175,25 @@ __device__ __forceinline__ void helm_mfma_body(
             Qp = src + (row0 + half) * nrhs + rhs0 + col;
         };
 
-        floatx16 ur[2][TJ], ui[2][TJ];
+        // M3: pa = A, pb = B, pc = C; otherwise ur = pa (Re U), ui = pb (Im U)
+        constexpr int NC = M3 ? TJ : 1;
+        floatx16 pa[2][TJ], pb[2][TJ], pc[2][NC];
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < 2; ++a) {
 #pragma unroll
-            for (int b = 0; b < TJ; ++b) {
-                ur[a][b] = floatx16{0};
-                ui[a][b] = floatx16{0};
-            }
+            for (int b = 0; b < TJ; ++b) pa[a][b] = pb[a][b] = floatx16{0};
+#pragma unroll
+            for (int b = 0; b < NC; ++b) pc[a][b] = floatx16{0};
+        }
+        auto re_of = [&](int a, int b, int r) -> float {
+            if constexpr (M3) return CONJ ? pa[a][b][r] + pb[a][b][r] : pa[a][b][r] - pb[a][b][r];
+            else return pa[a][b][r];
+        };
+        auto im_of = [&](int a, int b, int r) -> float {
+            if constexpr (M3)
+                return CONJ ? pc[a][b % NC][r] - pa[a][b][r] + pb[a][b][r] : pc[a][b % NC][r] - pa[a][b][r] - pb[a][b][r];
+            else return pb[a][b][r];
+        };
         // FP64 per-target sums of the per-box partial products (COMP)
         constexpr int CN = COMP ? 16 : 1;
         double cr[2][TJ][CN], ci[2][TJ][CN];
@@ -185,24 +207,41 @@ __device__ __forceinline__ void helm_mfma_body(
         }
 
         const int64_t qstep = 2 * static_cast<int64_t>(nrhs);   // two source rows per k-step
-        auto load = [&](const float2 *Gp, const float2 *Qp, int kk, float2 (&gv)[2], float2 (&qv)[TJ]) {
+        auto load = [&](const float4 *Gp, const float2 *Qp, int kk, float4 (&gv)[2], float2 (&qv)[TJ]) {
 #pragma unroll
             for (int a = 0; a < 2; ++a) gv[a] = Gp[kk * 128 + 32 * a];
 #pragma unroll
             for (int b = 0; b < TJ; ++b) qv[b] = Qp[kk * qstep + 32 * b];
         };
         // fresh: the first k-step of a box under COMP starts from zero accumulators
-        auto mma = [&](const float2 (&gv)[2], const float2 (&qv)[TJ], bool fresh) {
+        auto mma = [&](const float4 (&gv)[2], const float2 (&qv)[TJ], bool fresh) {
             const floatx16 zero = floatx16{0};
+            if constexpr (M3) {
+                float qs[TJ];
 #pragma unroll
-            for (int a = 0; a < 2; ++a) {
-                const float gr = gv[a].x, gi = CONJ ? -gv[a].y : gv[a].y;
+                for (int b = 0; b < TJ; ++b) qs[b] = qv[b].x + qv[b].y;
 #pragma unroll
-                for (int b = 0; b < TJ; ++b) {
-                    ur[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(gr, qv[b].x, fresh ? zero : ur[a][b], 0, 0, 0);
-                    ui[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(gr, qv[b].y, fresh ? zero : ui[a][b], 0, 0, 0);
-                    ur[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(-gi, qv[b].y, ur[a][b], 0, 0, 0);
-                    ui[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(gi, qv[b].x, ui[a][b], 0, 0, 0);
+                for (int a = 0; a < 2; ++a) {
+                    const float gs = CONJ ? gv[a].w : gv[a].z;
+#pragma unroll
+                    for (int b = 0; b < TJ; ++b) {
+                        pa[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(gv[a].x, qv[b].x, fresh ? zero : pa[a][b], 0, 0, 0);
+                        pb[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(gv[a].y, qv[b].y, fresh ? zero : pb[a][b], 0, 0, 0);
+                        pc[a][b % NC] =
+                            __builtin_amdgcn_mfma_f32_32x32x2f32(gs, qs[b], fresh ? zero : pc[a][b % NC], 0, 0, 0);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    const float gr = gv[a].x, gi = CONJ ? -gv[a].y : gv[a].y;
+#pragma unroll
+                    for (int b = 0; b < TJ; ++b) {
+                        pa[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(gr, qv[b].x, fresh ? zero : pa[a][b], 0, 0, 0);
+                        pb[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(gr, qv[b].y, fresh ? zero : pb[a][b], 0, 0, 0);
+                        pa[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(-gi, qv[b].y, pa[a][b], 0, 0, 0);
+                        pb[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(gi, qv[b].x, pb[a][b], 0, 0, 0);
+                    }
                 }
             }
         };
@@ -210,9 +249,11 @@ __device__ __forceinline__ void helm_mfma_body(
         // four operand buffers in rotation: the loads of k-step kk + 3 are issued
         // while step kk runs, across box boundaries (the last box prefetches
         // its own first steps again, harmlessly)
-        const float2 *Gc, *Qc, *Gn, *Qn;
+        const float4 *Gc, *Gn;
+        const float2 *Qc, *Qn;
         box_ptrs(0, Gc, Qc);
-        float2 gbuf[4][2], qbuf[4][TJ];
+        float4 gbuf[4][2];
+        float2 qbuf[4][TJ];
         load(Gc, Qc, 0, gbuf[0], qbuf[0]);
         load(Gc, Qc, 1, gbuf[1], qbuf[1]);
         load(Gc, Qc, 2, gbuf[2], qbuf[2]);
@@ -239,8 +280,8 @@ __device__ __forceinline__ void helm_mfma_body(
                     for (int b = 0; b < TJ; ++b)
 #pragma unroll
                         for (int r = 0; r < 16; ++r) {
-                            cr[a][b][r] += static_cast<double>(ur[a][b][r]);
-                            ci[a][b][r] += static_cast<double>(ui[a][b][r]);
+                            cr[a][b][r] += static_cast<double>(re_of(a, b, r));
+                            ci[a][b][r] += static_cast<double>(im_of(a, b, r));
                         }
             }
             Gc = Gn;
@@ -260,7 +301,7 @@ __device__ __forceinline__ void helm_mfma_body(
                         u[row + 32 * b] = make_float2(static_cast<float>(cr[a][b][r] * sc),
                                                       static_cast<float>(ci[a][b][r] * sc));
                     else
-                        u[row + 32 * b] = make_float2(ur[a][b][r] * sc, ui[a][b][r] * sc);
+                        u[row + 32 * b] = make_float2(re_of(a, b, r) * sc, im_of(a, b, r) * sc);
                 }
             }
     }
@@ -271,33 +312,39 @@ __device__ __forceinline__ void helm_mfma_body(
         const uint64_t *__restrict__ leaf_key, const int32_t *__restrict__ perm,                        \
         const int64_t *__restrict__ nbr_start, const int32_t *__restrict__ nbr_idx,                     \
         const int64_t *__restrict__ red_start, const int64_t *__restrict__ red_row,                     \
-        const float2 *__restrict__ src, const float2 *__restrict__ blocks, int32_t copies,              \
+        const float2 *__restrict__ src, const float4 *__restrict__ blocks, int32_t copies,              \
         const int32_t *__restrict__ inst_table, const float *__restrict__ inst_scale,                   \
         const int32_t *__restrict__ work, int32_t *__restrict__ counter, float2 *__restrict__ u
 #define P2P_HELM_MFMA_ARGS                                                                              \
     L, key_bits, nrhs, leaf_start, leaf_key, perm, nbr_start, nbr_idx, red_start, red_row, src, blocks, \
         copies, inst_table, inst_scale, work, counter, u
 
-// Two waves per SIMD.
+// The product form of each variant: three real products, except 64 right-hand
+// sides per wave with FP64 sums, whose 128 doubles per lane of sums leave no
+// room for a third set of accumulators.
+template <int TJ, bool COMP>
+constexpr bool kM3 = !(TJ == 2 && COMP);
+
+// Two waves per SIMD: 32 right-hand sides per wave in FP32.
 template <bool RED, bool CONJ, int TJ, bool COMP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_helm_mfma(P2P_HELM_MFMA_PARAMS) {
-    helm_mfma_body<RED, CONJ, TJ, COMP>(P2P_HELM_MFMA_ARGS);
+    helm_mfma_body<RED, CONJ, TJ, COMP, kM3<TJ, COMP>>(P2P_HELM_MFMA_ARGS);
 }
 
-// 64 right-hand sides per wave with FP64 sums: the 128 doubles per lane of the
-// sums do not fit beside the accumulators at two waves per SIMD, so one.
-template <bool RED, bool CONJ>
+// One wave per SIMD: 64 right-hand sides per wave, or FP64 sums (their doubles
+// per lane do not fit beside the accumulators at two waves per SIMD).
+template <bool RED, bool CONJ, int TJ, bool COMP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1))) void k_helm_mfma_wide(
     P2P_HELM_MFMA_PARAMS) {
-    helm_mfma_body<RED, CONJ, 2, true>(P2P_HELM_MFMA_ARGS);
+    helm_mfma_body<RED, CONJ, TJ, COMP, kM3<TJ, COMP>>(P2P_HELM_MFMA_ARGS);
 }
 
 }  // namespace
 
 p2p_status launch_green_blocks(const double *d_kh, const HelmInline &inl, int32_t n_tables, int32_t copies,
-                               bool cols, float2 *blocks, hipStream_t s) {
+                               bool cols, void *blocks, hipStream_t s) {
     if (cols && copies != 1) return fail(P2P_EINVAL, "internal: the single-RHS G layout has one copy");
-    const int64_t n = static_cast<int64_t>(n_tables) * copies * 27 * 4096 + 64;
+    const int64_t n = static_cast<int64_t>(n_tables) * copies * 27 * 4096 + (cols ? 64 : 0);
     k_green_blocks<<<grid_for(n, 256), 256, 0, s>>>(d_kh, inl, n_tables, copies, cols, blocks);
     P2P_LAUNCH_CHECK();
     return P2P_OK;
@@ -314,14 +361,15 @@ p2p_status launch_work_order(const int64_t *nbr_start, int64_t L, int32_t *work,
 
 template <bool RED, bool CONJ, int TJ, bool COMP>
 static void launch_mfma_t(const HelmholtzMfmaArgs &a, unsigned grid, unsigned block, hipStream_t s) {
-    if constexpr (TJ == 2 && COMP)
-        k_helm_mfma_wide<RED, CONJ><<<grid, block, 0, s>>>(
+    const float4 *g4 = reinterpret_cast<const float4 *>(a.blocks);
+    if constexpr (TJ == 2 || COMP)
+        k_helm_mfma_wide<RED, CONJ, TJ, COMP><<<grid, block, 0, s>>>(
             a.L, a.key_bits, a.nrhs, a.leaf_start, a.leaf_key, a.perm, a.nbr_start, a.nbr_idx,
-            a.red_start, a.red_row, a.src, a.blocks, a.copies, a.inst_table, a.inst_scale, a.work, a.counter, a.u);
+            a.red_start, a.red_row, a.src, g4, a.copies, a.inst_table, a.inst_scale, a.work, a.counter, a.u);
     else
         k_helm_mfma<RED, CONJ, TJ, COMP><<<grid, block, 0, s>>>(
             a.L, a.key_bits, a.nrhs, a.leaf_start, a.leaf_key, a.perm, a.nbr_start, a.nbr_idx,
-            a.red_start, a.red_row, a.src, a.blocks, a.copies, a.inst_table, a.inst_scale, a.work, a.counter, a.u);
+            a.red_start, a.red_row, a.src, g4, a.copies, a.inst_table, a.inst_scale, a.work, a.counter, a.u);
 }
 
 p2p_status launch_helmholtz_mfma(const HelmholtzMfmaArgs &a, bool redundant, int waves_per_wg,

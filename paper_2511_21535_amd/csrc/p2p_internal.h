@@ -297,8 +297,9 @@ struct HelmholtzMfmaArgs {
     const int64_t *red_start;
     const int64_t *red_row;    // tile-grain layout: first row of each entry's source box (else null)
     const float2 *src;         // sorted q rows (gather) or redundant rows, [.][nrhs]
-    const float2 *blocks;      // [n_tables][copies][27][64 src][64 tgt] complex G blocks (unit spacing);
-                               // single RHS: [n_tables][27][64 src][16][4] (target 16 r + c at [c][r])
+    const float2 *blocks;      // multi-RHS: float4 (Re, Im, Re + Im, Re - Im) G at [n_tables][copies][27][64 src]
+                               // [64 tgt] (unit spacing); single RHS: float2 at [n_tables][27][64 src][16][4]
+                               // (target 16 r + c at [c][r])
     const float2 *zeros;       // 64 zero rows (an absent neighbour's sources, single RHS)
     int32_t copies;            // copies of each table; workgroup w reads copy (w / 8) % copies
     const int32_t *inst_table; // per instance: table index
@@ -327,7 +328,7 @@ struct HelmInline {
 // G blocks for the k h values of d_kh, or of inl.kh when inl.n_grids > 0, in the
 // multi-RHS or (cols) the single-RHS layout, followed by 64 zero entries.
 p2p_status launch_green_blocks(const double *d_kh, const HelmInline &inl, int32_t n_tables, int32_t copies,
-                               bool cols, float2 *blocks, hipStream_t s);
+                               bool cols, void *blocks, hipStream_t s);
 p2p_status launch_work_order(const int64_t *nbr_start, int64_t L, int32_t *work, uint64_t *keys,
                              uint64_t *keys_tmp, int32_t *vals_tmp, uint32_t *hist,
                              hipStream_t s);

@@ -60,11 +60,17 @@ def test_mfma_tiles_agree_and_conjugate():
     gt, gn = _grid_tree([12, 16])
     q = W.grid_rhs(gt.n, 64, seed=62)
     gq = _t(q)
-    base = _n(api.helmholtz(gt, gn, gq, prec="fp32"))
-    # every launch shape and every number of copies of the G blocks gives the same bits
+    # FP32_MIXED: 32 right-hand sides per wave take the complex product as three real
+    # products, 64 per wave (with the FP64 sums) as four; within one product form every
+    # launch shape and every number of copies of the G blocks gives the same bits, and
+    # the two forms agree with each other and with the oracle
+    base = {r: _n(api.helmholtz(gt, gn, gq, prec="fp32", tile=(4, 2, r, 1))) for r in (32, 64)}
     for tile in list(autotune.CANDIDATES) + [(4, 2, 64, c) for c in autotune.COPIES]:
         u = _n(api.helmholtz(gt, gn, gq, prec="fp32", tile=tile))
-        np.testing.assert_array_equal(u, base)
+        np.testing.assert_array_equal(u, base[tile[2]])
+    ref = oracle.helmholtz([12, 16], q)
+    assert _rel(base[32], base[64]) <= 1e-6
+    assert _rel(base[32], ref) <= TOL32 and _rel(base[64], ref) <= TOL32
     # conjugated action A^H g = conj(A conj(g)) on the matrix cores
     outc = _n(api.helmholtz_adjoint(gt, gn, gq, prec="fp32", conjugate=True))
     assert _rel(outc, np.conj(oracle.helmholtz([12, 16], np.conj(q)))) <= TOL32
