@@ -30,6 +30,7 @@ namespace {
 constexpr int kColBoxes = kHelmColBoxes;
 constexpr int kColWaves = 4;
 constexpr int kColOffsets = (27 + kColWaves - 1) / kColWaves;
+static_assert(kColWaves == 4, "wave w finishes row tile w of the four");
 // operand buffers of the prefetch pipeline; the rotation runs on across offsets
 // of 16 k-steps each, so the count divides 16
 // prefetch distances of the G and Q operands, in k-steps
@@ -77,9 +78,13 @@ __global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols(
     typedef float floatx4 __attribute__((ext_vector_type(4)));
     __shared__ int64_t s_row[27][kColBoxes];             // first source row of (offset, column); -1: none
     __shared__ int64_t s_nstart[kColBoxes + 1];
-    // partial sums of waves 1.. for wave 0: FP32 tiles, or FP64 sums under COMP
-    __shared__ floatx4 s_red[COMP ? 1 : kColWaves - 1][4][2][64];
-    __shared__ double s_redd[COMP ? (kColWaves - 1) * 4 * 2 * 4 * 64 : 1];
+    __shared__ uint64_t s_key[kColBoxes];                 // local Morton key of each column's box
+    __shared__ int64_t s_rstart[kColBoxes];               // its segment start (redundant layout, box grain)
+    __shared__ int32_t s_tstart[kColBoxes];               // its first sorted target row
+    // the partial sums of every wave for every row tile (wave w finishes row
+    // tile w): FP32 tiles, or FP64 sums under COMP
+    __shared__ floatx4 s_red[COMP ? 1 : kColWaves][4][2][64];
+    __shared__ double s_redd[COMP ? kColWaves * 4 * 2 * 4 * 64 : 1];
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     // the tile: its first box, its box count, the G table and 1/h of its instance
@@ -90,22 +95,54 @@ __global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols(
     // first source row of every (offset, column), from the tile's near lists
     // (one contiguous run of the CSR); -1 where the column has no such neighbour
     const uint64_t local_mask = (1ull << (3 * key_bits)) - 1ull;
+    // (each column's list start, key, segment start and first target row in
+    // one round of loads; then the entries, two per thread with their loads
+    // issued together: at most 27 per box, so one round covers a tile)
     for (int i = tid; i < 27 * kColBoxes; i += 64 * kColWaves) s_row[i / kColBoxes][i % kColBoxes] = -1;
-    if (tid <= cnt) s_nstart[tid] = nbr_start[A0 + tid];
+    if (tid <= cnt) {
+        // all four loads in flight at once (thread cnt only needs the list end)
+        const int32_t a = A0 + min(tid, cnt - 1);
+        const int64_t ns = nbr_start[A0 + tid];
+        const uint64_t key = leaf_key[a];
+        const int64_t rs = (RED && !red_row) ? red_start[a] : 0;
+        const int32_t ts = leaf_start[a];
+        s_nstart[tid] = ns;
+        if (tid < cnt) {
+            s_key[tid] = key & local_mask;
+            s_rstart[tid] = rs;
+            s_tstart[tid] = ts;
+        }
+    }
     __syncthreads();
     const int64_t e_lo = s_nstart[0], e_hi = s_nstart[cnt];
-    for (int64_t e = e_lo + tid; e < e_hi; e += 64 * kColWaves) {
-        int j = 0;
-        while (j + 1 < cnt && s_nstart[j + 1] <= e) ++j;
-        const int64_t A = A0 + j;
-        const int32_t B = nbr_idx[e];
-        const uint64_t lA = leaf_key[A] & local_mask, lB = leaf_key[B] & local_mask;
-        const int ox = (static_cast<int>(p2pd::compact3(lB)) - static_cast<int>(p2pd::compact3(lA))) / 4;
-        const int oy = (static_cast<int>(p2pd::compact3(lB >> 1)) - static_cast<int>(p2pd::compact3(lA >> 1))) / 4;
-        const int oz = (static_cast<int>(p2pd::compact3(lB >> 2)) - static_cast<int>(p2pd::compact3(lA >> 2))) / 4;
-        const int o = (ox + 1) + 3 * (oy + 1) + 9 * (oz + 1);
-        s_row[o][j] = RED ? (red_row ? red_row[e] : red_start[A] + 64 * (e - s_nstart[j]))
-                          : static_cast<int64_t>(leaf_start[B]);
+    constexpr int kT = 64 * kColWaves;
+    for (int64_t e0 = e_lo + tid; e0 < e_hi; e0 += 2 * kT) {
+        int64_t ev[2] = {e0, e0 + kT};
+        int32_t Bv[2];
+        uint64_t lB[2];
+        int64_t rv[2];
+#pragma unroll
+        for (int p = 0; p < 2; ++p) Bv[p] = nbr_idx[ev[p] < e_hi ? ev[p] : e0];
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            lB[p] = leaf_key[Bv[p]] & local_mask;
+            rv[p] = RED ? (red_row ? red_row[ev[p] < e_hi ? ev[p] : e0] : 0) : static_cast<int64_t>(leaf_start[Bv[p]]);
+        }
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const int64_t e = ev[p];
+            if (e >= e_hi) break;
+            int j = 0;
+            while (j + 1 < cnt && s_nstart[j + 1] <= e) ++j;
+            const uint64_t lA = s_key[j];
+            const int ox = (static_cast<int>(p2pd::compact3(lB[p])) - static_cast<int>(p2pd::compact3(lA))) / 4;
+            const int oy =
+                (static_cast<int>(p2pd::compact3(lB[p] >> 1)) - static_cast<int>(p2pd::compact3(lA >> 1))) / 4;
+            const int oz =
+                (static_cast<int>(p2pd::compact3(lB[p] >> 2)) - static_cast<int>(p2pd::compact3(lA >> 2))) / 4;
+            const int o = (ox + 1) + 3 * (oy + 1) + 9 * (oz + 1);
+            s_row[o][j] = (RED && !red_row) ? s_rstart[j] + 64 * (e - s_nstart[j]) : rv[p];
+        }
     }
     __syncthreads();
 
@@ -133,6 +170,7 @@ __global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols(
         Gs = gbase + (o < 27 ? o : 0) * 4096;
         Qp = (row >= 0 ? src + row : zeros) + kq;
     };
+    int32_t dst[4] = {0, 0, 0, 0};
     // ar = sum Re G Re Q, br = sum Im G Im Q, ai = sum Re G Im Q, bi = sum Im G Re Q
     floatx4 ar[4], br[4], ai[4], bi[4];
 #pragma unroll
@@ -190,6 +228,14 @@ __global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols(
         for (int st = 0; st < kColPrefG; ++st) load_g(st);
 #pragma unroll
         for (int st = 0; st < kColPrefQ; ++st) load_q(st);
+        // the caller-order rows of the four targets this lane stores at the end
+        // (row tile w), loaded behind the first operands so that no k-step waits
+        // for them
+        if (li < cnt) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) dst[r] = perm[s_tstart[li] + 16 * w + 4 * kq + r];
+        }
+        __builtin_amdgcn_sched_barrier(0);
         // (two nested unrolled loops: one loop of 112 steps exceeds the unroller's limit)
 #pragma unroll
         for (int idx = 0; idx < kColOffsets; ++idx) {
@@ -225,50 +271,47 @@ __global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols(
                 ui[rt][r] = im_of(rt, r);
             }
     }
+    // Wave w finishes row tile w: every wave leaves its partial sums in LDS,
+    // then wave w adds the four waves' partials of row tile w in wave order
+    // 0..3 and stores its targets.
     auto red_at = [&](int q, int rt, int im, int r) -> double & {
         return s_redd[(((q * 4 + rt) * 2 + im) * 4 + r) * 64 + lane];
     };
-    if (w > 0) {
 #pragma unroll
-        for (int rt = 0; rt < 4; ++rt) {
-            if constexpr (COMP) {
+    for (int rt = 0; rt < 4; ++rt) {
+        if constexpr (COMP) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    red_at(w - 1, rt, 0, r) = cr[rt][r];
-                    red_at(w - 1, rt, 1, r) = ci[rt][r];
-                }
-            } else {
-                s_red[w - 1][rt][0][lane] = ur[rt];
-                s_red[w - 1][rt][1][lane] = ui[rt];
+            for (int r = 0; r < 4; ++r) {
+                red_at(w, rt, 0, r) = cr[rt][r];
+                red_at(w, rt, 1, r) = ci[rt][r];
             }
+        } else {
+            s_red[w][rt][0][lane] = ur[rt];
+            s_red[w][rt][1][lane] = ui[rt];
         }
     }
     __syncthreads();
-    if (w == 0 && li < cnt) {
-        const int32_t t0 = leaf_start[A0 + li];
-#pragma unroll
-        for (int rt = 0; rt < 4; ++rt) {
-#pragma unroll
-            for (int q = 0; q < kColWaves - 1; ++q) {
-                if constexpr (COMP) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        cr[rt][r] += red_at(q, rt, 0, r);
-                        ci[rt][r] += red_at(q, rt, 1, r);
-                    }
-                } else {
-                    ur[rt] += s_red[q][rt][0][lane];
-                    ui[rt] += s_red[q][rt][1][lane];
-                }
-            }
+    if (li < cnt) {
+        if constexpr (COMP) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int i = 16 * rt + 4 * kq + r;
-                if constexpr (COMP)
-                    u[perm[t0 + i]] = make_float2(static_cast<float>(cr[rt][r] * sc), static_cast<float>(ci[rt][r] * sc));
-                else
-                    u[perm[t0 + i]] = make_float2(ur[rt][r] * sc, ui[rt][r] * sc);
+                double tr = red_at(0, w, 0, r), ti = red_at(0, w, 1, r);
+#pragma unroll
+                for (int q = 1; q < kColWaves; ++q) {
+                    tr += red_at(q, w, 0, r);
+                    ti += red_at(q, w, 1, r);
+                }
+                u[dst[r]] = make_float2(static_cast<float>(tr * sc), static_cast<float>(ti * sc));
             }
+        } else {
+            floatx4 fr = s_red[0][w][0][lane], fi = s_red[0][w][1][lane];
+#pragma unroll
+            for (int q = 1; q < kColWaves; ++q) {
+                fr += s_red[q][w][0][lane];
+                fi += s_red[q][w][1][lane];
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) u[dst[r]] = make_float2(fr[r] * sc, fi[r] * sc);
         }
     }
 }
