@@ -102,6 +102,90 @@ __global__ void k_leaf_level_particles(const uint8_t *__restrict__ c, int64_t n,
     flag[i] = (i == 0 || static_cast<int>(c[i - 1]) < l) ? 1 : 0;
 }
 
+// The same leaf levels for leaf_cap <= 64 without the merge: slot i's leaf
+// level is the coarsest level l whose node around i holds at most leaf_cap
+// slots (the merge's last common-digit count v satisfies v + 1 = that level;
+// past the node the merge only meets smaller counts), capped at depth.  The
+// node at level l spans the run of counts >= l on either side of i, and no
+// run longer than 64 matters, so a wave of 64 slots reads the counts of
+// slots -64..127 around it as three ballots per level, and each lane measures
+// its run with one leading- and one trailing-ones count.  Levels are tried
+// from the root down until every lane has its answer.
+__global__ __launch_bounds__(256) void k_leaf_level_ballot(const uint64_t *__restrict__ sk, int64_t n, int depth,
+                                                           int leaf_cap, int8_t *__restrict__ level,
+                                                           int32_t *__restrict__ flag) {
+    __shared__ int8_t cs[256 + 128];   // cs[k] = c[b - 64 + k], -1 past either end
+    const int64_t b = static_cast<int64_t>(blockIdx.x) * 256;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    for (int k = t; k < 256 + 128; k += 256) {
+        const int64_t j = b - 64 + k;
+        cs[k] = (j >= 0 && j + 1 < n) ? static_cast<int8_t>(common_digits(sk[j], sk[j + 1])) : int8_t(-1);
+    }
+    __syncthreads();
+    // this wave's window: c of slots (wave's first) - 64 + k, k < 192, in three registers
+    const int c0 = cs[64 * wv + lane], c1 = cs[64 * wv + 64 + lane], c2 = cs[64 * wv + 128 + lane];
+    const int sh = lane;   // the lane's own count c[i] sits at window bit 64 + lane
+    int lev = -1;
+    for (int l = 0; l <= 21; ++l) {
+        const uint64_t W0 = __ballot(c0 >= l), W1 = __ballot(c1 >= l), W2 = __ballot(c2 >= l);
+        // right: window bits 64 + lane .. 127 + lane; left: bits lane .. 63 + lane (top bit: c[i - 1])
+        const uint64_t R = sh == 0 ? W1 : (W1 >> sh) | (W2 << (64 - sh));
+        const uint64_t Lw = sh == 0 ? W0 : (W0 >> sh) | (W1 << (64 - sh));
+        const int right = R == ~0ull ? 64 : __builtin_ctzll(~R);
+        const int left = Lw == ~0ull ? 64 : __builtin_clzll(~Lw);
+        if (lev < 0 && left + right + 1 <= leaf_cap) lev = l;
+        if (__ballot(lev < 0) == 0) break;
+    }
+    const int64_t i = b + 64 * wv + lane;
+    if (i >= n) return;
+    const int l = min(depth, lev);
+    level[i] = static_cast<int8_t>(l);
+    flag[i] = (i == 0 || static_cast<int>(cs[64 * wv + 63 + lane]) < l) ? 1 : 0;
+}
+
+// The same leaf levels for leaf_cap <= kTileCap, a block of 256 slots at a
+// time: the block first forms the common-digit counts of its slots and of
+// leaf_cap slots on either side (the farthest the merge can reach) from the
+// sorted keys into LDS, -1 past either end of the sequence, so the merge loop
+// reads LDS instead of issuing a scattered byte load per step.
+constexpr int kTileCap = 2048;
+constexpr int kTileSlots = 256;
+__global__ __launch_bounds__(kTileSlots) void k_leaf_level_tile(const uint64_t *__restrict__ sk, int64_t n,
+                                                                  int depth, int leaf_cap,
+                                                                  int8_t *__restrict__ level,
+                                                                  int32_t *__restrict__ flag) {
+    extern __shared__ int8_t cs[];   // cs[k] = c[b - leaf_cap + k], k < kTileSlots + 2 leaf_cap
+    const int64_t b = static_cast<int64_t>(blockIdx.x) * kTileSlots;
+    const int t = threadIdx.x, w = kTileSlots + 2 * leaf_cap;
+    for (int k = t; k < w; k += kTileSlots) {
+        const int64_t j = b - leaf_cap + k;
+        cs[k] = (j >= 0 && j + 1 < n) ? static_cast<int8_t>(common_digits(sk[j], sk[j + 1])) : int8_t(-1);
+    }
+    __syncthreads();
+    const int64_t i = b + t;
+    if (i >= n) return;
+    // left slot i - 1 - dl at cs[t + leaf_cap - 1 - dl], right slot i + dr at cs[t + leaf_cap + dr]
+    int kl = t + leaf_cap - 1, kr = t + leaf_cap;
+    int mL = 127, mR = 127, v = -1;
+    int cl = cs[kl], cr = cs[kr];
+    // after step + 1 < leaf_cap moves, kl >= t and kr < t + 2 leaf_cap: both in the tile
+    for (int step = 0; step < leaf_cap; ++step) {
+        const int candL = min(mL, cl), candR = min(mR, cr);
+        if (candL < 0 && candR < 0) { v = -1; break; }
+        const bool more = step + 1 < leaf_cap;
+        if (candL >= candR) {
+            v = candL; mL = candL; --kl;
+            if (more) cl = cs[kl];
+        } else {
+            v = candR; mR = candR; ++kr;
+            if (more) cr = cs[kr];
+        }
+    }
+    const int l = min(depth, v + 1);
+    level[i] = static_cast<int8_t>(l);
+    flag[i] = (i == 0 || static_cast<int>(cs[t + leaf_cap - 1]) < l) ? 1 : 0;
+}
+
 __global__ void k_leaf_flag_grids(const uint64_t *__restrict__ sk, int64_t n,
                                   int32_t *__restrict__ flag, int8_t *__restrict__ level,
                                   int box_level) {
@@ -198,7 +282,12 @@ p2p_status launch_grid_keys(const int32_t *d_n_side, const int64_t *d_point_off,
 p2p_status launch_leaf_levels(const uint64_t *skeys, int64_t n, int kind, int depth, int leaf_cap,
                               uint8_t *pair_common, int8_t *level, int32_t *flags, hipStream_t s) {
     if (n <= 0) return P2P_OK;
-    if (kind == P2P_TREE_PARTICLES) {
+    if (kind == P2P_TREE_PARTICLES && leaf_cap > 0 && leaf_cap <= 64) {
+        k_leaf_level_ballot<<<grid_for(n, 256), 256, 0, s>>>(skeys, n, depth, leaf_cap, level, flags);
+    } else if (kind == P2P_TREE_PARTICLES && leaf_cap > 0 && leaf_cap <= kTileCap) {
+        k_leaf_level_tile<<<grid_for(n, kTileSlots), kTileSlots, kTileSlots + 2 * leaf_cap, s>>>(
+            skeys, n, depth, leaf_cap, level, flags);
+    } else if (kind == P2P_TREE_PARTICLES) {
         if (n > 1) {
             k_pair_common<<<grid_for(n - 1, 256), 256, 0, s>>>(skeys, n, pair_common);
             P2P_LAUNCH_CHECK();

@@ -60,6 +60,8 @@ PARTICLE_CASES = [
     ("plummer", 3001, 10, 20, 1),
     ("plummer", 777, 11, 6, 16),      # depth cap reached
     ("uniform", 20000, 13, 1, 0),     # 8 leaves of ~2500 points: segments of 20000 rows, >256 targets per leaf
+    ("plummer", 30000, 14, 20, 2048),  # the largest cap of the LDS-tiled leaf levels
+    ("plummer", 30000, 15, 20, 2049),  # past it: the per-slot merge over global memory
 ]
 
 
