@@ -467,8 +467,11 @@ __global__ __launch_bounds__(kGBlock) __attribute__((amdgpu_waves_per_eu(6))) vo
 // kernels: positions relative to the target leaf's centre, taken in double
 // and rounded to float once per staged source, float pair terms summed at
 // most 32 at a time before they are added to double accumulators.
+// Five waves per SIMD: the FP32-mixed form then fits in 96 registers without
+// spills (15% faster than at four); the FP64 form runs as fast either way.
 template <bool PER, bool MIXED>
-__global__ __launch_bounds__(kGBlock) void k_gravity_adjoint(GravityAdjointArgs a) {
+__global__ __launch_bounds__(kGBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_gravity_adjoint(
+    GravityAdjointArgs a) {
     using Src = typename std::conditional<MIXED, float4, Row4d>::type;
     __shared__ Src s_p[kGTile];    // sources (x, y, z, m)
     __shared__ Src s_g[kGTile];    // their upstream gradients (g_phi, g_ax, g_ay, g_az)
