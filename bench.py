@@ -81,6 +81,7 @@ SLOTS_PER_PAIR_ADJ_MIXED = 42 + 1                    # = 43
 FP32_VALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12  # = 78.6
 FP32_MFMA_PEAK_TFLOPS = 157.3                        # dense FP32 matrix (published)
 FP64_VALU_PEAK_TFLOPS = 78.6                         # FP64 vector (published)
+FP64_MFMA_PEAK_TFLOPS = 78.6                         # dense FP64 matrix (published)
 CACHE_BYTES = 32.0 * 2 ** 20                         # C of the Locality metric: 8 XCDs x 4 MB L2
 
 
@@ -1007,13 +1008,15 @@ def run_adjoint_helmholtz(wname, args):
                   "n": tree.n, "boxes": tree.n_leaves, "pairs": pairs, "parallelism": "single GPU"})
     line["ms"] = {"forward": t_fwd / K * 1e3, "adjoint": t_adj / K * 1e3, "adjoint_fp32": t_adj32 / K * 1e3}
     line["rates"] = {"forward_plus_adjoint": value, "adjoint": pairs * K / t_adj, "adjoint_fp32": pairs * K / t_adj32}
-    # FP64 adjoint on the FP64 vector units (one complex multiply-add, 8 flop, per pair);
-    # FP32 adjoint on the matrix cores (target boxes as the columns)
+    # both adjoints on the matrix cores with the target boxes as the columns (one
+    # complex multiply-add, 8 flop, per pair): FP64 on the FP64 matrix instructions
+    # (a tile's offsets shared by two workgroups on this grid), FP32 on the FP32 ones
     a64 = 8.0 * pairs / (t_adj / K) / 1e12
     a32 = 8.0 * pairs / (t_adj32 / K) / 1e12
-    line["roofline"] = {"bound": "alu", "kernel": "k_helmholtz<FP64>", "achieved": a64, "peak": FP64_VALU_PEAK_TFLOPS,
-                        "unit": "TFLOP/s", "frac": a64 / FP64_VALU_PEAK_TFLOPS, "traffic": None,
-                        "algorithmic_per_pair": "8 flop per complex multiply-add"}
+    line["roofline"] = {"bound": "mfma", "kernel": "k_helm_mfma_cols64<conj>", "achieved": a64,
+                        "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": a64 / FP64_MFMA_PEAK_TFLOPS,
+                        "traffic": None, "algorithmic_per_pair": "8 flop per complex multiply-add",
+                        "timed": "the whole adjoint call (sorted copy, G blocks, cleared output, product)"}
     line["roofline_fp32"] = with_measured_peak(
         {"bound": "mfma", "kernel": "k_helm_mfma_cols<conj>", "achieved": a32, "peak": FP32_MFMA_PEAK_TFLOPS,
          "unit": "TFLOP/s", "frac": a32 / FP32_MFMA_PEAK_TFLOPS,

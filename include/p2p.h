@@ -329,7 +329,9 @@ p2p_status p2p_eval_gravity_noalloc(const p2p_tree *tree, const p2p_nbrs *nbrs, 
  * nrhs a multiple of 32 runs on FP32 matrix cores (v_mfma_f32_32x32x2f32) in
  * one persistent launch over all boxes of all instances, taking boxes from a
  * work queue ordered by decreasing near-list length; instances whose k h
- * agree to 1e-12 share one set of G blocks.  `tile` (host int32[4], may be
+ * agree to 1e-12 share one set of G blocks.  nrhs == 1 runs on the matrix
+ * cores of its precision (v_mfma_f32_16x16x4f32 or v_mfma_f64_16x16x4f64) with
+ * tiles of 16 target boxes as the columns of the product.  `tile` (host int32[4], may be
  * NULL = default {4, 2, 64 or 32, 1}) is the launch shape the autotuner picked:
  * tile[0] = waves per workgroup (1, 2 or 4), tile[1] = workgroups per compute
  * unit (1..16), tile[2] = right-hand sides per wave (32 or 64, dividing nrhs),
@@ -347,8 +349,8 @@ p2p_status p2p_eval_helmholtz(const p2p_tree *tree, const p2p_nbrs *nbrs, const 
  * reused by every box and every call).  A plan holds, in a caller-owned device
  * buffer, what p2p_eval_helmholtz otherwise rebuilds on every call: the
  * instances' parameters, the G blocks of every distinct k h built in double
- * precision and rounded to single (matrix-core paths) or the G(d^2) tables
- * (vector path), and the work-queue order by decreasing near-list length
+ * precision (rounded to single on the FP32 matrix-core paths) or the G(d^2)
+ * tables (vector path), and the work-queue order by decreasing near-list length
  * (several right-hand sides).  Host struct. */
 typedef struct {
     void *buf;            /* in: device buffer, 256-byte aligned; NULL asks for the size */

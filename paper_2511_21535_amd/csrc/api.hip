@@ -846,8 +846,8 @@ p2p_status helm_setup(const p2p_tree *tree, const p2p_nbrs *nbrs, p2p_precision 
     h->n_grids = n_grids;
     h->fp64 = prec == P2P_FP64;
     h->mfma = !h->fp64 && nrhs % 32 == 0;
-    // one RHS in FP32: matrix cores with the target boxes as columns
-    h->cols = !h->fp64 && nrhs == 1;
+    // one RHS: matrix cores (FP32, or FP64 on the FP64 matrix instructions) with the target boxes as columns
+    h->cols = nrhs == 1;
     h->rhs_tile = (nrhs % 64 == 0) ? 64 : 32;
     if (tile) {
         if (!h->mfma) return fail(P2P_EINVAL, "tile applies to the matrix-core path (FP32_MIXED, nrhs % 32 == 0)");
@@ -914,6 +914,7 @@ p2p_status helm_setup(const p2p_tree *tree, const p2p_nbrs *nbrs, p2p_precision 
             inl.leaf_first[g] = lf;
             inl.itab[g] = h->itab[g];
             inl.iscale[g] = h->iscale[g];
+            inl.iscale64[g] = 1.0 / grids[g].h;
             tf += (nb + kHelmColBoxes - 1) / kHelmColBoxes;
             lf += nb;
         }
@@ -929,9 +930,10 @@ HelmSetupBufs helm_take(Arena &ar, const HelmSetup &h, int64_t L) {
     HelmSetupBufs b;
     b.params = ar.take<char>(h.param_bytes);
     if (!h.blk) b.table = ar.take<char>(static_cast<size_t>(h.n_grids) * kTableLen * csize);
-    // the G blocks: multi-RHS float4 entries; single RHS float2 entries and 64 zero entries after them
+    // the G blocks: multi-RHS float4 entries; single RHS float2 (FP64: double2) entries and 64 zero
+    // entries after them
     if (h.blk)
-        b.blocks = ar.take<float2>(h.cols ? static_cast<size_t>(h.n_tables) * 27 * 4096 + 64
+        b.blocks = ar.take<float2>(h.cols ? (static_cast<size_t>(h.n_tables) * 27 * 4096 + 64) * (h.fp64 ? 2 : 1)
                                           : static_cast<size_t>(h.n_tables) * h.copies * 27 * 4096 * 2);
     if (h.mfma) {
         b.work = ar.take<int32_t>(L);
@@ -964,7 +966,7 @@ p2p_status helm_fill(const HelmSetup &h, const HelmSetupBufs &b, const p2p_tree 
         // a copy from pageable memory has read its source when it returns
         P2P_HIP(hipMemcpyAsync(b.params, hp.data(), h.param_bytes, hipMemcpyHostToDevice, s));
     }
-    if (h.blk) P2P_TRY(launch_green_blocks(d_kh, h.inl, h.n_tables, h.copies, h.cols, b.blocks, s));
+    if (h.blk) P2P_TRY(launch_green_blocks(d_kh, h.inl, h.n_tables, h.copies, h.cols, h.fp64, b.blocks, s));
     else P2P_TRY(launch_green_tables(d_h, d_k, h.n_grids, h.fp64, b.table, s));
     if (h.mfma)
         P2P_TRY(launch_work_order(nbrs->nbr_start, tree->n_leaves, b.work, b.wkeys, b.wkeys_tmp, b.wvals_tmp,
@@ -1030,7 +1032,12 @@ p2p_status helm_run(const HelmSetup &h, const HelmSetupBufs &b, int32_t *counter
         a.red_row = tiled ? red->red_row : nullptr;
         a.src = redundant ? static_cast<const float2 *>(red->planes[0]) : reinterpret_cast<const float2 *>(sorted);
         a.blocks = b.blocks;
-        a.zeros = h.cols ? b.blocks + static_cast<int64_t>(h.n_tables) * 27 * 4096 : nullptr;
+        const int64_t nblk = static_cast<int64_t>(h.n_tables) * 27 * 4096;
+        a.zeros = !h.cols ? nullptr
+                  : h.fp64 ? reinterpret_cast<const float2 *>(reinterpret_cast<const double2 *>(b.blocks) + nblk)
+                           : b.blocks + nblk;
+        a.inst_h = h.inline_params ? nullptr : reinterpret_cast<const double *>(b.params);
+        a.n = n;
         a.inst_table = d_itab;
         a.inst_scale = d_iscale;
         a.conj = conj;
@@ -1039,7 +1046,7 @@ p2p_status helm_run(const HelmSetup &h, const HelmSetupBufs &b, int32_t *counter
         if (h.cols) {
             a.copies = 1;
             a.nrhs = 1;
-            return launch_helmholtz_mfma_cols(a, d_tiles, h.inl, h.n_tiles, redundant, s);
+            return launch_helmholtz_mfma_cols(a, d_tiles, h.inl, h.n_tiles, redundant, h.fp64, s);
         }
         a.copies = h.copies;
         a.work = b.work;

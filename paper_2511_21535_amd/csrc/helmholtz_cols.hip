@@ -38,11 +38,13 @@ constexpr int kColPrefG = 3;
 constexpr int kColPrefQ = 7;
 
 // The column tile of workgroup b: its first box A0, box count cnt, G table tab
-// and 1/h of its instance.
+// and 1/h of its instance (sc in float; sc64 in double from inl.iscale64 or
+// inst_h, when inst_h or the inline parameters are given).
 __device__ inline void col_tile(int key_bits, const int32_t *__restrict__ tiles, const HelmInline &inl,
                                 const uint64_t *__restrict__ leaf_key, const int32_t *__restrict__ inst_table,
-                                const float *__restrict__ inst_scale, int32_t b, int32_t &A0, int32_t &cnt,
-                                int32_t &tab, float &sc) {
+                                const float *__restrict__ inst_scale, const double *__restrict__ inst_h, int32_t b,
+                                int32_t &A0, int32_t &cnt, int32_t &tab, float &sc, double &sc64) {
+    sc64 = 1.0;
     if (inl.n_grids > 0) {
         int32_t tf = 0, lf = 0, lf1 = 0;
         tab = 0;
@@ -55,6 +57,7 @@ __device__ inline void col_tile(int key_bits, const int32_t *__restrict__ tiles,
                 lf1 = inl.leaf_first[i + 1];
                 tab = inl.itab[i];
                 sc = inl.iscale[i];
+                sc64 = inl.iscale64[i];
             }
         A0 = lf + kColBoxes * (b - tf);
         cnt = min(kColBoxes, lf1 - A0);
@@ -64,41 +67,34 @@ __device__ inline void col_tile(int key_bits, const int32_t *__restrict__ tiles,
         const int g = static_cast<int>(leaf_key[A0] >> (3 * key_bits));
         tab = inst_table ? inst_table[g] : 0;
         sc = inst_scale ? inst_scale[g] : 1.f;
+        if (inst_h) sc64 = 1.0 / inst_h[g];
     }
 }
 
-template <bool RED, bool CONJ, bool COMP>
-__global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols(
-    int key_bits, const int32_t *__restrict__ tiles, HelmInline inl, const int32_t *__restrict__ leaf_start,
-    const uint64_t *__restrict__ leaf_key, const int32_t *__restrict__ perm,
-    const int64_t *__restrict__ nbr_start, const int32_t *__restrict__ nbr_idx,
-    const int64_t *__restrict__ red_start, const int64_t *__restrict__ red_row, const float2 *__restrict__ src,
-    const float2 *__restrict__ blocks, const float2 *__restrict__ zeros, const int32_t *__restrict__ inst_table,
-    const float *__restrict__ inst_scale, float2 *__restrict__ u) {
-    typedef float floatx4 __attribute__((ext_vector_type(4)));
-    __shared__ int64_t s_row[27][kColBoxes];             // first source row of (offset, column); -1: none
-    __shared__ int64_t s_nstart[kColBoxes + 1];
-    __shared__ uint64_t s_key[kColBoxes];                 // local Morton key of each column's box
-    __shared__ int64_t s_rstart[kColBoxes];               // its segment start (redundant layout, box grain)
-    __shared__ int32_t s_tstart[kColBoxes];               // its first sorted target row
-    // the partial sums of every wave for every row tile (wave w finishes row
-    // tile w): FP32 tiles, or FP64 sums under COMP
-    __shared__ floatx4 s_red[COMP ? 1 : kColWaves][4][2][64];
-    __shared__ double s_redd[COMP ? kColWaves * 4 * 2 * 4 * 64 : 1];
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-    // the tile: its first box, its box count, the G table and 1/h of its instance
-    int32_t A0, cnt, tab;
-    float sc;
-    col_tile(key_bits, tiles, inl, leaf_key, inst_table, inst_scale, static_cast<int32_t>(blockIdx.x), A0, cnt, tab,
-             sc);
-    // first source row of every (offset, column), from the tile's near lists
-    // (one contiguous run of the CSR); -1 where the column has no such neighbour
+// The (offset, column) map of a tile in LDS: the first source row of every
+// (offset, column) from the tile's near lists (one contiguous run of the CSR;
+// -1 where the column has no such neighbour), and each column's first sorted
+// target row.
+struct ColMap {
+    int64_t row[27][kColBoxes];
+    int64_t nstart[kColBoxes + 1];
+    uint64_t key[kColBoxes];      // local Morton key of each column's box
+    int64_t rstart[kColBoxes];    // its segment start (redundant layout, box grain)
+    int32_t tstart[kColBoxes];    // its first sorted target row
+};
+
+// Fills m; called by the whole workgroup (64 kColWaves threads), ends with a
+// barrier.  Each column's list start, key, segment start and first target row
+// come in one round of loads; then the entries, two per thread with their
+// loads issued together: at most 27 per box, so one round covers a tile.
+template <bool RED>
+__device__ void col_map(ColMap &m, int key_bits, int32_t A0, int32_t cnt, const int32_t *__restrict__ leaf_start,
+                        const uint64_t *__restrict__ leaf_key, const int64_t *__restrict__ nbr_start,
+                        const int32_t *__restrict__ nbr_idx, const int64_t *__restrict__ red_start,
+                        const int64_t *__restrict__ red_row) {
+    const int tid = threadIdx.x;
     const uint64_t local_mask = (1ull << (3 * key_bits)) - 1ull;
-    // (each column's list start, key, segment start and first target row in
-    // one round of loads; then the entries, two per thread with their loads
-    // issued together: at most 27 per box, so one round covers a tile)
-    for (int i = tid; i < 27 * kColBoxes; i += 64 * kColWaves) s_row[i / kColBoxes][i % kColBoxes] = -1;
+    for (int i = tid; i < 27 * kColBoxes; i += 64 * kColWaves) m.row[i / kColBoxes][i % kColBoxes] = -1;
     if (tid <= cnt) {
         // all four loads in flight at once (thread cnt only needs the list end)
         const int32_t a = A0 + min(tid, cnt - 1);
@@ -106,15 +102,15 @@ __global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols(
         const uint64_t key = leaf_key[a];
         const int64_t rs = (RED && !red_row) ? red_start[a] : 0;
         const int32_t ts = leaf_start[a];
-        s_nstart[tid] = ns;
+        m.nstart[tid] = ns;
         if (tid < cnt) {
-            s_key[tid] = key & local_mask;
-            s_rstart[tid] = rs;
-            s_tstart[tid] = ts;
+            m.key[tid] = key & local_mask;
+            m.rstart[tid] = rs;
+            m.tstart[tid] = ts;
         }
     }
     __syncthreads();
-    const int64_t e_lo = s_nstart[0], e_hi = s_nstart[cnt];
+    const int64_t e_lo = m.nstart[0], e_hi = m.nstart[cnt];
     constexpr int kT = 64 * kColWaves;
     for (int64_t e0 = e_lo + tid; e0 < e_hi; e0 += 2 * kT) {
         int64_t ev[2] = {e0, e0 + kT};
@@ -133,18 +129,43 @@ __global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols(
             const int64_t e = ev[p];
             if (e >= e_hi) break;
             int j = 0;
-            while (j + 1 < cnt && s_nstart[j + 1] <= e) ++j;
-            const uint64_t lA = s_key[j];
+            while (j + 1 < cnt && m.nstart[j + 1] <= e) ++j;
+            const uint64_t lA = m.key[j];
             const int ox = (static_cast<int>(p2pd::compact3(lB[p])) - static_cast<int>(p2pd::compact3(lA))) / 4;
             const int oy =
                 (static_cast<int>(p2pd::compact3(lB[p] >> 1)) - static_cast<int>(p2pd::compact3(lA >> 1))) / 4;
             const int oz =
                 (static_cast<int>(p2pd::compact3(lB[p] >> 2)) - static_cast<int>(p2pd::compact3(lA >> 2))) / 4;
             const int o = (ox + 1) + 3 * (oy + 1) + 9 * (oz + 1);
-            s_row[o][j] = (RED && !red_row) ? s_rstart[j] + 64 * (e - s_nstart[j]) : rv[p];
+            m.row[o][j] = (RED && !red_row) ? m.rstart[j] + 64 * (e - m.nstart[j]) : rv[p];
         }
     }
     __syncthreads();
+}
+
+template <bool RED, bool CONJ, bool COMP>
+__global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols(
+    int key_bits, const int32_t *__restrict__ tiles, HelmInline inl, const int32_t *__restrict__ leaf_start,
+    const uint64_t *__restrict__ leaf_key, const int32_t *__restrict__ perm,
+    const int64_t *__restrict__ nbr_start, const int32_t *__restrict__ nbr_idx,
+    const int64_t *__restrict__ red_start, const int64_t *__restrict__ red_row, const float2 *__restrict__ src,
+    const float2 *__restrict__ blocks, const float2 *__restrict__ zeros, const int32_t *__restrict__ inst_table,
+    const float *__restrict__ inst_scale, float2 *__restrict__ u) {
+    typedef float floatx4 __attribute__((ext_vector_type(4)));
+    __shared__ ColMap sm;
+    // the partial sums of every wave for every row tile (wave w finishes row
+    // tile w): FP32 tiles, or FP64 sums under COMP
+    __shared__ floatx4 s_red[COMP ? 1 : kColWaves][4][2][64];
+    __shared__ double s_redd[COMP ? kColWaves * 4 * 2 * 4 * 64 : 1];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    // the tile: its first box, its box count, the G table and 1/h of its instance
+    int32_t A0, cnt, tab;
+    float sc;
+    double sc64;
+    col_tile(key_bits, tiles, inl, leaf_key, inst_table, inst_scale, nullptr, static_cast<int32_t>(blockIdx.x), A0,
+             cnt, tab, sc, sc64);
+    col_map<RED>(sm, key_bits, A0, cnt, leaf_start, leaf_key, nbr_start, nbr_idx, red_start, red_row);
 
     const int li = lane & 15, kq = lane >> 4;
     const float2 *__restrict__ gbase = blocks + static_cast<int64_t>(tab) * (27 * 4096);
@@ -166,7 +187,7 @@ __global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols(
     const int goff = (kq * 16 + li) * 4;
     auto ptrs = [&](int idx, const float2 *&Gs, const float2 *&Qp) {
         const int o = w + kColWaves * idx;
-        const int64_t row = o < 27 ? s_row[o][li] : int64_t(-1);
+        const int64_t row = o < 27 ? sm.row[o][li] : int64_t(-1);
         Gs = gbase + (o < 27 ? o : 0) * 4096;
         Qp = (row >= 0 ? src + row : zeros) + kq;
     };
@@ -233,7 +254,7 @@ __global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols(
         // for them
         if (li < cnt) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) dst[r] = perm[s_tstart[li] + 16 * w + 4 * kq + r];
+            for (int r = 0; r < 4; ++r) dst[r] = perm[sm.tstart[li] + 16 * w + 4 * kq + r];
         }
         __builtin_amdgcn_sched_barrier(0);
         // (two nested unrolled loops: one loop of 112 steps exceeds the unroller's limit)
@@ -316,6 +337,138 @@ __global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols(
     }
 }
 
+
+// FP64 single right-hand side on the FP64 matrix cores: the same product as
+// k_helm_mfma_cols with v_mfma_f64_16x16x4f64 (four real products per
+// complex one, all sums in double; G blocks in double2, same layout).  Lane l
+// supplies A[l%16][l/16] and B[l/16][l%16] as in FP32, but accumulator
+// register r of lane l holds row l/16 + 4 r (rows interleaved), column l%16.
+// A tile's 27 offsets may be shared by H workgroups (H = 2 on grids with at
+// most half as many tiles as CUs, so that twice the CUs work): wave w of part
+// p takes offsets o = 4 p + w + 4 H idx.  With H = 2 both parts add their
+// results into u, which the launcher has cleared: two additions onto zero,
+// whose sum does not depend on their order.
+template <bool RED, bool CONJ, int H>
+__global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols64(
+    int key_bits, const int32_t *__restrict__ tiles, HelmInline inl, const int32_t *__restrict__ leaf_start,
+    const uint64_t *__restrict__ leaf_key, const int32_t *__restrict__ perm,
+    const int64_t *__restrict__ nbr_start, const int32_t *__restrict__ nbr_idx,
+    const int64_t *__restrict__ red_start, const int64_t *__restrict__ red_row, const double2 *__restrict__ src,
+    const double2 *__restrict__ blocks, const double2 *__restrict__ zeros, const int32_t *__restrict__ inst_table,
+    const double *__restrict__ inst_h, double2 *__restrict__ u) {
+    typedef double f64x4 __attribute__((ext_vector_type(4)));
+    constexpr int VW = kColWaves * H;              // waves sharing a tile's offsets
+    constexpr int NSL = (27 + VW - 1) / VW;        // offset slots per wave
+    __shared__ ColMap sm;
+    __shared__ double s_red[kColWaves][4][2][4][64];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int32_t b = static_cast<int32_t>(blockIdx.x) / H, part = static_cast<int32_t>(blockIdx.x) % H;
+    int32_t A0, cnt, tab;
+    float sc;
+    double sc64;
+    col_tile(key_bits, tiles, inl, leaf_key, inst_table, nullptr, inst_h, b, A0, cnt, tab, sc, sc64);
+    col_map<RED>(sm, key_bits, A0, cnt, leaf_start, leaf_key, nbr_start, nbr_idx, red_start, red_row);
+
+    const int li = lane & 15, kq = lane >> 4;
+    const double2 *__restrict__ gbase = blocks + static_cast<int64_t>(tab) * (27 * 4096);
+    // lane (kq, li) reads, at k-step kk, G_o[source 4 kk + kq][targets li, 16 + li, 32 + li, 48 + li]
+    // (one 64-byte run) and Q[source 4 kk + kq] of column li; the slots past the 27
+    // offsets and absent neighbours read the zero rows
+    const int goff = (kq * 16 + li) * 4;
+    const int vw = part * kColWaves + w;
+    auto ptrs = [&](int idx, const double2 *&Gs, const double2 *&Qp) {
+        const int o = vw + VW * idx;
+        const int64_t row = o < 27 ? sm.row[o][li] : int64_t(-1);
+        Gs = gbase + (o < 27 ? o : 0) * 4096;
+        Qp = (row >= 0 ? src + row : zeros) + kq;
+    };
+    int32_t dst[4] = {0, 0, 0, 0};
+    // ar = sum Re G Re Q, br = sum Im G Im Q, ai = sum Re G Im Q, bi = sum Im G Re Q
+    f64x4 ar[4], br[4], ai[4], bi[4];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) ar[rt] = br[rt] = ai[rt] = bi[rt] = f64x4{0.0, 0.0, 0.0, 0.0};
+    {
+        const double2 *Gs[NSL], *Qs[NSL];
+#pragma unroll
+        for (int idx = 0; idx < NSL; ++idx) ptrs(idx, Gs[idx], Qs[idx]);
+        constexpr int NS = NSL * 16;
+        double2 gbuf[kColPrefG + 1][4], qbuf[kColPrefQ + 1];
+        auto load_g = [&](int st) {
+            const double2 *g = Gs[st / 16] + (st % 16) * 256 + goff;
+            double2(&gv)[4] = gbuf[st % (kColPrefG + 1)];
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt) gv[rt] = g[rt];
+        };
+        auto load_q = [&](int st) { qbuf[st % (kColPrefQ + 1)] = Qs[st / 16][(st % 16) * 4]; };
+#pragma unroll
+        for (int st = 0; st < kColPrefG; ++st) load_g(st);
+#pragma unroll
+        for (int st = 0; st < kColPrefQ; ++st) load_q(st);
+        // the caller-order rows of the four targets this lane stores at the end
+        if (li < cnt) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) dst[r] = perm[sm.tstart[li] + 16 * w + kq + 4 * r];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int idx = 0; idx < NSL; ++idx) {
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk) {
+                const int st = idx * 16 + kk;
+                if (st + kColPrefG < NS) load_g(st + kColPrefG);
+                if (st + kColPrefQ < NS) load_q(st + kColPrefQ);
+                __builtin_amdgcn_sched_barrier(0);
+                const double2(&gv)[4] = gbuf[st % (kColPrefG + 1)];
+                const double2 q = qbuf[st % (kColPrefQ + 1)];
+#pragma unroll
+                for (int rt = 0; rt < 4; ++rt) {
+                    ar[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(gv[rt].x, q.x, ar[rt], 0, 0, 0);
+                    ai[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(gv[rt].x, q.y, ai[rt], 0, 0, 0);
+                }
+#pragma unroll
+                for (int rt = 0; rt < 4; ++rt) {
+                    br[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(gv[rt].y, q.y, br[rt], 0, 0, 0);
+                    bi[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(gv[rt].y, q.x, bi[rt], 0, 0, 0);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    }
+    // U = G Q: Re = ar - br, Im = ai + bi; with CONJ (conj G): Re = ar + br, Im = ai - bi.
+    // Wave w finishes row tile w from the four waves' partials, in wave order.
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            s_red[w][rt][0][r][lane] = CONJ ? ar[rt][r] + br[rt][r] : ar[rt][r] - br[rt][r];
+            s_red[w][rt][1][r][lane] = CONJ ? ai[rt][r] - bi[rt][r] : ai[rt][r] + bi[rt][r];
+        }
+    __syncthreads();
+    if (li < cnt) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            double tr = s_red[0][w][0][r][lane], ti = s_red[0][w][1][r][lane];
+#pragma unroll
+            for (int q = 1; q < kColWaves; ++q) {
+                tr += s_red[q][w][0][r][lane];
+                ti += s_red[q][w][1][r][lane];
+            }
+            if constexpr (H == 1) {
+                u[dst[r]] = make_double2(tr * sc64, ti * sc64);
+            } else {
+                unsafeAtomicAdd(&u[dst[r]].x, tr * sc64);
+                unsafeAtomicAdd(&u[dst[r]].y, ti * sc64);
+            }
+        }
+    }
+}
+
+__global__ void k_zero_rows64(double2 *__restrict__ u, int64_t n) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) u[i] = make_double2(0.0, 0.0);
+}
+
 }  // namespace
 
 int32_t helmholtz_cols_tiles(const p2p_grid *grids, int32_t n_grids, int32_t *tiles) {
@@ -334,9 +487,38 @@ int32_t helmholtz_cols_tiles(const p2p_grid *grids, int32_t n_grids, int32_t *ti
     return t;
 }
 
+template <bool R, bool C, int H>
+static void launch_cols64(const HelmholtzMfmaArgs &a, const int32_t *tiles, const HelmInline &inl, int32_t n_tiles,
+                          hipStream_t s) {
+    k_helm_mfma_cols64<R, C, H><<<static_cast<unsigned>(n_tiles) * H, 64 * kColWaves, 0, s>>>(
+        a.key_bits, tiles, inl, a.leaf_start, a.leaf_key, a.perm, a.nbr_start, a.nbr_idx, a.red_start, a.red_row,
+        reinterpret_cast<const double2 *>(a.src), reinterpret_cast<const double2 *>(a.blocks),
+        reinterpret_cast<const double2 *>(a.zeros), a.inst_table, a.inst_h, reinterpret_cast<double2 *>(a.u));
+}
+
 p2p_status launch_helmholtz_mfma_cols(const HelmholtzMfmaArgs &a, const int32_t *tiles, const HelmInline &inl,
-                                      int32_t n_tiles, bool redundant, hipStream_t s) {
+                                      int32_t n_tiles, bool redundant, bool fp64, hipStream_t s) {
     if (n_tiles <= 0) return P2P_OK;
+    if (fp64) {
+        int dev = 0, cus = 0;
+        P2P_HIP(hipGetDevice(&dev));
+        P2P_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        const bool split = 2 * static_cast<int64_t>(n_tiles) <= cus;
+        if (split) {
+            k_zero_rows64<<<grid_for(a.n, 256), 256, 0, s>>>(reinterpret_cast<double2 *>(a.u), a.n);
+            P2P_LAUNCH_CHECK();
+        }
+        const bool cj = a.conj != 0;
+#define P2P_MF64(H)                                                                  \
+    if (redundant) { if (cj) launch_cols64<true, true, H>(a, tiles, inl, n_tiles, s);    \
+                     else launch_cols64<true, false, H>(a, tiles, inl, n_tiles, s); }    \
+    else { if (cj) launch_cols64<false, true, H>(a, tiles, inl, n_tiles, s);             \
+           else launch_cols64<false, false, H>(a, tiles, inl, n_tiles, s); }
+        if (split) { P2P_MF64(2) } else { P2P_MF64(1) }
+#undef P2P_MF64
+        P2P_LAUNCH_CHECK();
+        return P2P_OK;
+    }
 #define P2P_MFC2(R, C, M)                                                                               \
     k_helm_mfma_cols<R, C, M><<<static_cast<unsigned>(n_tiles), 64 * kColWaves, 0, s>>>(               \
         a.key_bits, tiles, inl, a.leaf_start, a.leaf_key, a.perm, a.nbr_start, a.nbr_idx, a.red_start, a.red_row, a.src, \

@@ -45,14 +45,17 @@ constexpr double kPi = 3.14159265358979323846;
 // double and rounded once).  Single-RHS (COLS) layout: float2 at [t][o][s][i % 16][i / 16],
 // the four row tiles of a target column next to each other, so a lane reads the four it
 // needs in one 32-byte run, followed by 64 zero entries (the source rows of an absent
-// neighbour).
+// neighbour); the FP64 single-RHS path keeps the same layout in double2.
 __global__ void k_green_blocks(const double *__restrict__ kh_dev, HelmInline inl, int32_t n_tables,
-                               int32_t copies, bool cols, void *__restrict__ out) {
+                               int32_t copies, bool cols, bool f64, void *__restrict__ out) {
     const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t per = 27 * 64 * 64, total = per * n_tables * copies;
     if (t >= total + (cols ? 64 : 0)) return;
     if (t >= total) {
-        static_cast<float2 *>(out)[t] = make_float2(0.f, 0.f);
+        if (f64)
+            static_cast<double2 *>(out)[t] = make_double2(0.0, 0.0);
+        else
+            static_cast<float2 *>(out)[t] = make_float2(0.f, 0.f);
         return;
     }
     const int tab = static_cast<int>(t / (per * copies));
@@ -85,9 +88,11 @@ __global__ void k_green_blocks(const double *__restrict__ kh_dev, HelmInline inl
         gr = cs * a;
         gi = sn * a;
     }
-    if (cols)
-        static_cast<float2 *>(out)[static_cast<int64_t>(tab) * per + o * 4096 + s * 64 + (i % 16) * 4 + i / 16] =
-            make_float2(static_cast<float>(gr), static_cast<float>(gi));
+    const int64_t at = static_cast<int64_t>(tab) * per + o * 4096 + s * 64 + (i % 16) * 4 + i / 16;
+    if (cols && f64)
+        static_cast<double2 *>(out)[at] = make_double2(gr, gi);
+    else if (cols)
+        static_cast<float2 *>(out)[at] = make_float2(static_cast<float>(gr), static_cast<float>(gi));
     else
         static_cast<float4 *>(out)[t] = make_float4(static_cast<float>(gr), static_cast<float>(gi),
                                                     static_cast<float>(gr + gi), static_cast<float>(gr - gi));
@@ -342,10 +347,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1))) void k
 }  // namespace
 
 p2p_status launch_green_blocks(const double *d_kh, const HelmInline &inl, int32_t n_tables, int32_t copies,
-                               bool cols, void *blocks, hipStream_t s) {
+                               bool cols, bool f64, void *blocks, hipStream_t s) {
     if (cols && copies != 1) return fail(P2P_EINVAL, "internal: the single-RHS G layout has one copy");
+    if (f64 && !cols) return fail(P2P_EINVAL, "internal: FP64 G blocks exist in the single-RHS layout only");
     const int64_t n = static_cast<int64_t>(n_tables) * copies * 27 * 4096 + (cols ? 64 : 0);
-    k_green_blocks<<<grid_for(n, 256), 256, 0, s>>>(d_kh, inl, n_tables, copies, cols, blocks);
+    k_green_blocks<<<grid_for(n, 256), 256, 0, s>>>(d_kh, inl, n_tables, copies, cols, f64, blocks);
     P2P_LAUNCH_CHECK();
     return P2P_OK;
 }

@@ -298,9 +298,11 @@ struct HelmholtzMfmaArgs {
     const int64_t *red_row;    // tile-grain layout: first row of each entry's source box (else null)
     const float2 *src;         // sorted q rows (gather) or redundant rows, [.][nrhs]
     const float2 *blocks;      // multi-RHS: float4 (Re, Im, Re + Im, Re - Im) G at [n_tables][copies][27][64 src]
-                               // [64 tgt] (unit spacing); single RHS: float2 at [n_tables][27][64 src][16][4]
-                               // (target 16 r + c at [c][r])
-    const float2 *zeros;       // 64 zero rows (an absent neighbour's sources, single RHS)
+                               // [64 tgt] (unit spacing); single RHS: float2 (double2 on the FP64 path) at
+                               // [n_tables][27][64 src][16][4] (target 16 r + c at [c][r])
+    const float2 *zeros;       // 64 zero rows (an absent neighbour's sources, single RHS; double2 on FP64)
+    const double *inst_h;      // per instance: h (FP64 single-RHS path with uploaded parameters)
+    int64_t n;                 // points (FP64 single-RHS path: rows of u cleared before a split tile)
     int32_t copies;            // copies of each table; workgroup w reads copy (w / 8) % copies
     const int32_t *inst_table; // per instance: table index
     const float *inst_scale;   // per instance: 1/h
@@ -324,11 +326,13 @@ struct HelmInline {
     int32_t itab[kInlineGrids];             // G table of each instance
     float iscale[kInlineGrids];             // 1/h of each instance
     double kh[kInlineGrids];                // k h of each table
+    double iscale64[kInlineGrids];          // 1/h of each instance in double (FP64 path)
 };
 // G blocks for the k h values of d_kh, or of inl.kh when inl.n_grids > 0, in the
-// multi-RHS or (cols) the single-RHS layout, followed by 64 zero entries.
+// multi-RHS or (cols) the single-RHS layout, followed by 64 zero entries; with
+// f64 (single-RHS layout only) the entries are double2.
 p2p_status launch_green_blocks(const double *d_kh, const HelmInline &inl, int32_t n_tables, int32_t copies,
-                               bool cols, void *blocks, hipStream_t s);
+                               bool cols, bool f64, void *blocks, hipStream_t s);
 p2p_status launch_work_order(const int64_t *nbr_start, int64_t L, int32_t *work, uint64_t *keys,
                              uint64_t *keys_tmp, int32_t *vals_tmp, uint32_t *hist,
                              hipStream_t s);
@@ -340,7 +344,7 @@ p2p_status launch_helmholtz_mfma(const HelmholtzMfmaArgs &a, bool redundant, int
 // conj and u of the arguments (copies 1, no work queue).
 int32_t helmholtz_cols_tiles(const p2p_grid *grids, int32_t n_grids, int32_t *tiles);
 p2p_status launch_helmholtz_mfma_cols(const HelmholtzMfmaArgs &a, const int32_t *tiles, const HelmInline &inl,
-                                      int32_t n_tiles, bool redundant, hipStream_t s);
+                                      int32_t n_tiles, bool redundant, bool fp64, hipStream_t s);
 
 // Locality (locality.hip).
 p2p_status launch_locality_stats(const int32_t *leaf_start, const int64_t *nbr_start,
