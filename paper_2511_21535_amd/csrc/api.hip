@@ -1000,7 +1000,7 @@ p2p_status helm_check_call(const HelmSetup &h, const p2p_tree *tree, const p2p_n
 
 // The evaluation from a filled set-up: the sorted copy of q (GATHER), then one
 // product launch (the matrix-core queue's counter is zeroed first).
-p2p_status helm_run(const HelmSetup &h, const HelmSetupBufs &b, int32_t *counter, char *sorted,
+p2p_status helm_run(const HelmSetup &h, const HelmSetupBufs &b, int32_t *counter, char *sorted, double2 *parts,
                     const p2p_tree *tree, const p2p_nbrs *nbrs, const p2p_redundant *red, p2p_layout layout,
                     const void *q, void *u, int32_t conj, hipStream_t s) {
     P2P_TRY(helm_check_call(h, tree, nbrs, red, layout, q, u, conj));
@@ -1038,6 +1038,7 @@ p2p_status helm_run(const HelmSetup &h, const HelmSetupBufs &b, int32_t *counter
                            : b.blocks + nblk;
         a.inst_h = h.inline_params ? nullptr : reinterpret_cast<const double *>(b.params);
         a.n = n;
+        a.parts = parts;
         a.inst_table = d_itab;
         a.inst_scale = d_iscale;
         a.conj = conj;
@@ -1074,11 +1075,14 @@ p2p_status helm_run(const HelmSetup &h, const HelmSetupBufs &b, int32_t *counter
 }
 
 // Per-call scratch of an evaluation beside the set-up: the queue counter
-// (matrix cores, several RHS) and the sorted copy of q (GATHER).
-void helm_take_call(Arena &ar, const HelmSetup &h, int64_t n, bool redundant, int32_t **counter, char **sorted) {
+// (matrix cores, several RHS), the sorted copy of q (GATHER) and, for one RHS
+// in FP64, the two partial results of tiles whose offsets two workgroups share.
+void helm_take_call(Arena &ar, const HelmSetup &h, int64_t n, bool redundant, int32_t **counter, char **sorted,
+                    double2 **parts) {
     const size_t csize = h.fp64 ? sizeof(double2) : sizeof(float2);
     *counter = h.mfma ? ar.take<int32_t>(64) : nullptr;
     *sorted = redundant ? nullptr : ar.take<char>(static_cast<size_t>(n) * h.nrhs * csize);
+    *parts = (h.cols && h.fp64) ? ar.take<double2>(2 * static_cast<size_t>(n)) : nullptr;
 }
 
 p2p_status helmholtz_common(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2p_redundant *red,
@@ -1093,13 +1097,14 @@ p2p_status helmholtz_common(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2
     const HelmSetupBufs b = helm_take(ar, h, tree->n_leaves);
     int32_t *counter;
     char *sorted;
-    helm_take_call(ar, h, tree->n, layout == P2P_REDUNDANT, &counter, &sorted);
+    double2 *parts;
+    helm_take_call(ar, h, tree->n, layout == P2P_REDUNDANT, &counter, &sorted, &parts);
     p2p_status st;
     if (ws_query(ws, ws_bytes, ar, &st)) return st;
     // every argument is checked before the set-up is queued
     P2P_TRY(helm_check_call(h, tree, nbrs, red, layout, q, u, conj));
     P2P_TRY(helm_fill(h, b, tree, nbrs, grids, s));
-    return helm_run(h, b, counter, sorted, tree, nbrs, red, layout, q, u, conj, s);
+    return helm_run(h, b, counter, sorted, parts, tree, nbrs, red, layout, q, u, conj, s);
 }
 
 // FNV-1a over the arguments a set-up depends on.
@@ -1199,10 +1204,11 @@ extern "C" p2p_status p2p_eval_helmholtz_prepared(const p2p_tree *tree, const p2
     Arena ar(ws);
     int32_t *counter;
     char *sorted;
-    helm_take_call(ar, h, tree->n, layout == P2P_REDUNDANT, &counter, &sorted);
+    double2 *parts;
+    helm_take_call(ar, h, tree->n, layout == P2P_REDUNDANT, &counter, &sorted, &parts);
     p2p_status st;
     if (ws_query(ws, ws_bytes, ar, &st)) return st;
-    return helm_run(h, b, counter, sorted, tree, nbrs, red, layout, q, u, 0, as_stream(stream));
+    return helm_run(h, b, counter, sorted, parts, tree, nbrs, red, layout, q, u, 0, as_stream(stream));
 }
 
 // ------------------------------------------------------------- adjoint ----

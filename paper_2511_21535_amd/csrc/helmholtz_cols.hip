@@ -345,9 +345,10 @@ __global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols(
 // register r of lane l holds row l/16 + 4 r (rows interleaved), column l%16.
 // A tile's 27 offsets may be shared by H workgroups (H = 2 on grids with at
 // most half as many tiles as CUs, so that twice the CUs work): wave w of part
-// p takes offsets o = 4 p + w + 4 H idx.  With H = 2 both parts add their
-// results into u, which the launcher has cleared: two additions onto zero,
-// whose sum does not depend on their order.
+// p takes offsets o = 4 p + w + 4 H idx.  With H = 2 each part stores its
+// result in sorted order to parts[p][.] (coalesced), and k_join_parts64 adds
+// part 0 and part 1 and scatters the sum to the caller's order (FP64 atomic
+// additions at the scattered caller rows took 7 us more on a 48^3 grid).
 template <bool RED, bool CONJ, int H>
 __global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols64(
     int key_bits, const int32_t *__restrict__ tiles, HelmInline inl, const int32_t *__restrict__ leaf_start,
@@ -355,7 +356,7 @@ __global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols64(
     const int64_t *__restrict__ nbr_start, const int32_t *__restrict__ nbr_idx,
     const int64_t *__restrict__ red_start, const int64_t *__restrict__ red_row, const double2 *__restrict__ src,
     const double2 *__restrict__ blocks, const double2 *__restrict__ zeros, const int32_t *__restrict__ inst_table,
-    const double *__restrict__ inst_h, double2 *__restrict__ u) {
+    const double *__restrict__ inst_h, double2 *__restrict__ u, double2 *__restrict__ parts, int64_t n) {
     typedef double f64x4 __attribute__((ext_vector_type(4)));
     constexpr int VW = kColWaves * H;              // waves sharing a tile's offsets
     constexpr int NSL = (27 + VW - 1) / VW;        // offset slots per wave
@@ -405,10 +406,14 @@ __global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols64(
         for (int st = 0; st < kColPrefG; ++st) load_g(st);
 #pragma unroll
         for (int st = 0; st < kColPrefQ; ++st) load_q(st);
-        // the caller-order rows of the four targets this lane stores at the end
+        // the rows of the four targets this lane stores at the end: caller-order
+        // rows, or sorted rows in this part's half of `parts`
         if (li < cnt) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) dst[r] = perm[sm.tstart[li] + 16 * w + kq + 4 * r];
+            for (int r = 0; r < 4; ++r) {
+                const int32_t sr = sm.tstart[li] + 16 * w + kq + 4 * r;
+                dst[r] = H == 1 ? perm[sr] : sr;
+            }
         }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -454,19 +459,21 @@ __global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols64(
                 tr += s_red[q][w][0][r][lane];
                 ti += s_red[q][w][1][r][lane];
             }
-            if constexpr (H == 1) {
+            if constexpr (H == 1)
                 u[dst[r]] = make_double2(tr * sc64, ti * sc64);
-            } else {
-                unsafeAtomicAdd(&u[dst[r]].x, tr * sc64);
-                unsafeAtomicAdd(&u[dst[r]].y, ti * sc64);
-            }
+            else
+                parts[part * n + dst[r]] = make_double2(tr * sc64, ti * sc64);
         }
     }
 }
 
-__global__ void k_zero_rows64(double2 *__restrict__ u, int64_t n) {
+// u[perm[s]] = parts[0][s] + parts[1][s] for every sorted row s.
+__global__ void k_join_parts64(const double2 *__restrict__ parts, const int32_t *__restrict__ perm, int64_t n,
+                               double2 *__restrict__ u) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) u[i] = make_double2(0.0, 0.0);
+    if (i >= n) return;
+    const double2 a = parts[i], b = parts[n + i];
+    u[perm[i]] = make_double2(a.x + b.x, a.y + b.y);
 }
 
 }  // namespace
@@ -493,7 +500,8 @@ static void launch_cols64(const HelmholtzMfmaArgs &a, const int32_t *tiles, cons
     k_helm_mfma_cols64<R, C, H><<<static_cast<unsigned>(n_tiles) * H, 64 * kColWaves, 0, s>>>(
         a.key_bits, tiles, inl, a.leaf_start, a.leaf_key, a.perm, a.nbr_start, a.nbr_idx, a.red_start, a.red_row,
         reinterpret_cast<const double2 *>(a.src), reinterpret_cast<const double2 *>(a.blocks),
-        reinterpret_cast<const double2 *>(a.zeros), a.inst_table, a.inst_h, reinterpret_cast<double2 *>(a.u));
+        reinterpret_cast<const double2 *>(a.zeros), a.inst_table, a.inst_h, reinterpret_cast<double2 *>(a.u), a.parts,
+        a.n);
 }
 
 p2p_status launch_helmholtz_mfma_cols(const HelmholtzMfmaArgs &a, const int32_t *tiles, const HelmInline &inl,
@@ -503,11 +511,7 @@ p2p_status launch_helmholtz_mfma_cols(const HelmholtzMfmaArgs &a, const int32_t 
         int dev = 0, cus = 0;
         P2P_HIP(hipGetDevice(&dev));
         P2P_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        const bool split = 2 * static_cast<int64_t>(n_tiles) <= cus;
-        if (split) {
-            k_zero_rows64<<<grid_for(a.n, 256), 256, 0, s>>>(reinterpret_cast<double2 *>(a.u), a.n);
-            P2P_LAUNCH_CHECK();
-        }
+        const bool split = 2 * static_cast<int64_t>(n_tiles) <= cus && a.parts;
         const bool cj = a.conj != 0;
 #define P2P_MF64(H)                                                                  \
     if (redundant) { if (cj) launch_cols64<true, true, H>(a, tiles, inl, n_tiles, s);    \
@@ -517,6 +521,10 @@ p2p_status launch_helmholtz_mfma_cols(const HelmholtzMfmaArgs &a, const int32_t 
         if (split) { P2P_MF64(2) } else { P2P_MF64(1) }
 #undef P2P_MF64
         P2P_LAUNCH_CHECK();
+        if (split) {
+            k_join_parts64<<<grid_for(a.n, 256), 256, 0, s>>>(a.parts, a.perm, a.n, reinterpret_cast<double2 *>(a.u));
+            P2P_LAUNCH_CHECK();
+        }
         return P2P_OK;
     }
 #define P2P_MFC2(R, C, M)                                                                               \
