@@ -1075,14 +1075,14 @@ p2p_status helm_run(const HelmSetup &h, const HelmSetupBufs &b, int32_t *counter
 }
 
 // Per-call scratch of an evaluation beside the set-up: the queue counter
-// (matrix cores, several RHS), the sorted copy of q (GATHER) and, for one RHS
-// in FP64, the two partial results of tiles whose offsets two workgroups share.
+// (matrix cores, several RHS), the sorted copy of q (GATHER) and, for one RHS,
+// the two partial results of tiles whose offsets two workgroups share.
 void helm_take_call(Arena &ar, const HelmSetup &h, int64_t n, bool redundant, int32_t **counter, char **sorted,
                     double2 **parts) {
     const size_t csize = h.fp64 ? sizeof(double2) : sizeof(float2);
     *counter = h.mfma ? ar.take<int32_t>(64) : nullptr;
     *sorted = redundant ? nullptr : ar.take<char>(static_cast<size_t>(n) * h.nrhs * csize);
-    *parts = (h.cols && h.fp64) ? ar.take<double2>(2 * static_cast<size_t>(n)) : nullptr;
+    *parts = h.cols ? ar.take<double2>(2 * static_cast<size_t>(n)) : nullptr;
 }
 
 p2p_status helmholtz_common(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2p_redundant *red,

@@ -29,7 +29,6 @@ namespace {
 // tile's near lists, which are one contiguous run of the CSR.
 constexpr int kColBoxes = kHelmColBoxes;
 constexpr int kColWaves = 4;
-constexpr int kColOffsets = (27 + kColWaves - 1) / kColWaves;
 static_assert(kColWaves == 4, "wave w finishes row tile w of the four");
 // operand buffers of the prefetch pipeline; the rotation runs on across offsets
 // of 16 k-steps each, so the count divides 16
@@ -143,15 +142,21 @@ __device__ void col_map(ColMap &m, int key_bits, int32_t A0, int32_t cnt, const 
     __syncthreads();
 }
 
-template <bool RED, bool CONJ, bool COMP>
+// H workgroups per tile as in k_helm_mfma_cols64 below (H = 2 on grids with at
+// most half as many tiles as CUs): each part then stores its result, the FP64
+// sums or the FP32 tile, in sorted order to parts[p][.] as double2, and
+// k_join_parts adds the two in double and rounds the sum once.
+template <bool RED, bool CONJ, bool COMP, int H>
 __global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols(
     int key_bits, const int32_t *__restrict__ tiles, HelmInline inl, const int32_t *__restrict__ leaf_start,
     const uint64_t *__restrict__ leaf_key, const int32_t *__restrict__ perm,
     const int64_t *__restrict__ nbr_start, const int32_t *__restrict__ nbr_idx,
     const int64_t *__restrict__ red_start, const int64_t *__restrict__ red_row, const float2 *__restrict__ src,
     const float2 *__restrict__ blocks, const float2 *__restrict__ zeros, const int32_t *__restrict__ inst_table,
-    const float *__restrict__ inst_scale, float2 *__restrict__ u) {
+    const float *__restrict__ inst_scale, float2 *__restrict__ u, double2 *__restrict__ parts, int64_t n) {
     typedef float floatx4 __attribute__((ext_vector_type(4)));
+    constexpr int VW = kColWaves * H;              // waves sharing a tile's offsets
+    constexpr int NSL = (27 + VW - 1) / VW;        // offset slots per wave
     __shared__ ColMap sm;
     // the partial sums of every wave for every row tile (wave w finishes row
     // tile w): FP32 tiles, or FP64 sums under COMP
@@ -163,11 +168,12 @@ __global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols(
     int32_t A0, cnt, tab;
     float sc;
     double sc64;
-    col_tile(key_bits, tiles, inl, leaf_key, inst_table, inst_scale, nullptr, static_cast<int32_t>(blockIdx.x), A0,
-             cnt, tab, sc, sc64);
+    const int32_t b = static_cast<int32_t>(blockIdx.x) / H, part = static_cast<int32_t>(blockIdx.x) % H;
+    col_tile(key_bits, tiles, inl, leaf_key, inst_table, inst_scale, nullptr, b, A0, cnt, tab, sc, sc64);
     col_map<RED>(sm, key_bits, A0, cnt, leaf_start, leaf_key, nbr_start, nbr_idx, red_start, red_row);
 
     const int li = lane & 15, kq = lane >> 4;
+    const int vw = part * kColWaves + w;
     const float2 *__restrict__ gbase = blocks + static_cast<int64_t>(tab) * (27 * 4096);
     // Every instruction of the k-step loop that is not a matrix product or a load
     // takes issue cycles from the matrix cores (the vector and matrix units share
@@ -179,14 +185,14 @@ __global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols(
     // Im Q from two accumulators).  Lane (k, i) reads, at k-step kk, G_o[source
     // 4 kk + k][targets i, 16 + i, 32 + i, 48 + i] and Q[source 4 kk + k] of
     // column i.
-    // Wave w takes the offsets o = w + 4 idx, idx = 0..6, without a branch: the
-    // one slot past the 27 offsets (wave 3's last) and every column without the
-    // neighbour read the zero rows, which add exact zeros.  A branch would let
-    // the compiler sink the next offset's prefetch loads below it and drain the
-    // load pipeline at every offset.
+    // Wave w takes the offsets o = w + 4 idx, idx = 0..6 (H = 1), without a
+    // branch: the one slot past the 27 offsets (wave 3's last) and every column
+    // without the neighbour read the zero rows, which add exact zeros.  A
+    // branch would let the compiler sink the next offset's prefetch loads below
+    // it and drain the load pipeline at every offset.
     const int goff = (kq * 16 + li) * 4;
     auto ptrs = [&](int idx, const float2 *&Gs, const float2 *&Qp) {
-        const int o = w + kColWaves * idx;
+        const int o = vw + VW * idx;
         const int64_t row = o < 27 ? sm.row[o][li] : int64_t(-1);
         Gs = gbase + (o < 27 ? o : 0) * 4096;
         Qp = (row >= 0 ? src + row : zeros) + kq;
@@ -230,10 +236,10 @@ __global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols(
         // streams from HBM) kColPrefQ steps ahead, each step's G loads issued
         // before its Q load so that waiting for a step's G never waits for a
         // younger Q.  Scheduling barriers keep the loads where they are.
-        const float2 *Gs[kColOffsets], *Qs[kColOffsets];
+        const float2 *Gs[NSL], *Qs[NSL];
 #pragma unroll
-        for (int idx = 0; idx < kColOffsets; ++idx) ptrs(idx, Gs[idx], Qs[idx]);
-        constexpr int NS = kColOffsets * 16;
+        for (int idx = 0; idx < NSL; ++idx) ptrs(idx, Gs[idx], Qs[idx]);
+        constexpr int NS = NSL * 16;
         float2 gbuf[kColPrefG + 1][4], qbuf[kColPrefQ + 1];
         auto load_g = [&](int st) {
             const float4 *g4 = reinterpret_cast<const float4 *>(Gs[st / 16] + (st % 16) * 256 + goff);
@@ -254,12 +260,15 @@ __global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols(
         // for them
         if (li < cnt) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) dst[r] = perm[sm.tstart[li] + 16 * w + 4 * kq + r];
+            for (int r = 0; r < 4; ++r) {
+                const int32_t sr = sm.tstart[li] + 16 * w + 4 * kq + r;
+                dst[r] = H == 1 ? perm[sr] : sr;
+            }
         }
         __builtin_amdgcn_sched_barrier(0);
         // (two nested unrolled loops: one loop of 112 steps exceeds the unroller's limit)
 #pragma unroll
-        for (int idx = 0; idx < kColOffsets; ++idx) {
+        for (int idx = 0; idx < NSL; ++idx) {
 #pragma unroll
             for (int kk = 0; kk < 16; ++kk) {
                 const int st = idx * 16 + kk;
@@ -322,7 +331,10 @@ __global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols(
                     tr += red_at(q, w, 0, r);
                     ti += red_at(q, w, 1, r);
                 }
-                u[dst[r]] = make_float2(static_cast<float>(tr * sc), static_cast<float>(ti * sc));
+                if constexpr (H == 1)
+                    u[dst[r]] = make_float2(static_cast<float>(tr * sc), static_cast<float>(ti * sc));
+                else
+                    parts[part * n + dst[r]] = make_double2(tr * sc, ti * sc);
             }
         } else {
             floatx4 fr = s_red[0][w][0][lane], fi = s_red[0][w][1][lane];
@@ -332,7 +344,12 @@ __global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols(
                 fi += s_red[q][w][1][lane];
             }
 #pragma unroll
-            for (int r = 0; r < 4; ++r) u[dst[r]] = make_float2(fr[r] * sc, fi[r] * sc);
+            for (int r = 0; r < 4; ++r) {
+                if constexpr (H == 1)
+                    u[dst[r]] = make_float2(fr[r] * sc, fi[r] * sc);
+                else
+                    parts[part * n + dst[r]] = make_double2(fr[r] * sc, fi[r] * sc);
+            }
         }
     }
 }
@@ -467,6 +484,16 @@ __global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols64(
     }
 }
 
+// u[perm[s]] = parts[0][s] + parts[1][s] for every sorted row s, added in
+// double and rounded once.
+__global__ void k_join_parts(const double2 *__restrict__ parts, const int32_t *__restrict__ perm, int64_t n,
+                             float2 *__restrict__ u) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double2 a = parts[i], b = parts[n + i];
+    u[perm[i]] = make_float2(static_cast<float>(a.x + b.x), static_cast<float>(a.y + b.y));
+}
+
 // u[perm[s]] = parts[0][s] + parts[1][s] for every sorted row s.
 __global__ void k_join_parts64(const double2 *__restrict__ parts, const int32_t *__restrict__ perm, int64_t n,
                                double2 *__restrict__ u) {
@@ -527,17 +554,27 @@ p2p_status launch_helmholtz_mfma_cols(const HelmholtzMfmaArgs &a, const int32_t 
         }
         return P2P_OK;
     }
-#define P2P_MFC2(R, C, M)                                                                               \
-    k_helm_mfma_cols<R, C, M><<<static_cast<unsigned>(n_tiles), 64 * kColWaves, 0, s>>>(               \
+    int dev = 0, cus = 0;
+    P2P_HIP(hipGetDevice(&dev));
+    P2P_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const bool split = 2 * static_cast<int64_t>(n_tiles) <= cus && a.parts;
+#define P2P_MFC3(R, C, M, H)                                                                            \
+    k_helm_mfma_cols<R, C, M, H><<<static_cast<unsigned>(n_tiles) * H, 64 * kColWaves, 0, s>>>(        \
         a.key_bits, tiles, inl, a.leaf_start, a.leaf_key, a.perm, a.nbr_start, a.nbr_idx, a.red_start, a.red_row, a.src, \
-        a.blocks, a.zeros, a.inst_table, a.inst_scale, a.u)
-#define P2P_MFC(R, C) if (a.comp) P2P_MFC2(R, C, true); else P2P_MFC2(R, C, false)
+        a.blocks, a.zeros, a.inst_table, a.inst_scale, a.u, a.parts, a.n)
+#define P2P_MFC2(R, C, M) if (split) P2P_MFC3(R, C, M, 2); else P2P_MFC3(R, C, M, 1)
+#define P2P_MFC(R, C) if (a.comp) { P2P_MFC2(R, C, true); } else { P2P_MFC2(R, C, false); }
     const bool cj = a.conj != 0;
     if (redundant) { if (cj) { P2P_MFC(true, true); } else { P2P_MFC(true, false); } }
     else { if (cj) { P2P_MFC(false, true); } else { P2P_MFC(false, false); } }
 #undef P2P_MFC
 #undef P2P_MFC2
+#undef P2P_MFC3
     P2P_LAUNCH_CHECK();
+    if (split) {
+        k_join_parts<<<grid_for(a.n, 256), 256, 0, s>>>(a.parts, a.perm, a.n, a.u);
+        P2P_LAUNCH_CHECK();
+    }
     return P2P_OK;
 }
 

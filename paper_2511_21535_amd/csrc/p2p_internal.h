@@ -303,7 +303,7 @@ struct HelmholtzMfmaArgs {
     const float2 *zeros;       // 64 zero rows (an absent neighbour's sources, single RHS; double2 on FP64)
     const double *inst_h;      // per instance: h (FP64 single-RHS path with uploaded parameters)
     int64_t n;                 // points
-    double2 *parts;            // FP64 single RHS: [2][n] partial results in sorted order (tiles split in two)
+    double2 *parts;            // single RHS: [2][n] partial results in sorted order (tiles split in two)
     int32_t copies;            // copies of each table; workgroup w reads copy (w / 8) % copies
     const int32_t *inst_table; // per instance: table index
     const float *inst_scale;   // per instance: 1/h
