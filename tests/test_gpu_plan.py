@@ -1,9 +1,9 @@
 """Helmholtz evaluation from a plan (p2p_helmholtz_prepare once, then
 p2p_eval_helmholtz_prepared): bit for bit the results of p2p_eval_helmholtz,
 which builds the same set-up on every call, on every path -- single RHS on
-the matrix cores with parameters in the kernel arguments and uploaded (more
-than 8 instances), several tables of G blocks, multi-RHS on the matrix cores
-with and without a tile, the vector kernel in FP32 and FP64 -- in both
+the matrix cores in FP32 and FP64 with parameters in the kernel arguments and
+uploaded (more than 8 instances), several tables of G blocks, multi-RHS on the
+matrix cores with and without a tile, the vector kernel in FP32 and FP64 -- in both
 layouts and both grains, repeated calls from one plan, and within the
 tolerances of the FP64 oracle."""
 import numpy as np
@@ -45,6 +45,8 @@ CASES = [
     ([12, 8], [10, 6], 64, "fp32", (4, 2, 32, 2)),
     ([12, 8], [10, 10], 3, "fp32", None),
     ([12, 8], [10, 6], 3, "fp64", None),
+    ([12, 8, 20, 4], [10, 6, 10, 8], 1, "fp64", None),        # FP64 matrix cores, tiles split in two
+    ([8] * 5 + [4] * 5, [10, 6] * 5, 1, "fp64", None),        # ... with uploaded parameters (1/h in double)
 ]
 
 
