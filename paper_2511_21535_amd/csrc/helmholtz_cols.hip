@@ -1,9 +1,9 @@
-// Single right-hand side of the near-field Helmholtz sum on FP32 matrix cores
-// (the dense regular case of Sec. 5.1 with one right-hand side), the target
-// boxes taken as the columns of the product.  Kept in a file of its own: it is
-// compiled with the matrix accumulators in ordinary vector registers
-// (-amdgpu-mfma-vgpr-form), so its per-offset FP64 flush reads them without a
-// copy out of the accumulation registers.
+// Single right-hand side of the near-field Helmholtz sum on the matrix cores,
+// FP32 and FP64 (the dense regular case of Sec. 5.1 with one right-hand side),
+// the target boxes taken as the columns of the product.  Kept in a file of its
+// own: it is compiled with the matrix accumulators in ordinary vector
+// registers (-amdgpu-mfma-vgpr-form), so the FP32 kernel's per-offset FP64
+// flush reads them without a copy out of the accumulation registers.
 #include <algorithm>
 
 #include "p2p_internal.h"
@@ -17,22 +17,21 @@ namespace {
 // column j of Q_o holding the 64 sources of the box at offset o from b_j (a
 // zero column where b_j has no such neighbour, at the faces of the grid), so
 // every column of an instruction shares the one G_o.  v_mfma_f32_16x16x4f32,
-// complex as four real products as above; lane l supplies A[l%16][l/16] and
+// complex as four real products; lane l supplies A[l%16][l/16] and
 // B[l/16][l%16], and accumulator register r of lane l holds row 4 (l/16) + r,
 // column l%16.  A workgroup of 4 wavefronts owns a tile; wave w takes the
 // offsets o = w, w + 4, ... for all 64 targets (four row tiles, 16
 // instructions per k-step of 4 sources) with a deep operand prefetch, and the
-// four partial products
-// are summed through LDS at the end.  The workgroup first maps every (offset,
-// column) to the first row of its sources -- the sorted rows of the neighbour
-// box (gather) or its place in the target's segment (redundant) -- from the
-// tile's near lists, which are one contiguous run of the CSR.
+// four partial products are summed through LDS at the end.  The workgroup
+// first maps every (offset, column) to the first row of its sources -- the
+// sorted rows of the neighbour box (gather) or its place in the target's
+// segment (redundant) -- from the tile's near lists, which are one contiguous
+// run of the CSR.
 constexpr int kColBoxes = kHelmColBoxes;
 constexpr int kColWaves = 4;
 static_assert(kColWaves == 4, "wave w finishes row tile w of the four");
-// operand buffers of the prefetch pipeline; the rotation runs on across offsets
-// of 16 k-steps each, so the count divides 16
-// prefetch distances of the G and Q operands, in k-steps
+// prefetch distances of the G and Q operands, in k-steps (the buffer rotation
+// runs on across offsets of 16 k-steps each)
 constexpr int kColPrefG = 3;
 constexpr int kColPrefQ = 7;
 
