@@ -1008,17 +1008,18 @@ def run_adjoint_helmholtz(wname, args):
                   "n": tree.n, "boxes": tree.n_leaves, "pairs": pairs, "parallelism": "single GPU"})
     line["ms"] = {"forward": t_fwd / K * 1e3, "adjoint": t_adj / K * 1e3, "adjoint_fp32": t_adj32 / K * 1e3}
     line["rates"] = {"forward_plus_adjoint": value, "adjoint": pairs * K / t_adj, "adjoint_fp32": pairs * K / t_adj32}
-    # both adjoints on the matrix cores with the target boxes as the columns (one
-    # complex multiply-add, 8 flop, per pair): FP64 on the FP64 matrix instructions
-    # (a tile's offsets shared by two workgroups on this grid), FP32 on the FP32 ones
+    # both adjoints (A^T g = A g, A symmetric: the forward product on g) on the
+    # matrix cores with the target boxes as the columns (one complex multiply-add,
+    # 8 flop, per pair): FP64 on the FP64 matrix instructions, FP32 on the FP32
+    # ones (a tile's offsets shared by two workgroups on this grid)
     a64 = 8.0 * pairs / (t_adj / K) / 1e12
     a32 = 8.0 * pairs / (t_adj32 / K) / 1e12
-    line["roofline"] = {"bound": "mfma", "kernel": "k_helm_mfma_cols64<conj>", "achieved": a64,
+    line["roofline"] = {"bound": "mfma", "kernel": "k_helm_mfma_cols64", "achieved": a64,
                         "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": a64 / FP64_MFMA_PEAK_TFLOPS,
                         "traffic": None, "algorithmic_per_pair": "8 flop per complex multiply-add",
                         "timed": "the whole adjoint call (sorted copy, G blocks, cleared output, product)"}
     line["roofline_fp32"] = with_measured_peak(
-        {"bound": "mfma", "kernel": "k_helm_mfma_cols<conj>", "achieved": a32, "peak": FP32_MFMA_PEAK_TFLOPS,
+        {"bound": "mfma", "kernel": "k_helm_mfma_cols", "achieved": a32, "peak": FP32_MFMA_PEAK_TFLOPS,
          "unit": "TFLOP/s", "frac": a32 / FP32_MFMA_PEAK_TFLOPS,
          "timed": "the whole adjoint call (sorted copy, G blocks, product)"}, "mfma_f32_TFLOPs")
     # A^T g against the oracle's transpose action (a scatter over every target's near field)
