@@ -999,7 +999,8 @@ p2p_status helm_check_call(const HelmSetup &h, const p2p_tree *tree, const p2p_n
 }
 
 // The evaluation from a filled set-up: the sorted copy of q (GATHER), then one
-// product launch (the matrix-core queue's counter is zeroed first).
+// product launch (the matrix-core queue's counter is zeroed first; one RHS on a
+// grid of few tiles adds the join of the two halves of each tile).
 p2p_status helm_run(const HelmSetup &h, const HelmSetupBufs &b, int32_t *counter, char *sorted, double2 *parts,
                     const p2p_tree *tree, const p2p_nbrs *nbrs, const p2p_redundant *red, p2p_layout layout,
                     const void *q, void *u, int32_t conj, hipStream_t s) {
