@@ -68,14 +68,14 @@ VALU_PEAK_SLOTS = 256 * 4 * 16 * 2.4e9               # = 3.93e13
 SLOTS_PER_PAIR_MIXED = 3 + 3 + 2 + 3 + 1 + 3        # = 15
 # FP64 gravity pair: the instructions hipcc emits per pair, each taken as one
 # slot: 3 differences, 3 FMA for r^2 + eps^2, 3 multiplies, 1 FMA (phi),
-# 3 FMA (a), and 9 for the reciprocal square root (v_rsq_f64, Newton steps to
-# full precision, a special-case test and two selects).
-SLOTS_PER_PAIR_FP64 = 3 + 3 + 3 + 1 + 3 + 9         # = 22
+# 3 FMA (a), and 6 for the reciprocal square root (v_rsq_f64 and one
+# third-order refinement step to full precision).
+SLOTS_PER_PAIR_FP64 = 3 + 3 + 3 + 1 + 3 + 6         # = 19
 # Gravity adjoint per pair, the VALU instructions hipcc emits in the pair
-# loop without its loop control: FP64 41 arithmetic + 9 for the reciprocal
+# loop without its loop control: FP64 41 arithmetic + 6 for the reciprocal
 # square root (as in the forward count); FP32-mixed 42, with v_rsq_f32 at
 # half rate (one more slot).
-SLOTS_PER_PAIR_ADJ_FP64 = 41 + 9                     # = 50
+SLOTS_PER_PAIR_ADJ_FP64 = 41 + 6                     # = 47
 SLOTS_PER_PAIR_ADJ_MIXED = 42 + 1                    # = 43
 # FP32 vector FMA without packed issue: 256 CUs x 64 lanes x 2 flop x 2.4 GHz
 FP32_VALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12  # = 78.6

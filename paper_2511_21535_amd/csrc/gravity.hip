@@ -347,7 +347,7 @@ __device__ __forceinline__ void gravity_body(const GravityArgs &a) {
                 auto pair = [&](const Row4d v, int j) {
                     const double dx = tv.x - v.x, dy = tv.y - v.y, dz = tv.z - v.z;
                     const double r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
-                    double w = rsqrt(r2);
+                    double w = p2pd::rsqrt_normal(r2);
                     if constexpr (EPS0) w = (r2 > 0.0) ? w : 0.0;
                     if constexpr (MASK) w = (j == selfj) ? 0.0 : w;
                     const double mw = v.w * w;
@@ -556,7 +556,7 @@ __global__ __launch_bounds__(kGBlock) __attribute__((amdgpu_waves_per_eu(5))) vo
                 for (int s = g; s < nt; s += G) {
                     const Row4d pk = s_p[s], gk = s_g[s];
                     const double dx = pj.x - pk.x, dy = pj.y - pk.y, dz = pj.z - pk.z;
-                    double w = rsqrt(fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2))));
+                    double w = p2pd::rsqrt_normal(fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2))));
                     w = (s == selfs) ? 0.0 : w;
                     const double w3 = w * w * w, w5 = w3 * w * w;
                     const double gdj = gj.y * dx + gj.z * dy + gj.w * dz;

@@ -296,7 +296,7 @@ __global__ __launch_bounds__(64 * kEvalWaves) void k_eval_records(
                             const Row4d v = s_src[w][j];
                             const double dx = tv.x - v.x, dy = tv.y - v.y, dz = tv.z - v.z;
                             const double r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2)));
-                            double wv = rsqrt(r2);
+                            double wv = p2pd::rsqrt_normal(r2);
                             if constexpr (EPS0) wv = (r2 > 0.0) ? wv : 0.0;
                             wv = (j == selfj) ? 0.0 : wv;
                             const double mw = v.w * wv;
