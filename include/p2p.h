@@ -289,7 +289,8 @@ p2p_status p2p_restructure_redundant(const p2p_tree *tree, const p2p_nbrs *nbrs,
  * GATHER layout -- the SoA + indexing baseline of Sec. 5.2.1 -- or from the
  * REDUNDANT layout of Sec. 5.2.1; the update step of Eq. 2 fused): for every
  * particle i, phi_i and a_i as in the header comment, eps >= 0 (eps == 0
- * drops pairs at zero distance; a positive eps must be >= 1e-4 with
+ * drops pairs at zero distance and needs distinct points at least 2^-511
+ * apart in FP64, whose r^-1 is formed for r^2 >= 2^-1022; a positive eps must be >= 1e-4 with
  * FP32_MIXED, whose add-back of the target's own term m_i/eps leaves its
  * float rounding in phi_i, and >= 2^-511 with FP64, which drops that pair by
  * position; smaller positive eps is P2P_EINVAL).  x, y, z, m: caller-order double[n] (needed

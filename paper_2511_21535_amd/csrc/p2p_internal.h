@@ -392,7 +392,8 @@ __device__ inline int64_t xcd_contiguous(int64_t b, int64_t n) {
 
 // 1/sqrt(x) in double for finite x >= 2^-1022 (every r^2 + eps^2 the FP64
 // kernels form: eps >= 2^-511, or eps = 0 with the zero distance selected
-// away): the hardware estimate y refined by one third-order step of the
+// away and distinct points at least 2^-511 apart, as the interface states):
+// the hardware estimate y refined by one third-order step of the
 // series (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 + ..., e = 1 - x y^2, which leaves
 // an error of order e^3, below double rounding.  No special-case tests.
 __device__ inline double rsqrt_normal(double x) {
