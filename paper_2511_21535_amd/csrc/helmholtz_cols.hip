@@ -17,10 +17,10 @@ namespace {
 // column j of Q_o holding the 64 sources of the box at offset o from b_j (a
 // zero column where b_j has no such neighbour, at the faces of the grid), so
 // every column of an instruction shares the one G_o.  v_mfma_f32_16x16x4f32,
-// complex as four real products; lane l supplies A[l%16][l/16] and
+// complex as three real products; lane l supplies A[l%16][l/16] and
 // B[l/16][l%16], and accumulator register r of lane l holds row 4 (l/16) + r,
 // column l%16.  A workgroup of 4 wavefronts owns a tile; wave w takes the
-// offsets o = w, w + 4, ... for all 64 targets (four row tiles, 16
+// offsets o = w, w + 4, ... for all 64 targets (four row tiles, 12
 // instructions per k-step of 4 sources) with a deep operand prefetch, and the
 // four partial products are summed through LDS at the end.  The workgroup
 // first maps every (offset, column) to the first row of its sources -- the
@@ -176,12 +176,14 @@ __global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols(
     const float2 *__restrict__ gbase = blocks + static_cast<int64_t>(tab) * (27 * 4096);
     // Every instruction of the k-step loop that is not a matrix product or a load
     // takes issue cycles from the matrix cores (the vector and matrix units share
-    // them), so the loop holds none: the G base of an offset is uniform (scalar
-    // registers, a lane adds only its fixed offset), a lane's four row-tile
-    // values of G sit in one 32-byte run (the single-RHS layout), a column
-    // without the neighbour reads 64 zero rows instead of being masked, and the
-    // sign of Im G is applied once at the end (Re U = sum Re G Re Q - sum Im G
-    // Im Q from two accumulators).  Lane (k, i) reads, at k-step kk, G_o[source
+    // them), so the loop holds only the five additions of the three-product form
+    // (Re Q + Im Q and the four Re G +- Im G, cheaper than a G layout that stores
+    // the sums: that doubles the G reads from L2, measured slower): the G base of
+    // an offset is uniform (scalar registers, a lane adds only its fixed offset),
+    // a lane's four row-tile values of G sit in one 32-byte run (the single-RHS
+    // layout), a column without the neighbour reads 64 zero rows instead of being
+    // masked, and the signs of the three-product form are applied once per offset
+    // or at the end, from the three accumulators.  Lane (k, i) reads, at k-step kk, G_o[source
     // 4 kk + k][targets i, 16 + i, 32 + i, 48 + i] and Q[source 4 kk + k] of
     // column i.
     // Wave w takes the offsets o = w + 4 idx, idx = 0..6 (H = 1), without a
@@ -197,13 +199,18 @@ __global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols(
         Qp = (row >= 0 ? src + row : zeros) + kq;
     };
     int32_t dst[4] = {0, 0, 0, 0};
-    // ar = sum Re G Re Q, br = sum Im G Im Q, ai = sum Re G Im Q, bi = sum Im G Re Q
-    floatx4 ar[4], br[4], ai[4], bi[4];
+    // The complex product in three real products (the 3M form, as in the
+    // multi-RHS kernel): pa = sum Re G Re Q, pb = sum Im G Im Q,
+    // pc = sum (Re G + Im G)(Re Q + Im Q); U = G Q: Re = pa - pb,
+    // Im = pc - pa - pb.  With CONJ (conj G) pc takes Re G - Im G:
+    // Re = pa + pb, Im = pc - pa + pb.
+    floatx4 pa[4], pb[4], pc[4];
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt) ar[rt] = br[rt] = ai[rt] = bi[rt] = floatx4{0.f, 0.f, 0.f, 0.f};
-    // U = G Q: Re = ar - br, Im = ai + bi; with CONJ (conj G): Re = ar + br, Im = ai - bi
-    auto re_of = [&](int rt, int r) { return CONJ ? ar[rt][r] + br[rt][r] : ar[rt][r] - br[rt][r]; };
-    auto im_of = [&](int rt, int r) { return CONJ ? ai[rt][r] - bi[rt][r] : ai[rt][r] + bi[rt][r]; };
+    for (int rt = 0; rt < 4; ++rt) pa[rt] = pb[rt] = pc[rt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    auto re_of = [&](int rt, int r) { return CONJ ? pa[rt][r] + pb[rt][r] : pa[rt][r] - pb[rt][r]; };
+    auto im_of = [&](int rt, int r) {
+        return CONJ ? pc[rt][r] - pa[rt][r] + pb[rt][r] : pc[rt][r] - pa[rt][r] - pb[rt][r];
+    };
     // COMP: FP64 per-target sums of the per-offset FP32 partial products
     constexpr int CN = COMP ? 4 : 1;
     double cr[4][CN], ci[4][CN];
@@ -216,20 +223,18 @@ __global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols(
     // fresh: the first k-step of an offset under COMP starts from zero
     auto mma = [&](const float2 (&gv)[4], const float2 q, bool fresh) {
         const floatx4 zero = floatx4{0.f, 0.f, 0.f, 0.f};
+        const float qs = q.x + q.y;
 #pragma unroll
         for (int rt = 0; rt < 4; ++rt) {
-            ar[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[rt].x, q.x, fresh ? zero : ar[rt], 0, 0, 0);
-            ai[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[rt].x, q.y, fresh ? zero : ai[rt], 0, 0, 0);
-        }
-#pragma unroll
-        for (int rt = 0; rt < 4; ++rt) {
-            br[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[rt].y, q.y, fresh ? zero : br[rt], 0, 0, 0);
-            bi[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[rt].y, q.x, fresh ? zero : bi[rt], 0, 0, 0);
+            const float gs = CONJ ? gv[rt].x - gv[rt].y : gv[rt].x + gv[rt].y;
+            pa[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[rt].x, q.x, fresh ? zero : pa[rt], 0, 0, 0);
+            pb[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[rt].y, q.y, fresh ? zero : pb[rt], 0, 0, 0);
+            pc[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(gs, qs, fresh ? zero : pc[rt], 0, 0, 0);
         }
     };
     {
         // The wave's 7 x 16 k-steps, unrolled as one sequence (a loop would carry
-        // the sixteen accumulators across its back edge, which the register
+        // the twelve accumulators across its back edge, which the register
         // allocator pays for with copies on every iteration).  G is read from
         // L2 and issued kColPrefG steps ahead; the Q rows (the redundant layout
         // streams from HBM) kColPrefQ steps ahead, each step's G loads issued
@@ -401,10 +406,11 @@ __global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols64(
         Qp = (row >= 0 ? src + row : zeros) + kq;
     };
     int32_t dst[4] = {0, 0, 0, 0};
-    // ar = sum Re G Re Q, br = sum Im G Im Q, ai = sum Re G Im Q, bi = sum Im G Re Q
-    f64x4 ar[4], br[4], ai[4], bi[4];
+    // three real products per complex one, as in the FP32 kernel: pa = sum Re G Re Q,
+    // pb = sum Im G Im Q, pc = sum (Re G +- Im G)(Re Q + Im Q), the sums formed per k-step
+    f64x4 pa[4], pb[4], pc[4];
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt) ar[rt] = br[rt] = ai[rt] = bi[rt] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int rt = 0; rt < 4; ++rt) pa[rt] = pb[rt] = pc[rt] = f64x4{0.0, 0.0, 0.0, 0.0};
     {
         const double2 *Gs[NSL], *Qs[NSL];
 #pragma unroll
@@ -442,28 +448,27 @@ __global__ __launch_bounds__(64 * kColWaves) void k_helm_mfma_cols64(
                 __builtin_amdgcn_sched_barrier(0);
                 const double2(&gv)[4] = gbuf[st % (kColPrefG + 1)];
                 const double2 q = qbuf[st % (kColPrefQ + 1)];
+                const double qs = q.x + q.y;
 #pragma unroll
                 for (int rt = 0; rt < 4; ++rt) {
-                    ar[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(gv[rt].x, q.x, ar[rt], 0, 0, 0);
-                    ai[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(gv[rt].x, q.y, ai[rt], 0, 0, 0);
-                }
-#pragma unroll
-                for (int rt = 0; rt < 4; ++rt) {
-                    br[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(gv[rt].y, q.y, br[rt], 0, 0, 0);
-                    bi[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(gv[rt].y, q.x, bi[rt], 0, 0, 0);
+                    const double gs = CONJ ? gv[rt].x - gv[rt].y : gv[rt].x + gv[rt].y;
+                    pa[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(gv[rt].x, q.x, pa[rt], 0, 0, 0);
+                    pb[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(gv[rt].y, q.y, pb[rt], 0, 0, 0);
+                    pc[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(gs, qs, pc[rt], 0, 0, 0);
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
     }
-    // U = G Q: Re = ar - br, Im = ai + bi; with CONJ (conj G): Re = ar + br, Im = ai - bi.
-    // Wave w finishes row tile w from the four waves' partials, in wave order.
+    // U = G Q: Re = pa - pb, Im = pc - pa - pb; with CONJ (conj G): Re = pa + pb,
+    // Im = pc - pa + pb.  Wave w finishes row tile w from the four waves' partials, in
+    // wave order.
 #pragma unroll
     for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            s_red[w][rt][0][r][lane] = CONJ ? ar[rt][r] + br[rt][r] : ar[rt][r] - br[rt][r];
-            s_red[w][rt][1][r][lane] = CONJ ? ai[rt][r] - bi[rt][r] : ai[rt][r] + bi[rt][r];
+            s_red[w][rt][0][r][lane] = CONJ ? pa[rt][r] + pb[rt][r] : pa[rt][r] - pb[rt][r];
+            s_red[w][rt][1][r][lane] = CONJ ? pc[rt][r] - pa[rt][r] + pb[rt][r] : pc[rt][r] - pa[rt][r] - pb[rt][r];
         }
     __syncthreads();
     if (li < cnt) {
