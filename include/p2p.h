@@ -328,8 +328,10 @@ p2p_status p2p_eval_gravity_noalloc(const p2p_tree *tree, const p2p_nbrs *nbrs, 
  * float2 (FP32_MIXED) or double2 (FP64) interleaved complex.  REDUNDANT reads
  * q from `red` (built with the same precision and nrhs).  FP32_MIXED with
  * nrhs a multiple of 32 runs on FP32 matrix cores (v_mfma_f32_32x32x2f32) in
- * one persistent launch over all boxes of all instances, taking boxes from a
- * work queue ordered by decreasing near-list length; instances whose k h
+ * one persistent launch over all boxes of all instances, taking (box, RHS
+ * chunk) items in tree order from eight queues, one per XCD, each over a
+ * contiguous eighth of the items, a wave whose own queue is empty taking from
+ * the others in turn (neighbouring boxes meet in one XCD's L2); instances whose k h
  * agree to 1e-12 share one set of G blocks.  nrhs == 1 runs on the matrix
  * cores of its precision (v_mfma_f32_16x16x4f32 or v_mfma_f64_16x16x4f64) with
  * tiles of 16 target boxes as the columns of the product.  `tile` (host int32[4], may be
@@ -351,8 +353,7 @@ p2p_status p2p_eval_helmholtz(const p2p_tree *tree, const p2p_nbrs *nbrs, const 
  * buffer, what p2p_eval_helmholtz otherwise rebuilds on every call: the
  * instances' parameters, the G blocks of every distinct k h built in double
  * precision (rounded to single on the FP32 matrix-core paths) or the G(d^2)
- * tables (vector path), and the work-queue order by decreasing near-list length
- * (several right-hand sides).  Host struct. */
+ * tables (vector path).  Host struct. */
 typedef struct {
     void *buf;            /* in: device buffer, 256-byte aligned; NULL asks for the size */
     size_t bytes;         /* in: size of buf; out (buf == NULL): bytes needed */
@@ -379,9 +380,9 @@ p2p_status p2p_helmholtz_prepare(const p2p_tree *tree, const p2p_nbrs *nbrs, p2p
 
 /* p2p_eval_helmholtz from a plan: the same results, with the precision, nrhs
  * and tile of the plan, and no set-up work: a REDUNDANT call is one product
- * launch (two with several right-hand sides: the work-queue counter is
+ * launch (two with several right-hand sides: the work-queue counters are
  * zeroed first), a GATHER call adds the copy of q into box order.  The
- * workspace holds only that copy and the counter.  P2P_EINVAL if the plan was
+ * workspace holds only that copy and the counters.  P2P_EINVAL if the plan was
  * prepared for other sizes, grids, precision, nrhs or tile.  Never copies
  * from host memory or synchronises, so it may be captured into a HIP graph.
  * Calls that share one plan may overlap (the plan is only read). */

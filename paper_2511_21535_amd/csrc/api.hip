@@ -805,7 +805,7 @@ namespace {
 // the path (matrix cores multi-RHS or single RHS, or the vector kernel), the
 // launch shape, the distinct k h values (one G table or set of G blocks each),
 // and the layout of the set-up buffer.  The set-up buffer (the plan) holds the
-// instances' parameters, the G tables or blocks and the work-queue order; it
+// instances' parameters and the G tables or blocks; it
 // is filled by helm_fill, either on every call (p2p_eval_helmholtz, in the
 // workspace) or once (p2p_helmholtz_prepare, in a caller buffer).
 struct HelmSetup {
@@ -826,10 +826,6 @@ struct HelmSetupBufs {
     char *params = nullptr;
     char *table = nullptr;
     float2 *blocks = nullptr;
-    int32_t *work = nullptr;
-    uint64_t *wkeys = nullptr, *wkeys_tmp = nullptr;
-    int32_t *wvals_tmp = nullptr;
-    uint32_t *whist = nullptr;
 };
 
 p2p_status helm_setup(const p2p_tree *tree, const p2p_nbrs *nbrs, p2p_precision prec, const p2p_grid *grids,
@@ -925,7 +921,7 @@ p2p_status helm_setup(const p2p_tree *tree, const p2p_nbrs *nbrs, p2p_precision 
     return P2P_OK;
 }
 
-HelmSetupBufs helm_take(Arena &ar, const HelmSetup &h, int64_t L) {
+HelmSetupBufs helm_take(Arena &ar, const HelmSetup &h) {
     const size_t csize = h.fp64 ? sizeof(double2) : sizeof(float2);
     HelmSetupBufs b;
     b.params = ar.take<char>(h.param_bytes);
@@ -935,18 +931,11 @@ HelmSetupBufs helm_take(Arena &ar, const HelmSetup &h, int64_t L) {
     if (h.blk)
         b.blocks = ar.take<float2>(h.cols ? (static_cast<size_t>(h.n_tables) * 27 * 4096 + 64) * (h.fp64 ? 2 : 1)
                                           : static_cast<size_t>(h.n_tables) * h.copies * 27 * 4096 * 2);
-    if (h.mfma) {
-        b.work = ar.take<int32_t>(L);
-        b.wkeys = ar.take<uint64_t>(L);
-        b.wkeys_tmp = ar.take<uint64_t>(L);
-        b.wvals_tmp = ar.take<int32_t>(L);
-        b.whist = ar.take<uint32_t>(radix_hist_elems(L));
-    }
     return b;
 }
 
 // Fill the set-up buffer: parameters uploaded (unless they travel inline),
-// the G tables (vector path) or blocks (matrix cores), the work order.
+// the G tables (vector path) or blocks (matrix cores).
 p2p_status helm_fill(const HelmSetup &h, const HelmSetupBufs &b, const p2p_tree *tree, const p2p_nbrs *nbrs,
                      const p2p_grid *grids, hipStream_t s) {
     double *d_h = reinterpret_cast<double *>(b.params);
@@ -968,9 +957,6 @@ p2p_status helm_fill(const HelmSetup &h, const HelmSetupBufs &b, const p2p_tree 
     }
     if (h.blk) P2P_TRY(launch_green_blocks(d_kh, h.inl, h.n_tables, h.copies, h.cols, h.fp64, b.blocks, s));
     else P2P_TRY(launch_green_tables(d_h, d_k, h.n_grids, h.fp64, b.table, s));
-    if (h.mfma)
-        P2P_TRY(launch_work_order(nbrs->nbr_start, tree->n_leaves, b.work, b.wkeys, b.wkeys_tmp, b.wvals_tmp,
-                                  b.whist, s));
     return P2P_OK;
 }
 
@@ -999,7 +985,7 @@ p2p_status helm_check_call(const HelmSetup &h, const p2p_tree *tree, const p2p_n
 }
 
 // The evaluation from a filled set-up: the sorted copy of q (GATHER), then one
-// product launch (the matrix-core queue's counter is zeroed first; one RHS on a
+// product launch (the matrix-core queues' counters are zeroed first; one RHS on a
 // grid of few tiles adds the join of the two halves of each tile).
 p2p_status helm_run(const HelmSetup &h, const HelmSetupBufs &b, int32_t *counter, char *sorted, double2 *parts,
                     const p2p_tree *tree, const p2p_nbrs *nbrs, const p2p_redundant *red, p2p_layout layout,
@@ -1051,7 +1037,6 @@ p2p_status helm_run(const HelmSetup &h, const HelmSetupBufs &b, int32_t *counter
             return launch_helmholtz_mfma_cols(a, d_tiles, h.inl, h.n_tiles, redundant, h.fp64, s);
         }
         a.copies = h.copies;
-        a.work = b.work;
         a.counter = counter;
         a.nrhs = nrhs;
         return launch_helmholtz_mfma(a, redundant, h.waves_per_wg, h.wg_per_cu, h.rhs_tile, s);
@@ -1075,7 +1060,7 @@ p2p_status helm_run(const HelmSetup &h, const HelmSetupBufs &b, int32_t *counter
     return launch_helmholtz(a, redundant, h.fp64, s);
 }
 
-// Per-call scratch of an evaluation beside the set-up: the queue counter
+// Per-call scratch of an evaluation beside the set-up: the eight queue counters
 // (matrix cores, several RHS), the sorted copy of q (GATHER) and, for one RHS,
 // the two partial results of tiles whose offsets two workgroups share.
 void helm_take_call(Arena &ar, const HelmSetup &h, int64_t n, bool redundant, int32_t **counter, char **sorted,
@@ -1095,7 +1080,7 @@ p2p_status helmholtz_common(const p2p_tree *tree, const p2p_nbrs *nbrs, const p2
     P2P_TRY(helm_setup(tree, nbrs, prec, grids, n_grids, nrhs, tile, &h));
     if (layout != P2P_GATHER && layout != P2P_REDUNDANT) return fail(P2P_EINVAL, "bad layout");
     Arena ar(ws);
-    const HelmSetupBufs b = helm_take(ar, h, tree->n_leaves);
+    const HelmSetupBufs b = helm_take(ar, h);
     int32_t *counter;
     char *sorted;
     double2 *parts;
@@ -1164,7 +1149,7 @@ extern "C" p2p_status p2p_helmholtz_prepare(const p2p_tree *tree, const p2p_nbrs
     HelmSetup h;
     P2P_TRY(helm_setup(tree, nbrs, prec, grids, n_grids, nrhs, tile, &h));
     Arena ar(plan->buf);
-    const HelmSetupBufs b = helm_take(ar, h, tree->n_leaves);
+    const HelmSetupBufs b = helm_take(ar, h);
     if (!plan->buf) {
         plan->bytes = ar.used;
         return P2P_OK;
@@ -1200,7 +1185,7 @@ extern "C" p2p_status p2p_eval_helmholtz_prepared(const p2p_tree *tree, const p2
     if (helm_fingerprint(h, tree, nbrs, grids) != plan->fingerprint)
         return fail(P2P_EINVAL, "plan was prepared for another tree, grid set, precision, nrhs or tile");
     Arena pa(plan->buf);
-    const HelmSetupBufs b = helm_take(pa, h, tree->n_leaves);
+    const HelmSetupBufs b = helm_take(pa, h);
     if (plan->bytes < pa.used) return fail(P2P_EINVAL, "plan->bytes smaller than the set-up");
     Arena ar(ws);
     int32_t *counter;

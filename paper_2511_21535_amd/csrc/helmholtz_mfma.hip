@@ -19,9 +19,9 @@
 // lane k*32 + j, and accumulator register r of lane l holds row
 // 8 (r/4) + 4 (l/32) + r%4, column l%32.
 //
-// Work distribution: waves take boxes from an atomic counter over a list
-// ordered by decreasing near-list length (longest processing time first),
-// and exit when the list is exhausted.
+// Work distribution: waves take (box, RHS chunk) items in tree order from
+// eight atomic counters, one per XCD, each over a contiguous eighth of the
+// items, and exit when every eighth is exhausted.
 //
 // The G blocks can be held in several identical copies (the block-level
 // pattern redundancy of the paper's electromagnetic case, Sec. 5.1.2, there
@@ -98,15 +98,6 @@ __global__ void k_green_blocks(const double *__restrict__ kh_dev, HelmInline inl
                                                     static_cast<float>(gr + gi), static_cast<float>(gr - gi));
 }
 
-__global__ void k_work_keys(const int64_t *__restrict__ nbr_start, int64_t L,
-                            uint64_t *__restrict__ keys, int32_t *__restrict__ vals) {
-    const int64_t A = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (A >= L) return;
-    const int64_t c = nbr_start[A + 1] - nbr_start[A];
-    keys[A] = static_cast<uint64_t>(255 - min<int64_t>(c, 255));   // longest lists first
-    vals[A] = static_cast<int32_t>(A);
-}
-
 __global__ void k_zero_counter(int32_t *c, int n) {
     if (static_cast<int>(threadIdx.x) < n) c[threadIdx.x] = 0;
 }
@@ -128,20 +119,37 @@ __device__ __forceinline__ void helm_mfma_body(
     const int64_t *__restrict__ nbr_start, const int32_t *__restrict__ nbr_idx,
     const int64_t *__restrict__ red_start, const int64_t *__restrict__ red_row, const float2 *__restrict__ src,
     const float4 *__restrict__ blocks, int32_t copies, const int32_t *__restrict__ inst_table,
-    const float *__restrict__ inst_scale, const int32_t *__restrict__ work,
-    int32_t *__restrict__ counter, float2 *__restrict__ u) {
+    const float *__restrict__ inst_scale, int32_t *__restrict__ counter, float2 *__restrict__ u) {
     const int lane = threadIdx.x & 63;
     const int half = lane >> 5, col = lane & 31;
     const uint64_t local_mask = (1ull << (3 * key_bits)) - 1ull;
     const int chunks = nrhs / (32 * TJ);
     const int64_t items = L * chunks;
 
+    // The items (box, RHS chunk), boxes in tree order, form eight contiguous
+    // slices, one per XCD (workgroups are dispatched to the XCDs round-robin,
+    // blockIdx.x % 8): the boxes one XCD runs at a time are neighbours, whose
+    // near fields overlap in its L2.  A wave whose slice is exhausted takes
+    // items from the next slices in turn; counters only grow, so a slice found
+    // exhausted stays so and every wave ends after at most eight misses.
+    const int xcd = static_cast<int>(blockIdx.x & 7);
+    int sl = 0;   // lane 0: slices found exhausted
     for (;;) {
-        int item = 0;
-        if (lane == 0) item = atomicAdd(counter, 1);
+        int item = -1;
+        if (lane == 0) {
+            for (; sl < 8; ++sl) {
+                const int x = (xcd + sl) & 7;
+                const int64_t lo = items * x / 8, hi = items * (x + 1) / 8;
+                const int64_t it = lo + atomicAdd(&counter[x], 1);
+                if (it < hi) {
+                    item = static_cast<int>(it);
+                    break;
+                }
+            }
+        }
         item = __builtin_amdgcn_readfirstlane(__shfl(item, 0, 64));
-        if (item >= items) break;
-        const int64_t A = work[item / chunks];
+        if (item < 0) break;
+        const int64_t A = item / chunks;
         const int rhs0 = (item % chunks) * 32 * TJ;
         const uint64_t kA = leaf_key[A];
         const int g = static_cast<int>(kA >> (3 * key_bits));
@@ -319,10 +327,10 @@ __device__ __forceinline__ void helm_mfma_body(
         const int64_t *__restrict__ red_start, const int64_t *__restrict__ red_row,                     \
         const float2 *__restrict__ src, const float4 *__restrict__ blocks, int32_t copies,              \
         const int32_t *__restrict__ inst_table, const float *__restrict__ inst_scale,                   \
-        const int32_t *__restrict__ work, int32_t *__restrict__ counter, float2 *__restrict__ u
+        int32_t *__restrict__ counter, float2 *__restrict__ u
 #define P2P_HELM_MFMA_ARGS                                                                              \
     L, key_bits, nrhs, leaf_start, leaf_key, perm, nbr_start, nbr_idx, red_start, red_row, src, blocks, \
-        copies, inst_table, inst_scale, work, counter, u
+        copies, inst_table, inst_scale, counter, u
 
 // The product form of each variant: three real products, except 64 right-hand
 // sides per wave with FP64 sums, whose 128 doubles per lane of sums leave no
@@ -356,14 +364,6 @@ p2p_status launch_green_blocks(const double *d_kh, const HelmInline &inl, int32_
     return P2P_OK;
 }
 
-p2p_status launch_work_order(const int64_t *nbr_start, int64_t L, int32_t *work, uint64_t *keys,
-                             uint64_t *keys_tmp, int32_t *vals_tmp, uint32_t *hist,
-                             hipStream_t s) {
-    if (L <= 0) return P2P_OK;
-    k_work_keys<<<grid_for(L, 256), 256, 0, s>>>(nbr_start, L, keys, work);
-    P2P_LAUNCH_CHECK();
-    return radix_sort_pairs(keys, work, keys_tmp, vals_tmp, L, 8, hist, s);
-}
 
 template <bool RED, bool CONJ, int TJ, bool COMP>
 static void launch_mfma_t(const HelmholtzMfmaArgs &a, unsigned grid, unsigned block, hipStream_t s) {
@@ -371,11 +371,11 @@ static void launch_mfma_t(const HelmholtzMfmaArgs &a, unsigned grid, unsigned bl
     if constexpr (TJ == 2 || COMP)
         k_helm_mfma_wide<RED, CONJ, TJ, COMP><<<grid, block, 0, s>>>(
             a.L, a.key_bits, a.nrhs, a.leaf_start, a.leaf_key, a.perm, a.nbr_start, a.nbr_idx,
-            a.red_start, a.red_row, a.src, g4, a.copies, a.inst_table, a.inst_scale, a.work, a.counter, a.u);
+            a.red_start, a.red_row, a.src, g4, a.copies, a.inst_table, a.inst_scale, a.counter, a.u);
     else
         k_helm_mfma<RED, CONJ, TJ, COMP><<<grid, block, 0, s>>>(
             a.L, a.key_bits, a.nrhs, a.leaf_start, a.leaf_key, a.perm, a.nbr_start, a.nbr_idx,
-            a.red_start, a.red_row, a.src, g4, a.copies, a.inst_table, a.inst_scale, a.work, a.counter, a.u);
+            a.red_start, a.red_row, a.src, g4, a.copies, a.inst_table, a.inst_scale, a.counter, a.u);
 }
 
 p2p_status launch_helmholtz_mfma(const HelmholtzMfmaArgs &a, bool redundant, int waves_per_wg,
@@ -384,7 +384,7 @@ p2p_status launch_helmholtz_mfma(const HelmholtzMfmaArgs &a, bool redundant, int
     int dev = 0, cus = 0;
     P2P_HIP(hipGetDevice(&dev));
     P2P_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    k_zero_counter<<<1, 64, 0, s>>>(a.counter, 1);
+    k_zero_counter<<<1, 64, 0, s>>>(a.counter, 8);
     P2P_LAUNCH_CHECK();
     const unsigned block = 64u * static_cast<unsigned>(waves_per_wg);
     const unsigned grid = static_cast<unsigned>(cus) * static_cast<unsigned>(wg_per_cu);

@@ -307,8 +307,7 @@ struct HelmholtzMfmaArgs {
     int32_t copies;            // copies of each table; workgroup w reads copy (w / 8) % copies
     const int32_t *inst_table; // per instance: table index
     const float *inst_scale;   // per instance: 1/h
-    const int32_t *work;       // box ids in processing order (longest first)
-    int32_t *counter;          // work-queue counter (zeroed by the launcher)
+    int32_t *counter;          // [8] work-queue counters, one per XCD slice (zeroed by the launcher)
     int32_t nrhs;
     int32_t conj;
     int32_t comp;              // 1: each near box's FP32 partial product summed into FP64 per target
@@ -334,9 +333,6 @@ struct HelmInline {
 // f64 (single-RHS layout only) the entries are double2.
 p2p_status launch_green_blocks(const double *d_kh, const HelmInline &inl, int32_t n_tables, int32_t copies,
                                bool cols, bool f64, void *blocks, hipStream_t s);
-p2p_status launch_work_order(const int64_t *nbr_start, int64_t L, int32_t *work, uint64_t *keys,
-                             uint64_t *keys_tmp, int32_t *vals_tmp, uint32_t *hist,
-                             hipStream_t s);
 p2p_status launch_helmholtz_mfma(const HelmholtzMfmaArgs &a, bool redundant, int waves_per_wg,
                                  int wg_per_cu, int rhs_tile, hipStream_t s);
 // Single RHS on matrix cores, target boxes as the columns: tiles of up to 16

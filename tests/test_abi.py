@@ -342,7 +342,7 @@ def test_peaks_library_exports_and_rejects_bad_arguments():
 
 def test_helmholtz_plan_host_checks(lib):
     """p2p_helmholtz_prepare with plan->buf == NULL only sizes the plan (the
-    G blocks of every distinct k h, the work order with several RHS); an
+    G blocks of every distinct k h, float4 entries with several RHS); an
     unprepared plan, or one whose fingerprint is of other arguments, is refused
     on the host by p2p_eval_helmholtz_prepared."""
     n = 16 ** 3
@@ -361,7 +361,7 @@ def test_helmholtz_plan_host_checks(lib):
     assert one >= 27 * 64 * 64 * 8 and p.fingerprint == 0     # one set of G blocks; nothing prepared
     assert lib.p2p_helmholtz_prepare(ctypes.byref(t), ctypes.byref(nl), L.P2P_FP32_MIXED, g, 1, 64, None,
                                      ctypes.byref(p), None) == L.P2P_OK
-    assert p.bytes > one                                       # plus the work order of the queue
+    assert p.bytes > one                       # float4 G entries (sums of the three-product form)
     nb = ctypes.c_size_t(0)
     st = lib.p2p_eval_helmholtz_prepared(ctypes.byref(t), ctypes.byref(nl), None, L.P2P_GATHER, g, 1,
                                          ctypes.byref(p), z, z, None, ctypes.byref(nb), None)
