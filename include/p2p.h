@@ -327,7 +327,7 @@ p2p_status p2p_eval_gravity_noalloc(const p2p_tree *tree, const p2p_nbrs *nbrs, 
  * array the tree was built from.  q (GATHER) and u: caller order [n][nrhs],
  * float2 (FP32_MIXED) or double2 (FP64) interleaved complex.  REDUNDANT reads
  * q from `red` (built with the same precision and nrhs).  FP32_MIXED with
- * nrhs a multiple of 32 runs on FP32 matrix cores (v_mfma_f32_32x32x2f32) in
+ * nrhs a multiple of 32 (at most 2^20) runs on FP32 matrix cores (v_mfma_f32_32x32x2f32) in
  * one persistent launch over all boxes of all instances, taking (box, RHS
  * chunk) items in tree order from eight queues, one per XCD, each over a
  * contiguous eighth of the items, a wave whose own queue is empty taking from

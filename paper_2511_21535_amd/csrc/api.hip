@@ -841,7 +841,9 @@ p2p_status helm_setup(const p2p_tree *tree, const p2p_nbrs *nbrs, p2p_precision 
     h->nrhs = nrhs;
     h->n_grids = n_grids;
     h->fp64 = prec == P2P_FP64;
-    h->mfma = !h->fp64 && nrhs % 32 == 0;
+    // the matrix-core product addresses a box's 64 source rows with 32-bit byte
+    // offsets (buffer loads), so nrhs above 2^20 takes the vector kernel
+    h->mfma = !h->fp64 && nrhs % 32 == 0 && nrhs <= (1 << 20);
     // one RHS: matrix cores (FP32, or FP64 on the FP64 matrix instructions) with the target boxes as columns
     h->cols = nrhs == 1;
     h->rhs_tile = (nrhs % 64 == 0) ? 64 : 32;

@@ -34,6 +34,13 @@
 namespace p2p {
 namespace {
 
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+// A raw buffer descriptor over [p, p + bytes): dword 3 holds the 32-bit data
+// format that untyped (raw) buffer loads expect on this target.
+__device__ inline Rsrc buffer_rsrc(const void *p, int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, bytes, 0x00020000);
+}
+
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 constexpr double kPi = 3.14159265358979323846;
 
@@ -180,13 +187,20 @@ __device__ __forceinline__ void helm_mfma_body(
             my_row_lo = static_cast<int>(row0 & 0xffffffff);
             my_row_hi = static_cast<int>(row0 >> 32);
         }
-        auto box_ptrs = [&](int e, const float4 *&Gp, const float2 *&Qp) {
+        // Operands through buffer loads: a descriptor per near box over its G
+        // block and its 64 source rows (scalar registers), a lane offset fixed
+        // for the whole item and a per-k-step scalar offset, so that no k-step
+        // spends vector instructions on address arithmetic.  Reads beyond a
+        // descriptor's range would return zeros; the offsets stay inside it.
+        auto box_ptrs = [&](int e, Rsrc &Gp, Rsrc &Qp) {
             const int goff = __builtin_amdgcn_readlane(my_goff, e);
             const int64_t row0 = (static_cast<int64_t>(__builtin_amdgcn_readlane(my_row_hi, e)) << 32) |
                                  static_cast<uint32_t>(__builtin_amdgcn_readlane(my_row_lo, e));
-            Gp = gbase + goff + half * 64 + col;
-            Qp = src + (row0 + half) * nrhs + rhs0 + col;
+            Gp = buffer_rsrc(gbase + goff, 4096 * static_cast<int>(sizeof(float4)));
+            Qp = buffer_rsrc(src + row0 * nrhs + rhs0, (64 * nrhs - rhs0) * static_cast<int>(sizeof(float2)));
         };
+        const int vg = (half * 64 + col) * static_cast<int>(sizeof(float4));
+        const int vq = (half * nrhs + col) * static_cast<int>(sizeof(float2));
 
         // M3: pa = A, pb = B, pc = C; otherwise ur = pa (Re U), ui = pb (Im U)
         constexpr int NC = M3 ? TJ : 1;
@@ -219,12 +233,16 @@ __device__ __forceinline__ void helm_mfma_body(
                     for (int r = 0; r < 16; ++r) cr[a][b][r] = ci[a][b][r] = 0.0;
         }
 
-        const int64_t qstep = 2 * static_cast<int64_t>(nrhs);   // two source rows per k-step
-        auto load = [&](const float4 *Gp, const float2 *Qp, int kk, float4 (&gv)[2], float2 (&qv)[TJ]) {
+        const int qstep = 2 * nrhs * static_cast<int>(sizeof(float2));   // two source rows per k-step
+        auto load = [&](Rsrc Gp, Rsrc Qp, int kk, float4 (&gv)[2], float2 (&qv)[TJ]) {
 #pragma unroll
-            for (int a = 0; a < 2; ++a) gv[a] = Gp[kk * 128 + 32 * a];
+            for (int a = 0; a < 2; ++a)
+                gv[a] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(
+                                                       Gp, vg + 32 * a * static_cast<int>(sizeof(float4)), kk * 2048, 0));
 #pragma unroll
-            for (int b = 0; b < TJ; ++b) qv[b] = Qp[kk * qstep + 32 * b];
+            for (int b = 0; b < TJ; ++b)
+                qv[b] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(
+                                                       Qp, vq + 32 * b * static_cast<int>(sizeof(float2)), kk * qstep, 0));
         };
         // fresh: the first k-step of a box under COMP starts from zero accumulators
         auto mma = [&](const float4 (&gv)[2], const float2 (&qv)[TJ], bool fresh) {
@@ -262,8 +280,7 @@ __device__ __forceinline__ void helm_mfma_body(
         // four operand buffers in rotation: the loads of k-step kk + 3 are issued
         // while step kk runs, across box boundaries (the last box prefetches
         // its own first steps again, harmlessly)
-        const float4 *Gc, *Gn;
-        const float2 *Qc, *Qn;
+        Rsrc Gc, Gn, Qc, Qn;
         box_ptrs(0, Gc, Qc);
         float4 gbuf[4][2];
         float2 qbuf[4][TJ];
