@@ -212,16 +212,6 @@ def measured_peaks():
     return rec
 
 
-def add_8flop_fracs(obj):
-    """Beside every roofline that counts the executed flop of the three-product form,
-    states the fraction of peak its four-product (8 flop) equivalent rate would be."""
-    if isinstance(obj, dict):
-        if "achieved_8flop_equivalent" in obj and "peak" in obj:
-            obj["frac_8flop_equivalent"] = obj["achieved_8flop_equivalent"] / obj["peak"]
-        for v in obj.values():
-            add_8flop_fracs(v)
-
-
 def with_measured_peak(roof, key):
     """Adds the measured peak of the same unit beside the published one."""
     rec = measured_peaks()
@@ -1087,7 +1077,6 @@ def main():
         line[NESTED_WORKLOAD] = {k: v for k, v in sub.items()
                                  if k not in ("n_gpus", "steps", "warmup", "higher_is_better", "scaling",
                                               "vs_baseline", "data")}
-    add_8flop_fracs(line)
     print(json.dumps(line), flush=True)
 
 
