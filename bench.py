@@ -72,11 +72,13 @@ SLOTS_PER_PAIR_MIXED = 3 + 3 + 2 + 3 + 1 + 3        # = 15
 # third-order refinement step to full precision).
 SLOTS_PER_PAIR_FP64 = 3 + 3 + 3 + 1 + 3 + 6         # = 19
 # Gravity adjoint per pair, the VALU instructions hipcc emits in the pair
-# loop without its loop control: FP64 41 arithmetic + 6 for the reciprocal
-# square root (as in the forward count); FP32-mixed 42, with v_rsq_f32 at
-# half rate (one more slot).
-SLOTS_PER_PAIR_ADJ_FP64 = 41 + 6                     # = 47
-SLOTS_PER_PAIR_ADJ_MIXED = 42 + 1                    # = 43
+# loop without its loop control: FP64 33 arithmetic + 6 for the reciprocal
+# square root (as in the forward count); FP32-mixed 34, with v_rsq_f32 at
+# half rate (one more slot).  The term w^3 (m_j ga_k - m_k ga_j) is summed as
+# two running sums (m_j sum w^3 ga_k - ga_j sum w^3 m_k), which took 8 of the
+# 41 and 42 instructions a per-pair difference needed.
+SLOTS_PER_PAIR_ADJ_FP64 = 33 + 6                     # = 39
+SLOTS_PER_PAIR_ADJ_MIXED = 34 + 1                    # = 35
 # FP32 vector FMA without packed issue: 256 CUs x 64 lanes x 2 flop x 2.4 GHz
 FP32_VALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12  # = 78.6
 FP32_MFMA_PEAK_TFLOPS = 157.3                        # dense FP32 matrix (published)

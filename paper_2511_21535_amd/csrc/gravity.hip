@@ -513,6 +513,10 @@ __global__ __launch_bounds__(kGBlock) __attribute__((amdgpu_waves_per_eu(5))) vo
             gj = a.g4[tr];
         }
         double om = 0.0, ox = 0.0, oy = 0.0, oz = 0.0;
+        // The term w^3 (m_j ga_k - m_k ga_j) is summed as m_j sum_k w^3 ga_k -
+        // ga_j sum_k w^3 m_k: two running sums instead of a difference per pair
+        // (FP64 over all sources; FP32_MIXED per group of at most kGFlush pairs)
+        double s1x = 0.0, s1y = 0.0, s1z = 0.0, s2 = 0.0;
         // a periodic source image at x_k + s: both pair directions see the
         // same d = x_j - (x_k + s) (the reverse entry carries -s)
         auto stage = [&](int i, int64_t row, int code) {
@@ -531,6 +535,8 @@ __global__ __launch_bounds__(kGBlock) __attribute__((amdgpu_waves_per_eu(5))) vo
                 int s = g;
                 while (s < nt) {
                     float fm = 0.f, fx = 0.f, fy = 0.f, fz = 0.f;
+                    // sum w^3 ga_k and sum w^3 m_k of the group, as in FP64
+                    float f1x = 0.f, f1y = 0.f, f1z = 0.f, f2 = 0.f;
                     for (int k = 0; k < kGFlush && s < nt; ++k, s += G) {
                         const float4 pk = s_p[s], gk = s_g[s];
                         const float dx = pj.x - pk.x, dy = pj.y - pk.y, dz = pj.z - pk.z;
@@ -539,15 +545,19 @@ __global__ __launch_bounds__(kGBlock) __attribute__((amdgpu_waves_per_eu(5))) vo
                         const float gdj = fmaf(gj.y, dx, fmaf(gj.z, dy, gj.w * dz));
                         const float gdk = fmaf(gk.y, dx, fmaf(gk.z, dy, gk.w * dz));
                         const float cc = pk.w * fmaf(3.f * w5, gdj, gj.x * w3) + pj.w * fmaf(-3.f * w5, gdk, gk.x * w3);
-                        fx += fmaf(cc, dx, w3 * (pj.w * gk.y - pk.w * gj.y));
-                        fy += fmaf(cc, dy, w3 * (pj.w * gk.z - pk.w * gj.z));
-                        fz += fmaf(cc, dz, w3 * (pj.w * gk.w - pk.w * gj.w));
+                        fx = fmaf(cc, dx, fx);
+                        fy = fmaf(cc, dy, fy);
+                        fz = fmaf(cc, dz, fz);
+                        f1x = fmaf(w3, gk.y, f1x);
+                        f1y = fmaf(w3, gk.z, f1y);
+                        f1z = fmaf(w3, gk.w, f1z);
+                        f2 = fmaf(w3, pk.w, f2);
                         fm -= gk.x * w - w3 * gdk;
                     }
                     om += fm;
-                    ox += fx;
-                    oy += fy;
-                    oz += fz;
+                    ox += fmaf(pj.w, f1x, fmaf(-gj.y, f2, fx));
+                    oy += fmaf(pj.w, f1y, fmaf(-gj.z, f2, fy));
+                    oz += fmaf(pj.w, f1z, fmaf(-gj.w, f2, fz));
                 }
             } else {
                 // the tile position of the target's own row, whose pair is dropped
@@ -562,15 +572,24 @@ __global__ __launch_bounds__(kGBlock) __attribute__((amdgpu_waves_per_eu(5))) vo
                     const double gdj = gj.y * dx + gj.z * dy + gj.w * dz;
                     const double gdk = gk.y * dx + gk.z * dy + gk.w * dz;
                     const double cc = pk.w * (gj.x * w3 + 3.0 * w5 * gdj) + pj.w * (gk.x * w3 - 3.0 * w5 * gdk);
-                    ox += cc * dx + w3 * (pj.w * gk.y - pk.w * gj.y);
-                    oy += cc * dy + w3 * (pj.w * gk.z - pk.w * gj.z);
-                    oz += cc * dz + w3 * (pj.w * gk.w - pk.w * gj.w);
+                    ox += cc * dx;
+                    oy += cc * dy;
+                    oz += cc * dz;
+                    s1x += w3 * gk.y;
+                    s1y += w3 * gk.z;
+                    s1z += w3 * gk.w;
+                    s2 += w3 * pk.w;
                     om -= gk.x * w - w3 * gdk;
                 }
             }
         };
         for_each_source_tile<false, PER>(A, nullptr, nullptr, a.nbr_start, a.nbr_idx, a.nbr_shift, a.leaf_start,
                                          s_pre, s_first, s_code, s_w, &s_self, [](int) {}, stage, body);
+        if constexpr (!MIXED) {
+            ox += pj.w * s1x - gj.y * s2;
+            oy += pj.w * s1y - gj.z * s2;
+            oz += pj.w * s1z - gj.w * s2;
+        }
         __syncthreads();
         s_red[0 * kGBlock + threadIdx.x] = active ? om : 0.0;
         s_red[1 * kGBlock + threadIdx.x] = active ? ox : 0.0;

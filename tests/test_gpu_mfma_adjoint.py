@@ -33,7 +33,9 @@ def _grid_tree(sides):
     return t, t.neighbors()
 
 
-@pytest.mark.parametrize("sides,nrhs", [([16], 64), ([12, 8, 20], 32), ([8, 16], 96)])
+# [4] and [4, 8]: one and nine boxes, fewer (box, RHS chunk) items than the
+# product's eight per-XCD queues, most of which start empty
+@pytest.mark.parametrize("sides,nrhs", [([16], 64), ([12, 8, 20], 32), ([8, 16], 96), ([4], 32), ([4, 8], 64)])
 def test_helmholtz_mfma_parity(sides, nrhs):
     print(f"case mfma sides={sides} nrhs={nrhs}", flush=True)
     gt, gn = _grid_tree(sides)
