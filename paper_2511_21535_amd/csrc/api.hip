@@ -503,6 +503,7 @@ p2p_status restructure_common(const p2p_tree *tree, const p2p_tree *srct, const 
         boxes.red_start = out->red_start;
         boxes.red_self = out->red_self;
         boxes.box_rows = 64;
+        boxes.entries = nbrs->count;
         if (L == 0) P2P_TRY((exclusive_scan<int32_t, int64_t>(seg_len, out->red_start, 0, scan_tmp, s)));
     } else {
         P2P_TRY(launch_seg_lengths(srct->leaf_start, nbrs->nbr_start, nbrs->nbr_idx, shifts(nbrs), L, seg_len,

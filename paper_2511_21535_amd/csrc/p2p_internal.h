@@ -162,6 +162,7 @@ struct BoxSegments {
     int64_t *red_start = nullptr;
     int32_t *red_self = nullptr;
     int32_t box_rows = 0;
+    int64_t entries = 0;   // near-list entries (with box_rows > 0)
 };
 template <class T>
 p2p_status launch_copy_segments(const T *sorted, int64_t row_len, const int32_t *leaf_start,

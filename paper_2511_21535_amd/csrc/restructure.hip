@@ -509,6 +509,33 @@ p2p_status permute_units(const void *src, const int32_t *perm, int64_t n, int64_
     return P2P_OK;
 }
 
+// Box-grain segments of full grid boxes (64 rows each) with 8- or 16-byte
+// rows: near-list entry e copies its source box's 64 rows, 2^LGU 16-byte
+// units, to units [e 2^LGU, (e + 1) 2^LGU) of the layout, one unit per thread,
+// so that each group of 2^LGU lanes moves one contiguous run.  Threads below L
+// also write box A's segment offset and the position of its own rows.
+template <int LGU, bool NT>
+__global__ __launch_bounds__(256) void k_copy_box_entries(const uint4 *__restrict__ sorted,
+                                                          const int32_t *__restrict__ leaf_start,
+                                                          const int64_t *__restrict__ nbr_start,
+                                                          const int32_t *__restrict__ nbr_idx, int64_t L,
+                                                          uint4 *__restrict__ dst, BoxSegments boxes) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (t < L) {
+        const int64_t e0 = nbr_start[t], e1 = nbr_start[t + 1];
+        boxes.red_start[t] = static_cast<int64_t>(boxes.box_rows) * e0;
+        if (t == L - 1) boxes.red_start[L] = static_cast<int64_t>(boxes.box_rows) * e1;
+        for (int64_t e = e0; e < e1; ++e)
+            if (nbr_idx[e] == t) boxes.red_self[t] = boxes.box_rows * static_cast<int32_t>(e - e0);
+    }
+    if (t >= (boxes.entries << LGU)) return;
+    const int64_t e = t >> LGU;
+    const int k = static_cast<int>(t & ((1 << LGU) - 1));
+    // 64 rows are 2^LGU units, so row r starts at unit r 2^LGU / 64 (r a multiple of 64)
+    const int64_t src = (static_cast<int64_t>(leaf_start[nbr_idx[e]]) << LGU) >> 6;
+    put_row<NT>(dst + t, sorted[src + k]);
+}
+
 template <class U>
 p2p_status copy_units(const void *sorted, int64_t row_bytes, const int32_t *leaf_start,
                       const int64_t *nbr_start, const int32_t *nbr_idx, const int64_t *red_start,
@@ -587,6 +614,23 @@ p2p_status launch_copy_segments(const T *sorted, int64_t row_len, const int32_t 
     if (boxes.box_rows > 0 && (!boxes.red_start || !boxes.red_self))
         return fail(P2P_EINVAL, "internal: box segments without their arrays");
     const int64_t rb = row_len * static_cast<int64_t>(sizeof(T));
+    if (boxes.box_rows == 64 && (rb == 8 || rb == 16) && (reinterpret_cast<uintptr_t>(dst) & 15) == 0 &&
+        (reinterpret_cast<uintptr_t>(sorted) & 15) == 0) {
+        // full grid boxes with one right-hand side (16-byte aligned layout): one
+        // 16-byte unit per thread
+        const int lgu = rb == 8 ? 5 : 6;
+        const int64_t threads = std::max<int64_t>(L, boxes.entries << lgu);
+        const unsigned grid = static_cast<unsigned>((threads + 255) / 256);
+        const uint4 *src4 = reinterpret_cast<const uint4 *>(sorted);
+        uint4 *dst4 = reinterpret_cast<uint4 *>(dst);
+#define P2P_CBE(G, N) \
+    k_copy_box_entries<G, N><<<grid, 256, 0, s>>>(src4, leaf_start, nbr_start, nbr_idx, L, dst4, boxes)
+        if (lgu == 5) { if (streaming) P2P_CBE(5, true); else P2P_CBE(5, false); }
+        else { if (streaming) P2P_CBE(6, true); else P2P_CBE(6, false); }
+#undef P2P_CBE
+        P2P_LAUNCH_CHECK();
+        return P2P_OK;
+    }
     switch (unit_bytes(rb)) {
     case 16:
         return copy_units<uint4>(sorted, rb, leaf_start, nbr_start, nbr_idx, red_start, L, dst, streaming, s,
