@@ -549,8 +549,8 @@ def helmholtz(tree: Tree, nbrs: Nbrs, q: Optional[torch.Tensor] = None, layout="
 
 class HelmholtzPlan:
     """The set-up of the Helmholtz evaluation built once (p2p_helmholtz_prepare):
-    parameters, FP64-built G blocks or tables, work-queue order, in a device
-    buffer owned here.  Pass it to helmholtz(..., plan=...)."""
+    parameters and the FP64-built G blocks or tables, in a device buffer
+    owned here.  Pass it to helmholtz(..., plan=...)."""
 
     def __init__(self, tree: Tree, nbrs: Nbrs, prec="fp32", nrhs: int = 1,
                  tile: Optional[Sequence[int]] = None):
